@@ -1,0 +1,182 @@
+"""Benchmark: block-Lanczos kernel columns phi(L) E_W on one MI355X.
+
+Workload (default): random geometric graph, N = 100,000 points uniform in the
+unit square, symmetrised 8-NN, Gaussian weights with sigma = median 8-NN
+distance; spline kernel (0.01 I + L)^(-2); s = 64 samples; m = 40 blocks;
+classical block Lanczos.  One step = one krylov_kernel_columns call (all
+stages: start block, SpMM + orthogonalisation per block, phi of the projected
+matrix, assembly of the n x s columns) with the Laplacian and samples resident
+on the device and the columns written to device memory.
+
+Metric: kernel columns per second of the mixed-precision path, valid only if
+its columns match the float64 GPU path to 1e-5 relative Frobenius error
+(checked in the same run).  Printed as one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def _kernel_hash(files):
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(ROOT, "paper_2301_06384_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _traffic_from_profile(kernel_file: str, src_hash: str):
+    """HBM bytes per launch of the SpMM kernel from a committed rocprofv3
+    --pmc summary, only if it was taken on the current kernel source."""
+    p = os.path.join(ROOT, "profiles", kernel_file)
+    if not os.path.exists(p):
+        return None
+    vals = {}
+    with open(p) as fh:
+        for line in fh:
+            if ":" in line:
+                k, v = line.split(":", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("source_hash") != src_hash:
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(L, W, phi, m, s_sample: int):
+    """The FP64 oracle on a bounded sample: the same graph, phi and m, the
+    first s_sample of the samples."""
+    from oracle import krylov
+    try:
+        import threadpoolctl
+        info = threadpoolctl.threadpool_info()
+        blas_threads = max([i.get("num_threads", 1) for i in info] or [1])
+    except Exception:
+        blas_threads = None
+    A = L.to_scipy()
+    t0 = time.perf_counter()
+    krylov.cbl(A, W[:s_sample], phi, m)
+    dt = time.perf_counter() - t0
+    cores = len(os.sched_getaffinity(0))
+    return dict(value=s_sample / dt, unit="cols/s", cores=blas_threads or cores, host_cores=cores,
+                kind="oracle", seconds=dt,
+                sample=f"float64 CPU oracle cbl on the full graph with the first {s_sample} of the "
+                       f"{len(W)} samples, same phi and m (BLAS threads {blas_threads}; scipy sparse "
+                       f"products single-threaded)")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="rgg100k_spline")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-sample", type=int, default=8)
+    ap.add_argument("--reorder", type=int, default=1)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); multi-GPU sharding is not built",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2301_06384_amd import gk
+    from paper_2301_06384_amd import inputs as I
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    L, W, phi, m = I.workload(args.workload)
+    s = len(W)
+    flags_g = gk.REORDER if args.reorder else 0
+    g = gk.Graph.from_laplacian(L, flags=flags_g)
+    stream = torch.cuda.current_stream()
+    gk.set_stream(stream)
+    Wd = torch.as_tensor(W, device=dev)
+    out = {p: torch.empty((s, L.n), dtype=torch.float64, device=dev) for p in ("mixed", "fp64")}
+    kout = {p: torch.empty((s, s), dtype=torch.float64, device=dev) for p in ("mixed", "fp64")}
+
+    def step(prec, flags=0):
+        gk.krylov_kernel_columns(g, Wd, phi, m, "cbl", prec, flags=gk.IO_DEVICE | flags,
+                                 out_cols=out[prec], out_kww=kout[prec])
+
+    def timed(prec, steps, warmup):
+        for _ in range(warmup):
+            step(prec)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            step(prec)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    ms_mixed = timed("mixed", args.steps, args.warmup)
+    ms_fp64 = timed("fp64", max(2, args.steps // 2), 1)
+    P_m = out["mixed"].cpu().numpy()
+    P_d = out["fp64"].cpu().numpy()
+    err = float(np.linalg.norm(P_m - P_d) / np.linalg.norm(P_d))
+
+    # per-phase device times of one mixed step (HIP events inside the library,
+    # on the stream the kernels run on)
+    st = gk.Stats()
+    p, keep = gk.make_phi(phi)
+    step("mixed", gk.TIMING)
+    torch.cuda.synchronize()
+    _, _, st = gk.krylov_kernel_columns(g, Wd, phi, m, "cbl", "mixed", flags=gk.IO_DEVICE | gk.TIMING,
+                                        out_cols=out["mixed"], out_kww=kout["mixed"])
+    stats = st.as_dict()
+    n_spmm = max(stats["spmm_launches"], 1)
+    spmm_ms = stats["t_spmm_ms"] / n_spmm
+    spmm_bytes = stats["bytes_spmm"] / n_spmm
+    spmm_gbs = spmm_bytes / (spmm_ms * 1e-3) / 1e9
+    src_hash = _kernel_hash(["spmm.hip"])
+    traffic = _traffic_from_profile("spmm_rgg100k_s64_traffic.txt", src_hash)
+    value = s / (ms_mixed * 1e-3)
+    res = {
+        "metric": "kernel cols/s at 1e-5 rel err vs FP64 path",
+        "value": value if err <= 1e-5 else None,
+        "unit": "cols/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_mixed,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64+f32",
+        "data": "synthetic",
+        "config": {"workload": "rgg100k_knn8_spline_eps0.01_k2_s64_m40_cbl", "n": L.n, "nnz": L.nnz,
+                   "s": s, "m": m, "reorder": bool(args.reorder)},
+        "rel_err_vs_fp64_path": err,
+        "fp64_path": {"ms_per_step": ms_fp64, "cols_per_s": s / (ms_fp64 * 1e-3),
+                      "speedup_mixed_over_fp64": ms_fp64 / ms_mixed},
+        "phase_ms": {k: stats[k] for k in ("t_spmm_ms", "t_orth_ms", "t_reorth_ms", "t_phi_ms", "t_asm_ms",
+                                           "t_total_ms")},
+        "phi_method": stats["phi_method"],
+        "roofline": {"kernel": "spmm_diff_kernel", "bound": "hbm", "achieved": spmm_gbs,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": spmm_gbs / HBM_PEAK_GBS,
+                     "traffic": traffic, "avg_launch_ms": spmm_ms, "alg_bytes_per_launch": spmm_bytes},
+    }
+    if not args.no_cpu:
+        res["cpu_baseline"] = cpu_baseline(L, W, phi, m, args.cpu_sample)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,196 @@
+// Internal declarations of the block-Krylov graph-kernel library (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "gk/graph_kernel.h"
+
+namespace gk {
+
+// ------------------------------------------------------------------ errors
+void set_detail(const std::string& msg);
+
+struct Error {
+  int code;
+  std::string msg;
+};
+
+#define GK_HIP(expr)                                                              \
+  do {                                                                            \
+    hipError_t e_ = (expr);                                                       \
+    if (e_ != hipSuccess)                                                         \
+      throw ::gk::Error{GK_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)}; \
+  } while (0)
+
+#define GK_REQUIRE(cond, code, msg) \
+  do {                              \
+    if (!(cond)) throw ::gk::Error{(code), (msg)}; \
+  } while (0)
+
+// ------------------------------------------------------------- allocation
+void* dev_alloc(size_t bytes);
+void dev_free(void* p);
+hipStream_t current_stream();
+
+// A set of device buffers released together (RAII).
+struct Arena {
+  std::vector<void*> ptrs;
+  uint64_t bytes = 0;
+  template <typename T>
+  T* get(size_t count) {
+    size_t b = ((count * sizeof(T) + 255) / 256) * 256;
+    if (b == 0) b = 256;
+    void* p = dev_alloc(b);
+    if (!p) throw Error{GK_ENOMEM, "device allocation of " + std::to_string(b) + " bytes failed"};
+    ptrs.push_back(p);
+    bytes += b;
+    return static_cast<T*>(p);
+  }
+  ~Arena() {
+    for (void* p : ptrs) dev_free(p);
+  }
+};
+
+// ------------------------------------------------------------------ graph
+}  // namespace gk
+
+struct gk_graph {
+  int64_t n = 0;
+  int64_t nnz = 0;          // off-diagonal nonzeros (both triangles)
+  int device = 0;
+  bool unit = false;
+  double lambda_max = 0;    // Gershgorin bound of spec(L)
+  int max_row = 0;          // max off-diagonal entries of a row
+  // device arrays (node order of the device, see perm)
+  int32_t* rp = nullptr;    // n+1
+  int32_t* ci = nullptr;    // nnz
+  double* w64 = nullptr;    // nnz (null for unit weights)
+  float* w32 = nullptr;     // nnz (null for unit weights)
+  double* d64 = nullptr;    // n: sum_j w64_ij + c_i
+  double* d32 = nullptr;    // n: sum_j (double) w32_ij + c_i
+  // node relabelling: device node i is caller node perm[i]
+  bool reordered = false;
+  int64_t* d_perm = nullptr;   // n (device -> caller)
+  int64_t* d_iperm = nullptr;  // n (caller -> device)
+  std::vector<int64_t> h_iperm;
+  std::mutex mu;               // serialises calls that share per-graph scratch
+};
+
+namespace gk {
+
+// block leading dimension for block width s (rows of an n x s block are
+// stored with stride ld; columns s..ld-1 are zero)
+inline int block_ld(int s) { return s <= 8 ? 8 : ((s + 15) / 16) * 16; }
+
+// ----------------------------------------------------------- kernel launchers
+// spmm.hip
+// out[i,c] = a*(L v)_i,c + b*V[i,c] + g*Vprev[i,c]  (difference form), and
+// acc[i,c] += e*out[i,c] if acc != null (e read from e_dev when non-null).
+void launch_spmm(const gk_graph* g, bool fp32_weights, int ld, const double* V, const double* Vprev,
+                 double* out, double a, double b, double gmul, double* acc, double e, const double* e_dev,
+                 hipStream_t st);
+
+// ortho.hip -- tall-skinny products over a list of equally shaped blocks.
+struct BlockList {
+  const void* base = nullptr;   // first block
+  int64_t stride = 0;           // elements between consecutive blocks (may be negative)
+  int nb = 0;                   // number of blocks
+  bool f32 = false;             // element type float (else double)
+};
+size_t gram_scratch_elems(int64_t n, int nb, int ld);
+// C (nb*ld x ld) = A^T B,  B = n x ld double block; `part` scratch
+void launch_gram(int64_t n, int ld, BlockList A, const double* B, double* C, double* part,
+                 const int* flag, hipStream_t st);
+// out = beta*in + alpha*(A * C), C (nb*ld x ld); optional float copy of out
+void launch_tsgemm(int64_t n, int ld, BlockList A, const double* C, const double* in, double* out,
+                   float* out32, double alpha, double beta, const int* flag, hipStream_t st);
+// column-major n x s output P[perm(i), c] = sum_a A[i,a] U[a,c]
+void launch_assemble(int64_t n, int ld, int s, BlockList A, const double* U, int ldu, double* P,
+                     const int64_t* perm, hipStream_t st);
+// P[perm(i), c] = sum_k D[k*ld + c] * A_k[i, c]
+void launch_assemble_diag(int64_t n, int ld, int s, BlockList A, const double* D, double* P,
+                          const int64_t* perm, bool colmajor, hipStream_t st);
+size_t coldots_scratch_elems(int64_t n, int nb, int ld);
+// out[k*ld + c] = sum_i A_k[i,c] * B[i,c]
+void launch_coldots(int64_t n, int ld, BlockList A, const double* B, double* out, double* part,
+                    const int* flag, hipStream_t st);
+// X[i,c] -= sum_k D[k*ld + c] * A_k[i,c]
+void launch_axpy_diag(int64_t n, int ld, BlockList A, const double* D, double* X, const int* flag,
+                      hipStream_t st);
+// Y[i,c] = X[i,c] * scale[c] (and optional float copy)
+void launch_colscale(int64_t n, int ld, const double* X, const double* scale, double* Y, float* Y32,
+                     hipStream_t st);
+// out[r*s + c] = sum_k D[k*ld + c] * A_k[rows[r], c]
+void launch_gather_diag(int64_t n, int ld, int s, BlockList A, const double* D, const int64_t* rows,
+                        double* out, hipStream_t st);
+void launch_start_block(int64_t n, int ld, int s, const int64_t* dev_samples, double value, double* V,
+                        float* V32, hipStream_t st);
+void launch_zero(void* p, size_t bytes, hipStream_t st);
+void launch_copy_f64_to_f32(const double* a, float* b, size_t count, hipStream_t st);
+
+// small.hip -- small dense FP64 work in one workgroup
+void launch_cholqr_factor(const double* G, int ld, int s, int pass, const double* diag_prev, double thr,
+                          double* W, double* R, double* Rinv, double* diag_out, int* n_defl,
+                          hipStream_t st);
+void launch_small_gemm(int M, int N, int K, const double* A, int lda, bool ta, const double* B, int ldb,
+                       bool tb, double* C, int ldc, double alpha, double beta, hipStream_t st);
+void launch_store_H(const double* C, int ld, int s, double* Hk, hipStream_t st);
+void launch_assemble_T(int m, int s, const double* Hd, const double* Bd, double* T, int ldt,
+                       hipStream_t st);
+void launch_sym_eig(int n, double* A, int lda, double* V, int ldv, double* theta, int batch,
+                    int64_t strideA, int64_t strideV, int64_t strideTheta, int* order_ws, double* cs_ws,
+                    hipStream_t st);
+size_t eig_order_elems(int n, int batch);
+void launch_phi_values(int n, const double* theta, const gk_phi& phi, const double* poly_dev, double* fv,
+                       bool use_sqrt, int* bad, hipStream_t st);
+void launch_phi_apply(int n, int s, const double* S, int lds, const double* fv, double* U, int ldu,
+                      double outer, hipStream_t st);
+void launch_kww_gram(int n, int s, const double* S, int lds, const double* g, double* K, hipStream_t st);
+size_t banded_work_elems(int m, int s);
+void launch_banded_spline(int m, int s, const double* Hd, const double* Bd, double eps, int k,
+                          double* work, double* U, int* bad, hipStream_t st);
+void launch_small_solve(int s, const double* K, double gamma, const double* y, double* c, double* work,
+                        int* piv, bool spd, int* bad, hipStream_t st);
+
+// krylov.hip -- one call of the compute entry points
+struct CallArgs {
+  gk_graph* g;
+  const int64_t* samples;
+  int32_t s;
+  const gk_phi* phi;
+  int32_t m, variant, precision;
+  uint32_t flags;
+  const double* y;        // fit only
+  double gamma;
+  double* cols_out;
+  double* kww_out;
+  double* coef_out;
+  double* pred_out;
+  gk_stats* st;
+  bool fit;
+};
+int run_call(const CallArgs& a, hipStream_t stream);
+uint64_t footprint_bytes(int64_t n, int s, int m, int variant, int precision);
+void set_thread_stream(hipStream_t s);
+
+// ------------------------------------------------------------- timing
+struct PhaseTimer {
+  bool on = false;
+  hipStream_t st = nullptr;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev;
+  int cur = -1;
+  hipEvent_t cur_start = nullptr;
+  void begin(int phase);
+  void end();
+  void collect(gk_stats* s);
+  ~PhaseTimer();
+};
+enum Phase { PH_SPMM = 0, PH_ORTH, PH_REORTH, PH_PHI, PH_ASM, PH_FIT, PH_TOTAL };
+
+}  // namespace gk

@@ -1,0 +1,788 @@
+// Krylov drivers: classical block Lanczos (Alg. 1), global block Lanczos
+// (Alg. 2), sequential Lanczos (Sec. 3.3), Chebyshev and squared Chebyshev
+// (Sec. 3.4), followed by phi of the projected matrix, assembly of the kernel
+// columns and the kernel RLS machine (Sec. 2.3, Alg. 3).
+//
+// Every step is enqueued on one stream; all data-dependent decisions
+// (deflation, breakdown) are taken on the device, so the host never waits
+// inside the iteration.
+//
+// Precision paths
+//   GK_FP64  : all blocks float64; each new block is orthogonalised against
+//              its two predecessors and then twice against the whole basis.
+//   GK_MIXED : the three-term recurrence (current and previous block, X) and
+//              all small factors stay float64, the operator uses float32
+//              weights and the basis is archived in float32 for the
+//              reorthogonalisation against older blocks and the final
+//              assembly.  Rounding the recurrence vectors themselves would
+//              perturb the Krylov space at first order (the unconverged Ritz
+//              values move), which the near-singular spline kernels amplify
+//              beyond a 1e-5 budget; the archive copy only enters through
+//              small projection coefficients and the final linear
+//              combination.
+#include <cmath>
+
+#include "gk_internal.h"
+
+namespace gk {
+
+// ------------------------------------------------------------ glue kernels
+// Upad[b*ld + r, c] = U[b*s + r, c] (r < s), zero for padding rows
+__global__ void pad_rows_kernel(int nb, int s, int ld, const double* __restrict__ U, double* __restrict__ Up) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t tot = (int64_t)nb * ld * s;
+  if (t >= tot) return;
+  const int c = (int)(t % s);
+  const int64_t row = t / s;
+  const int b = (int)(row / ld), r = (int)(row % ld);
+  Up[t] = (r < s) ? U[((int64_t)b * s + r) * s + c] : 0.0;
+}
+
+// gbl: coef_j = sum_{c<s} cd[j*ld + c]; D[j*ld + c] = coef_j (c < ld);
+// optionally store coef of the last block into alpha_out
+__global__ void frob_coef_kernel(int nb, int s, int ld, const double* __restrict__ cd, double* __restrict__ D,
+                                 double* __restrict__ alpha_out) {
+  const int j = blockIdx.x;
+  __shared__ double red[256];
+  double v = 0.0;
+  for (int c = threadIdx.x; c < s; c += 256) v += cd[j * ld + c];
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  const double coef = red[0];
+  for (int c = threadIdx.x; c < ld; c += 256) D[j * ld + c] = (c < s) ? coef : 0.0;
+  if (threadIdx.x == 0 && alpha_out && j == nb - 1) *alpha_out = coef;
+}
+
+// gbl norm: beta = ||X||_F from column sums of squares; scale = 1/beta or 0
+__global__ void frob_norm_kernel(int s, int ld, const double* __restrict__ cd, double thr,
+                                 double* __restrict__ beta_out, double* __restrict__ scale,
+                                 double* __restrict__ resid) {
+  __shared__ double red[256];
+  double v = 0.0;
+  for (int c = threadIdx.x; c < s; c += 256) v += cd[c];
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  const double b = sqrt(red[0]);
+  const double keep = (b >= thr) ? b : 0.0;
+  if (threadIdx.x == 0) {
+    if (beta_out) *beta_out = keep;
+    if (resid) *resid = b;
+  }
+  for (int c = threadIdx.x; c < ld; c += 256) scale[c] = (keep > 0.0 && c < s) ? 1.0 / keep : 0.0;
+}
+
+// sbl: per-column norms beta_c = sqrt(cd[c]); scale_c = 1/beta_c or 0
+__global__ void col_norm_kernel(int s, int ld, const double* __restrict__ cd, double thr,
+                                double* __restrict__ beta_out, double* __restrict__ scale,
+                                double* __restrict__ resid) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ld) return;
+  double b = (c < s) ? sqrt(cd[c]) : 0.0;
+  const double keep = (b >= thr) ? b : 0.0;
+  if (c < s && beta_out) beta_out[c] = keep;
+  if (c < s && resid) resid[c] = b;
+  scale[c] = (keep > 0.0) ? 1.0 / keep : 0.0;
+}
+
+// dense symmetric tridiagonal matrices from (alpha, beta): batch b uses
+// alpha[k*astride + b], beta[k*astride + b]
+__global__ void tridiag_dense_kernel(int m, int batch, int astride, const double* __restrict__ alpha,
+                                     const double* __restrict__ beta, double* __restrict__ T) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t per = (int64_t)m * m;
+  if (t >= per * batch) return;
+  const int b = (int)(t / per);
+  const int r = (int)((t % per) / m), c = (int)(t % m);
+  double v = 0.0;
+  if (r == c) v = alpha[(int64_t)r * astride + b];
+  else if (r == c + 1) v = beta[(int64_t)c * astride + b];
+  else if (c == r + 1) v = beta[(int64_t)r * astride + b];
+  T[t] = v;
+}
+
+// sequential: D[k*ld + c] = outer * sum_l S_c[k, l] fv_c[l] S_c[0, l]
+__global__ void seq_coef_kernel(int m, int s, int ld, const double* __restrict__ S,
+                                const double* __restrict__ fv, double* __restrict__ D) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= m * ld) return;
+  const int k = t / ld, c = t % ld;
+  if (c >= s) {
+    D[t] = 0.0;
+    return;
+  }
+  const double* Sc = S + (int64_t)c * m * m;
+  const double* fc = fv + (int64_t)c * m;
+  double acc = 0.0;
+  for (int l = 0; l < m; ++l) acc = fma(Sc[k * m + l] * fc[l], Sc[l], acc);
+  D[t] = acc;
+}
+
+// gbl: D[k*ld + c] = u[k] (c < s)
+__global__ void bcast_coef_kernel(int m, int s, int ld, const double* __restrict__ u, double* __restrict__ D) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= m * ld) return;
+  const int k = t / ld, c = t % ld;
+  D[t] = (c < s) ? u[k] : 0.0;
+}
+
+// z[k*ld + c] = D[k*ld + c] * coef[c]
+__global__ void zdiag_kernel(int m, int s, int ld, const double* __restrict__ D, const double* __restrict__ coef,
+                             double* __restrict__ z) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= m * ld) return;
+  const int c = t % ld;
+  z[t] = (c < s) ? D[t] * coef[c] : 0.0;
+}
+
+// Chebyshev-Lobatto coefficients of phi (or sqrt(phi)) of degree deg on
+// [0, Lam]: a_k = (2/deg) sum_j'' f(lam_j) cos(pi j k / deg), lam_j =
+// (Lam/2)(1 - cos(pi j / deg)); a_0 and a_deg halved (Sec. 3.4, standard
+// Lobatto interpolant).
+__global__ void cheb_coef_kernel(int deg, double Lam, int kind, double t, double eps, double kexp,
+                                 const double* __restrict__ poly, int plen, int use_sqrt,
+                                 double* __restrict__ a, int* __restrict__ bad) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k > deg) return;
+  const double pi = 3.14159265358979323846;
+  double acc = 0.0;
+  for (int j = 0; j <= deg; ++j) {
+    const double lam = 0.5 * Lam * (1.0 - cos(pi * j / deg));
+    double f;
+    if (kind == GK_PHI_DIFFUSION) {
+      f = exp(-t * lam);
+    } else if (kind == GK_PHI_SPLINE) {
+      f = pow(eps + lam, -kexp);
+    } else {
+      f = 0.0;
+      for (int q = plen - 1; q >= 0; --q) f = f * lam + poly[q];
+    }
+    if (use_sqrt) {
+      if (f < 0.0) {
+        *bad = 2;
+        f = 0.0;
+      }
+      f = sqrt(f);
+    }
+    const double w = (j == 0 || j == deg) ? 0.5 : 1.0;
+    acc += w * f * cos(pi * (double)j * (double)k / deg);
+  }
+  acc *= 2.0 / deg;
+  if (k == 0 || k == deg) acc *= 0.5;
+  a[k] = acc;
+}
+
+// out = sqrt(sum_{c<s} G[c, c])
+__global__ void trace_sqrt_kernel(const double* __restrict__ G, int ld, int s, double* __restrict__ out) {
+  __shared__ double red[256];
+  double v = 0.0;
+  for (int c = threadIdx.x; c < s; c += 256) v += G[(int64_t)c * ld + c];
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = sqrt(red[0]);
+}
+
+// acc = a0 * Y
+__global__ void scale_copy_kernel(int64_t cnt, const double* __restrict__ a0, const double* __restrict__ Y,
+                                  double* __restrict__ acc) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < cnt) acc[i] = (*a0) * Y[i];
+}
+
+// column-major copy of a row-major s x s matrix
+__global__ void transpose_kernel(int s, const double* __restrict__ A, double* __restrict__ B) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= s * s) return;
+  const int r = t / s, c = t % s;
+  B[(int64_t)c * s + r] = A[t];
+}
+
+__global__ void fill_kernel(double* __restrict__ p, int cnt, double v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < cnt) p[i] = v;
+}
+
+// samples given in caller numbering -> device numbering
+__global__ void map_samples_kernel(int s, const int64_t* __restrict__ in, const int64_t* __restrict__ iperm,
+                                   int64_t* __restrict__ out) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < s) out[j] = iperm ? iperm[in[j]] : in[j];
+}
+
+static inline unsigned nblk(int64_t n, int b = 256) { return (unsigned)((n + b - 1) / b); }
+
+// ------------------------------------------------------------ job state
+struct Job {
+  gk_graph* g = nullptr;
+  int s = 0, ld = 0, m = 0, variant = 0, precision = 0;
+  uint32_t flags = 0;
+  gk_phi phi{};
+  hipStream_t st = nullptr;
+  Arena ar;
+  PhaseTimer tm;
+  int64_t* samp = nullptr;        // device numbering
+  int* dflags = nullptr;          // [0] phi bad, [1] deflations, [2] solve bad, [3] reorth count
+  double* dscal = nullptr;        // [0] residual norm
+  double* poly_dev = nullptr;
+  bool mixed() const { return precision == GK_MIXED; }
+  double thr() const { return 1e-12 * g->lambda_max; }
+  // result of the Krylov stage
+  BlockList arch;                 // archived basis (nb blocks)
+  double* Upad = nullptr;         // dense coefficients (nb*ld x s) or null
+  double* D = nullptr;            // diagonal coefficients (nb*ld) or null
+  double* K = nullptr;            // s x s sampled block
+  bool spd = false;               // K symmetric positive definite by construction
+  int phi_method = 0;
+};
+
+static void phi_check(const gk_phi& p) {
+  if (p.kind == GK_PHI_DIFFUSION) {
+    GK_REQUIRE(std::isfinite(p.t) && p.t >= 0.0, GK_EINVAL, "diffusion needs finite t >= 0");
+  } else if (p.kind == GK_PHI_SPLINE) {
+    GK_REQUIRE(std::isfinite(p.eps) && p.eps > 0.0, GK_EINVAL, "spline needs eps > 0");
+    GK_REQUIRE(std::isfinite(p.k) && p.k > 0.0, GK_EINVAL, "spline needs k > 0");
+  } else if (p.kind == GK_PHI_POLYNOMIAL) {
+    GK_REQUIRE(p.poly && p.poly_len >= 1 && p.poly_len <= 4096, GK_EINVAL, "polynomial needs coefficients");
+    for (int i = 0; i < p.poly_len; ++i) GK_REQUIRE(std::isfinite(p.poly[i]), GK_EINVAL, "non-finite coefficient");
+  } else {
+    throw Error{GK_EINVAL, "unknown phi kind"};
+  }
+}
+
+// ------------------------------------------------------------- phi stage
+// U (m*s x s) = phi(H_m) F_1 and K = F_1^T phi(H_m) F_1 from the blocks
+// (Hd: H_kk, Bd: H_{k+1,k}) of the block tridiagonal projected matrix.
+static void phi_stage_block(Job& J, const double* Hd, const double* Bd, double* U, double* K) {
+  const int m = J.m, s = J.s;
+  const int ms = m * s;
+  const double kk = J.phi.k;
+  const bool int_spline = J.phi.kind == GK_PHI_SPLINE && kk == std::floor(kk) && kk >= 1 && kk <= 16;
+  if (int_spline && !(J.flags & GK_PHI_EIG)) {
+    // exact banded evaluation (block tridiagonal Cholesky solves)
+    double* work = J.ar.get<double>(banded_work_elems(m, s));
+    launch_banded_spline(m, s, Hd, Bd, J.phi.eps, (int)kk, work, U, J.dflags + 0, J.st);
+    launch_store_H(U, s, s, K, J.st);          // K = sym(U[0:s, :])
+    J.phi_method = 1;
+    return;
+  }
+  // spectral decomposition H_m = S Theta S^T (Sec. 6, Table 1 row phi(H_m))
+  double* T = J.ar.get<double>((size_t)ms * ms);
+  double* S = J.ar.get<double>((size_t)ms * ms);
+  double* th = J.ar.get<double>(ms);
+  double* fv = J.ar.get<double>(ms);
+  int* ord = J.ar.get<int>(eig_order_elems(ms, 1));
+  double* cs = J.ar.get<double>(eig_order_elems(ms, 1));
+  launch_assemble_T(m, s, Hd, Bd, T, ms, J.st);
+  launch_sym_eig(ms, T, ms, S, ms, th, 1, 0, 0, 0, ord, cs, J.st);
+  launch_phi_values(ms, th, J.phi, J.poly_dev, fv, false, J.dflags + 0, J.st);
+  launch_phi_apply(ms, s, S, ms, fv, U, s, 1.0, J.st);
+  if (J.phi.kind != GK_PHI_POLYNOMIAL) {
+    double* g = J.ar.get<double>(ms);
+    launch_phi_values(ms, th, J.phi, J.poly_dev, g, true, J.dflags + 0, J.st);
+    launch_kww_gram(ms, s, S, ms, g, K, J.st);  // SPD by construction (Theorem 3.1)
+  } else {
+    launch_store_H(U, s, s, K, J.st);
+  }
+  J.phi_method = 0;
+}
+
+// ---------------------------------------------------------------- cbl
+static void run_cbl(Job& J) {
+  gk_graph* g = J.g;
+  const int64_t n = g->n;
+  const int ld = J.ld, m = J.m, s = J.s;
+  const int64_t blk = n * ld;
+  const bool mixed = J.mixed();
+  const bool full = !mixed || (J.flags & GK_FULL_REORTH);
+  const bool no_reorth = mixed && (J.flags & 0x10u);
+  hipStream_t st = J.st;
+  // storage
+  double* Vb = nullptr;     // FP64 basis (GK_FP64)
+  double* ring = nullptr;   // 3 FP64 recurrence blocks (GK_MIXED)
+  float* Va = nullptr;      // FP32 archive (GK_MIXED)
+  if (!mixed) Vb = J.ar.get<double>((size_t)m * blk);
+  else {
+    ring = J.ar.get<double>((size_t)3 * blk);
+    Va = J.ar.get<float>((size_t)m * blk);
+  }
+  double* X = J.ar.get<double>(blk);
+  double* Y = J.ar.get<double>(blk);
+  // scratch for every block count the Gram launches use (1 .. m)
+  size_t pe = 0;
+  for (int nb = 1; nb <= (full ? m : 2); ++nb) pe = std::max(pe, gram_scratch_elems(n, nb, ld));
+  double* part = J.ar.get<double>(pe);
+  double* C = J.ar.get<double>((size_t)m * ld * ld);
+  const size_t l2 = (size_t)ld * ld;
+  double* G = J.ar.get<double>(l2);
+  double* W = J.ar.get<double>(l2);
+  double* R1 = J.ar.get<double>(l2);
+  double* R1i = J.ar.get<double>(l2);
+  double* R2 = J.ar.get<double>(l2);
+  double* R2i = J.ar.get<double>(l2);
+  double* R12i = J.ar.get<double>(l2);
+  double* d1 = J.ar.get<double>(ld);
+  double* d2 = J.ar.get<double>(ld);
+  double* Hd = J.ar.get<double>((size_t)m * s * s);
+  double* Bd = J.ar.get<double>((size_t)m * s * s);
+  launch_zero(Bd, (size_t)m * s * s * sizeof(double), st);
+
+  auto V64 = [&](int k) -> double* { return mixed ? ring + (int64_t)(k % 3) * blk : Vb + (int64_t)k * blk; };
+  // start block Q_1 = E_W (Alg. 1)
+  launch_start_block(n, ld, s, J.samp, 1.0, V64(0), mixed ? Va : nullptr, st);
+
+  for (int k = 0; k < m; ++k) {
+    double* Vk = V64(k);
+    // X = L Q_k
+    J.tm.begin(PH_SPMM);
+    launch_spmm(g, mixed, ld, Vk, nullptr, X, 1.0, 0.0, 0.0, nullptr, 0.0, nullptr, st);
+    J.tm.begin(PH_ORTH);
+    // local block: [Q_{k-1}, Q_k];  C = local^T X; H_kk = sym(C_k); X -= local C
+    BlockList loc;
+    if (k > 0) {
+      double* Vkm1 = V64(k - 1);
+      loc = BlockList{Vkm1, (int64_t)(Vk - Vkm1), 2, false};
+    } else {
+      loc = BlockList{Vk, blk, 1, false};
+    }
+    launch_gram(n, ld, loc, X, C, part, nullptr, st);
+    launch_store_H(C + (int64_t)(loc.nb - 1) * l2, ld, s, Hd + (int64_t)k * s * s, st);
+    launch_tsgemm(n, ld, loc, C, X, X, nullptr, -1.0, 1.0, nullptr, st);
+    // second local pass (both paths)
+    launch_gram(n, ld, loc, X, C, part, nullptr, st);
+    launch_tsgemm(n, ld, loc, C, X, X, nullptr, -1.0, 1.0, nullptr, st);
+    J.tm.begin(PH_REORTH);
+    if (!no_reorth && full && k >= 1) {
+      BlockList all = mixed ? BlockList{Va, blk, k + 1, true} : BlockList{Vb, blk, k + 1, false};
+      for (int pass = 0; pass < 2; ++pass) {
+        launch_gram(n, ld, all, X, C, part, nullptr, st);
+        launch_tsgemm(n, ld, all, C, X, X, nullptr, -1.0, 1.0, nullptr, st);
+      }
+    }
+    J.tm.begin(PH_ORTH);
+    BlockList xl{X, blk, 1, false};
+    launch_gram(n, ld, xl, X, G, part, nullptr, st);
+    if (k + 1 < m) {
+      // CholQR2: X = Q_{k+1} H_{k+1,k}
+      launch_cholqr_factor(G, ld, s, 1, nullptr, J.thr(), W, R1, R1i, d1, nullptr, st);
+      launch_tsgemm(n, ld, xl, R1i, nullptr, Y, nullptr, 1.0, 0.0, nullptr, st);
+      BlockList yl{Y, blk, 1, false};
+      launch_gram(n, ld, yl, Y, G, part, nullptr, st);
+      launch_cholqr_factor(G, ld, s, 2, d1, J.thr(), W, R2, R2i, d2, J.dflags + 1, st);
+      launch_small_gemm(ld, ld, ld, R1i, ld, false, R2i, ld, false, R12i, ld, 1.0, 0.0, st);
+      launch_small_gemm(s, s, s, R2, ld, false, R1, ld, false, Bd + (int64_t)k * s * s, s, 1.0, 0.0, st);
+      launch_tsgemm(n, ld, xl, R12i, nullptr, V64(k + 1), mixed ? Va + (int64_t)(k + 1) * blk : nullptr,
+                    1.0, 0.0, nullptr, st);
+    } else {
+      // ||X_m||_F: residual indicator (the unused H_{m+1,m})
+      hipLaunchKernelGGL(trace_sqrt_kernel, dim3(1), dim3(256), 0, st, G, ld, s, J.dscal);
+      GK_HIP(hipGetLastError());
+    }
+  }
+  J.tm.begin(PH_PHI);
+  double* U = J.ar.get<double>((size_t)m * s * s);
+  J.K = J.ar.get<double>((size_t)s * s);
+  phi_stage_block(J, Hd, Bd, U, J.K);
+  J.Upad = J.ar.get<double>((size_t)m * ld * s);
+  hipLaunchKernelGGL(pad_rows_kernel, dim3(nblk((int64_t)m * ld * s)), dim3(256), 0, st, m, s, ld, U, J.Upad);
+  GK_HIP(hipGetLastError());
+  J.arch = mixed ? BlockList{Va, blk, m, true} : BlockList{Vb, blk, m, false};
+  J.spd = J.phi.kind != GK_PHI_POLYNOMIAL;
+  // residual: sqrt(trace(G)) of the last iteration
+  J.tm.end();
+}
+
+// ---------------------------------------------------------------- gbl / sbl
+static void run_scalar_lanczos(Job& J, bool global) {
+  gk_graph* g = J.g;
+  const int64_t n = g->n;
+  const int ld = J.ld, m = J.m, s = J.s;
+  const int64_t blk = n * ld;
+  const bool mixed = J.mixed();
+  const bool full = !mixed || (J.flags & GK_FULL_REORTH);
+  const bool no_reorth = mixed && (J.flags & 0x10u);
+  hipStream_t st = J.st;
+  double* Vb = nullptr;
+  double* ring = nullptr;
+  float* Va = nullptr;
+  if (!mixed) Vb = J.ar.get<double>((size_t)m * blk);
+  else {
+    ring = J.ar.get<double>((size_t)3 * blk);
+    Va = J.ar.get<float>((size_t)m * blk);
+  }
+  double* X = J.ar.get<double>(blk);
+  double* part = J.ar.get<double>(coldots_scratch_elems(n, m, ld));
+  double* cd = J.ar.get<double>((size_t)m * ld);
+  double* D = J.ar.get<double>((size_t)m * ld);
+  double* scale = J.ar.get<double>(ld);
+  // alpha / beta: global -> m scalars; sequential -> m x s
+  const int ab = global ? 1 : s;
+  double* alpha = J.ar.get<double>((size_t)m * ab);
+  double* beta = J.ar.get<double>((size_t)m * ab);
+  launch_zero(beta, (size_t)m * ab * sizeof(double), st);
+  double* resid = J.ar.get<double>(ab);
+  auto V64 = [&](int k) -> double* { return mixed ? ring + (int64_t)(k % 3) * blk : Vb + (int64_t)k * blk; };
+  // Q_1 = E_W / sqrt(N) (Alg. 2) or E_W (sequential, each column a unit vector)
+  launch_start_block(n, ld, s, J.samp, global ? 1.0 / std::sqrt((double)s) : 1.0, V64(0),
+                     mixed ? Va : nullptr, st);
+  for (int k = 0; k < m; ++k) {
+    double* Vk = V64(k);
+    J.tm.begin(PH_SPMM);
+    launch_spmm(g, mixed, ld, Vk, nullptr, X, 1.0, 0.0, 0.0, nullptr, 0.0, nullptr, st);
+    J.tm.begin(PH_ORTH);
+    BlockList loc = (k > 0) ? BlockList{V64(k - 1), (int64_t)(Vk - V64(k - 1)), 2, false}
+                            : BlockList{Vk, blk, 1, false};
+    for (int pass = 0; pass < 2; ++pass) {
+      launch_coldots(n, ld, loc, X, cd, part, nullptr, st);
+      if (global) {
+        hipLaunchKernelGGL(frob_coef_kernel, dim3(loc.nb), dim3(256), 0, st, loc.nb, s, ld, cd, D,
+                           pass == 0 ? alpha + k : (double*)nullptr);
+      } else {
+        // per-column coefficients are the dots themselves; alpha_k = D of Q_k
+        GK_HIP(hipMemcpyAsync(D, cd, sizeof(double) * loc.nb * ld, hipMemcpyDeviceToDevice, st));
+        if (pass == 0)
+          GK_HIP(hipMemcpyAsync(alpha + (int64_t)k * s, cd + (int64_t)(loc.nb - 1) * ld, sizeof(double) * s,
+                                hipMemcpyDeviceToDevice, st));
+      }
+      GK_HIP(hipGetLastError());
+      launch_axpy_diag(n, ld, loc, D, X, nullptr, st);
+    }
+    J.tm.begin(PH_REORTH);
+    if (!no_reorth && full && k >= 1) {
+      BlockList all = mixed ? BlockList{Va, blk, k + 1, true} : BlockList{Vb, blk, k + 1, false};
+      for (int pass = 0; pass < 2; ++pass) {
+        launch_coldots(n, ld, all, X, cd, part, nullptr, st);
+        if (global)
+          hipLaunchKernelGGL(frob_coef_kernel, dim3(all.nb), dim3(256), 0, st, all.nb, s, ld, cd, D,
+                             (double*)nullptr);
+        else
+          GK_HIP(hipMemcpyAsync(D, cd, sizeof(double) * all.nb * ld, hipMemcpyDeviceToDevice, st));
+        launch_axpy_diag(n, ld, all, D, X, nullptr, st);
+      }
+    }
+    J.tm.begin(PH_ORTH);
+    BlockList xl{X, blk, 1, false};
+    launch_coldots(n, ld, xl, X, cd, part, nullptr, st);
+    if (global)
+      hipLaunchKernelGGL(frob_norm_kernel, dim3(1), dim3(256), 0, st, s, ld, cd, J.thr(),
+                         (k + 1 < m) ? beta + k : (double*)nullptr, scale, resid);
+    else
+      hipLaunchKernelGGL(col_norm_kernel, dim3(nblk(ld)), dim3(256), 0, st, s, ld, cd, J.thr(),
+                         (k + 1 < m) ? beta + (int64_t)k * s : (double*)nullptr, scale, resid);
+    GK_HIP(hipGetLastError());
+    if (k + 1 < m) launch_colscale(n, ld, X, scale, V64(k + 1), mixed ? Va + (int64_t)(k + 1) * blk : nullptr, st);
+  }
+  J.tm.begin(PH_PHI);
+  // tridiagonal H_m (global) or s tridiagonal H_m^(w) (sequential): eigh
+  const int batch = global ? 1 : s;
+  const int64_t mm = (int64_t)m * m;
+  double* T = J.ar.get<double>((size_t)mm * batch);
+  double* S = J.ar.get<double>((size_t)mm * batch);
+  double* th = J.ar.get<double>((size_t)m * batch);
+  double* fv = J.ar.get<double>((size_t)m * batch);
+  int* ord = J.ar.get<int>(eig_order_elems(m, batch));
+  double* cs = J.ar.get<double>(eig_order_elems(m, batch));
+  hipLaunchKernelGGL(tridiag_dense_kernel, dim3(nblk(mm * batch)), dim3(256), 0, st, m, batch, ab, alpha, beta, T);
+  GK_HIP(hipGetLastError());
+  launch_sym_eig(m, T, m, S, m, th, batch, mm, mm, m, ord, cs, st);
+  launch_phi_values(m * batch, th, J.phi, J.poly_dev, fv, false, J.dflags + 0, st);
+  J.D = J.ar.get<double>((size_t)m * ld);
+  if (global) {
+    double* u = J.ar.get<double>(m);
+    launch_phi_apply(m, 1, S, m, fv, u, 1, std::sqrt((double)s), st);   // u = sqrt(N) phi(H_m) f_1
+    hipLaunchKernelGGL(bcast_coef_kernel, dim3(nblk((int64_t)m * ld)), dim3(256), 0, st, m, s, ld, u, J.D);
+  } else {
+    hipLaunchKernelGGL(seq_coef_kernel, dim3(nblk((int64_t)m * ld)), dim3(256), 0, st, m, s, ld, S, fv, J.D);
+  }
+  GK_HIP(hipGetLastError());
+  J.arch = mixed ? BlockList{Va, blk, m, true} : BlockList{Vb, blk, m, false};
+  J.K = J.ar.get<double>((size_t)s * s);
+  launch_gather_diag(n, ld, s, J.arch, J.D, J.samp, J.K, st);   // K = E_W^T P
+  J.spd = false;
+  J.phi_method = 0;
+  J.tm.end();
+}
+
+// ------------------------------------------------------------- Chebyshev
+static void run_cheb(Job& J, bool squared) {
+  gk_graph* g = J.g;
+  const int64_t n = g->n;
+  const int ld = J.ld, s = J.s;
+  const int64_t blk = n * ld;
+  const bool mixed = J.mixed();
+  hipStream_t st = J.st;
+  const double Lam = g->lambda_max;
+  const int deg = squared ? std::max(J.m / 2, 1) : J.m;
+  double* a = J.ar.get<double>(deg + 1);
+  hipLaunchKernelGGL(cheb_coef_kernel, dim3(nblk(deg + 1)), dim3(256), 0, st, deg, Lam, J.phi.kind, J.phi.t,
+                     J.phi.eps, J.phi.k, J.poly_dev, J.phi.poly_len, squared ? 1 : 0, a, J.dflags + 0);
+  GK_HIP(hipGetLastError());
+  double* ring = J.ar.get<double>((size_t)3 * blk);
+  double* acc = J.ar.get<double>(blk);
+  double* acc2 = squared ? J.ar.get<double>(blk) : nullptr;
+  auto Yb = [&](int k) -> double* { return ring + (int64_t)(k % 3) * blk; };
+  launch_start_block(n, ld, s, J.samp, 1.0, Yb(0), nullptr, st);
+  for (int rep = 0; rep < (squared ? 2 : 1); ++rep) {
+    double* out = (rep == 0) ? acc : acc2;
+    if (rep == 1) GK_HIP(hipMemcpyAsync(Yb(0), acc, sizeof(double) * blk, hipMemcpyDeviceToDevice, st));
+    hipLaunchKernelGGL(scale_copy_kernel, dim3(nblk(blk)), dim3(256), 0, st, blk, a, Yb(0), out);
+    GK_HIP(hipGetLastError());
+    J.tm.begin(PH_SPMM);
+    // T_1(x) = x with x = I - (2/Lam) L ; T_{k+1} = 2 x T_k - T_{k-1}
+    if (deg >= 1) launch_spmm(g, mixed, ld, Yb(0), nullptr, Yb(1), -2.0 / Lam, 1.0, 0.0, out, 0.0, a + 1, st);
+    for (int k = 1; k < deg; ++k)
+      launch_spmm(g, mixed, ld, Yb(k), Yb(k - 1), Yb(k + 1), -4.0 / Lam, 2.0, -1.0, out, 0.0, a + k + 1, st);
+    J.tm.end();
+  }
+  double* P = squared ? acc2 : acc;
+  J.arch = BlockList{P, blk, 1, false};
+  J.D = J.ar.get<double>(ld);
+  hipLaunchKernelGGL(fill_kernel, dim3(nblk(ld)), dim3(256), 0, st, J.D, ld, 1.0);
+  GK_HIP(hipGetLastError());
+  J.K = J.ar.get<double>((size_t)s * s);
+  launch_gather_diag(n, ld, s, J.arch, J.D, J.samp, J.K, st);
+  J.spd = false;
+  J.phi_method = 2;
+}
+
+// ----------------------------------------------------------- call wrapper
+uint64_t footprint_bytes(int64_t n, int s, int m, int variant, int precision) {
+  const int ld = block_ld(s);
+  const double blk8 = (double)n * ld * 8.0;
+  double b = 0;
+  const bool mixed = precision == GK_MIXED;
+  if (variant == GK_CHEB || variant == GK_CHEB2) {
+    b = blk8 * (variant == GK_CHEB2 ? 5 : 4);
+  } else {
+    b = mixed ? (3 * blk8 + m * blk8 / 2) : m * blk8;
+    b += 2 * blk8;   // X, Y
+    const double ms = (double)m * s;
+    if (variant == GK_CBL) b += 2 * ms * ms * 8.0 + (double)m * ld * ld * 8.0 + 4.0 * m * s * s * 8.0;
+  }
+  b += (double)n * s * 8.0 + 64.0 * (1 << 20);   // output staging + small scratch
+  return (uint64_t)b;
+}
+
+static void validate_common(const CallArgs& a) {
+  GK_REQUIRE(a.g, GK_EINVAL, "graph is NULL");
+  GK_REQUIRE(a.s >= 1 && a.s <= 1024, GK_EINVAL, "s must be in [1, 1024]");
+  GK_REQUIRE(a.m >= 1 && a.m <= 4096, GK_EINVAL, "m must be in [1, 4096]");
+  GK_REQUIRE(a.phi, GK_EINVAL, "phi is NULL");
+  GK_REQUIRE(a.samples, GK_EINVAL, "samples is NULL");
+  GK_REQUIRE(a.variant >= GK_CBL && a.variant <= GK_CHEB2, GK_EINVAL, "unknown variant");
+  GK_REQUIRE(a.precision == GK_FP64 || a.precision == GK_MIXED, GK_EINVAL, "unknown precision");
+  phi_check(*a.phi);
+  if (a.fit) {
+    GK_REQUIRE(a.y, GK_EINVAL, "y is NULL");
+    GK_REQUIRE(std::isfinite(a.gamma) && a.gamma >= 0.0, GK_EINVAL, "gamma must be finite and >= 0");
+  }
+  const int64_t ms = (int64_t)a.m * a.s;
+  if (a.variant == GK_CBL && (!(a.phi->kind == GK_PHI_SPLINE && a.phi->k == std::floor(a.phi->k) &&
+                                a.phi->k <= 16) || (a.flags & GK_PHI_EIG)))
+    GK_REQUIRE(ms <= 16384, GK_EUNSUPPORTED, "spectral decomposition limited to m*s <= 16384");
+}
+
+static void check_samples_host(const int64_t* h, int s, int64_t n) {
+  std::vector<int64_t> v(h, h + s);
+  for (int64_t x : v) GK_REQUIRE(x >= 0 && x < n, GK_ERANGE, "sample " + std::to_string(x) + " out of range");
+  std::sort(v.begin(), v.end());
+  for (int i = 1; i < s; ++i) GK_REQUIRE(v[i] != v[i - 1], GK_EDUPSAMPLE, "duplicate sample " + std::to_string(v[i]));
+}
+
+int run_call(const CallArgs& a, hipStream_t stream) {
+  validate_common(a);
+  gk_graph* g = a.g;
+  const bool dev_io = (a.flags & GK_IO_DEVICE) != 0;
+  // samples: validate on the host
+  std::vector<int64_t> hs(a.s);
+  if (dev_io) GK_HIP(hipMemcpy(hs.data(), a.samples, sizeof(int64_t) * a.s, hipMemcpyDeviceToHost));
+  else std::memcpy(hs.data(), a.samples, sizeof(int64_t) * a.s);
+  check_samples_host(hs.data(), a.s, g->n);
+  GK_HIP(hipSetDevice(g->device));
+
+  Job J;
+  J.g = g;
+  J.s = a.s;
+  J.ld = block_ld(a.s);
+  J.m = a.m;
+  J.variant = a.variant;
+  J.precision = a.precision;
+  J.flags = a.flags;
+  J.phi = *a.phi;
+  J.st = stream;
+  J.tm.on = (a.flags & GK_TIMING) != 0;
+  J.tm.st = stream;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  if (J.tm.on) {
+    GK_HIP(hipEventCreate(&ev0));
+    GK_HIP(hipEventCreate(&ev1));
+    GK_HIP(hipEventRecord(ev0, stream));
+  }
+  J.dflags = J.ar.get<int>(8);
+  launch_zero(J.dflags, 256, stream);
+  J.dscal = J.ar.get<double>(8);
+  launch_zero(J.dscal, 256, stream);
+  if (a.phi->kind == GK_PHI_POLYNOMIAL) {
+    J.poly_dev = J.ar.get<double>(a.phi->poly_len);
+    GK_HIP(hipMemcpyAsync(J.poly_dev, a.phi->poly, sizeof(double) * a.phi->poly_len, hipMemcpyHostToDevice, stream));
+  }
+  // samples in device numbering
+  int64_t* samp_in = J.ar.get<int64_t>(a.s);
+  GK_HIP(hipMemcpyAsync(samp_in, hs.data(), sizeof(int64_t) * a.s, hipMemcpyHostToDevice, stream));
+  J.samp = J.ar.get<int64_t>(a.s);
+  hipLaunchKernelGGL(map_samples_kernel, dim3(nblk(a.s)), dim3(256), 0, stream, a.s, samp_in,
+                     g->reordered ? g->d_iperm : (const int64_t*)nullptr, J.samp);
+  GK_HIP(hipGetLastError());
+
+  switch (a.variant) {
+    case GK_CBL: run_cbl(J); break;
+    case GK_GBL: run_scalar_lanczos(J, true); break;
+    case GK_SBL: run_scalar_lanczos(J, false); break;
+    case GK_CHEB: run_cheb(J, false); break;
+    case GK_CHEB2: run_cheb(J, true); break;
+  }
+  const int64_t n = g->n;
+  const int s = a.s, ld = J.ld;
+  const int64_t* perm = g->reordered ? g->d_perm : nullptr;
+  // outputs
+  double* hcols = nullptr;
+  J.tm.begin(PH_ASM);
+  if (a.cols_out) {
+    double* P = dev_io ? a.cols_out : J.ar.get<double>((size_t)n * s);
+    if (J.Upad)
+      launch_assemble(n, ld, s, J.arch, J.Upad, s, P, perm, stream);   // [Q_1..Q_m] U (Alg. 1)
+    else
+      launch_assemble_diag(n, ld, s, J.arch, J.D, P, perm, true, stream);   // sum_k u_k Q_k (Alg. 2)
+    hcols = P;
+  }
+  J.tm.end();
+  double* hK = nullptr;
+  if (a.kww_out) {   // K is row-major internally; the ABI hands out column-major
+    hK = J.ar.get<double>((size_t)s * s);
+    hipLaunchKernelGGL(transpose_kernel, dim3(nblk((int64_t)s * s)), dim3(256), 0, stream, s, J.K, hK);
+    GK_HIP(hipGetLastError());
+  }
+  double* coef = nullptr;
+  double* pred = nullptr;
+  if (a.fit) {
+    J.tm.begin(PH_FIT);
+    const double* y = a.y;
+    if (!dev_io) {
+      double* yd = J.ar.get<double>(s);
+      GK_HIP(hipMemcpyAsync(yd, a.y, sizeof(double) * s, hipMemcpyHostToDevice, stream));
+      y = yd;
+    }
+    coef = (dev_io && a.coef_out) ? a.coef_out : J.ar.get<double>(s);
+    double* wk = J.ar.get<double>((size_t)s * s);
+    int* piv = J.ar.get<int>(s);
+    launch_small_solve(s, J.K, a.gamma, y, coef, wk, piv, J.spd, J.dflags + 2, stream);
+    J.tm.begin(PH_ASM);
+    if (a.pred_out) {
+      const int nbk = J.arch.nb;
+      double* z = J.ar.get<double>((size_t)nbk * ld);
+      if (J.Upad)   // z = phi(H_m) F_1 c  (Corollary 1)
+        launch_small_gemm(nbk * ld, 1, s, J.Upad, s, false, coef, 1, false, z, 1, 1.0, 0.0, stream);
+      else
+        hipLaunchKernelGGL(zdiag_kernel, dim3(nblk((int64_t)nbk * ld)), dim3(256), 0, stream, nbk, s, ld, J.D, coef, z);
+      GK_HIP(hipGetLastError());
+      pred = dev_io ? a.pred_out : J.ar.get<double>(n);
+      launch_assemble(n, ld, 1, J.arch, z, 1, pred, perm, stream);
+    }
+    J.tm.end();
+  }
+  if (J.tm.on) GK_HIP(hipEventRecord(ev1, stream));
+  // copy back
+  int hflags[8] = {0};
+  double hscal[8] = {0};
+  GK_HIP(hipMemcpyAsync(hflags, J.dflags, sizeof(hflags), hipMemcpyDeviceToHost, stream));
+  GK_HIP(hipMemcpyAsync(hscal, J.dscal, sizeof(hscal), hipMemcpyDeviceToHost, stream));
+  if (!dev_io) {
+    if (a.cols_out) GK_HIP(hipMemcpyAsync(a.cols_out, hcols, sizeof(double) * n * s, hipMemcpyDeviceToHost, stream));
+    if (a.coef_out && coef) GK_HIP(hipMemcpyAsync(a.coef_out, coef, sizeof(double) * s, hipMemcpyDeviceToHost, stream));
+    if (a.pred_out && pred) GK_HIP(hipMemcpyAsync(a.pred_out, pred, sizeof(double) * n, hipMemcpyDeviceToHost, stream));
+  }
+  if (a.kww_out) {
+    GK_HIP(hipMemcpyAsync(a.kww_out, hK, sizeof(double) * s * s,
+                          dev_io ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, stream));
+  }
+  GK_HIP(hipStreamSynchronize(stream));
+  if (a.st) {
+    std::memset(a.st, 0, sizeof(gk_stats));
+    J.tm.collect(a.st);
+    if (ev0 && ev1) {
+      float ms = 0;
+      GK_HIP(hipEventElapsedTime(&ms, ev0, ev1));
+      a.st->t_total_ms = ms;
+    }
+    a.st->n_deflated = hflags[1];
+    a.st->resid_norm = hscal[0];
+    a.st->phi_method = J.phi_method;
+    a.st->footprint_bytes = J.ar.bytes;
+    a.st->n_reorth = (J.variant <= GK_SBL && (!J.mixed() || (J.flags & GK_FULL_REORTH))) ? std::max(J.m - 1, 0) : 0;
+    const int ldv = J.ld;
+    const int slots = ldv <= 128 ? ldv / 2 : (ldv <= 256 ? ldv / 4 : ldv / 8);
+    (void)slots;
+    const double wb = g->unit ? 0.0 : (J.mixed() ? 4.0 : 8.0);
+    a.st->bytes_spmm = a.st->spmm_launches * (4.0 * (n + 1) + g->nnz * (4.0 + wb) + 8.0 * n + 2.0 * 8.0 * n * ld);
+  }
+  if (ev0) (void)hipEventDestroy(ev0);
+  if (ev1) (void)hipEventDestroy(ev1);
+  if (hflags[0] == 1) throw Error{GK_EINVAL, "eps + theta <= 0 for a Ritz value theta"};
+  if (hflags[0] == 3) throw Error{GK_ENOTSPD, "eps I + H_m not positive definite"};
+  if (hflags[2]) throw Error{GK_ENOTSPD, "(K_W + gamma I) c = y not solvable"};
+  return GK_OK;
+}
+
+}  // namespace gk
+
+// ------------------------------------------------------------------ ABI
+extern "C" {
+
+static int guarded(const gk::CallArgs& a) {
+  try {
+    return gk::run_call(a, gk::current_stream());
+  } catch (const gk::Error& e) {
+    gk::set_detail(e.msg);
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    gk::set_detail("host allocation failed");
+    return GK_ENOMEM;
+  }
+}
+
+int krylov_kernel_columns(gk_graph* g, const int64_t* samples, int32_t s, const gk_phi* phi, int32_t m,
+                          int32_t variant, int32_t precision, uint32_t flags, double* cols_out,
+                          double* kww_out, gk_stats* st) {
+  gk::CallArgs a{g, samples, s, phi, m, variant, precision, flags, nullptr, 0.0, cols_out, kww_out,
+                 nullptr, nullptr, st, false};
+  return guarded(a);
+}
+
+int kernel_machine_fit_predict(gk_graph* g, const int64_t* samples, int32_t s, const double* y,
+                               const gk_phi* phi, int32_t m, int32_t variant, int32_t precision,
+                               uint32_t flags, double gamma, double* coef_out, double* pred_out,
+                               gk_stats* st) {
+  gk::CallArgs a{g, samples, s, phi, m, variant, precision, flags, y, gamma, nullptr, nullptr,
+                 coef_out, pred_out, st, true};
+  return guarded(a);
+}
+
+int gk_request_footprint(int64_t n, int32_t s, int32_t m, int32_t variant, int32_t precision, uint64_t* bytes) {
+  if (!bytes || n < 1 || s < 1 || s > 1024 || m < 1 || m > 4096 || variant < GK_CBL || variant > GK_CHEB2 ||
+      (precision != GK_FP64 && precision != GK_MIXED))
+    return GK_EINVAL;
+  *bytes = gk::footprint_bytes(n, s, m, variant, precision);
+  return GK_OK;
+}
+
+}  // extern "C"

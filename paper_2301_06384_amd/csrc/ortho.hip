@@ -1,0 +1,480 @@
+// Tall-skinny block products: Gram matrices A^T B, block updates X -= A C,
+// kernel-column assembly [Q_1..Q_m] U, and the column-wise (Frobenius /
+// sequential) variants.
+//
+// These realise the DOT and AXPY work of Table 1: H_kk = Q_k^T X (Alg. 1),
+// the projections that keep the basis orthonormal (Sec. 3.1), the QR of X,
+// tr(Q_k^T X) and ||X||_F (Alg. 2), and the final [Q_1..Q_m] U (Alg. 1, 2).
+// A "block list" is nb equally shaped n x ld row-major blocks, float or
+// double, seen as one n x (nb*ld) matrix.  All accumulation is float64.
+// Reductions over rows are split in fixed chunks whose partial results are
+// summed in a fixed order by a second kernel: no atomics, so results are
+// bitwise reproducible and independent of other work on the device.
+#include "gk_internal.h"
+
+namespace gk {
+
+template <bool F32>
+__device__ __forceinline__ double ldA(const void* base, int64_t off) {
+  if (F32) return (double)static_cast<const float*>(base)[off];
+  return static_cast<const double*>(base)[off];
+}
+
+// ------------------------------------------------------------------ Gram
+constexpr int G_TA = 64, G_TB = 64, G_RS = 16;
+
+template <bool F32>
+__global__ void __launch_bounds__(256)
+gram_kernel(int64_t n, int ld, const void* __restrict__ Abase, int64_t astride, int nb,
+            const double* __restrict__ B, double* __restrict__ part, int64_t rows_per_chunk,
+            const int* __restrict__ flag) {
+  if (flag && *flag == 0) return;
+  __shared__ double sA[G_RS][G_TA + 1];
+  __shared__ double sB[G_RS][G_TB + 1];
+  const int pa = nb * ld;
+  const int a0 = blockIdx.x * G_TA;
+  const int b0 = blockIdx.y * G_TB;
+  const int64_t r_begin = (int64_t)blockIdx.z * rows_per_chunk;
+  const int64_t r_end = min(n, r_begin + rows_per_chunk);
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  double acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+  for (int64_t r0 = r_begin; r0 < r_end; r0 += G_RS) {
+    for (int q = threadIdx.x; q < G_RS * G_TA; q += 256) {
+      const int rr = q / G_TA, cc = q % G_TA;
+      const int64_t r = r0 + rr;
+      const int a = a0 + cc, b = b0 + cc;
+      double va = 0.0, vb = 0.0;
+      if (r < r_end) {
+        if (a < pa) {
+          const int blk = a / ld, col = a - blk * ld;
+          va = ldA<F32>(Abase, (int64_t)blk * astride + r * ld + col);
+        }
+        if (b < ld) vb = B[r * ld + b];
+      }
+      sA[rr][cc] = va;
+      sB[rr][cc] = vb;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int rr = 0; rr < G_RS; ++rr) {
+      double av[4], bv[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) av[i] = sA[rr][ty * 4 + i];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) bv[j] = sB[rr][tx * 4 + j];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = fma(av[i], bv[j], acc[i][j]);
+    }
+    __syncthreads();
+  }
+  double* P = part + (int64_t)blockIdx.z * pa * ld;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int a = a0 + ty * 4 + i, b = b0 + tx * 4 + j;
+      if (a < pa && b < ld) P[(int64_t)a * ld + b] = acc[i][j];
+    }
+}
+
+__global__ void reduce_chunks_kernel(int64_t len, int nchunks, const double* __restrict__ part,
+                                     double* __restrict__ out, const int* __restrict__ flag) {
+  if (flag && *flag == 0) return;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= len) return;
+  double s = 0.0;
+  for (int c = 0; c < nchunks; ++c) s += part[(int64_t)c * len + i];
+  out[i] = s;
+}
+
+static void gram_geometry(int64_t n, int nb, int ld, int* nx, int* ny, int* nch, int64_t* rpc) {
+  const int pa = nb * ld;
+  *nx = (pa + G_TA - 1) / G_TA;
+  *ny = (ld + G_TB - 1) / G_TB;
+  int64_t want = (2048 + (*nx) * (*ny) - 1) / ((*nx) * (*ny));
+  int64_t maxc = (n + 255) / 256;
+  if (want > maxc) want = maxc;
+  if (want < 1) want = 1;
+  if (want > 1024) want = 1024;
+  int64_t r = (n + want - 1) / want;
+  r = ((r + G_RS - 1) / G_RS) * G_RS;
+  *rpc = r;
+  *nch = (int)((n + r - 1) / r);
+}
+
+size_t gram_scratch_elems(int64_t n, int nb, int ld) {
+  int nx, ny, nch;
+  int64_t rpc;
+  gram_geometry(n, nb, ld, &nx, &ny, &nch, &rpc);
+  return (size_t)nch * nb * ld * ld;
+}
+
+void launch_gram(int64_t n, int ld, BlockList A, const double* B, double* C, double* part,
+                 const int* flag, hipStream_t st) {
+  int nx, ny, nch;
+  int64_t rpc;
+  gram_geometry(n, A.nb, ld, &nx, &ny, &nch, &rpc);
+  dim3 grid(nx, ny, nch);
+  if (A.f32)
+    hipLaunchKernelGGL(gram_kernel<true>, grid, dim3(256), 0, st, n, ld, A.base, A.stride, A.nb, B,
+                       part, rpc, flag);
+  else
+    hipLaunchKernelGGL(gram_kernel<false>, grid, dim3(256), 0, st, n, ld, A.base, A.stride, A.nb, B,
+                       part, rpc, flag);
+  GK_HIP(hipGetLastError());
+  const int64_t len = (int64_t)A.nb * ld * ld;
+  hipLaunchKernelGGL(reduce_chunks_kernel, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, st, len,
+                     nch, part, C, flag);
+  GK_HIP(hipGetLastError());
+}
+
+// ------------------------------------------------------- tall-skinny GEMM
+constexpr int T_TR = 64, T_TB = 64, T_KS = 16;
+
+// out[r,b] = beta*in[r,b] + alpha*sum_a A[r,a] C[a,b]   (b < ncols)
+// row-major output (ld) or column-major output (ld_out rows, optional perm)
+template <bool F32, bool COLMAJ>
+__global__ void __launch_bounds__(256)
+tsgemm_kernel(int64_t n, int ld, int ncols, const void* __restrict__ Abase, int64_t astride, int nb,
+              const double* __restrict__ C, int ldc, const double* __restrict__ in,
+              double* __restrict__ out, float* __restrict__ out32, double alpha, double beta,
+              int64_t ldo, const int64_t* __restrict__ perm, const int* __restrict__ flag) {
+  if (flag && *flag == 0) return;
+  __shared__ double sA[T_TR][T_KS + 1];
+  __shared__ double sC[T_KS][T_TB + 1];
+  const int pa = nb * ld;
+  const int64_t r0 = (int64_t)blockIdx.x * T_TR;
+  const int b0 = blockIdx.y * T_TB;
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  double acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+  for (int a0 = 0; a0 < pa; a0 += T_KS) {
+    for (int q = threadIdx.x; q < T_TR * T_KS; q += 256) {
+      const int rr = q / T_KS, kk = q % T_KS;
+      const int64_t r = r0 + rr;
+      const int a = a0 + kk;
+      double v = 0.0;
+      if (r < n && a < pa) {
+        const int blk = a / ld, col = a - blk * ld;
+        v = ldA<F32>(Abase, (int64_t)blk * astride + r * ld + col);
+      }
+      sA[rr][kk] = v;
+    }
+    for (int q = threadIdx.x; q < T_KS * T_TB; q += 256) {
+      const int kk = q / T_TB, cc = q % T_TB;
+      const int a = a0 + kk, b = b0 + cc;
+      sC[kk][cc] = (a < pa && b < ncols) ? C[(int64_t)a * ldc + b] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < T_KS; ++kk) {
+      double av[4], cv[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) av[i] = sA[ty * 4 + i][kk];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) cv[j] = sC[kk][tx * 4 + j];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = fma(av[i], cv[j], acc[i][j]);
+    }
+    __syncthreads();
+  }
+  if (!COLMAJ) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int64_t r = r0 + ty * 4 + i;
+      if (r >= n) continue;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int b = b0 + tx * 4 + j;
+        if (b >= ld) continue;
+        double v = alpha * acc[i][j];
+        if (beta != 0.0) v += beta * in[r * ld + b];
+        if (b >= ncols) v = (beta != 0.0) ? beta * in[r * ld + b] : 0.0;
+        out[r * ld + b] = v;
+        if (out32) out32[r * ld + b] = (float)v;
+      }
+    }
+  } else {
+    // stage through LDS so that each column is written as contiguous rows
+    __shared__ double sO[T_TB][T_TR + 1];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) sO[tx * 4 + j][ty * 4 + i] = alpha * acc[i][j];
+    __syncthreads();
+    for (int q = threadIdx.x; q < T_TB * T_TR; q += 256) {
+      const int cc = q / T_TR, rr = q % T_TR;
+      const int64_t r = r0 + rr;
+      const int b = b0 + cc;
+      if (r < n && b < ncols) {
+        const int64_t orow = perm ? perm[r] : r;
+        out[(int64_t)b * ldo + orow] = sO[cc][rr];
+      }
+    }
+  }
+}
+
+void launch_tsgemm(int64_t n, int ld, BlockList A, const double* C, const double* in, double* out,
+                   float* out32, double alpha, double beta, const int* flag, hipStream_t st) {
+  dim3 grid((unsigned)((n + T_TR - 1) / T_TR), (ld + T_TB - 1) / T_TB);
+  if (A.f32)
+    hipLaunchKernelGGL((tsgemm_kernel<true, false>), grid, dim3(256), 0, st, n, ld, ld, A.base, A.stride,
+                       A.nb, C, ld, in, out, out32, alpha, beta, (int64_t)ld, (const int64_t*)nullptr,
+                       flag);
+  else
+    hipLaunchKernelGGL((tsgemm_kernel<false, false>), grid, dim3(256), 0, st, n, ld, ld, A.base,
+                       A.stride, A.nb, C, ld, in, out, out32, alpha, beta, (int64_t)ld,
+                       (const int64_t*)nullptr, flag);
+  GK_HIP(hipGetLastError());
+}
+
+void launch_assemble(int64_t n, int ld, int s, BlockList A, const double* U, int ldu, double* P,
+                     const int64_t* perm, hipStream_t st) {
+  dim3 grid((unsigned)((n + T_TR - 1) / T_TR), (s + T_TB - 1) / T_TB);
+  if (A.f32)
+    hipLaunchKernelGGL((tsgemm_kernel<true, true>), grid, dim3(256), 0, st, n, ld, s, A.base, A.stride,
+                       A.nb, U, ldu, (const double*)nullptr, P, (float*)nullptr, 1.0, 0.0, n, perm,
+                       (const int*)nullptr);
+  else
+    hipLaunchKernelGGL((tsgemm_kernel<false, true>), grid, dim3(256), 0, st, n, ld, s, A.base, A.stride,
+                       A.nb, U, ldu, (const double*)nullptr, P, (float*)nullptr, 1.0, 0.0, n, perm,
+                       (const int*)nullptr);
+  GK_HIP(hipGetLastError());
+}
+
+// ------------------------------------------------- column-wise operations
+// out[i, c] = sum_k D[k*ld + c] * A_k[i, c]
+template <bool F32, bool COLMAJ>
+__global__ void assemble_diag_kernel(int64_t n, int ld, int s, const void* __restrict__ Abase,
+                                     int64_t astride, int nb, const double* __restrict__ D,
+                                     double* __restrict__ P, const int64_t* __restrict__ perm) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t i = t / ld;
+  const int c = (int)(t - i * ld);
+  if (i >= n || c >= s) return;
+  double acc = 0.0;
+  for (int k = 0; k < nb; ++k) acc = fma(D[k * ld + c], ldA<F32>(Abase, (int64_t)k * astride + i * ld + c), acc);
+  const int64_t orow = perm ? perm[i] : i;
+  if (COLMAJ)
+    P[(int64_t)c * n + orow] = acc;
+  else
+    P[orow * ld + c] = acc;
+}
+
+void launch_assemble_diag(int64_t n, int ld, int s, BlockList A, const double* D, double* P,
+                          const int64_t* perm, bool colmajor, hipStream_t st) {
+  const int64_t tot = n * ld;
+  dim3 grid((unsigned)((tot + 255) / 256));
+#define GK_AD(F, CM)                                                                              \
+  hipLaunchKernelGGL((assemble_diag_kernel<F, CM>), grid, dim3(256), 0, st, n, ld, s, A.base, A.stride, \
+                     A.nb, D, P, perm)
+  if (A.f32) {
+    if (colmajor) GK_AD(true, true); else GK_AD(true, false);
+  } else {
+    if (colmajor) GK_AD(false, true); else GK_AD(false, false);
+  }
+#undef GK_AD
+  GK_HIP(hipGetLastError());
+}
+
+// part[chunk][k*ld + c] = sum_{i in chunk} A_k[i,c] * B[i,c]
+template <bool F32>
+__global__ void __launch_bounds__(256)
+coldots_kernel(int64_t n, int ld, const void* __restrict__ Abase, int64_t astride, int nb,
+               const double* __restrict__ B, double* __restrict__ part, int64_t rows_per_chunk,
+               const int* __restrict__ flag) {
+  if (flag && *flag == 0) return;
+  __shared__ double red[256];
+  const int cols = ld < 256 ? ld : 256;
+  const int groups = 256 / cols;
+  const int64_t r_begin = (int64_t)blockIdx.x * rows_per_chunk;
+  const int64_t r_end = min(n, r_begin + rows_per_chunk);
+  const int tid = threadIdx.x;
+  const int cl = tid % cols, gr = tid / cols;
+  double* P = part + (int64_t)blockIdx.x * nb * ld;
+  for (int cb = 0; cb < ld; cb += cols) {
+    const int c = cb + cl;
+    for (int k = 0; k < nb; ++k) {
+      double sacc = 0.0;
+      if (gr < groups && c < ld)
+        for (int64_t r = r_begin + gr; r < r_end; r += groups)
+          sacc = fma(ldA<F32>(Abase, (int64_t)k * astride + r * ld + c), B[r * ld + c], sacc);
+      red[tid] = sacc;
+      __syncthreads();
+      if (tid < cols && c < ld) {
+        double t = 0.0;
+        for (int q = 0; q < groups; ++q) t += red[q * cols + tid];
+        P[k * ld + c] = t;
+      }
+      __syncthreads();
+    }
+  }
+}
+
+static void coldots_geometry(int64_t n, int* nch, int64_t* rpc) {
+  int64_t want = 512;
+  int64_t maxc = (n + 63) / 64;
+  if (want > maxc) want = maxc;
+  if (want < 1) want = 1;
+  int64_t r = (n + want - 1) / want;
+  *rpc = r;
+  *nch = (int)((n + r - 1) / r);
+}
+
+size_t coldots_scratch_elems(int64_t n, int nb, int ld) {
+  int nch;
+  int64_t rpc;
+  coldots_geometry(n, &nch, &rpc);
+  return (size_t)nch * nb * ld;
+}
+
+void launch_coldots(int64_t n, int ld, BlockList A, const double* B, double* out, double* part,
+                    const int* flag, hipStream_t st) {
+  int nch;
+  int64_t rpc;
+  coldots_geometry(n, &nch, &rpc);
+  if (A.f32)
+    hipLaunchKernelGGL(coldots_kernel<true>, dim3(nch), dim3(256), 0, st, n, ld, A.base, A.stride, A.nb,
+                       B, part, rpc, flag);
+  else
+    hipLaunchKernelGGL(coldots_kernel<false>, dim3(nch), dim3(256), 0, st, n, ld, A.base, A.stride, A.nb,
+                       B, part, rpc, flag);
+  GK_HIP(hipGetLastError());
+  const int64_t len = (int64_t)A.nb * ld;
+  hipLaunchKernelGGL(reduce_chunks_kernel, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, st, len,
+                     nch, part, out, flag);
+  GK_HIP(hipGetLastError());
+}
+
+template <bool F32>
+__global__ void axpy_diag_kernel(int64_t n, int ld, const void* __restrict__ Abase, int64_t astride,
+                                 int nb, const double* __restrict__ D, double* __restrict__ X,
+                                 const int* __restrict__ flag) {
+  if (flag && *flag == 0) return;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * ld) return;
+  const int c = (int)(t % ld);
+  double x = X[t];
+  for (int k = 0; k < nb; ++k) x = fma(-D[k * ld + c], ldA<F32>(Abase, (int64_t)k * astride + t), x);
+  X[t] = x;
+}
+
+void launch_axpy_diag(int64_t n, int ld, BlockList A, const double* D, double* X, const int* flag,
+                      hipStream_t st) {
+  const int64_t tot = n * ld;
+  dim3 grid((unsigned)((tot + 255) / 256));
+  if (A.f32)
+    hipLaunchKernelGGL(axpy_diag_kernel<true>, grid, dim3(256), 0, st, n, ld, A.base, A.stride, A.nb, D,
+                       X, flag);
+  else
+    hipLaunchKernelGGL(axpy_diag_kernel<false>, grid, dim3(256), 0, st, n, ld, A.base, A.stride, A.nb, D,
+                       X, flag);
+  GK_HIP(hipGetLastError());
+}
+
+__global__ void colscale_kernel(int64_t n, int ld, const double* __restrict__ X,
+                                const double* __restrict__ scale, double* __restrict__ Y,
+                                float* __restrict__ Y32) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * ld) return;
+  const double v = X[t] * scale[t % ld];
+  Y[t] = v;
+  if (Y32) Y32[t] = (float)v;
+}
+
+void launch_colscale(int64_t n, int ld, const double* X, const double* scale, double* Y, float* Y32,
+                     hipStream_t st) {
+  const int64_t tot = n * ld;
+  hipLaunchKernelGGL(colscale_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, n, ld, X,
+                     scale, Y, Y32);
+  GK_HIP(hipGetLastError());
+}
+
+// out[r*s + c] = sum_k D[k*ld + c] * A_k[rows[r], c]   (D == null: single block, weight 1)
+template <bool F32>
+__global__ void gather_rows_kernel(int ld, int s, const void* __restrict__ Abase, int64_t astride,
+                                   int nb, const double* __restrict__ D, const int64_t* __restrict__ rows,
+                                   double* __restrict__ out) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= s * s) return;
+  const int r = t / s, c = t % s;
+  const int64_t i = rows[r];
+  double acc = 0.0;
+  for (int k = 0; k < nb; ++k) {
+    const double w = D ? D[k * ld + c] : 1.0;
+    acc = fma(w, ldA<F32>(Abase, (int64_t)k * astride + i * ld + c), acc);
+  }
+  out[t] = acc;
+}
+
+void launch_gather_diag(int64_t n, int ld, int s, BlockList A, const double* D, const int64_t* rows,
+                        double* out, hipStream_t st) {
+  (void)n;
+  const int tot = s * s;
+  if (A.f32)
+    hipLaunchKernelGGL(gather_rows_kernel<true>, dim3((tot + 255) / 256), dim3(256), 0, st, ld, s, A.base,
+                       A.stride, A.nb, D, rows, out);
+  else
+    hipLaunchKernelGGL(gather_rows_kernel<false>, dim3((tot + 255) / 256), dim3(256), 0, st, ld, s,
+                       A.base, A.stride, A.nb, D, rows, out);
+  GK_HIP(hipGetLastError());
+}
+
+// ------------------------------------------------------------ misc
+__global__ void start_block_kernel(int64_t n, int ld, int s, const int64_t* __restrict__ samples,
+                                   double value, double* __restrict__ V, float* __restrict__ V32) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= s) return;
+  const int64_t w = samples[j];
+  V[w * ld + j] = value;
+  if (V32) V32[w * ld + j] = (float)value;
+}
+
+__global__ void zero_kernel(uint64_t* __restrict__ p, size_t words) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (; i < words; i += stride) p[i] = 0;
+}
+
+void launch_zero(void* p, size_t bytes, hipStream_t st) {
+  // buffers come from the arena and are multiples of 256 bytes
+  const size_t words = (bytes + 7) / 8;
+  size_t blocks = (words + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  if (blocks == 0) return;
+  hipLaunchKernelGGL(zero_kernel, dim3((unsigned)blocks), dim3(256), 0, st, (uint64_t*)p, words);
+  GK_HIP(hipGetLastError());
+}
+
+void launch_start_block(int64_t n, int ld, int s, const int64_t* dev_samples, double value, double* V,
+                        float* V32, hipStream_t st) {
+  launch_zero(V, (size_t)n * ld * sizeof(double), st);
+  if (V32) launch_zero(V32, (size_t)n * ld * sizeof(float), st);
+  hipLaunchKernelGGL(start_block_kernel, dim3((s + 255) / 256), dim3(256), 0, st, n, ld, s, dev_samples,
+                     value, V, V32);
+  GK_HIP(hipGetLastError());
+}
+
+__global__ void f64_to_f32_kernel(const double* __restrict__ a, float* __restrict__ b, size_t cnt) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < cnt) b[i] = (float)a[i];
+}
+
+void launch_copy_f64_to_f32(const double* a, float* b, size_t count, hipStream_t st) {
+  hipLaunchKernelGGL(f64_to_f32_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, a, b,
+                     count);
+  GK_HIP(hipGetLastError());
+}
+
+}  // namespace gk

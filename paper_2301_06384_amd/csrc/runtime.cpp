@@ -1,0 +1,205 @@
+// ABI plumbing: error reporting, device memory (caching allocator or a
+// caller-installed one), per-thread stream, phase timers, version.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <map>
+
+#include "gk_internal.h"
+
+namespace gk {
+
+static thread_local std::string t_detail;
+void set_detail(const std::string& msg) { t_detail = msg; }
+
+// ------------------------------------------------------------ allocator
+// Default: a size-keyed cache over hipMalloc.  A block returned to the cache
+// carries an event recorded on the stream that last used it; a later
+// allocation on another stream waits for that event before reuse.  Nothing
+// is returned to HIP until process exit (or gk_trim).
+namespace {
+struct CachedBlock {
+  void* p;
+  size_t bytes;
+  hipEvent_t ev;
+};
+struct Cache {
+  std::mutex mu;
+  std::multimap<size_t, CachedBlock> free_blocks;
+  std::map<void*, size_t> live;
+  uint64_t live_bytes = 0;
+  uint64_t cached_bytes = 0;
+};
+Cache& cache() {
+  static Cache* c = new Cache();   // never destroyed: blocks may outlive static destruction order
+  return *c;
+}
+void* (*g_alloc_fn)(size_t, void*) = nullptr;
+void (*g_free_fn)(void*, void*) = nullptr;
+void* g_alloc_ctx = nullptr;
+thread_local hipStream_t t_stream = nullptr;
+}  // namespace
+
+hipStream_t current_stream() { return t_stream; }
+
+void* dev_alloc(size_t bytes) {
+  if (g_alloc_fn) {
+    void* p = g_alloc_fn(bytes, g_alloc_ctx);
+    return p;
+  }
+  Cache& c = cache();
+  std::lock_guard<std::mutex> lk(c.mu);
+  auto it = c.free_blocks.lower_bound(bytes);
+  if (it != c.free_blocks.end() && it->first <= bytes * 2 + (64u << 20)) {
+    CachedBlock b = it->second;
+    c.free_blocks.erase(it);
+    c.cached_bytes -= b.bytes;
+    if (b.ev) {
+      (void)hipStreamWaitEvent(t_stream, b.ev, 0);
+      (void)hipEventDestroy(b.ev);
+    }
+    c.live[b.p] = b.bytes;
+    c.live_bytes += b.bytes;
+    return b.p;
+  }
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    // release cached blocks and retry once
+    for (auto& kv : c.free_blocks) {
+      if (kv.second.ev) {
+        (void)hipEventSynchronize(kv.second.ev);
+        (void)hipEventDestroy(kv.second.ev);
+      }
+      (void)hipFree(kv.second.p);
+    }
+    c.free_blocks.clear();
+    c.cached_bytes = 0;
+    e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+  }
+  c.live[p] = bytes;
+  c.live_bytes += bytes;
+  return p;
+}
+
+void dev_free(void* p) {
+  if (!p) return;
+  if (g_free_fn) {
+    g_free_fn(p, g_alloc_ctx);
+    return;
+  }
+  Cache& c = cache();
+  std::lock_guard<std::mutex> lk(c.mu);
+  auto it = c.live.find(p);
+  if (it == c.live.end()) return;
+  const size_t b = it->second;
+  c.live.erase(it);
+  c.live_bytes -= b;
+  hipEvent_t ev = nullptr;
+  if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess) {
+    if (hipEventRecord(ev, t_stream) != hipSuccess) {
+      (void)hipEventDestroy(ev);
+      ev = nullptr;
+    }
+  }
+  c.free_blocks.emplace(b, CachedBlock{p, b, ev});
+  c.cached_bytes += b;
+}
+
+void set_thread_stream(hipStream_t s) { t_stream = s; }
+
+// ------------------------------------------------------------ timers
+void PhaseTimer::begin(int phase) {
+  if (!on) return;
+  end();
+  hipEvent_t a;
+  GK_HIP(hipEventCreate(&a));
+  GK_HIP(hipEventRecord(a, st));
+  cur = phase;
+  cur_start = a;
+}
+void PhaseTimer::end() {
+  if (!on || cur < 0) return;
+  hipEvent_t b;
+  GK_HIP(hipEventCreate(&b));
+  GK_HIP(hipEventRecord(b, st));
+  ev.push_back({cur, {cur_start, b}});
+  cur = -1;
+  cur_start = nullptr;
+}
+void PhaseTimer::collect(gk_stats* s) {
+  if (!on) return;
+  end();
+  if (!s) return;
+  double t[PH_TOTAL + 1] = {0};
+  double nspmm = 0;
+  for (auto& e : ev) {
+    GK_HIP(hipEventSynchronize(e.second.second));
+    float ms = 0;
+    GK_HIP(hipEventElapsedTime(&ms, e.second.first, e.second.second));
+    t[e.first] += ms;
+    if (e.first == PH_SPMM) nspmm += 1;
+  }
+  s->t_spmm_ms = t[PH_SPMM];
+  s->t_orth_ms = t[PH_ORTH];
+  s->t_reorth_ms = t[PH_REORTH];
+  s->t_phi_ms = t[PH_PHI];
+  s->t_asm_ms = t[PH_ASM];
+  s->t_fit_ms = t[PH_FIT];
+  s->t_total_ms = t[PH_TOTAL];
+  s->spmm_launches = nspmm;
+}
+PhaseTimer::~PhaseTimer() {
+  for (auto& e : ev) {
+    (void)hipEventDestroy(e.second.first);
+    (void)hipEventDestroy(e.second.second);
+  }
+  if (cur_start) (void)hipEventDestroy(cur_start);
+}
+
+}  // namespace gk
+
+// ------------------------------------------------------------------ ABI
+extern "C" {
+
+const char* gk_strerror(int code) {
+  switch (code) {
+    case GK_OK: return "ok";
+    case GK_EINVAL: return "invalid argument";
+    case GK_ENOTSYM: return "Laplacian not symmetric";
+    case GK_ENOTLAP: return "not a graph Laplacian (positive off-diagonal or negative diagonal excess)";
+    case GK_EDUPSAMPLE: return "duplicate sample nodes";
+    case GK_ERANGE: return "sample node out of range";
+    case GK_ENOMEM: return "out of device memory or refused by admission";
+    case GK_ENOTSPD: return "kernel system not solvable";
+    case GK_EDEVICE: return "HIP device error";
+    case GK_EUNSUPPORTED: return "unsupported combination";
+    case GK_EAGAIN: return "not finished";
+    case GK_ESHUTDOWN: return "serving loop stopped";
+    default: return "unknown error";
+  }
+}
+
+const char* gk_last_error_detail(void) { return gk::t_detail.c_str(); }
+
+int gk_set_allocator(void* (*alloc_fn)(size_t, void*), void (*free_fn)(void*, void*), void* ctx) {
+  if ((alloc_fn == nullptr) != (free_fn == nullptr)) return GK_EINVAL;
+  gk::g_alloc_fn = alloc_fn;
+  gk::g_free_fn = free_fn;
+  gk::g_alloc_ctx = ctx;
+  return GK_OK;
+}
+
+int gk_set_stream(void* hip_stream) {
+  gk::t_stream = static_cast<hipStream_t>(hip_stream);
+  return GK_OK;
+}
+
+const char* gk_version(void) { return "gk 0.1 gfx950"; }
+
+}  // extern "C"

@@ -1,0 +1,636 @@
+// Small dense float64 work: QR factors of the Lanczos blocks, the projected
+// matrix H_m, its spectral decomposition and phi(H_m) F_1, the exact banded
+// evaluation of spline kernels, and the s x s kernel system.
+//
+// Everything here is float64 (the small factors of the method).  Matrices
+// live in device memory; one workgroup owns one matrix, so these kernels
+// need no grid-wide synchronisation.
+#include "gk_internal.h"
+
+namespace gk {
+
+constexpr int SB = 1024;   // threads of the single-workgroup kernels
+
+// ------------------------------------------------------------- CholQR
+// Upper Cholesky G = R^T R of a Gram matrix with column deflation, followed
+// by the pseudo-inverse Rinv on the kept columns (X Rinv has orthonormal kept
+// columns and zero deflated columns; X ~ (X Rinv) R).
+//
+// pass 1: a column whose Gram diagonal is below thr^2 is deflated; otherwise
+//   the pivot is clamped from below by eta^2 G_jj, so nearly dependent
+//   columns survive into pass 2 scaled down instead of being dropped on a
+//   noisy pivot.
+// pass 2: a column is deflated when its pivot is not positive or when the
+//   combined diagonal R2_jj * R1_jj (the true residual norm of the column
+//   after the first pass) is below thr.  This matches the rank decision of a
+//   Householder QR with threshold thr.
+__global__ void __launch_bounds__(SB)
+cholqr_factor_kernel(const double* __restrict__ G, int ld, int s, int pass,
+                     const double* __restrict__ diag_prev, double thr, double* __restrict__ W,
+                     double* __restrict__ R, double* __restrict__ Rinv, double* __restrict__ diag_out,
+                     int* __restrict__ n_defl) {
+  __shared__ double rjj_sh;
+  __shared__ int ndef_sh;
+  const int tid = threadIdx.x;
+  const double eta = 1e-7;
+  for (int q = tid; q < ld * ld; q += SB) {
+    W[q] = G[q];
+    R[q] = 0.0;
+    Rinv[q] = 0.0;
+  }
+  if (tid == 0) ndef_sh = 0;
+  __syncthreads();
+  for (int j = 0; j < s; ++j) {
+    if (tid == 0) {
+      const double piv = W[j * ld + j];
+      double r = 0.0;
+      if (pass == 1) {
+        const double g0 = G[j * ld + j];
+        if (g0 > thr * thr) r = sqrt(fmax(piv, eta * eta * g0));
+      } else {
+        if (piv > 0.0) {
+          r = sqrt(piv);
+          if (r * diag_prev[j] < thr) r = 0.0;
+        }
+      }
+      if (r == 0.0) ndef_sh++;
+      rjj_sh = r;
+      diag_out[j] = r;
+      R[j * ld + j] = r;
+    }
+    __syncthreads();
+    const double rjj = rjj_sh;
+    if (rjj != 0.0) {
+      for (int c = j + 1 + tid; c < s; c += SB) R[j * ld + c] = W[j * ld + c] / rjj;
+      __syncthreads();
+      const int w = s - j - 1;
+      for (int q = tid; q < w * w; q += SB) {
+        const int r = j + 1 + q / w, c = j + 1 + q % w;
+        if (c >= r) W[r * ld + c] -= R[j * ld + r] * R[j * ld + c];
+      }
+    }
+    __syncthreads();
+  }
+  for (int j = s + tid; j < ld; j += SB) diag_out[j] = 0.0;
+  // Rinv: one thread per column, back substitution over kept rows
+  for (int c = tid; c < s; c += SB) {
+    if (R[c * ld + c] == 0.0) continue;
+    Rinv[c * ld + c] = 1.0 / R[c * ld + c];
+    for (int i = c - 1; i >= 0; --i) {
+      const double rii = R[i * ld + i];
+      if (rii == 0.0) continue;
+      double acc = 0.0;
+      for (int l = i + 1; l <= c; ++l) acc += R[i * ld + l] * Rinv[l * ld + c];
+      Rinv[i * ld + c] = -acc / rii;
+    }
+  }
+  if (tid == 0 && n_defl && pass == 2) *n_defl += ndef_sh;
+}
+
+void launch_cholqr_factor(const double* G, int ld, int s, int pass, const double* diag_prev, double thr,
+                          double* W, double* R, double* Rinv, double* diag_out, int* n_defl,
+                          hipStream_t st) {
+  hipLaunchKernelGGL(cholqr_factor_kernel, dim3(1), dim3(SB), 0, st, G, ld, s, pass, diag_prev, thr, W, R,
+                     Rinv, diag_out, n_defl);
+  GK_HIP(hipGetLastError());
+}
+
+// ------------------------------------------------------------ small GEMM
+// C = alpha * op(A) op(B) + beta * C, one thread per entry (small sizes).
+__global__ void small_gemm_kernel(int M, int N, int K, const double* __restrict__ A, int lda, int ta,
+                                  const double* __restrict__ B, int ldb, int tb, double* __restrict__ C,
+                                  int ldc, double alpha, double beta) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)M * N) return;
+  const int i = (int)(t / N), j = (int)(t % N);
+  double acc = 0.0;
+  for (int l = 0; l < K; ++l) {
+    const double a = ta ? A[(int64_t)l * lda + i] : A[(int64_t)i * lda + l];
+    const double b = tb ? B[(int64_t)j * ldb + l] : B[(int64_t)l * ldb + j];
+    acc = fma(a, b, acc);
+  }
+  double* c = C + (int64_t)i * ldc + j;
+  *c = alpha * acc + (beta != 0.0 ? beta * (*c) : 0.0);
+}
+
+void launch_small_gemm(int M, int N, int K, const double* A, int lda, bool ta, const double* B, int ldb,
+                       bool tb, double* C, int ldc, double alpha, double beta, hipStream_t st) {
+  const int64_t tot = (int64_t)M * N;
+  hipLaunchKernelGGL(small_gemm_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, M, N, K, A,
+                     lda, ta ? 1 : 0, B, ldb, tb ? 1 : 0, C, ldc, alpha, beta);
+  GK_HIP(hipGetLastError());
+}
+
+// Hk = sym(C[0:s, 0:s]) (C has leading dimension ld; Hk is s x s)
+__global__ void store_H_kernel(const double* __restrict__ C, int ld, int s, double* __restrict__ Hk) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= s * s) return;
+  const int i = t / s, j = t % s;
+  Hk[t] = 0.5 * (C[i * ld + j] + C[j * ld + i]);
+}
+
+void launch_store_H(const double* C, int ld, int s, double* Hk, hipStream_t st) {
+  hipLaunchKernelGGL(store_H_kernel, dim3((s * s + 255) / 256), dim3(256), 0, st, C, ld, s, Hk);
+  GK_HIP(hipGetLastError());
+}
+
+// Dense H_m from its blocks: H_kk on the diagonal, H_{k+1,k} = B_k below and
+// its transpose above (Sec. 3.1: H_{k,k+1} = H_{k+1,k}^*).
+__global__ void assemble_T_kernel(int m, int s, const double* __restrict__ Hd, const double* __restrict__ Bd,
+                                  double* __restrict__ T, int ldt) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t ms = (int64_t)m * s;
+  if (t >= ms * ms) return;
+  const int r = (int)(t / ms), c = (int)(t % ms);
+  const int br = r / s, bc = c / s, i = r % s, j = c % s;
+  double v = 0.0;
+  if (br == bc) v = Hd[((int64_t)br * s + i) * s + j];
+  else if (br == bc + 1) v = Bd[((int64_t)bc * s + i) * s + j];
+  else if (bc == br + 1) v = Bd[((int64_t)br * s + j) * s + i];
+  T[(int64_t)r * ldt + c] = v;
+}
+
+void launch_assemble_T(int m, int s, const double* Hd, const double* Bd, double* T, int ldt,
+                       hipStream_t st) {
+  const int64_t tot = (int64_t)m * s * m * s;
+  hipLaunchKernelGGL(assemble_T_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, m, s, Hd, Bd,
+                     T, ldt);
+  GK_HIP(hipGetLastError());
+}
+
+// ------------------------------------------------- symmetric eigensolver
+// Cyclic two-sided Jacobi with round-robin pair ordering (n/2 disjoint
+// rotations per round), one workgroup per matrix.  A is overwritten
+// (diagonal -> eigenvalues), V receives the eigenvectors as columns:
+// A_in = V diag(theta) V^T.  Sweeps stop when the off-diagonal mass is
+// below (1e-17 ||A||_F)^2 or after 40 sweeps.
+__global__ void __launch_bounds__(SB)
+jacobi_eig_kernel(int n, double* __restrict__ Abase, int lda, double* __restrict__ Vbase, int ldv,
+                  double* __restrict__ thbase, int64_t strideA, int64_t strideV, int64_t strideT,
+                  int* __restrict__ order_base, double* __restrict__ cs_base) {
+  double* A = Abase + blockIdx.x * strideA;
+  double* V = Vbase + blockIdx.x * strideV;
+  double* theta = thbase + blockIdx.x * strideT;
+  const int np = (n + 1) & ~1;          // even number of players (one dummy if n odd)
+  int* order = order_base + (int64_t)blockIdx.x * np;
+  double* cs = cs_base + (int64_t)blockIdx.x * np;   // (c, s) per pair
+  __shared__ double red[SB];
+  __shared__ int go_sh;
+  const int tid = threadIdx.x;
+  for (int q = tid; q < n * n; q += SB) {
+    const int i = q / n, j = q % n;
+    V[(int64_t)i * ldv + j] = (i == j) ? 1.0 : 0.0;
+  }
+  for (int q = tid; q < np; q += SB) order[q] = q;
+  __syncthreads();
+  const int npairs = np / 2;
+  for (int sweep = 0; sweep < 40; ++sweep) {
+    // convergence test
+    double off = 0.0, tot = 0.0;
+    for (int q = tid; q < n * n; q += SB) {
+      const int i = q / n, j = q % n;
+      const double a = A[(int64_t)i * lda + j];
+      tot += a * a;
+      if (i != j) off += a * a;
+    }
+    red[tid] = off;
+    __syncthreads();
+    for (int w = SB / 2; w > 0; w >>= 1) {
+      if (tid < w) red[tid] += red[tid + w];
+      __syncthreads();
+    }
+    const double offs = red[0];
+    __syncthreads();
+    red[tid] = tot;
+    __syncthreads();
+    for (int w = SB / 2; w > 0; w >>= 1) {
+      if (tid < w) red[tid] += red[tid + w];
+      __syncthreads();
+    }
+    const double tots = red[0];
+    __syncthreads();
+    if (tid == 0) go_sh = (offs > 1e-34 * tots && offs > 1e-300) ? 1 : 0;
+    __syncthreads();
+    if (!go_sh) break;
+    for (int round = 0; round < np - 1; ++round) {
+      // rotation parameters
+      for (int pi = tid; pi < npairs; pi += SB) {
+        int p = order[pi], q = order[np - 1 - pi];
+        double c = 1.0, sn = 0.0;
+        if (p < n && q < n) {
+          if (p > q) { const int t = p; p = q; q = t; }
+          const double apq = A[(int64_t)p * lda + q];
+          const double app = A[(int64_t)p * lda + p], aqq = A[(int64_t)q * lda + q];
+          if (apq != 0.0 && fabs(apq) > 1e-300) {
+            const double th = (aqq - app) / (2.0 * apq);
+            const double t = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+            c = 1.0 / sqrt(t * t + 1.0);
+            sn = t * c;
+          }
+        }
+        cs[2 * pi] = c;
+        cs[2 * pi + 1] = sn;
+      }
+      __syncthreads();
+      // columns of A and V:  col_p' = c col_p - s col_q ; col_q' = s col_p + c col_q
+      for (int q2 = tid; q2 < npairs * n; q2 += SB) {
+        const int pi = q2 / n, r = q2 % n;
+        int p = order[pi], q = order[np - 1 - pi];
+        if (p >= n || q >= n) continue;
+        if (p > q) { const int t = p; p = q; q = t; }
+        const double c = cs[2 * pi], sn = cs[2 * pi + 1];
+        if (sn == 0.0) continue;
+        double* ar = A + (int64_t)r * lda;
+        const double ap = ar[p], aq = ar[q];
+        ar[p] = c * ap - sn * aq;
+        ar[q] = sn * ap + c * aq;
+        double* vr = V + (int64_t)r * ldv;
+        const double vp = vr[p], vq = vr[q];
+        vr[p] = c * vp - sn * vq;
+        vr[q] = sn * vp + c * vq;
+      }
+      __syncthreads();
+      // rows of A
+      for (int q2 = tid; q2 < npairs * n; q2 += SB) {
+        const int pi = q2 / n, cc = q2 % n;
+        int p = order[pi], q = order[np - 1 - pi];
+        if (p >= n || q >= n) continue;
+        if (p > q) { const int t = p; p = q; q = t; }
+        const double c = cs[2 * pi], sn = cs[2 * pi + 1];
+        if (sn == 0.0) continue;
+        const double ap = A[(int64_t)p * lda + cc], aq = A[(int64_t)q * lda + cc];
+        A[(int64_t)p * lda + cc] = c * ap - sn * aq;
+        A[(int64_t)q * lda + cc] = sn * ap + c * aq;
+      }
+      __syncthreads();
+      for (int pi = tid; pi < npairs; pi += SB) {
+        int p = order[pi], q = order[np - 1 - pi];
+        if (p < n && q < n && cs[2 * pi + 1] != 0.0) {
+          A[(int64_t)p * lda + q] = 0.0;
+          A[(int64_t)q * lda + p] = 0.0;
+        }
+      }
+      __syncthreads();
+      // rotate players 1..np-1 by one position
+      if (tid == 0) {
+        const int last = order[np - 1];
+        for (int q = np - 1; q > 1; --q) order[q] = order[q - 1];
+        order[1] = last;
+      }
+      __syncthreads();
+    }
+  }
+  for (int q = tid; q < n; q += SB) theta[q] = A[(int64_t)q * lda + q];
+}
+
+void launch_sym_eig(int n, double* A, int lda, double* V, int ldv, double* theta, int batch,
+                    int64_t strideA, int64_t strideV, int64_t strideTheta, int* order_ws, double* cs_ws,
+                    hipStream_t st) {
+  hipLaunchKernelGGL(jacobi_eig_kernel, dim3(batch), dim3(SB), 0, st, n, A, lda, V, ldv, theta, strideA,
+                     strideV, strideTheta, order_ws, cs_ws);
+  GK_HIP(hipGetLastError());
+}
+
+size_t eig_order_elems(int n, int batch) { return (size_t)(((n + 1) & ~1)) * batch; }
+
+// ------------------------------------------------------------- phi
+struct PhiDev {
+  int kind;
+  double t, eps, k;
+  int plen;
+};
+
+__device__ __forceinline__ double phi_eval(const PhiDev& f, const double* poly, double lam, int* bad) {
+  if (f.kind == GK_PHI_DIFFUSION) return exp(-f.t * lam);
+  if (f.kind == GK_PHI_SPLINE) {
+    const double z = f.eps + lam;
+    if (!(z > 0.0)) {
+      if (bad) *bad = 1;
+      return 0.0;
+    }
+    return pow(z, -f.k);
+  }
+  double acc = 0.0;
+  for (int j = f.plen - 1; j >= 0; --j) acc = acc * lam + poly[j];
+  return acc;
+}
+
+static PhiDev to_dev(const gk_phi& p) {
+  PhiDev f;
+  f.kind = p.kind;
+  f.t = p.t;
+  f.eps = p.eps;
+  f.k = p.k;
+  f.plen = p.poly_len;
+  return f;
+}
+
+// fv[l] = scale_l * phi(theta_l); kind of scale: 0 plain, 1 sqrt (needs phi >= 0)
+__global__ void phi_values_kernel(int n, const double* __restrict__ theta, PhiDev f,
+                                  const double* __restrict__ poly, double* __restrict__ fv, int use_sqrt,
+                                  int* __restrict__ bad) {
+  const int l = blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= n) return;
+  double v = phi_eval(f, poly, theta[l], bad);
+  if (use_sqrt) {
+    if (v < 0.0) {
+      if (bad) *bad = 2;
+      v = 0.0;
+    }
+    v = sqrt(v);
+  }
+  fv[l] = v;
+}
+
+// U[i, c] = outer * sum_l S[i, l] fv[l] S[row0 + c*rstride, l]
+__global__ void phi_apply_kernel(int n, int s, const double* __restrict__ S, int lds,
+                                 const double* __restrict__ fv, double* __restrict__ U, int ldu,
+                                 double outer) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)n * s) return;
+  const int i = (int)(t / s), c = (int)(t % s);
+  const double* si = S + (int64_t)i * lds;
+  const double* sc = S + (int64_t)c * lds;
+  double acc = 0.0;
+  for (int l = 0; l < n; ++l) acc = fma(si[l] * fv[l], sc[l], acc);
+  U[(int64_t)i * ldu + c] = outer * acc;
+}
+
+void launch_phi_values(int n, const double* theta, const gk_phi& phi, const double* poly_dev, double* fv,
+                       bool use_sqrt, int* bad, hipStream_t st) {
+  hipLaunchKernelGGL(phi_values_kernel, dim3((n + 255) / 256), dim3(256), 0, st, n, theta, to_dev(phi),
+                     poly_dev, fv, use_sqrt ? 1 : 0, bad);
+  GK_HIP(hipGetLastError());
+}
+
+void launch_phi_apply(int n, int s, const double* S, int lds, const double* fv, double* U, int ldu,
+                      double outer, hipStream_t st) {
+  const int64_t tot = (int64_t)n * s;
+  hipLaunchKernelGGL(phi_apply_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, n, s, S, lds,
+                     fv, U, ldu, outer);
+  GK_HIP(hipGetLastError());
+}
+
+// K[i, j] = sum_l (g_l S[i,l]) (g_l S[j,l]),  g = sqrt(phi(theta))   (i, j < s)
+__global__ void kww_gram_kernel(int n, int s, const double* __restrict__ S, int lds,
+                                const double* __restrict__ g, double* __restrict__ K) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= s * s) return;
+  const int i = t / s, j = t % s;
+  const double* si = S + (int64_t)i * lds;
+  const double* sj = S + (int64_t)j * lds;
+  double acc = 0.0;
+  for (int l = 0; l < n; ++l) acc = fma(g[l] * si[l], g[l] * sj[l], acc);
+  K[t] = acc;
+}
+
+void launch_kww_gram(int n, int s, const double* S, int lds, const double* g, double* K, hipStream_t st) {
+  hipLaunchKernelGGL(kww_gram_kernel, dim3((s * s + 255) / 256), dim3(256), 0, st, n, s, S, lds, g, K);
+  GK_HIP(hipGetLastError());
+}
+
+// ------------------------------------- banded evaluation of spline kernels
+// (eps I + H_m)^(-k) F_1 for integer k by block Cholesky of the block
+// tridiagonal eps I + H_m (blocks D_j = eps I + H_jj, sub-diagonal B_j):
+//   L_00 = chol(D_0); L_{j+1,j} = B_j L_jj^{-T};
+//   L_{j+1,j+1} = chol(D_{j+1} - L_{j+1,j} L_{j+1,j}^T)
+// then k forward / backward block substitutions.  eps I + H_m is SPD
+// because spec(H_m) lies in [0, Lambda] (Theorem 3.1, Cauchy interlacing).
+// All blocks are s x s row-major; U is (m s) x s row-major.
+__device__ void wg_chol_lower(double* A, int s, int* bad) {
+  // in place lower Cholesky A = L L^T (A row-major s x s, full storage)
+  const int tid = threadIdx.x;
+  for (int j = 0; j < s; ++j) {
+    __syncthreads();
+    if (tid == 0) {
+      const double d = A[j * s + j];
+      if (!(d > 0.0)) {
+        *bad = 3;
+        A[j * s + j] = 1.0;
+      } else {
+        A[j * s + j] = sqrt(d);
+      }
+    }
+    __syncthreads();
+    const double ljj = A[j * s + j];
+    for (int r = j + 1 + tid; r < s; r += SB) A[r * s + j] /= ljj;
+    __syncthreads();
+    const int w = s - j - 1;
+    for (int q = tid; q < w * w; q += SB) {
+      const int r = j + 1 + q / w, c = j + 1 + q % w;
+      if (c <= r) A[r * s + c] -= A[r * s + j] * A[c * s + j];
+    }
+  }
+  __syncthreads();
+  for (int q = tid; q < s * s; q += SB) {
+    const int r = q / s, c = q % s;
+    if (c > r) A[q] = 0.0;
+  }
+  __syncthreads();
+}
+
+// X <- L^{-1} X (trans=0) or L^{-T} X (trans=1); L lower s x s, X s x nr (ld ldx)
+__device__ void wg_trsm_lower(const double* L, int s, double* X, int nr, int ldx, int trans) {
+  const int tid = threadIdx.x;
+  for (int c = tid; c < nr; c += SB) {
+    if (!trans) {
+      for (int i = 0; i < s; ++i) {
+        double acc = X[i * ldx + c];
+        for (int l = 0; l < i; ++l) acc -= L[i * s + l] * X[l * ldx + c];
+        X[i * ldx + c] = acc / L[i * s + i];
+      }
+    } else {
+      for (int i = s - 1; i >= 0; --i) {
+        double acc = X[i * ldx + c];
+        for (int l = i + 1; l < s; ++l) acc -= L[l * s + i] * X[l * ldx + c];
+        X[i * ldx + c] = acc / L[i * s + i];
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// C (s x nr) += alpha * op(A) (s x s) * B (s x nr)
+__device__ void wg_gemm_acc(const double* A, int s, int ta, const double* B, int ldb, double* C, int ldc,
+                            int nr, double alpha) {
+  const int tid = threadIdx.x;
+  for (int q = tid; q < s * nr; q += SB) {
+    const int i = q / nr, c = q % nr;
+    double acc = 0.0;
+    for (int l = 0; l < s; ++l) acc += (ta ? A[l * s + i] : A[i * s + l]) * B[l * ldb + c];
+    C[i * ldc + c] += alpha * acc;
+  }
+  __syncthreads();
+}
+
+__global__ void __launch_bounds__(SB)
+banded_spline_kernel(int m, int s, const double* __restrict__ Hd, const double* __restrict__ Bd, double eps,
+                     int kpow, double* __restrict__ Ld, double* __restrict__ Lsub, double* __restrict__ U,
+                     double* __restrict__ tmp, int* __restrict__ bad) {
+  const int tid = threadIdx.x;
+  const int ss = s * s;
+  // factorisation
+  for (int j = 0; j < m; ++j) {
+    double* D = Ld + (int64_t)j * ss;
+    for (int q = tid; q < ss; q += SB) D[q] = Hd[(int64_t)j * ss + q] + ((q / s == q % s) ? eps : 0.0);
+    __syncthreads();
+    if (j > 0) {
+      // D -= Lsub_{j-1} Lsub_{j-1}^T
+      const double* Ls = Lsub + (int64_t)(j - 1) * ss;
+      for (int q = tid; q < ss; q += SB) {
+        const int r = q / s, c = q % s;
+        double acc = 0.0;
+        for (int l = 0; l < s; ++l) acc += Ls[r * s + l] * Ls[c * s + l];
+        D[q] -= acc;
+      }
+      __syncthreads();
+    }
+    wg_chol_lower(D, s, bad);
+    if (j + 1 < m) {
+      // Lsub_j = B_j L_jj^{-T}  <=>  Lsub_j^T = L_jj^{-1} B_j^T
+      double* Ls = Lsub + (int64_t)j * ss;
+      const double* B = Bd + (int64_t)j * ss;
+      for (int q = tid; q < ss; q += SB) {
+        const int r = q / s, c = q % s;
+        tmp[q] = B[c * s + r];   // B^T
+      }
+      __syncthreads();
+      wg_trsm_lower(D, s, tmp, s, s, 0);
+      for (int q = tid; q < ss; q += SB) {
+        const int r = q / s, c = q % s;
+        Ls[q] = tmp[c * s + r];
+      }
+      __syncthreads();
+    }
+  }
+  // right-hand side F_1
+  const int64_t ms = (int64_t)m * s;
+  for (int64_t q = tid; q < ms * s; q += SB) {
+    const int64_t r = q / s;
+    const int c = (int)(q % s);
+    U[q] = (r == c) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  for (int rep = 0; rep < kpow; ++rep) {
+    // forward: Z_j = L_jj^{-1} (Y_j - Lsub_{j-1} Z_{j-1})
+    for (int j = 0; j < m; ++j) {
+      double* Yj = U + (int64_t)j * ss;
+      if (j > 0) wg_gemm_acc(Lsub + (int64_t)(j - 1) * ss, s, 0, U + (int64_t)(j - 1) * ss, s, Yj, s, s, -1.0);
+      wg_trsm_lower(Ld + (int64_t)j * ss, s, Yj, s, s, 0);
+    }
+    // backward: Y_j = L_jj^{-T} (Z_j - Lsub_j^T Y_{j+1})
+    for (int j = m - 1; j >= 0; --j) {
+      double* Yj = U + (int64_t)j * ss;
+      if (j + 1 < m) wg_gemm_acc(Lsub + (int64_t)j * ss, s, 1, U + (int64_t)(j + 1) * ss, s, Yj, s, s, -1.0);
+      wg_trsm_lower(Ld + (int64_t)j * ss, s, Yj, s, s, 1);
+    }
+  }
+}
+
+size_t banded_work_elems(int m, int s) { return (size_t)(2 * m + 1) * s * s; }
+
+void launch_banded_spline(int m, int s, const double* Hd, const double* Bd, double eps, int k, double* work,
+                          double* U, int* bad, hipStream_t st) {
+  const size_t ss = (size_t)s * s;
+  hipLaunchKernelGGL(banded_spline_kernel, dim3(1), dim3(SB), 0, st, m, s, Hd, Bd, eps, k, work,
+                     work + m * ss, U, work + 2 * m * ss, bad);
+  GK_HIP(hipGetLastError());
+}
+
+// ------------------------------------------------------------ s x s solve
+// (K + gamma I) c = y.  spd: Cholesky; otherwise LU with partial pivoting.
+// W is scratch of s*s doubles.  bad = 4 when the system is not solvable.
+__global__ void __launch_bounds__(SB)
+small_solve_kernel(int s, const double* __restrict__ K, double gamma, const double* __restrict__ y,
+                   double* __restrict__ c, double* __restrict__ W, int* __restrict__ piv, int spd,
+                   int* __restrict__ bad) {
+  const int tid = threadIdx.x;
+  __shared__ int pr_sh;
+  __shared__ int fail_sh;
+  for (int q = tid; q < s * s; q += SB) W[q] = K[q] + ((q / s == q % s) ? gamma : 0.0);
+  for (int q = tid; q < s; q += SB) c[q] = y[q];
+  if (tid == 0) fail_sh = 0;
+  __syncthreads();
+  if (spd) {
+    // symmetrise (K is symmetric up to rounding) and factor
+    for (int q = tid; q < s * s; q += SB) {
+      const int r = q / s, cc = q % s;
+      if (cc < r) {
+        const double v = 0.5 * (W[r * s + cc] + W[cc * s + r]);
+        W[r * s + cc] = v;
+        W[cc * s + r] = v;
+      }
+    }
+    int b = 0;
+    wg_chol_lower(W, s, &b);
+    if (tid == 0 && b) fail_sh = 1;
+    __syncthreads();
+    if (!fail_sh) {
+      wg_trsm_lower(W, s, c, 1, 1, 0);
+      wg_trsm_lower(W, s, c, 1, 1, 1);
+    }
+  } else {
+    for (int j = 0; j < s; ++j) {
+      if (tid == 0) {
+        int p = j;
+        double best = fabs(W[j * s + j]);
+        for (int r = j + 1; r < s; ++r)
+          if (fabs(W[r * s + j]) > best) {
+            best = fabs(W[r * s + j]);
+            p = r;
+          }
+        pr_sh = p;
+        if (best == 0.0) fail_sh = 1;
+        piv[j] = p;
+      }
+      __syncthreads();
+      if (fail_sh) break;
+      const int p = pr_sh;
+      if (p != j) {
+        for (int q = tid; q < s; q += SB) {
+          const double t = W[j * s + q];
+          W[j * s + q] = W[p * s + q];
+          W[p * s + q] = t;
+        }
+        if (tid == 0) {
+          const double t = c[j];
+          c[j] = c[p];
+          c[p] = t;
+        }
+      }
+      __syncthreads();
+      const double d = W[j * s + j];
+      for (int r = j + 1 + tid; r < s; r += SB) W[r * s + j] /= d;
+      __syncthreads();
+      const int w = s - j - 1;
+      for (int q = tid; q < w * w; q += SB) {
+        const int r = j + 1 + q / w, cc = j + 1 + q % w;
+        W[r * s + cc] -= W[r * s + j] * W[j * s + cc];
+      }
+      __syncthreads();
+    }
+    if (!fail_sh && tid == 0) {
+      for (int i = 0; i < s; ++i) {
+        double acc = c[i];
+        for (int l = 0; l < i; ++l) acc -= W[i * s + l] * c[l];
+        c[i] = acc;
+      }
+      for (int i = s - 1; i >= 0; --i) {
+        double acc = c[i];
+        for (int l = i + 1; l < s; ++l) acc -= W[i * s + l] * c[l];
+        c[i] = acc / W[i * s + i];
+      }
+    }
+  }
+  __syncthreads();
+  if (tid == 0 && fail_sh) *bad = 4;
+}
+
+void launch_small_solve(int s, const double* K, double gamma, const double* y, double* c, double* work,
+                        int* piv, bool spd, int* bad, hipStream_t st) {
+  hipLaunchKernelGGL(small_solve_kernel, dim3(1), dim3(SB), 0, st, s, K, gamma, y, c, work, piv, spd ? 1 : 0,
+                     bad);
+  GK_HIP(hipGetLastError());
+}
+
+}  // namespace gk

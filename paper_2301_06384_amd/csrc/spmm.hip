@@ -1,0 +1,152 @@
+// CSR SpMM with the Laplacian in difference form, fused three-term epilogue.
+//
+// The products L*Q_k of Alg. 1 / Alg. 2 (and T_k(I - 2L/Lambda) E_W of the
+// Chebyshev recurrence, Sec. 3.4) are the block matrix-vector products
+// counted in Table 1.  Blocks are row-major n x ld (ld >= s, zero padded),
+// so a neighbour's row is one contiguous ld*8-byte segment: each row of the
+// output is owned by ld/VPT consecutive lanes that read VPT doubles of every
+// neighbour row with one vector load (coalesced gathers).
+//
+// (L v)_i = d_i v_i - sum_{j != i} w_ij v_j with d_i = sum_j w_ij + c_i
+// accumulated in float64; with float32 weights d_i is the float64 sum of the
+// rounded weights, so L 1 = c holds for the rounded operator too.
+#include "gk_internal.h"
+
+namespace gk {
+
+enum { W_UNIT = 0, W_F64 = 1, W_F32 = 2 };
+
+template <int VPT>
+struct VecD;
+template <>
+struct VecD<1> {
+  __device__ static void load(const double* p, double* v) { v[0] = p[0]; }
+  __device__ static void store(double* p, const double* v) { p[0] = v[0]; }
+};
+template <>
+struct VecD<2> {
+  __device__ static void load(const double* p, double* v) {
+    double2 t = *reinterpret_cast<const double2*>(p);
+    v[0] = t.x; v[1] = t.y;
+  }
+  __device__ static void store(double* p, const double* v) {
+    *reinterpret_cast<double2*>(p) = make_double2(v[0], v[1]);
+  }
+};
+template <>
+struct VecD<4> {
+  __device__ static void load(const double* p, double* v) {
+    VecD<2>::load(p, v); VecD<2>::load(p + 2, v + 2);
+  }
+  __device__ static void store(double* p, const double* v) {
+    VecD<2>::store(p, v); VecD<2>::store(p + 2, v + 2);
+  }
+};
+template <>
+struct VecD<8> {
+  __device__ static void load(const double* p, double* v) {
+    VecD<4>::load(p, v); VecD<4>::load(p + 4, v + 4);
+  }
+  __device__ static void store(double* p, const double* v) {
+    VecD<4>::store(p, v); VecD<4>::store(p + 4, v + 4);
+  }
+};
+
+template <int VPT, int WM>
+__global__ void __launch_bounds__(256)
+spmm_diff_kernel(int64_t n, int ld, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                 const double* __restrict__ w64, const float* __restrict__ w32,
+                 const double* __restrict__ d, const double* __restrict__ V,
+                 const double* __restrict__ Vprev, double* __restrict__ out, double a, double b,
+                 double gm, double* __restrict__ acc, double e, const double* __restrict__ e_dev) {
+  const int slots = ld / VPT;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t row = t / slots;
+  if (row >= n) return;
+  const int c0 = (int)(t - row * slots) * VPT;
+  double s[VPT];
+#pragma unroll
+  for (int q = 0; q < VPT; ++q) s[q] = 0.0;
+  const int p0 = rp[row], p1 = rp[row + 1];
+  int p = p0;
+  // two neighbours per iteration to keep two gathers in flight
+  for (; p + 1 < p1; p += 2) {
+    const int j0 = ci[p], j1 = ci[p + 1];
+    double w0 = 1.0, w1 = 1.0;
+    if (WM == W_F64) { w0 = w64[p]; w1 = w64[p + 1]; }
+    if (WM == W_F32) { w0 = (double)w32[p]; w1 = (double)w32[p + 1]; }
+    double v0[VPT], v1[VPT];
+    VecD<VPT>::load(V + (int64_t)j0 * ld + c0, v0);
+    VecD<VPT>::load(V + (int64_t)j1 * ld + c0, v1);
+#pragma unroll
+    for (int q = 0; q < VPT; ++q) s[q] = fma(w0, v0[q], fma(w1, v1[q], s[q]));
+  }
+  if (p < p1) {
+    const int j0 = ci[p];
+    double w0 = 1.0;
+    if (WM == W_F64) w0 = w64[p];
+    if (WM == W_F32) w0 = (double)w32[p];
+    double v0[VPT];
+    VecD<VPT>::load(V + (int64_t)j0 * ld + c0, v0);
+#pragma unroll
+    for (int q = 0; q < VPT; ++q) s[q] = fma(w0, v0[q], s[q]);
+  }
+  double vi[VPT], o[VPT];
+  VecD<VPT>::load(V + row * ld + c0, vi);
+  const double di = d[row];
+#pragma unroll
+  for (int q = 0; q < VPT; ++q) o[q] = a * (di * vi[q] - s[q]) + b * vi[q];
+  if (Vprev) {
+    double vp[VPT];
+    VecD<VPT>::load(Vprev + row * ld + c0, vp);
+#pragma unroll
+    for (int q = 0; q < VPT; ++q) o[q] += gm * vp[q];
+  }
+  VecD<VPT>::store(out + row * ld + c0, o);
+  if (acc) {
+    if (e_dev) e = *e_dev;
+    double ac[VPT];
+    VecD<VPT>::load(acc + row * ld + c0, ac);
+#pragma unroll
+    for (int q = 0; q < VPT; ++q) ac[q] = fma(e, o[q], ac[q]);
+    VecD<VPT>::store(acc + row * ld + c0, ac);
+  }
+}
+
+template <int VPT>
+static void spmm_dispatch_w(const gk_graph* g, bool fp32w, int ld, const double* V, const double* Vp,
+                            double* out, double a, double b, double gm, double* acc, double e,
+                            const double* e_dev, hipStream_t st) {
+  const int slots = ld / VPT;
+  const int64_t threads = g->n * slots;
+  const int bs = 256;
+  const int64_t grid = (threads + bs - 1) / bs;
+  const double* d = fp32w ? g->d32 : g->d64;
+  if (g->unit) {
+    hipLaunchKernelGGL((spmm_diff_kernel<VPT, W_UNIT>), dim3((unsigned)grid), dim3(bs), 0, st, g->n,
+                       ld, g->rp, g->ci, g->w64, g->w32, d, V, Vp, out, a, b, gm, acc, e, e_dev);
+  } else if (fp32w) {
+    hipLaunchKernelGGL((spmm_diff_kernel<VPT, W_F32>), dim3((unsigned)grid), dim3(bs), 0, st, g->n,
+                       ld, g->rp, g->ci, g->w64, g->w32, d, V, Vp, out, a, b, gm, acc, e, e_dev);
+  } else {
+    hipLaunchKernelGGL((spmm_diff_kernel<VPT, W_F64>), dim3((unsigned)grid), dim3(bs), 0, st, g->n,
+                       ld, g->rp, g->ci, g->w64, g->w32, d, V, Vp, out, a, b, gm, acc, e, e_dev);
+  }
+  GK_HIP(hipGetLastError());
+}
+
+void launch_spmm(const gk_graph* g, bool fp32_weights, int ld, const double* V, const double* Vprev,
+                 double* out, double a, double b, double gmul, double* acc, double e, const double* e_dev,
+                 hipStream_t st) {
+  // lanes per row: at most 64 (one wavefront), VPT doubles each
+  if (ld <= 128) {
+    spmm_dispatch_w<2>(g, fp32_weights, ld, V, Vprev, out, a, b, gmul, acc, e, e_dev, st);
+  } else if (ld <= 256) {
+    spmm_dispatch_w<4>(g, fp32_weights, ld, V, Vprev, out, a, b, gmul, acc, e, e_dev, st);
+  } else {
+    // ld is a multiple of 16; 8 doubles per lane
+    spmm_dispatch_w<8>(g, fp32_weights, ld, V, Vprev, out, a, b, gmul, acc, e, e_dev, st);
+  }
+}
+
+}  // namespace gk
