@@ -169,6 +169,8 @@ def main():
         "phase_ms": {k: stats[k] for k in ("t_spmm_ms", "t_orth_ms", "t_reorth_ms", "t_phi_ms", "t_asm_ms",
                                            "t_total_ms")},
         "phi_method": stats["phi_method"],
+        "mixed_reorth_steps": stats["n_reorth"],
+        "mixed_orth_estimate": stats["orth_est"],
         "roofline": {"kernel": "spmm_diff_kernel", "bound": "hbm", "achieved": spmm_gbs,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": spmm_gbs / HBM_PEAK_GBS,
                      "traffic": traffic, "avg_launch_ms": spmm_ms, "alg_bytes_per_launch": spmm_bytes},

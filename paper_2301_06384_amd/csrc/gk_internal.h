@@ -155,8 +155,35 @@ void launch_kww_gram(int n, int s, const double* S, int lds, const double* g, do
 size_t banded_work_elems(int m, int s);
 void launch_banded_spline(int m, int s, const double* Hd, const double* Bd, double eps, int k,
                           double* work, double* U, int* bad, hipStream_t st);
+bool small_wave_ok(int ld);
+void launch_cholqr_wave(const double* G, int ld, int s, int pass, const double* diag_prev, double thr, double* R,
+                        double* Rinv, double* diag_out, int* n_defl, const double* R1, const double* R1inv,
+                        double* Rc, double* Bout, hipStream_t st);
+void launch_banded_spline_wave(int m, int s, const double* Hd, const double* Bd, double eps, int k, double* work,
+                               double* U, int* bad, hipStream_t st);
+void launch_cholqr_reg(const double* G, int ld, int s, int pass, const double* diag_prev, double thr, double* R,
+                       double* Rinv, double* diag_out, int* n_defl, const double* R1, const double* R1inv, double* Rc,
+                       double* Bout, hipStream_t st);
+void launch_banded_spline_reg(int m, int s, const double* Hd, const double* Bd, double eps, int k, double* work,
+                              double* U, int* bad, hipStream_t st);
+void launch_cholqr_flag(const double* G, int ld, int s, int pass, const double* diag_prev, double thr, double* R,
+                        double* Rinv, double* diag_out, int* n_defl, const double* R1, const double* R1inv, double* Rc,
+                        double* Bout, const int* flag, hipStream_t st);
+void launch_omega(int k, int s, int ld, const double* Wk, const double* Wkm1, double* Wk1, const double* Hd,
+                  const double* Bd, const double* Rc, double nu, double tau, double floor_re, double floor_loc,
+                  double* est_part, int* fr, int* forced, double* est_out, int* nre, hipStream_t st);
+// deterministic sum of nparts equally long partial vectors: out[i] = sum_c part[c*len + i]
+void launch_reduce_parts(int64_t len, int nparts, const double* part, double* out, const int* flag, hipStream_t st);
 void launch_small_solve(int s, const double* K, double gamma, const double* y, double* c, double* work,
                         int* piv, bool spd, int* bad, hipStream_t st);
+
+// panel.hip -- fused row-panel MFMA passes (ld in {16, 32, 48, 64})
+enum { PM_GRAMV = 0, PM_UPDATE_SELF = 1, PM_APPLY_SELF = 2, PM_APPLY_WRITE = 3 };
+bool panel_ok(int ld);
+size_t panel_scratch_elems(int64_t n, int ld);
+void launch_panel(int mode, int64_t n, int ld, int nbv, const double* X, double* Xout, float* X32,
+                  const double* V0, const double* V1, const double* Cupd, const double* Rm, double* part,
+                  double* Cout, hipStream_t st, const int* flag = nullptr);
 
 // krylov.hip -- one call of the compute entry points
 struct CallArgs {

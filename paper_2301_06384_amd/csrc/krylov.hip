@@ -271,7 +271,10 @@ static void phi_stage_block(Job& J, const double* Hd, const double* Bd, double* 
   if (int_spline && !(J.flags & GK_PHI_EIG)) {
     // exact banded evaluation (block tridiagonal Cholesky solves)
     double* work = J.ar.get<double>(banded_work_elems(m, s));
-    launch_banded_spline(m, s, Hd, Bd, J.phi.eps, (int)kk, work, U, J.dflags + 0, J.st);
+    if (s <= 64)
+      launch_banded_spline_reg(m, s, Hd, Bd, J.phi.eps, (int)kk, work, U, J.dflags + 0, J.st);
+    else
+      launch_banded_spline(m, s, Hd, Bd, J.phi.eps, (int)kk, work, U, J.dflags + 0, J.st);
     launch_store_H(U, s, s, K, J.st);          // K = sym(U[0:s, :])
     J.phi_method = 1;
     return;
@@ -341,48 +344,124 @@ static void run_cbl(Job& J) {
   // start block Q_1 = E_W (Alg. 1)
   launch_start_block(n, ld, s, J.samp, 1.0, V64(0), mixed ? Va : nullptr, st);
 
+  const bool pan = panel_ok(ld);
+  double* ppart = pan ? J.ar.get<double>(panel_scratch_elems(n, ld)) : nullptr;
+  // partial reorthogonalisation (GK_MIXED, s <= 64): block omega estimate,
+  // reorthogonalisation against the float32 archive only when it is needed
+  const bool pro = mixed && !full && !no_reorth && small_wave_ok(ld) && m > 2;
+  double* Wr[3] = {nullptr, nullptr, nullptr};
+  double* est_part = nullptr;
+  int* fr = nullptr;
+  int* forced = nullptr;
+  size_t pe_all = 0;
+  double* part_all = nullptr;
+  if (pro) {
+    for (int i = 0; i < 3; ++i) {
+      Wr[i] = J.ar.get<double>((size_t)m * s * s);
+      launch_zero(Wr[i], (size_t)m * s * s * sizeof(double), st);
+    }
+    est_part = J.ar.get<double>(m);
+    fr = J.ar.get<int>(m);
+    forced = J.ar.get<int>(m + 1);
+    launch_zero(forced, sizeof(int) * (m + 1), st);
+    for (int nb = 1; nb <= m; ++nb) pe_all = std::max(pe_all, gram_scratch_elems(n, nb, ld));
+    part_all = J.ar.get<double>(pe_all);
+  }
+  // tolerances of the estimate: threshold, floor after a reorthogonalisation
+  // against the float32 archive, floor of the two explicitly orthogonalised
+  // neighbours, and the per-step rounding model
+  const double om_tau = 1e-4, om_floor_re = 2e-8, om_floor_loc = 1e-14;
+  const double om_nu = 1.1102230246251565e-16 * g->lambda_max * std::sqrt((double)s);
   for (int k = 0; k < m; ++k) {
     double* Vk = V64(k);
+    double* Vkm1 = k > 0 ? V64(k - 1) : nullptr;
+    const int nbv = k > 0 ? 2 : 1;
     // X = L Q_k
     J.tm.begin(PH_SPMM);
     launch_spmm(g, mixed, ld, Vk, nullptr, X, 1.0, 0.0, 0.0, nullptr, 0.0, nullptr, st);
     J.tm.begin(PH_ORTH);
-    // local block: [Q_{k-1}, Q_k];  C = local^T X; H_kk = sym(C_k); X -= local C
-    BlockList loc;
-    if (k > 0) {
-      double* Vkm1 = V64(k - 1);
-      loc = BlockList{Vkm1, (int64_t)(Vk - Vkm1), 2, false};
-    } else {
-      loc = BlockList{Vk, blk, 1, false};
+    // local block [Q_{k-1}, Q_k]:  C = local^T X;  H_kk = sym(C_k);  X -= local C
+    // (the Q_{k-1} part realises the three-term recurrence of Alg. 1)
+    BlockList loc = (k > 0) ? BlockList{Vkm1, (int64_t)(Vk - Vkm1), 2, false} : BlockList{Vk, blk, 1, false};
+    const double* V0 = k > 0 ? Vkm1 : Vk;
+    const double* V1 = k > 0 ? Vk : nullptr;
+    const int local_passes = mixed ? 1 : 2;
+    for (int pass = 0; pass < local_passes; ++pass) {
+      if (pan) {
+        launch_panel(PM_GRAMV, n, ld, nbv, X, nullptr, nullptr, V0, V1, nullptr, nullptr, ppart, C, st);
+        if (pass == 0) launch_store_H(C + (int64_t)(nbv - 1) * l2, ld, s, Hd + (int64_t)k * s * s, st);
+        launch_panel(PM_UPDATE_SELF, n, ld, nbv, X, X, nullptr, V0, V1, C, nullptr, ppart, G, st);
+      } else {
+        launch_gram(n, ld, loc, X, C, part, nullptr, st);
+        if (pass == 0) launch_store_H(C + (int64_t)(loc.nb - 1) * l2, ld, s, Hd + (int64_t)k * s * s, st);
+        launch_tsgemm(n, ld, loc, C, X, X, nullptr, -1.0, 1.0, nullptr, st);
+      }
     }
-    launch_gram(n, ld, loc, X, C, part, nullptr, st);
-    launch_store_H(C + (int64_t)(loc.nb - 1) * l2, ld, s, Hd + (int64_t)k * s * s, st);
-    launch_tsgemm(n, ld, loc, C, X, X, nullptr, -1.0, 1.0, nullptr, st);
-    // second local pass (both paths)
-    launch_gram(n, ld, loc, X, C, part, nullptr, st);
-    launch_tsgemm(n, ld, loc, C, X, X, nullptr, -1.0, 1.0, nullptr, st);
     J.tm.begin(PH_REORTH);
+    bool g_ready = pan;   // the panel update already produced G = X^T X
     if (!no_reorth && full && k >= 1) {
       BlockList all = mixed ? BlockList{Va, blk, k + 1, true} : BlockList{Vb, blk, k + 1, false};
       for (int pass = 0; pass < 2; ++pass) {
         launch_gram(n, ld, all, X, C, part, nullptr, st);
         launch_tsgemm(n, ld, all, C, X, X, nullptr, -1.0, 1.0, nullptr, st);
       }
+      g_ready = false;
     }
     J.tm.begin(PH_ORTH);
     BlockList xl{X, blk, 1, false};
-    launch_gram(n, ld, xl, X, G, part, nullptr, st);
+    if (!g_ready) launch_gram(n, ld, xl, X, G, part, nullptr, st);
     if (k + 1 < m) {
       // CholQR2: X = Q_{k+1} H_{k+1,k}
-      launch_cholqr_factor(G, ld, s, 1, nullptr, J.thr(), W, R1, R1i, d1, nullptr, st);
-      launch_tsgemm(n, ld, xl, R1i, nullptr, Y, nullptr, 1.0, 0.0, nullptr, st);
-      BlockList yl{Y, blk, 1, false};
-      launch_gram(n, ld, yl, Y, G, part, nullptr, st);
-      launch_cholqr_factor(G, ld, s, 2, d1, J.thr(), W, R2, R2i, d2, J.dflags + 1, st);
-      launch_small_gemm(ld, ld, ld, R1i, ld, false, R2i, ld, false, R12i, ld, 1.0, 0.0, st);
-      launch_small_gemm(s, s, s, R2, ld, false, R1, ld, false, Bd + (int64_t)k * s * s, s, 1.0, 0.0, st);
-      launch_tsgemm(n, ld, xl, R12i, nullptr, V64(k + 1), mixed ? Va + (int64_t)(k + 1) * blk : nullptr,
-                    1.0, 0.0, nullptr, st);
+      const bool wave = small_wave_ok(ld);
+      if (wave)
+        launch_cholqr_reg(G, ld, s, 1, nullptr, J.thr(), R1, R1i, d1, nullptr, nullptr, nullptr, nullptr, nullptr, st);
+      else
+        launch_cholqr_factor(G, ld, s, 1, nullptr, J.thr(), W, R1, R1i, d1, nullptr, st);
+      if (pan) {
+        launch_panel(PM_APPLY_SELF, n, ld, 0, X, nullptr, nullptr, nullptr, nullptr, nullptr, R1i, ppart, G, st);
+      } else {
+        launch_tsgemm(n, ld, xl, R1i, nullptr, Y, nullptr, 1.0, 0.0, nullptr, st);
+        BlockList yl{Y, blk, 1, false};
+        launch_gram(n, ld, yl, Y, G, part, nullptr, st);
+      }
+      if (wave) {
+        launch_cholqr_reg(G, ld, s, 2, d1, J.thr(), R2, R2i, d2, J.dflags + 1, R1, R1i, R12i,
+                          Bd + (int64_t)k * s * s, st);
+      } else {
+        launch_cholqr_factor(G, ld, s, 2, d1, J.thr(), W, R2, R2i, d2, J.dflags + 1, st);
+        launch_small_gemm(ld, ld, ld, R1i, ld, false, R2i, ld, false, R12i, ld, 1.0, 0.0, st);
+        launch_small_gemm(s, s, s, R2, ld, false, R1, ld, false, Bd + (int64_t)k * s * s, s, 1.0, 0.0, st);
+      }
+      if (pro && k >= 1) {
+        const int* fk = fr + k;
+        launch_omega(k, s, ld, Wr[k % 3], Wr[(k + 2) % 3], Wr[(k + 1) % 3], Hd, Bd, R12i, om_nu, om_tau, om_floor_re,
+                     om_floor_loc, est_part, fr, forced, J.dscal + 1, J.dflags + 3, st);
+        // flagged: reorthogonalise X against the archive (two passes), redo CholQR2
+        J.tm.begin(PH_REORTH);
+        BlockList all{Va, blk, k + 1, true};
+        for (int pass = 0; pass < 2; ++pass) {
+          launch_gram(n, ld, all, X, C, part_all, fk, st);
+          launch_tsgemm(n, ld, all, C, X, X, nullptr, -1.0, 1.0, fk, st);
+        }
+        launch_gram(n, ld, xl, X, G, part_all, fk, st);
+        launch_cholqr_flag(G, ld, s, 1, nullptr, J.thr(), R1, R1i, d1, nullptr, nullptr, nullptr, nullptr, nullptr, fk,
+                           st);
+        if (pan) {
+          launch_panel(PM_APPLY_SELF, n, ld, 0, X, nullptr, nullptr, nullptr, nullptr, nullptr, R1i, ppart, G, st, fk);
+        } else {
+          launch_tsgemm(n, ld, xl, R1i, nullptr, Y, nullptr, 1.0, 0.0, fk, st);
+          launch_gram(n, ld, BlockList{Y, blk, 1, false}, Y, G, part_all, fk, st);
+        }
+        launch_cholqr_flag(G, ld, s, 2, d1, J.thr(), R2, R2i, d2, nullptr, R1, R1i, R12i, Bd + (int64_t)k * s * s, fk,
+                           st);
+        J.tm.begin(PH_ORTH);
+      }
+      float* arch32 = mixed ? Va + (int64_t)(k + 1) * blk : nullptr;
+      if (pan)
+        launch_panel(PM_APPLY_WRITE, n, ld, 0, X, V64(k + 1), arch32, nullptr, nullptr, nullptr, R12i, ppart,
+                     nullptr, st);
+      else
+        launch_tsgemm(n, ld, xl, R12i, nullptr, V64(k + 1), arch32, 1.0, 0.0, nullptr, st);
     } else {
       // ||X_m||_F: residual indicator (the unused H_{m+1,m})
       hipLaunchKernelGGL(trace_sqrt_kernel, dim3(1), dim3(256), 0, st, G, ld, s, J.dscal);
@@ -728,7 +807,9 @@ int run_call(const CallArgs& a, hipStream_t stream) {
     a.st->resid_norm = hscal[0];
     a.st->phi_method = J.phi_method;
     a.st->footprint_bytes = J.ar.bytes;
-    a.st->n_reorth = (J.variant <= GK_SBL && (!J.mixed() || (J.flags & GK_FULL_REORTH))) ? std::max(J.m - 1, 0) : 0;
+    a.st->n_reorth = (J.variant <= GK_SBL && (!J.mixed() || (J.flags & GK_FULL_REORTH))) ? std::max(J.m - 1, 0)
+                                                                                       : hflags[3];
+    a.st->orth_est = hscal[1];
     const int ldv = J.ld;
     const int slots = ldv <= 128 ? ldv / 2 : (ldv <= 256 ? ldv / 4 : ldv / 8);
     (void)slots;

@@ -83,14 +83,32 @@ gram_kernel(int64_t n, int ld, const void* __restrict__ Abase, int64_t astride, 
     }
 }
 
-__global__ void reduce_chunks_kernel(int64_t len, int nchunks, const double* __restrict__ part,
-                                     double* __restrict__ out, const int* __restrict__ flag) {
+// out[i] = sum_{c < nparts} part[c*len + i] in a fixed order: block b owns
+// outputs [16b, 16b+16); its 16 thread groups sum interleaved parts, then
+// the 16 partial sums are added in group order.
+__global__ void __launch_bounds__(256)
+reduce_parts_kernel(int64_t len, int nparts, const double* __restrict__ part, double* __restrict__ out,
+                    const int* __restrict__ flag) {
   if (flag && *flag == 0) return;
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= len) return;
+  __shared__ double red[16][17];
+  const int o = threadIdx.x & 15, g = threadIdx.x >> 4;
+  const int64_t i = (int64_t)blockIdx.x * 16 + o;
   double s = 0.0;
-  for (int c = 0; c < nchunks; ++c) s += part[(int64_t)c * len + i];
-  out[i] = s;
+  if (i < len)
+    for (int c = g; c < nparts; c += 16) s += part[(int64_t)c * len + i];
+  red[g][o] = s;
+  __syncthreads();
+  if (g == 0 && i < len) {
+    double t = 0.0;
+    for (int q = 0; q < 16; ++q) t += red[q][o];
+    out[i] = t;
+  }
+}
+
+void launch_reduce_parts(int64_t len, int nparts, const double* part, double* out, const int* flag, hipStream_t st) {
+  hipLaunchKernelGGL(reduce_parts_kernel, dim3((unsigned)((len + 15) / 16)), dim3(256), 0, st, len, nparts, part, out,
+                     flag);
+  GK_HIP(hipGetLastError());
 }
 
 static void gram_geometry(int64_t n, int nb, int ld, int* nx, int* ny, int* nch, int64_t* rpc) {
@@ -128,10 +146,7 @@ void launch_gram(int64_t n, int ld, BlockList A, const double* B, double* C, dou
     hipLaunchKernelGGL(gram_kernel<false>, grid, dim3(256), 0, st, n, ld, A.base, A.stride, A.nb, B,
                        part, rpc, flag);
   GK_HIP(hipGetLastError());
-  const int64_t len = (int64_t)A.nb * ld * ld;
-  hipLaunchKernelGGL(reduce_chunks_kernel, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, st, len,
-                     nch, part, C, flag);
-  GK_HIP(hipGetLastError());
+  launch_reduce_parts((int64_t)A.nb * ld * ld, nch, part, C, flag, st);
 }
 
 // ------------------------------------------------------- tall-skinny GEMM
@@ -351,10 +366,7 @@ void launch_coldots(int64_t n, int ld, BlockList A, const double* B, double* out
     hipLaunchKernelGGL(coldots_kernel<false>, dim3(nch), dim3(256), 0, st, n, ld, A.base, A.stride, A.nb,
                        B, part, rpc, flag);
   GK_HIP(hipGetLastError());
-  const int64_t len = (int64_t)A.nb * ld;
-  hipLaunchKernelGGL(reduce_chunks_kernel, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, st, len,
-                     nch, part, out, flag);
-  GK_HIP(hipGetLastError());
+  launch_reduce_parts((int64_t)A.nb * ld, nch, part, out, flag, st);
 }
 
 template <bool F32>

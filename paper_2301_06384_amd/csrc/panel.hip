@@ -1,0 +1,290 @@
+// Fused row-panel kernels on FP64 matrix cores for the local block
+// orthogonalisation of classical block Lanczos (Alg. 1: H_kk = Q_k^T X,
+// X -= Q_k H_kk, QR of X) with block widths ld in {16, 32, 48, 64}.
+//
+// A workgroup (4 wavefronts) walks over 32-row tiles of the n x ld blocks.
+// Per tile it stages the rows of X and of the local basis blocks in LDS, forms
+// the updated rows X_new (X - V C, or X R) on MFMA, optionally writes them,
+// and accumulates Gram products G^T X_new (G = basis blocks and/or X_new
+// itself) in registers across all its tiles.  Per-workgroup Gram partials are
+// summed afterwards in a fixed order (no atomics: bitwise reproducible).
+//
+// v_mfma_f64_16x16x4f64 operand layout (lane l of 64):
+//   A (16 x 4):  A[l % 16][l / 16]
+//   B (4 x 16):  B[l / 16][l % 16]
+//   D (16 x 16): register r of lane l holds D[4 r + l / 16][l % 16]
+#include "gk_internal.h"
+
+namespace gk {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+constexpr int PT_ROWS = 32;      // rows per tile
+constexpr int PT_THREADS = 256;  // 4 wavefronts: slab (w & 1) x column half (w >> 1)
+constexpr int PT_MAXGRID = 512;  // two workgroups per CU
+
+__device__ __forceinline__ d4 mfma64(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+struct PanelArgs {
+  int64_t n;
+  const double* X;       // n x ld input
+  double* Xout;          // n x ld output (WRITE)
+  float* X32;            // n x ld float copy (W32)
+  const double* V0;      // local basis blocks (n x ld)
+  const double* V1;
+  const double* C;       // (nbv*ld) x ld update coefficients (UPDATE)
+  const double* Rm;      // ld x ld upper triangular right factor (APPLY)
+  double* part;          // [gridDim.x][ngb*ld][ld] Gram partials
+  const int* flag;       // when non-null and *flag == 0 the pass is skipped
+};
+
+// NT: ld / 16.  NBV: local blocks staged.  UPDATE: X_new = X - [V] C.
+// APPLY: X_new = X Rm.  GRAMV: Gram [V]^T X_new.  SELF: Gram X_new^T X_new
+// (symmetric: only tiles gi <= xj are formed, the partial is mirrored).
+template <int NT, int NBV, bool UPDATE, bool APPLY, bool GRAMV, bool SELF, bool WRITE, bool W32>
+__global__ void __launch_bounds__(PT_THREADS, 2) panel_kernel(PanelArgs p) {
+  if (p.flag && *p.flag == 0) return;
+  constexpr int LD = NT * 16;
+  constexpr int P = LD + 4;                      // LDS row pitch (doubles)
+  constexpr int KS = LD / 4;                     // MFMA k-steps over ld
+  constexpr int CT = (NT + 1) / 2;               // column tiles per wavefront
+  constexpr int NGB = (GRAMV ? NBV : 0) + (SELF ? 1 : 0);
+  constexpr bool SYM = SELF && !GRAMV;
+  constexpr int NPAIR = SYM ? NT * (NT + 1) / 2 : NGB * NT * NT;
+  constexpr int TPW = (NPAIR + 3) / 4;           // Gram tiles per wavefront
+  constexpr bool NEED_V = NBV > 0 && (UPDATE || GRAMV);
+  constexpr int NBC = UPDATE ? NBV : (APPLY ? 1 : 0);   // coefficient blocks in registers
+  __shared__ double sX[PT_ROWS * P];
+  __shared__ double sV[(NEED_V ? NBV : 1) * PT_ROWS * P];
+
+  const int tid = threadIdx.x;
+  const int w = tid >> 6;
+  const int l = tid & 63;
+  const int li = l & 15;
+  const int lk = l >> 4;
+  const int slab = w & 1;
+  const int half = w >> 1;
+
+  // right operands of the update / apply product, resident for the whole kernel
+  double creg[NBC > 0 ? NBC : 1][KS][CT];
+  if (NBC > 0) {
+#pragma unroll
+    for (int b = 0; b < (NBC > 0 ? NBC : 1); ++b)
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct) {
+          const int nt = half + 2 * ct;
+          double v = 0.0;
+          if (nt < NT) {
+            const double* src = UPDATE ? p.C : p.Rm;
+            v = src[(int64_t)(b * LD + 4 * ks + lk) * LD + 16 * nt + li];
+          }
+          creg[b][ks][ct] = v;
+        }
+  }
+  // Gram tile list of this wavefront
+  int tgi[TPW > 0 ? TPW : 1], txj[TPW > 0 ? TPW : 1];
+#pragma unroll
+  for (int t = 0; t < (TPW > 0 ? TPW : 1); ++t) {
+    const int tt = w + 4 * t;
+    int gi = -1, xj = -1;
+    if (tt < NPAIR) {
+      if (SYM) {
+        int cnt = 0;
+        for (int i = 0; i < NT; ++i)
+          for (int j = i; j < NT; ++j) {
+            if (cnt == tt) { gi = i; xj = j; }
+            ++cnt;
+          }
+      } else {
+        gi = tt / NT;
+        xj = tt - gi * NT;
+      }
+    }
+    tgi[t] = gi;
+    txj[t] = xj;
+  }
+  d4 gacc[TPW > 0 ? TPW : 1];
+#pragma unroll
+  for (int t = 0; t < (TPW > 0 ? TPW : 1); ++t) gacc[t] = d4{0.0, 0.0, 0.0, 0.0};
+
+  const int64_t ntiles = (p.n + PT_ROWS - 1) / PT_ROWS;
+  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int64_t r0 = tile * PT_ROWS;
+    // ---- stage X and V rows (coalesced, zero beyond n)
+#pragma unroll
+    for (int q0 = 0; q0 < PT_ROWS * LD; q0 += PT_THREADS) {
+      const int q = q0 + tid;
+      const int rr = q / LD, cc = q - rr * LD;
+      const int64_t r = r0 + rr;
+      const bool in = r < p.n;
+      sX[rr * P + cc] = in ? p.X[r * LD + cc] : 0.0;
+      if (NEED_V) {
+        sV[rr * P + cc] = in ? p.V0[r * LD + cc] : 0.0;
+        if (NBV > 1) sV[PT_ROWS * P + rr * P + cc] = in ? p.V1[r * LD + cc] : 0.0;
+      }
+    }
+    __syncthreads();
+    // ---- X_new for (slab, column half) of this wavefront
+    if (UPDATE || APPLY) {
+      d4 acc[CT];
+      const int rs = 16 * slab;
+#pragma unroll
+      for (int ct = 0; ct < CT; ++ct) {
+        const int nt = half + 2 * ct;
+        acc[ct] = d4{0.0, 0.0, 0.0, 0.0};
+        if (UPDATE && nt < NT) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) acc[ct][r] = sX[(rs + 4 * r + lk) * P + 16 * nt + li];
+        }
+      }
+      if (UPDATE) {
+#pragma unroll
+        for (int b = 0; b < (NBV > 0 ? NBV : 1); ++b) {
+          const double* sv = sV + b * PT_ROWS * P;
+#pragma unroll
+          for (int ks = 0; ks < KS; ++ks) {
+            const double a = -sv[(rs + li) * P + 4 * ks + lk];
+#pragma unroll
+            for (int ct = 0; ct < CT; ++ct)
+              if (half + 2 * ct < NT) acc[ct] = mfma64(a, creg[b][ks][ct], acc[ct]);
+          }
+        }
+      } else {
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+          const double a = sX[(rs + li) * P + 4 * ks + lk];
+#pragma unroll
+          for (int ct = 0; ct < CT; ++ct) {
+            const int nt = half + 2 * ct;
+            // Rm is upper triangular: rows 4ks.. of column tile nt vanish once 4ks >= 16(nt+1)
+            if (nt < NT && 4 * ks < 16 * (nt + 1)) acc[ct] = mfma64(a, creg[0][ks][ct], acc[ct]);
+          }
+        }
+      }
+      __syncthreads();   // every wavefront has read its sX rows
+#pragma unroll
+      for (int ct = 0; ct < CT; ++ct) {
+        const int nt = half + 2 * ct;
+        if (nt < NT) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) sX[(rs + 4 * r + lk) * P + 16 * nt + li] = acc[ct][r];
+        }
+      }
+      __syncthreads();
+      if (WRITE || W32) {
+#pragma unroll
+        for (int q0 = 0; q0 < PT_ROWS * LD; q0 += PT_THREADS) {
+          const int q = q0 + tid;
+          const int rr = q / LD, cc = q - rr * LD;
+          const int64_t r = r0 + rr;
+          if (r < p.n) {
+            const double v = sX[rr * P + cc];
+            if (WRITE) p.Xout[r * LD + cc] = v;
+            if (W32) p.X32[r * LD + cc] = (float)v;
+          }
+        }
+      }
+    }
+    // ---- Gram accumulation over the 32 rows of the tile
+    if (NPAIR > 0) {
+#pragma unroll
+      for (int t = 0; t < TPW; ++t) {
+        const int gi = tgi[t], xj = txj[t];
+        if (gi >= 0) {
+          const int gb = gi / NT, gc0 = 16 * (gi - gb * NT);
+          const double* gsrc = (GRAMV && gb < NBV) ? (sV + gb * PT_ROWS * P) : sX;
+          d4 a4 = gacc[t];
+#pragma unroll
+          for (int k0 = 0; k0 < PT_ROWS; k0 += 4) {
+            const double a = gsrc[(k0 + lk) * P + gc0 + li];
+            const double b = sX[(k0 + lk) * P + 16 * xj + li];
+            a4 = mfma64(a, b, a4);
+          }
+          gacc[t] = a4;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // ---- write the Gram partial of this workgroup
+  if (NPAIR > 0) {
+    double* P0 = p.part + (int64_t)blockIdx.x * NGB * LD * LD;
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) {
+      const int gi = tgi[t], xj = txj[t];
+      if (gi >= 0) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = 16 * gi + 4 * r + lk, col = 16 * xj + li;
+          P0[(int64_t)row * LD + col] = gacc[t][r];
+          if (SYM && gi != xj) P0[(int64_t)col * LD + row] = gacc[t][r];
+        }
+      }
+    }
+  }
+}
+
+bool panel_ok(int ld) { return ld == 16 || ld == 32 || ld == 48 || ld == 64; }
+
+int panel_grid(int64_t n) {
+  const int64_t nt = (n + PT_ROWS - 1) / PT_ROWS;
+  return (int)std::min<int64_t>(nt, PT_MAXGRID);
+}
+
+size_t panel_scratch_elems(int64_t n, int ld) { return (size_t)panel_grid(n) * 3 * ld * ld; }
+
+typedef int PanelMode;
+
+template <int NT>
+static void panel_dispatch(PanelMode mode, int nbv, const PanelArgs& a, int grid, hipStream_t st) {
+  dim3 g(grid), b(PT_THREADS);
+#define GK_PK(NBV, U, AP, GV, SF, WR, W3) \
+  hipLaunchKernelGGL((panel_kernel<NT, NBV, U, AP, GV, SF, WR, W3>), g, b, 0, st, a)
+  switch (mode) {
+    case PM_GRAMV:
+      if (nbv == 1) GK_PK(1, false, false, true, false, false, false);
+      else GK_PK(2, false, false, true, false, false, false);
+      break;
+    case PM_UPDATE_SELF:
+      if (nbv == 1) GK_PK(1, true, false, false, true, true, false);
+      else GK_PK(2, true, false, false, true, true, false);
+      break;
+    case PM_APPLY_SELF:
+      GK_PK(0, false, true, false, true, false, false);
+      break;
+    case PM_APPLY_WRITE:
+      if (a.X32) GK_PK(0, false, true, false, false, true, true);
+      else GK_PK(0, false, true, false, false, true, false);
+      break;
+  }
+#undef GK_PK
+  GK_HIP(hipGetLastError());
+}
+
+// Launch one panel pass and (when it produces a Gram) reduce it into C.
+void launch_panel(int mode, int64_t n, int ld, int nbv, const double* X, double* Xout, float* X32,
+                  const double* V0, const double* V1, const double* Cupd, const double* Rm, double* part,
+                  double* Cout, hipStream_t st, const int* flag) {
+  PanelArgs a{n, X, Xout, X32, V0, V1, Cupd, Rm, part, flag};
+  const int grid = panel_grid(n);
+  const PanelMode pm = (PanelMode)mode;
+  switch (ld) {
+    case 16: panel_dispatch<1>(pm, nbv, a, grid, st); break;
+    case 32: panel_dispatch<2>(pm, nbv, a, grid, st); break;
+    case 48: panel_dispatch<3>(pm, nbv, a, grid, st); break;
+    case 64: panel_dispatch<4>(pm, nbv, a, grid, st); break;
+    default: throw Error{GK_EUNSUPPORTED, "panel kernel needs ld in {16,32,48,64}"};
+  }
+  int ngb = 0;
+  if (pm == PM_GRAMV) ngb = nbv;
+  if (pm == PM_UPDATE_SELF || pm == PM_APPLY_SELF) ngb = 1;
+  if (ngb > 0) {
+    launch_reduce_parts((int64_t)ngb * ld * ld, grid, part, Cout, flag, st);
+  }
+}
+
+}  // namespace gk

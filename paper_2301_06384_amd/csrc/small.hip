@@ -634,3 +634,499 @@ void launch_small_solve(int s, const double* K, double gamma, const double* y, d
 }
 
 }  // namespace gk
+
+namespace gk {
+
+// ===================================================================
+// Small-matrix kernels for block widths up to 64: one workgroup of 256
+// threads, s x s operands staged in LDS (row pitch 65 doubles), products
+// register-blocked 4 x 4 per thread.
+// ===================================================================
+constexpr int WS = 64;
+constexpr int LP = WS + 1;
+constexpr int ST = 256;
+
+// acc = op(A) op(B) for the 4 x 4 block (rows 4ty.., cols 4tx..) of this
+// thread; op(A)[r][l] = TA ? A[l][r] : A[r][l], op(B)[l][c] = TB ? B[c][l] : B[l][c].
+template <bool TA, bool TB>
+__device__ __forceinline__ void lds_mm(const double (*A)[LP], const double (*B)[LP], int s, double (&acc)[4][4]) {
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+  for (int l = 0; l < s; ++l) {
+    double av[4], bv[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) av[i] = TA ? A[l][4 * ty + i] : A[4 * ty + i][l];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) bv[j] = TB ? B[4 * tx + j][l] : B[l][4 * tx + j];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[i][j] = fma(av[i], bv[j], acc[i][j]);
+  }
+}
+
+// Right-looking lower Cholesky of the symmetric A (s x s, lower part used)
+// together with Y = L^{-1} (on the kept indices), by one elimination:
+//   Y[j,:] = Z[j,:] / L_jj ;  Z[r,:] -= L_rj Y[j,:]  (r > j),   Z = I initially.
+// mode 0: plain (non-positive pivot -> *bad = 3, pivot 1 used);
+// mode 1 / 2: the CholQR deflation rules (see cholqr_factor_kernel);
+// deflated columns give zero columns of L and zero rows of Y.
+__device__ void blk_chol_inv(double (*A)[LP], double (*Y)[LP], int s, int mode, const double* g0, const double* dprev,
+                             double thr, double* dg, int* bad) {
+  const int tid = threadIdx.x;
+  const int tx = tid & 15, ty = tid >> 4;
+  const double eta = 1e-7;
+  for (int r = ty; r < s; r += 16)
+    for (int c = tx; c < s; c += 16) Y[r][c] = (r == c) ? 1.0 : 0.0;
+  __syncthreads();
+  for (int j = 0; j < s; ++j) {
+    const double piv = A[j][j];
+    double ljj;
+    if (mode == 0) {
+      ljj = sqrt((piv > 0.0) ? piv : 1.0);
+      if (!(piv > 0.0) && tid == 0 && bad) *bad = 3;
+    } else if (mode == 1) {
+      ljj = (g0[j] > thr * thr) ? sqrt(fmax(piv, eta * eta * g0[j])) : 0.0;
+    } else {
+      ljj = 0.0;
+      if (piv > 0.0) {
+        ljj = sqrt(piv);
+        if (ljj * dprev[j] < thr) ljj = 0.0;
+      }
+    }
+    const double inv = (ljj != 0.0) ? 1.0 / ljj : 0.0;
+    __syncthreads();   // everyone has read A[j][j]
+    // phase 1: column j of L, row j of Y
+    for (int q = tid; q < s; q += ST) {
+      if (q > j) A[q][j] *= inv;
+      if (q <= j) Y[j][q] *= inv;
+    }
+    if (tid == 0) {
+      A[j][j] = ljj;
+      if (dg) dg[j] = ljj;
+    }
+    __syncthreads();
+    // phase 2: trailing update of A (lower part) and of the rows of Y below j
+    // (16 x 16 thread grid, no index division)
+    for (int r = j + 1 + ty; r < s; r += 16) {
+      const double lr = A[r][j];
+      for (int c = tx; c <= r; c += 16) {
+        if (c > j) A[r][c] -= lr * A[c][j];
+        else Y[r][c] -= lr * Y[j][c];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// CholQR factor of a Gram matrix (ld <= 64), 256 threads.
+//   pass 1: R1 = chol(G) with clamped pivots, R1inv, diag_out = diag(R1)
+//   pass 2: R2 with the combined-diagonal deflation rule, R2inv, and the
+//           products Rc = R1inv R2inv and B = R2 R1 (s x s, H_{k+1,k}).
+// flag (may be null): when *flag == 0 the kernel does nothing.
+__global__ void __launch_bounds__(ST)
+cholqr_blk_kernel(const double* __restrict__ G, int ld, int s, int pass, const double* __restrict__ diag_prev,
+                  double thr, double* __restrict__ R, double* __restrict__ Rinv, double* __restrict__ diag_out,
+                  int* __restrict__ n_defl, const double* __restrict__ R1, const double* __restrict__ R1inv,
+                  double* __restrict__ Rc, double* __restrict__ Bout, const int* __restrict__ flag) {
+  if (flag && *flag == 0) return;
+  __shared__ double A[WS][LP];
+  __shared__ double Y[WS][LP];
+  __shared__ double S1[WS][LP];
+  __shared__ double S2[WS][LP];
+  __shared__ double g0[WS], dp[WS], dg[WS];
+  const int tid = threadIdx.x;
+  for (int i = tid >> 4; i < s; i += 16)
+    for (int c = tid & 15; c < s; c += 16) {
+      A[i][c] = G[i * ld + c];
+      if (pass == 2) {
+        S1[i][c] = R1[i * ld + c];
+        S2[i][c] = R1inv[i * ld + c];
+      }
+    }
+  for (int q = tid; q < s; q += ST) {
+    g0[q] = G[q * ld + q];
+    dp[q] = (pass == 2) ? diag_prev[q] : 0.0;
+  }
+  __syncthreads();
+  blk_chol_inv(A, Y, s, pass, g0, dp, thr, dg, nullptr);
+  // R = L^T, Rinv = Y^T (upper), coalesced stores with zero padding
+  for (int q = tid; q < ld * ld; q += ST) {
+    const int i = q / ld, c = q % ld;
+    const bool in = i < s && c < s && c >= i;
+    R[q] = in ? A[c][i] : 0.0;
+    Rinv[q] = in ? Y[c][i] : 0.0;
+  }
+  for (int q = tid; q < ld; q += ST) diag_out[q] = (q < s) ? dg[q] : 0.0;
+  if (pass == 2) {
+    if (tid == 0 && n_defl) {
+      int cnt = 0;
+      for (int j = 0; j < s; ++j) cnt += (dg[j] == 0.0);
+      *n_defl += cnt;
+    }
+    // zero the strict upper part of L so that products can use it directly
+    for (int q = tid; q < s * s; q += ST) {
+      const int i = q / s, c = q % s;
+      if (c > i) A[i][c] = 0.0;
+    }
+    __syncthreads();
+    const int tx = tid & 15, ty = tid >> 4;
+    double acc[4][4];
+    // Rc = R1inv * R2inv = S2 * Y^T
+    lds_mm<false, true>(S2, Y, s, acc);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int r = 4 * ty + i, c = 4 * tx + j;
+        if (r < ld && c < ld) Rc[r * ld + c] = (r < s && c < s) ? acc[i][j] : 0.0;
+      }
+    // B = R2 * R1 = L^T * S1
+    lds_mm<true, false>(A, S1, s, acc);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int r = 4 * ty + i, c = 4 * tx + j;
+        if (r < s && c < s) Bout[r * s + c] = acc[i][j];
+      }
+  }
+}
+
+// Banded spline factor phase (s <= 64): for each block j
+//   A = eps I + H_jj - Lsub_{j-1} Lsub_{j-1}^T ; A = L_jj L_jj^T ;
+//   Linv_j = L_jj^{-1} ; Lsub_j = H_{j+1,j} Linv_j^T
+__global__ void __launch_bounds__(ST)
+banded_factor_blk_kernel(int m, int s, const double* __restrict__ Hd, const double* __restrict__ Bd, double eps,
+                         double* __restrict__ Linv_all, double* __restrict__ Lsub_all, int* __restrict__ bad) {
+  __shared__ double A[WS][LP];
+  __shared__ double Y[WS][LP];
+  __shared__ double SB[WS][LP];
+  __shared__ double Ls[WS][LP];
+  const int tid = threadIdx.x;
+  const int tx = tid & 15, ty = tid >> 4;
+  const int ss = s * s;
+  for (int j = 0; j < m; ++j) {
+    const double* H = Hd + (int64_t)j * ss;
+    const double* Bj = Bd + (int64_t)j * ss;
+    for (int i = ty; i < s; i += 16)
+      for (int c = tx; c < s; c += 16) {
+        A[i][c] = H[i * s + c] + ((i == c) ? eps : 0.0);
+        if (j + 1 < m) SB[i][c] = Bj[i * s + c];
+      }
+    __syncthreads();
+    if (j > 0) {
+      double acc[4][4];
+      lds_mm<false, true>(Ls, Ls, s, acc);
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) {
+          const int r = 4 * ty + i, c = 4 * tx + jj;
+          if (r < s && c < s) A[r][c] -= acc[i][jj];
+        }
+      __syncthreads();
+    }
+    blk_chol_inv(A, Y, s, 0, nullptr, nullptr, 0.0, nullptr, bad);
+    double* LiG = Linv_all + (int64_t)j * ss;
+    for (int i = ty; i < s; i += 16)
+      for (int c = tx; c < s; c += 16) LiG[i * s + c] = (c <= i) ? Y[i][c] : 0.0;
+    if (j + 1 < m) {
+      // Y has zeros above its diagonal (set at initialisation), so the product is exact
+      double acc[4][4];
+      lds_mm<false, true>(SB, Y, s, acc);
+      __syncthreads();
+      double* LsG = Lsub_all + (int64_t)j * ss;
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) {
+          const int r = 4 * ty + i, c = 4 * tx + jj;
+          if (r < s && c < s) {
+            Ls[r][c] = acc[i][jj];
+            LsG[r * s + c] = acc[i][jj];
+          }
+        }
+    }
+    __syncthreads();
+  }
+}
+
+// Solve phase: kpow times  Y <- (L L^T)^{-1} Y  with Y = U (m s x s), starting
+// from U = F_1.  Thread (c, g): column c, rows i = g, g + G, ...  Each block
+// step stages its s x s operands in LDS with coalesced loads.
+// ---------------------------------------------------------------------
+// Orthogonality estimate for partial reorthogonalisation (block form of the
+// omega recurrence).  With W_{k,j} = V_k^T V_j and the block Lanczos relation
+// L V_j = V_{j+1} B_j + V_j H_j + V_{j-1} B_{j-1}^T + F_j (B_j = H_{j+1,j}),
+// symmetry of L gives
+//   B_k^T W_{k+1,j} = W_{k,j+1} B_j + W_{k,j} H_j - H_k W_{k,j}
+//                     + W_{k,j-1} B_{j-1}^T - B_{k-1} W_{k-1,j} + (rounding),
+// so W_{k+1,j} = B_k^{-T} (...) with B_k^{-1} = Rc from the QR.  The rounding
+// term is modelled pessimistically by +-nu added in the direction of each
+// entry.  One workgroup per j <= k-2; W_{k+1,k-1} and W_{k+1,k} are kept at a
+// floor because the new block is orthogonalised against V_{k-1}, V_k.
+__global__ void __launch_bounds__(ST)
+omega_kernel(int k, int s, int ld, const double* __restrict__ Wk, const double* __restrict__ Wkm1,
+             double* __restrict__ Wk1, const double* __restrict__ Hd, const double* __restrict__ Bd,
+             const double* __restrict__ Rc, double nu, double* __restrict__ est_part) {
+  __shared__ double S1[WS][LP];
+  __shared__ double S2[WS][LP];
+  __shared__ double S3[WS][LP];
+  __shared__ double red[ST];
+  const int j = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int tx = tid & 15, ty = tid >> 4;
+  const int ss = s * s;
+  double tot[4][4], acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) tot[a][b] = 0.0;
+  auto load = [&](double (*D)[LP], const double* src) {
+    for (int i = ty; i < s; i += 16)
+      for (int c = tx; c < s; c += 16) D[i][c] = src[i * s + c];
+  };
+  auto addto = [&](double sign) {
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) tot[a][b] += sign * acc[a][b];
+  };
+  // W_{k,j+1} B_j
+  load(S1, Wk + (int64_t)(j + 1) * ss);
+  load(S2, Bd + (int64_t)j * ss);
+  __syncthreads();
+  lds_mm<false, false>(S1, S2, s, acc);
+  addto(1.0);
+  __syncthreads();
+  // W_{k,j} H_j - H_k W_{k,j}
+  load(S1, Wk + (int64_t)j * ss);
+  load(S2, Hd + (int64_t)j * ss);
+  load(S3, Hd + (int64_t)k * ss);
+  __syncthreads();
+  lds_mm<false, false>(S1, S2, s, acc);
+  addto(1.0);
+  lds_mm<false, false>(S3, S1, s, acc);
+  addto(-1.0);
+  __syncthreads();
+  // + W_{k,j-1} B_{j-1}^T - B_{k-1} W_{k-1,j}
+  if (j >= 1) {
+    load(S1, Wk + (int64_t)(j - 1) * ss);
+    load(S2, Bd + (int64_t)(j - 1) * ss);
+    __syncthreads();
+    lds_mm<false, true>(S1, S2, s, acc);
+    addto(1.0);
+    __syncthreads();
+  }
+  load(S1, Bd + (int64_t)(k - 1) * ss);
+  load(S2, Wkm1 + (int64_t)j * ss);
+  __syncthreads();
+  lds_mm<false, false>(S1, S2, s, acc);
+  addto(-1.0);
+  __syncthreads();
+  // rounding model, then W_{k+1,j} = Rc^T * RHS
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int r = 4 * ty + a, c = 4 * tx + b;
+      if (r < s && c < s) S3[r][c] = tot[a][b] + copysign(nu, tot[a][b]);
+    }
+  for (int i = ty; i < s; i += 16)
+    for (int c = tx; c < s; c += 16) S1[i][c] = Rc[i * ld + c];
+  __syncthreads();
+  lds_mm<true, false>(S1, S3, s, acc);
+  double mx = 0.0;
+  double* out = Wk1 + (int64_t)j * ss;
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int r = 4 * ty + a, c = 4 * tx + b;
+      if (r < s && c < s) {
+        out[r * s + c] = acc[a][b];
+        mx = fmax(mx, fabs(acc[a][b]));
+      }
+    }
+  red[tid] = mx;
+  __syncthreads();
+  for (int w = ST / 2; w > 0; w >>= 1) {
+    if (tid < w) red[tid] = fmax(red[tid], red[tid + w]);
+    __syncthreads();
+  }
+  if (tid == 0) est_part[j] = red[0];
+}
+
+// Decision after the estimate of step k: reorthogonalise when the estimate
+// exceeds tau, and once more on the next step (the three-term coupling
+// carries the lost orthogonality one block further).  After a
+// reorthogonalisation the estimates restart from floor_re (the float32
+// archive limits the attainable orthogonality); the two local blocks are
+// always at floor_loc.
+__global__ void __launch_bounds__(ST)
+omega_decide_kernel(int k, int s, int nj, const double* __restrict__ est_part, double tau, double floor_re,
+                    double floor_loc, double* __restrict__ Wk1, int* __restrict__ fr, int* __restrict__ forced,
+                    double* __restrict__ est_out, int* __restrict__ nre) {
+  __shared__ int go_sh;
+  const int tid = threadIdx.x;
+  const int ss = s * s;
+  if (tid == 0) {
+    double e = 0.0;
+    for (int j = 0; j < nj; ++j) e = fmax(e, est_part[j]);
+    const int f = forced[k];
+    const int go = (e > tau || f) ? 1 : 0;
+    fr[k] = go;
+    forced[k + 1] = (go && !f) ? 1 : 0;
+    if (go) {
+      *nre += 1;
+      e = floor_re;
+    }
+    *est_out = fmax(*est_out, e);
+    go_sh = go;
+  }
+  __syncthreads();
+  if (go_sh)
+    for (int q = tid; q < nj * ss; q += ST) Wk1[q] = floor_re;
+  for (int q = tid; q < 2 * ss; q += ST) {
+    const int jj = k - 1 + q / ss;
+    if (jj >= 0) Wk1[(int64_t)jj * ss + q % ss] = floor_loc;
+  }
+}
+
+__global__ void __launch_bounds__(1024)
+banded_solve_kernel(int m, int s, int kpow, const double* __restrict__ Linv_all, const double* __restrict__ Lsub_all,
+                    double* __restrict__ U) {
+  __shared__ double T[WS][LP];
+  __shared__ double SL[WS][LP];   // Lsub
+  __shared__ double SY[WS][LP];   // neighbouring block of Y
+  __shared__ double SI[WS][LP];   // Linv
+  const int tid = threadIdx.x;
+  const int nt = blockDim.x;
+  const int c = tid % s;
+  const int g = tid / s;
+  const int G = nt / s;
+  const bool act = g < G;
+  const int ss = s * s;
+  const int64_t ms = (int64_t)m * s;
+  for (int64_t q = tid; q < ms * s; q += nt) U[q] = ((q / s) == (q % s)) ? 1.0 : 0.0;
+  __syncthreads();
+  for (int rep = 0; rep < kpow; ++rep) {
+    for (int dir = 0; dir < 2; ++dir) {
+      for (int jj = 0; jj < m; ++jj) {
+        const int j = dir == 0 ? jj : m - 1 - jj;
+        double* Y = U + (int64_t)j * ss;
+        const bool has_nb = dir == 0 ? (j > 0) : (j + 1 < m);
+        const double* Ls = Lsub_all + (int64_t)(dir == 0 ? j - 1 : j) * ss;
+        const double* Yn = U + (int64_t)(dir == 0 ? j - 1 : j + 1) * ss;
+        const double* Li = Linv_all + (int64_t)j * ss;
+        for (int i = g; i < s; i += G) {
+          if (!act) break;
+          SI[i][c] = Li[i * s + c];
+          T[i][c] = Y[i * s + c];
+          if (has_nb) {
+            SL[i][c] = Ls[i * s + c];
+            SY[i][c] = Yn[i * s + c];
+          }
+        }
+        __syncthreads();
+        if (act && has_nb) {
+          for (int i = g; i < s; i += G) {
+            double a0 = 0.0, a1 = 0.0;
+            if (dir == 0) {          // T -= Lsub_{j-1} Z_{j-1}
+              for (int l = 0; l + 1 < s; l += 2) {
+                a0 += SL[i][l] * SY[l][c];
+                a1 += SL[i][l + 1] * SY[l + 1][c];
+              }
+              if (s & 1) a0 += SL[i][s - 1] * SY[s - 1][c];
+            } else {                 // T -= Lsub_j^T X_{j+1}
+              for (int l = 0; l + 1 < s; l += 2) {
+                a0 += SL[l][i] * SY[l][c];
+                a1 += SL[l + 1][i] * SY[l + 1][c];
+              }
+              if (s & 1) a0 += SL[s - 1][i] * SY[s - 1][c];
+            }
+            T[i][c] -= a0 + a1;
+          }
+        }
+        __syncthreads();
+        if (act) {
+          for (int i = g; i < s; i += G) {
+            double a0 = 0.0, a1 = 0.0;
+            if (dir == 0) {          // Z_j = Linv_j T
+              int l = 0;
+              for (; l + 1 <= i; l += 2) {
+                a0 += SI[i][l] * T[l][c];
+                a1 += SI[i][l + 1] * T[l + 1][c];
+              }
+              if (l <= i) a0 += SI[i][l] * T[l][c];
+            } else {                 // X_j = Linv_j^T T
+              int l = i;
+              for (; l + 1 < s; l += 2) {
+                a0 += SI[l][i] * T[l][c];
+                a1 += SI[l + 1][i] * T[l + 1][c];
+              }
+              if (l < s) a0 += SI[l][i] * T[l][c];
+            }
+            Y[i * s + c] = a0 + a1;
+          }
+        }
+        __syncthreads();
+      }
+    }
+  }
+}
+
+}  // namespace gk
+
+
+namespace gk {
+
+bool small_wave_ok(int ld) { return ld <= WS; }
+
+void launch_cholqr_reg(const double* G, int ld, int s, int pass, const double* diag_prev, double thr, double* R,
+                       double* Rinv, double* diag_out, int* n_defl, const double* R1, const double* R1inv, double* Rc,
+                       double* Bout, hipStream_t st) {
+  hipLaunchKernelGGL(cholqr_blk_kernel, dim3(1), dim3(ST), 0, st, G, ld, s, pass, diag_prev, thr, R, Rinv, diag_out,
+                     n_defl, R1, R1inv, Rc, Bout, (const int*)nullptr);
+  GK_HIP(hipGetLastError());
+}
+
+void launch_cholqr_flag(const double* G, int ld, int s, int pass, const double* diag_prev, double thr, double* R,
+                        double* Rinv, double* diag_out, int* n_defl, const double* R1, const double* R1inv, double* Rc,
+                        double* Bout, const int* flag, hipStream_t st) {
+  hipLaunchKernelGGL(cholqr_blk_kernel, dim3(1), dim3(ST), 0, st, G, ld, s, pass, diag_prev, thr, R, Rinv, diag_out,
+                     n_defl, R1, R1inv, Rc, Bout, flag);
+  GK_HIP(hipGetLastError());
+}
+
+void launch_omega(int k, int s, int ld, const double* Wk, const double* Wkm1, double* Wk1, const double* Hd,
+                  const double* Bd, const double* Rc, double nu, double tau, double floor_re, double floor_loc,
+                  double* est_part, int* fr, int* forced, double* est_out, int* nre, hipStream_t st) {
+  const int nj = k - 1;   // recurrence for j <= k-2
+  if (nj > 0) {
+    hipLaunchKernelGGL(omega_kernel, dim3(nj), dim3(ST), 0, st, k, s, ld, Wk, Wkm1, Wk1, Hd, Bd, Rc, nu, est_part);
+    GK_HIP(hipGetLastError());
+  }
+  hipLaunchKernelGGL(omega_decide_kernel, dim3(1), dim3(ST), 0, st, k, s, nj > 0 ? nj : 0, est_part, tau, floor_re,
+                     floor_loc, Wk1, fr, forced, est_out, nre);
+  GK_HIP(hipGetLastError());
+}
+
+void launch_banded_spline_reg(int m, int s, const double* Hd, const double* Bd, double eps, int k, double* work,
+                              double* U, int* bad, hipStream_t st) {
+  const size_t ss = (size_t)s * s;
+  double* Linv = work;
+  double* Lsub = work + m * ss;
+  hipLaunchKernelGGL(banded_factor_blk_kernel, dim3(1), dim3(ST), 0, st, m, s, Hd, Bd, eps, Linv, Lsub, bad);
+  GK_HIP(hipGetLastError());
+  int nt = (1024 / s) * s;
+  hipLaunchKernelGGL(banded_solve_kernel, dim3(1), dim3(nt), 0, st, m, s, k, Linv, Lsub, U);
+  GK_HIP(hipGetLastError());
+}
+
+}  // namespace gk

@@ -168,13 +168,16 @@ def test_interpolation_gamma_zero_gpu():
     assert np.max(np.abs(pred[W] - y)) < 1e-9
 
 
-@pytest.mark.parametrize("s", [1, 3, 8, 9, 16, 33])
+@pytest.mark.parametrize("s", [1, 3, 8, 9, 16, 33, 50, 64])
 def test_block_widths(s):
+    # every block-width class: ld = 8 (generic kernels), 16..64 (MFMA panels)
     L, g = G("grid3d")
     W = I.samples(L.n, s, 40 + s)
     phi = dict(kind="diffusion", t=0.4)
-    P, K, st = gk.krylov_kernel_columns(g, W, phi, 5, "cbl", "fp64")
-    assert rel(P, krylov.cbl(L.to_scipy(), W, phi, 5)["P"]) < 1e-10
+    ref = krylov.cbl(L.to_scipy(), W, phi, 5)["P"]
+    for prec in ("fp64", "mixed"):
+        P, K, st = gk.krylov_kernel_columns(g, W, phi, 5, "cbl", prec)
+        assert rel(P, ref) < TOL[prec], (prec, rel(P, ref))
 
 
 def test_single_sample_variants_coincide_gpu():
