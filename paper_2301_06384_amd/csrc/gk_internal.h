@@ -172,6 +172,9 @@ void launch_cholqr_flag(const double* G, int ld, int s, int pass, const double* 
 void launch_omega(int k, int s, int ld, const double* Wk, const double* Wkm1, double* Wk1, const double* Hd,
                   const double* Bd, const double* Rc, double nu, double tau, double floor_re, double floor_loc,
                   double* est_part, int* fr, int* forced, double* est_out, int* nre, hipStream_t st);
+int cheb_diffusion_degree(double t, double Lam);
+void launch_cheb_diffusion(int m, int s, const double* Hd, const double* Bd, double t, double Lam, int deg,
+                           const double* coef, double* Y0, double* Y1, double* Y2, double* U, hipStream_t st);
 // deterministic sum of nparts equally long partial vectors: out[i] = sum_c part[c*len + i]
 void launch_reduce_parts(int64_t len, int nparts, const double* part, double* out, const int* flag, hipStream_t st);
 void launch_small_solve(int s, const double* K, double gamma, const double* y, double* c, double* work,

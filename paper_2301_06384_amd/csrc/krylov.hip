@@ -279,6 +279,23 @@ static void phi_stage_block(Job& J, const double* Hd, const double* Bd, double* 
     J.phi_method = 1;
     return;
   }
+  if (J.phi.kind == GK_PHI_DIFFUSION && !(J.flags & GK_PHI_EIG)) {
+    // Chebyshev series of exp(-t lam) on [0, Lambda] applied to F_1
+    const double Lam = J.g->lambda_max;
+    const int deg = cheb_diffusion_degree(J.phi.t, Lam);
+    double* coef = J.ar.get<double>(deg + 1);
+    hipLaunchKernelGGL(cheb_coef_kernel, dim3(nblk(deg + 1)), dim3(256), 0, J.st, deg, Lam, (int)GK_PHI_DIFFUSION,
+                       J.phi.t, 0.0, 0.0, (const double*)nullptr, 0, 0, coef, J.dflags + 0);
+    GK_HIP(hipGetLastError());
+    const size_t tot = (size_t)m * s * s;
+    double* Y0 = J.ar.get<double>(tot);
+    double* Y1 = J.ar.get<double>(tot);
+    double* Y2 = J.ar.get<double>(tot);
+    launch_cheb_diffusion(m, s, Hd, Bd, J.phi.t, Lam, deg, coef, Y0, Y1, Y2, U, J.st);
+    launch_store_H(U, s, s, K, J.st);          // K = sym(U[0:s, :])
+    J.phi_method = 2;
+    return;
+  }
   // spectral decomposition H_m = S Theta S^T (Sec. 6, Table 1 row phi(H_m))
   double* T = J.ar.get<double>((size_t)ms * ms);
   double* S = J.ar.get<double>((size_t)ms * ms);
@@ -436,13 +453,13 @@ static void run_cbl(Job& J) {
         const int* fk = fr + k;
         launch_omega(k, s, ld, Wr[k % 3], Wr[(k + 2) % 3], Wr[(k + 1) % 3], Hd, Bd, R12i, om_nu, om_tau, om_floor_re,
                      om_floor_loc, est_part, fr, forced, J.dscal + 1, J.dflags + 3, st);
-        // flagged: reorthogonalise X against the archive (two passes), redo CholQR2
+        // flagged: reorthogonalise X against the archive and redo CholQR2.  One
+        // pass suffices: from a loss of at most tau it reaches the floor set by
+        // the float32 archive.
         J.tm.begin(PH_REORTH);
         BlockList all{Va, blk, k + 1, true};
-        for (int pass = 0; pass < 2; ++pass) {
-          launch_gram(n, ld, all, X, C, part_all, fk, st);
-          launch_tsgemm(n, ld, all, C, X, X, nullptr, -1.0, 1.0, fk, st);
-        }
+        launch_gram(n, ld, all, X, C, part_all, fk, st);
+        launch_tsgemm(n, ld, all, C, X, X, nullptr, -1.0, 1.0, fk, st);
         launch_gram(n, ld, xl, X, G, part_all, fk, st);
         launch_cholqr_flag(G, ld, s, 1, nullptr, J.thr(), R1, R1i, d1, nullptr, nullptr, nullptr, nullptr, nullptr, fk,
                            st);
@@ -666,9 +683,11 @@ static void validate_common(const CallArgs& a) {
     GK_REQUIRE(std::isfinite(a.gamma) && a.gamma >= 0.0, GK_EINVAL, "gamma must be finite and >= 0");
   }
   const int64_t ms = (int64_t)a.m * a.s;
-  if (a.variant == GK_CBL && (!(a.phi->kind == GK_PHI_SPLINE && a.phi->k == std::floor(a.phi->k) &&
-                                a.phi->k <= 16) || (a.flags & GK_PHI_EIG)))
-    GK_REQUIRE(ms <= 16384, GK_EUNSUPPORTED, "spectral decomposition limited to m*s <= 16384");
+  const bool banded_ok = a.phi->kind == GK_PHI_SPLINE && a.phi->k == std::floor(a.phi->k) && a.phi->k <= 16;
+  const bool cheb_ok = a.phi->kind == GK_PHI_DIFFUSION;
+  if (a.variant == GK_CBL && (!(banded_ok || cheb_ok) || (a.flags & GK_PHI_EIG)))
+    GK_REQUIRE(ms <= 4096, GK_EUNSUPPORTED,
+               "the single-workgroup spectral decomposition is limited to m*s <= 4096");
 }
 
 static void check_samples_host(const int64_t* h, int s, int64_t n) {

@@ -1130,3 +1130,80 @@ void launch_banded_spline_reg(int m, int s, const double* Hd, const double* Bd, 
 }
 
 }  // namespace gk
+
+namespace gk {
+
+// ---------------------------------------------------------------------
+// phi(H_m) F_1 for the diffusion kernel without a spectral decomposition:
+// exp(-t lam) on [0, Lambda] (spec(H_m) lies there, Theorem 3.1) is expanded
+// in Chebyshev polynomials of x = 1 - 2 lam / Lambda and the series is applied
+// to F_1 with the three-term recurrence, each term one block tridiagonal
+// product.  The degree is chosen past the point where the coefficients
+// (2 e^{-z} I_k(z), z = t Lambda / 2) fall below 1e-17.
+// out = alpha * (H Y) + beta * Y + gamma * Yp ;  acc += coef[kk] * out
+// (H Y)_j = H_{j,j-1} Y_{j-1} + H_jj Y_j + H_{j,j+1} Y_{j+1}, H_{j,j-1} = B_{j-1},
+// H_{j,j+1} = B_j^T.  One thread per entry (j, r, c) of the m s x s output.
+__global__ void btd_cheb_step_kernel(int m, int s, const double* __restrict__ Hd, const double* __restrict__ Bd,
+                                     const double* __restrict__ Y, const double* __restrict__ Yp,
+                                     double* __restrict__ out, double alpha, double beta, double gamma,
+                                     double* __restrict__ acc, const double* __restrict__ coef, int kk) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t ss = (int64_t)s * s;
+  if (t >= (int64_t)m * ss) return;
+  const int j = (int)(t / ss);
+  const int r = (int)((t / s) % s), c = (int)(t % s);
+  double hy = 0.0;
+  const double* Hj = Hd + j * ss + (int64_t)r * s;
+  const double* Yj = Y + j * ss + c;
+  for (int l = 0; l < s; ++l) hy = fma(Hj[l], Yj[(int64_t)l * s], hy);
+  if (j > 0) {
+    const double* B = Bd + (j - 1) * ss + (int64_t)r * s;     // B_{j-1}[r][l]
+    const double* Ym = Y + (j - 1) * ss + c;
+    for (int l = 0; l < s; ++l) hy = fma(B[l], Ym[(int64_t)l * s], hy);
+  }
+  if (j + 1 < m) {
+    const double* B = Bd + j * ss + r;                        // B_j^T[r][l] = B_j[l][r]
+    const double* Yn = Y + (j + 1) * ss + c;
+    for (int l = 0; l < s; ++l) hy = fma(B[(int64_t)l * s], Yn[(int64_t)l * s], hy);
+  }
+  double v = alpha * hy + beta * Y[t];
+  if (Yp) v += gamma * Yp[t];
+  out[t] = v;
+  acc[t] += coef[kk] * v;
+}
+
+__global__ void f1_init_kernel(int64_t rows, int s, double* __restrict__ Y, double* __restrict__ acc,
+                               const double* __restrict__ coef) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= rows * s) return;
+  const double v = ((t / s) == (t % s)) ? 1.0 : 0.0;
+  Y[t] = v;
+  acc[t] = coef[0] * v;
+}
+
+int cheb_diffusion_degree(double t, double Lam) {
+  const double z = 0.5 * t * Lam;
+  const double k = fmax(sqrt(80.0 * z), z) + 24.0;
+  return (int)fmin(4096.0, ceil(k));
+}
+
+void launch_cheb_diffusion(int m, int s, const double* Hd, const double* Bd, double t, double Lam, int deg,
+                           const double* coef, double* Y0, double* Y1, double* Y2, double* U, hipStream_t st) {
+  const int64_t tot = (int64_t)m * s * s;
+  const unsigned nb = (unsigned)((tot + 255) / 256);
+  hipLaunchKernelGGL(f1_init_kernel, dim3(nb), dim3(256), 0, st, (int64_t)m * s, s, Y0, U, coef);
+  GK_HIP(hipGetLastError());
+  if (deg < 1) return;
+  double* Y[3] = {Y0, Y1, Y2};
+  // T_1: out = Y - (2/Lam) H Y
+  hipLaunchKernelGGL(btd_cheb_step_kernel, dim3(nb), dim3(256), 0, st, m, s, Hd, Bd, Y[0], (const double*)nullptr,
+                     Y[1], -2.0 / Lam, 1.0, 0.0, U, coef, 1);
+  GK_HIP(hipGetLastError());
+  for (int k = 1; k < deg; ++k) {
+    hipLaunchKernelGGL(btd_cheb_step_kernel, dim3(nb), dim3(256), 0, st, m, s, Hd, Bd, Y[k % 3], Y[(k - 1) % 3],
+                       Y[(k + 1) % 3], -4.0 / Lam, 2.0, -1.0, U, coef, k + 1);
+    GK_HIP(hipGetLastError());
+  }
+}
+
+}  // namespace gk

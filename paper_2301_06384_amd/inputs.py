@@ -215,6 +215,37 @@ def labels(s: int, seed: int = 0) -> np.ndarray:
 # configurations; the kernel parameters are those of the diffusion and
 # variational spline kernels of Sec. 2.4).
 
+def serving_pool(n_graphs: int = 8, n_min: int = 10_000, n_max: int = 500_000):
+    """Resident graph pool of the serving workload: symmetrised 8-NN random
+    geometric graphs with log-spaced orders N_i = n_min (n_max/n_min)^(i/7),
+    seeds 100 + i."""
+    out = []
+    for i in range(n_graphs):
+        n = int(round(n_min * (n_max / n_min) ** (i / max(n_graphs - 1, 1))))
+        out.append(rgg_knn(n, 8, seed=100 + i))
+    return out
+
+
+def serving_requests(n_req: int, graph_sizes, seed: int = 0, s_range=(4, 128), m: int = 30,
+                     gamma: float = 1e-3):
+    """Request stream of the serving workload: graph uniform over the pool,
+    s uniform in s_range, diffusion t ~ U[0.1, 2] or spline eps ~ U[0.001, 0.1]
+    with k = 2 (each with probability 1/2), labels y ~ N(0, 1)."""
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for r in range(n_req):
+        gi = int(rng.integers(len(graph_sizes)))
+        s = int(rng.integers(s_range[0], s_range[1] + 1))
+        if rng.random() < 0.5:
+            phi = dict(kind="diffusion", t=float(rng.uniform(0.1, 2.0)))
+        else:
+            phi = dict(kind="spline", eps=float(rng.uniform(0.001, 0.1)), k=2.0)
+        smp = rng.choice(graph_sizes[gi], s, replace=False).astype(np.int64)
+        y = rng.standard_normal(s)
+        reqs.append(dict(graph=gi, samples=smp, y=y, phi=phi, m=m, gamma=gamma))
+    return reqs
+
+
 def workload(name: str, seed: int = 0):
     """Return (L, samples, phi dict, m) for a named workload."""
     if name == "grid32_diffusion":

@@ -145,6 +145,23 @@ def test_banded_and_spectral_phi_agree():
     assert rel(P1, P2) < 1e-11 and rel(K1, K2) < 1e-11
 
 
+@pytest.mark.parametrize("t", [0.1, 1.0, 30.0])
+def test_chebyshev_and_spectral_phi_agree(t):
+    # exp(-t H_m) F_1 by the Chebyshev series on [0, Lambda] vs by the
+    # spectral decomposition of H_m (Sec. 6): same result to rounding.
+    L, g = G("ba1500")
+    W = I.samples(L.n, 12, 4)
+    phi = dict(kind="diffusion", t=t)
+    P1, K1, s1 = gk.krylov_kernel_columns(g, W, phi, 8, "cbl", "fp64")
+    P2, K2, s2 = gk.krylov_kernel_columns(g, W, phi, 8, "cbl", "fp64", flags=gk.PHI_EIG)
+    assert s1.phi_method == 2 and s2.phi_method == 0
+    # The series error is uniform on [0, Lambda] relative to max|exp| = 1, so
+    # it is measured against ||E_W||_F = sqrt(s), not against the (for large
+    # t tiny) columns themselves.
+    sc = np.sqrt(len(W))
+    assert np.linalg.norm(P1 - P2) < 1e-11 * sc and np.linalg.norm(K1 - K2) < 1e-11 * sc
+
+
 @pytest.mark.parametrize("variant", ["cbl", "gbl", "sbl"])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_fit_predict_matches_oracle(variant, precision):
