@@ -1,0 +1,287 @@
+// Reorthogonalisation of a block against the float32 basis archive on FP32
+// matrix cores (mixed precision, block widths ld in {16, 32, 48, 64}):
+//
+//   C = Q^T X      (Q = [Q_1 .. Q_nb] archived blocks, X the new block)
+//   X -= Q C
+//
+// The orthonormality of the Krylov basis assumed in Sec. 3 (and used by
+// Theorem 3.1) is restored by this projection.  Coefficients only need the
+// accuracy of the archive itself (unit roundoff 2^-24 relative to |Q||X|), so
+// the products run as v_mfma_f32_16x16x4f32 with float accumulation inside a
+// workgroup's row range; partial sums are reduced in float64 in a fixed order
+// (bitwise reproducible, no atomics).
+//
+// v_mfma_f32_16x16x4f32 operand layout (lane l of 64, i = l % 16, k = l / 16):
+//   A (16 x 4):  lane l holds A[i][k]
+//   B (4 x 16):  lane l holds B[k][i]
+//   D (16 x 16): register r of lane l holds D[4 k + r][i]
+#include "gk_internal.h"
+
+namespace gk {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ f4 mfma32(float a, float b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// ------------------------------------------------------------- Gram C = Q^T X
+// Workgroup = 8 wavefronts; wavefront w owns archive block j = 8 bx + w and
+// accumulates C_j over the row range of blockIdx.y.  X rows are staged in LDS
+// as float (shared by the 8 wavefronts); Q rows stream from memory straight
+// into MFMA operands: lane (i, k) of a 4-row step loads the NT consecutive
+// floats Q_j[r + k][NT i .. NT i + NT - 1], so operand e (< NT) covers the
+// archive columns {NT i + e}.
+constexpr int AG_WAVES = 8;
+constexpr int AG_THREADS = 64 * AG_WAVES;
+constexpr int AG_SUB = 64;        // rows staged per LDS round
+constexpr int AG_TARGET_WG = 512; // two workgroups per compute unit
+
+template <int NT>
+__device__ __forceinline__ void load_row_seg(const float* __restrict__ p, float (&a)[NT]) {
+  if constexpr (NT == 4) {
+    const f4 v = *reinterpret_cast<const f4*>(p);
+    a[0] = v[0]; a[1] = v[1]; a[2] = v[2]; a[3] = v[3];
+  } else if constexpr (NT == 2) {
+    const float2 v = *reinterpret_cast<const float2*>(p);
+    a[0] = v.x; a[1] = v.y;
+  } else {
+#pragma unroll
+    for (int e = 0; e < NT; ++e) a[e] = p[e];
+  }
+}
+
+template <int NT>
+__global__ void __launch_bounds__(AG_THREADS, 2)
+arch_gram_kernel(int64_t n, const float* __restrict__ Q, int64_t qstride, int nb, const double* __restrict__ X,
+                 float* __restrict__ part, int64_t rpc, const int* __restrict__ flag) {
+  if (flag && *flag == 0) return;
+  constexpr int LD = 16 * NT;
+  constexpr int P = LD + 16;                 // LDS pitch (floats)
+  __shared__ float sX[AG_SUB * P];
+  const int tid = threadIdx.x;
+  const int w = tid >> 6, l = tid & 63, li = l & 15, lk = l >> 4;
+  const int j = blockIdx.x * AG_WAVES + w;
+  const bool active = j < nb;
+  const float* Qj = Q + (int64_t)(active ? j : 0) * qstride;
+  const int64_t rb = (int64_t)blockIdx.y * rpc;
+  const int64_t re = min(n, rb + rpc);
+
+  f4 acc[NT][NT];
+#pragma unroll
+  for (int e = 0; e < NT; ++e)
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[e][t] = f4{0.f, 0.f, 0.f, 0.f};
+
+  for (int64_t r0 = rb; r0 < re; r0 += AG_SUB) {
+    for (int q = tid; q < AG_SUB * LD; q += AG_THREADS) {
+      const int rr = q / LD, cc = q - rr * LD;
+      const int64_t r = r0 + rr;
+      sX[rr * P + cc] = r < re ? (float)X[r * LD + cc] : 0.f;
+    }
+    __syncthreads();
+    if (active) {
+#pragma unroll 4
+      for (int s4 = 0; s4 < AG_SUB / 4; ++s4) {
+        const int64_t r = r0 + 4 * s4 + lk;
+        float a[NT];
+        if (r < re) load_row_seg<NT>(Qj + r * LD + NT * li, a);
+        else {
+#pragma unroll
+          for (int e = 0; e < NT; ++e) a[e] = 0.f;
+        }
+        float b[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) b[t] = sX[(4 * s4 + lk) * P + 16 * t + li];
+#pragma unroll
+        for (int e = 0; e < NT; ++e)
+#pragma unroll
+          for (int t = 0; t < NT; ++t) acc[e][t] = mfma32(a[e], b[t], acc[e][t]);
+      }
+    }
+    __syncthreads();
+  }
+  if (active) {
+    // D_{e,t}[4k + r][i] = C_j[NT (4k + r) + e][16 t + i]
+    float* P0 = part + ((int64_t)blockIdx.y * nb + j) * LD * LD;
+#pragma unroll
+    for (int e = 0; e < NT; ++e)
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) P0[(NT * (4 * lk + r) + e) * LD + 16 * t + li] = acc[e][t][r];
+  }
+}
+
+// out[i] = sum_c part[c * len + i] in float64, chunks added in index order.
+__global__ void __launch_bounds__(256)
+reduce_f32_parts_kernel(int64_t len, int nparts, const float* __restrict__ part, double* __restrict__ out,
+                        const int* __restrict__ flag) {
+  if (flag && *flag == 0) return;
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= len) return;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int c = 0;
+  for (; c + 4 <= nparts; c += 4) {
+    s0 += (double)part[(int64_t)c * len + i];
+    s1 += (double)part[(int64_t)(c + 1) * len + i];
+    s2 += (double)part[(int64_t)(c + 2) * len + i];
+    s3 += (double)part[(int64_t)(c + 3) * len + i];
+  }
+  for (; c < nparts; ++c) s0 += (double)part[(int64_t)c * len + i];
+  out[i] = (s0 + s1) + (s2 + s3);
+}
+
+// ---------------------------------------------------------- update X -= Q C
+// Workgroup = 4 wavefronts over 128 rows; wavefront w owns rows 32 w .. 32 w + 31
+// as two groups of 16.  The product is formed transposed, D = C^T Q^T, so
+// that the archive rows are the B operand: lane (i, k) loads the LD/4
+// consecutive floats Q_j[row i][k LD/4 .. (k+1) LD/4 - 1] (float4 loads), and
+// operand e contracts over the columns {k LD/4 + e}.  The coefficient block
+// C_j (float64) is staged in LDS as float, double buffered over j.
+constexpr int AU_ROWS = 128;
+
+template <int NT>
+__global__ void __launch_bounds__(256, 2)
+arch_update_kernel(int64_t n, const float* __restrict__ Q, int64_t qstride, int nb, const double* __restrict__ C,
+                   double* __restrict__ X, const int* __restrict__ flag) {
+  if (flag && *flag == 0) return;
+  constexpr int LD = 16 * NT;
+  constexpr int KQ = LD / 4;                 // floats per lane per block row
+  constexpr int PC = LD + 4;                 // LDS pitch of the staged coefficients
+  __shared__ float sC[2][LD * PC];
+  const int tid = threadIdx.x;
+  const int w = tid >> 6, l = tid & 63, li = l & 15, lk = l >> 4;
+  const int64_t R0 = (int64_t)blockIdx.x * AU_ROWS + 32 * w;
+
+  f4 acc[2][NT];
+#pragma unroll
+  for (int g = 0; g < 2; ++g)
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[g][t] = f4{0.f, 0.f, 0.f, 0.f};
+
+  auto stage = [&](int jb, int buf) {
+    const double* Cj = C + (int64_t)jb * LD * LD;
+    for (int q = tid; q < LD * LD; q += 256) {
+      const int a = q / LD, b = q - a * LD;
+      sC[buf][a * PC + b] = (float)Cj[q];
+    }
+  };
+  auto load_q = [&](int jb, float (&qv)[2][KQ]) {
+    const float* Qj = Q + (int64_t)jb * qstride;
+#pragma unroll
+    for (int g = 0; g < 2; ++g) {
+      const int64_t r = R0 + 16 * g + li;
+      if (r < n) {
+#pragma unroll
+        for (int v = 0; v < KQ / 4; ++v) {
+          const f4 x = *reinterpret_cast<const f4*>(Qj + r * LD + lk * KQ + 4 * v);
+          qv[g][4 * v] = x[0]; qv[g][4 * v + 1] = x[1]; qv[g][4 * v + 2] = x[2]; qv[g][4 * v + 3] = x[3];
+        }
+      } else {
+#pragma unroll
+        for (int e = 0; e < KQ; ++e) qv[g][e] = 0.f;
+      }
+    }
+  };
+
+  float qcur[2][KQ];
+  stage(0, 0);
+  load_q(0, qcur);
+  __syncthreads();
+  for (int jb = 0; jb < nb; ++jb) {
+    const int buf = jb & 1;
+    if (jb + 1 < nb) stage(jb + 1, buf ^ 1);
+    float qnext[2][KQ];
+    if (jb + 1 < nb) load_q(jb + 1, qnext);
+    const float* sc = sC[buf];
+#pragma unroll
+    for (int e = 0; e < KQ; ++e) {
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const float cv = sc[(lk * KQ + e) * PC + 16 * t + li];
+#pragma unroll
+        for (int g = 0; g < 2; ++g) acc[g][t] = mfma32(cv, qcur[g][e], acc[g][t]);
+      }
+    }
+    __syncthreads();
+    if (jb + 1 < nb) {
+#pragma unroll
+      for (int g = 0; g < 2; ++g)
+#pragma unroll
+        for (int e = 0; e < KQ; ++e) qcur[g][e] = qnext[g][e];
+    }
+  }
+  // D_{g,t}[4k + r][i] = (Q C)[row 16 g + i][16 t + 4 k + r]
+#pragma unroll
+  for (int g = 0; g < 2; ++g) {
+    const int64_t r = R0 + 16 * g + li;
+    if (r >= n) continue;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      double* xp = X + r * LD + 16 * t + 4 * lk;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) xp[q] -= (double)acc[g][t][q];
+    }
+  }
+}
+
+// ------------------------------------------------------------------ launchers
+bool arch_ok(int ld) { return ld == 16 || ld == 32 || ld == 48 || ld == 64; }
+
+static void arch_gram_geometry(int64_t n, int nb, int* ngroups, int* nchunks, int64_t* rpc) {
+  *ngroups = (nb + AG_WAVES - 1) / AG_WAVES;
+  int64_t want = (AG_TARGET_WG + *ngroups - 1) / *ngroups;
+  const int64_t maxc = (n + AG_SUB - 1) / AG_SUB;
+  if (want > maxc) want = maxc;
+  if (want < 1) want = 1;
+  int64_t r = (n + want - 1) / want;
+  r = ((r + AG_SUB - 1) / AG_SUB) * AG_SUB;
+  *rpc = r;
+  *nchunks = (int)((n + r - 1) / r);
+}
+
+size_t arch_scratch_floats(int64_t n, int nb_max, int ld) {
+  size_t mx = 0;
+  for (int nb = 1; nb <= nb_max; ++nb) {
+    int ng, nc;
+    int64_t rpc;
+    arch_gram_geometry(n, nb, &ng, &nc, &rpc);
+    mx = std::max(mx, (size_t)nc * nb * ld * ld);
+  }
+  return mx;
+}
+
+template <int NT>
+static void arch_launch(int64_t n, BlockList A, double* X, double* C, float* part, const int* flag, hipStream_t st) {
+  const float* Q = static_cast<const float*>(A.base);
+  int ng, nc;
+  int64_t rpc;
+  arch_gram_geometry(n, A.nb, &ng, &nc, &rpc);
+  hipLaunchKernelGGL(arch_gram_kernel<NT>, dim3(ng, nc), dim3(AG_THREADS), 0, st, n, Q, A.stride, A.nb,
+                     (const double*)X, part, rpc, flag);
+  GK_HIP(hipGetLastError());
+  const int64_t len = (int64_t)A.nb * 16 * NT * 16 * NT;
+  hipLaunchKernelGGL(reduce_f32_parts_kernel, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, st, len, nc,
+                     (const float*)part, C, flag);
+  GK_HIP(hipGetLastError());
+  hipLaunchKernelGGL(arch_update_kernel<NT>, dim3((unsigned)((n + AU_ROWS - 1) / AU_ROWS)), dim3(256), 0, st, n, Q,
+                     A.stride, A.nb, (const double*)C, X, flag);
+  GK_HIP(hipGetLastError());
+}
+
+// One projection X -= Q (Q^T X) against the float32 archive A (A.f32, A.stride
+// > 0, blocks n x ld row-major).  C receives the nb*ld x ld coefficients.
+void launch_arch_reorth(int64_t n, int ld, BlockList A, double* X, double* C, float* part, const int* flag,
+                        hipStream_t st) {
+  GK_REQUIRE(A.f32 && A.stride > 0 && A.nb >= 1, GK_EUNSUPPORTED, "archive projection needs a float32 archive");
+  switch (ld) {
+    case 16: arch_launch<1>(n, A, X, C, part, flag, st); break;
+    case 32: arch_launch<2>(n, A, X, C, part, flag, st); break;
+    case 48: arch_launch<3>(n, A, X, C, part, flag, st); break;
+    case 64: arch_launch<4>(n, A, X, C, part, flag, st); break;
+    default: throw Error{GK_EUNSUPPORTED, "archive projection needs ld in {16,32,48,64}"};
+  }
+}
+
+}  // namespace gk

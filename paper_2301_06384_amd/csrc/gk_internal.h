@@ -181,8 +181,13 @@ void launch_small_solve(int s, const double* K, double gamma, const double* y, d
                         int* piv, bool spd, int* bad, hipStream_t st);
 
 // panel.hip -- fused row-panel MFMA passes (ld in {16, 32, 48, 64})
-enum { PM_GRAMV = 0, PM_UPDATE_SELF = 1, PM_APPLY_SELF = 2, PM_APPLY_WRITE = 3 };
+enum { PM_GRAMV = 0, PM_UPDATE_SELF = 1, PM_APPLY_SELF = 2, PM_APPLY_WRITE = 3, PM_SELF = 4 };
 bool panel_ok(int ld);
+// arch.hip -- projection against the float32 archive on FP32 matrix cores
+bool arch_ok(int ld);
+size_t arch_scratch_floats(int64_t n, int nb_max, int ld);
+void launch_arch_reorth(int64_t n, int ld, BlockList A, double* X, double* C, float* part, const int* flag,
+                        hipStream_t st);
 size_t panel_scratch_elems(int64_t n, int ld);
 void launch_panel(int mode, int64_t n, int ld, int nbv, const double* X, double* Xout, float* X32,
                   const double* V0, const double* V1, const double* Cupd, const double* Rm, double* part,

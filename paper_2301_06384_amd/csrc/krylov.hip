@@ -372,6 +372,7 @@ static void run_cbl(Job& J) {
   int* forced = nullptr;
   size_t pe_all = 0;
   double* part_all = nullptr;
+  float* part32 = nullptr;
   if (pro) {
     for (int i = 0; i < 3; ++i) {
       Wr[i] = J.ar.get<double>((size_t)m * s * s);
@@ -381,8 +382,11 @@ static void run_cbl(Job& J) {
     fr = J.ar.get<int>(m);
     forced = J.ar.get<int>(m + 1);
     launch_zero(forced, sizeof(int) * (m + 1), st);
-    for (int nb = 1; nb <= m; ++nb) pe_all = std::max(pe_all, gram_scratch_elems(n, nb, ld));
-    part_all = J.ar.get<double>(pe_all);
+    if (arch_ok(ld)) part32 = J.ar.get<float>(arch_scratch_floats(n, m, ld));
+    else {
+      for (int nb = 1; nb <= m; ++nb) pe_all = std::max(pe_all, gram_scratch_elems(n, nb, ld));
+      part_all = J.ar.get<double>(pe_all);
+    }
   }
   // tolerances of the estimate: threshold, floor after a reorthogonalisation
   // against the float32 archive, floor of the two explicitly orthogonalised
@@ -458,9 +462,16 @@ static void run_cbl(Job& J) {
         // the float32 archive.
         J.tm.begin(PH_REORTH);
         BlockList all{Va, blk, k + 1, true};
-        launch_gram(n, ld, all, X, C, part_all, fk, st);
-        launch_tsgemm(n, ld, all, C, X, X, nullptr, -1.0, 1.0, fk, st);
-        launch_gram(n, ld, xl, X, G, part_all, fk, st);
+        if (part32) {
+          launch_arch_reorth(n, ld, all, X, C, part32, fk, st);
+        } else {
+          launch_gram(n, ld, all, X, C, part_all, fk, st);
+          launch_tsgemm(n, ld, all, C, X, X, nullptr, -1.0, 1.0, fk, st);
+        }
+        if (pan)
+          launch_panel(PM_SELF, n, ld, 0, X, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, ppart, G, st, fk);
+        else
+          launch_gram(n, ld, xl, X, G, part_all, fk, st);
         launch_cholqr_flag(G, ld, s, 1, nullptr, J.thr(), R1, R1i, d1, nullptr, nullptr, nullptr, nullptr, nullptr, fk,
                            st);
         if (pan) {
@@ -663,7 +674,26 @@ uint64_t footprint_bytes(int64_t n, int s, int m, int variant, int precision) {
     b = mixed ? (3 * blk8 + m * blk8 / 2) : m * blk8;
     b += 2 * blk8;   // X, Y
     const double ms = (double)m * s;
-    if (variant == GK_CBL) b += 2 * ms * ms * 8.0 + (double)m * ld * ld * 8.0 + 4.0 * m * s * s * 8.0;
+    if (variant == GK_CBL) {
+      b += 2 * ms * ms * 8.0 + (double)m * ld * ld * 8.0 + 4.0 * m * s * s * 8.0;
+      // Gram partials of the orthogonalisation passes
+      const bool full = !mixed;
+      size_t pe = 0;
+      for (int nb = 1; nb <= (full ? m : 2); ++nb) pe = std::max(pe, gram_scratch_elems(n, nb, ld));
+      b += 8.0 * pe;
+      if (panel_ok(ld)) b += 8.0 * panel_scratch_elems(n, ld);
+      if (mixed) {
+        // partial reorthogonalisation: estimate blocks and archive partials
+        b += 3.0 * m * s * s * 8.0;
+        if (arch_ok(ld)) {
+          b += 4.0 * arch_scratch_floats(n, m, ld);
+        } else {
+          size_t pa = 0;
+          for (int nb = 1; nb <= m; ++nb) pa = std::max(pa, gram_scratch_elems(n, nb, ld));
+          b += 8.0 * pa;
+        }
+      }
+    }
   }
   b += (double)n * s * 8.0 + 64.0 * (1 << 20);   // output staging + small scratch
   return (uint64_t)b;

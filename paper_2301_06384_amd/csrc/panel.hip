@@ -20,7 +20,7 @@ namespace gk {
 typedef double d4 __attribute__((ext_vector_type(4)));
 
 constexpr int PT_ROWS = 32;      // rows per tile
-constexpr int PT_THREADS = 256;  // 4 wavefronts: slab (w & 1) x column half (w >> 1)
+constexpr int PT_THREADS = 256;  // 4 wavefronts
 constexpr int PT_MAXGRID = 512;  // two workgroups per CU
 
 __device__ __forceinline__ d4 mfma64(double a, double b, d4 c) {
@@ -49,7 +49,6 @@ __global__ void __launch_bounds__(PT_THREADS, 2) panel_kernel(PanelArgs p) {
   constexpr int LD = NT * 16;
   constexpr int P = LD + 4;                      // LDS row pitch (doubles)
   constexpr int KS = LD / 4;                     // MFMA k-steps over ld
-  constexpr int CT = (NT + 1) / 2;               // column tiles per wavefront
   constexpr int NGB = (GRAMV ? NBV : 0) + (SELF ? 1 : 0);
   constexpr bool SYM = SELF && !GRAMV;
   constexpr int NPAIR = SYM ? NT * (NT + 1) / 2 : NGB * NT * NT;
@@ -64,26 +63,27 @@ __global__ void __launch_bounds__(PT_THREADS, 2) panel_kernel(PanelArgs p) {
   const int l = tid & 63;
   const int li = l & 15;
   const int lk = l >> 4;
-  const int slab = w & 1;
-  const int half = w >> 1;
 
-  // right operands of the update / apply product, resident for the whole kernel
-  double creg[NBC > 0 ? NBC : 1][KS][CT];
+  // Update / apply product: wavefront w owns one 16-column tile (unt) of X_new
+  // over UP slabs of 16 rows; its right operands stay in registers for the
+  // whole kernel.
+  constexpr int UP = NT >= 3 ? 2 : 1;
+  const int unt = NT >= 3 ? w : (w >> 1);
+  const int us0 = NT >= 3 ? 0 : (w & 1);
+  const bool uact = unt < NT;
+  double creg[NBC > 0 ? NBC : 1][KS];
   if (NBC > 0) {
 #pragma unroll
     for (int b = 0; b < (NBC > 0 ? NBC : 1); ++b)
 #pragma unroll
-      for (int ks = 0; ks < KS; ++ks)
-#pragma unroll
-        for (int ct = 0; ct < CT; ++ct) {
-          const int nt = half + 2 * ct;
-          double v = 0.0;
-          if (nt < NT) {
-            const double* src = UPDATE ? p.C : p.Rm;
-            v = src[(int64_t)(b * LD + 4 * ks + lk) * LD + 16 * nt + li];
-          }
-          creg[b][ks][ct] = v;
+      for (int ks = 0; ks < KS; ++ks) {
+        double v = 0.0;
+        if (uact) {
+          const double* src = UPDATE ? p.C : p.Rm;
+          v = src[(int64_t)(b * LD + 4 * ks + lk) * LD + 16 * unt + li];
         }
+        creg[b][ks] = v;
+      }
   }
   // Gram tile list of this wavefront
   int tgi[TPW > 0 ? TPW : 1], txj[TPW > 0 ? TPW : 1];
@@ -128,50 +128,53 @@ __global__ void __launch_bounds__(PT_THREADS, 2) panel_kernel(PanelArgs p) {
       }
     }
     __syncthreads();
-    // ---- X_new for (slab, column half) of this wavefront
+    // ---- X_new for the (slabs, column tile) of this wavefront
     if (UPDATE || APPLY) {
-      d4 acc[CT];
-      const int rs = 16 * slab;
+      d4 acc[UP];
 #pragma unroll
-      for (int ct = 0; ct < CT; ++ct) {
-        const int nt = half + 2 * ct;
-        acc[ct] = d4{0.0, 0.0, 0.0, 0.0};
-        if (UPDATE && nt < NT) {
+      for (int u = 0; u < UP; ++u) {
+        const int rs = 16 * (us0 + u);
+        acc[u] = d4{0.0, 0.0, 0.0, 0.0};
+        if (UPDATE && uact) {
 #pragma unroll
-          for (int r = 0; r < 4; ++r) acc[ct][r] = sX[(rs + 4 * r + lk) * P + 16 * nt + li];
+          for (int r = 0; r < 4; ++r) acc[u][r] = sX[(rs + 4 * r + lk) * P + 16 * unt + li];
         }
       }
-      if (UPDATE) {
+      if (uact) {
+        if (UPDATE) {
 #pragma unroll
-        for (int b = 0; b < (NBV > 0 ? NBV : 1); ++b) {
-          const double* sv = sV + b * PT_ROWS * P;
+          for (int b = 0; b < (NBV > 0 ? NBV : 1); ++b) {
+            const double* sv = sV + b * PT_ROWS * P;
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) {
+#pragma unroll
+              for (int u = 0; u < UP; ++u) {
+                const double a = -sv[(16 * (us0 + u) + li) * P + 4 * ks + lk];
+                acc[u] = mfma64(a, creg[b][ks], acc[u]);
+              }
+            }
+          }
+        } else {
 #pragma unroll
           for (int ks = 0; ks < KS; ++ks) {
-            const double a = -sv[(rs + li) * P + 4 * ks + lk];
+            // Rm is upper triangular: rows 4ks.. of column tile unt vanish once 4ks >= 16(unt+1)
+            if (4 * ks < 16 * (unt + 1)) {
 #pragma unroll
-            for (int ct = 0; ct < CT; ++ct)
-              if (half + 2 * ct < NT) acc[ct] = mfma64(a, creg[b][ks][ct], acc[ct]);
-          }
-        }
-      } else {
-#pragma unroll
-        for (int ks = 0; ks < KS; ++ks) {
-          const double a = sX[(rs + li) * P + 4 * ks + lk];
-#pragma unroll
-          for (int ct = 0; ct < CT; ++ct) {
-            const int nt = half + 2 * ct;
-            // Rm is upper triangular: rows 4ks.. of column tile nt vanish once 4ks >= 16(nt+1)
-            if (nt < NT && 4 * ks < 16 * (nt + 1)) acc[ct] = mfma64(a, creg[0][ks][ct], acc[ct]);
+              for (int u = 0; u < UP; ++u) {
+                const double a = sX[(16 * (us0 + u) + li) * P + 4 * ks + lk];
+                acc[u] = mfma64(a, creg[0][ks], acc[u]);
+              }
+            }
           }
         }
       }
       __syncthreads();   // every wavefront has read its sX rows
+      if (uact) {
 #pragma unroll
-      for (int ct = 0; ct < CT; ++ct) {
-        const int nt = half + 2 * ct;
-        if (nt < NT) {
+        for (int u = 0; u < UP; ++u) {
+          const int rs = 16 * (us0 + u);
 #pragma unroll
-          for (int r = 0; r < 4; ++r) sX[(rs + 4 * r + lk) * P + 16 * nt + li] = acc[ct][r];
+          for (int r = 0; r < 4; ++r) sX[(rs + 4 * r + lk) * P + 16 * unt + li] = acc[u][r];
         }
       }
       __syncthreads();
@@ -260,6 +263,9 @@ static void panel_dispatch(PanelMode mode, int nbv, const PanelArgs& a, int grid
       if (a.X32) GK_PK(0, false, true, false, false, true, true);
       else GK_PK(0, false, true, false, false, true, false);
       break;
+    case PM_SELF:
+      GK_PK(0, false, false, false, true, false, false);
+      break;
   }
 #undef GK_PK
   GK_HIP(hipGetLastError());
@@ -281,7 +287,7 @@ void launch_panel(int mode, int64_t n, int ld, int nbv, const double* X, double*
   }
   int ngb = 0;
   if (pm == PM_GRAMV) ngb = nbv;
-  if (pm == PM_UPDATE_SELF || pm == PM_APPLY_SELF) ngb = 1;
+  if (pm == PM_UPDATE_SELF || pm == PM_APPLY_SELF || pm == PM_SELF) ngb = 1;
   if (ngb > 0) {
     launch_reduce_parts((int64_t)ngb * ld * ld, grid, part, Cout, flag, st);
   }

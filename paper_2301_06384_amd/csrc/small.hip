@@ -655,6 +655,7 @@ __device__ __forceinline__ void lds_mm(const double (*A)[LP], const double (*B)[
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+#pragma unroll 4
   for (int l = 0; l < s; ++l) {
     double av[4], bv[4];
 #pragma unroll
@@ -668,58 +669,236 @@ __device__ __forceinline__ void lds_mm(const double (*A)[LP], const double (*B)[
   }
 }
 
-// Right-looking lower Cholesky of the symmetric A (s x s, lower part used)
-// together with Y = L^{-1} (on the kept indices), by one elimination:
-//   Y[j,:] = Z[j,:] / L_jj ;  Z[r,:] -= L_rj Y[j,:]  (r > j),   Z = I initially.
-// mode 0: plain (non-positive pivot -> *bad = 3, pivot 1 used);
-// mode 1 / 2: the CholQR deflation rules (see cholqr_factor_kernel);
-// deflated columns give zero columns of L and zero rows of Y.
-__device__ void blk_chol_inv(double (*A)[LP], double (*Y)[LP], int s, int mode, const double* g0, const double* dprev,
-                             double thr, double* dg, int* bad) {
-  const int tid = threadIdx.x;
-  const int tx = tid & 15, ty = tid >> 4;
-  const double eta = 1e-7;
-  for (int r = ty; r < s; r += 16)
-    for (int c = tx; c < s; c += 16) Y[r][c] = (r == c) ? 1.0 : 0.0;
-  __syncthreads();
-  for (int j = 0; j < s; ++j) {
-    const double piv = A[j][j];
-    double ljj;
-    if (mode == 0) {
-      ljj = sqrt((piv > 0.0) ? piv : 1.0);
-      if (!(piv > 0.0) && tid == 0 && bad) *bad = 3;
-    } else if (mode == 1) {
-      ljj = (g0[j] > thr * thr) ? sqrt(fmax(piv, eta * eta * g0[j])) : 0.0;
+// D[i][c] = src[i * lds + c] for i, c < s and 0 elsewhere in the 64 x 64
+// tile (256 threads).  All loads are issued before the LDS stores.
+__device__ __forceinline__ void fetch64(const double* __restrict__ src, int s, int lds, double (&v)[16]) {
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int i = ty + 16 * a, c = tx + 16 * b;
+      v[4 * a + b] = (src && i < s && c < s) ? src[i * lds + c] : 0.0;
+    }
+}
+__device__ __forceinline__ void put64(double (*D)[LP], const double (&v)[16]) {
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) D[ty + 16 * a][tx + 16 * b] = v[4 * a + b];
+}
+__device__ __forceinline__ void stage64(double (*D)[LP], const double* __restrict__ src, int s, int lds) {
+  double v[16];
+  fetch64(src, s, lds, v);
+  put64(D, v);
+}
+
+// Lower Cholesky of the symmetric A (s x s, lower part used) together with
+// Y = L^{-1}, blocked by 16 (256 threads):
+//   for each diagonal block b:  A_bb = L_bb L_bb^T and Y_bb = L_bb^{-1}
+//   (one wavefront, registers and lane shuffles);  then
+//   L_ib = A_ib Y_bb^T,  Y_b = Y_bb Z_b,  A_ij -= L_ib L_jb^T,  Z_i -= L_ib Y_b
+//   for the block rows i, j > b, where Z (= I initially) carries the
+//   right-hand sides of L Y = I.
+// Inside a diagonal block the pivots follow the rules of `mode`:
+//   0: plain (non-positive pivot -> *bad = 3, pivot 1 used);
+//   1 / 2: the CholQR deflation rules (see cholqr_factor_kernel).
+// Deflated columns give zero columns of L and zero rows of Y.  Indices s..63
+// are padded with an identity block.  Z is clobbered.
+// 1/sqrt(p) for p > 0: hardware estimate refined by two Newton steps.
+__device__ __forceinline__ double rsqrt_nr(double p) {
+  double y = __builtin_amdgcn_rsq(p);
+  y = y * fma(-0.5 * p * y, y, 1.5);
+  y = y * fma(-0.5 * p * y, y, 1.5);
+  return y;
+}
+
+// Pivot rule of column j (global index gj): returns l_jj and 1 / l_jj (0 for
+// a deflated column).  gjj = original Gram diagonal (mode 1), dpj = first-pass
+// diagonal (mode 2).
+template <int MODE>
+__device__ __forceinline__ void chol_pivot(double piv, int gj, int s, double gjj, double dpj, double thr, int* bad,
+                                           double& l, double& inv) {
+  if (gj >= s) { l = 1.0; inv = 1.0; return; }
+  if (MODE == 0) {
+    if (!(piv > 0.0)) {
+      if (bad) *bad = 3;
+      l = 1.0; inv = 1.0;
+      return;
+    }
+    inv = rsqrt_nr(piv);
+    l = piv * inv;
+  } else if (MODE == 1) {
+    const double eta = 1e-7;
+    if (gjj > thr * thr) {
+      const double pp = fmax(piv, eta * eta * gjj);
+      inv = rsqrt_nr(pp);
+      l = pp * inv;
     } else {
-      ljj = 0.0;
-      if (piv > 0.0) {
-        ljj = sqrt(piv);
-        if (ljj * dprev[j] < thr) ljj = 0.0;
+      l = 0.0; inv = 0.0;
+    }
+  } else {
+    l = 0.0; inv = 0.0;
+    if (piv > 0.0) {
+      const double y = rsqrt_nr(piv);
+      const double ll = piv * y;
+      if (!(ll * dpj < thr)) { l = ll; inv = y; }
+    }
+  }
+}
+
+template <int MODE>
+__device__ void blk_chol_inv_t(double (*A)[LP], double (*Y)[LP], double (*Z)[LP], int s, const double* g0,
+                               const double* dprev, double thr, double* dg, int* bad) {
+  const int tid = threadIdx.x;
+  const int nbk = (s + 15) >> 4;
+  const int S16 = nbk << 4;
+  // pad A with an identity block, Z = I, Y = 0
+  for (int r = tid >> 4; r < S16; r += 16)
+    for (int c = tid & 15; c < S16; c += 16) {
+      if (r >= s || c >= s) A[r][c] = (r == c) ? 1.0 : 0.0;
+      Z[r][c] = (r == c) ? 1.0 : 0.0;
+      Y[r][c] = 0.0;
+    }
+  __syncthreads();
+  for (int b = 0; b < nbk; ++b) {
+    const int o = 16 * b;
+    // ---- diagonal block: wavefront 0, lane (r = l % 16, columns 4 (l / 16) + q).
+    // Register arrays are only indexed by constants (selects below), so they
+    // stay in registers whether or not the column loop is unrolled.
+    if (tid < 64) {
+      const int r = tid & 15, cg = tid >> 4;
+      double a0 = A[o + r][o + 4 * cg], a1 = A[o + r][o + 4 * cg + 1];
+      double a2 = A[o + r][o + 4 * cg + 2], a3 = A[o + r][o + 4 * cg + 3];
+      double y0 = (r == 4 * cg) ? 1.0 : 0.0, y1 = (r == 4 * cg + 1) ? 1.0 : 0.0;
+      double y2 = (r == 4 * cg + 2) ? 1.0 : 0.0, y3 = (r == 4 * cg + 3) ? 1.0 : 0.0;
+      const double gr = (MODE == 1 && o + r < s) ? g0[o + r] : 0.0;
+      const double dr = (MODE == 2 && o + r < s) ? dprev[o + r] : 0.0;
+      double myl = 0.0;
+      for (int j = 0; j < 16; ++j) {
+        const int own = j & 3, jg = j >> 2;
+        const double aj = own == 0 ? a0 : own == 1 ? a1 : own == 2 ? a2 : a3;   // A[r][4 cg + own]
+        const double gjj = __shfl(gr, j), dpj = __shfl(dr, j);
+        const double piv = __shfl(aj, j + 16 * jg);
+        double ljj, inv;
+        chol_pivot<MODE>(piv, o + j, s, gjj, dpj, thr, bad, ljj, inv);
+        if (r == j) myl = ljj;
+        double ajn = aj;
+        if (cg == jg) {
+          if (r > j) ajn = aj * inv;
+          if (r == j) ajn = ljj;
+        }
+        if (own == 0) a0 = ajn; else if (own == 1) a1 = ajn; else if (own == 2) a2 = ajn; else a3 = ajn;
+        if (r == j) {
+          y0 *= inv; y1 *= inv; y2 *= inv; y3 *= inv;
+        }
+        const double lrj = __shfl(ajn, r + 16 * jg);
+        const double lc0 = __shfl(ajn, 4 * cg + 16 * jg), lc1 = __shfl(ajn, 4 * cg + 1 + 16 * jg);
+        const double lc2 = __shfl(ajn, 4 * cg + 2 + 16 * jg), lc3 = __shfl(ajn, 4 * cg + 3 + 16 * jg);
+        const double yj0 = __shfl(y0, j + 16 * cg), yj1 = __shfl(y1, j + 16 * cg);
+        const double yj2 = __shfl(y2, j + 16 * cg), yj3 = __shfl(y3, j + 16 * cg);
+        if (r > j) {
+          const int c0 = 4 * cg;
+          if (c0 > j && c0 <= r) a0 -= lrj * lc0;
+          if (c0 + 1 > j && c0 + 1 <= r) a1 -= lrj * lc1;
+          if (c0 + 2 > j && c0 + 2 <= r) a2 -= lrj * lc2;
+          if (c0 + 3 > j && c0 + 3 <= r) a3 -= lrj * lc3;
+          y0 -= lrj * yj0; y1 -= lrj * yj1; y2 -= lrj * yj2; y3 -= lrj * yj3;
+        }
+      }
+      if (dg && tid < 16) dg[o + r] = (o + r < s) ? myl : 0.0;
+      const double av[4] = {a0, a1, a2, a3}, yv[4] = {y0, y1, y2, y3};
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int c = 4 * cg + q;
+        A[o + r][o + c] = (c <= r) ? av[q] : 0.0;
+        Z[o + r][o + c] = (c <= r) ? yv[q] : 0.0;   // Y_bb, kept in the diagonal block of Z
       }
     }
-    const double inv = (ljj != 0.0) ? 1.0 / ljj : 0.0;
-    __syncthreads();   // everyone has read A[j][j]
-    // phase 1: column j of L, row j of Y
-    for (int q = tid; q < s; q += ST) {
-      if (q > j) A[q][j] *= inv;
-      if (q <= j) Y[j][q] *= inv;
-    }
-    if (tid == 0) {
-      A[j][j] = ljj;
-      if (dg) dg[j] = ljj;
+    __syncthreads();
+    // ---- panel L_ib = A_ib Y_bb^T and Y_b = Y_bb Z_b, one element per thread
+    // and round; the in-place L_ib results are written after a barrier.
+    {
+      const int prow = S16 - o - 16;              // rows below the diagonal block
+      const int npan = prow * 16;
+      const int ntot = npan + 16 * o;
+      constexpr int KMAX = (48 * 16 + 16 * 48 + ST - 1) / ST;
+      double res[KMAX];
+#pragma unroll
+      for (int k = 0; k < KMAX; ++k) {
+        const int q = tid + k * ST;
+        res[k] = 0.0;
+        if (q < npan) {
+          const int r = o + 16 + (q >> 4), c = q & 15;
+          double acc = 0.0;
+#pragma unroll
+          for (int t = 0; t < 16; ++t)
+            if (t <= c) acc = fma(A[r][o + t], Z[o + c][o + t], acc);
+          res[k] = acc;
+        } else if (q < ntot) {
+          // Y_b[r][c] = sum_t Y_bb[r][t] Z[o + t][c] for the columns c < o
+          const int qq = q - npan;
+          const int r = qq / o, c = qq - r * o;
+          double acc = 0.0;
+#pragma unroll
+          for (int t = 0; t < 16; ++t)
+            if (t <= r) acc = fma(Z[o + r][o + t], Z[o + t][c], acc);
+          Y[o + r][c] = acc;
+        }
+      }
+      // diagonal block of Y
+      for (int q = tid; q < 256; q += ST) {
+        const int r = q >> 4, c = q & 15;
+        Y[o + r][o + c] = (c <= r) ? Z[o + r][o + c] : 0.0;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < KMAX; ++k) {
+        const int q = tid + k * ST;
+        if (q < npan) A[o + 16 + (q >> 4)][o + (q & 15)] = res[k];
+      }
     }
     __syncthreads();
-    // phase 2: trailing update of A (lower part) and of the rows of Y below j
-    // (16 x 16 thread grid, no index division)
-    for (int r = j + 1 + ty; r < s; r += 16) {
-      const double lr = A[r][j];
-      for (int c = tx; c <= r; c += 16) {
-        if (c > j) A[r][c] -= lr * A[c][j];
-        else Y[r][c] -= lr * Y[j][c];
+    // ---- trailing updates: A_ij -= L_ib L_jb^T (lower), Z_i -= L_ib Y_b
+    {
+      const int t0 = o + 16;
+      const int nt = S16 - t0;
+      const int na = nt * nt;
+      const int nz = nt * t0;
+      for (int q = tid; q < na + nz; q += ST) {
+        if (q < na) {
+          const int r = t0 + q / nt, c = t0 + q % nt;
+          if (c <= r) {
+            double acc = A[r][c];
+#pragma unroll
+            for (int t = 0; t < 16; ++t) acc = fma(-A[r][o + t], A[c][o + t], acc);
+            A[r][c] = acc;
+          }
+        } else {
+          const int qq = q - na;
+          const int r = t0 + qq / t0, c = qq % t0;
+          double acc = Z[r][c];
+#pragma unroll
+          for (int t = 0; t < 16; ++t) acc = fma(-A[r][o + t], Y[o + t][c], acc);
+          Z[r][c] = acc;
+        }
       }
     }
     __syncthreads();
   }
+  // strict upper part of L is zero
+  for (int r = tid >> 4; r < S16; r += 16)
+    for (int c = tid & 15; c < S16; c += 16)
+      if (c > r) A[r][c] = 0.0;
+  __syncthreads();
+}
+
+__device__ void blk_chol_inv(double (*A)[LP], double (*Y)[LP], double (*Z)[LP], int s, int mode, const double* g0,
+                             const double* dprev, double thr, double* dg, int* bad) {
+  if (mode == 0) blk_chol_inv_t<0>(A, Y, Z, s, g0, dprev, thr, dg, bad);
+  else if (mode == 1) blk_chol_inv_t<1>(A, Y, Z, s, g0, dprev, thr, dg, bad);
+  else blk_chol_inv_t<2>(A, Y, Z, s, g0, dprev, thr, dg, bad);
 }
 
 // CholQR factor of a Gram matrix (ld <= 64), 256 threads.
@@ -738,21 +917,71 @@ cholqr_blk_kernel(const double* __restrict__ G, int ld, int s, int pass, const d
   __shared__ double S1[WS][LP];
   __shared__ double S2[WS][LP];
   __shared__ double g0[WS], dp[WS], dg[WS];
+  __shared__ double red[2][ST];
   const int tid = threadIdx.x;
-  for (int i = tid >> 4; i < s; i += 16)
-    for (int c = tid & 15; c < s; c += 16) {
-      A[i][c] = G[i * ld + c];
-      if (pass == 2) {
-        S1[i][c] = R1[i * ld + c];
-        S2[i][c] = R1inv[i * ld + c];
-      }
-    }
+  const int tx = tid & 15, ty = tid >> 4;
+  stage64(A, G, s, ld);
   for (int q = tid; q < s; q += ST) {
     g0[q] = G[q * ld + q];
     dp[q] = (pass == 2) ? diag_prev[q] : 0.0;
   }
   __syncthreads();
-  blk_chol_inv(A, Y, s, pass, g0, dp, thr, dg, nullptr);
+  // Second pass with G = I + E, |E| <= 1e-6 and no column near the deflation
+  // threshold: the Cholesky factor of I + E and its inverse follow from the
+  // expansion R = I + U + W, R^{-1} = I - U - W + U^2 with U = triu(E) - diag(E)/2
+  // and W = -(triu(M) - diag(M)/2), M = U^T U; the neglected terms are O(|E|^3).
+  bool fast = false;
+  if (pass == 2) {
+    double e = 0.0, dmin = INFINITY;
+    for (int i = ty; i < s; i += 16)
+      for (int c = tx; c < s; c += 16) e = fmax(e, fabs(A[i][c] - (i == c ? 1.0 : 0.0)));
+    for (int q = tid; q < s; q += ST) dmin = fmin(dmin, dp[q]);
+    red[0][tid] = e;
+    red[1][tid] = dmin;
+    __syncthreads();
+    for (int w = ST / 2; w > 0; w >>= 1) {
+      if (tid < w) {
+        red[0][tid] = fmax(red[0][tid], red[0][tid + w]);
+        red[1][tid] = fmin(red[1][tid], red[1][tid + w]);
+      }
+      __syncthreads();
+    }
+    fast = red[0][0] <= 1e-6 && red[1][0] >= 2.0 * thr;
+  }
+  if (fast) {
+    for (int i = ty; i < WS; i += 16)
+      for (int c = tx; c < WS; c += 16) {
+        double u = 0.0;
+        if (i < s && c < s) {
+          if (c > i) u = A[i][c];
+          else if (c == i) u = 0.5 * (A[i][i] - 1.0);
+        }
+        S1[i][c] = u;
+      }
+    __syncthreads();
+    double mm[4][4], u2[4][4];
+    lds_mm<true, false>(S1, S1, s, mm);    // U^T U
+    lds_mm<false, false>(S1, S1, s, u2);   // U U
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int r = 4 * ty + i, c = 4 * tx + j;
+        if (r < s && c < s) {
+          const double u = S1[r][c];
+          const double w = (c > r) ? -mm[i][j] : (c == r ? -0.5 * mm[i][j] : 0.0);
+          const double del = (r == c) ? 1.0 : 0.0;
+          const double r2 = (c >= r) ? del + u + w : 0.0;
+          const double r2i = (c >= r) ? del - u - w + u2[i][j] : 0.0;
+          A[c][r] = r2;    // L = R^T
+          Y[c][r] = r2i;   // L^{-1} = R^{-T}
+          if (r == c) dg[r] = r2;
+        }
+      }
+    __syncthreads();
+  } else {
+    blk_chol_inv(A, Y, S1, s, pass, g0, dp, thr, dg, nullptr);
+  }
   // R = L^T, Rinv = Y^T (upper), coalesced stores with zero padding
   for (int q = tid; q < ld * ld; q += ST) {
     const int i = q / ld, c = q % ld;
@@ -767,13 +996,14 @@ cholqr_blk_kernel(const double* __restrict__ G, int ld, int s, int pass, const d
       for (int j = 0; j < s; ++j) cnt += (dg[j] == 0.0);
       *n_defl += cnt;
     }
-    // zero the strict upper part of L so that products can use it directly
-    for (int q = tid; q < s * s; q += ST) {
-      const int i = q / s, c = q % s;
-      if (c > i) A[i][c] = 0.0;
+    {
+      double v1[16], v2[16];
+      fetch64(R1, s, ld, v1);
+      fetch64(R1inv, s, ld, v2);
+      put64(S1, v1);
+      put64(S2, v2);
     }
     __syncthreads();
-    const int tx = tid & 15, ty = tid >> 4;
     double acc[4][4];
     // Rc = R1inv * R2inv = S2 * Y^T
     lds_mm<false, true>(S2, Y, s, acc);
@@ -809,15 +1039,19 @@ banded_factor_blk_kernel(int m, int s, const double* __restrict__ Hd, const doub
   const int tid = threadIdx.x;
   const int tx = tid & 15, ty = tid >> 4;
   const int ss = s * s;
+  double hv[16], bv[16];
+  fetch64(Hd, s, s, hv);
   for (int j = 0; j < m; ++j) {
-    const double* H = Hd + (int64_t)j * ss;
-    const double* Bj = Bd + (int64_t)j * ss;
-    for (int i = ty; i < s; i += 16)
-      for (int c = tx; c < s; c += 16) {
-        A[i][c] = H[i * s + c] + ((i == c) ? eps : 0.0);
-        if (j + 1 < m) SB[i][c] = Bj[i * s + c];
-      }
+    // A = eps I + H_jj (operands of the next block are fetched ahead)
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+        if (ty + 16 * a == tx + 16 * b && ty + 16 * a < s) hv[4 * a + b] += eps;
+    put64(A, hv);
+    fetch64(Bd + (int64_t)j * ss, s, s, bv);
     __syncthreads();
+    if (j + 1 < m) fetch64(Hd + (int64_t)(j + 1) * ss, s, s, hv);
     if (j > 0) {
       double acc[4][4];
       lds_mm<false, true>(Ls, Ls, s, acc);
@@ -831,12 +1065,15 @@ banded_factor_blk_kernel(int m, int s, const double* __restrict__ Hd, const doub
         }
       __syncthreads();
     }
-    blk_chol_inv(A, Y, s, 0, nullptr, nullptr, 0.0, nullptr, bad);
+    blk_chol_inv(A, Y, SB, s, 0, nullptr, nullptr, 0.0, nullptr, bad);
     double* LiG = Linv_all + (int64_t)j * ss;
     for (int i = ty; i < s; i += 16)
       for (int c = tx; c < s; c += 16) LiG[i * s + c] = (c <= i) ? Y[i][c] : 0.0;
     if (j + 1 < m) {
-      // Y has zeros above its diagonal (set at initialisation), so the product is exact
+      // SB served as elimination workspace; stage H_{j+1,j} now
+      put64(SB, bv);
+      __syncthreads();
+      // Y has zeros above its diagonal, so the product is exact
       double acc[4][4];
       lds_mm<false, true>(SB, Y, s, acc);
       __syncthreads();
@@ -857,8 +1094,95 @@ banded_factor_blk_kernel(int m, int s, const double* __restrict__ Hd, const doub
 }
 
 // Solve phase: kpow times  Y <- (L L^T)^{-1} Y  with Y = U (m s x s), starting
-// from U = F_1.  Thread (c, g): column c, rows i = g, g + G, ...  Each block
-// step stages its s x s operands in LDS with coalesced loads.
+// from U = F_1, as forward (L) and backward (L^T) block substitutions:
+//   forward  Y_j <- Linv_j (Y_j - Lsub_{j-1} Y_{j-1})
+//   backward Y_j <- Linv_j^T (Y_j - Lsub_j^T Y_{j+1})
+// 256 threads; the operands of the next block step are fetched into registers
+// while the current one computes; the neighbouring block stays in LDS.
+__global__ void __launch_bounds__(ST)
+banded_solve_kernel(int m, int s, int kpow, const double* __restrict__ Linv_all, const double* __restrict__ Lsub_all,
+                    double* __restrict__ U) {
+  __shared__ double T[WS][LP];
+  __shared__ double SL[WS][LP];   // Lsub
+  __shared__ double SY[WS][LP];   // neighbouring block of Y (previous step's result)
+  __shared__ double SI[WS][LP];   // Linv
+  const int tid = threadIdx.x;
+  const int tx = tid & 15, ty = tid >> 4;
+  const int ss = s * s;
+  const int nsteps = 2 * kpow * m;
+  // step -> (direction, block)
+  auto blk_of = [&](int st, int& dir, int& j) {
+    const int w = st % (2 * m);
+    dir = w / m;
+    const int jj = w - dir * m;
+    j = dir == 0 ? jj : m - 1 - jj;
+  };
+  auto has_nb = [&](int dir, int j) { return dir == 0 ? (j > 0) : (j + 1 < m); };
+  // U = F_1 (first block identity)
+  for (int64_t q = tid; q < (int64_t)m * ss; q += ST) {
+    const int64_t r = q / s, c = q - r * s;
+    U[q] = (r == c) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  double pi[16], pl[16], pt[16];
+  {
+    int dir, j;
+    blk_of(0, dir, j);
+    fetch64(Linv_all + (int64_t)j * ss, s, s, pi);
+    fetch64(nullptr, s, s, pl);
+    fetch64(U + (int64_t)j * ss, s, s, pt);
+  }
+  int pj = -1;
+  for (int st = 0; st < nsteps; ++st) {
+    int dir, j;
+    blk_of(st, dir, j);
+    const bool nb = has_nb(dir, j);
+    put64(SI, pi);
+    put64(SL, pl);
+    if (j == pj) {
+      // the previous step finished this very block (turn of a sweep)
+      for (int i = ty; i < WS; i += 16)
+        for (int c = tx; c < WS; c += 16) T[i][c] = SY[i][c];
+    } else {
+      put64(T, pt);
+    }
+    __syncthreads();
+    if (st + 1 < nsteps) {
+      int d2, j2;
+      blk_of(st + 1, d2, j2);
+      fetch64(Linv_all + (int64_t)j2 * ss, s, s, pi);
+      fetch64(has_nb(d2, j2) ? Lsub_all + (int64_t)(d2 == 0 ? j2 - 1 : j2) * ss : nullptr, s, s, pl);
+      fetch64(U + (int64_t)j2 * ss, s, s, pt);
+    }
+    double acc[4][4];
+    if (nb) {
+      if (dir == 0) lds_mm<false, false>(SL, SY, s, acc);   // Lsub_{j-1} Y_{j-1}
+      else lds_mm<true, false>(SL, SY, s, acc);             // Lsub_j^T Y_{j+1}
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) T[4 * ty + i][4 * tx + jj] -= acc[i][jj];
+      __syncthreads();
+    }
+    if (dir == 0) lds_mm<false, false>(SI, T, s, acc);
+    else lds_mm<true, false>(SI, T, s, acc);
+    __syncthreads();   // SY is read above (nb) and rewritten below
+    double* Y = U + (int64_t)j * ss;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) {
+        const int r = 4 * ty + i, c = 4 * tx + jj;
+        const double v = (r < s && c < s) ? acc[i][jj] : 0.0;
+        SY[r][c] = v;
+        if (r < s && c < s) Y[r * s + c] = v;
+      }
+    __syncthreads();
+    pj = j;
+  }
+}
+
 // ---------------------------------------------------------------------
 // Orthogonality estimate for partial reorthogonalisation (block form of the
 // omega recurrence).  With W_{k,j} = V_k^T V_j and the block Lanczos relation
@@ -877,70 +1201,69 @@ omega_kernel(int k, int s, int ld, const double* __restrict__ Wk, const double* 
   __shared__ double S1[WS][LP];
   __shared__ double S2[WS][LP];
   __shared__ double S3[WS][LP];
+  __shared__ double S4[WS][LP];
   __shared__ double red[ST];
   const int j = blockIdx.x;
   const int tid = threadIdx.x;
   const int tx = tid & 15, ty = tid >> 4;
   const int ss = s * s;
   double tot[4][4], acc[4][4];
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) tot[a][b] = 0.0;
-  auto load = [&](double (*D)[LP], const double* src) {
-    for (int i = ty; i < s; i += 16)
-      for (int c = tx; c < s; c += 16) D[i][c] = src[i * s + c];
-  };
   auto addto = [&](double sign) {
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
       for (int b = 0; b < 4; ++b) tot[a][b] += sign * acc[a][b];
   };
-  // W_{k,j+1} B_j
-  load(S1, Wk + (int64_t)(j + 1) * ss);
-  load(S2, Bd + (int64_t)j * ss);
-  __syncthreads();
-  lds_mm<false, false>(S1, S2, s, acc);
-  addto(1.0);
-  __syncthreads();
-  // W_{k,j} H_j - H_k W_{k,j}
-  load(S1, Wk + (int64_t)j * ss);
-  load(S2, Hd + (int64_t)j * ss);
-  load(S3, Hd + (int64_t)k * ss);
-  __syncthreads();
-  lds_mm<false, false>(S1, S2, s, acc);
-  addto(1.0);
-  lds_mm<false, false>(S3, S1, s, acc);
-  addto(-1.0);
-  __syncthreads();
-  // + W_{k,j-1} B_{j-1}^T - B_{k-1} W_{k-1,j}
-  if (j >= 1) {
-    load(S1, Wk + (int64_t)(j - 1) * ss);
-    load(S2, Bd + (int64_t)(j - 1) * ss);
-    __syncthreads();
-    lds_mm<false, true>(S1, S2, s, acc);
-    addto(1.0);
-    __syncthreads();
+  {
+    // W_{k,j+1} B_j + W_{k,j} H_j
+    double v1[16], v2[16], v3[16], v4[16];
+    fetch64(Wk + (int64_t)(j + 1) * ss, s, s, v1);
+    fetch64(Bd + (int64_t)j * ss, s, s, v2);
+    fetch64(Wk + (int64_t)j * ss, s, s, v3);
+    fetch64(Hd + (int64_t)j * ss, s, s, v4);
+    put64(S1, v1); put64(S2, v2); put64(S3, v3); put64(S4, v4);
   }
-  load(S1, Bd + (int64_t)(k - 1) * ss);
-  load(S2, Wkm1 + (int64_t)j * ss);
+  __syncthreads();
+  lds_mm<false, false>(S1, S2, s, tot);
+  lds_mm<false, false>(S3, S4, s, acc);
+  addto(1.0);
+  __syncthreads();
+  {
+    // - H_k W_{k,j} + W_{k,j-1} B_{j-1}^T
+    double v1[16], v2[16], v4[16];
+    fetch64(Hd + (int64_t)k * ss, s, s, v1);
+    fetch64(j >= 1 ? Wk + (int64_t)(j - 1) * ss : nullptr, s, s, v2);
+    fetch64(j >= 1 ? Bd + (int64_t)(j - 1) * ss : nullptr, s, s, v4);
+    put64(S1, v1); put64(S2, v2); put64(S4, v4);
+  }
+  __syncthreads();
+  lds_mm<false, false>(S1, S3, s, acc);
+  addto(-1.0);
+  if (j >= 1) {
+    lds_mm<false, true>(S2, S4, s, acc);
+    addto(1.0);
+  }
+  __syncthreads();
+  {
+    // - B_{k-1} W_{k-1,j}, then W_{k+1,j} = Rc^T (RHS + rounding model)
+    double v1[16], v2[16], v4[16];
+    fetch64(Bd + (int64_t)(k - 1) * ss, s, s, v1);
+    fetch64(Wkm1 + (int64_t)j * ss, s, s, v2);
+    fetch64(Rc, s, ld, v4);
+    put64(S1, v1); put64(S2, v2); put64(S4, v4);
+  }
   __syncthreads();
   lds_mm<false, false>(S1, S2, s, acc);
   addto(-1.0);
-  __syncthreads();
-  // rounding model, then W_{k+1,j} = Rc^T * RHS
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
       const int r = 4 * ty + a, c = 4 * tx + b;
-      if (r < s && c < s) S3[r][c] = tot[a][b] + copysign(nu, tot[a][b]);
+      S3[r][c] = (r < s && c < s) ? tot[a][b] + copysign(nu, tot[a][b]) : 0.0;
     }
-  for (int i = ty; i < s; i += 16)
-    for (int c = tx; c < s; c += 16) S1[i][c] = Rc[i * ld + c];
   __syncthreads();
-  lds_mm<true, false>(S1, S3, s, acc);
+  lds_mm<true, false>(S4, S3, s, acc);
   double mx = 0.0;
   double* out = Wk1 + (int64_t)j * ss;
 #pragma unroll
@@ -998,88 +1321,6 @@ omega_decide_kernel(int k, int s, int nj, const double* __restrict__ est_part, d
   }
 }
 
-__global__ void __launch_bounds__(1024)
-banded_solve_kernel(int m, int s, int kpow, const double* __restrict__ Linv_all, const double* __restrict__ Lsub_all,
-                    double* __restrict__ U) {
-  __shared__ double T[WS][LP];
-  __shared__ double SL[WS][LP];   // Lsub
-  __shared__ double SY[WS][LP];   // neighbouring block of Y
-  __shared__ double SI[WS][LP];   // Linv
-  const int tid = threadIdx.x;
-  const int nt = blockDim.x;
-  const int c = tid % s;
-  const int g = tid / s;
-  const int G = nt / s;
-  const bool act = g < G;
-  const int ss = s * s;
-  const int64_t ms = (int64_t)m * s;
-  for (int64_t q = tid; q < ms * s; q += nt) U[q] = ((q / s) == (q % s)) ? 1.0 : 0.0;
-  __syncthreads();
-  for (int rep = 0; rep < kpow; ++rep) {
-    for (int dir = 0; dir < 2; ++dir) {
-      for (int jj = 0; jj < m; ++jj) {
-        const int j = dir == 0 ? jj : m - 1 - jj;
-        double* Y = U + (int64_t)j * ss;
-        const bool has_nb = dir == 0 ? (j > 0) : (j + 1 < m);
-        const double* Ls = Lsub_all + (int64_t)(dir == 0 ? j - 1 : j) * ss;
-        const double* Yn = U + (int64_t)(dir == 0 ? j - 1 : j + 1) * ss;
-        const double* Li = Linv_all + (int64_t)j * ss;
-        for (int i = g; i < s; i += G) {
-          if (!act) break;
-          SI[i][c] = Li[i * s + c];
-          T[i][c] = Y[i * s + c];
-          if (has_nb) {
-            SL[i][c] = Ls[i * s + c];
-            SY[i][c] = Yn[i * s + c];
-          }
-        }
-        __syncthreads();
-        if (act && has_nb) {
-          for (int i = g; i < s; i += G) {
-            double a0 = 0.0, a1 = 0.0;
-            if (dir == 0) {          // T -= Lsub_{j-1} Z_{j-1}
-              for (int l = 0; l + 1 < s; l += 2) {
-                a0 += SL[i][l] * SY[l][c];
-                a1 += SL[i][l + 1] * SY[l + 1][c];
-              }
-              if (s & 1) a0 += SL[i][s - 1] * SY[s - 1][c];
-            } else {                 // T -= Lsub_j^T X_{j+1}
-              for (int l = 0; l + 1 < s; l += 2) {
-                a0 += SL[l][i] * SY[l][c];
-                a1 += SL[l + 1][i] * SY[l + 1][c];
-              }
-              if (s & 1) a0 += SL[s - 1][i] * SY[s - 1][c];
-            }
-            T[i][c] -= a0 + a1;
-          }
-        }
-        __syncthreads();
-        if (act) {
-          for (int i = g; i < s; i += G) {
-            double a0 = 0.0, a1 = 0.0;
-            if (dir == 0) {          // Z_j = Linv_j T
-              int l = 0;
-              for (; l + 1 <= i; l += 2) {
-                a0 += SI[i][l] * T[l][c];
-                a1 += SI[i][l + 1] * T[l + 1][c];
-              }
-              if (l <= i) a0 += SI[i][l] * T[l][c];
-            } else {                 // X_j = Linv_j^T T
-              int l = i;
-              for (; l + 1 < s; l += 2) {
-                a0 += SI[l][i] * T[l][c];
-                a1 += SI[l + 1][i] * T[l + 1][c];
-              }
-              if (l < s) a0 += SI[l][i] * T[l][c];
-            }
-            Y[i * s + c] = a0 + a1;
-          }
-        }
-        __syncthreads();
-      }
-    }
-  }
-}
 
 }  // namespace gk
 
@@ -1124,8 +1365,7 @@ void launch_banded_spline_reg(int m, int s, const double* Hd, const double* Bd, 
   double* Lsub = work + m * ss;
   hipLaunchKernelGGL(banded_factor_blk_kernel, dim3(1), dim3(ST), 0, st, m, s, Hd, Bd, eps, Linv, Lsub, bad);
   GK_HIP(hipGetLastError());
-  int nt = (1024 / s) * s;
-  hipLaunchKernelGGL(banded_solve_kernel, dim3(1), dim3(nt), 0, st, m, s, k, Linv, Lsub, U);
+  hipLaunchKernelGGL(banded_solve_kernel, dim3(1), dim3(ST), 0, st, m, s, k, Linv, Lsub, U);
   GK_HIP(hipGetLastError());
 }
 
