@@ -28,6 +28,30 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
+# Roof of each kernel class: (bound, peak, unit, source file).  Peaks are the
+# MI355X datasheet figures: HBM3E 8 TB/s, FP64 vector and FP64 matrix
+# 78.6 TFLOP/s, FP32 matrix 157.3 TFLOP/s (dense).
+ROOFS = {
+    "spmm_diff": ("hbm", HBM_PEAK_GBS, "GB/s", "spmm.hip"),
+    "reduce_parts": ("hbm", HBM_PEAK_GBS, "GB/s", "ortho.hip"),
+    "panel_gramv": ("mfma", 78.6, "TFLOP/s", "panel.hip"),
+    "panel_update_self": ("mfma", 78.6, "TFLOP/s", "panel.hip"),
+    "panel_apply_self": ("mfma", 78.6, "TFLOP/s", "panel.hip"),
+    "panel_apply_write": ("mfma", 78.6, "TFLOP/s", "panel.hip"),
+    "panel_self": ("mfma", 78.6, "TFLOP/s", "panel.hip"),
+    "arch_gram": ("mfma", 157.3, "TFLOP/s", "arch.hip"),
+    "arch_update": ("mfma", 157.3, "TFLOP/s", "arch.hip"),
+    "gram": ("alu", 78.6, "TFLOP/s", "ortho.hip"),
+    "tsgemm": ("alu", 78.6, "TFLOP/s", "ortho.hip"),
+    "assemble": ("alu", 78.6, "TFLOP/s", "ortho.hip"),
+    "cholqr": ("alu", 78.6, "TFLOP/s", "small.hip"),
+    "omega": ("alu", 78.6, "TFLOP/s", "small.hip"),
+    "banded_factor": ("alu", 78.6, "TFLOP/s", "small.hip"),
+    "banded_solve": ("alu", 78.6, "TFLOP/s", "small.hip"),
+    "cheb_step": ("alu", 78.6, "TFLOP/s", "small.hip"),
+    "jacobi_eig": ("alu", 78.6, "TFLOP/s", "small.hip"),
+}
+
 
 def _kernel_hash(files):
     h = hashlib.sha256()
@@ -37,10 +61,10 @@ def _kernel_hash(files):
     return h.hexdigest()[:16]
 
 
-def _traffic_from_profile(kernel_file: str, src_hash: str):
-    """HBM bytes per launch of the SpMM kernel from a committed rocprofv3
-    --pmc summary, only if it was taken on the current kernel source."""
-    p = os.path.join(ROOT, "profiles", kernel_file)
+def _traffic_from_profile(kernel: str, workload: str, src_hash: str):
+    """HBM bytes per launch of a kernel from a committed rocprofv3 --pmc
+    summary, only if it was taken on the current kernel source."""
+    p = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.txt")
     if not os.path.exists(p):
         return None
     vals = {}
@@ -55,6 +79,15 @@ def _traffic_from_profile(kernel_file: str, src_hash: str):
         return float(vals["hbm_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
+
+
+def _achieved(k):
+    bound, peak, unit, _ = ROOFS.get(k["name"], ("alu", 78.6, "TFLOP/s", ""))
+    t = k["total_ms"] * 1e-3
+    if t <= 0:
+        return bound, peak, unit, 0.0
+    a = k["alg_bytes"] / t / 1e9 if unit == "GB/s" else k["alg_flops"] / t / 1e12
+    return bound, peak, unit, a
 
 
 def cpu_baseline(L, W, phi, m, s_sample: int):
@@ -86,8 +119,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="rgg100k_spline")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-sample", type=int, default=8)
+    ap.add_argument("--cpu-sample", type=int, default=24)
     ap.add_argument("--reorder", type=int, default=1)
+    ap.add_argument("--counters", action="store_true",
+                    help="for hardware-counter runs: one mixed step, then a 1 GiB device-to-device copy of "
+                         "known size (calibration of the byte counters); prints no benchmark line")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); multi-GPU sharding is not built",
@@ -126,27 +162,54 @@ def main():
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / steps
 
+    if args.counters:
+        step("mixed")
+        torch.cuda.synchronize()
+        nbytes = 1 << 30
+        x = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"counters_run": True, "copy_bytes": nbytes}), flush=True)
+        return
+
     ms_mixed = timed("mixed", args.steps, args.warmup)
     ms_fp64 = timed("fp64", max(2, args.steps // 2), 1)
     P_m = out["mixed"].cpu().numpy()
     P_d = out["fp64"].cpu().numpy()
     err = float(np.linalg.norm(P_m - P_d) / np.linalg.norm(P_d))
 
-    # per-phase device times of one mixed step (HIP events inside the library,
-    # on the stream the kernels run on)
-    st = gk.Stats()
-    p, keep = gk.make_phi(phi)
-    step("mixed", gk.TIMING)
-    torch.cuda.synchronize()
-    _, _, st = gk.krylov_kernel_columns(g, Wd, phi, m, "cbl", "mixed", flags=gk.IO_DEVICE | gk.TIMING,
-                                        out_cols=out["mixed"], out_kww=kout["mixed"])
-    stats = st.as_dict()
-    n_spmm = max(stats["spmm_launches"], 1)
-    spmm_ms = stats["t_spmm_ms"] / n_spmm
-    spmm_bytes = stats["bytes_spmm"] / n_spmm
-    spmm_gbs = spmm_bytes / (spmm_ms * 1e-3) / 1e9
-    src_hash = _kernel_hash(["spmm.hip"])
-    traffic = _traffic_from_profile("spmm_rgg100k_s64_traffic.txt", src_hash)
+    # per-phase and per-kernel device times of the mixed step, from HIP events
+    # the library records on the stream the kernels run on (same K steps)
+    agg = {}
+    stats = None
+    for _ in range(args.steps):
+        _, _, st = gk.krylov_kernel_columns(g, Wd, phi, m, "cbl", "mixed", flags=gk.IO_DEVICE | gk.TIMING,
+                                            out_cols=out["mixed"], out_kww=kout["mixed"])
+        d = st.as_dict()
+        if stats is not None:
+            for f in ("t_spmm_ms", "t_orth_ms", "t_reorth_ms", "t_phi_ms", "t_asm_ms", "t_total_ms"):
+                d[f] += stats[f]
+        stats = d
+        for k in gk.kernel_timings():
+            if k["launches"] == 0:
+                continue
+            a_ = agg.setdefault(k["name"], dict(name=k["name"], launches=0, total_ms=0.0, alg_bytes=0.0,
+                                                alg_flops=0.0))
+            for f in ("launches", "total_ms", "alg_bytes", "alg_flops"):
+                a_[f] += k[f]
+    K = float(args.steps)
+    kernels = {}
+    for name, k in sorted(agg.items(), key=lambda kv: -kv[1]["total_ms"]):
+        bound, peak, unit, ach = _achieved(k)
+        kernels[name] = {"launches_per_step": k["launches"] / K, "ms_per_step": k["total_ms"] / K,
+                         "avg_launch_us": 1e3 * k["total_ms"] / k["launches"], "bound": bound,
+                         "achieved": ach, "unit": unit, "frac": ach / peak}
+    dom = max(agg.values(), key=lambda k: k["total_ms"])
+    bound, peak, unit, ach = _achieved(dom)
+    src = ROOFS.get(dom["name"], (None, None, None, "small.hip"))[3]
+    traffic = _traffic_from_profile(dom["name"], "rgg100k_s64", _kernel_hash([src]))
     value = s / (ms_mixed * 1e-3)
     res = {
         "metric": "kernel cols/s at 1e-5 rel err vs FP64 path",
@@ -166,14 +229,17 @@ def main():
         "rel_err_vs_fp64_path": err,
         "fp64_path": {"ms_per_step": ms_fp64, "cols_per_s": s / (ms_fp64 * 1e-3),
                       "speedup_mixed_over_fp64": ms_fp64 / ms_mixed},
-        "phase_ms": {k: stats[k] for k in ("t_spmm_ms", "t_orth_ms", "t_reorth_ms", "t_phi_ms", "t_asm_ms",
-                                           "t_total_ms")},
+        "phase_ms": {k: stats[k] / K for k in ("t_spmm_ms", "t_orth_ms", "t_reorth_ms", "t_phi_ms", "t_asm_ms",
+                                               "t_total_ms")},
         "phi_method": stats["phi_method"],
         "mixed_reorth_steps": stats["n_reorth"],
         "mixed_orth_estimate": stats["orth_est"],
-        "roofline": {"kernel": "spmm_diff_kernel", "bound": "hbm", "achieved": spmm_gbs,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": spmm_gbs / HBM_PEAK_GBS,
-                     "traffic": traffic, "avg_launch_ms": spmm_ms, "alg_bytes_per_launch": spmm_bytes},
+        "roofline": {"kernel": dom["name"], "bound": bound, "achieved": ach, "peak": peak, "unit": unit,
+                     "frac": ach / peak, "traffic": traffic,
+                     "avg_launch_ms": dom["total_ms"] / dom["launches"],
+                     "alg_bytes_per_launch": dom["alg_bytes"] / dom["launches"],
+                     "alg_flops_per_launch": dom["alg_flops"] / dom["launches"]},
+        "kernels": kernels,
     }
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(L, W, phi, m, args.cpu_sample)

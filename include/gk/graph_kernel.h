@@ -23,8 +23,8 @@
  *     are device pointers on the current HIP device; otherwise host pointers.
  *   - Work is enqueued on the stream installed with gk_set_stream (default:
  *     the null stream of the current device).  Calls return after the
- *     results are complete (host outputs) or enqueued (device outputs: the
- *     caller synchronises the stream).
+ *     results are complete, for host and device outputs alike (the call
+ *     synchronises that stream before returning).
  *   - Results are deterministic: for fixed inputs, precision and flags the
  *     outputs are bitwise identical from run to run, alone or while other
  *     requests run (no atomics in any reduction; fixed reduction order).
@@ -237,6 +237,23 @@ int gk_set_allocator(void* (*alloc_fn)(size_t bytes, void* ctx), void (*free_fn)
 int gk_set_stream(void* hip_stream);
 /* Library version string. */
 const char* gk_version(void);
+
+/* Per-kernel device times of the calling thread's most recent call made with
+ * GK_TIMING: one record per kernel class (SpMM, each orthogonalisation pass,
+ * archive projection, small factorisations, phi evaluation, assembly), each
+ * with its launch count, summed time between HIP events recorded on the
+ * call's stream around the launches, and the algorithmic bytes and flops of
+ * those launches (operand sizes of the method, not hardware counters).
+ * Writes min(cap, *count) records to `out` and the number of classes to
+ * *count.  Returns GK_EINVAL for a NULL count or a NULL out with cap > 0. */
+typedef struct {
+  char name[32];
+  int64_t launches;
+  double total_ms;
+  double alg_bytes;
+  double alg_flops;
+} gk_kernel_timing;
+int gk_kernel_timings(gk_kernel_timing* out, int32_t cap, int32_t* count);
 
 #ifdef __cplusplus
 }

@@ -7,9 +7,9 @@
 // The orthonormality of the Krylov basis assumed in Sec. 3 (and used by
 // Theorem 3.1) is restored by this projection.  Coefficients only need the
 // accuracy of the archive itself (unit roundoff 2^-24 relative to |Q||X|), so
-// the products run as v_mfma_f32_16x16x4f32 with float accumulation inside a
-// workgroup's row range; partial sums are reduced in float64 in a fixed order
-// (bitwise reproducible, no atomics).
+// the products run as v_mfma_f32_16x16x4f32 with float accumulation over short
+// row runs that are added into float64; partial sums are reduced in float64 in
+// a fixed order (bitwise reproducible, no atomics).
 //
 // v_mfma_f32_16x16x4f32 operand layout (lane l of 64, i = l % 16, k = l / 16):
 //   A (16 x 4):  lane l holds A[i][k]
@@ -26,16 +26,22 @@ __device__ __forceinline__ f4 mfma32(float a, float b, f4 c) {
 }
 
 // ------------------------------------------------------------- Gram C = Q^T X
-// Workgroup = 8 wavefronts; wavefront w owns archive block j = 8 bx + w and
-// accumulates C_j over the row range of blockIdx.y.  X rows are staged in LDS
-// as float (shared by the 8 wavefronts); Q rows stream from memory straight
-// into MFMA operands: lane (i, k) of a 4-row step loads the NT consecutive
-// floats Q_j[r + k][NT i .. NT i + NT - 1], so operand e (< NT) covers the
-// archive columns {NT i + e}.
-constexpr int AG_WAVES = 8;
+// Workgroup = 16 wavefronts; wavefront w owns column tile t = w % NT of
+// archive block j = (16 / NT) bx + w / NT and accumulates C_j[:, 16t .. 16t+15]
+// over the row range of blockIdx.y.  X rows are staged in LDS as float
+// (shared by all wavefronts); Q rows stream from memory straight into MFMA
+// operands: lane (i, k) of a 4-row step loads the NT consecutive floats
+// Q_j[r + k][NT i .. NT i + NT - 1], so operand e (< NT) covers the archive
+// columns {NT i + e}.  The float MFMA accumulators are added into float64
+// registers every 32 rows, which keeps the accumulation error of C at the
+// level of a 32-term float sum.
+constexpr int AG_WAVES = 16;
 constexpr int AG_THREADS = 64 * AG_WAVES;
 constexpr int AG_SUB = 64;        // rows staged per LDS round
-constexpr int AG_TARGET_WG = 512; // two workgroups per compute unit
+constexpr int AG_FLUSH = 8;       // 4-row steps between float64 flushes
+constexpr int AG_TARGET_WG = 256; // one workgroup per compute unit
+
+constexpr int ag_blocks(int nt) { return AG_WAVES / nt; }
 
 template <int NT>
 __device__ __forceinline__ void load_row_seg(const float* __restrict__ p, float (&a)[NT]) {
@@ -52,26 +58,31 @@ __device__ __forceinline__ void load_row_seg(const float* __restrict__ p, float 
 }
 
 template <int NT>
-__global__ void __launch_bounds__(AG_THREADS, 2)
+__global__ void __launch_bounds__(AG_THREADS, 1)
 arch_gram_kernel(int64_t n, const float* __restrict__ Q, int64_t qstride, int nb, const double* __restrict__ X,
-                 float* __restrict__ part, int64_t rpc, const int* __restrict__ flag) {
+                 double* __restrict__ part, int64_t rpc, const int* __restrict__ flag) {
   if (flag && *flag == 0) return;
   constexpr int LD = 16 * NT;
   constexpr int P = LD + 16;                 // LDS pitch (floats)
+  constexpr int BPW = ag_blocks(NT);
   __shared__ float sX[AG_SUB * P];
   const int tid = threadIdx.x;
   const int w = tid >> 6, l = tid & 63, li = l & 15, lk = l >> 4;
-  const int j = blockIdx.x * AG_WAVES + w;
-  const bool active = j < nb;
+  const int wb = w / NT, t = w - wb * NT;
+  const int j = blockIdx.x * BPW + wb;
+  const bool active = wb < BPW && j < nb;
   const float* Qj = Q + (int64_t)(active ? j : 0) * qstride;
   const int64_t rb = (int64_t)blockIdx.y * rpc;
   const int64_t re = min(n, rb + rpc);
 
-  f4 acc[NT][NT];
+  f4 acc[NT];
+  double a64[NT][4];
 #pragma unroll
-  for (int e = 0; e < NT; ++e)
+  for (int e = 0; e < NT; ++e) {
+    acc[e] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int t = 0; t < NT; ++t) acc[e][t] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int r = 0; r < 4; ++r) a64[e][r] = 0.0;
+  }
 
   for (int64_t r0 = rb; r0 < re; r0 += AG_SUB) {
     for (int q = tid; q < AG_SUB * LD; q += AG_THREADS) {
@@ -81,55 +92,40 @@ arch_gram_kernel(int64_t n, const float* __restrict__ Q, int64_t qstride, int nb
     }
     __syncthreads();
     if (active) {
-#pragma unroll 4
-      for (int s4 = 0; s4 < AG_SUB / 4; ++s4) {
-        const int64_t r = r0 + 4 * s4 + lk;
-        float a[NT];
-        if (r < re) load_row_seg<NT>(Qj + r * LD + NT * li, a);
-        else {
 #pragma unroll
-          for (int e = 0; e < NT; ++e) a[e] = 0.f;
+      for (int h = 0; h < AG_SUB / (4 * AG_FLUSH); ++h) {
+#pragma unroll
+        for (int s8 = 0; s8 < AG_FLUSH; ++s8) {
+          const int s4 = h * AG_FLUSH + s8;
+          const int64_t r = r0 + 4 * s4 + lk;
+          float a[NT];
+          if (r < re) load_row_seg<NT>(Qj + r * LD + NT * li, a);
+          else {
+#pragma unroll
+            for (int e = 0; e < NT; ++e) a[e] = 0.f;
+          }
+          const float b = sX[(4 * s4 + lk) * P + 16 * t + li];
+#pragma unroll
+          for (int e = 0; e < NT; ++e) acc[e] = mfma32(a[e], b, acc[e]);
         }
-        float b[NT];
 #pragma unroll
-        for (int t = 0; t < NT; ++t) b[t] = sX[(4 * s4 + lk) * P + 16 * t + li];
+        for (int e = 0; e < NT; ++e) {
 #pragma unroll
-        for (int e = 0; e < NT; ++e)
-#pragma unroll
-          for (int t = 0; t < NT; ++t) acc[e][t] = mfma32(a[e], b[t], acc[e][t]);
+          for (int q = 0; q < 4; ++q) a64[e][q] += (double)acc[e][q];
+          acc[e] = f4{0.f, 0.f, 0.f, 0.f};
+        }
       }
     }
     __syncthreads();
   }
   if (active) {
-    // D_{e,t}[4k + r][i] = C_j[NT (4k + r) + e][16 t + i]
-    float* P0 = part + ((int64_t)blockIdx.y * nb + j) * LD * LD;
+    // D_e[4k + r][i] = C_j[NT (4k + r) + e][16 t + i]
+    double* P0 = part + ((int64_t)blockIdx.y * nb + j) * LD * LD;
 #pragma unroll
     for (int e = 0; e < NT; ++e)
 #pragma unroll
-      for (int t = 0; t < NT; ++t)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) P0[(NT * (4 * lk + r) + e) * LD + 16 * t + li] = acc[e][t][r];
+      for (int r = 0; r < 4; ++r) P0[(NT * (4 * lk + r) + e) * LD + 16 * t + li] = a64[e][r];
   }
-}
-
-// out[i] = sum_c part[c * len + i] in float64, chunks added in index order.
-__global__ void __launch_bounds__(256)
-reduce_f32_parts_kernel(int64_t len, int nparts, const float* __restrict__ part, double* __restrict__ out,
-                        const int* __restrict__ flag) {
-  if (flag && *flag == 0) return;
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= len) return;
-  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-  int c = 0;
-  for (; c + 4 <= nparts; c += 4) {
-    s0 += (double)part[(int64_t)c * len + i];
-    s1 += (double)part[(int64_t)(c + 1) * len + i];
-    s2 += (double)part[(int64_t)(c + 2) * len + i];
-    s3 += (double)part[(int64_t)(c + 3) * len + i];
-  }
-  for (; c < nparts; ++c) s0 += (double)part[(int64_t)c * len + i];
-  out[i] = (s0 + s1) + (s2 + s3);
 }
 
 // ---------------------------------------------------------- update X -= Q C
@@ -229,9 +225,10 @@ arch_update_kernel(int64_t n, const float* __restrict__ Q, int64_t qstride, int 
 // ------------------------------------------------------------------ launchers
 bool arch_ok(int ld) { return ld == 16 || ld == 32 || ld == 48 || ld == 64; }
 
-static void arch_gram_geometry(int64_t n, int nb, int* ngroups, int* nchunks, int64_t* rpc) {
-  *ngroups = (nb + AG_WAVES - 1) / AG_WAVES;
-  int64_t want = (AG_TARGET_WG + *ngroups - 1) / *ngroups;
+static void arch_gram_geometry(int64_t n, int nb, int ld, int* ngroups, int* nchunks, int64_t* rpc) {
+  const int bpw = ag_blocks(ld / 16);
+  *ngroups = (nb + bpw - 1) / bpw;
+  int64_t want = AG_TARGET_WG / *ngroups;    // at most one round of workgroups
   const int64_t maxc = (n + AG_SUB - 1) / AG_SUB;
   if (want > maxc) want = maxc;
   if (want < 1) want = 1;
@@ -241,38 +238,42 @@ static void arch_gram_geometry(int64_t n, int nb, int* ngroups, int* nchunks, in
   *nchunks = (int)((n + r - 1) / r);
 }
 
-size_t arch_scratch_floats(int64_t n, int nb_max, int ld) {
+size_t arch_scratch_elems(int64_t n, int nb_max, int ld) {
   size_t mx = 0;
   for (int nb = 1; nb <= nb_max; ++nb) {
     int ng, nc;
     int64_t rpc;
-    arch_gram_geometry(n, nb, &ng, &nc, &rpc);
+    arch_gram_geometry(n, nb, ld, &ng, &nc, &rpc);
     mx = std::max(mx, (size_t)nc * nb * ld * ld);
   }
   return mx;
 }
 
 template <int NT>
-static void arch_launch(int64_t n, BlockList A, double* X, double* C, float* part, const int* flag, hipStream_t st) {
+static void arch_launch(int64_t n, BlockList A, double* X, double* C, double* part, const int* flag, hipStream_t st) {
   const float* Q = static_cast<const float*>(A.base);
   int ng, nc;
   int64_t rpc;
-  arch_gram_geometry(n, A.nb, &ng, &nc, &rpc);
+  arch_gram_geometry(n, A.nb, 16 * NT, &ng, &nc, &rpc);
+  const double qb = 4.0 * (double)n * 16 * NT * A.nb, xb = 8.0 * (double)n * 16 * NT;
+  const double fl = 2.0 * (double)n * 16 * NT * 16 * NT * A.nb;
+  kt_begin(KC_ARCH_GRAM, st);
   hipLaunchKernelGGL(arch_gram_kernel<NT>, dim3(ng, nc), dim3(AG_THREADS), 0, st, n, Q, A.stride, A.nb,
                      (const double*)X, part, rpc, flag);
   GK_HIP(hipGetLastError());
+  kt_end(st, qb + xb, fl);
   const int64_t len = (int64_t)A.nb * 16 * NT * 16 * NT;
-  hipLaunchKernelGGL(reduce_f32_parts_kernel, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, st, len, nc,
-                     (const float*)part, C, flag);
-  GK_HIP(hipGetLastError());
+  launch_reduce_parts(len, nc, part, C, flag, st);
+  kt_begin(KC_ARCH_UPDATE, st);
   hipLaunchKernelGGL(arch_update_kernel<NT>, dim3((unsigned)((n + AU_ROWS - 1) / AU_ROWS)), dim3(256), 0, st, n, Q,
                      A.stride, A.nb, (const double*)C, X, flag);
   GK_HIP(hipGetLastError());
+  kt_end(st, qb + 2.0 * xb, fl);
 }
 
 // One projection X -= Q (Q^T X) against the float32 archive A (A.f32, A.stride
 // > 0, blocks n x ld row-major).  C receives the nb*ld x ld coefficients.
-void launch_arch_reorth(int64_t n, int ld, BlockList A, double* X, double* C, float* part, const int* flag,
+void launch_arch_reorth(int64_t n, int ld, BlockList A, double* X, double* C, double* part, const int* flag,
                         hipStream_t st) {
   GK_REQUIRE(A.f32 && A.stride > 0 && A.nb >= 1, GK_EUNSUPPORTED, "archive projection needs a float32 archive");
   switch (ld) {

@@ -185,8 +185,8 @@ enum { PM_GRAMV = 0, PM_UPDATE_SELF = 1, PM_APPLY_SELF = 2, PM_APPLY_WRITE = 3, 
 bool panel_ok(int ld);
 // arch.hip -- projection against the float32 archive on FP32 matrix cores
 bool arch_ok(int ld);
-size_t arch_scratch_floats(int64_t n, int nb_max, int ld);
-void launch_arch_reorth(int64_t n, int ld, BlockList A, double* X, double* C, float* part, const int* flag,
+size_t arch_scratch_elems(int64_t n, int nb_max, int ld);
+void launch_arch_reorth(int64_t n, int ld, BlockList A, double* X, double* C, double* part, const int* flag,
                         hipStream_t st);
 size_t panel_scratch_elems(int64_t n, int ld);
 void launch_panel(int mode, int64_t n, int ld, int nbv, const double* X, double* Xout, float* X32,
@@ -227,5 +227,19 @@ struct PhaseTimer {
   ~PhaseTimer();
 };
 enum Phase { PH_SPMM = 0, PH_ORTH, PH_REORTH, PH_PHI, PH_ASM, PH_FIT, PH_TOTAL };
+
+// Per-kernel timing of timed calls (GK_TIMING): launchers bracket their main
+// kernel with kt_begin / kt_end (events on the launch stream) and state the
+// algorithmic bytes and flops of that launch.  kt_start / kt_finish bracket a
+// call on the calling thread; gk_kernel_timings returns the aggregate.
+enum KernelClass {
+  KC_SPMM = 0, KC_PANEL_GRAMV, KC_PANEL_UPDATE_SELF, KC_PANEL_APPLY_SELF, KC_PANEL_APPLY_WRITE, KC_PANEL_SELF,
+  KC_GRAM, KC_TSGEMM, KC_ARCH_GRAM, KC_ARCH_UPDATE, KC_REDUCE, KC_CHOLQR, KC_OMEGA, KC_BANDED_FACTOR,
+  KC_BANDED_SOLVE, KC_CHEB, KC_EIG, KC_ASSEMBLE, KC_COUNT
+};
+void kt_start(bool on);
+void kt_finish();
+void kt_begin(int cls, hipStream_t st);
+void kt_end(hipStream_t st, double bytes, double flops);
 
 }  // namespace gk

@@ -372,7 +372,7 @@ static void run_cbl(Job& J) {
   int* forced = nullptr;
   size_t pe_all = 0;
   double* part_all = nullptr;
-  float* part32 = nullptr;
+  double* part_arch = nullptr;
   if (pro) {
     for (int i = 0; i < 3; ++i) {
       Wr[i] = J.ar.get<double>((size_t)m * s * s);
@@ -382,7 +382,7 @@ static void run_cbl(Job& J) {
     fr = J.ar.get<int>(m);
     forced = J.ar.get<int>(m + 1);
     launch_zero(forced, sizeof(int) * (m + 1), st);
-    if (arch_ok(ld)) part32 = J.ar.get<float>(arch_scratch_floats(n, m, ld));
+    if (arch_ok(ld)) part_arch = J.ar.get<double>(arch_scratch_elems(n, m, ld));
     else {
       for (int nb = 1; nb <= m; ++nb) pe_all = std::max(pe_all, gram_scratch_elems(n, nb, ld));
       part_all = J.ar.get<double>(pe_all);
@@ -462,8 +462,8 @@ static void run_cbl(Job& J) {
         // the float32 archive.
         J.tm.begin(PH_REORTH);
         BlockList all{Va, blk, k + 1, true};
-        if (part32) {
-          launch_arch_reorth(n, ld, all, X, C, part32, fk, st);
+        if (part_arch) {
+          launch_arch_reorth(n, ld, all, X, C, part_arch, fk, st);
         } else {
           launch_gram(n, ld, all, X, C, part_all, fk, st);
           launch_tsgemm(n, ld, all, C, X, X, nullptr, -1.0, 1.0, fk, st);
@@ -686,7 +686,7 @@ uint64_t footprint_bytes(int64_t n, int s, int m, int variant, int precision) {
         // partial reorthogonalisation: estimate blocks and archive partials
         b += 3.0 * m * s * s * 8.0;
         if (arch_ok(ld)) {
-          b += 4.0 * arch_scratch_floats(n, m, ld);
+          b += 8.0 * arch_scratch_elems(n, m, ld);
         } else {
           size_t pa = 0;
           for (int nb = 1; nb <= m; ++nb) pa = std::max(pa, gram_scratch_elems(n, nb, ld));
@@ -750,6 +750,7 @@ int run_call(const CallArgs& a, hipStream_t stream) {
   J.st = stream;
   J.tm.on = (a.flags & GK_TIMING) != 0;
   J.tm.st = stream;
+  kt_start(J.tm.on);
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   if (J.tm.on) {
     GK_HIP(hipEventCreate(&ev0));
@@ -844,6 +845,7 @@ int run_call(const CallArgs& a, hipStream_t stream) {
                           dev_io ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, stream));
   }
   GK_HIP(hipStreamSynchronize(stream));
+  kt_finish();
   if (a.st) {
     std::memset(a.st, 0, sizeof(gk_stats));
     J.tm.collect(a.st);
@@ -859,9 +861,6 @@ int run_call(const CallArgs& a, hipStream_t stream) {
     a.st->n_reorth = (J.variant <= GK_SBL && (!J.mixed() || (J.flags & GK_FULL_REORTH))) ? std::max(J.m - 1, 0)
                                                                                        : hflags[3];
     a.st->orth_est = hscal[1];
-    const int ldv = J.ld;
-    const int slots = ldv <= 128 ? ldv / 2 : (ldv <= 256 ? ldv / 4 : ldv / 8);
-    (void)slots;
     const double wb = g->unit ? 0.0 : (J.mixed() ? 4.0 : 8.0);
     a.st->bytes_spmm = a.st->spmm_launches * (4.0 * (n + 1) + g->nnz * (4.0 + wb) + 8.0 * n + 2.0 * 8.0 * n * ld);
   }

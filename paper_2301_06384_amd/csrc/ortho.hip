@@ -106,9 +106,11 @@ reduce_parts_kernel(int64_t len, int nparts, const double* __restrict__ part, do
 }
 
 void launch_reduce_parts(int64_t len, int nparts, const double* part, double* out, const int* flag, hipStream_t st) {
+  kt_begin(KC_REDUCE, st);
   hipLaunchKernelGGL(reduce_parts_kernel, dim3((unsigned)((len + 15) / 16)), dim3(256), 0, st, len, nparts, part, out,
                      flag);
   GK_HIP(hipGetLastError());
+  kt_end(st, 8.0 * (double)len * (nparts + 1), (double)len * nparts);
 }
 
 static void gram_geometry(int64_t n, int nb, int ld, int* nx, int* ny, int* nch, int64_t* rpc) {
@@ -139,6 +141,7 @@ void launch_gram(int64_t n, int ld, BlockList A, const double* B, double* C, dou
   int64_t rpc;
   gram_geometry(n, A.nb, ld, &nx, &ny, &nch, &rpc);
   dim3 grid(nx, ny, nch);
+  kt_begin(KC_GRAM, st);
   if (A.f32)
     hipLaunchKernelGGL(gram_kernel<true>, grid, dim3(256), 0, st, n, ld, A.base, A.stride, A.nb, B,
                        part, rpc, flag);
@@ -146,6 +149,7 @@ void launch_gram(int64_t n, int ld, BlockList A, const double* B, double* C, dou
     hipLaunchKernelGGL(gram_kernel<false>, grid, dim3(256), 0, st, n, ld, A.base, A.stride, A.nb, B,
                        part, rpc, flag);
   GK_HIP(hipGetLastError());
+  kt_end(st, (double)n * ld * ((A.f32 ? 4.0 : 8.0) * A.nb + 8.0), 2.0 * (double)n * ld * ld * A.nb);
   launch_reduce_parts((int64_t)A.nb * ld * ld, nch, part, C, flag, st);
 }
 
@@ -243,6 +247,7 @@ tsgemm_kernel(int64_t n, int ld, int ncols, const void* __restrict__ Abase, int6
 void launch_tsgemm(int64_t n, int ld, BlockList A, const double* C, const double* in, double* out,
                    float* out32, double alpha, double beta, const int* flag, hipStream_t st) {
   dim3 grid((unsigned)((n + T_TR - 1) / T_TR), (ld + T_TB - 1) / T_TB);
+  kt_begin(KC_TSGEMM, st);
   if (A.f32)
     hipLaunchKernelGGL((tsgemm_kernel<true, false>), grid, dim3(256), 0, st, n, ld, ld, A.base, A.stride,
                        A.nb, C, ld, in, out, out32, alpha, beta, (int64_t)ld, (const int64_t*)nullptr,
@@ -252,11 +257,14 @@ void launch_tsgemm(int64_t n, int ld, BlockList A, const double* C, const double
                        A.stride, A.nb, C, ld, in, out, out32, alpha, beta, (int64_t)ld,
                        (const int64_t*)nullptr, flag);
   GK_HIP(hipGetLastError());
+  kt_end(st, (double)n * ld * ((A.f32 ? 4.0 : 8.0) * A.nb + (beta != 0.0 ? 16.0 : 8.0) + (out32 ? 4.0 : 0.0)),
+         2.0 * (double)n * ld * ld * A.nb);
 }
 
 void launch_assemble(int64_t n, int ld, int s, BlockList A, const double* U, int ldu, double* P,
                      const int64_t* perm, hipStream_t st) {
   dim3 grid((unsigned)((n + T_TR - 1) / T_TR), (s + T_TB - 1) / T_TB);
+  kt_begin(KC_ASSEMBLE, st);
   if (A.f32)
     hipLaunchKernelGGL((tsgemm_kernel<true, true>), grid, dim3(256), 0, st, n, ld, s, A.base, A.stride,
                        A.nb, U, ldu, (const double*)nullptr, P, (float*)nullptr, 1.0, 0.0, n, perm,
@@ -266,6 +274,7 @@ void launch_assemble(int64_t n, int ld, int s, BlockList A, const double* U, int
                        A.nb, U, ldu, (const double*)nullptr, P, (float*)nullptr, 1.0, 0.0, n, perm,
                        (const int*)nullptr);
   GK_HIP(hipGetLastError());
+  kt_end(st, (double)n * ((A.f32 ? 4.0 : 8.0) * ld * A.nb + 8.0 * s), 2.0 * (double)n * ld * s * A.nb);
 }
 
 // ------------------------------------------------- column-wise operations

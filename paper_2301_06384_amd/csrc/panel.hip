@@ -278,6 +278,19 @@ void launch_panel(int mode, int64_t n, int ld, int nbv, const double* X, double*
   PanelArgs a{n, X, Xout, X32, V0, V1, Cupd, Rm, part, flag};
   const int grid = panel_grid(n);
   const PanelMode pm = (PanelMode)mode;
+  // algorithmic bytes / flops of the pass (block = n x ld float64)
+  const double blk = 8.0 * (double)n * ld, nl2 = (double)n * ld * ld, self = (double)n * ld * (ld + 1);
+  static const int kc[5] = {KC_PANEL_GRAMV, KC_PANEL_UPDATE_SELF, KC_PANEL_APPLY_SELF, KC_PANEL_APPLY_WRITE,
+                            KC_PANEL_SELF};
+  double kb = 0, kf = 0;
+  switch (pm) {
+    case PM_GRAMV: kb = blk * (1 + nbv); kf = 2.0 * nl2 * nbv; break;
+    case PM_UPDATE_SELF: kb = blk * (2 + nbv); kf = 2.0 * nl2 * nbv + self; break;
+    case PM_APPLY_SELF: kb = blk; kf = 2.0 * self; break;
+    case PM_APPLY_WRITE: kb = blk * (X32 ? 2.5 : 2.0); kf = self; break;
+    case PM_SELF: kb = blk; kf = self; break;
+  }
+  kt_begin(kc[pm], st);
   switch (ld) {
     case 16: panel_dispatch<1>(pm, nbv, a, grid, st); break;
     case 32: panel_dispatch<2>(pm, nbv, a, grid, st); break;
@@ -285,6 +298,7 @@ void launch_panel(int mode, int64_t n, int ld, int nbv, const double* X, double*
     case 64: panel_dispatch<4>(pm, nbv, a, grid, st); break;
     default: throw Error{GK_EUNSUPPORTED, "panel kernel needs ld in {16,32,48,64}"};
   }
+  kt_end(st, kb, kf);
   int ngb = 0;
   if (pm == PM_GRAMV) ngb = nbv;
   if (pm == PM_UPDATE_SELF || pm == PM_APPLY_SELF || pm == PM_SELF) ngb = 1;

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstring>
 #include <map>
 
 #include "gk_internal.h"
@@ -154,6 +155,81 @@ void PhaseTimer::collect(gk_stats* s) {
   s->t_total_ms = t[PH_TOTAL];
   s->spmm_launches = nspmm;
 }
+// ------------------------------------------------------------ kernel timer
+namespace {
+const char* const kKernelClassName[KC_COUNT] = {
+    "spmm_diff",          "panel_gramv",     "panel_update_self", "panel_apply_self", "panel_apply_write",
+    "panel_self",         "gram",            "tsgemm",            "arch_gram",        "arch_update",
+    "reduce_parts",       "cholqr",          "omega",             "banded_factor",    "banded_solve",
+    "cheb_step",          "jacobi_eig",      "assemble"};
+struct KtRec {
+  int cls;
+  hipEvent_t a, b;
+  double bytes, flops;
+};
+struct KtState {
+  bool on = false;
+  std::vector<KtRec> recs;
+  int cur = -1;
+  hipEvent_t cur_a = nullptr;
+  gk_kernel_timing agg[KC_COUNT];
+  int nagg = 0;
+};
+thread_local KtState t_kt;
+}  // namespace
+
+void kt_start(bool on) {
+  for (auto& r : t_kt.recs) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  if (t_kt.cur_a) (void)hipEventDestroy(t_kt.cur_a);
+  t_kt.cur_a = nullptr;
+  t_kt.on = on;
+  t_kt.recs.clear();
+  t_kt.cur = -1;
+}
+void kt_begin(int cls, hipStream_t st) {
+  if (!t_kt.on) return;
+  hipEvent_t a;
+  GK_HIP(hipEventCreate(&a));
+  GK_HIP(hipEventRecord(a, st));
+  t_kt.cur = cls;
+  t_kt.cur_a = a;
+}
+void kt_end(hipStream_t st, double bytes, double flops) {
+  if (!t_kt.on || t_kt.cur < 0) return;
+  hipEvent_t b;
+  GK_HIP(hipEventCreate(&b));
+  GK_HIP(hipEventRecord(b, st));
+  t_kt.recs.push_back({t_kt.cur, t_kt.cur_a, b, bytes, flops});
+  t_kt.cur = -1;
+  t_kt.cur_a = nullptr;
+}
+void kt_finish() {
+  if (!t_kt.on) return;
+  for (int c = 0; c < KC_COUNT; ++c) {
+    gk_kernel_timing& g = t_kt.agg[c];
+    std::memset(&g, 0, sizeof(g));
+    std::strncpy(g.name, kKernelClassName[c], sizeof(g.name) - 1);
+  }
+  for (auto& r : t_kt.recs) {
+    float ms = 0.f;
+    if (hipEventSynchronize(r.b) == hipSuccess && hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+      gk_kernel_timing& g = t_kt.agg[r.cls];
+      g.launches += 1;
+      g.total_ms += ms;
+      g.alg_bytes += r.bytes;
+      g.alg_flops += r.flops;
+    }
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  t_kt.recs.clear();
+  t_kt.nagg = KC_COUNT;
+  t_kt.on = false;
+}
+
 PhaseTimer::~PhaseTimer() {
   for (auto& e : ev) {
     (void)hipEventDestroy(e.second.first);
@@ -203,3 +279,12 @@ int gk_set_stream(void* hip_stream) {
 const char* gk_version(void) { return "gk 0.1 gfx950"; }
 
 }  // extern "C"
+
+extern "C" int gk_kernel_timings(gk_kernel_timing* out, int32_t cap, int32_t* count) {
+  using namespace gk;
+  if (!count || cap < 0 || (cap > 0 && !out)) return GK_EINVAL;
+  const int n = std::min<int>(cap, t_kt.nagg);
+  for (int i = 0; i < n; ++i) out[i] = t_kt.agg[i];
+  *count = t_kt.nagg;
+  return GK_OK;
+}

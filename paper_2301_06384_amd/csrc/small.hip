@@ -90,9 +90,11 @@ cholqr_factor_kernel(const double* __restrict__ G, int ld, int s, int pass,
 void launch_cholqr_factor(const double* G, int ld, int s, int pass, const double* diag_prev, double thr,
                           double* W, double* R, double* Rinv, double* diag_out, int* n_defl,
                           hipStream_t st) {
+  kt_begin(KC_CHOLQR, st);
   hipLaunchKernelGGL(cholqr_factor_kernel, dim3(1), dim3(SB), 0, st, G, ld, s, pass, diag_prev, thr, W, R,
                      Rinv, diag_out, n_defl);
   GK_HIP(hipGetLastError());
+  kt_end(st, 8.0 * 4 * ld * ld, (double)s * s * s);
 }
 
 // ------------------------------------------------------------ small GEMM
@@ -286,9 +288,11 @@ jacobi_eig_kernel(int n, double* __restrict__ Abase, int lda, double* __restrict
 void launch_sym_eig(int n, double* A, int lda, double* V, int ldv, double* theta, int batch,
                     int64_t strideA, int64_t strideV, int64_t strideTheta, int* order_ws, double* cs_ws,
                     hipStream_t st) {
+  kt_begin(KC_EIG, st);
   hipLaunchKernelGGL(jacobi_eig_kernel, dim3(batch), dim3(SB), 0, st, n, A, lda, V, ldv, theta, strideA,
                      strideV, strideTheta, order_ws, cs_ws);
   GK_HIP(hipGetLastError());
+  kt_end(st, 16.0 * batch * (double)n * n, 10.0 * batch * (double)n * n * n);
 }
 
 size_t eig_order_elems(int n, int batch) { return (size_t)(((n + 1) & ~1)) * batch; }
@@ -532,9 +536,11 @@ size_t banded_work_elems(int m, int s) { return (size_t)(2 * m + 1) * s * s; }
 void launch_banded_spline(int m, int s, const double* Hd, const double* Bd, double eps, int k, double* work,
                           double* U, int* bad, hipStream_t st) {
   const size_t ss = (size_t)s * s;
+  kt_begin(KC_BANDED_FACTOR, st);
   hipLaunchKernelGGL(banded_spline_kernel, dim3(1), dim3(SB), 0, st, m, s, Hd, Bd, eps, k, work,
                      work + m * ss, U, work + 2 * m * ss, bad);
   GK_HIP(hipGetLastError());
+  kt_end(st, 8.0 * 6 * m * (double)ss, (double)m * ss * s * (3.0 + 4.0 * k));
 }
 
 // ------------------------------------------------------------ s x s solve
@@ -748,10 +754,88 @@ __device__ __forceinline__ void chol_pivot(double piv, int gj, int s, double gjj
   }
 }
 
+typedef double dv4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ double readlane_d(double v, int lane) {
+  const unsigned long long u = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(u & 0xffffffffu), lane);
+  const int hi = __builtin_amdgcn_readlane((int)(u >> 32), lane);
+  return __longlong_as_double(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+
+// One pivot step J of the 16 x 16 diagonal-block factorisation by wavefront
+// 0.  Lane c (< 16) holds column c of the block (a, both triangles) and column
+// c of its inverse (y).  With symmetric storage lane c already holds
+// L[c][J] = a[J] / l_JJ; the column is exchanged through a 16-entry LDS
+// buffer (one write per lane, broadcast reads; the wavefront executes its LDS
+// accesses in order, so no barrier is involved).
+template <int MODE, int J>
+struct DiagStep {
+  __device__ __forceinline__ static void run(double (&a)[16], double (&y)[16], int c, int o, int s, const double* g0,
+                                             const double* dprev, double thr, int* bad, double* dg,
+                                             double* colbuf) {
+    const double piv = readlane_d(a[J], J);
+    const double gjj = (MODE == 1 && o + J < s) ? g0[o + J] : 0.0;
+    const double dpj = (MODE == 2 && o + J < s) ? dprev[o + J] : 0.0;
+    double ljj, inv;
+    chol_pivot<MODE>(piv, o + J, s, gjj, dpj, thr, bad, ljj, inv);
+    if (dg && threadIdx.x == 0) dg[o + J] = (o + J < s) ? ljj : 0.0;
+    const double lcj = a[J] * inv;     // L[c][J] (used for c > J)
+    if (threadIdx.x < 16) colbuf[c] = lcj;
+    if (c == J) {
+#pragma unroll
+      for (int r = J + 1; r < 16; ++r) a[r] *= inv;
+      a[J] = ljj;
+    }
+    y[J] *= inv;                       // row J of the inverse
+#pragma unroll
+    for (int r = J + 1; r < 16; ++r) {
+      const double lrj = colbuf[r];    // L[r][J]
+      if (c > J) a[r] -= lrj * lcj;
+      y[r] -= lrj * y[J];
+    }
+    DiagStep<MODE, J + 1>::run(a, y, c, o, s, g0, dprev, thr, bad, dg, colbuf);
+  }
+};
 template <int MODE>
-__device__ void blk_chol_inv_t(double (*A)[LP], double (*Y)[LP], double (*Z)[LP], int s, const double* g0,
+struct DiagStep<MODE, 16> {
+  __device__ __forceinline__ static void run(double (&)[16], double (&)[16], int, int, int, const double*,
+                                             const double*, double, int*, double*, double*) {}
+};
+
+// 16 x 16 tile product on FP64 matrix cores (v_mfma_f64_16x16x4f64, lane
+// l = i + 16 k holds A[i][k] and B[k][i]; register r holds D[4 r + k][i]):
+// acc += op(A) op(B) with op(A)[i][k] = TA ? A[ra + k][ca + i] : A[ra + i][ca + k]
+// and op(B)[k][j] = TB ? B[rb + j][cb + k] : B[rb + k][cb + j].
+template <bool TA, bool TB>
+__device__ __forceinline__ dv4 mma_tile(const double (*A)[LP], int ra, int ca, const double (*B)[LP], int rb, int cb,
+                                        dv4 acc) {
+  const int l = threadIdx.x & 63, i = l & 15, k = l >> 4;
+#pragma unroll
+  for (int ks = 0; ks < 4; ++ks) {
+    const int kk = 4 * ks + k;
+    const double av = TA ? A[ra + kk][ca + i] : A[ra + i][ca + kk];
+    const double bv = TB ? B[rb + i][cb + kk] : B[rb + kk][cb + i];
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+  }
+  return acc;
+}
+__device__ __forceinline__ dv4 tile_load(const double (*A)[LP], int r0, int c0) {
+  const int l = threadIdx.x & 63, i = l & 15, k = l >> 4;
+  return dv4{A[r0 + k][c0 + i], A[r0 + 4 + k][c0 + i], A[r0 + 8 + k][c0 + i], A[r0 + 12 + k][c0 + i]};
+}
+__device__ __forceinline__ void tile_store(double (*A)[LP], int r0, int c0, dv4 v) {
+  const int l = threadIdx.x & 63, i = l & 15, k = l >> 4;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) A[r0 + 4 * r + k][c0 + i] = v[r];
+}
+
+template <int MODE>
+__device__ __forceinline__ void blk_chol_inv_t(double (*A)[LP], double (*Y)[LP], double (*Z)[LP], int s, const double* g0,
                                const double* dprev, double thr, double* dg, int* bad) {
+  __shared__ double colbuf[16];
   const int tid = threadIdx.x;
+  const int wv = tid >> 6;
   const int nbk = (s + 15) >> 4;
   const int S16 = nbk << 4;
   // pad A with an identity block, Z = I, Y = 0
@@ -764,124 +848,64 @@ __device__ void blk_chol_inv_t(double (*A)[LP], double (*Y)[LP], double (*Z)[LP]
   __syncthreads();
   for (int b = 0; b < nbk; ++b) {
     const int o = 16 * b;
-    // ---- diagonal block: wavefront 0, lane (r = l % 16, columns 4 (l / 16) + q).
-    // Register arrays are only indexed by constants (selects below), so they
-    // stay in registers whether or not the column loop is unrolled.
+    const int T = nbk - 1 - b;                 // tile rows below the diagonal block
+    // ---- diagonal block: wavefront 0, lane c < 16 holds column c
     if (tid < 64) {
-      const int r = tid & 15, cg = tid >> 4;
-      double a0 = A[o + r][o + 4 * cg], a1 = A[o + r][o + 4 * cg + 1];
-      double a2 = A[o + r][o + 4 * cg + 2], a3 = A[o + r][o + 4 * cg + 3];
-      double y0 = (r == 4 * cg) ? 1.0 : 0.0, y1 = (r == 4 * cg + 1) ? 1.0 : 0.0;
-      double y2 = (r == 4 * cg + 2) ? 1.0 : 0.0, y3 = (r == 4 * cg + 3) ? 1.0 : 0.0;
-      const double gr = (MODE == 1 && o + r < s) ? g0[o + r] : 0.0;
-      const double dr = (MODE == 2 && o + r < s) ? dprev[o + r] : 0.0;
-      double myl = 0.0;
-      for (int j = 0; j < 16; ++j) {
-        const int own = j & 3, jg = j >> 2;
-        const double aj = own == 0 ? a0 : own == 1 ? a1 : own == 2 ? a2 : a3;   // A[r][4 cg + own]
-        const double gjj = __shfl(gr, j), dpj = __shfl(dr, j);
-        const double piv = __shfl(aj, j + 16 * jg);
-        double ljj, inv;
-        chol_pivot<MODE>(piv, o + j, s, gjj, dpj, thr, bad, ljj, inv);
-        if (r == j) myl = ljj;
-        double ajn = aj;
-        if (cg == jg) {
-          if (r > j) ajn = aj * inv;
-          if (r == j) ajn = ljj;
-        }
-        if (own == 0) a0 = ajn; else if (own == 1) a1 = ajn; else if (own == 2) a2 = ajn; else a3 = ajn;
-        if (r == j) {
-          y0 *= inv; y1 *= inv; y2 *= inv; y3 *= inv;
-        }
-        const double lrj = __shfl(ajn, r + 16 * jg);
-        const double lc0 = __shfl(ajn, 4 * cg + 16 * jg), lc1 = __shfl(ajn, 4 * cg + 1 + 16 * jg);
-        const double lc2 = __shfl(ajn, 4 * cg + 2 + 16 * jg), lc3 = __shfl(ajn, 4 * cg + 3 + 16 * jg);
-        const double yj0 = __shfl(y0, j + 16 * cg), yj1 = __shfl(y1, j + 16 * cg);
-        const double yj2 = __shfl(y2, j + 16 * cg), yj3 = __shfl(y3, j + 16 * cg);
-        if (r > j) {
-          const int c0 = 4 * cg;
-          if (c0 > j && c0 <= r) a0 -= lrj * lc0;
-          if (c0 + 1 > j && c0 + 1 <= r) a1 -= lrj * lc1;
-          if (c0 + 2 > j && c0 + 2 <= r) a2 -= lrj * lc2;
-          if (c0 + 3 > j && c0 + 3 <= r) a3 -= lrj * lc3;
-          y0 -= lrj * yj0; y1 -= lrj * yj1; y2 -= lrj * yj2; y3 -= lrj * yj3;
-        }
-      }
-      if (dg && tid < 16) dg[o + r] = (o + r < s) ? myl : 0.0;
-      const double av[4] = {a0, a1, a2, a3}, yv[4] = {y0, y1, y2, y3};
+      const int c = tid & 15;
+      double a[16], y[16];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int c = 4 * cg + q;
-        A[o + r][o + c] = (c <= r) ? av[q] : 0.0;
-        Z[o + r][o + c] = (c <= r) ? yv[q] : 0.0;   // Y_bb, kept in the diagonal block of Z
+      for (int r = 0; r < 16; ++r) {
+        a[r] = A[o + r][o + c];
+        y[r] = (r == c) ? 1.0 : 0.0;
+      }
+      DiagStep<MODE, 0>::run(a, y, c, o, s, g0, dprev, thr, bad, dg, colbuf);
+      if (tid < 16) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          A[o + r][o + c] = (r >= c) ? a[r] : 0.0;
+          Z[o + r][o + c] = (r >= c) ? y[r] : 0.0;   // Y_bb, kept in the diagonal block of Z
+          Y[o + r][o + c] = (r >= c) ? y[r] : 0.0;
+        }
       }
     }
     __syncthreads();
-    // ---- panel L_ib = A_ib Y_bb^T and Y_b = Y_bb Z_b, one element per thread
-    // and round; the in-place L_ib results are written after a barrier.
+    // ---- panel: L_ib = A_ib Y_bb^T (i > b, written after a barrier: in place)
+    //      and Y_b[:, c] = Y_bb Z_b[:, c] (c < b)
     {
-      const int prow = S16 - o - 16;              // rows below the diagonal block
-      const int npan = prow * 16;
-      const int ntot = npan + 16 * o;
-      constexpr int KMAX = (48 * 16 + 16 * 48 + ST - 1) / ST;
-      double res[KMAX];
-#pragma unroll
-      for (int k = 0; k < KMAX; ++k) {
-        const int q = tid + k * ST;
-        res[k] = 0.0;
-        if (q < npan) {
-          const int r = o + 16 + (q >> 4), c = q & 15;
-          double acc = 0.0;
-#pragma unroll
-          for (int t = 0; t < 16; ++t)
-            if (t <= c) acc = fma(A[r][o + t], Z[o + c][o + t], acc);
-          res[k] = acc;
-        } else if (q < ntot) {
-          // Y_b[r][c] = sum_t Y_bb[r][t] Z[o + t][c] for the columns c < o
-          const int qq = q - npan;
-          const int r = qq / o, c = qq - r * o;
-          double acc = 0.0;
-#pragma unroll
-          for (int t = 0; t < 16; ++t)
-            if (t <= r) acc = fma(Z[o + r][o + t], Z[o + t][c], acc);
-          Y[o + r][c] = acc;
-        }
+      dv4 res = dv4{0.0, 0.0, 0.0, 0.0};
+      const int task = wv;                     // at most 3 panel tiles + 3 inverse tiles
+      const int ntask = T + b;
+      dv4 res2 = dv4{0.0, 0.0, 0.0, 0.0};
+      if (task < ntask) {
+        if (task < T) res = mma_tile<false, true>(A, o + 16 * (1 + task), o, Z, o, o, res);
+        else tile_store(Y, o, 16 * (task - T), mma_tile<false, false>(Z, o, o, Z, o, 16 * (task - T), res));
       }
-      // diagonal block of Y
-      for (int q = tid; q < 256; q += ST) {
-        const int r = q >> 4, c = q & 15;
-        Y[o + r][o + c] = (c <= r) ? Z[o + r][o + c] : 0.0;
+      if (task + 4 < ntask) {
+        const int t2 = task + 4;
+        if (t2 < T) res2 = mma_tile<false, true>(A, o + 16 * (1 + t2), o, Z, o, o, res2);
+        else tile_store(Y, o, 16 * (t2 - T), mma_tile<false, false>(Z, o, o, Z, o, 16 * (t2 - T), res2));
       }
       __syncthreads();
-#pragma unroll
-      for (int k = 0; k < KMAX; ++k) {
-        const int q = tid + k * ST;
-        if (q < npan) A[o + 16 + (q >> 4)][o + (q & 15)] = res[k];
-      }
+      if (task < T) tile_store(A, o + 16 * (1 + task), o, res);
+      if (task + 4 < T) tile_store(A, o + 16 * (1 + task + 4), o, res2);
     }
     __syncthreads();
-    // ---- trailing updates: A_ij -= L_ib L_jb^T (lower), Z_i -= L_ib Y_b
+    // ---- trailing: A_ij -= L_ib L_jb^T (b < j <= i), Z_i[:, c] -= L_ib Y_b[:, c] (c <= b)
     {
-      const int t0 = o + 16;
-      const int nt = S16 - t0;
-      const int na = nt * nt;
-      const int nz = nt * t0;
-      for (int q = tid; q < na + nz; q += ST) {
-        if (q < na) {
-          const int r = t0 + q / nt, c = t0 + q % nt;
-          if (c <= r) {
-            double acc = A[r][c];
-#pragma unroll
-            for (int t = 0; t < 16; ++t) acc = fma(-A[r][o + t], A[c][o + t], acc);
-            A[r][c] = acc;
-          }
+      const int na = T * (T + 1) / 2;
+      const int nz = T * (b + 1);
+      for (int task = wv; task < na + nz; task += 4) {
+        if (task < na) {
+          int ii = 0, rem = task;
+          while (rem > ii) { rem -= ii + 1; ++ii; }
+          const int ti = b + 1 + ii, tj = b + 1 + rem;     // tile (ti, tj), tj <= ti
+          const dv4 p = mma_tile<false, true>(A, 16 * ti, o, A, 16 * tj, o, dv4{0.0, 0.0, 0.0, 0.0});
+          tile_store(A, 16 * ti, 16 * tj, tile_load(A, 16 * ti, 16 * tj) - p);
         } else {
-          const int qq = q - na;
-          const int r = t0 + qq / t0, c = qq % t0;
-          double acc = Z[r][c];
-#pragma unroll
-          for (int t = 0; t < 16; ++t) acc = fma(-A[r][o + t], Y[o + t][c], acc);
-          Z[r][c] = acc;
+          const int q = task - na;
+          const int ti = b + 1 + q / (b + 1), tc = q % (b + 1);
+          const dv4 p = mma_tile<false, false>(A, 16 * ti, o, Y, o, 16 * tc, dv4{0.0, 0.0, 0.0, 0.0});
+          tile_store(Z, 16 * ti, 16 * tc, tile_load(Z, 16 * ti, 16 * tc) - p);
         }
       }
     }
@@ -894,7 +918,7 @@ __device__ void blk_chol_inv_t(double (*A)[LP], double (*Y)[LP], double (*Z)[LP]
   __syncthreads();
 }
 
-__device__ void blk_chol_inv(double (*A)[LP], double (*Y)[LP], double (*Z)[LP], int s, int mode, const double* g0,
+__device__ __forceinline__ void blk_chol_inv(double (*A)[LP], double (*Y)[LP], double (*Z)[LP], int s, int mode, const double* g0,
                              const double* dprev, double thr, double* dg, int* bad) {
   if (mode == 0) blk_chol_inv_t<0>(A, Y, Z, s, g0, dprev, thr, dg, bad);
   else if (mode == 1) blk_chol_inv_t<1>(A, Y, Z, s, g0, dprev, thr, dg, bad);
@@ -1332,17 +1356,21 @@ bool small_wave_ok(int ld) { return ld <= WS; }
 void launch_cholqr_reg(const double* G, int ld, int s, int pass, const double* diag_prev, double thr, double* R,
                        double* Rinv, double* diag_out, int* n_defl, const double* R1, const double* R1inv, double* Rc,
                        double* Bout, hipStream_t st) {
+  kt_begin(KC_CHOLQR, st);
   hipLaunchKernelGGL(cholqr_blk_kernel, dim3(1), dim3(ST), 0, st, G, ld, s, pass, diag_prev, thr, R, Rinv, diag_out,
                      n_defl, R1, R1inv, Rc, Bout, (const int*)nullptr);
   GK_HIP(hipGetLastError());
+  kt_end(st, 8.0 * 4 * ld * ld, (double)s * s * s);
 }
 
 void launch_cholqr_flag(const double* G, int ld, int s, int pass, const double* diag_prev, double thr, double* R,
                         double* Rinv, double* diag_out, int* n_defl, const double* R1, const double* R1inv, double* Rc,
                         double* Bout, const int* flag, hipStream_t st) {
+  kt_begin(KC_CHOLQR, st);
   hipLaunchKernelGGL(cholqr_blk_kernel, dim3(1), dim3(ST), 0, st, G, ld, s, pass, diag_prev, thr, R, Rinv, diag_out,
                      n_defl, R1, R1inv, Rc, Bout, flag);
   GK_HIP(hipGetLastError());
+  kt_end(st, 8.0 * 4 * ld * ld, (double)s * s * s);
 }
 
 void launch_omega(int k, int s, int ld, const double* Wk, const double* Wkm1, double* Wk1, const double* Hd,
@@ -1350,8 +1378,10 @@ void launch_omega(int k, int s, int ld, const double* Wk, const double* Wkm1, do
                   double* est_part, int* fr, int* forced, double* est_out, int* nre, hipStream_t st) {
   const int nj = k - 1;   // recurrence for j <= k-2
   if (nj > 0) {
+    kt_begin(KC_OMEGA, st);
     hipLaunchKernelGGL(omega_kernel, dim3(nj), dim3(ST), 0, st, k, s, ld, Wk, Wkm1, Wk1, Hd, Bd, Rc, nu, est_part);
     GK_HIP(hipGetLastError());
+    kt_end(st, 8.0 * 10 * nj * (double)s * s, 12.0 * nj * (double)s * s * s);
   }
   hipLaunchKernelGGL(omega_decide_kernel, dim3(1), dim3(ST), 0, st, k, s, nj > 0 ? nj : 0, est_part, tau, floor_re,
                      floor_loc, Wk1, fr, forced, est_out, nre);
@@ -1363,10 +1393,14 @@ void launch_banded_spline_reg(int m, int s, const double* Hd, const double* Bd, 
   const size_t ss = (size_t)s * s;
   double* Linv = work;
   double* Lsub = work + m * ss;
+  kt_begin(KC_BANDED_FACTOR, st);
   hipLaunchKernelGGL(banded_factor_blk_kernel, dim3(1), dim3(ST), 0, st, m, s, Hd, Bd, eps, Linv, Lsub, bad);
   GK_HIP(hipGetLastError());
+  kt_end(st, 8.0 * 4 * m * (double)ss, (double)m * ss * s * (2.0 + 1.0 / 3.0 + 1.0));
+  kt_begin(KC_BANDED_SOLVE, st);
   hipLaunchKernelGGL(banded_solve_kernel, dim3(1), dim3(ST), 0, st, m, s, k, Linv, Lsub, U);
   GK_HIP(hipGetLastError());
+  kt_end(st, 8.0 * 4 * 2 * k * m * (double)ss, 4.0 * 2 * k * m * (double)ss * s);
 }
 
 }  // namespace gk
@@ -1436,13 +1470,18 @@ void launch_cheb_diffusion(int m, int s, const double* Hd, const double* Bd, dou
   if (deg < 1) return;
   double* Y[3] = {Y0, Y1, Y2};
   // T_1: out = Y - (2/Lam) H Y
+  const double cb = 8.0 * 6 * (double)m * s * s, cf = 2.0 * 3 * (double)m * s * s * s;
+  kt_begin(KC_CHEB, st);
   hipLaunchKernelGGL(btd_cheb_step_kernel, dim3(nb), dim3(256), 0, st, m, s, Hd, Bd, Y[0], (const double*)nullptr,
                      Y[1], -2.0 / Lam, 1.0, 0.0, U, coef, 1);
   GK_HIP(hipGetLastError());
+  kt_end(st, cb, cf);
   for (int k = 1; k < deg; ++k) {
+    kt_begin(KC_CHEB, st);
     hipLaunchKernelGGL(btd_cheb_step_kernel, dim3(nb), dim3(256), 0, st, m, s, Hd, Bd, Y[k % 3], Y[(k - 1) % 3],
                        Y[(k + 1) % 3], -4.0 / Lam, 2.0, -1.0, U, coef, k + 1);
     GK_HIP(hipGetLastError());
+    kt_end(st, cb, cf);
   }
 }
 

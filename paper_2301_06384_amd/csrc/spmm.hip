@@ -138,6 +138,10 @@ static void spmm_dispatch_w(const gk_graph* g, bool fp32w, int ld, const double*
 void launch_spmm(const gk_graph* g, bool fp32_weights, int ld, const double* V, const double* Vprev,
                  double* out, double a, double b, double gmul, double* acc, double e, const double* e_dev,
                  hipStream_t st) {
+  // algorithmic traffic: CSR structure, weights, diagonal, V (and V_prev) in, out
+  const double wb = g->unit ? 0.0 : (fp32_weights ? 4.0 : 8.0);
+  const double vb = 8.0 * (double)g->n * ld;
+  kt_begin(KC_SPMM, st);
   // lanes per row: at most 64 (one wavefront), VPT doubles each
   if (ld <= 128) {
     spmm_dispatch_w<2>(g, fp32_weights, ld, V, Vprev, out, a, b, gmul, acc, e, e_dev, st);
@@ -147,6 +151,8 @@ void launch_spmm(const gk_graph* g, bool fp32_weights, int ld, const double* V, 
     // ld is a multiple of 16; 8 doubles per lane
     spmm_dispatch_w<8>(g, fp32_weights, ld, V, Vprev, out, a, b, gmul, acc, e, e_dev, st);
   }
+  kt_end(st, 4.0 * (g->n + 1) + (double)g->nnz * (4.0 + wb) + 8.0 * g->n + vb * (Vprev ? 3.0 : 2.0),
+         2.0 * ((double)g->nnz + g->n) * ld);
 }
 
 }  // namespace gk

@@ -96,10 +96,28 @@ _ALLOC_T = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
 _FREE_T = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
 _lib.gk_set_allocator.argtypes = [_ALLOC_T, _FREE_T, C.c_void_p]
 
+class KernelTiming(C.Structure):
+    _fields_ = [("name", C.c_char * 32), ("launches", C.c_int64), ("total_ms", C.c_double),
+                ("alg_bytes", C.c_double), ("alg_flops", C.c_double)]
+
+
+_lib.gk_kernel_timings.argtypes = [C.POINTER(KernelTiming), C.c_int32, C.POINTER(C.c_int32)]
+_lib.gk_kernel_timings.restype = C.c_int
+
 EXPORTED = ["graph_kernel_init", "graph_kernel_release", "gk_graph_info", "krylov_kernel_columns",
             "kernel_machine_fit_predict", "gk_request_footprint", "gk_serve_start", "gk_submit", "gk_poll",
             "gk_serve_stop", "gk_strerror", "gk_last_error_detail", "gk_set_allocator", "gk_set_stream",
-            "gk_version"]
+            "gk_version", "gk_kernel_timings"]
+
+
+def kernel_timings() -> list:
+    """Per-kernel-class device times of this thread's last call made with TIMING."""
+    cnt = C.c_int32(0)
+    _check(_lib.gk_kernel_timings(None, 0, C.byref(cnt)), "gk_kernel_timings")
+    arr = (KernelTiming * max(cnt.value, 1))()
+    _check(_lib.gk_kernel_timings(arr, cnt.value, C.byref(cnt)), "gk_kernel_timings")
+    return [dict(name=r.name.decode(), launches=int(r.launches), total_ms=float(r.total_ms),
+                 alg_bytes=float(r.alg_bytes), alg_flops=float(r.alg_flops)) for r in arr[:cnt.value]]
 
 
 def _check(rc: int, where: str):
