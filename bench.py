@@ -112,6 +112,62 @@ def cpu_baseline(L, W, phi, m, s_sample: int):
                        f"products single-threaded)")
 
 
+def serving_bench(gk, I, n_req: int, seed: int = 0, max_active: int = 8, n_streams: int = 8):
+    """Serving workload: 8 resident random geometric graphs (N 10k..500k),
+    requests with s ~ U{4..128}, diffusion or spline kernels, m = 30, cbl,
+    mixed precision, fit + predict on all N nodes.  A closed-loop warm-up
+    measures the saturated throughput; the timed stream has Poisson arrivals
+    at 0.7 x that rate.  Latency = completion - scheduled arrival."""
+    t_gen = time.perf_counter()
+    pool = I.serving_pool()
+    graphs = [gk.Graph.from_laplacian(L, flags=gk.REORDER) for L in pool]
+    sizes = [L.n for L in pool]
+    t_gen = time.perf_counter() - t_gen
+    srv = gk.Server(max_active=max_active, hbm_budget=0, n_streams=n_streams)
+    try:
+        warm = I.serving_requests(min(64, n_req), sizes, seed=seed + 1)
+        t0 = time.perf_counter()
+        tk = [srv.submit(graphs[r["graph"]], r["samples"], r["y"], r["phi"], r["m"], r["gamma"]) for r in warm]
+        for t in tk:
+            res = srv.poll(t, -1)
+            if res["status"] != 0:
+                raise RuntimeError(f"warm-up request failed with status {res['status']}")
+        sat = len(warm) / (time.perf_counter() - t0)
+        lam = 0.7 * sat
+        reqs = I.serving_requests(n_req, sizes, seed=seed)
+        arrivals = np.cumsum(np.random.default_rng(seed + 2).exponential(1.0 / lam, n_req))
+        start = time.perf_counter()
+        subs = []
+        for r, ta in zip(reqs, arrivals):
+            now = time.perf_counter() - start
+            if ta > now:
+                time.sleep(ta - now)
+            t_host = time.perf_counter() - start
+            subs.append((srv.submit(graphs[r["graph"]], r["samples"], r["y"], r["phi"], r["m"], r["gamma"]), ta,
+                         t_host))
+        lat, fails, done_at = [], 0, []
+        for ticket, ta, t_host in subs:
+            res = srv.poll(ticket, -1)
+            if res["status"] != 0:
+                fails += 1
+                continue
+            service = (res["t_complete_ms"] - res["t_submit_ms"]) * 1e-3
+            lat.append(service + (t_host - ta))
+            done_at.append(t_host + service)
+        span = max(done_at) - arrivals[0] if done_at else float("nan")
+    finally:
+        srv.stop()
+    lat = np.sort(np.asarray(lat))
+    return {"requests": n_req, "failed": fails, "graphs_n": sizes, "max_active": max_active,
+            "streams": n_streams, "saturated_req_per_s": sat, "arrival_rate_req_per_s": lam,
+            "throughput_req_per_s": len(lat) / span, "p50_ms": 1e3 * float(np.percentile(lat, 50)),
+            "p99_ms": 1e3 * float(np.percentile(lat, 99)), "mean_ms": 1e3 * float(lat.mean()),
+            "pool_build_s": t_gen,
+            "workload": "8 RGG 8-NN graphs N=10k..500k (seeds 100+i); s~U{4..128}; diffusion t~U[0.1,2] or "
+                        "spline eps~U[0.001,0.1] k=2; m=30; cbl mixed; gamma=1e-3; Poisson arrivals at 0.7x "
+                        "saturated closed-loop throughput"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -121,6 +177,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-sample", type=int, default=24)
     ap.add_argument("--reorder", type=int, default=1)
+    ap.add_argument("--serving-requests", type=int, default=512,
+                    help="requests of the serving leg (0 skips it)")
     ap.add_argument("--counters", action="store_true",
                     help="for hardware-counter runs: one mixed step, then a 1 GiB device-to-device copy of "
                          "known size (calibration of the byte counters); prints no benchmark line")
@@ -241,6 +299,8 @@ def main():
                      "alg_flops_per_launch": dom["alg_flops"] / dom["launches"]},
         "kernels": kernels,
     }
+    if args.serving_requests > 0:
+        res["serving"] = serving_bench(gk, I, args.serving_requests)
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(L, W, phi, m, args.cpu_sample)
     print(json.dumps(res), flush=True)

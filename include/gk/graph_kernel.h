@@ -50,7 +50,7 @@ typedef enum {
   GK_ERANGE = -5,        /* sample index outside [0, n) */
   GK_ENOMEM = -6,        /* request refused by HBM admission, or allocation failed */
   GK_ENOTSPD = -7,       /* kernel system (K_W + gamma I) not solvable (cbl: not SPD; gbl/sbl/cheb:
-                            singular), cf. Sec. 7.3 */
+                            singular), cf. Sec. 8.3 */
   GK_EDEVICE = -8,       /* HIP runtime error or no usable gfx950 device */
   GK_EUNSUPPORTED = -9,  /* combination not implemented */
   GK_EAGAIN = -10,       /* gk_poll: request not finished yet */

@@ -201,7 +201,7 @@ def fit_predict(L, samples, y, phi_spec, m: int, gamma: float, variant: str = "c
     cbl (Alg. 3): K = F_1^T phi(H_m) F_1 (Theorem 3.1: SPD), c from a Cholesky
     solve of (K + gamma I) c = y, prediction [Q_1..Q_m] phi(H_m) F_1 c
     (Corollary 1).  gbl / sbl: K = E_W^T P (symmetric but possibly indefinite,
-    resp. non-symmetric, Sec. 7.3), c from an LU solve, prediction P c.
+    resp. non-symmetric, Sec. 8.3), c from an LU solve, prediction P c.
     `gamma` is the full diagonal shift.
     Returns (c, yhat, K).
     """

@@ -236,6 +236,12 @@ struct Job {
   double* dscal = nullptr;        // [0] residual norm
   double* poly_dev = nullptr;
   bool mixed() const { return precision == GK_MIXED; }
+  // Full reorthogonalisation every step: always for GK_FP64, on request for
+  // GK_MIXED, and for GK_MIXED cbl blocks wider than 64 (the orthogonality
+  // estimate of partial reorthogonalisation is built for widths up to 64).
+  bool full_reorth() const {
+    return !mixed() || (flags & GK_FULL_REORTH) || (variant == GK_CBL && !small_wave_ok(ld));
+  }
   double thr() const { return 1e-12 * g->lambda_max; }
   // result of the Krylov stage
   BlockList arch;                 // archived basis (nb blocks)
@@ -296,7 +302,7 @@ static void phi_stage_block(Job& J, const double* Hd, const double* Bd, double* 
     J.phi_method = 2;
     return;
   }
-  // spectral decomposition H_m = S Theta S^T (Sec. 6, Table 1 row phi(H_m))
+  // spectral decomposition H_m = S Theta S^T (Sec. 7, Table 1 row phi(H_m))
   double* T = J.ar.get<double>((size_t)ms * ms);
   double* S = J.ar.get<double>((size_t)ms * ms);
   double* th = J.ar.get<double>(ms);
@@ -324,7 +330,7 @@ static void run_cbl(Job& J) {
   const int ld = J.ld, m = J.m, s = J.s;
   const int64_t blk = n * ld;
   const bool mixed = J.mixed();
-  const bool full = !mixed || (J.flags & GK_FULL_REORTH);
+  const bool full = J.full_reorth();
   const bool no_reorth = mixed && (J.flags & 0x10u);
   hipStream_t st = J.st;
   // storage
@@ -677,7 +683,7 @@ uint64_t footprint_bytes(int64_t n, int s, int m, int variant, int precision) {
     if (variant == GK_CBL) {
       b += 2 * ms * ms * 8.0 + (double)m * ld * ld * 8.0 + 4.0 * m * s * s * 8.0;
       // Gram partials of the orthogonalisation passes
-      const bool full = !mixed;
+      const bool full = !mixed || (variant == GK_CBL && !small_wave_ok(ld));
       size_t pe = 0;
       for (int nb = 1; nb <= (full ? m : 2); ++nb) pe = std::max(pe, gram_scratch_elems(n, nb, ld));
       b += 8.0 * pe;
@@ -858,7 +864,7 @@ int run_call(const CallArgs& a, hipStream_t stream) {
     a.st->resid_norm = hscal[0];
     a.st->phi_method = J.phi_method;
     a.st->footprint_bytes = J.ar.bytes;
-    a.st->n_reorth = (J.variant <= GK_SBL && (!J.mixed() || (J.flags & GK_FULL_REORTH))) ? std::max(J.m - 1, 0)
+    a.st->n_reorth = (J.variant <= GK_SBL && J.full_reorth()) ? std::max(J.m - 1, 0)
                                                                                        : hflags[3];
     a.st->orth_est = hscal[1];
     const double wb = g->unit ? 0.0 : (J.mixed() ? 4.0 : 8.0);

@@ -148,7 +148,7 @@ def test_banded_and_spectral_phi_agree():
 @pytest.mark.parametrize("t", [0.1, 1.0, 30.0])
 def test_chebyshev_and_spectral_phi_agree(t):
     # exp(-t H_m) F_1 by the Chebyshev series on [0, Lambda] vs by the
-    # spectral decomposition of H_m (Sec. 6): same result to rounding.
+    # spectral decomposition of H_m (Sec. 7): same result to rounding.
     L, g = G("ba1500")
     W = I.samples(L.n, 12, 4)
     phi = dict(kind="diffusion", t=t)
@@ -195,6 +195,20 @@ def test_block_widths(s):
     for prec in ("fp64", "mixed"):
         P, K, st = gk.krylov_kernel_columns(g, W, phi, 5, "cbl", prec)
         assert rel(P, ref) < TOL[prec], (prec, rel(P, ref))
+
+
+@pytest.mark.parametrize("s", [72, 100, 128])
+@pytest.mark.parametrize("phi", [dict(kind="spline", eps=0.02, k=2.0), dict(kind="diffusion", t=0.7)])
+def test_wide_blocks(s, phi):
+    # block widths above 64: generic orthogonalisation kernels, full
+    # reorthogonalisation in both precisions, global small factorisations
+    L, g = G("rgg2003")
+    W = I.samples(L.n, s, 90 + s)
+    ref = krylov.cbl(L.to_scipy(), W, phi, 10)["P"]
+    for prec in ("fp64", "mixed"):
+        P, K, st = gk.krylov_kernel_columns(g, W, phi, 10, "cbl", prec)
+        assert rel(P, ref) < TOL[prec], (prec, rel(P, ref))
+        assert st.n_reorth == 9
 
 
 def test_single_sample_variants_coincide_gpu():

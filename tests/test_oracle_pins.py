@@ -192,7 +192,7 @@ def test_scalar_variants_exact_at_full_degree(variant):
 
 
 def test_single_sample_all_lanczos_coincide():
-    # Sec. 7.1: with N = 1 the three Lanczos variants give the same approximant.
+    # Sec. 8.1: with N = 1 the three Lanczos variants give the same approximant.
     L = I.path(201).to_scipy()
     spec = dict(kind="spline", eps=0.001, k=2.0)
     a = krylov.cbl(L, [100], spec, 15)["P"]
@@ -202,7 +202,7 @@ def test_single_sample_all_lanczos_coincide():
 
 
 def _radius_graph_standin(seed=0):
-    # Synthetic stand-in for the paper's 900-point planar graph of Sec. 7.2
+    # Synthetic stand-in for the paper's 900-point planar graph of Sec. 8.2
     # (its dataset is not available): 900 uniform points, radius graph.
     from scipy.spatial import cKDTree
     pts = np.random.default_rng(seed).random((900, 2))
@@ -211,7 +211,7 @@ def _radius_graph_standin(seed=0):
 
 
 def test_collocation_matrix_structure():
-    # Theorem 3.1: cbl K_W SPD; Proposition 1: gbl K_W symmetric; Sec. 7.3:
+    # Theorem 3.1: cbl K_W SPD; Proposition 1: gbl K_W symmetric; Sec. 8.3:
     # gbl can be indefinite and sbl non-symmetric with complex eigenvalues.
     L = _radius_graph_standin()
     W = I.samples(900, 40, 1)
@@ -370,7 +370,7 @@ def test_chebyshev_polynomial_exactness_and_bound():
 
 def test_squared_chebyshev_is_psd():
     # Sec. 3.4.1: the squared interpolant is non-negative, so its sampled
-    # block is positive semi-definite (Sec. 7.3), unlike plain cheb.
+    # block is positive semi-definite (Sec. 8.3), unlike plain cheb.
     L = _radius_graph_standin()
     W = I.samples(900, 40, 1)
     spec = dict(kind="diffusion", t=1.0)
