@@ -112,6 +112,10 @@ def cpu_baseline(L, W, phi, m, s_sample: int):
                        f"products single-threaded)")
 
 
+def _progress(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def serving_bench(gk, I, n_req: int, seed: int = 0, max_active: int = 8, n_streams: int = 8):
     """Serving workload: 8 resident random geometric graphs (N 10k..500k),
     requests with s ~ U{4..128}, diffusion or spline kernels, m = 30, cbl,
@@ -134,6 +138,7 @@ def serving_bench(gk, I, n_req: int, seed: int = 0, max_active: int = 8, n_strea
                 raise RuntimeError(f"warm-up request failed with status {res['status']}")
         sat = len(warm) / (time.perf_counter() - t0)
         lam = 0.7 * sat
+        _progress(f"serving: saturated {sat:.2f} req/s, arrivals at {lam:.2f} req/s")
         reqs = I.serving_requests(n_req, sizes, seed=seed)
         arrivals = np.cumsum(np.random.default_rng(seed + 2).exponential(1.0 / lam, n_req))
         start = time.perf_counter()
@@ -143,8 +148,11 @@ def serving_bench(gk, I, n_req: int, seed: int = 0, max_active: int = 8, n_strea
             if ta > now:
                 time.sleep(ta - now)
             t_host = time.perf_counter() - start
+            if len(subs) % 64 == 63:
+                _progress(f"serving: {len(subs) + 1}/{n_req} submitted")
             subs.append((srv.submit(graphs[r["graph"]], r["samples"], r["y"], r["phi"], r["m"], r["gamma"]), ta,
                          t_host))
+        _progress(f"serving: {n_req} requests submitted")
         lat, fails, done_at = [], 0, []
         for ticket, ta, t_host in subs:
             res = srv.poll(ticket, -1)
@@ -175,7 +183,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="rgg100k_spline")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-sample", type=int, default=24)
+    ap.add_argument("--cpu-sample", type=int, default=64)
     ap.add_argument("--reorder", type=int, default=1)
     ap.add_argument("--serving-requests", type=int, default=512,
                     help="requests of the serving leg (0 skips it)")
@@ -232,12 +240,15 @@ def main():
         print(json.dumps({"counters_run": True, "copy_bytes": nbytes}), flush=True)
         return
 
+    _progress("timing the mixed path")
     ms_mixed = timed("mixed", args.steps, args.warmup)
+    _progress(f"mixed {ms_mixed:.2f} ms/step; timing the float64 path")
     ms_fp64 = timed("fp64", max(2, args.steps // 2), 1)
     P_m = out["mixed"].cpu().numpy()
     P_d = out["fp64"].cpu().numpy()
     err = float(np.linalg.norm(P_m - P_d) / np.linalg.norm(P_d))
 
+    _progress("per-kernel timing pass")
     # per-phase and per-kernel device times of the mixed step, from HIP events
     # the library records on the stream the kernels run on (same K steps)
     agg = {}
@@ -300,8 +311,10 @@ def main():
         "kernels": kernels,
     }
     if args.serving_requests > 0:
+        _progress("serving leg")
         res["serving"] = serving_bench(gk, I, args.serving_requests)
     if not args.no_cpu:
+        _progress("cpu baseline (oracle)")
         res["cpu_baseline"] = cpu_baseline(L, W, phi, m, args.cpu_sample)
     print(json.dumps(res), flush=True)
 
