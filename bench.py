@@ -303,6 +303,7 @@ def main():
         "phi_method": stats["phi_method"],
         "mixed_reorth_steps": stats["n_reorth"],
         "mixed_orth_estimate": stats["orth_est"],
+        "mixed_qr2_series_steps": stats["n_qr2_series"],
         "roofline": {"kernel": dom["name"], "bound": bound, "achieved": ach, "peak": peak, "unit": unit,
                      "frac": ach / peak, "traffic": traffic,
                      "avg_launch_ms": dom["total_ms"] / dom["launches"],

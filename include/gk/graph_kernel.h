@@ -121,7 +121,7 @@ typedef struct {
   int32_t n_reorth;       /* steps with reorthogonalisation against the stored basis */
   int32_t n_deflated;     /* basis columns deflated (rank-deficient QR) */
   int32_t phi_method;     /* 0 eigendecomposition, 1 banded Cholesky, 2 Chebyshev-on-H, 3 Horner */
-  int32_t reserved;
+  int32_t n_qr2_series;   /* second CholQR passes taken by the series expansion of chol(I + E) */
   uint64_t footprint_bytes; /* device bytes the call held */
 } gk_stats;
 

@@ -222,6 +222,111 @@ arch_update_kernel(int64_t n, const float* __restrict__ Q, int64_t qstride, int 
   }
 }
 
+// ------------------------------------------------------- assembly P = Q U
+// P[perm(r), c] = sum_j Q_j[r, :] U_j[:, c] for c < s (Alg. 1 output
+// [Q_1 .. Q_m] phi(H_m) F_1): float32 archive and coefficients rounded to
+// float on matrix cores, same operand scheme as the update kernel; the float
+// accumulators are added into float64 after every archive block.  Output
+// column-major n x s in caller node order (perm may be null).
+template <int NT>
+__global__ void __launch_bounds__(256, 2)
+arch_assemble_kernel(int64_t n, const float* __restrict__ Q, int64_t qstride, int nb, const double* __restrict__ U,
+                     int s, double* __restrict__ P, const int64_t* __restrict__ perm) {
+  constexpr int LD = 16 * NT;
+  constexpr int KQ = LD / 4;
+  constexpr int PC = LD + 4;
+  __shared__ float sC[2][LD * PC];
+  const int tid = threadIdx.x;
+  const int w = tid >> 6, l = tid & 63, li = l & 15, lk = l >> 4;
+  const int64_t R0 = (int64_t)blockIdx.x * AU_ROWS + 32 * w;
+
+  f4 acc[2][NT];
+  double a64[2][NT][4];
+#pragma unroll
+  for (int g = 0; g < 2; ++g)
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      acc[g][t] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int q = 0; q < 4; ++q) a64[g][t][q] = 0.0;
+    }
+
+  auto stage = [&](int jb, int buf) {
+    const double* Uj = U + (int64_t)jb * LD * s;
+    for (int q = tid; q < LD * LD; q += 256) {
+      const int a = q / LD, b = q - a * LD;
+      sC[buf][a * PC + b] = (b < s) ? (float)Uj[(int64_t)a * s + b] : 0.f;
+    }
+  };
+  auto load_q = [&](int jb, float (&qv)[2][KQ]) {
+    const float* Qj = Q + (int64_t)jb * qstride;
+#pragma unroll
+    for (int g = 0; g < 2; ++g) {
+      const int64_t r = R0 + 16 * g + li;
+      if (r < n) {
+#pragma unroll
+        for (int v = 0; v < KQ / 4; ++v) {
+          const f4 x = *reinterpret_cast<const f4*>(Qj + r * LD + lk * KQ + 4 * v);
+          qv[g][4 * v] = x[0]; qv[g][4 * v + 1] = x[1]; qv[g][4 * v + 2] = x[2]; qv[g][4 * v + 3] = x[3];
+        }
+      } else {
+#pragma unroll
+        for (int e = 0; e < KQ; ++e) qv[g][e] = 0.f;
+      }
+    }
+  };
+
+  float qcur[2][KQ];
+  stage(0, 0);
+  load_q(0, qcur);
+  __syncthreads();
+  for (int jb = 0; jb < nb; ++jb) {
+    const int buf = jb & 1;
+    if (jb + 1 < nb) stage(jb + 1, buf ^ 1);
+    float qnext[2][KQ];
+    if (jb + 1 < nb) load_q(jb + 1, qnext);
+    const float* sc = sC[buf];
+#pragma unroll
+    for (int e = 0; e < KQ; ++e) {
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const float cv = sc[(lk * KQ + e) * PC + 16 * t + li];
+#pragma unroll
+        for (int g = 0; g < 2; ++g) acc[g][t] = mfma32(cv, qcur[g][e], acc[g][t]);
+      }
+    }
+#pragma unroll
+    for (int g = 0; g < 2; ++g)
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) a64[g][t][q] += (double)acc[g][t][q];
+        acc[g][t] = f4{0.f, 0.f, 0.f, 0.f};
+      }
+    __syncthreads();
+    if (jb + 1 < nb) {
+#pragma unroll
+      for (int g = 0; g < 2; ++g)
+#pragma unroll
+        for (int e = 0; e < KQ; ++e) qcur[g][e] = qnext[g][e];
+    }
+  }
+  // D_{g,t}[4k + r][i] = P[row 16 g + i][16 t + 4 k + r]
+#pragma unroll
+  for (int g = 0; g < 2; ++g) {
+    const int64_t r = R0 + 16 * g + li;
+    if (r >= n) continue;
+    const int64_t orow = perm ? perm[r] : r;
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int c = 16 * t + 4 * lk + q;
+        if (c < s) P[(int64_t)c * n + orow] = a64[g][t][q];
+      }
+  }
+}
+
 // ------------------------------------------------------------------ launchers
 bool arch_ok(int ld) { return ld == 16 || ld == 32 || ld == 48 || ld == 64; }
 
@@ -261,14 +366,14 @@ static void arch_launch(int64_t n, BlockList A, double* X, double* C, double* pa
   hipLaunchKernelGGL(arch_gram_kernel<NT>, dim3(ng, nc), dim3(AG_THREADS), 0, st, n, Q, A.stride, A.nb,
                      (const double*)X, part, rpc, flag);
   GK_HIP(hipGetLastError());
-  kt_end(st, qb + xb, fl);
+  kt_end(st, qb + xb, fl, flag);
   const int64_t len = (int64_t)A.nb * 16 * NT * 16 * NT;
   launch_reduce_parts(len, nc, part, C, flag, st);
   kt_begin(KC_ARCH_UPDATE, st);
   hipLaunchKernelGGL(arch_update_kernel<NT>, dim3((unsigned)((n + AU_ROWS - 1) / AU_ROWS)), dim3(256), 0, st, n, Q,
                      A.stride, A.nb, (const double*)C, X, flag);
   GK_HIP(hipGetLastError());
-  kt_end(st, qb + 2.0 * xb, fl);
+  kt_end(st, qb + 2.0 * xb, fl, flag);
 }
 
 // One projection X -= Q (Q^T X) against the float32 archive A (A.f32, A.stride
@@ -282,6 +387,35 @@ void launch_arch_reorth(int64_t n, int ld, BlockList A, double* X, double* C, do
     case 48: arch_launch<3>(n, A, X, C, part, flag, st); break;
     case 64: arch_launch<4>(n, A, X, C, part, flag, st); break;
     default: throw Error{GK_EUNSUPPORTED, "archive projection needs ld in {16,32,48,64}"};
+  }
+}
+
+}  // namespace gk
+
+namespace gk {
+
+template <int NT>
+static void arch_assemble_launch(int64_t n, int s, BlockList A, const double* U, double* P, const int64_t* perm,
+                                 hipStream_t st) {
+  kt_begin(KC_ASSEMBLE, st);
+  hipLaunchKernelGGL(arch_assemble_kernel<NT>, dim3((unsigned)((n + AU_ROWS - 1) / AU_ROWS)), dim3(256), 0, st, n,
+                     static_cast<const float*>(A.base), A.stride, A.nb, U, s, P, perm);
+  GK_HIP(hipGetLastError());
+  kt_end(st, (double)n * (4.0 * 16 * NT * A.nb + 8.0 * s), 2.0 * (double)n * 16 * NT * s * A.nb);
+}
+
+// P (column-major n x s, caller order through perm) = [A_1 .. A_nb] U with U
+// (nb*ld x s, row-major) for a float32 archive with ld in {16, 32, 48, 64}.
+void launch_arch_assemble(int64_t n, int ld, int s, BlockList A, const double* U, double* P, const int64_t* perm,
+                          hipStream_t st) {
+  GK_REQUIRE(A.f32 && A.stride > 0 && A.nb >= 1 && s >= 1 && s <= ld, GK_EUNSUPPORTED,
+             "archive assembly needs a float32 archive and s <= ld");
+  switch (ld) {
+    case 16: arch_assemble_launch<1>(n, s, A, U, P, perm, st); break;
+    case 32: arch_assemble_launch<2>(n, s, A, U, P, perm, st); break;
+    case 48: arch_assemble_launch<3>(n, s, A, U, P, perm, st); break;
+    case 64: arch_assemble_launch<4>(n, s, A, U, P, perm, st); break;
+    default: throw Error{GK_EUNSUPPORTED, "archive assembly needs ld in {16,32,48,64}"};
   }
 }
 

@@ -188,6 +188,8 @@ bool arch_ok(int ld);
 size_t arch_scratch_elems(int64_t n, int nb_max, int ld);
 void launch_arch_reorth(int64_t n, int ld, BlockList A, double* X, double* C, double* part, const int* flag,
                         hipStream_t st);
+void launch_arch_assemble(int64_t n, int ld, int s, BlockList A, const double* U, double* P, const int64_t* perm,
+                          hipStream_t st);
 size_t panel_scratch_elems(int64_t n, int ld);
 void launch_panel(int mode, int64_t n, int ld, int nbv, const double* X, double* Xout, float* X32,
                   const double* V0, const double* V1, const double* Cupd, const double* Rm, double* part,
@@ -240,6 +242,6 @@ enum KernelClass {
 void kt_start(bool on);
 void kt_finish();
 void kt_begin(int cls, hipStream_t st);
-void kt_end(hipStream_t st, double bytes, double flops);
+void kt_end(hipStream_t st, double bytes, double flops, const int* flag = nullptr);
 
 }  // namespace gk

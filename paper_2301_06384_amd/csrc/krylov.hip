@@ -232,15 +232,18 @@ struct Job {
   Arena ar;
   PhaseTimer tm;
   int64_t* samp = nullptr;        // device numbering
-  int* dflags = nullptr;          // [0] phi bad, [1] deflations, [2] solve bad, [3] reorth count
+  int* dflags = nullptr;          // [0] phi bad, [1] deflations, [2] solve bad, [3] reorth count,
+                                  // [5] second CholQR passes by series expansion
   double* dscal = nullptr;        // [0] residual norm
   double* poly_dev = nullptr;
   bool mixed() const { return precision == GK_MIXED; }
-  // Full reorthogonalisation every step: always for GK_FP64, on request for
-  // GK_MIXED, and for GK_MIXED cbl blocks wider than 64 (the orthogonality
-  // estimate of partial reorthogonalisation is built for widths up to 64).
+  // Full reorthogonalisation every step: always for GK_FP64 and for the
+  // scalar-coefficient variants (gbl, sbl: their projections are column dot
+  // products, memory-bound and cheap), on request for GK_MIXED cbl, and for
+  // GK_MIXED cbl blocks wider than 64 (the orthogonality estimate of partial
+  // reorthogonalisation is built for widths up to 64).
   bool full_reorth() const {
-    return !mixed() || (flags & GK_FULL_REORTH) || (variant == GK_CBL && !small_wave_ok(ld));
+    return !mixed() || (flags & GK_FULL_REORTH) || variant != GK_CBL || !small_wave_ok(ld);
   }
   double thr() const { return 1e-12 * g->lambda_max; }
   // result of the Krylov stage
@@ -426,8 +429,14 @@ static void run_cbl(Job& J) {
     }
     J.tm.begin(PH_REORTH);
     bool g_ready = pan;   // the panel update already produced G = X^T X
-    if (!no_reorth && full && k >= 1) {
-      BlockList all = mixed ? BlockList{Va, blk, k + 1, true} : BlockList{Vb, blk, k + 1, false};
+    // Against the stored basis.  The float32 archive copies of the two local
+    // blocks differ from their float64 recurrence blocks by the float32
+    // rounding; projecting against them would put that rounding back into X,
+    // so the mixed path stops at block k-2 (the local blocks were handled
+    // exactly in float64 above).
+    const int nb_re = mixed ? k - 1 : k + 1;
+    if (!no_reorth && full && k >= 1 && nb_re >= 1) {
+      BlockList all = mixed ? BlockList{Va, blk, nb_re, true} : BlockList{Vb, blk, nb_re, false};
       for (int pass = 0; pass < 2; ++pass) {
         launch_gram(n, ld, all, X, C, part, nullptr, st);
         launch_tsgemm(n, ld, all, C, X, X, nullptr, -1.0, 1.0, nullptr, st);
@@ -463,32 +472,35 @@ static void run_cbl(Job& J) {
         const int* fk = fr + k;
         launch_omega(k, s, ld, Wr[k % 3], Wr[(k + 2) % 3], Wr[(k + 1) % 3], Hd, Bd, R12i, om_nu, om_tau, om_floor_re,
                      om_floor_loc, est_part, fr, forced, J.dscal + 1, J.dflags + 3, st);
-        // flagged: reorthogonalise X against the archive and redo CholQR2.  One
+        // flagged: reorthogonalise X against the archive blocks 0..k-2 (the
+        // local blocks were handled exactly in float64) and redo CholQR2.  One
         // pass suffices: from a loss of at most tau it reaches the floor set by
-        // the float32 archive.
-        J.tm.begin(PH_REORTH);
-        BlockList all{Va, blk, k + 1, true};
-        if (part_arch) {
-          launch_arch_reorth(n, ld, all, X, C, part_arch, fk, st);
-        } else {
-          launch_gram(n, ld, all, X, C, part_all, fk, st);
-          launch_tsgemm(n, ld, all, C, X, X, nullptr, -1.0, 1.0, fk, st);
+        // the float32 archive.  At k = 1 the estimate has no block to act on.
+        if (k >= 2) {
+          J.tm.begin(PH_REORTH);
+          BlockList all{Va, blk, k - 1, true};
+          if (part_arch) {
+            launch_arch_reorth(n, ld, all, X, C, part_arch, fk, st);
+          } else {
+            launch_gram(n, ld, all, X, C, part_all, fk, st);
+            launch_tsgemm(n, ld, all, C, X, X, nullptr, -1.0, 1.0, fk, st);
+          }
+          if (pan)
+            launch_panel(PM_SELF, n, ld, 0, X, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, ppart, G, st, fk);
+          else
+            launch_gram(n, ld, xl, X, G, part_all, fk, st);
+          launch_cholqr_flag(G, ld, s, 1, nullptr, J.thr(), R1, R1i, d1, nullptr, nullptr, nullptr, nullptr, nullptr, fk,
+                             st);
+          if (pan) {
+            launch_panel(PM_APPLY_SELF, n, ld, 0, X, nullptr, nullptr, nullptr, nullptr, nullptr, R1i, ppart, G, st, fk);
+          } else {
+            launch_tsgemm(n, ld, xl, R1i, nullptr, Y, nullptr, 1.0, 0.0, fk, st);
+            launch_gram(n, ld, BlockList{Y, blk, 1, false}, Y, G, part_all, fk, st);
+          }
+          launch_cholqr_flag(G, ld, s, 2, d1, J.thr(), R2, R2i, d2, nullptr, R1, R1i, R12i, Bd + (int64_t)k * s * s, fk,
+                             st);
+          J.tm.begin(PH_ORTH);
         }
-        if (pan)
-          launch_panel(PM_SELF, n, ld, 0, X, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, ppart, G, st, fk);
-        else
-          launch_gram(n, ld, xl, X, G, part_all, fk, st);
-        launch_cholqr_flag(G, ld, s, 1, nullptr, J.thr(), R1, R1i, d1, nullptr, nullptr, nullptr, nullptr, nullptr, fk,
-                           st);
-        if (pan) {
-          launch_panel(PM_APPLY_SELF, n, ld, 0, X, nullptr, nullptr, nullptr, nullptr, nullptr, R1i, ppart, G, st, fk);
-        } else {
-          launch_tsgemm(n, ld, xl, R1i, nullptr, Y, nullptr, 1.0, 0.0, fk, st);
-          launch_gram(n, ld, BlockList{Y, blk, 1, false}, Y, G, part_all, fk, st);
-        }
-        launch_cholqr_flag(G, ld, s, 2, d1, J.thr(), R2, R2i, d2, nullptr, R1, R1i, R12i, Bd + (int64_t)k * s * s, fk,
-                           st);
-        J.tm.begin(PH_ORTH);
       }
       float* arch32 = mixed ? Va + (int64_t)(k + 1) * blk : nullptr;
       if (pan)
@@ -522,7 +534,7 @@ static void run_scalar_lanczos(Job& J, bool global) {
   const int ld = J.ld, m = J.m, s = J.s;
   const int64_t blk = n * ld;
   const bool mixed = J.mixed();
-  const bool full = !mixed || (J.flags & GK_FULL_REORTH);
+  const bool full = J.full_reorth();
   const bool no_reorth = mixed && (J.flags & 0x10u);
   hipStream_t st = J.st;
   double* Vb = nullptr;
@@ -571,8 +583,10 @@ static void run_scalar_lanczos(Job& J, bool global) {
       launch_axpy_diag(n, ld, loc, D, X, nullptr, st);
     }
     J.tm.begin(PH_REORTH);
-    if (!no_reorth && full && k >= 1) {
-      BlockList all = mixed ? BlockList{Va, blk, k + 1, true} : BlockList{Vb, blk, k + 1, false};
+    // against the stored basis; the mixed path stops at block k-2 (see run_cbl)
+    const int nb_re = mixed ? k - 1 : k + 1;
+    if (!no_reorth && full && k >= 1 && nb_re >= 1) {
+      BlockList all = mixed ? BlockList{Va, blk, nb_re, true} : BlockList{Vb, blk, nb_re, false};
       for (int pass = 0; pass < 2; ++pass) {
         launch_coldots(n, ld, all, X, cd, part, nullptr, st);
         if (global)
@@ -794,10 +808,15 @@ int run_call(const CallArgs& a, hipStream_t stream) {
   J.tm.begin(PH_ASM);
   if (a.cols_out) {
     double* P = dev_io ? a.cols_out : J.ar.get<double>((size_t)n * s);
-    if (J.Upad)
-      launch_assemble(n, ld, s, J.arch, J.Upad, s, P, perm, stream);   // [Q_1..Q_m] U (Alg. 1)
-    else
+    if (J.Upad) {
+      // [Q_1..Q_m] U (Alg. 1)
+      if (J.arch.f32 && J.arch.stride > 0 && arch_ok(ld))
+        launch_arch_assemble(n, ld, s, J.arch, J.Upad, P, perm, stream);
+      else
+        launch_assemble(n, ld, s, J.arch, J.Upad, s, P, perm, stream);
+    } else {
       launch_assemble_diag(n, ld, s, J.arch, J.D, P, perm, true, stream);   // sum_k u_k Q_k (Alg. 2)
+    }
     hcols = P;
   }
   J.tm.end();
@@ -861,6 +880,7 @@ int run_call(const CallArgs& a, hipStream_t stream) {
       a.st->t_total_ms = ms;
     }
     a.st->n_deflated = hflags[1];
+    a.st->n_qr2_series = hflags[5];
     a.st->resid_norm = hscal[0];
     a.st->phi_method = J.phi_method;
     a.st->footprint_bytes = J.ar.bytes;

@@ -110,7 +110,7 @@ void launch_reduce_parts(int64_t len, int nparts, const double* part, double* ou
   hipLaunchKernelGGL(reduce_parts_kernel, dim3((unsigned)((len + 15) / 16)), dim3(256), 0, st, len, nparts, part, out,
                      flag);
   GK_HIP(hipGetLastError());
-  kt_end(st, 8.0 * (double)len * (nparts + 1), (double)len * nparts);
+  kt_end(st, 8.0 * (double)len * (nparts + 1), (double)len * nparts, flag);
 }
 
 static void gram_geometry(int64_t n, int nb, int ld, int* nx, int* ny, int* nch, int64_t* rpc) {
@@ -149,7 +149,7 @@ void launch_gram(int64_t n, int ld, BlockList A, const double* B, double* C, dou
     hipLaunchKernelGGL(gram_kernel<false>, grid, dim3(256), 0, st, n, ld, A.base, A.stride, A.nb, B,
                        part, rpc, flag);
   GK_HIP(hipGetLastError());
-  kt_end(st, (double)n * ld * ((A.f32 ? 4.0 : 8.0) * A.nb + 8.0), 2.0 * (double)n * ld * ld * A.nb);
+  kt_end(st, (double)n * ld * ((A.f32 ? 4.0 : 8.0) * A.nb + 8.0), 2.0 * (double)n * ld * ld * A.nb, flag);
   launch_reduce_parts((int64_t)A.nb * ld * ld, nch, part, C, flag, st);
 }
 
@@ -258,7 +258,7 @@ void launch_tsgemm(int64_t n, int ld, BlockList A, const double* C, const double
                        (const int64_t*)nullptr, flag);
   GK_HIP(hipGetLastError());
   kt_end(st, (double)n * ld * ((A.f32 ? 4.0 : 8.0) * A.nb + (beta != 0.0 ? 16.0 : 8.0) + (out32 ? 4.0 : 0.0)),
-         2.0 * (double)n * ld * ld * A.nb);
+         2.0 * (double)n * ld * ld * A.nb, flag);
 }
 
 void launch_assemble(int64_t n, int ld, int s, BlockList A, const double* U, int ldu, double* P,

@@ -166,6 +166,7 @@ struct KtRec {
   int cls;
   hipEvent_t a, b;
   double bytes, flops;
+  const int* flag;   // device flag of a flag-gated launch (work only when *flag != 0)
 };
 struct KtState {
   bool on = false;
@@ -197,12 +198,12 @@ void kt_begin(int cls, hipStream_t st) {
   t_kt.cur = cls;
   t_kt.cur_a = a;
 }
-void kt_end(hipStream_t st, double bytes, double flops) {
+void kt_end(hipStream_t st, double bytes, double flops, const int* flag) {
   if (!t_kt.on || t_kt.cur < 0) return;
   hipEvent_t b;
   GK_HIP(hipEventCreate(&b));
   GK_HIP(hipEventRecord(b, st));
-  t_kt.recs.push_back({t_kt.cur, t_kt.cur_a, b, bytes, flops});
+  t_kt.recs.push_back({t_kt.cur, t_kt.cur_a, b, bytes, flops, flag});
   t_kt.cur = -1;
   t_kt.cur_a = nullptr;
 }
@@ -216,11 +217,15 @@ void kt_finish() {
   for (auto& r : t_kt.recs) {
     float ms = 0.f;
     if (hipEventSynchronize(r.b) == hipSuccess && hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+      int active = 1;
+      if (r.flag && hipMemcpy(&active, r.flag, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) active = 1;
       gk_kernel_timing& g = t_kt.agg[r.cls];
       g.launches += 1;
       g.total_ms += ms;
-      g.alg_bytes += r.bytes;
-      g.alg_flops += r.flops;
+      if (active) {
+        g.alg_bytes += r.bytes;
+        g.alg_flops += r.flops;
+      }
     }
     (void)hipEventDestroy(r.a);
     (void)hipEventDestroy(r.b);

@@ -1018,7 +1018,8 @@ cholqr_blk_kernel(const double* __restrict__ G, int ld, int s, int pass, const d
     if (tid == 0 && n_defl) {
       int cnt = 0;
       for (int j = 0; j < s; ++j) cnt += (dg[j] == 0.0);
-      *n_defl += cnt;
+      n_defl[0] += cnt;
+      if (fast) n_defl[4] += 1;   // counter slot four entries after the deflation count
     }
     {
       double v1[16], v2[16];
@@ -1370,7 +1371,7 @@ void launch_cholqr_flag(const double* G, int ld, int s, int pass, const double* 
   hipLaunchKernelGGL(cholqr_blk_kernel, dim3(1), dim3(ST), 0, st, G, ld, s, pass, diag_prev, thr, R, Rinv, diag_out,
                      n_defl, R1, R1inv, Rc, Bout, flag);
   GK_HIP(hipGetLastError());
-  kt_end(st, 8.0 * 4 * ld * ld, (double)s * s * s);
+  kt_end(st, 8.0 * 4 * ld * ld, (double)s * s * s, flag);
 }
 
 void launch_omega(int k, int s, int ld, const double* Wk, const double* Wkm1, double* Wk1, const double* Hd,

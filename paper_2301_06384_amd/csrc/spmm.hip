@@ -52,7 +52,7 @@ struct VecD<8> {
   }
 };
 
-template <int VPT, int WM>
+template <int VPT, int WM, bool SHFL>
 __global__ void __launch_bounds__(256)
 spmm_diff_kernel(int64_t n, int ld, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
                  const double* __restrict__ w64, const float* __restrict__ w32,
@@ -60,7 +60,14 @@ spmm_diff_kernel(int64_t n, int ld, const int32_t* __restrict__ rp, const int32_
                  const double* __restrict__ Vprev, double* __restrict__ out, double a, double b,
                  double gm, double* __restrict__ acc, double e, const double* __restrict__ e_dev) {
   const int slots = ld / VPT;
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  // Workgroups are dealt round-robin to the 8 XCDs, each with its own L2.
+  // Renumber them so that every XCD walks one contiguous range of rows: with
+  // a locality ordering of the nodes, the neighbour rows it gathers are then
+  // mostly fetched into one L2 instead of several.
+  const unsigned G = gridDim.x, q8 = G >> 3, r8 = G & 7;
+  const unsigned x = blockIdx.x & 7, k = blockIdx.x >> 3;
+  const unsigned lb = x * q8 + (x < r8 ? x : r8) + k;
+  const int64_t t = (int64_t)lb * blockDim.x + threadIdx.x;
   const int64_t row = t / slots;
   if (row >= n) return;
   const int c0 = (int)(t - row * slots) * VPT;
@@ -68,28 +75,70 @@ spmm_diff_kernel(int64_t n, int ld, const int32_t* __restrict__ rp, const int32_
 #pragma unroll
   for (int q = 0; q < VPT; ++q) s[q] = 0.0;
   const int p0 = rp[row], p1 = rp[row + 1];
-  int p = p0;
-  // two neighbours per iteration to keep two gathers in flight
-  for (; p + 1 < p1; p += 2) {
-    const int j0 = ci[p], j1 = ci[p + 1];
-    double w0 = 1.0, w1 = 1.0;
-    if (WM == W_F64) { w0 = w64[p]; w1 = w64[p + 1]; }
-    if (WM == W_F32) { w0 = (double)w32[p]; w1 = (double)w32[p + 1]; }
-    double v0[VPT], v1[VPT];
-    VecD<VPT>::load(V + (int64_t)j0 * ld + c0, v0);
-    VecD<VPT>::load(V + (int64_t)j1 * ld + c0, v1);
+  if (SHFL) {
+    // The lanes of a row (a power of two dividing 64, so a row never straddles
+    // wavefronts) load `slots` column indices and weights at once, then walk
+    // them with lane shuffles, four gathers in flight.
+    const int lr = c0 / VPT;
+    const int gbase = (int)(threadIdx.x & 63) - lr;
+    for (int pc = p0; pc < p1; pc += slots) {
+      const int pp = pc + lr;
+      int myj = 0;
+      double myw = 0.0;
+      if (pp < p1) {
+        myj = ci[pp];
+        myw = (WM == W_F64) ? w64[pp] : (WM == W_F32 ? (double)w32[pp] : 1.0);
+      }
+      const int cnt = min(slots, p1 - pc);
+      int k = 0;
+      for (; k + 3 < cnt; k += 4) {
+        int j[4];
+        double w[4], v[4][VPT];
 #pragma unroll
-    for (int q = 0; q < VPT; ++q) s[q] = fma(w0, v0[q], fma(w1, v1[q], s[q]));
-  }
-  if (p < p1) {
-    const int j0 = ci[p];
-    double w0 = 1.0;
-    if (WM == W_F64) w0 = w64[p];
-    if (WM == W_F32) w0 = (double)w32[p];
-    double v0[VPT];
-    VecD<VPT>::load(V + (int64_t)j0 * ld + c0, v0);
+        for (int u = 0; u < 4; ++u) {
+          j[u] = __shfl(myj, gbase + k + u);
+          w[u] = __shfl(myw, gbase + k + u);
+        }
 #pragma unroll
-    for (int q = 0; q < VPT; ++q) s[q] = fma(w0, v0[q], s[q]);
+        for (int u = 0; u < 4; ++u) VecD<VPT>::load(V + (int64_t)j[u] * ld + c0, v[u]);
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int q = 0; q < VPT; ++q) s[q] = fma(w[u], v[u][q], s[q]);
+      }
+      for (; k < cnt; ++k) {
+        const int j0 = __shfl(myj, gbase + k);
+        const double w0 = __shfl(myw, gbase + k);
+        double v0[VPT];
+        VecD<VPT>::load(V + (int64_t)j0 * ld + c0, v0);
+#pragma unroll
+        for (int q = 0; q < VPT; ++q) s[q] = fma(w0, v0[q], s[q]);
+      }
+    }
+  } else {
+    int p = p0;
+    // two neighbours per iteration to keep two gathers in flight
+    for (; p + 1 < p1; p += 2) {
+      const int j0 = ci[p], j1 = ci[p + 1];
+      double w0 = 1.0, w1 = 1.0;
+      if (WM == W_F64) { w0 = w64[p]; w1 = w64[p + 1]; }
+      if (WM == W_F32) { w0 = (double)w32[p]; w1 = (double)w32[p + 1]; }
+      double v0[VPT], v1[VPT];
+      VecD<VPT>::load(V + (int64_t)j0 * ld + c0, v0);
+      VecD<VPT>::load(V + (int64_t)j1 * ld + c0, v1);
+#pragma unroll
+      for (int q = 0; q < VPT; ++q) s[q] = fma(w0, v0[q], fma(w1, v1[q], s[q]));
+    }
+    if (p < p1) {
+      const int j0 = ci[p];
+      double w0 = 1.0;
+      if (WM == W_F64) w0 = w64[p];
+      if (WM == W_F32) w0 = (double)w32[p];
+      double v0[VPT];
+      VecD<VPT>::load(V + (int64_t)j0 * ld + c0, v0);
+#pragma unroll
+      for (int q = 0; q < VPT; ++q) s[q] = fma(w0, v0[q], s[q]);
+    }
   }
   double vi[VPT], o[VPT];
   VecD<VPT>::load(V + row * ld + c0, vi);
@@ -122,16 +171,18 @@ static void spmm_dispatch_w(const gk_graph* g, bool fp32w, int ld, const double*
   const int bs = 256;
   const int64_t grid = (threads + bs - 1) / bs;
   const double* d = fp32w ? g->d32 : g->d64;
+  const bool shfl = slots <= 64 && (64 % slots) == 0;
+#define GK_SPMM(WM_, SH_)                                                                                   \
+  hipLaunchKernelGGL((spmm_diff_kernel<VPT, WM_, SH_>), dim3((unsigned)grid), dim3(bs), 0, st, g->n, ld, g->rp, \
+                     g->ci, g->w64, g->w32, d, V, Vp, out, a, b, gm, acc, e, e_dev)
   if (g->unit) {
-    hipLaunchKernelGGL((spmm_diff_kernel<VPT, W_UNIT>), dim3((unsigned)grid), dim3(bs), 0, st, g->n,
-                       ld, g->rp, g->ci, g->w64, g->w32, d, V, Vp, out, a, b, gm, acc, e, e_dev);
+    if (shfl) GK_SPMM(W_UNIT, true); else GK_SPMM(W_UNIT, false);
   } else if (fp32w) {
-    hipLaunchKernelGGL((spmm_diff_kernel<VPT, W_F32>), dim3((unsigned)grid), dim3(bs), 0, st, g->n,
-                       ld, g->rp, g->ci, g->w64, g->w32, d, V, Vp, out, a, b, gm, acc, e, e_dev);
+    if (shfl) GK_SPMM(W_F32, true); else GK_SPMM(W_F32, false);
   } else {
-    hipLaunchKernelGGL((spmm_diff_kernel<VPT, W_F64>), dim3((unsigned)grid), dim3(bs), 0, st, g->n,
-                       ld, g->rp, g->ci, g->w64, g->w32, d, V, Vp, out, a, b, gm, acc, e, e_dev);
+    if (shfl) GK_SPMM(W_F64, true); else GK_SPMM(W_F64, false);
   }
+#undef GK_SPMM
   GK_HIP(hipGetLastError());
 }
 

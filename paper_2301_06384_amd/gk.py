@@ -16,6 +16,12 @@ LIB_PATH = os.path.join(_HERE, "libgk.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2301_06384_amd.build`")
+# PyTorch brings its own HIP runtime; it is loaded before the library so that
+# the process sets up the device the same way whatever the caller imports first.
+try:
+    import torch  # noqa: F401
+except ImportError:
+    pass
 _lib = C.CDLL(LIB_PATH)
 
 # ------------------------------------------------------------------ constants
@@ -47,7 +53,7 @@ class Stats(C.Structure):
                 ("t_reorth_ms", C.c_double), ("t_phi_ms", C.c_double), ("t_asm_ms", C.c_double),
                 ("t_fit_ms", C.c_double), ("spmm_launches", C.c_double), ("bytes_spmm", C.c_double),
                 ("resid_norm", C.c_double), ("orth_est", C.c_double), ("n_reorth", C.c_int32),
-                ("n_deflated", C.c_int32), ("phi_method", C.c_int32), ("reserved", C.c_int32),
+                ("n_deflated", C.c_int32), ("phi_method", C.c_int32), ("n_qr2_series", C.c_int32),
                 ("footprint_bytes", C.c_uint64)]
 
     def as_dict(self):
