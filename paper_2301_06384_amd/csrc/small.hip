@@ -649,7 +649,7 @@ namespace gk {
 // register-blocked 4 x 4 per thread.
 // ===================================================================
 constexpr int WS = 64;
-constexpr int LP = WS + 1;
+constexpr int LP = WS + 2;   // even pitch: rows start 16-byte aligned
 constexpr int ST = 256;
 
 // acc = op(A) op(B) for the 4 x 4 block (rows 4ty.., cols 4tx..) of this
@@ -664,10 +664,23 @@ __device__ __forceinline__ void lds_mm(const double (*A)[LP], const double (*B)[
 #pragma unroll 4
   for (int l = 0; l < s; ++l) {
     double av[4], bv[4];
+    if (TA) {
+      // contiguous along the output row index: two 16-byte reads
+      const double2 a01 = *reinterpret_cast<const double2*>(&A[l][4 * ty]);
+      const double2 a23 = *reinterpret_cast<const double2*>(&A[l][4 * ty + 2]);
+      av[0] = a01.x; av[1] = a01.y; av[2] = a23.x; av[3] = a23.y;
+    } else {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) av[i] = TA ? A[l][4 * ty + i] : A[4 * ty + i][l];
+      for (int i = 0; i < 4; ++i) av[i] = A[4 * ty + i][l];
+    }
+    if (!TB) {
+      const double2 b01 = *reinterpret_cast<const double2*>(&B[l][4 * tx]);
+      const double2 b23 = *reinterpret_cast<const double2*>(&B[l][4 * tx + 2]);
+      bv[0] = b01.x; bv[1] = b01.y; bv[2] = b23.x; bv[3] = b23.y;
+    } else {
 #pragma unroll
-    for (int j = 0; j < 4; ++j) bv[j] = TB ? B[4 * tx + j][l] : B[l][4 * tx + j];
+      for (int j = 0; j < 4; ++j) bv[j] = B[4 * tx + j][l];
+    }
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -693,6 +706,14 @@ __device__ __forceinline__ void put64(double (*D)[LP], const double (&v)[16]) {
   for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int b = 0; b < 4; ++b) D[ty + 16 * a][tx + 16 * b] = v[4 * a + b];
+}
+// D[c][i] = v (the transpose of what put64 stores)
+__device__ __forceinline__ void put64T(double (*D)[LP], const double (&v)[16]) {
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) D[tx + 16 * b][ty + 16 * a] = v[4 * a + b];
 }
 __device__ __forceinline__ void stage64(double (*D)[LP], const double* __restrict__ src, int s, int lds) {
   double v[16];
@@ -936,10 +957,10 @@ cholqr_blk_kernel(const double* __restrict__ G, int ld, int s, int pass, const d
                   int* __restrict__ n_defl, const double* __restrict__ R1, const double* __restrict__ R1inv,
                   double* __restrict__ Rc, double* __restrict__ Bout, const int* __restrict__ flag) {
   if (flag && *flag == 0) return;
-  __shared__ double A[WS][LP];
-  __shared__ double Y[WS][LP];
-  __shared__ double S1[WS][LP];
-  __shared__ double S2[WS][LP];
+  __shared__ __align__(16) double A[WS][LP];
+  __shared__ __align__(16) double Y[WS][LP];
+  __shared__ __align__(16) double S1[WS][LP];
+  __shared__ __align__(16) double S2[WS][LP];
   __shared__ double g0[WS], dp[WS], dg[WS];
   __shared__ double red[2][ST];
   const int tid = threadIdx.x;
@@ -981,11 +1002,12 @@ cholqr_blk_kernel(const double* __restrict__ G, int ld, int s, int pass, const d
           else if (c == i) u = 0.5 * (A[i][i] - 1.0);
         }
         S1[i][c] = u;
+        S2[c][i] = u;
       }
     __syncthreads();
     double mm[4][4], u2[4][4];
     lds_mm<true, false>(S1, S1, s, mm);    // U^T U
-    lds_mm<false, false>(S1, S1, s, u2);   // U U
+    lds_mm<true, false>(S2, S1, s, u2);    // U U
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -1026,19 +1048,10 @@ cholqr_blk_kernel(const double* __restrict__ G, int ld, int s, int pass, const d
       fetch64(R1, s, ld, v1);
       fetch64(R1inv, s, ld, v2);
       put64(S1, v1);
-      put64(S2, v2);
+      put64T(S2, v2);
     }
     __syncthreads();
     double acc[4][4];
-    // Rc = R1inv * R2inv = S2 * Y^T
-    lds_mm<false, true>(S2, Y, s, acc);
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int r = 4 * ty + i, c = 4 * tx + j;
-        if (r < ld && c < ld) Rc[r * ld + c] = (r < s && c < s) ? acc[i][j] : 0.0;
-      }
     // B = R2 * R1 = L^T * S1
     lds_mm<true, false>(A, S1, s, acc);
 #pragma unroll
@@ -1047,6 +1060,19 @@ cholqr_blk_kernel(const double* __restrict__ G, int ld, int s, int pass, const d
       for (int j = 0; j < 4; ++j) {
         const int r = 4 * ty + i, c = 4 * tx + j;
         if (r < s && c < s) Bout[r * s + c] = acc[i][j];
+      }
+    __syncthreads();
+    // S1 <- R2inv = Y^T; Rc = R1inv * R2inv = (R1inv^T)^T R2inv
+    for (int i = ty; i < WS; i += 16)
+      for (int c = tx; c < WS; c += 16) S1[c][i] = (i < s && c < s) ? Y[i][c] : 0.0;
+    __syncthreads();
+    lds_mm<true, false>(S2, S1, s, acc);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int r = 4 * ty + i, c = 4 * tx + j;
+        if (r < ld && c < ld) Rc[r * ld + c] = (r < s && c < s) ? acc[i][j] : 0.0;
       }
   }
 }
@@ -1057,10 +1083,10 @@ cholqr_blk_kernel(const double* __restrict__ G, int ld, int s, int pass, const d
 __global__ void __launch_bounds__(ST)
 banded_factor_blk_kernel(int m, int s, const double* __restrict__ Hd, const double* __restrict__ Bd, double eps,
                          double* __restrict__ Linv_all, double* __restrict__ Lsub_all, int* __restrict__ bad) {
-  __shared__ double A[WS][LP];
-  __shared__ double Y[WS][LP];
-  __shared__ double SB[WS][LP];
-  __shared__ double Ls[WS][LP];
+  __shared__ __align__(16) double A[WS][LP];
+  __shared__ __align__(16) double Y[WS][LP];
+  __shared__ __align__(16) double SB[WS][LP];
+  __shared__ __align__(16) double Ls[WS][LP];
   const int tid = threadIdx.x;
   const int tx = tid & 15, ty = tid >> 4;
   const int ss = s * s;
@@ -1079,7 +1105,7 @@ banded_factor_blk_kernel(int m, int s, const double* __restrict__ Hd, const doub
     if (j + 1 < m) fetch64(Hd + (int64_t)(j + 1) * ss, s, s, hv);
     if (j > 0) {
       double acc[4][4];
-      lds_mm<false, true>(Ls, Ls, s, acc);
+      lds_mm<true, false>(Ls, Ls, s, acc);   // Ls holds Lsub_{j-1}^T: Lsub Lsub^T
       __syncthreads();
 #pragma unroll
       for (int i = 0; i < 4; ++i)
@@ -1095,12 +1121,15 @@ banded_factor_blk_kernel(int m, int s, const double* __restrict__ Hd, const doub
     for (int i = ty; i < s; i += 16)
       for (int c = tx; c < s; c += 16) LiG[i * s + c] = (c <= i) ? Y[i][c] : 0.0;
     if (j + 1 < m) {
-      // SB served as elimination workspace; stage H_{j+1,j} now
-      put64(SB, bv);
+      // SB served as elimination workspace; stage H_{j+1,j} transposed now,
+      // and Y^T into A (L itself is no longer needed)
+      put64T(SB, bv);
+      for (int i = ty; i < WS; i += 16)
+        for (int c = tx; c < WS; c += 16) A[c][i] = (i < s && c < s) ? Y[i][c] : 0.0;
       __syncthreads();
-      // Y has zeros above its diagonal, so the product is exact
+      // Lsub_j = H_{j+1,j} Y^T (Y has zeros above its diagonal: exact)
       double acc[4][4];
-      lds_mm<false, true>(SB, Y, s, acc);
+      lds_mm<true, false>(SB, A, s, acc);
       __syncthreads();
       double* LsG = Lsub_all + (int64_t)j * ss;
 #pragma unroll
@@ -1108,10 +1137,8 @@ banded_factor_blk_kernel(int m, int s, const double* __restrict__ Hd, const doub
 #pragma unroll
         for (int jj = 0; jj < 4; ++jj) {
           const int r = 4 * ty + i, c = 4 * tx + jj;
-          if (r < s && c < s) {
-            Ls[r][c] = acc[i][jj];
-            LsG[r * s + c] = acc[i][jj];
-          }
+          Ls[c][r] = (r < s && c < s) ? acc[i][jj] : 0.0;   // kept transposed
+          if (r < s && c < s) LsG[r * s + c] = acc[i][jj];
         }
     }
     __syncthreads();
@@ -1127,10 +1154,10 @@ banded_factor_blk_kernel(int m, int s, const double* __restrict__ Hd, const doub
 __global__ void __launch_bounds__(ST)
 banded_solve_kernel(int m, int s, int kpow, const double* __restrict__ Linv_all, const double* __restrict__ Lsub_all,
                     double* __restrict__ U) {
-  __shared__ double T[WS][LP];
-  __shared__ double SL[WS][LP];   // Lsub
-  __shared__ double SY[WS][LP];   // neighbouring block of Y (previous step's result)
-  __shared__ double SI[WS][LP];   // Linv
+  __shared__ __align__(16) double T[WS][LP];
+  __shared__ __align__(16) double SL[WS][LP];   // Lsub
+  __shared__ __align__(16) double SY[WS][LP];   // neighbouring block of Y (previous step's result)
+  __shared__ __align__(16) double SI[WS][LP];   // Linv
   const int tid = threadIdx.x;
   const int tx = tid & 15, ty = tid >> 4;
   const int ss = s * s;
@@ -1162,8 +1189,14 @@ banded_solve_kernel(int m, int s, int kpow, const double* __restrict__ Linv_all,
     int dir, j;
     blk_of(st, dir, j);
     const bool nb = has_nb(dir, j);
-    put64(SI, pi);
-    put64(SL, pl);
+    // products run as C = X^T B: the forward sweep stages Lsub and Linv transposed
+    if (dir == 0) {
+      put64T(SI, pi);
+      put64T(SL, pl);
+    } else {
+      put64(SI, pi);
+      put64(SL, pl);
+    }
     if (j == pj) {
       // the previous step finished this very block (turn of a sweep)
       for (int i = ty; i < WS; i += 16)
@@ -1181,8 +1214,7 @@ banded_solve_kernel(int m, int s, int kpow, const double* __restrict__ Linv_all,
     }
     double acc[4][4];
     if (nb) {
-      if (dir == 0) lds_mm<false, false>(SL, SY, s, acc);   // Lsub_{j-1} Y_{j-1}
-      else lds_mm<true, false>(SL, SY, s, acc);             // Lsub_j^T Y_{j+1}
+      lds_mm<true, false>(SL, SY, s, acc);   // Lsub_{j-1} Y_{j-1} (forward) or Lsub_j^T Y_{j+1} (backward)
       __syncthreads();
 #pragma unroll
       for (int i = 0; i < 4; ++i)
@@ -1190,8 +1222,7 @@ banded_solve_kernel(int m, int s, int kpow, const double* __restrict__ Linv_all,
         for (int jj = 0; jj < 4; ++jj) T[4 * ty + i][4 * tx + jj] -= acc[i][jj];
       __syncthreads();
     }
-    if (dir == 0) lds_mm<false, false>(SI, T, s, acc);
-    else lds_mm<true, false>(SI, T, s, acc);
+    lds_mm<true, false>(SI, T, s, acc);     // Linv_j T (forward) or Linv_j^T T (backward)
     __syncthreads();   // SY is read above (nb) and rewritten below
     double* Y = U + (int64_t)j * ss;
 #pragma unroll
@@ -1223,10 +1254,10 @@ __global__ void __launch_bounds__(ST)
 omega_kernel(int k, int s, int ld, const double* __restrict__ Wk, const double* __restrict__ Wkm1,
              double* __restrict__ Wk1, const double* __restrict__ Hd, const double* __restrict__ Bd,
              const double* __restrict__ Rc, double nu, double* __restrict__ est_part) {
-  __shared__ double S1[WS][LP];
-  __shared__ double S2[WS][LP];
-  __shared__ double S3[WS][LP];
-  __shared__ double S4[WS][LP];
+  __shared__ __align__(16) double S1[WS][LP];
+  __shared__ __align__(16) double S2[WS][LP];
+  __shared__ __align__(16) double S3[WS][LP];
+  __shared__ __align__(16) double S4[WS][LP];
   __shared__ double red[ST];
   const int j = blockIdx.x;
   const int tid = threadIdx.x;
@@ -1239,6 +1270,8 @@ omega_kernel(int k, int s, int ld, const double* __restrict__ Wk, const double* 
 #pragma unroll
       for (int b = 0; b < 4; ++b) tot[a][b] += sign * acc[a][b];
   };
+  // Every product runs as X^T B (contiguous operand reads); left operands
+  // are staged transposed, and the H blocks are symmetric.
   {
     // W_{k,j+1} B_j + W_{k,j} H_j
     double v1[16], v2[16], v3[16], v4[16];
@@ -1246,26 +1279,27 @@ omega_kernel(int k, int s, int ld, const double* __restrict__ Wk, const double* 
     fetch64(Bd + (int64_t)j * ss, s, s, v2);
     fetch64(Wk + (int64_t)j * ss, s, s, v3);
     fetch64(Hd + (int64_t)j * ss, s, s, v4);
-    put64(S1, v1); put64(S2, v2); put64(S3, v3); put64(S4, v4);
+    put64T(S1, v1); put64(S2, v2); put64T(S3, v3); put64(S4, v4);
   }
   __syncthreads();
-  lds_mm<false, false>(S1, S2, s, tot);
-  lds_mm<false, false>(S3, S4, s, acc);
+  lds_mm<true, false>(S1, S2, s, tot);
+  lds_mm<true, false>(S3, S4, s, acc);
   addto(1.0);
   __syncthreads();
   {
     // - H_k W_{k,j} + W_{k,j-1} B_{j-1}^T
-    double v1[16], v2[16], v4[16];
+    double v1[16], v2[16], v3[16], v4[16];
     fetch64(Hd + (int64_t)k * ss, s, s, v1);
+    fetch64(Wk + (int64_t)j * ss, s, s, v3);
     fetch64(j >= 1 ? Wk + (int64_t)(j - 1) * ss : nullptr, s, s, v2);
     fetch64(j >= 1 ? Bd + (int64_t)(j - 1) * ss : nullptr, s, s, v4);
-    put64(S1, v1); put64(S2, v2); put64(S4, v4);
+    put64(S1, v1); put64(S3, v3); put64T(S2, v2); put64T(S4, v4);
   }
   __syncthreads();
-  lds_mm<false, false>(S1, S3, s, acc);
+  lds_mm<true, false>(S1, S3, s, acc);   // H_k symmetric: H_k^T W_{k,j}
   addto(-1.0);
   if (j >= 1) {
-    lds_mm<false, true>(S2, S4, s, acc);
+    lds_mm<true, false>(S2, S4, s, acc);   // (W_{k,j-1}^T)^T (B_{j-1}^T)
     addto(1.0);
   }
   __syncthreads();
@@ -1275,10 +1309,10 @@ omega_kernel(int k, int s, int ld, const double* __restrict__ Wk, const double* 
     fetch64(Bd + (int64_t)(k - 1) * ss, s, s, v1);
     fetch64(Wkm1 + (int64_t)j * ss, s, s, v2);
     fetch64(Rc, s, ld, v4);
-    put64(S1, v1); put64(S2, v2); put64(S4, v4);
+    put64T(S1, v1); put64(S2, v2); put64(S4, v4);
   }
   __syncthreads();
-  lds_mm<false, false>(S1, S2, s, acc);
+  lds_mm<true, false>(S1, S2, s, acc);
   addto(-1.0);
 #pragma unroll
   for (int a = 0; a < 4; ++a)
