@@ -41,9 +41,10 @@ ROOFS = {
     "panel_self": ("mfma", 78.6, "TFLOP/s", "panel.hip"),
     "arch_gram": ("mfma", 157.3, "TFLOP/s", "arch.hip"),
     "arch_update": ("mfma", 157.3, "TFLOP/s", "arch.hip"),
-    "gram": ("alu", 78.6, "TFLOP/s", "ortho.hip"),
-    "tsgemm": ("alu", 78.6, "TFLOP/s", "ortho.hip"),
-    "assemble": ("alu", 78.6, "TFLOP/s", "ortho.hip"),
+    "gram": ("mfma", 78.6, "TFLOP/s", "ortho.hip"),
+    "tsgemm": ("mfma", 78.6, "TFLOP/s", "ortho.hip"),
+    "assemble": ("mfma", 157.3, "TFLOP/s", "arch.hip"),
+    "predict": ("hbm", HBM_PEAK_GBS, "GB/s", "ortho.hip"),
     "cholqr": ("alu", 78.6, "TFLOP/s", "small.hip"),
     "omega": ("alu", 78.6, "TFLOP/s", "small.hip"),
     "banded_factor": ("alu", 78.6, "TFLOP/s", "small.hip"),

@@ -114,6 +114,9 @@ void launch_tsgemm(int64_t n, int ld, BlockList A, const double* C, const double
 void launch_assemble(int64_t n, int ld, int s, BlockList A, const double* U, int ldu, double* P,
                      const int64_t* perm, hipStream_t st);
 // P[perm(i), c] = sum_k D[k*ld + c] * A_k[i, c]
+// out[perm[r]] = sum_k A_k[r, :] z[k ld : (k+1) ld] (kernel machine predictor)
+void launch_predict(int64_t n, int ld, BlockList A, const double* z, double* out, const int64_t* perm,
+                    hipStream_t st);
 void launch_assemble_diag(int64_t n, int ld, int s, BlockList A, const double* D, double* P,
                           const int64_t* perm, bool colmajor, hipStream_t st);
 size_t coldots_scratch_elems(int64_t n, int nb, int ld);
@@ -169,9 +172,26 @@ void launch_banded_spline_reg(int m, int s, const double* Hd, const double* Bd, 
 void launch_cholqr_flag(const double* G, int ld, int s, int pass, const double* diag_prev, double thr, double* R,
                         double* Rinv, double* diag_out, int* n_defl, const double* R1, const double* R1inv, double* Rc,
                         double* Bout, const int* flag, hipStream_t st);
+// Block orthogonality estimate (partial reorthogonalisation) for s <= 512.
+// est_part holds m * omega_est_per_block(s) entries; rhs_wide is null for
+// s <= 64 and omega_wide_scratch_elems(m, s) doubles otherwise.
 void launch_omega(int k, int s, int ld, const double* Wk, const double* Wkm1, double* Wk1, const double* Hd,
                   const double* Bd, const double* Rc, double nu, double tau, double floor_re, double floor_loc,
-                  double* est_part, int* fr, int* forced, double* est_out, int* nre, hipStream_t st);
+                  double* est_part, int* fr, int* forced, double* est_out, int* nre, double* rhs_wide,
+                  hipStream_t st);
+int omega_est_per_block(int s);
+// Small kernels for widths 65..512 (tiles of 64, one workgroup each).
+bool wide_ok(int ld);
+size_t cholqr_wide_scratch_elems(int ld);
+void launch_cholqr_wide(const double* G, int ld, int s, int pass, const double* diag_prev, double thr, double* wk,
+                        double* R, double* Rinv, double* diag_out, int* n_defl, const double* R1, const double* R1inv,
+                        double* Rc, double* Bout, const int* flag, hipStream_t st);
+size_t omega_wide_scratch_elems(int m, int s);
+void launch_omega_wide(int k, int s, int ld, const double* Wk, const double* Wkm1, double* Wk1, const double* Hd,
+                       const double* Bd, const double* Rc, double nu, double* rhs, double* est_part, hipStream_t st);
+size_t banded_wide_work_elems(int m, int s);
+void launch_banded_spline_wide(int m, int s, const double* Hd, const double* Bd, double eps, int k, double* work,
+                               double* U, int* bad, hipStream_t st);
 int cheb_diffusion_degree(double t, double Lam);
 void launch_cheb_diffusion(int m, int s, const double* Hd, const double* Bd, double t, double Lam, int deg,
                            const double* coef, double* Y0, double* Y1, double* Y2, double* U, hipStream_t st);
@@ -237,7 +257,7 @@ enum Phase { PH_SPMM = 0, PH_ORTH, PH_REORTH, PH_PHI, PH_ASM, PH_FIT, PH_TOTAL }
 enum KernelClass {
   KC_SPMM = 0, KC_PANEL_GRAMV, KC_PANEL_UPDATE_SELF, KC_PANEL_APPLY_SELF, KC_PANEL_APPLY_WRITE, KC_PANEL_SELF,
   KC_GRAM, KC_TSGEMM, KC_ARCH_GRAM, KC_ARCH_UPDATE, KC_REDUCE, KC_CHOLQR, KC_OMEGA, KC_BANDED_FACTOR,
-  KC_BANDED_SOLVE, KC_CHEB, KC_EIG, KC_ASSEMBLE, KC_COUNT
+  KC_BANDED_SOLVE, KC_CHEB, KC_EIG, KC_ASSEMBLE, KC_PREDICT, KC_COUNT
 };
 void kt_start(bool on);
 void kt_finish();

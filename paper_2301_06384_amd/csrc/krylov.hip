@@ -240,10 +240,10 @@ struct Job {
   // Full reorthogonalisation every step: always for GK_FP64 and for the
   // scalar-coefficient variants (gbl, sbl: their projections are column dot
   // products, memory-bound and cheap), on request for GK_MIXED cbl, and for
-  // GK_MIXED cbl blocks wider than 64 (the orthogonality estimate of partial
-  // reorthogonalisation is built for widths up to 64).
+  // GK_MIXED cbl blocks wider than 512 (the orthogonality estimate of partial
+  // reorthogonalisation is built for widths up to 512).
   bool full_reorth() const {
-    return !mixed() || (flags & GK_FULL_REORTH) || variant != GK_CBL || !small_wave_ok(ld);
+    return !mixed() || (flags & GK_FULL_REORTH) || variant != GK_CBL || !(small_wave_ok(ld) || wide_ok(ld));
   }
   double thr() const { return 1e-12 * g->lambda_max; }
   // result of the Krylov stage
@@ -279,11 +279,16 @@ static void phi_stage_block(Job& J, const double* Hd, const double* Bd, double* 
   const bool int_spline = J.phi.kind == GK_PHI_SPLINE && kk == std::floor(kk) && kk >= 1 && kk <= 16;
   if (int_spline && !(J.flags & GK_PHI_EIG)) {
     // exact banded evaluation (block tridiagonal Cholesky solves)
-    double* work = J.ar.get<double>(banded_work_elems(m, s));
-    if (s <= 64)
+    if (small_wave_ok(s)) {
+      double* work = J.ar.get<double>(banded_work_elems(m, s));
       launch_banded_spline_reg(m, s, Hd, Bd, J.phi.eps, (int)kk, work, U, J.dflags + 0, J.st);
-    else
+    } else if (wide_ok(s)) {
+      double* work = J.ar.get<double>(banded_wide_work_elems(m, s));
+      launch_banded_spline_wide(m, s, Hd, Bd, J.phi.eps, (int)kk, work, U, J.dflags + 0, J.st);
+    } else {
+      double* work = J.ar.get<double>(banded_work_elems(m, s));
       launch_banded_spline(m, s, Hd, Bd, J.phi.eps, (int)kk, work, U, J.dflags + 0, J.st);
+    }
     launch_store_H(U, s, s, K, J.st);          // K = sym(U[0:s, :])
     J.phi_method = 1;
     return;
@@ -353,8 +358,9 @@ static void run_cbl(Job& J) {
   double* part = J.ar.get<double>(pe);
   double* C = J.ar.get<double>((size_t)m * ld * ld);
   const size_t l2 = (size_t)ld * ld;
+  const bool wave = small_wave_ok(ld), widek = wide_ok(ld);
   double* G = J.ar.get<double>(l2);
-  double* W = J.ar.get<double>(l2);
+  double* W = J.ar.get<double>(widek ? cholqr_wide_scratch_elems(ld) : l2);
   double* R1 = J.ar.get<double>(l2);
   double* R1i = J.ar.get<double>(l2);
   double* R2 = J.ar.get<double>(l2);
@@ -372,11 +378,12 @@ static void run_cbl(Job& J) {
 
   const bool pan = panel_ok(ld);
   double* ppart = pan ? J.ar.get<double>(panel_scratch_elems(n, ld)) : nullptr;
-  // partial reorthogonalisation (GK_MIXED, s <= 64): block omega estimate,
+  // partial reorthogonalisation (GK_MIXED, s <= 512): block omega estimate,
   // reorthogonalisation against the float32 archive only when it is needed
-  const bool pro = mixed && !full && !no_reorth && small_wave_ok(ld) && m > 2;
+  const bool pro = mixed && !full && !no_reorth && (wave || widek) && m > 2;
   double* Wr[3] = {nullptr, nullptr, nullptr};
   double* est_part = nullptr;
+  double* om_rhs = nullptr;
   int* fr = nullptr;
   int* forced = nullptr;
   size_t pe_all = 0;
@@ -387,7 +394,8 @@ static void run_cbl(Job& J) {
       Wr[i] = J.ar.get<double>((size_t)m * s * s);
       launch_zero(Wr[i], (size_t)m * s * s * sizeof(double), st);
     }
-    est_part = J.ar.get<double>(m);
+    est_part = J.ar.get<double>((size_t)m * omega_est_per_block(s));
+    if (widek) om_rhs = J.ar.get<double>(omega_wide_scratch_elems(m, s));
     fr = J.ar.get<int>(m);
     forced = J.ar.get<int>(m + 1);
     launch_zero(forced, sizeof(int) * (m + 1), st);
@@ -448,9 +456,11 @@ static void run_cbl(Job& J) {
     if (!g_ready) launch_gram(n, ld, xl, X, G, part, nullptr, st);
     if (k + 1 < m) {
       // CholQR2: X = Q_{k+1} H_{k+1,k}
-      const bool wave = small_wave_ok(ld);
       if (wave)
         launch_cholqr_reg(G, ld, s, 1, nullptr, J.thr(), R1, R1i, d1, nullptr, nullptr, nullptr, nullptr, nullptr, st);
+      else if (widek)
+        launch_cholqr_wide(G, ld, s, 1, nullptr, J.thr(), W, R1, R1i, d1, nullptr, nullptr, nullptr, nullptr, nullptr,
+                           nullptr, st);
       else
         launch_cholqr_factor(G, ld, s, 1, nullptr, J.thr(), W, R1, R1i, d1, nullptr, st);
       if (pan) {
@@ -463,6 +473,9 @@ static void run_cbl(Job& J) {
       if (wave) {
         launch_cholqr_reg(G, ld, s, 2, d1, J.thr(), R2, R2i, d2, J.dflags + 1, R1, R1i, R12i,
                           Bd + (int64_t)k * s * s, st);
+      } else if (widek) {
+        launch_cholqr_wide(G, ld, s, 2, d1, J.thr(), W, R2, R2i, d2, J.dflags + 1, R1, R1i, R12i,
+                           Bd + (int64_t)k * s * s, nullptr, st);
       } else {
         launch_cholqr_factor(G, ld, s, 2, d1, J.thr(), W, R2, R2i, d2, J.dflags + 1, st);
         launch_small_gemm(ld, ld, ld, R1i, ld, false, R2i, ld, false, R12i, ld, 1.0, 0.0, st);
@@ -471,7 +484,7 @@ static void run_cbl(Job& J) {
       if (pro && k >= 1) {
         const int* fk = fr + k;
         launch_omega(k, s, ld, Wr[k % 3], Wr[(k + 2) % 3], Wr[(k + 1) % 3], Hd, Bd, R12i, om_nu, om_tau, om_floor_re,
-                     om_floor_loc, est_part, fr, forced, J.dscal + 1, J.dflags + 3, st);
+                     om_floor_loc, est_part, fr, forced, J.dscal + 1, J.dflags + 3, om_rhs, st);
         // flagged: reorthogonalise X against the archive blocks 0..k-2 (the
         // local blocks were handled exactly in float64) and redo CholQR2.  One
         // pass suffices: from a loss of at most tau it reaches the floor set by
@@ -489,16 +502,24 @@ static void run_cbl(Job& J) {
             launch_panel(PM_SELF, n, ld, 0, X, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, ppart, G, st, fk);
           else
             launch_gram(n, ld, xl, X, G, part_all, fk, st);
-          launch_cholqr_flag(G, ld, s, 1, nullptr, J.thr(), R1, R1i, d1, nullptr, nullptr, nullptr, nullptr, nullptr, fk,
-                             st);
+          if (wave)
+            launch_cholqr_flag(G, ld, s, 1, nullptr, J.thr(), R1, R1i, d1, nullptr, nullptr, nullptr, nullptr, nullptr,
+                               fk, st);
+          else
+            launch_cholqr_wide(G, ld, s, 1, nullptr, J.thr(), W, R1, R1i, d1, nullptr, nullptr, nullptr, nullptr,
+                               nullptr, fk, st);
           if (pan) {
             launch_panel(PM_APPLY_SELF, n, ld, 0, X, nullptr, nullptr, nullptr, nullptr, nullptr, R1i, ppart, G, st, fk);
           } else {
             launch_tsgemm(n, ld, xl, R1i, nullptr, Y, nullptr, 1.0, 0.0, fk, st);
             launch_gram(n, ld, BlockList{Y, blk, 1, false}, Y, G, part_all, fk, st);
           }
-          launch_cholqr_flag(G, ld, s, 2, d1, J.thr(), R2, R2i, d2, nullptr, R1, R1i, R12i, Bd + (int64_t)k * s * s, fk,
-                             st);
+          if (wave)
+            launch_cholqr_flag(G, ld, s, 2, d1, J.thr(), R2, R2i, d2, nullptr, R1, R1i, R12i, Bd + (int64_t)k * s * s,
+                               fk, st);
+          else
+            launch_cholqr_wide(G, ld, s, 2, d1, J.thr(), W, R2, R2i, d2, nullptr, R1, R1i, R12i,
+                               Bd + (int64_t)k * s * s, fk, st);
           J.tm.begin(PH_ORTH);
         }
       }
@@ -697,7 +718,7 @@ uint64_t footprint_bytes(int64_t n, int s, int m, int variant, int precision) {
     if (variant == GK_CBL) {
       b += 2 * ms * ms * 8.0 + (double)m * ld * ld * 8.0 + 4.0 * m * s * s * 8.0;
       // Gram partials of the orthogonalisation passes
-      const bool full = !mixed || (variant == GK_CBL && !small_wave_ok(ld));
+      const bool full = !mixed || (variant == GK_CBL && !(small_wave_ok(ld) || wide_ok(ld)));
       size_t pe = 0;
       for (int nb = 1; nb <= (full ? m : 2); ++nb) pe = std::max(pe, gram_scratch_elems(n, nb, ld));
       b += 8.0 * pe;
@@ -705,6 +726,7 @@ uint64_t footprint_bytes(int64_t n, int s, int m, int variant, int precision) {
       if (mixed) {
         // partial reorthogonalisation: estimate blocks and archive partials
         b += 3.0 * m * s * s * 8.0;
+        if (wide_ok(ld)) b += 8.0 * (omega_wide_scratch_elems(m, s) + cholqr_wide_scratch_elems(ld));
         if (arch_ok(ld)) {
           b += 8.0 * arch_scratch_elems(n, m, ld);
         } else {
@@ -850,7 +872,7 @@ int run_call(const CallArgs& a, hipStream_t stream) {
         hipLaunchKernelGGL(zdiag_kernel, dim3(nblk((int64_t)nbk * ld)), dim3(256), 0, stream, nbk, s, ld, J.D, coef, z);
       GK_HIP(hipGetLastError());
       pred = dev_io ? a.pred_out : J.ar.get<double>(n);
-      launch_assemble(n, ld, 1, J.arch, z, 1, pred, perm, stream);
+      launch_predict(n, ld, J.arch, z, pred, perm, stream);
     }
     J.tm.end();
   }

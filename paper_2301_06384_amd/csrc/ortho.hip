@@ -113,7 +113,13 @@ void launch_reduce_parts(int64_t len, int nparts, const double* part, double* ou
   kt_end(st, 8.0 * (double)len * (nparts + 1), (double)len * nparts, flag);
 }
 
+// Blocks wider than 64 use the FP64 matrix-core kernels below (rows staged
+// 32 at a time); narrower ones the vector kernel above.
+static bool mfma_ok(int ld) { return ld > 64 && ld % 16 == 0; }
+constexpr int MG_T = 64, MG_RS = 32, MG_P = MG_T + 2;
+
 static void gram_geometry(int64_t n, int nb, int ld, int* nx, int* ny, int* nch, int64_t* rpc) {
+  const int rs = mfma_ok(ld) ? MG_RS : G_RS;
   const int pa = nb * ld;
   *nx = (pa + G_TA - 1) / G_TA;
   *ny = (ld + G_TB - 1) / G_TB;
@@ -123,7 +129,7 @@ static void gram_geometry(int64_t n, int nb, int ld, int* nx, int* ny, int* nch,
   if (want < 1) want = 1;
   if (want > 1024) want = 1024;
   int64_t r = (n + want - 1) / want;
-  r = ((r + G_RS - 1) / G_RS) * G_RS;
+  r = ((r + rs - 1) / rs) * rs;
   *rpc = r;
   *nch = (int)((n + r - 1) / r);
 }
@@ -135,6 +141,198 @@ size_t gram_scratch_elems(int64_t n, int nb, int ld) {
   return (size_t)nch * nb * ld * ld;
 }
 
+// ------------------------------------------- FP64 matrix-core Gram / update
+typedef double d4v __attribute__((ext_vector_type(4)));
+
+// eight consecutive elements (16-byte aligned) as doubles
+template <bool F32>
+__device__ __forceinline__ void ld8(const void* __restrict__ base, int64_t off, double (&v)[8]) {
+  if (F32) {
+    const float4* p = reinterpret_cast<const float4*>(static_cast<const float*>(base) + off);
+    const float4 a = p[0], b = p[1];
+    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+    v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+  } else {
+    const double2* p = reinterpret_cast<const double2*>(static_cast<const double*>(base) + off);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const double2 t = p[q];
+      v[2 * q] = t.x;
+      v[2 * q + 1] = t.y;
+    }
+  }
+}
+
+// part[z] (pa x ld) = A^T B over the rows of chunk z, one 64 x 64 output tile
+// per workgroup.  Wave w owns a 32 x 32 quarter as 2 x 2 tiles of
+// v_mfma_f64_16x16x4f64 (lane l = i + 16 k: A operand A[r0+k][a+i], B operand
+// B[r0+k][b+i]; accumulator register q holds output row 4q + k, column i).
+// The next 32 rows are fetched into registers while the current ones are
+// multiplied.
+template <bool F32>
+__global__ void __launch_bounds__(256)
+gram_mfma_kernel(int64_t n, int ld, const void* __restrict__ Abase, int64_t astride, int nb,
+                 const double* __restrict__ B, double* __restrict__ part, int64_t rows_per_chunk,
+                 const int* __restrict__ flag) {
+  if (flag && *flag == 0) return;
+  __shared__ __align__(16) double sA[MG_RS][MG_P];
+  __shared__ __align__(16) double sB[MG_RS][MG_P];
+  const int pa = nb * ld;
+  const int a0 = blockIdx.x * MG_T, b0 = blockIdx.y * MG_T;
+  const int64_t rb = (int64_t)blockIdx.z * rows_per_chunk;
+  const int64_t re = min(n, rb + rows_per_chunk);
+  const int tid = threadIdx.x;
+  const int w = tid >> 6, l = tid & 63, li = l & 15, lk = l >> 4;
+  const int wa = 32 * (w >> 1), wb = 32 * (w & 1);
+  // staging: row sr, columns sc .. sc+7 (never across a block: ld % 16 == 0)
+  const int sr = tid >> 3, sc = 8 * (tid & 7);
+  const int ga = a0 + sc, gb = b0 + sc;
+  const bool aok = ga < pa, bok = gb < ld;
+  int64_t aoff = 0;
+  if (aok) {
+    const int blk = ga / ld;
+    aoff = (int64_t)blk * astride + (ga - blk * ld);
+  }
+  d4v acc[2][2];
+#pragma unroll
+  for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < 2; ++tj) acc[ti][tj] = d4v{0.0, 0.0, 0.0, 0.0};
+  double va[8], vb[8];
+  auto fetch = [&](int64_t r0) {
+    const int64_t r = r0 + sr;
+    if (r < re && aok) ld8<F32>(Abase, aoff + r * ld, va);
+    else
+#pragma unroll
+      for (int q = 0; q < 8; ++q) va[q] = 0.0;
+    if (r < re && bok) ld8<false>(B, r * ld + gb, vb);
+    else
+#pragma unroll
+      for (int q = 0; q < 8; ++q) vb[q] = 0.0;
+  };
+  fetch(rb);
+  for (int64_t r0 = rb; r0 < re; r0 += MG_RS) {
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      *reinterpret_cast<double2*>(&sA[sr][sc + 2 * q]) = make_double2(va[2 * q], va[2 * q + 1]);
+      *reinterpret_cast<double2*>(&sB[sr][sc + 2 * q]) = make_double2(vb[2 * q], vb[2 * q + 1]);
+    }
+    __syncthreads();
+    if (r0 + MG_RS < re) fetch(r0 + MG_RS);
+#pragma unroll
+    for (int ks = 0; ks < MG_RS / 4; ++ks) {
+      double av[2], bv[2];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        av[t] = sA[4 * ks + lk][wa + 16 * t + li];
+        bv[t] = sB[4 * ks + lk][wb + 16 * t + li];
+      }
+#pragma unroll
+      for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+        for (int tj = 0; tj < 2; ++tj)
+          acc[ti][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[ti], bv[tj], acc[ti][tj], 0, 0, 0);
+    }
+  }
+  double* P = part + (int64_t)blockIdx.z * pa * ld;
+#pragma unroll
+  for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int a = a0 + wa + 16 * ti + 4 * q + lk, b = b0 + wb + 16 * tj + li;
+        if (a < pa && b < ld) P[(int64_t)a * ld + b] = acc[ti][tj][q];
+      }
+}
+
+// out[r, b] = beta in[r, b] + alpha sum_a A[r, a] C[a, b] (row-major, ld
+// columns), one 64-row x 64-column tile per workgroup, 32 contraction
+// indices per stage; A is staged transposed so both operands are read
+// along their contiguous LDS rows.
+constexpr int MT_R = 64, MT_C = 64, MT_K = 32;
+template <bool F32>
+__global__ void __launch_bounds__(256)
+tsgemm_mfma_kernel(int64_t n, int ld, const void* __restrict__ Abase, int64_t astride, int nb,
+                   const double* __restrict__ C, const double* __restrict__ in, double* __restrict__ out,
+                   float* __restrict__ out32, double alpha, double beta, const int* __restrict__ flag) {
+  if (flag && *flag == 0) return;
+  __shared__ __align__(16) double sAT[MT_K][MT_R + 2];
+  __shared__ __align__(16) double sC[MT_K][MT_C + 2];
+  const int pa = nb * ld;
+  const int64_t r0 = (int64_t)blockIdx.x * MT_R;
+  const int b0 = blockIdx.y * MT_C;
+  const int tid = threadIdx.x;
+  const int w = tid >> 6, l = tid & 63, li = l & 15, lk = l >> 4;
+  const int wr = 32 * (w >> 1), wc = 32 * (w & 1);
+  const int ar = tid >> 2, ak = 8 * (tid & 3);     // A staging: row, 8 contraction indices
+  const int cr = tid >> 3, cc = 8 * (tid & 7);     // C staging: row, 8 columns
+  const int64_t arow = r0 + ar;
+  const bool cok = b0 + cc < ld;
+  d4v acc[2][2];
+#pragma unroll
+  for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < 2; ++tj) acc[ti][tj] = d4v{0.0, 0.0, 0.0, 0.0};
+  double va[8], vc[8];
+  auto fetch = [&](int a0) {
+    const int ga = a0 + ak;
+    if (arow < n && ga < pa) {
+      const int blk = ga / ld;
+      ld8<F32>(Abase, (int64_t)blk * astride + arow * ld + (ga - blk * ld), va);
+    } else {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) va[q] = 0.0;
+    }
+    const int gc = a0 + cr;
+    if (gc < pa && cok) ld8<false>(C, (int64_t)gc * ld + b0 + cc, vc);
+    else
+#pragma unroll
+      for (int q = 0; q < 8; ++q) vc[q] = 0.0;
+  };
+  fetch(0);
+  for (int a0 = 0; a0 < pa; a0 += MT_K) {
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 8; ++q) sAT[ak + q][ar] = va[q];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      *reinterpret_cast<double2*>(&sC[cr][cc + 2 * q]) = make_double2(vc[2 * q], vc[2 * q + 1]);
+    __syncthreads();
+    if (a0 + MT_K < pa) fetch(a0 + MT_K);
+#pragma unroll
+    for (int ks = 0; ks < MT_K / 4; ++ks) {
+      double av[2], bv[2];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        av[t] = sAT[4 * ks + lk][wr + 16 * t + li];
+        bv[t] = sC[4 * ks + lk][wc + 16 * t + li];
+      }
+#pragma unroll
+      for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+        for (int tj = 0; tj < 2; ++tj)
+          acc[ti][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[ti], bv[tj], acc[ti][tj], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int64_t r = r0 + wr + 16 * ti + 4 * q + lk;
+        const int b = b0 + wc + 16 * tj + li;
+        if (r < n && b < ld) {
+          double v = alpha * acc[ti][tj][q];
+          if (beta != 0.0) v += beta * in[r * ld + b];
+          out[r * ld + b] = v;
+          if (out32) out32[r * ld + b] = (float)v;
+        }
+      }
+}
+
 void launch_gram(int64_t n, int ld, BlockList A, const double* B, double* C, double* part,
                  const int* flag, hipStream_t st) {
   int nx, ny, nch;
@@ -142,7 +340,14 @@ void launch_gram(int64_t n, int ld, BlockList A, const double* B, double* C, dou
   gram_geometry(n, A.nb, ld, &nx, &ny, &nch, &rpc);
   dim3 grid(nx, ny, nch);
   kt_begin(KC_GRAM, st);
-  if (A.f32)
+  if (mfma_ok(ld)) {
+    if (A.f32)
+      hipLaunchKernelGGL(gram_mfma_kernel<true>, grid, dim3(256), 0, st, n, ld, A.base, A.stride, A.nb, B, part, rpc,
+                         flag);
+    else
+      hipLaunchKernelGGL(gram_mfma_kernel<false>, grid, dim3(256), 0, st, n, ld, A.base, A.stride, A.nb, B, part,
+                         rpc, flag);
+  } else if (A.f32)
     hipLaunchKernelGGL(gram_kernel<true>, grid, dim3(256), 0, st, n, ld, A.base, A.stride, A.nb, B,
                        part, rpc, flag);
   else
@@ -248,7 +453,15 @@ void launch_tsgemm(int64_t n, int ld, BlockList A, const double* C, const double
                    float* out32, double alpha, double beta, const int* flag, hipStream_t st) {
   dim3 grid((unsigned)((n + T_TR - 1) / T_TR), (ld + T_TB - 1) / T_TB);
   kt_begin(KC_TSGEMM, st);
-  if (A.f32)
+  if (mfma_ok(ld)) {
+    static_assert(MT_R == T_TR && MT_C == T_TB, "same tile grid");
+    if (A.f32)
+      hipLaunchKernelGGL(tsgemm_mfma_kernel<true>, grid, dim3(256), 0, st, n, ld, A.base, A.stride, A.nb, C, in, out,
+                         out32, alpha, beta, flag);
+    else
+      hipLaunchKernelGGL(tsgemm_mfma_kernel<false>, grid, dim3(256), 0, st, n, ld, A.base, A.stride, A.nb, C, in,
+                         out, out32, alpha, beta, flag);
+  } else if (A.f32)
     hipLaunchKernelGGL((tsgemm_kernel<true, false>), grid, dim3(256), 0, st, n, ld, ld, A.base, A.stride,
                        A.nb, C, ld, in, out, out32, alpha, beta, (int64_t)ld, (const int64_t*)nullptr,
                        flag);
@@ -275,6 +488,66 @@ void launch_assemble(int64_t n, int ld, int s, BlockList A, const double* U, int
                        (const int*)nullptr);
   GK_HIP(hipGetLastError());
   kt_end(st, (double)n * ((A.f32 ? 4.0 : 8.0) * ld * A.nb + 8.0 * s), 2.0 * (double)n * ld * s * A.nb);
+}
+
+// ------------------------------------------------------------- predictor
+// out[perm[r]] = sum_k sum_c A_k[r, c] z[k ld + c] (the GEMV of the kernel
+// machine predictor, HBM-bound): q lanes per row (a power of two with
+// 16 q >= ld), lane j reading float4 / double4 groups j, j + q, .. of each
+// block row (contiguous across the lanes of a row), float64 accumulation,
+// butterfly reduction over the q lanes.
+template <bool F32>
+__global__ void __launch_bounds__(256)
+predict_kernel(int64_t n, int ld, int q, const void* __restrict__ Abase, int64_t astride, int nb,
+               const double* __restrict__ z, double* __restrict__ out, const int64_t* __restrict__ perm) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t r = t / q;
+  const int j = (int)(t - r * q);
+  double acc = 0.0;
+  if (r < n) {
+    for (int k = 0; k < nb; ++k) {
+      const int64_t base = (int64_t)k * astride + r * ld;
+      const double* zk = z + (int64_t)k * ld;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int c = 4 * (j + q * u);
+        if (c < ld) {
+          double a0, a1, a2, a3;
+          if (F32) {
+            const float4 v = *reinterpret_cast<const float4*>(static_cast<const float*>(Abase) + base + c);
+            a0 = v.x; a1 = v.y; a2 = v.z; a3 = v.w;
+          } else {
+            const double2* p = reinterpret_cast<const double2*>(static_cast<const double*>(Abase) + base + c);
+            const double2 v0 = p[0], v1 = p[1];
+            a0 = v0.x; a1 = v0.y; a2 = v1.x; a3 = v1.y;
+          }
+          acc = fma(a0, zk[c], acc);
+          acc = fma(a1, zk[c + 1], acc);
+          acc = fma(a2, zk[c + 2], acc);
+          acc = fma(a3, zk[c + 3], acc);
+        }
+      }
+    }
+  }
+  for (int o = q >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+  if (r < n && j == 0) out[perm ? perm[r] : r] = acc;
+}
+
+void launch_predict(int64_t n, int ld, BlockList A, const double* z, double* out, const int64_t* perm,
+                    hipStream_t st) {
+  int q = 1;
+  while (16 * q < ld) q <<= 1;
+  GK_REQUIRE(q <= 64 && ld % 4 == 0, GK_EINVAL, "predictor: unsupported block width");
+  const int64_t tot = n * q;
+  kt_begin(KC_PREDICT, st);
+  if (A.f32)
+    hipLaunchKernelGGL(predict_kernel<true>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, n, ld, q, A.base,
+                       A.stride, A.nb, z, out, perm);
+  else
+    hipLaunchKernelGGL(predict_kernel<false>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, n, ld, q,
+                       A.base, A.stride, A.nb, z, out, perm);
+  GK_HIP(hipGetLastError());
+  kt_end(st, (double)n * ld * A.nb * (A.f32 ? 4.0 : 8.0) + 8.0 * n, 2.0 * (double)n * ld * A.nb);
 }
 
 // ------------------------------------------------- column-wise operations

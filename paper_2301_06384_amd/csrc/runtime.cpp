@@ -161,7 +161,7 @@ const char* const kKernelClassName[KC_COUNT] = {
     "spmm_diff",          "panel_gramv",     "panel_update_self", "panel_apply_self", "panel_apply_write",
     "panel_self",         "gram",            "tsgemm",            "arch_gram",        "arch_update",
     "reduce_parts",       "cholqr",          "omega",             "banded_factor",    "banded_solve",
-    "cheb_step",          "jacobi_eig",      "assemble"};
+    "cheb_step",          "jacobi_eig",      "assemble",          "predict"};
 struct KtRec {
   int cls;
   hipEvent_t a, b;

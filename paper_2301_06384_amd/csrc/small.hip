@@ -6,6 +6,7 @@
 // live in device memory; one workgroup owns one matrix, so these kernels
 // need no grid-wide synchronisation.
 #include "gk_internal.h"
+#include "tile64.h"
 
 namespace gk {
 
@@ -645,306 +646,9 @@ namespace gk {
 
 // ===================================================================
 // Small-matrix kernels for block widths up to 64: one workgroup of 256
-// threads, s x s operands staged in LDS (row pitch 65 doubles), products
-// register-blocked 4 x 4 per thread.
+// threads, s x s operands staged in LDS (row pitch 66 doubles), products
+// register-blocked 4 x 4 per thread (toolkit in tile64.h).
 // ===================================================================
-constexpr int WS = 64;
-constexpr int LP = WS + 2;   // even pitch: rows start 16-byte aligned
-constexpr int ST = 256;
-
-// acc = op(A) op(B) for the 4 x 4 block (rows 4ty.., cols 4tx..) of this
-// thread; op(A)[r][l] = TA ? A[l][r] : A[r][l], op(B)[l][c] = TB ? B[c][l] : B[l][c].
-template <bool TA, bool TB>
-__device__ __forceinline__ void lds_mm(const double (*A)[LP], const double (*B)[LP], int s, double (&acc)[4][4]) {
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
-#pragma unroll 4
-  for (int l = 0; l < s; ++l) {
-    double av[4], bv[4];
-    if (TA) {
-      // contiguous along the output row index: two 16-byte reads
-      const double2 a01 = *reinterpret_cast<const double2*>(&A[l][4 * ty]);
-      const double2 a23 = *reinterpret_cast<const double2*>(&A[l][4 * ty + 2]);
-      av[0] = a01.x; av[1] = a01.y; av[2] = a23.x; av[3] = a23.y;
-    } else {
-#pragma unroll
-      for (int i = 0; i < 4; ++i) av[i] = A[4 * ty + i][l];
-    }
-    if (!TB) {
-      const double2 b01 = *reinterpret_cast<const double2*>(&B[l][4 * tx]);
-      const double2 b23 = *reinterpret_cast<const double2*>(&B[l][4 * tx + 2]);
-      bv[0] = b01.x; bv[1] = b01.y; bv[2] = b23.x; bv[3] = b23.y;
-    } else {
-#pragma unroll
-      for (int j = 0; j < 4; ++j) bv[j] = B[4 * tx + j][l];
-    }
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) acc[i][j] = fma(av[i], bv[j], acc[i][j]);
-  }
-}
-
-// D[i][c] = src[i * lds + c] for i, c < s and 0 elsewhere in the 64 x 64
-// tile (256 threads).  All loads are issued before the LDS stores.
-__device__ __forceinline__ void fetch64(const double* __restrict__ src, int s, int lds, double (&v)[16]) {
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const int i = ty + 16 * a, c = tx + 16 * b;
-      v[4 * a + b] = (src && i < s && c < s) ? src[i * lds + c] : 0.0;
-    }
-}
-__device__ __forceinline__ void put64(double (*D)[LP], const double (&v)[16]) {
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) D[ty + 16 * a][tx + 16 * b] = v[4 * a + b];
-}
-// D[c][i] = v (the transpose of what put64 stores)
-__device__ __forceinline__ void put64T(double (*D)[LP], const double (&v)[16]) {
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) D[tx + 16 * b][ty + 16 * a] = v[4 * a + b];
-}
-__device__ __forceinline__ void stage64(double (*D)[LP], const double* __restrict__ src, int s, int lds) {
-  double v[16];
-  fetch64(src, s, lds, v);
-  put64(D, v);
-}
-
-// Lower Cholesky of the symmetric A (s x s, lower part used) together with
-// Y = L^{-1}, blocked by 16 (256 threads):
-//   for each diagonal block b:  A_bb = L_bb L_bb^T and Y_bb = L_bb^{-1}
-//   (one wavefront, registers and lane shuffles);  then
-//   L_ib = A_ib Y_bb^T,  Y_b = Y_bb Z_b,  A_ij -= L_ib L_jb^T,  Z_i -= L_ib Y_b
-//   for the block rows i, j > b, where Z (= I initially) carries the
-//   right-hand sides of L Y = I.
-// Inside a diagonal block the pivots follow the rules of `mode`:
-//   0: plain (non-positive pivot -> *bad = 3, pivot 1 used);
-//   1 / 2: the CholQR deflation rules (see cholqr_factor_kernel).
-// Deflated columns give zero columns of L and zero rows of Y.  Indices s..63
-// are padded with an identity block.  Z is clobbered.
-// 1/sqrt(p) for p > 0: hardware estimate refined by two Newton steps.
-__device__ __forceinline__ double rsqrt_nr(double p) {
-  double y = __builtin_amdgcn_rsq(p);
-  y = y * fma(-0.5 * p * y, y, 1.5);
-  y = y * fma(-0.5 * p * y, y, 1.5);
-  return y;
-}
-
-// Pivot rule of column j (global index gj): returns l_jj and 1 / l_jj (0 for
-// a deflated column).  gjj = original Gram diagonal (mode 1), dpj = first-pass
-// diagonal (mode 2).
-template <int MODE>
-__device__ __forceinline__ void chol_pivot(double piv, int gj, int s, double gjj, double dpj, double thr, int* bad,
-                                           double& l, double& inv) {
-  if (gj >= s) { l = 1.0; inv = 1.0; return; }
-  if (MODE == 0) {
-    if (!(piv > 0.0)) {
-      if (bad) *bad = 3;
-      l = 1.0; inv = 1.0;
-      return;
-    }
-    inv = rsqrt_nr(piv);
-    l = piv * inv;
-  } else if (MODE == 1) {
-    const double eta = 1e-7;
-    if (gjj > thr * thr) {
-      const double pp = fmax(piv, eta * eta * gjj);
-      inv = rsqrt_nr(pp);
-      l = pp * inv;
-    } else {
-      l = 0.0; inv = 0.0;
-    }
-  } else {
-    l = 0.0; inv = 0.0;
-    if (piv > 0.0) {
-      const double y = rsqrt_nr(piv);
-      const double ll = piv * y;
-      if (!(ll * dpj < thr)) { l = ll; inv = y; }
-    }
-  }
-}
-
-typedef double dv4 __attribute__((ext_vector_type(4)));
-
-__device__ __forceinline__ double readlane_d(double v, int lane) {
-  const unsigned long long u = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_readlane((int)(u & 0xffffffffu), lane);
-  const int hi = __builtin_amdgcn_readlane((int)(u >> 32), lane);
-  return __longlong_as_double(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
-}
-
-// One pivot step J of the 16 x 16 diagonal-block factorisation by wavefront
-// 0.  Lane c (< 16) holds column c of the block (a, both triangles) and column
-// c of its inverse (y).  With symmetric storage lane c already holds
-// L[c][J] = a[J] / l_JJ; the column is exchanged through a 16-entry LDS
-// buffer (one write per lane, broadcast reads; the wavefront executes its LDS
-// accesses in order, so no barrier is involved).
-template <int MODE, int J>
-struct DiagStep {
-  __device__ __forceinline__ static void run(double (&a)[16], double (&y)[16], int c, int o, int s, const double* g0,
-                                             const double* dprev, double thr, int* bad, double* dg,
-                                             double* colbuf) {
-    const double piv = readlane_d(a[J], J);
-    const double gjj = (MODE == 1 && o + J < s) ? g0[o + J] : 0.0;
-    const double dpj = (MODE == 2 && o + J < s) ? dprev[o + J] : 0.0;
-    double ljj, inv;
-    chol_pivot<MODE>(piv, o + J, s, gjj, dpj, thr, bad, ljj, inv);
-    if (dg && threadIdx.x == 0) dg[o + J] = (o + J < s) ? ljj : 0.0;
-    const double lcj = a[J] * inv;     // L[c][J] (used for c > J)
-    if (threadIdx.x < 16) colbuf[c] = lcj;
-    if (c == J) {
-#pragma unroll
-      for (int r = J + 1; r < 16; ++r) a[r] *= inv;
-      a[J] = ljj;
-    }
-    y[J] *= inv;                       // row J of the inverse
-#pragma unroll
-    for (int r = J + 1; r < 16; ++r) {
-      const double lrj = colbuf[r];    // L[r][J]
-      if (c > J) a[r] -= lrj * lcj;
-      y[r] -= lrj * y[J];
-    }
-    DiagStep<MODE, J + 1>::run(a, y, c, o, s, g0, dprev, thr, bad, dg, colbuf);
-  }
-};
-template <int MODE>
-struct DiagStep<MODE, 16> {
-  __device__ __forceinline__ static void run(double (&)[16], double (&)[16], int, int, int, const double*,
-                                             const double*, double, int*, double*, double*) {}
-};
-
-// 16 x 16 tile product on FP64 matrix cores (v_mfma_f64_16x16x4f64, lane
-// l = i + 16 k holds A[i][k] and B[k][i]; register r holds D[4 r + k][i]):
-// acc += op(A) op(B) with op(A)[i][k] = TA ? A[ra + k][ca + i] : A[ra + i][ca + k]
-// and op(B)[k][j] = TB ? B[rb + j][cb + k] : B[rb + k][cb + j].
-template <bool TA, bool TB>
-__device__ __forceinline__ dv4 mma_tile(const double (*A)[LP], int ra, int ca, const double (*B)[LP], int rb, int cb,
-                                        dv4 acc) {
-  const int l = threadIdx.x & 63, i = l & 15, k = l >> 4;
-#pragma unroll
-  for (int ks = 0; ks < 4; ++ks) {
-    const int kk = 4 * ks + k;
-    const double av = TA ? A[ra + kk][ca + i] : A[ra + i][ca + kk];
-    const double bv = TB ? B[rb + i][cb + kk] : B[rb + kk][cb + i];
-    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
-  }
-  return acc;
-}
-__device__ __forceinline__ dv4 tile_load(const double (*A)[LP], int r0, int c0) {
-  const int l = threadIdx.x & 63, i = l & 15, k = l >> 4;
-  return dv4{A[r0 + k][c0 + i], A[r0 + 4 + k][c0 + i], A[r0 + 8 + k][c0 + i], A[r0 + 12 + k][c0 + i]};
-}
-__device__ __forceinline__ void tile_store(double (*A)[LP], int r0, int c0, dv4 v) {
-  const int l = threadIdx.x & 63, i = l & 15, k = l >> 4;
-#pragma unroll
-  for (int r = 0; r < 4; ++r) A[r0 + 4 * r + k][c0 + i] = v[r];
-}
-
-template <int MODE>
-__device__ __forceinline__ void blk_chol_inv_t(double (*A)[LP], double (*Y)[LP], double (*Z)[LP], int s, const double* g0,
-                               const double* dprev, double thr, double* dg, int* bad) {
-  __shared__ double colbuf[16];
-  const int tid = threadIdx.x;
-  const int wv = tid >> 6;
-  const int nbk = (s + 15) >> 4;
-  const int S16 = nbk << 4;
-  // pad A with an identity block, Z = I, Y = 0
-  for (int r = tid >> 4; r < S16; r += 16)
-    for (int c = tid & 15; c < S16; c += 16) {
-      if (r >= s || c >= s) A[r][c] = (r == c) ? 1.0 : 0.0;
-      Z[r][c] = (r == c) ? 1.0 : 0.0;
-      Y[r][c] = 0.0;
-    }
-  __syncthreads();
-  for (int b = 0; b < nbk; ++b) {
-    const int o = 16 * b;
-    const int T = nbk - 1 - b;                 // tile rows below the diagonal block
-    // ---- diagonal block: wavefront 0, lane c < 16 holds column c
-    if (tid < 64) {
-      const int c = tid & 15;
-      double a[16], y[16];
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        a[r] = A[o + r][o + c];
-        y[r] = (r == c) ? 1.0 : 0.0;
-      }
-      DiagStep<MODE, 0>::run(a, y, c, o, s, g0, dprev, thr, bad, dg, colbuf);
-      if (tid < 16) {
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          A[o + r][o + c] = (r >= c) ? a[r] : 0.0;
-          Z[o + r][o + c] = (r >= c) ? y[r] : 0.0;   // Y_bb, kept in the diagonal block of Z
-          Y[o + r][o + c] = (r >= c) ? y[r] : 0.0;
-        }
-      }
-    }
-    __syncthreads();
-    // ---- panel: L_ib = A_ib Y_bb^T (i > b, written after a barrier: in place)
-    //      and Y_b[:, c] = Y_bb Z_b[:, c] (c < b)
-    {
-      dv4 res = dv4{0.0, 0.0, 0.0, 0.0};
-      const int task = wv;                     // at most 3 panel tiles + 3 inverse tiles
-      const int ntask = T + b;
-      dv4 res2 = dv4{0.0, 0.0, 0.0, 0.0};
-      if (task < ntask) {
-        if (task < T) res = mma_tile<false, true>(A, o + 16 * (1 + task), o, Z, o, o, res);
-        else tile_store(Y, o, 16 * (task - T), mma_tile<false, false>(Z, o, o, Z, o, 16 * (task - T), res));
-      }
-      if (task + 4 < ntask) {
-        const int t2 = task + 4;
-        if (t2 < T) res2 = mma_tile<false, true>(A, o + 16 * (1 + t2), o, Z, o, o, res2);
-        else tile_store(Y, o, 16 * (t2 - T), mma_tile<false, false>(Z, o, o, Z, o, 16 * (t2 - T), res2));
-      }
-      __syncthreads();
-      if (task < T) tile_store(A, o + 16 * (1 + task), o, res);
-      if (task + 4 < T) tile_store(A, o + 16 * (1 + task + 4), o, res2);
-    }
-    __syncthreads();
-    // ---- trailing: A_ij -= L_ib L_jb^T (b < j <= i), Z_i[:, c] -= L_ib Y_b[:, c] (c <= b)
-    {
-      const int na = T * (T + 1) / 2;
-      const int nz = T * (b + 1);
-      for (int task = wv; task < na + nz; task += 4) {
-        if (task < na) {
-          int ii = 0, rem = task;
-          while (rem > ii) { rem -= ii + 1; ++ii; }
-          const int ti = b + 1 + ii, tj = b + 1 + rem;     // tile (ti, tj), tj <= ti
-          const dv4 p = mma_tile<false, true>(A, 16 * ti, o, A, 16 * tj, o, dv4{0.0, 0.0, 0.0, 0.0});
-          tile_store(A, 16 * ti, 16 * tj, tile_load(A, 16 * ti, 16 * tj) - p);
-        } else {
-          const int q = task - na;
-          const int ti = b + 1 + q / (b + 1), tc = q % (b + 1);
-          const dv4 p = mma_tile<false, false>(A, 16 * ti, o, Y, o, 16 * tc, dv4{0.0, 0.0, 0.0, 0.0});
-          tile_store(Z, 16 * ti, 16 * tc, tile_load(Z, 16 * ti, 16 * tc) - p);
-        }
-      }
-    }
-    __syncthreads();
-  }
-  // strict upper part of L is zero
-  for (int r = tid >> 4; r < S16; r += 16)
-    for (int c = tid & 15; c < S16; c += 16)
-      if (c > r) A[r][c] = 0.0;
-  __syncthreads();
-}
-
-__device__ __forceinline__ void blk_chol_inv(double (*A)[LP], double (*Y)[LP], double (*Z)[LP], int s, int mode, const double* g0,
-                             const double* dprev, double thr, double* dg, int* bad) {
-  if (mode == 0) blk_chol_inv_t<0>(A, Y, Z, s, g0, dprev, thr, dg, bad);
-  else if (mode == 1) blk_chol_inv_t<1>(A, Y, Z, s, g0, dprev, thr, dg, bad);
-  else blk_chol_inv_t<2>(A, Y, Z, s, g0, dprev, thr, dg, bad);
-}
 
 // CholQR factor of a Gram matrix (ld <= 64), 256 threads.
 //   pass 1: R1 = chol(G) with clamped pivots, R1inv, diag_out = diag(R1)
@@ -1351,7 +1055,7 @@ omega_kernel(int k, int s, int ld, const double* __restrict__ Wk, const double* 
 // archive limits the attainable orthogonality); the two local blocks are
 // always at floor_loc.
 __global__ void __launch_bounds__(ST)
-omega_decide_kernel(int k, int s, int nj, const double* __restrict__ est_part, double tau, double floor_re,
+omega_decide_kernel(int k, int s, int nj, int ne, const double* __restrict__ est_part, double tau, double floor_re,
                     double floor_loc, double* __restrict__ Wk1, int* __restrict__ fr, int* __restrict__ forced,
                     double* __restrict__ est_out, int* __restrict__ nre) {
   __shared__ int go_sh;
@@ -1359,7 +1063,7 @@ omega_decide_kernel(int k, int s, int nj, const double* __restrict__ est_part, d
   const int ss = s * s;
   if (tid == 0) {
     double e = 0.0;
-    for (int j = 0; j < nj; ++j) e = fmax(e, est_part[j]);
+    for (int j = 0; j < ne; ++j) e = fmax(e, est_part[j]);
     const int f = forced[k];
     const int go = (e > tau || f) ? 1 : 0;
     fr[k] = go;
@@ -1388,6 +1092,11 @@ namespace gk {
 
 bool small_wave_ok(int ld) { return ld <= WS; }
 
+int omega_est_per_block(int s) {
+  const int nq = (s + WS - 1) / WS;
+  return s > WS ? nq * nq : 1;
+}
+
 void launch_cholqr_reg(const double* G, int ld, int s, int pass, const double* diag_prev, double thr, double* R,
                        double* Rinv, double* diag_out, int* n_defl, const double* R1, const double* R1inv, double* Rc,
                        double* Bout, hipStream_t st) {
@@ -1410,16 +1119,24 @@ void launch_cholqr_flag(const double* G, int ld, int s, int pass, const double* 
 
 void launch_omega(int k, int s, int ld, const double* Wk, const double* Wkm1, double* Wk1, const double* Hd,
                   const double* Bd, const double* Rc, double nu, double tau, double floor_re, double floor_loc,
-                  double* est_part, int* fr, int* forced, double* est_out, int* nre, hipStream_t st) {
+                  double* est_part, int* fr, int* forced, double* est_out, int* nre, double* rhs_wide,
+                  hipStream_t st) {
   const int nj = k - 1;   // recurrence for j <= k-2
   if (nj > 0) {
-    kt_begin(KC_OMEGA, st);
-    hipLaunchKernelGGL(omega_kernel, dim3(nj), dim3(ST), 0, st, k, s, ld, Wk, Wkm1, Wk1, Hd, Bd, Rc, nu, est_part);
-    GK_HIP(hipGetLastError());
-    kt_end(st, 8.0 * 10 * nj * (double)s * s, 12.0 * nj * (double)s * s * s);
+    if (s > WS) {
+      GK_REQUIRE(rhs_wide, GK_EINVAL, "wide orthogonality estimate needs its scratch");
+      launch_omega_wide(k, s, ld, Wk, Wkm1, Wk1, Hd, Bd, Rc, nu, rhs_wide, est_part, st);
+    } else {
+      kt_begin(KC_OMEGA, st);
+      hipLaunchKernelGGL(omega_kernel, dim3(nj), dim3(ST), 0, st, k, s, ld, Wk, Wkm1, Wk1, Hd, Bd, Rc, nu,
+                         est_part);
+      GK_HIP(hipGetLastError());
+      kt_end(st, 8.0 * 10 * nj * (double)s * s, 12.0 * nj * (double)s * s * s);
+    }
   }
-  hipLaunchKernelGGL(omega_decide_kernel, dim3(1), dim3(ST), 0, st, k, s, nj > 0 ? nj : 0, est_part, tau, floor_re,
-                     floor_loc, Wk1, fr, forced, est_out, nre);
+  const int ne = nj > 0 ? nj * omega_est_per_block(s) : 0;
+  hipLaunchKernelGGL(omega_decide_kernel, dim3(1), dim3(ST), 0, st, k, s, nj > 0 ? nj : 0, ne, est_part, tau,
+                     floor_re, floor_loc, Wk1, fr, forced, est_out, nre);
   GK_HIP(hipGetLastError());
 }
 

@@ -197,18 +197,38 @@ def test_block_widths(s):
         assert rel(P, ref) < TOL[prec], (prec, rel(P, ref))
 
 
-@pytest.mark.parametrize("s", [72, 100, 128])
+@pytest.mark.parametrize("s", [72, 100, 128, 200])
 @pytest.mark.parametrize("phi", [dict(kind="spline", eps=0.02, k=2.0), dict(kind="diffusion", t=0.7)])
 def test_wide_blocks(s, phi):
-    # block widths above 64: generic orthogonalisation kernels, full
-    # reorthogonalisation in both precisions, global small factorisations
+    # block widths above 64: the small factors run on 64 x 64 tiles (CholQR,
+    # orthogonality estimate, banded spline); float64 reorthogonalises fully,
+    # the mixed path partially (estimate-driven) unless asked for full
     L, g = G("rgg2003")
     W = I.samples(L.n, s, 90 + s)
-    ref = krylov.cbl(L.to_scipy(), W, phi, 10)["P"]
-    for prec in ("fp64", "mixed"):
-        P, K, st = gk.krylov_kernel_columns(g, W, phi, 10, "cbl", prec)
-        assert rel(P, ref) < TOL[prec], (prec, rel(P, ref))
-        assert st.n_reorth == 9
+    m = 10 if s <= 128 else 6
+    ref = krylov.cbl(L.to_scipy(), W, phi, m)["P"]
+    for prec, flags in (("fp64", 0), ("mixed", 0), ("mixed", gk.FULL_REORTH)):
+        P, K, st = gk.krylov_kernel_columns(g, W, phi, m, "cbl", prec, flags=flags)
+        assert rel(P, ref) < TOL[prec], (prec, flags, rel(P, ref))
+        if prec == "fp64" or flags:
+            assert st.n_reorth == m - 1
+        else:
+            assert 0 <= st.n_reorth <= m - 2
+        if phi["kind"] == "spline":
+            assert st.as_dict()["phi_method"] == "banded"
+
+
+@pytest.mark.parametrize("s", [100, 192])
+def test_wide_banded_spline_matches_spectral(s):
+    # the tiled banded evaluation of (eps I + H_m)^(-k) F_1 against the
+    # spectral decomposition of H_m on the same Krylov blocks
+    L, g = G("rgg2003")
+    W = I.samples(L.n, s, 7)
+    phi = dict(kind="spline", eps=0.05, k=3.0)
+    Pb, Kb, sb = gk.krylov_kernel_columns(g, W, phi, 6, "cbl", "fp64")
+    Pe, Ke, se = gk.krylov_kernel_columns(g, W, phi, 6, "cbl", "fp64", flags=gk.PHI_EIG)
+    assert sb.as_dict()["phi_method"] == "banded" and se.as_dict()["phi_method"] == "eig"
+    assert rel(Pb, Pe) < 1e-11 and rel(Kb, Ke) < 1e-11
 
 
 def test_single_sample_variants_coincide_gpu():
