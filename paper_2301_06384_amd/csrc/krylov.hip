@@ -501,7 +501,7 @@ static void run_cbl(Job& J) {
           if (pan)
             launch_panel(PM_SELF, n, ld, 0, X, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, ppart, G, st, fk);
           else
-            launch_gram(n, ld, xl, X, G, part_all, fk, st);
+            launch_gram(n, ld, xl, X, G, part, fk, st);   // one-block Gram: `part` covers it
           if (wave)
             launch_cholqr_flag(G, ld, s, 1, nullptr, J.thr(), R1, R1i, d1, nullptr, nullptr, nullptr, nullptr, nullptr,
                                fk, st);
@@ -512,7 +512,7 @@ static void run_cbl(Job& J) {
             launch_panel(PM_APPLY_SELF, n, ld, 0, X, nullptr, nullptr, nullptr, nullptr, nullptr, R1i, ppart, G, st, fk);
           } else {
             launch_tsgemm(n, ld, xl, R1i, nullptr, Y, nullptr, 1.0, 0.0, fk, st);
-            launch_gram(n, ld, BlockList{Y, blk, 1, false}, Y, G, part_all, fk, st);
+            launch_gram(n, ld, BlockList{Y, blk, 1, false}, Y, G, part, fk, st);
           }
           if (wave)
             launch_cholqr_flag(G, ld, s, 2, d1, J.thr(), R2, R2i, d2, nullptr, R1, R1i, R12i, Bd + (int64_t)k * s * s,
