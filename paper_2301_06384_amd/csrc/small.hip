@@ -646,8 +646,8 @@ namespace gk {
 
 // ===================================================================
 // Small-matrix kernels for block widths up to 64: one workgroup of 256
-// threads, s x s operands staged in LDS (row pitch 66 doubles), products
-// register-blocked 4 x 4 per thread (toolkit in tile64.h).
+// threads, s x s operands staged in LDS (row pitch 66 doubles), products on
+// the FP64 matrix cores (toolkit in tile64.h).
 // ===================================================================
 
 // CholQR factor of a Gram matrix (ld <= 64), 256 threads.
@@ -716,7 +716,7 @@ cholqr_blk_kernel(const double* __restrict__ G, int ld, int s, int pass, const d
     for (int i = 0; i < 4; ++i)
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const int r = 4 * ty + i, c = 4 * tx + j;
+        const int r = acc_row(i), c = acc_col(j);
         if (r < s && c < s) {
           const double u = S1[r][c];
           const double w = (c > r) ? -mm[i][j] : (c == r ? -0.5 * mm[i][j] : 0.0);
@@ -762,7 +762,7 @@ cholqr_blk_kernel(const double* __restrict__ G, int ld, int s, int pass, const d
     for (int i = 0; i < 4; ++i)
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const int r = 4 * ty + i, c = 4 * tx + j;
+        const int r = acc_row(i), c = acc_col(j);
         if (r < s && c < s) Bout[r * s + c] = acc[i][j];
       }
     __syncthreads();
@@ -775,7 +775,7 @@ cholqr_blk_kernel(const double* __restrict__ G, int ld, int s, int pass, const d
     for (int i = 0; i < 4; ++i)
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const int r = 4 * ty + i, c = 4 * tx + j;
+        const int r = acc_row(i), c = acc_col(j);
         if (r < ld && c < ld) Rc[r * ld + c] = (r < s && c < s) ? acc[i][j] : 0.0;
       }
   }
@@ -815,7 +815,7 @@ banded_factor_blk_kernel(int m, int s, const double* __restrict__ Hd, const doub
       for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int jj = 0; jj < 4; ++jj) {
-          const int r = 4 * ty + i, c = 4 * tx + jj;
+          const int r = acc_row(i), c = acc_col(jj);
           if (r < s && c < s) A[r][c] -= acc[i][jj];
         }
       __syncthreads();
@@ -840,7 +840,7 @@ banded_factor_blk_kernel(int m, int s, const double* __restrict__ Hd, const doub
       for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int jj = 0; jj < 4; ++jj) {
-          const int r = 4 * ty + i, c = 4 * tx + jj;
+          const int r = acc_row(i), c = acc_col(jj);
           Ls[c][r] = (r < s && c < s) ? acc[i][jj] : 0.0;   // kept transposed
           if (r < s && c < s) LsG[r * s + c] = acc[i][jj];
         }
@@ -923,7 +923,7 @@ banded_solve_kernel(int m, int s, int kpow, const double* __restrict__ Linv_all,
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int jj = 0; jj < 4; ++jj) T[4 * ty + i][4 * tx + jj] -= acc[i][jj];
+        for (int jj = 0; jj < 4; ++jj) T[acc_row(i)][acc_col(jj)] -= acc[i][jj];
       __syncthreads();
     }
     lds_mm<true, false>(SI, T, s, acc);     // Linv_j T (forward) or Linv_j^T T (backward)
@@ -933,7 +933,7 @@ banded_solve_kernel(int m, int s, int kpow, const double* __restrict__ Linv_all,
     for (int i = 0; i < 4; ++i)
 #pragma unroll
       for (int jj = 0; jj < 4; ++jj) {
-        const int r = 4 * ty + i, c = 4 * tx + jj;
+        const int r = acc_row(i), c = acc_col(jj);
         const double v = (r < s && c < s) ? acc[i][jj] : 0.0;
         SY[r][c] = v;
         if (r < s && c < s) Y[r * s + c] = v;
@@ -1022,7 +1022,7 @@ omega_kernel(int k, int s, int ld, const double* __restrict__ Wk, const double* 
   for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
-      const int r = 4 * ty + a, c = 4 * tx + b;
+      const int r = acc_row(a), c = acc_col(b);
       S3[r][c] = (r < s && c < s) ? tot[a][b] + copysign(nu, tot[a][b]) : 0.0;
     }
   __syncthreads();
@@ -1033,7 +1033,7 @@ omega_kernel(int k, int s, int ld, const double* __restrict__ Wk, const double* 
   for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
-      const int r = 4 * ty + a, c = 4 * tx + b;
+      const int r = acc_row(a), c = acc_col(b);
       if (r < s && c < s) {
         out[r * s + c] = acc[a][b];
         mx = fmax(mx, fabs(acc[a][b]));

@@ -11,40 +11,61 @@ constexpr int WS = 64;
 constexpr int LP = WS + 2;   // even pitch: rows start 16-byte aligned
 constexpr int ST = 256;
 
-// acc = op(A) op(B) for the 4 x 4 block (rows 4ty.., cols 4tx..) of this
-// thread; op(A)[r][l] = TA ? A[l][r] : A[r][l], op(B)[l][c] = TB ? B[c][l] : B[l][c].
+typedef double dv4 __attribute__((ext_vector_type(4)));
+
+// Output layout of lds_mm (the FP64 matrix-core tile layout): this thread's
+// acc[a][b] is element (acc_row(a), acc_col(b)) of the 64 x 64 product.
+__device__ __forceinline__ int acc_row(int a) {
+  return 16 * (int)(threadIdx.x >> 6) + 4 * a + (int)((threadIdx.x & 63) >> 4);
+}
+__device__ __forceinline__ int acc_col(int b) { return 16 * b + (int)(threadIdx.x & 15); }
+
+// NT steps of four contraction indices (rows 4t + k, masked at s) of the
+// product below.
+template <int NT>
+__device__ __forceinline__ void mm_steps(const double (*A)[LP], const double (*B)[LP], int s, dv4 (&d)[4]) {
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63, li = l & 15, lk = l >> 4;
+  double av[2], bv[2][4];
+  // operands of step t are loaded while the MFMAs of step t - 1 run
+  av[0] = A[lk][16 * w + li];
+#pragma unroll
+  for (int b = 0; b < 4; ++b) bv[0][b] = B[lk][16 * b + li];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int cur = t & 1, nxt = cur ^ 1;
+    if (t + 1 < NT) {
+      const int kn = 4 * (t + 1) + lk;
+      av[nxt] = A[kn][16 * w + li];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) bv[nxt][b] = B[kn][16 * b + li];
+    }
+    const bool in = 4 * t + lk < s;
+    const double a = in ? av[cur] : 0.0;
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+      d[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, in ? bv[cur][b] : 0.0, d[b], 0, 0, 0);
+  }
+}
+
+// acc = A^T B summed over the first s rows of two 64 x 64 LDS operands
+// (256 threads).  Wave w computes output rows 16w .. 16w+15 as four 16 x 16
+// tiles of v_mfma_f64_16x16x4f64: lane l = i + 16k holds A[4t+k][16w+i] and
+// B[4t+k][16b+i]; accumulator register a holds row 4a + k, column i.  Rows at
+// and beyond s are masked, so no zero padding of the operands is assumed.
 template <bool TA, bool TB>
 __device__ __forceinline__ void lds_mm(const double (*A)[LP], const double (*B)[LP], int s, double (&acc)[4][4]) {
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  static_assert(TA && !TB, "products run as A^T B");
+  dv4 d[4];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int b = 0; b < 4; ++b) d[b] = dv4{0.0, 0.0, 0.0, 0.0};
+  if (s > 48) mm_steps<16>(A, B, s, d);
+  else if (s > 32) mm_steps<12>(A, B, s, d);
+  else if (s > 16) mm_steps<8>(A, B, s, d);
+  else mm_steps<4>(A, B, s, d);
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
-#pragma unroll 4
-  for (int l = 0; l < s; ++l) {
-    double av[4], bv[4];
-    if (TA) {
-      // contiguous along the output row index: two 16-byte reads
-      const double2 a01 = *reinterpret_cast<const double2*>(&A[l][4 * ty]);
-      const double2 a23 = *reinterpret_cast<const double2*>(&A[l][4 * ty + 2]);
-      av[0] = a01.x; av[1] = a01.y; av[2] = a23.x; av[3] = a23.y;
-    } else {
+  for (int a = 0; a < 4; ++a)
 #pragma unroll
-      for (int i = 0; i < 4; ++i) av[i] = A[4 * ty + i][l];
-    }
-    if (!TB) {
-      const double2 b01 = *reinterpret_cast<const double2*>(&B[l][4 * tx]);
-      const double2 b23 = *reinterpret_cast<const double2*>(&B[l][4 * tx + 2]);
-      bv[0] = b01.x; bv[1] = b01.y; bv[2] = b23.x; bv[3] = b23.y;
-    } else {
-#pragma unroll
-      for (int j = 0; j < 4; ++j) bv[j] = B[4 * tx + j][l];
-    }
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) acc[i][j] = fma(av[i], bv[j], acc[i][j]);
-  }
+    for (int b = 0; b < 4; ++b) acc[a][b] = d[b][a];
 }
 
 // D[i][c] = src[i * lds + c] for i, c < s and 0 elsewhere in the 64 x 64
@@ -106,35 +127,31 @@ __device__ __forceinline__ double rsqrt_nr(double p) {
 template <int MODE>
 __device__ __forceinline__ void chol_pivot(double piv, int gj, int s, double gjj, double dpj, double thr, int* bad,
                                            double& l, double& inv) {
-  if (gj >= s) { l = 1.0; inv = 1.0; return; }
+  // branch-free: the reciprocal square root is taken of a safe argument and
+  // the rule selects the result
   if (MODE == 0) {
-    if (!(piv > 0.0)) {
-      if (bad) *bad = 3;
-      l = 1.0; inv = 1.0;
-      return;
-    }
-    inv = rsqrt_nr(piv);
-    l = piv * inv;
+    const bool ok = piv > 0.0;
+    const double y = rsqrt_nr(ok ? piv : 1.0);
+    l = ok ? piv * y : 1.0;
+    inv = ok ? y : 1.0;
+    if (!ok && gj < s && bad) *bad = 3;
   } else if (MODE == 1) {
     const double eta = 1e-7;
-    if (gjj > thr * thr) {
-      const double pp = fmax(piv, eta * eta * gjj);
-      inv = rsqrt_nr(pp);
-      l = pp * inv;
-    } else {
-      l = 0.0; inv = 0.0;
-    }
+    const bool keep = gjj > thr * thr;
+    const double pp = keep ? fmax(piv, eta * eta * gjj) : 1.0;
+    const double y = rsqrt_nr(pp);
+    l = keep ? pp * y : 0.0;
+    inv = keep ? y : 0.0;
   } else {
-    l = 0.0; inv = 0.0;
-    if (piv > 0.0) {
-      const double y = rsqrt_nr(piv);
-      const double ll = piv * y;
-      if (!(ll * dpj < thr)) { l = ll; inv = y; }
-    }
+    const bool pos = piv > 0.0;
+    const double y = rsqrt_nr(pos ? piv : 1.0);
+    const double ll = piv * y;
+    const bool keep = pos && !(ll * dpj < thr);
+    l = keep ? ll : 0.0;
+    inv = keep ? y : 0.0;
   }
+  if (gj >= s) { l = 1.0; inv = 1.0; }   // identity padding
 }
-
-typedef double dv4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ double readlane_d(double v, int lane) {
   const unsigned long long u = __double_as_longlong(v);
@@ -146,41 +163,36 @@ __device__ __forceinline__ double readlane_d(double v, int lane) {
 // One pivot step J of the 16 x 16 diagonal-block factorisation by wavefront
 // 0.  Lane c (< 16) holds column c of the block (a, both triangles) and column
 // c of its inverse (y).  With symmetric storage lane c already holds
-// L[c][J] = a[J] / l_JJ; the column is exchanged through a 16-entry LDS
-// buffer (one write per lane, broadcast reads; the wavefront executes its LDS
-// accesses in order, so no barrier is involved).
+// L[c][J] = a[J] / l_JJ: it stores that entry of column J of L straight into
+// the LDS tile (zeros above the diagonal), and every lane reads the column
+// back for its update (a wavefront executes its LDS accesses in order, so no
+// barrier is involved).
 template <int MODE, int J>
 struct DiagStep {
-  __device__ __forceinline__ static void run(double (&a)[16], double (&y)[16], int c, int o, int s, const double* g0,
-                                             const double* dprev, double thr, int* bad, double* dg,
-                                             double* colbuf) {
+  __device__ __forceinline__ static void run(double (&a)[16], double (&y)[16], int c, int o, int s, double gl,
+                                             double dl, double thr, int* bad, double* dg, double (*A)[LP]) {
     const double piv = readlane_d(a[J], J);
-    const double gjj = (MODE == 1 && o + J < s) ? g0[o + J] : 0.0;
-    const double dpj = (MODE == 2 && o + J < s) ? dprev[o + J] : 0.0;
+    const double gjj = MODE == 1 ? readlane_d(gl, J) : 0.0;
+    const double dpj = MODE == 2 ? readlane_d(dl, J) : 0.0;
     double ljj, inv;
     chol_pivot<MODE>(piv, o + J, s, gjj, dpj, thr, bad, ljj, inv);
     if (dg && threadIdx.x == 0) dg[o + J] = (o + J < s) ? ljj : 0.0;
     const double lcj = a[J] * inv;     // L[c][J] (used for c > J)
-    if (threadIdx.x < 16) colbuf[c] = lcj;
-    if (c == J) {
-#pragma unroll
-      for (int r = J + 1; r < 16; ++r) a[r] *= inv;
-      a[J] = ljj;
-    }
+    if (threadIdx.x < 16) A[o + c][o + J] = c > J ? lcj : (c == J ? ljj : 0.0);
     y[J] *= inv;                       // row J of the inverse
 #pragma unroll
     for (int r = J + 1; r < 16; ++r) {
-      const double lrj = colbuf[r];    // L[r][J]
-      if (c > J) a[r] -= lrj * lcj;
-      y[r] -= lrj * y[J];
+      const double lrj = A[o + r][o + J];   // L[r][J]
+      a[r] = (c > J) ? fma(-lrj, lcj, a[r]) : a[r];
+      y[r] = fma(-lrj, y[J], y[r]);
     }
-    DiagStep<MODE, J + 1>::run(a, y, c, o, s, g0, dprev, thr, bad, dg, colbuf);
+    DiagStep<MODE, J + 1>::run(a, y, c, o, s, gl, dl, thr, bad, dg, A);
   }
 };
 template <int MODE>
 struct DiagStep<MODE, 16> {
-  __device__ __forceinline__ static void run(double (&)[16], double (&)[16], int, int, int, const double*,
-                                             const double*, double, int*, double*, double*) {}
+  __device__ __forceinline__ static void run(double (&)[16], double (&)[16], int, int, int, double, double, double,
+                                             int*, double*, double (*)[LP]) {}
 };
 
 // 16 x 16 tile product on FP64 matrix cores (v_mfma_f64_16x16x4f64, lane
@@ -213,7 +225,6 @@ __device__ __forceinline__ void tile_store(double (*A)[LP], int r0, int c0, dv4 
 template <int MODE>
 __device__ __forceinline__ void blk_chol_inv_t(double (*A)[LP], double (*Y)[LP], double (*Z)[LP], int s, const double* g0,
                                const double* dprev, double thr, double* dg, int* bad) {
-  __shared__ double colbuf[16];
   const int tid = threadIdx.x;
   const int wv = tid >> 6;
   const int nbk = (s + 15) >> 4;
@@ -238,11 +249,13 @@ __device__ __forceinline__ void blk_chol_inv_t(double (*A)[LP], double (*Y)[LP],
         a[r] = A[o + r][o + c];
         y[r] = (r == c) ? 1.0 : 0.0;
       }
-      DiagStep<MODE, 0>::run(a, y, c, o, s, g0, dprev, thr, bad, dg, colbuf);
+      // the pivot rule's per-column data, lane c holding column o + c
+      const double gl = (MODE == 1 && o + c < s) ? g0[o + c] : 0.0;
+      const double dl = (MODE == 2 && o + c < s) ? dprev[o + c] : 0.0;
+      DiagStep<MODE, 0>::run(a, y, c, o, s, gl, dl, thr, bad, dg, A);   // writes L_bb into A
       if (tid < 16) {
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
-          A[o + r][o + c] = (r >= c) ? a[r] : 0.0;
           Z[o + r][o + c] = (r >= c) ? y[r] : 0.0;   // Y_bb, kept in the diagonal block of Z
           Y[o + r][o + c] = (r >= c) ? y[r] : 0.0;
         }

@@ -42,15 +42,15 @@ __device__ __forceinline__ void zero44(double (&t)[4][4]) {
     for (int b = 0; b < 4; ++b) t[a][b] = 0.0;
 }
 
-// This thread's 4 x 4 part (rows 4ty.., cols 4tx..) of tile (I, J) of an
-// s x s matrix with leading dimension ld: load (0 outside) and store.
+// This thread's 16 elements of tile (I, J) of an s x s matrix with leading
+// dimension ld, in the lds_mm output layout: load (0 outside) and store.
 __device__ __forceinline__ void tile_get(const double* __restrict__ M, int ld, int s, int I, int J, double (&t)[4][4]) {
   const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
-      const int r = 64 * I + 4 * ty + a, c = 64 * J + 4 * tx + b;
+      const int r = 64 * I + acc_row(a), c = 64 * J + acc_col(b);
       t[a][b] = (r < s && c < s) ? M[(int64_t)r * ld + c] : 0.0;
     }
 }
@@ -60,7 +60,7 @@ __device__ __forceinline__ void tile_put(double* __restrict__ M, int ld, int s, 
   for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
-      const int r = 64 * I + 4 * ty + a, c = 64 * J + 4 * tx + b;
+      const int r = 64 * I + acc_row(a), c = 64 * J + acc_col(b);
       if (r < s && c < s) M[(int64_t)r * ld + c] = t[a][b];
     }
 }
@@ -349,7 +349,7 @@ banded_factor_wide_kernel(int m, int s, const double* __restrict__ Hd, const dou
           for (int a = 0; a < 4; ++a)
 #pragma unroll
             for (int b = 0; b < 4; ++b)
-              if (4 * ty + a == 4 * tx + b) t[a][b] += eps;
+              if (acc_row(a) == acc_col(b)) t[a][b] += eps;
         }
         if (j > 0) wterm(t, -1.0, Lsub + (j - 1) * ss, s, false, Lsub + (j - 1) * ss, s, true, s, I, J, 0, nQ, T0, T1);
         tile_put(Aw, s, s, I, J, t);
@@ -390,7 +390,7 @@ banded_solve_wide_kernel(int m, int s, int kpow, const double* __restrict__ Linv
       for (int a = 0; a < 4; ++a)
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
-          const int r = 64 * I + 4 * ty + a, c = 64 * J + 4 * tx + b;
+          const int r = 64 * I + acc_row(a), c = 64 * J + acc_col(b);
           t[a][b] = (j == 0 && r == c) ? 1.0 : 0.0;
         }
       tile_put(U + j * ss, s, s, I, J, t);
