@@ -84,29 +84,43 @@ arch_gram_kernel(int64_t n, const float* __restrict__ Q, int64_t qstride, int nb
     for (int r = 0; r < 4; ++r) a64[e][r] = 0.0;
   }
 
+  // Loads never sit behind a branch: rows past the range read the last valid
+  // row and are zeroed by a select, so a wavefront keeps all the loads of a
+  // flush group in flight before its MFMAs wait on them.
   for (int64_t r0 = rb; r0 < re; r0 += AG_SUB) {
-    for (int q = tid; q < AG_SUB * LD; q += AG_THREADS) {
+    static_assert(AG_SUB * LD == NT * AG_THREADS, "one element per thread and column tile");
+    double xv[NT];
+#pragma unroll
+    for (int e = 0; e < NT; ++e) {
+      const int q = tid + e * AG_THREADS;
       const int rr = q / LD, cc = q - rr * LD;
       const int64_t r = r0 + rr;
-      sX[rr * P + cc] = r < re ? (float)X[r * LD + cc] : 0.f;
+      xv[e] = X[(r < re ? r : re - 1) * LD + cc];
+    }
+#pragma unroll
+    for (int e = 0; e < NT; ++e) {
+      const int q = tid + e * AG_THREADS;
+      const int rr = q / LD, cc = q - rr * LD;
+      sX[rr * P + cc] = r0 + rr < re ? (float)xv[e] : 0.f;
     }
     __syncthreads();
     if (active) {
 #pragma unroll
       for (int h = 0; h < AG_SUB / (4 * AG_FLUSH); ++h) {
+        float a[AG_FLUSH][NT];
+#pragma unroll
+        for (int s8 = 0; s8 < AG_FLUSH; ++s8) {
+          const int64_t r = r0 + 4 * (h * AG_FLUSH + s8) + lk;
+          load_row_seg<NT>(Qj + (r < re ? r : re - 1) * LD + NT * li, a[s8]);
+        }
+        __builtin_amdgcn_sched_barrier(0);   // keep the group's loads ahead of its MFMAs
 #pragma unroll
         for (int s8 = 0; s8 < AG_FLUSH; ++s8) {
           const int s4 = h * AG_FLUSH + s8;
-          const int64_t r = r0 + 4 * s4 + lk;
-          float a[NT];
-          if (r < re) load_row_seg<NT>(Qj + r * LD + NT * li, a);
-          else {
-#pragma unroll
-            for (int e = 0; e < NT; ++e) a[e] = 0.f;
-          }
+          const bool in = r0 + 4 * s4 + lk < re;
           const float b = sX[(4 * s4 + lk) * P + 16 * t + li];
 #pragma unroll
-          for (int e = 0; e < NT; ++e) acc[e] = mfma32(a[e], b, acc[e]);
+          for (int e = 0; e < NT; ++e) acc[e] = mfma32(in ? a[s8][e] : 0.f, b, acc[e]);
         }
 #pragma unroll
         for (int e = 0; e < NT; ++e) {
@@ -156,40 +170,55 @@ arch_update_kernel(int64_t n, const float* __restrict__ Q, int64_t qstride, int 
 #pragma unroll
     for (int t = 0; t < NT; ++t) acc[g][t] = f4{0.f, 0.f, 0.f, 0.f};
 
-  auto stage = [&](int jb, int buf) {
+  // coefficient block jb -> registers (all loads issued together) -> LDS
+  constexpr int CE = LD * LD / 256;
+  auto fetch_c = [&](int jb, double (&cv)[CE]) {
     const double* Cj = C + (int64_t)jb * LD * LD;
-    for (int q = tid; q < LD * LD; q += 256) {
+#pragma unroll
+    for (int e = 0; e < CE; ++e) cv[e] = Cj[tid + 256 * e];
+  };
+  auto put_c = [&](int buf, const double (&cv)[CE]) {
+#pragma unroll
+    for (int e = 0; e < CE; ++e) {
+      const int q = tid + 256 * e;
       const int a = q / LD, b = q - a * LD;
-      sC[buf][a * PC + b] = (float)Cj[q];
+      sC[buf][a * PC + b] = (float)cv[e];
     }
   };
   auto load_q = [&](int jb, float (&qv)[2][KQ]) {
     const float* Qj = Q + (int64_t)jb * qstride;
 #pragma unroll
     for (int g = 0; g < 2; ++g) {
+      // rows past n read row n - 1: their results are never stored
       const int64_t r = R0 + 16 * g + li;
-      if (r < n) {
+      const int64_t rc = r < n ? r : n - 1;
 #pragma unroll
-        for (int v = 0; v < KQ / 4; ++v) {
-          const f4 x = *reinterpret_cast<const f4*>(Qj + r * LD + lk * KQ + 4 * v);
-          qv[g][4 * v] = x[0]; qv[g][4 * v + 1] = x[1]; qv[g][4 * v + 2] = x[2]; qv[g][4 * v + 3] = x[3];
-        }
-      } else {
-#pragma unroll
-        for (int e = 0; e < KQ; ++e) qv[g][e] = 0.f;
+      for (int v = 0; v < KQ / 4; ++v) {
+        const f4 x = *reinterpret_cast<const f4*>(Qj + rc * LD + lk * KQ + 4 * v);
+        qv[g][4 * v] = x[0];
+        qv[g][4 * v + 1] = x[1];
+        qv[g][4 * v + 2] = x[2];
+        qv[g][4 * v + 3] = x[3];
       }
     }
   };
 
   float qcur[2][KQ];
-  stage(0, 0);
+  {
+    double c0[CE];
+    fetch_c(0, c0);
+    put_c(0, c0);
+  }
   load_q(0, qcur);
   __syncthreads();
   for (int jb = 0; jb < nb; ++jb) {
     const int buf = jb & 1;
-    if (jb + 1 < nb) stage(jb + 1, buf ^ 1);
+    double cnext[CE];
     float qnext[2][KQ];
-    if (jb + 1 < nb) load_q(jb + 1, qnext);
+    if (jb + 1 < nb) {
+      fetch_c(jb + 1, cnext);
+      load_q(jb + 1, qnext);
+    }
     const float* sc = sC[buf];
 #pragma unroll
     for (int e = 0; e < KQ; ++e) {
@@ -200,6 +229,7 @@ arch_update_kernel(int64_t n, const float* __restrict__ Q, int64_t qstride, int 
         for (int g = 0; g < 2; ++g) acc[g][t] = mfma32(cv, qcur[g][e], acc[g][t]);
       }
     }
+    if (jb + 1 < nb) put_c(buf ^ 1, cnext);
     __syncthreads();
     if (jb + 1 < nb) {
 #pragma unroll
@@ -251,27 +281,44 @@ arch_assemble_kernel(int64_t n, const float* __restrict__ Q, int64_t qstride, in
       for (int q = 0; q < 4; ++q) a64[g][t][q] = 0.0;
     }
 
+  // coefficient block jb -> LDS as float, NT loads in flight per thread
+  // (columns past s read column s - 1 and are zeroed)
+  constexpr int CE = LD * LD / 256;   // = NT * NT
   auto stage = [&](int jb, int buf) {
     const double* Uj = U + (int64_t)jb * LD * s;
-    for (int q = tid; q < LD * LD; q += 256) {
-      const int a = q / LD, b = q - a * LD;
-      sC[buf][a * PC + b] = (b < s) ? (float)Uj[(int64_t)a * s + b] : 0.f;
+    constexpr int G4 = NT;
+#pragma unroll
+    for (int e0 = 0; e0 < CE; e0 += G4) {
+      double cv[G4];
+#pragma unroll
+      for (int e = 0; e < G4; ++e) {
+        const int q = tid + 256 * (e0 + e);
+        const int a = q / LD, b = q - a * LD;
+        cv[e] = Uj[(int64_t)a * s + (b < s ? b : s - 1)];
+      }
+#pragma unroll
+      for (int e = 0; e < G4; ++e) {
+        const int q = tid + 256 * (e0 + e);
+        const int a = q / LD, b = q - a * LD;
+        sC[buf][a * PC + b] = b < s ? (float)cv[e] : 0.f;
+      }
     }
   };
+
   auto load_q = [&](int jb, float (&qv)[2][KQ]) {
     const float* Qj = Q + (int64_t)jb * qstride;
 #pragma unroll
     for (int g = 0; g < 2; ++g) {
+      // rows past n read row n - 1: their results are never stored
       const int64_t r = R0 + 16 * g + li;
-      if (r < n) {
+      const int64_t rc = r < n ? r : n - 1;
 #pragma unroll
-        for (int v = 0; v < KQ / 4; ++v) {
-          const f4 x = *reinterpret_cast<const f4*>(Qj + r * LD + lk * KQ + 4 * v);
-          qv[g][4 * v] = x[0]; qv[g][4 * v + 1] = x[1]; qv[g][4 * v + 2] = x[2]; qv[g][4 * v + 3] = x[3];
-        }
-      } else {
-#pragma unroll
-        for (int e = 0; e < KQ; ++e) qv[g][e] = 0.f;
+      for (int v = 0; v < KQ / 4; ++v) {
+        const f4 x = *reinterpret_cast<const f4*>(Qj + rc * LD + lk * KQ + 4 * v);
+        qv[g][4 * v] = x[0];
+        qv[g][4 * v + 1] = x[1];
+        qv[g][4 * v + 2] = x[2];
+        qv[g][4 * v + 3] = x[3];
       }
     }
   };
@@ -282,7 +329,6 @@ arch_assemble_kernel(int64_t n, const float* __restrict__ Q, int64_t qstride, in
   __syncthreads();
   for (int jb = 0; jb < nb; ++jb) {
     const int buf = jb & 1;
-    if (jb + 1 < nb) stage(jb + 1, buf ^ 1);
     float qnext[2][KQ];
     if (jb + 1 < nb) load_q(jb + 1, qnext);
     const float* sc = sC[buf];
@@ -303,6 +349,9 @@ arch_assemble_kernel(int64_t n, const float* __restrict__ Q, int64_t qstride, in
         for (int q = 0; q < 4; ++q) a64[g][t][q] += (double)acc[g][t][q];
         acc[g][t] = f4{0.f, 0.f, 0.f, 0.f};
       }
+    // the next coefficient block is staged after the MFMAs: the float64
+    // accumulators leave no registers for a longer prefetch
+    if (jb + 1 < nb) stage(jb + 1, buf ^ 1);
     __syncthreads();
     if (jb + 1 < nb) {
 #pragma unroll

@@ -144,24 +144,38 @@ size_t gram_scratch_elems(int64_t n, int nb, int ld) {
 // ------------------------------------------- FP64 matrix-core Gram / update
 typedef double d4v __attribute__((ext_vector_type(4)));
 
-// eight consecutive elements (16-byte aligned) as doubles
+// Eight consecutive elements (16-byte aligned) held as loaded: the float to
+// double conversion happens only when they are stored to LDS, so a prefetch
+// does not wait for its own loads.
 template <bool F32>
-__device__ __forceinline__ void ld8(const void* __restrict__ base, int64_t off, double (&v)[8]) {
-  if (F32) {
+struct Raw8 {
+  float4 f[2];
+  __device__ __forceinline__ void load(const void* __restrict__ base, int64_t off) {
     const float4* p = reinterpret_cast<const float4*>(static_cast<const float*>(base) + off);
-    const float4 a = p[0], b = p[1];
-    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
-    v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
-  } else {
+    f[0] = p[0];
+    f[1] = p[1];
+  }
+  __device__ __forceinline__ void zero() { f[0] = f[1] = make_float4(0.f, 0.f, 0.f, 0.f); }
+  __device__ __forceinline__ double get(int q) const {
+    const float4& t = f[q >> 2];
+    const int e = q & 3;
+    return (double)(e == 0 ? t.x : e == 1 ? t.y : e == 2 ? t.z : t.w);
+  }
+};
+template <>
+struct Raw8<false> {
+  double2 d[4];
+  __device__ __forceinline__ void load(const void* __restrict__ base, int64_t off) {
     const double2* p = reinterpret_cast<const double2*>(static_cast<const double*>(base) + off);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const double2 t = p[q];
-      v[2 * q] = t.x;
-      v[2 * q + 1] = t.y;
-    }
+    for (int q = 0; q < 4; ++q) d[q] = p[q];
   }
-}
+  __device__ __forceinline__ void zero() {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) d[q] = make_double2(0.0, 0.0);
+  }
+  __device__ __forceinline__ double get(int q) const { return (q & 1) ? d[q >> 1].y : d[q >> 1].x; }
+};
 
 // part[z] (pa x ld) = A^T B over the rows of chunk z, one 64 x 64 output tile
 // per workgroup.  Wave w owns a 32 x 32 quarter as 2 x 2 tiles of
@@ -198,25 +212,22 @@ gram_mfma_kernel(int64_t n, int ld, const void* __restrict__ Abase, int64_t astr
   for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
     for (int tj = 0; tj < 2; ++tj) acc[ti][tj] = d4v{0.0, 0.0, 0.0, 0.0};
-  double va[8], vb[8];
+  Raw8<F32> va;
+  Raw8<false> vb;
   auto fetch = [&](int64_t r0) {
     const int64_t r = r0 + sr;
-    if (r < re && aok) ld8<F32>(Abase, aoff + r * ld, va);
-    else
-#pragma unroll
-      for (int q = 0; q < 8; ++q) va[q] = 0.0;
-    if (r < re && bok) ld8<false>(B, r * ld + gb, vb);
-    else
-#pragma unroll
-      for (int q = 0; q < 8; ++q) vb[q] = 0.0;
+    if (r < re && aok) va.load(Abase, aoff + r * ld);
+    else va.zero();
+    if (r < re && bok) vb.load(B, r * ld + gb);
+    else vb.zero();
   };
   fetch(rb);
   for (int64_t r0 = rb; r0 < re; r0 += MG_RS) {
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      *reinterpret_cast<double2*>(&sA[sr][sc + 2 * q]) = make_double2(va[2 * q], va[2 * q + 1]);
-      *reinterpret_cast<double2*>(&sB[sr][sc + 2 * q]) = make_double2(vb[2 * q], vb[2 * q + 1]);
+      *reinterpret_cast<double2*>(&sA[sr][sc + 2 * q]) = make_double2(va.get(2 * q), va.get(2 * q + 1));
+      *reinterpret_cast<double2*>(&sB[sr][sc + 2 * q]) = make_double2(vb.get(2 * q), vb.get(2 * q + 1));
     }
     __syncthreads();
     if (r0 + MG_RS < re) fetch(r0 + MG_RS);
@@ -275,30 +286,28 @@ tsgemm_mfma_kernel(int64_t n, int ld, const void* __restrict__ Abase, int64_t as
   for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
     for (int tj = 0; tj < 2; ++tj) acc[ti][tj] = d4v{0.0, 0.0, 0.0, 0.0};
-  double va[8], vc[8];
+  Raw8<F32> va;
+  Raw8<false> vc;
   auto fetch = [&](int a0) {
     const int ga = a0 + ak;
     if (arow < n && ga < pa) {
       const int blk = ga / ld;
-      ld8<F32>(Abase, (int64_t)blk * astride + arow * ld + (ga - blk * ld), va);
+      va.load(Abase, (int64_t)blk * astride + arow * ld + (ga - blk * ld));
     } else {
-#pragma unroll
-      for (int q = 0; q < 8; ++q) va[q] = 0.0;
+      va.zero();
     }
     const int gc = a0 + cr;
-    if (gc < pa && cok) ld8<false>(C, (int64_t)gc * ld + b0 + cc, vc);
-    else
-#pragma unroll
-      for (int q = 0; q < 8; ++q) vc[q] = 0.0;
+    if (gc < pa && cok) vc.load(C, (int64_t)gc * ld + b0 + cc);
+    else vc.zero();
   };
   fetch(0);
   for (int a0 = 0; a0 < pa; a0 += MT_K) {
     __syncthreads();
 #pragma unroll
-    for (int q = 0; q < 8; ++q) sAT[ak + q][ar] = va[q];
+    for (int q = 0; q < 8; ++q) sAT[ak + q][ar] = va.get(q);
 #pragma unroll
     for (int q = 0; q < 4; ++q)
-      *reinterpret_cast<double2*>(&sC[cr][cc + 2 * q]) = make_double2(vc[2 * q], vc[2 * q + 1]);
+      *reinterpret_cast<double2*>(&sC[cr][cc + 2 * q]) = make_double2(vc.get(2 * q), vc.get(2 * q + 1));
     __syncthreads();
     if (a0 + MT_K < pa) fetch(a0 + MT_K);
 #pragma unroll
@@ -316,6 +325,19 @@ tsgemm_mfma_kernel(int64_t n, int ld, const void* __restrict__ Abase, int64_t as
           acc[ti][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[ti], bv[tj], acc[ti][tj], 0, 0, 0);
     }
   }
+  // epilogue: the 16 `in` values of this thread are loaded together (rows
+  // and columns out of range read element 0 and are not stored)
+  double inv[2][2][4];
+#pragma unroll
+  for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int64_t r = r0 + wr + 16 * ti + 4 * q + lk;
+        const int b = b0 + wc + 16 * tj + li;
+        inv[ti][tj][q] = (beta != 0.0) ? in[(r < n && b < ld) ? r * ld + b : 0] : 0.0;
+      }
 #pragma unroll
   for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
@@ -325,8 +347,7 @@ tsgemm_mfma_kernel(int64_t n, int ld, const void* __restrict__ Abase, int64_t as
         const int64_t r = r0 + wr + 16 * ti + 4 * q + lk;
         const int b = b0 + wc + 16 * tj + li;
         if (r < n && b < ld) {
-          double v = alpha * acc[ti][tj][q];
-          if (beta != 0.0) v += beta * in[r * ld + b];
+          const double v = alpha * acc[ti][tj][q] + beta * inv[ti][tj][q];
           out[r * ld + b] = v;
           if (out32) out32[r * ld + b] = (float)v;
         }

@@ -115,16 +115,31 @@ __global__ void __launch_bounds__(PT_THREADS, 2) panel_kernel(PanelArgs p) {
   for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const int64_t r0 = tile * PT_ROWS;
     // ---- stage X and V rows (coalesced, zero beyond n)
+    // all loads first (rows past n read row n - 1), then the LDS stores with
+    // rows past n zeroed: one memory latency per tile instead of one per row group
+    constexpr int SQ = PT_ROWS * LD / PT_THREADS;
+    double lx[SQ], l0[NEED_V ? SQ : 1], l1[NEED_V && NBV > 1 ? SQ : 1];
 #pragma unroll
-    for (int q0 = 0; q0 < PT_ROWS * LD; q0 += PT_THREADS) {
-      const int q = q0 + tid;
+    for (int e = 0; e < SQ; ++e) {
+      const int q = e * PT_THREADS + tid;
       const int rr = q / LD, cc = q - rr * LD;
       const int64_t r = r0 + rr;
-      const bool in = r < p.n;
-      sX[rr * P + cc] = in ? p.X[r * LD + cc] : 0.0;
+      const int64_t off = (r < p.n ? r : p.n - 1) * LD + cc;
+      lx[e] = p.X[off];
       if (NEED_V) {
-        sV[rr * P + cc] = in ? p.V0[r * LD + cc] : 0.0;
-        if (NBV > 1) sV[PT_ROWS * P + rr * P + cc] = in ? p.V1[r * LD + cc] : 0.0;
+        l0[e] = p.V0[off];
+        if (NBV > 1) l1[e] = p.V1[off];
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < SQ; ++e) {
+      const int q = e * PT_THREADS + tid;
+      const int rr = q / LD, cc = q - rr * LD;
+      const bool in = r0 + rr < p.n;
+      sX[rr * P + cc] = in ? lx[e] : 0.0;
+      if (NEED_V) {
+        sV[rr * P + cc] = in ? l0[e] : 0.0;
+        if (NBV > 1) sV[PT_ROWS * P + rr * P + cc] = in ? l1[e] : 0.0;
       }
     }
     __syncthreads();
