@@ -471,10 +471,10 @@ static void run_cbl(Job& J) {
         launch_gram(n, ld, yl, Y, G, part, nullptr, st);
       }
       if (wave) {
-        launch_cholqr_reg(G, ld, s, 2, d1, J.thr(), R2, R2i, d2, J.dflags + 1, R1, R1i, R12i,
+        launch_cholqr_reg(G, ld, s, 2, d1, J.thr(), nullptr, nullptr, d2, J.dflags + 1, R1, R1i, R12i,
                           Bd + (int64_t)k * s * s, st);
       } else if (widek) {
-        launch_cholqr_wide(G, ld, s, 2, d1, J.thr(), W, R2, R2i, d2, J.dflags + 1, R1, R1i, R12i,
+        launch_cholqr_wide(G, ld, s, 2, d1, J.thr(), W, nullptr, nullptr, d2, J.dflags + 1, R1, R1i, R12i,
                            Bd + (int64_t)k * s * s, nullptr, st);
       } else {
         launch_cholqr_factor(G, ld, s, 2, d1, J.thr(), W, R2, R2i, d2, J.dflags + 1, st);
@@ -515,10 +515,10 @@ static void run_cbl(Job& J) {
             launch_gram(n, ld, BlockList{Y, blk, 1, false}, Y, G, part, fk, st);
           }
           if (wave)
-            launch_cholqr_flag(G, ld, s, 2, d1, J.thr(), R2, R2i, d2, nullptr, R1, R1i, R12i, Bd + (int64_t)k * s * s,
-                               fk, st);
+            launch_cholqr_flag(G, ld, s, 2, d1, J.thr(), nullptr, nullptr, d2, nullptr, R1, R1i, R12i,
+                               Bd + (int64_t)k * s * s, fk, st);
           else
-            launch_cholqr_wide(G, ld, s, 2, d1, J.thr(), W, R2, R2i, d2, nullptr, R1, R1i, R12i,
+            launch_cholqr_wide(G, ld, s, 2, d1, J.thr(), W, nullptr, nullptr, d2, nullptr, R1, R1i, R12i,
                                Bd + (int64_t)k * s * s, fk, st);
           J.tm.begin(PH_ORTH);
         }

@@ -84,8 +84,9 @@ gram_kernel(int64_t n, int ld, const void* __restrict__ Abase, int64_t astride, 
 }
 
 // out[i] = sum_{c < nparts} part[c*len + i] in a fixed order: block b owns
-// outputs [16b, 16b+16); its 16 thread groups sum interleaved parts, then
-// the 16 partial sums are added in group order.
+// outputs [16b, 16b+16); its 16 thread groups sum interleaved parts (eight
+// running sums per thread, so eight loads are in flight, combined pairwise),
+// then the 16 group sums are added in group order.
 __global__ void __launch_bounds__(256)
 reduce_parts_kernel(int64_t len, int nparts, const double* __restrict__ part, double* __restrict__ out,
                     const int* __restrict__ flag) {
@@ -94,8 +95,17 @@ reduce_parts_kernel(int64_t len, int nparts, const double* __restrict__ part, do
   const int o = threadIdx.x & 15, g = threadIdx.x >> 4;
   const int64_t i = (int64_t)blockIdx.x * 16 + o;
   double s = 0.0;
-  if (i < len)
-    for (int c = g; c < nparts; c += 16) s += part[(int64_t)c * len + i];
+  if (i < len) {
+    double a[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) a[u] = 0.0;
+    int c = g;
+    for (; c + 16 * 7 < nparts; c += 16 * 8)
+#pragma unroll
+      for (int u = 0; u < 8; ++u) a[u] += part[(int64_t)(c + 16 * u) * len + i];
+    for (; c < nparts; c += 16) a[0] += part[(int64_t)c * len + i];
+    s = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+  }
   red[g][o] = s;
   __syncthreads();
   if (g == 0 && i < len) {

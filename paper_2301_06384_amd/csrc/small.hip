@@ -732,13 +732,15 @@ cholqr_blk_kernel(const double* __restrict__ G, int ld, int s, int pass, const d
   } else {
     blk_chol_inv(A, Y, S1, s, pass, g0, dp, thr, dg, nullptr);
   }
-  // R = L^T, Rinv = Y^T (upper), coalesced stores with zero padding
-  for (int q = tid; q < ld * ld; q += ST) {
-    const int i = q / ld, c = q % ld;
-    const bool in = i < s && c < s && c >= i;
-    R[q] = in ? A[c][i] : 0.0;
-    Rinv[q] = in ? Y[c][i] : 0.0;
-  }
+  // R = L^T, Rinv = Y^T (upper), coalesced stores with zero padding; skipped
+  // when the caller passes null (pass 2 returns its factors through Rc and B)
+  if (R)
+    for (int q = tid; q < ld * ld; q += ST) {
+      const int i = q / ld, c = q % ld;
+      const bool in = i < s && c < s && c >= i;
+      R[q] = in ? A[c][i] : 0.0;
+      Rinv[q] = in ? Y[c][i] : 0.0;
+    }
   for (int q = tid; q < ld; q += ST) diag_out[q] = (q < s) ? dg[q] : 0.0;
   if (pass == 2) {
     if (tid == 0 && n_defl) {
@@ -853,17 +855,47 @@ banded_factor_blk_kernel(int m, int s, const double* __restrict__ Hd, const doub
 // from U = F_1, as forward (L) and backward (L^T) block substitutions:
 //   forward  Y_j <- Linv_j (Y_j - Lsub_{j-1} Y_{j-1})
 //   backward Y_j <- Linv_j^T (Y_j - Lsub_j^T Y_{j+1})
-// 256 threads; the operands of the next block step are fetched into registers
-// while the current one computes; the neighbouring block stays in LDS.
+// The columns of U are independent: one workgroup of 256 threads per
+// 16-column slice (grid ceil(s / 16)).  The operands of the next block step
+// are fetched into registers while the current one computes; the slice of
+// the neighbouring block stays in LDS.
+constexpr int SLP = 17;   // LDS pitch of a 64 x 16 slice
+
+// acc[a] = (A^T B)[acc_row(a)][lane & 15] for a 16-column slice B, summed
+// over the first s rows (NT steps of four, two accumulator chains).
+template <int NT>
+__device__ __forceinline__ void mm_slice_steps(const double (*A)[LP], const double (*B)[SLP], int s, dv4& d0,
+                                               dv4& d1) {
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63, li = l & 15, lk = l >> 4;
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int kk = 4 * t + lk;
+    const bool in = kk < s;
+    const double a0 = A[kk][16 * w + li], b0 = B[kk][li];
+    if (t & 1) d1 = __builtin_amdgcn_mfma_f64_16x16x4f64(in ? a0 : 0.0, in ? b0 : 0.0, d1, 0, 0, 0);
+    else d0 = __builtin_amdgcn_mfma_f64_16x16x4f64(in ? a0 : 0.0, in ? b0 : 0.0, d0, 0, 0, 0);
+  }
+}
+__device__ __forceinline__ void lds_mm_slice(const double (*A)[LP], const double (*B)[SLP], int s, double (&acc)[4]) {
+  dv4 d0 = dv4{0.0, 0.0, 0.0, 0.0}, d1 = dv4{0.0, 0.0, 0.0, 0.0};
+  if (s > 48) mm_slice_steps<16>(A, B, s, d0, d1);
+  else if (s > 32) mm_slice_steps<12>(A, B, s, d0, d1);
+  else if (s > 16) mm_slice_steps<8>(A, B, s, d0, d1);
+  else mm_slice_steps<4>(A, B, s, d0, d1);
+#pragma unroll
+  for (int a = 0; a < 4; ++a) acc[a] = d0[a] + d1[a];
+}
+
 __global__ void __launch_bounds__(ST)
 banded_solve_kernel(int m, int s, int kpow, const double* __restrict__ Linv_all, const double* __restrict__ Lsub_all,
                     double* __restrict__ U) {
-  __shared__ __align__(16) double T[WS][LP];
   __shared__ __align__(16) double SL[WS][LP];   // Lsub
-  __shared__ __align__(16) double SY[WS][LP];   // neighbouring block of Y (previous step's result)
   __shared__ __align__(16) double SI[WS][LP];   // Linv
+  __shared__ double T[WS][SLP];                 // right-hand side slice
+  __shared__ double SY[WS][SLP];                // slice of the previous step's result
   const int tid = threadIdx.x;
-  const int tx = tid & 15, ty = tid >> 4;
+  const int li = tid & 15;
+  const int c0 = 16 * blockIdx.x;
   const int ss = s * s;
   const int nsteps = 2 * kpow * m;
   // step -> (direction, block)
@@ -874,19 +906,28 @@ banded_solve_kernel(int m, int s, int kpow, const double* __restrict__ Linv_all,
     j = dir == 0 ? jj : m - 1 - jj;
   };
   auto has_nb = [&](int dir, int j) { return dir == 0 ? (j > 0) : (j + 1 < m); };
-  // U = F_1 (first block identity)
-  for (int64_t q = tid; q < (int64_t)m * ss; q += ST) {
-    const int64_t r = q / s, c = q - r * s;
-    U[q] = (r == c) ? 1.0 : 0.0;
+  // slice element e of this thread: row (tid + 256 e) / 16, column c0 + tid % 16
+  auto fetch_slice = [&](const double* Yj, double (&v)[4]) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int r = (tid + 256 * e) >> 4, c = c0 + li;
+      v[e] = (r < s && c < s) ? Yj[r * s + c] : 0.0;
+    }
+  };
+  // U = F_1 on this slice (first block identity)
+  for (int64_t q = tid; q < (int64_t)m * s * 16; q += ST) {
+    const int64_t r = q >> 4;
+    const int c = c0 + (int)(q & 15);
+    if (c < s) U[r * s + c] = (r == c) ? 1.0 : 0.0;
   }
   __syncthreads();
-  double pi[16], pl[16], pt[16];
+  double pi[16], pl[16], pt[4];
   {
     int dir, j;
     blk_of(0, dir, j);
     fetch64(Linv_all + (int64_t)j * ss, s, s, pi);
     fetch64(nullptr, s, s, pl);
-    fetch64(U + (int64_t)j * ss, s, s, pt);
+    fetch_slice(U + (int64_t)j * ss, pt);
   }
   int pj = -1;
   for (int st = 0; st < nsteps; ++st) {
@@ -901,12 +942,11 @@ banded_solve_kernel(int m, int s, int kpow, const double* __restrict__ Linv_all,
       put64(SI, pi);
       put64(SL, pl);
     }
-    if (j == pj) {
-      // the previous step finished this very block (turn of a sweep)
-      for (int i = ty; i < WS; i += 16)
-        for (int c = tx; c < WS; c += 16) T[i][c] = SY[i][c];
-    } else {
-      put64(T, pt);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int r = (tid + 256 * e) >> 4;
+      // the previous step finished this very block at the turn of a sweep
+      T[r][li] = (j == pj) ? SY[r][li] : pt[e];
     }
     __syncthreads();
     if (st + 1 < nsteps) {
@@ -914,30 +954,26 @@ banded_solve_kernel(int m, int s, int kpow, const double* __restrict__ Linv_all,
       blk_of(st + 1, d2, j2);
       fetch64(Linv_all + (int64_t)j2 * ss, s, s, pi);
       fetch64(has_nb(d2, j2) ? Lsub_all + (int64_t)(d2 == 0 ? j2 - 1 : j2) * ss : nullptr, s, s, pl);
-      fetch64(U + (int64_t)j2 * ss, s, s, pt);
+      fetch_slice(U + (int64_t)j2 * ss, pt);
     }
-    double acc[4][4];
+    double acc[4];
     if (nb) {
-      lds_mm<true, false>(SL, SY, s, acc);   // Lsub_{j-1} Y_{j-1} (forward) or Lsub_j^T Y_{j+1} (backward)
+      lds_mm_slice(SL, SY, s, acc);   // Lsub_{j-1} Y_{j-1} (forward) or Lsub_j^T Y_{j+1} (backward)
       __syncthreads();
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int jj = 0; jj < 4; ++jj) T[acc_row(i)][acc_col(jj)] -= acc[i][jj];
+      for (int a = 0; a < 4; ++a) T[acc_row(a)][li] -= acc[a];
       __syncthreads();
     }
-    lds_mm<true, false>(SI, T, s, acc);     // Linv_j T (forward) or Linv_j^T T (backward)
+    lds_mm_slice(SI, T, s, acc);     // Linv_j T (forward) or Linv_j^T T (backward)
     __syncthreads();   // SY is read above (nb) and rewritten below
     double* Y = U + (int64_t)j * ss;
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int jj = 0; jj < 4; ++jj) {
-        const int r = acc_row(i), c = acc_col(jj);
-        const double v = (r < s && c < s) ? acc[i][jj] : 0.0;
-        SY[r][c] = v;
-        if (r < s && c < s) Y[r * s + c] = v;
-      }
+    for (int a = 0; a < 4; ++a) {
+      const int r = acc_row(a), c = c0 + li;
+      const bool in = r < s && c < s;
+      SY[r][li] = in ? acc[a] : 0.0;
+      if (in) Y[r * s + c] = acc[a];
+    }
     __syncthreads();
     pj = j;
   }
@@ -1150,7 +1186,7 @@ void launch_banded_spline_reg(int m, int s, const double* Hd, const double* Bd, 
   GK_HIP(hipGetLastError());
   kt_end(st, 8.0 * 4 * m * (double)ss, (double)m * ss * s * (2.0 + 1.0 / 3.0 + 1.0));
   kt_begin(KC_BANDED_SOLVE, st);
-  hipLaunchKernelGGL(banded_solve_kernel, dim3(1), dim3(ST), 0, st, m, s, k, Linv, Lsub, U);
+  hipLaunchKernelGGL(banded_solve_kernel, dim3((s + 15) / 16), dim3(ST), 0, st, m, s, k, Linv, Lsub, U);
   GK_HIP(hipGetLastError());
   kt_end(st, 8.0 * 4 * 2 * k * m * (double)ss, 4.0 * 2 * k * m * (double)ss * s);
 }

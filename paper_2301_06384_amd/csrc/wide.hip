@@ -203,13 +203,14 @@ cholqr_wide_kernel(const double* __restrict__ G, int ld, int s, int pass, const 
     wide_chol_inv<1>(Aw, Yw, ld, s, g0, dp, thr, dg, nullptr, T0, T1, T2, T3);
   else
     wide_chol_inv<2>(Aw, Yw, ld, s, g0, dp, thr, dg, nullptr, T0, T1, T2, T3);
-  // R = L^T, Rinv = Y^T (upper, zero padded)
-  for (int q = tid; q < ld * ld; q += ST) {
-    const int i = q / ld, c = q % ld;
-    const bool in = i < s && c < s && c >= i;
-    R[q] = in ? Aw[(int64_t)c * ld + i] : 0.0;
-    Rinv[q] = in ? Yw[(int64_t)c * ld + i] : 0.0;
-  }
+  // R = L^T, Rinv = Y^T (upper, zero padded); skipped when R is null
+  if (R)
+    for (int q = tid; q < ld * ld; q += ST) {
+      const int i = q / ld, c = q % ld;
+      const bool in = i < s && c < s && c >= i;
+      R[q] = in ? Aw[(int64_t)c * ld + i] : 0.0;
+      Rinv[q] = in ? Yw[(int64_t)c * ld + i] : 0.0;
+    }
   for (int q = tid; q < ld; q += ST) diag_out[q] = (q < s) ? dg[q] : 0.0;
   if (pass != 2) return;
   if (tid == 0 && n_defl) {
