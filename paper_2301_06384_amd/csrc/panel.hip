@@ -55,6 +55,9 @@ __global__ void __launch_bounds__(PT_THREADS, 2) panel_kernel(PanelArgs p) {
   constexpr int TPW = (NPAIR + 3) / 4;           // Gram tiles per wavefront
   constexpr bool NEED_V = NBV > 0 && (UPDATE || GRAMV);
   constexpr int NBC = UPDATE ? NBV : (APPLY ? 1 : 0);   // coefficient blocks in registers
+  // prefetch of the next tile (registers permitting: not with the two-block
+  // update, whose coefficients already fill them)
+  constexpr bool PF = !(UPDATE && NBV > 1 && NT > 2);
   __shared__ double sX[PT_ROWS * P];
   __shared__ double sV[(NEED_V ? NBV : 1) * PT_ROWS * P];
 
@@ -112,13 +115,12 @@ __global__ void __launch_bounds__(PT_THREADS, 2) panel_kernel(PanelArgs p) {
   for (int t = 0; t < (TPW > 0 ? TPW : 1); ++t) gacc[t] = d4{0.0, 0.0, 0.0, 0.0};
 
   const int64_t ntiles = (p.n + PT_ROWS - 1) / PT_ROWS;
-  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-    const int64_t r0 = tile * PT_ROWS;
-    // ---- stage X and V rows (coalesced, zero beyond n)
-    // all loads first (rows past n read row n - 1), then the LDS stores with
-    // rows past n zeroed: one memory latency per tile instead of one per row group
-    constexpr int SQ = PT_ROWS * LD / PT_THREADS;
-    double lx[SQ], l0[NEED_V ? SQ : 1], l1[NEED_V && NBV > 1 ? SQ : 1];
+  // Tile rows go through registers: loads of the next tile are issued right
+  // after the current one is in LDS, so they are in flight during its
+  // products (rows past n read row n - 1 and are zeroed at the LDS store).
+  constexpr int SQ = PT_ROWS * LD / PT_THREADS;
+  double lx[SQ], l0[NEED_V ? SQ : 1], l1[NEED_V && NBV > 1 ? SQ : 1];
+  auto fetch_tile = [&](int64_t r0) {
 #pragma unroll
     for (int e = 0; e < SQ; ++e) {
       const int q = e * PT_THREADS + tid;
@@ -131,6 +133,11 @@ __global__ void __launch_bounds__(PT_THREADS, 2) panel_kernel(PanelArgs p) {
         if (NBV > 1) l1[e] = p.V1[off];
       }
     }
+  };
+  if (PF && (int64_t)blockIdx.x < ntiles) fetch_tile((int64_t)blockIdx.x * PT_ROWS);
+  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int64_t r0 = tile * PT_ROWS;
+    if (!PF) fetch_tile(r0);
 #pragma unroll
     for (int e = 0; e < SQ; ++e) {
       const int q = e * PT_THREADS + tid;
@@ -143,6 +150,7 @@ __global__ void __launch_bounds__(PT_THREADS, 2) panel_kernel(PanelArgs p) {
       }
     }
     __syncthreads();
+    if (PF && tile + gridDim.x < ntiles) fetch_tile((tile + gridDim.x) * PT_ROWS);
     // ---- X_new for the (slabs, column tile) of this wavefront
     if (UPDATE || APPLY) {
       d4 acc[UP];
