@@ -193,6 +193,10 @@ size_t banded_wide_work_elems(int m, int s);
 void launch_banded_spline_wide(int m, int s, const double* Hd, const double* Bd, double eps, int k, double* work,
                                double* U, int* bad, hipStream_t st);
 int cheb_diffusion_degree(double t, double Lam);
+// one Chebyshev series term through the block tridiagonal H_m (s <= 512)
+void launch_btd_cheb_tile(int m, int s, const double* Hd, const double* Bd, const double* Y, const double* Yp,
+                          double* out, double alpha, double beta, double gamma, double* acc, const double* coef,
+                          int kk, hipStream_t st);
 void launch_cheb_diffusion(int m, int s, const double* Hd, const double* Bd, double t, double Lam, int deg,
                            const double* coef, double* Y0, double* Y1, double* Y2, double* U, hipStream_t st);
 // deterministic sum of nparts equally long partial vectors: out[i] = sum_c part[c*len + i]

@@ -268,19 +268,24 @@ gram_mfma_kernel(int64_t n, int ld, const void* __restrict__ Abase, int64_t astr
       }
 }
 
-// out[r, b] = beta in[r, b] + alpha sum_a A[r, a] C[a, b] (row-major, ld
-// columns), one 64-row x 64-column tile per workgroup, 32 contraction
-// indices per stage; A is staged transposed so both operands are read
-// along their contiguous LDS rows.
+// out[r, b] = beta in[r, b] + alpha sum_a A[r, a] C[a, b], one 64-row x
+// 64-column tile per workgroup, 32 contraction indices per stage; A is
+// staged transposed so both operands are read along their contiguous LDS
+// rows.  Row-major: ld columns, C with leading dimension ld.  COLMAJ (the
+// assembly P = [Q_1 .. Q_nb] U): columns b < ncols written column-major
+// (leading dimension ldo, row r to perm[r]) through an LDS transpose, C with
+// leading dimension ldc, no in / out32.
 constexpr int MT_R = 64, MT_C = 64, MT_K = 32;
-template <bool F32>
+template <bool F32, bool COLMAJ>
 __global__ void __launch_bounds__(256)
 tsgemm_mfma_kernel(int64_t n, int ld, const void* __restrict__ Abase, int64_t astride, int nb,
-                   const double* __restrict__ C, const double* __restrict__ in, double* __restrict__ out,
-                   float* __restrict__ out32, double alpha, double beta, const int* __restrict__ flag) {
+                   const double* __restrict__ C, int ldc, int ncols, const double* __restrict__ in,
+                   double* __restrict__ out, float* __restrict__ out32, double alpha, double beta, int64_t ldo,
+                   const int64_t* __restrict__ perm, const int* __restrict__ flag) {
   if (flag && *flag == 0) return;
   __shared__ __align__(16) double sAT[MT_K][MT_R + 2];
   __shared__ __align__(16) double sC[MT_K][MT_C + 2];
+  __shared__ double sO[COLMAJ ? MT_C : 1][MT_R + 1];
   const int pa = nb * ld;
   const int64_t r0 = (int64_t)blockIdx.x * MT_R;
   const int b0 = blockIdx.y * MT_C;
@@ -291,6 +296,7 @@ tsgemm_mfma_kernel(int64_t n, int ld, const void* __restrict__ Abase, int64_t as
   const int cr = tid >> 3, cc = 8 * (tid & 7);     // C staging: row, 8 columns
   const int64_t arow = r0 + ar;
   const bool cok = b0 + cc < ld;
+  double vcs[COLMAJ ? 8 : 1];   // column-major case: scalar coefficient loads (ldc need not be even)
   d4v acc[2][2];
 #pragma unroll
   for (int ti = 0; ti < 2; ++ti)
@@ -307,17 +313,32 @@ tsgemm_mfma_kernel(int64_t n, int ld, const void* __restrict__ Abase, int64_t as
       va.zero();
     }
     const int gc = a0 + cr;
-    if (gc < pa && cok) vc.load(C, (int64_t)gc * ld + b0 + cc);
-    else vc.zero();
+    if (COLMAJ) {
+      const int gcc = gc < pa ? gc : pa - 1;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int col = b0 + cc + q;
+        vcs[q] = C[(int64_t)gcc * ldc + (col < ncols ? col : ncols - 1)];
+      }
+    } else {
+      if (gc < pa && cok) vc.load(C, (int64_t)gc * ld + b0 + cc);
+      else vc.zero();
+    }
   };
   fetch(0);
   for (int a0 = 0; a0 < pa; a0 += MT_K) {
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < 8; ++q) sAT[ak + q][ar] = va.get(q);
+    if (COLMAJ) {
+      const bool rin = a0 + cr < pa;
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
-      *reinterpret_cast<double2*>(&sC[cr][cc + 2 * q]) = make_double2(vc.get(2 * q), vc.get(2 * q + 1));
+      for (int q = 0; q < 8; ++q) sC[cr][cc + q] = (rin && b0 + cc + q < ncols) ? vcs[q] : 0.0;
+    } else {
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        *reinterpret_cast<double2*>(&sC[cr][cc + 2 * q]) = make_double2(vc.get(2 * q), vc.get(2 * q + 1));
+    }
     __syncthreads();
     if (a0 + MT_K < pa) fetch(a0 + MT_K);
 #pragma unroll
@@ -334,6 +355,23 @@ tsgemm_mfma_kernel(int64_t n, int ld, const void* __restrict__ Abase, int64_t as
         for (int tj = 0; tj < 2; ++tj)
           acc[ti][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[ti], bv[tj], acc[ti][tj], 0, 0, 0);
     }
+  }
+  if (COLMAJ) {
+    // transpose through LDS: each column is then written as contiguous rows
+#pragma unroll
+    for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+      for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) sO[wc + 16 * tj + li][wr + 16 * ti + 4 * q + lk] = alpha * acc[ti][tj][q];
+    __syncthreads();
+    for (int q = tid; q < MT_C * MT_R; q += 256) {
+      const int cc2 = q / MT_R, rr = q - cc2 * MT_R;
+      const int64_t r = r0 + rr;
+      const int b = b0 + cc2;
+      if (r < n && b < ncols) out[(int64_t)b * ldo + (perm ? perm[r] : r)] = sO[cc2][rr];
+    }
+    return;
   }
   // epilogue: the 16 `in` values of this thread are loaded together (rows
   // and columns out of range read element 0 and are not stored)
@@ -487,11 +525,11 @@ void launch_tsgemm(int64_t n, int ld, BlockList A, const double* C, const double
   if (mfma_ok(ld)) {
     static_assert(MT_R == T_TR && MT_C == T_TB, "same tile grid");
     if (A.f32)
-      hipLaunchKernelGGL(tsgemm_mfma_kernel<true>, grid, dim3(256), 0, st, n, ld, A.base, A.stride, A.nb, C, in, out,
-                         out32, alpha, beta, flag);
+      hipLaunchKernelGGL((tsgemm_mfma_kernel<true, false>), grid, dim3(256), 0, st, n, ld, A.base, A.stride, A.nb, C,
+                         ld, ld, in, out, out32, alpha, beta, (int64_t)ld, (const int64_t*)nullptr, flag);
     else
-      hipLaunchKernelGGL(tsgemm_mfma_kernel<false>, grid, dim3(256), 0, st, n, ld, A.base, A.stride, A.nb, C, in,
-                         out, out32, alpha, beta, flag);
+      hipLaunchKernelGGL((tsgemm_mfma_kernel<false, false>), grid, dim3(256), 0, st, n, ld, A.base, A.stride, A.nb,
+                         C, ld, ld, in, out, out32, alpha, beta, (int64_t)ld, (const int64_t*)nullptr, flag);
   } else if (A.f32)
     hipLaunchKernelGGL((tsgemm_kernel<true, false>), grid, dim3(256), 0, st, n, ld, ld, A.base, A.stride,
                        A.nb, C, ld, in, out, out32, alpha, beta, (int64_t)ld, (const int64_t*)nullptr,
@@ -509,7 +547,14 @@ void launch_assemble(int64_t n, int ld, int s, BlockList A, const double* U, int
                      const int64_t* perm, hipStream_t st) {
   dim3 grid((unsigned)((n + T_TR - 1) / T_TR), (s + T_TB - 1) / T_TB);
   kt_begin(KC_ASSEMBLE, st);
-  if (A.f32)
+  if (mfma_ok(ld)) {
+    if (A.f32)
+      hipLaunchKernelGGL((tsgemm_mfma_kernel<true, true>), grid, dim3(256), 0, st, n, ld, A.base, A.stride, A.nb, U,
+                         ldu, s, (const double*)nullptr, P, (float*)nullptr, 1.0, 0.0, n, perm, (const int*)nullptr);
+    else
+      hipLaunchKernelGGL((tsgemm_mfma_kernel<false, true>), grid, dim3(256), 0, st, n, ld, A.base, A.stride, A.nb, U,
+                         ldu, s, (const double*)nullptr, P, (float*)nullptr, 1.0, 0.0, n, perm, (const int*)nullptr);
+  } else if (A.f32)
     hipLaunchKernelGGL((tsgemm_kernel<true, true>), grid, dim3(256), 0, st, n, ld, s, A.base, A.stride,
                        A.nb, U, ldu, (const double*)nullptr, P, (float*)nullptr, 1.0, 0.0, n, perm,
                        (const int*)nullptr);

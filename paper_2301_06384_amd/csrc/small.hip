@@ -1204,7 +1204,9 @@ namespace gk {
 // (2 e^{-z} I_k(z), z = t Lambda / 2) fall below 1e-17.
 // out = alpha * (H Y) + beta * Y + gamma * Yp ;  acc += coef[kk] * out
 // (H Y)_j = H_{j,j-1} Y_{j-1} + H_jj Y_j + H_{j,j+1} Y_{j+1}, H_{j,j-1} = B_{j-1},
-// H_{j,j+1} = B_j^T.  One thread per entry (j, r, c) of the m s x s output.
+// H_{j,j+1} = B_j^T.  Blocks up to 512 wide run on 64 x 64 tiles
+// (launch_btd_cheb_tile); wider ones with one thread per entry (j, r, c) of
+// the m s x s output here.
 __global__ void btd_cheb_step_kernel(int m, int s, const double* __restrict__ Hd, const double* __restrict__ Bd,
                                      const double* __restrict__ Y, const double* __restrict__ Yp,
                                      double* __restrict__ out, double alpha, double beta, double gamma,
@@ -1243,9 +1245,12 @@ __global__ void f1_init_kernel(int64_t rows, int s, double* __restrict__ Y, doub
   acc[t] = coef[0] * v;
 }
 
+// The coefficients 2 e^{-z} I_k(z) fall below 1e-17 before k = sqrt(80 z) + 24
+// for every z (they decay like exp(-k^2 / (2 z)) once k exceeds sqrt(z));
+// sqrt(90 z) + 24 keeps a margin.
 int cheb_diffusion_degree(double t, double Lam) {
   const double z = 0.5 * t * Lam;
-  const double k = fmax(sqrt(80.0 * z), z) + 24.0;
+  const double k = sqrt(90.0 * z) + 24.0;
   return (int)fmin(4096.0, ceil(k));
 }
 
@@ -1259,18 +1264,19 @@ void launch_cheb_diffusion(int m, int s, const double* Hd, const double* Bd, dou
   double* Y[3] = {Y0, Y1, Y2};
   // T_1: out = Y - (2/Lam) H Y
   const double cb = 8.0 * 6 * (double)m * s * s, cf = 2.0 * 3 * (double)m * s * s * s;
-  kt_begin(KC_CHEB, st);
-  hipLaunchKernelGGL(btd_cheb_step_kernel, dim3(nb), dim3(256), 0, st, m, s, Hd, Bd, Y[0], (const double*)nullptr,
-                     Y[1], -2.0 / Lam, 1.0, 0.0, U, coef, 1);
-  GK_HIP(hipGetLastError());
-  kt_end(st, cb, cf);
-  for (int k = 1; k < deg; ++k) {
+  auto step = [&](const double* Yc, const double* Yp, double* out, double a, double b, double g, int kk) {
     kt_begin(KC_CHEB, st);
-    hipLaunchKernelGGL(btd_cheb_step_kernel, dim3(nb), dim3(256), 0, st, m, s, Hd, Bd, Y[k % 3], Y[(k - 1) % 3],
-                       Y[(k + 1) % 3], -4.0 / Lam, 2.0, -1.0, U, coef, k + 1);
-    GK_HIP(hipGetLastError());
+    if (s <= 512) {
+      launch_btd_cheb_tile(m, s, Hd, Bd, Yc, Yp, out, a, b, g, U, coef, kk, st);
+    } else {
+      hipLaunchKernelGGL(btd_cheb_step_kernel, dim3(nb), dim3(256), 0, st, m, s, Hd, Bd, Yc, Yp, out, a, b, g, U,
+                         coef, kk);
+      GK_HIP(hipGetLastError());
+    }
     kt_end(st, cb, cf);
-  }
+  };
+  step(Y[0], nullptr, Y[1], -2.0 / Lam, 1.0, 0.0, 1);
+  for (int k = 1; k < deg; ++k) step(Y[k % 3], Y[(k - 1) % 3], Y[(k + 1) % 3], -4.0 / Lam, 2.0, -1.0, k + 1);
 }
 
 }  // namespace gk

@@ -452,4 +452,53 @@ void launch_banded_spline_wide(int m, int s, const double* Hd, const double* Bd,
   kt_end(st, 8.0 * 4 * 2 * k * m * (double)ss, 4.0 * 2 * k * m * (double)ss * s);
 }
 
+// ------------------------------------------------ Chebyshev series step
+// One term of the series of exp(-t lam) applied to F_1 through the block
+// tridiagonal H_m (blocks H_jj, sub-diagonal B_j = H_{j+1,j}):
+//   out_j = alpha (B_{j-1} Y_{j-1} + H_jj Y_j + B_j^T Y_{j+1}) + beta Y_j + gamma Yp_j,
+//   acc_j += coef[kk] out_j,
+// one workgroup per 64 x 64 output tile (j, I, J) on the tile path above.
+__global__ void __launch_bounds__(ST)
+btd_cheb_tile_kernel(int m, int s, const double* __restrict__ Hd, const double* __restrict__ Bd,
+                     const double* __restrict__ Y, const double* __restrict__ Yp, double* __restrict__ out,
+                     double alpha, double beta, double gamma, double* __restrict__ acc,
+                     const double* __restrict__ coef, int kk) {
+  __shared__ __align__(16) double SA[WS][LP];
+  __shared__ __align__(16) double SB[WS][LP];
+  const int j = blockIdx.x, I = blockIdx.y, J = blockIdx.z;
+  const int nQ = (s + 63) >> 6;
+  const int64_t ss = (int64_t)s * s;
+  double t[4][4];
+  zero44(t);
+  wterm(t, 1.0, Hd + j * ss, s, false, Y + j * ss, s, false, s, I, J, 0, nQ, SA, SB);
+  if (j > 0) wterm(t, 1.0, Bd + (j - 1) * ss, s, false, Y + (j - 1) * ss, s, false, s, I, J, 0, nQ, SA, SB);
+  if (j + 1 < m) wterm(t, 1.0, Bd + j * ss, s, true, Y + (j + 1) * ss, s, false, s, I, J, 0, nQ, SA, SB);
+  double yv[4][4], pv[4][4], av[4][4];
+  tile_get(Y + j * ss, s, s, I, J, yv);
+  if (Yp) tile_get(Yp + j * ss, s, s, I, J, pv);
+  else zero44(pv);
+  tile_get(acc + j * ss, s, s, I, J, av);
+  const double ck = coef[kk];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const double v = alpha * t[a][b] + beta * yv[a][b] + gamma * pv[a][b];
+      t[a][b] = v;
+      av[a][b] += ck * v;
+    }
+  tile_put(out + j * ss, s, s, I, J, t);
+  tile_put(acc + j * ss, s, s, I, J, av);
+}
+
+void launch_btd_cheb_tile(int m, int s, const double* Hd, const double* Bd, const double* Y, const double* Yp,
+                          double* out, double alpha, double beta, double gamma, double* acc, const double* coef,
+                          int kk, hipStream_t st) {
+  GK_REQUIRE(s <= WCOL, GK_EINVAL, "Chebyshev step: block width above 512");
+  const int nQ = (s + 63) >> 6;
+  hipLaunchKernelGGL(btd_cheb_tile_kernel, dim3(m, nQ, nQ), dim3(ST), 0, st, m, s, Hd, Bd, Y, Yp, out, alpha, beta,
+                     gamma, acc, coef, kk);
+  GK_HIP(hipGetLastError());
+}
+
 }  // namespace gk
