@@ -123,9 +123,9 @@ void launch_reduce_parts(int64_t len, int nparts, const double* part, double* ou
   kt_end(st, 8.0 * (double)len * (nparts + 1), (double)len * nparts, flag);
 }
 
-// Blocks wider than 64 use the FP64 matrix-core kernels below (rows staged
-// 32 at a time); narrower ones the vector kernel above.
-static bool mfma_ok(int ld) { return ld > 64 && ld % 16 == 0; }
+// Blocks 64 and wider use the FP64 matrix-core kernels below (rows staged
+// 32 at a time, 64-wide output tiles); narrower ones the vector kernel above.
+static bool mfma_ok(int ld) { return ld >= 64 && ld % 16 == 0; }
 constexpr int MG_T = 64, MG_RS = 32, MG_P = MG_T + 2;
 
 static void gram_geometry(int64_t n, int nb, int ld, int* nx, int* ny, int* nch, int64_t* rpc) {
