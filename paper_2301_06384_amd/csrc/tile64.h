@@ -161,38 +161,40 @@ __device__ __forceinline__ double readlane_d(double v, int lane) {
 }
 
 // One pivot step J of the 16 x 16 diagonal-block factorisation by wavefront
-// 0.  Lane c (< 16) holds column c of the block (a, both triangles) and column
-// c of its inverse (y).  With symmetric storage lane c already holds
-// L[c][J] = a[J] / l_JJ: it stores that entry of column J of L straight into
-// the LDS tile (zeros above the diagonal), and every lane reads the column
-// back for its update (a wavefront executes its LDS accesses in order, so no
-// barrier is involved).
+// 0.  Lane c < 16 holds column c of the block (both triangles) and lane
+// 16 + c column c of its inverse, in the same registers v, so one stream of
+// FMAs updates both: with f = v[J] / l_JJ (L[c][J] on a factor lane, row J of
+// the inverse on an inverse lane), v[r] -= L[r][J] f for r > J.  Factor lanes
+// store their entry of column J of L straight into the LDS tile (zeros above
+// the diagonal) and every lane reads the column back (a wavefront executes
+// its LDS accesses in order, so no barrier is involved).  Factor lanes c <= J
+// update entries that are never read again, so they need no mask.
+// piv: the pivot A[J][J] after the steps before J.  The next pivot needs only
+// lane J+1's own entries (v[J+1] - f^2), so it is read out before the column
+// exchange; the exchange gives that lane the same value.
 template <int MODE, int J>
 struct DiagStep {
-  __device__ __forceinline__ static void run(double (&a)[16], double (&y)[16], int c, int o, int s, double gl,
-                                             double dl, double thr, int* bad, double* dg, double (*A)[LP]) {
-    const double piv = readlane_d(a[J], J);
+  __device__ __forceinline__ static void run(double (&v)[16], int c, bool ylane, int o, int s, double gl, double dl,
+                                             double thr, int* bad, double* dg, double (*A)[LP], double piv) {
     const double gjj = MODE == 1 ? readlane_d(gl, J) : 0.0;
     const double dpj = MODE == 2 ? readlane_d(dl, J) : 0.0;
     double ljj, inv;
     chol_pivot<MODE>(piv, o + J, s, gjj, dpj, thr, bad, ljj, inv);
     if (dg && threadIdx.x == 0) dg[o + J] = (o + J < s) ? ljj : 0.0;
-    const double lcj = a[J] * inv;     // L[c][J] (used for c > J)
-    if (threadIdx.x < 16) A[o + c][o + J] = c > J ? lcj : (c == J ? ljj : 0.0);
-    y[J] *= inv;                       // row J of the inverse
+    const double f = v[J] * inv;
+    if (ylane) v[J] = f;
+    double pnext = 0.0;
+    if (J + 1 < 16) pnext = readlane_d(fma(-f, f, v[J + 1 < 16 ? J + 1 : J]), J + 1);
+    if (threadIdx.x < 16) A[o + c][o + J] = c > J ? f : (c == J ? ljj : 0.0);
 #pragma unroll
-    for (int r = J + 1; r < 16; ++r) {
-      const double lrj = A[o + r][o + J];   // L[r][J]
-      a[r] = (c > J) ? fma(-lrj, lcj, a[r]) : a[r];
-      y[r] = fma(-lrj, y[J], y[r]);
-    }
-    DiagStep<MODE, J + 1>::run(a, y, c, o, s, gl, dl, thr, bad, dg, A);
+    for (int r = J + 1; r < 16; ++r) v[r] = fma(-A[o + r][o + J], f, v[r]);
+    DiagStep<MODE, J + 1>::run(v, c, ylane, o, s, gl, dl, thr, bad, dg, A, pnext);
   }
 };
 template <int MODE>
 struct DiagStep<MODE, 16> {
-  __device__ __forceinline__ static void run(double (&)[16], double (&)[16], int, int, int, double, double, double,
-                                             int*, double*, double (*)[LP]) {}
+  __device__ __forceinline__ static void run(double (&)[16], int, bool, int, int, double, double, double, int*,
+                                             double*, double (*)[LP], double) {}
 };
 
 // 16 x 16 tile product on FP64 matrix cores (v_mfma_f64_16x16x4f64, lane
@@ -240,24 +242,23 @@ __device__ __forceinline__ void blk_chol_inv_t(double (*A)[LP], double (*Y)[LP],
   for (int b = 0; b < nbk; ++b) {
     const int o = 16 * b;
     const int T = nbk - 1 - b;                 // tile rows below the diagonal block
-    // ---- diagonal block: wavefront 0, lane c < 16 holds column c
+    // ---- diagonal block: wavefront 0; lane c < 16 holds column c of the
+    //      block, lane 16 + c column c of its inverse (starting from I)
     if (tid < 64) {
       const int c = tid & 15;
-      double a[16], y[16];
+      const bool ylane = (tid & 16) != 0;
+      double v[16];
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        a[r] = A[o + r][o + c];
-        y[r] = (r == c) ? 1.0 : 0.0;
-      }
+      for (int r = 0; r < 16; ++r) v[r] = ylane ? ((r == c) ? 1.0 : 0.0) : A[o + r][o + c];
       // the pivot rule's per-column data, lane c holding column o + c
       const double gl = (MODE == 1 && o + c < s) ? g0[o + c] : 0.0;
       const double dl = (MODE == 2 && o + c < s) ? dprev[o + c] : 0.0;
-      DiagStep<MODE, 0>::run(a, y, c, o, s, gl, dl, thr, bad, dg, A);   // writes L_bb into A
-      if (tid < 16) {
+      DiagStep<MODE, 0>::run(v, c, ylane, o, s, gl, dl, thr, bad, dg, A, readlane_d(v[0], 0));   // L_bb into A
+      if (tid >= 16 && tid < 32) {
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
-          Z[o + r][o + c] = (r >= c) ? y[r] : 0.0;   // Y_bb, kept in the diagonal block of Z
-          Y[o + r][o + c] = (r >= c) ? y[r] : 0.0;
+          Z[o + r][o + c] = (r >= c) ? v[r] : 0.0;   // Y_bb, kept in the diagonal block of Z
+          Y[o + r][o + c] = (r >= c) ? v[r] : 0.0;
         }
       }
     }
