@@ -685,17 +685,19 @@ cholqr_blk_kernel(const double* __restrict__ G, int ld, int s, int pass, const d
     for (int i = ty; i < s; i += 16)
       for (int c = tx; c < s; c += 16) e = fmax(e, fabs(A[i][c] - (i == c ? 1.0 : 0.0)));
     for (int q = tid; q < s; q += ST) dmin = fmin(dmin, dp[q]);
-    red[0][tid] = e;
-    red[1][tid] = dmin;
-    __syncthreads();
-    for (int w = ST / 2; w > 0; w >>= 1) {
-      if (tid < w) {
-        red[0][tid] = fmax(red[0][tid], red[0][tid + w]);
-        red[1][tid] = fmin(red[1][tid], red[1][tid + w]);
-      }
-      __syncthreads();
+    // wavefront reductions, then the four wavefront results
+    for (int o = 32; o > 0; o >>= 1) {
+      e = fmax(e, __shfl_xor(e, o));
+      dmin = fmin(dmin, __shfl_xor(dmin, o));
     }
-    fast = red[0][0] <= 1e-6 && red[1][0] >= 2.0 * thr;
+    if ((tid & 63) == 0) {
+      red[0][tid >> 6] = e;
+      red[1][tid >> 6] = dmin;
+    }
+    __syncthreads();
+    const double emax = fmax(fmax(red[0][0], red[0][1]), fmax(red[0][2], red[0][3]));
+    const double dlo = fmin(fmin(red[1][0], red[1][1]), fmin(red[1][2], red[1][3]));
+    fast = emax <= 1e-6 && dlo >= 2.0 * thr;
   }
   if (fast) {
     for (int i = ty; i < WS; i += 16)
@@ -735,11 +737,13 @@ cholqr_blk_kernel(const double* __restrict__ G, int ld, int s, int pass, const d
   // R = L^T, Rinv = Y^T (upper), coalesced stores with zero padding; skipped
   // when the caller passes null (pass 2 returns its factors through Rc and B)
   if (R)
-    for (int q = tid; q < ld * ld; q += ST) {
-      const int i = q / ld, c = q % ld;
-      const bool in = i < s && c < s && c >= i;
-      R[q] = in ? A[c][i] : 0.0;
-      Rinv[q] = in ? Y[c][i] : 0.0;
+    for (int i = tid >> 6; i < ld; i += ST / 64) {
+      const int c = tid & 63;   // ld <= 64: one row per wavefront pass
+      if (c < ld) {
+        const bool in = i < s && c < s && c >= i;
+        R[i * ld + c] = in ? A[c][i] : 0.0;
+        Rinv[i * ld + c] = in ? Y[c][i] : 0.0;
+      }
     }
   for (int q = tid; q < ld; q += ST) diag_out[q] = (q < s) ? dg[q] : 0.0;
   if (pass == 2) {
