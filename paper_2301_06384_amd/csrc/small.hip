@@ -712,8 +712,7 @@ cholqr_blk_kernel(const double* __restrict__ G, int ld, int s, int pass, const d
       }
     __syncthreads();
     double mm[4][4], u2[4][4];
-    lds_mm<true, false>(S1, S1, s, mm);    // U^T U
-    lds_mm<true, false>(S2, S1, s, u2);    // U U
+    lds_mm2(S1, S1, S2, S1, s, mm, u2);    // U^T U and U U
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -726,7 +725,10 @@ cholqr_blk_kernel(const double* __restrict__ G, int ld, int s, int pass, const d
           const double r2 = (c >= r) ? del + u + w : 0.0;
           const double r2i = (c >= r) ? del - u - w + u2[i][j] : 0.0;
           A[c][r] = r2;    // L = R^T
-          Y[c][r] = r2i;   // L^{-1} = R^{-T}
+          // L^{-1} = R^{-T} when R^{-1} is returned; otherwise R^{-1} itself
+          // (row-major), the operand of Rc = R1inv R2inv below
+          if (R) Y[c][r] = r2i;
+          else Y[r][c] = r2i;
           if (r == c) dg[r] = r2;
         }
       }
@@ -762,6 +764,21 @@ cholqr_blk_kernel(const double* __restrict__ G, int ld, int s, int pass, const d
     }
     __syncthreads();
     double acc[4][4];
+    if (fast && !R) {
+      // B = R2 R1 = L^T S1 and Rc = R1inv R2inv = (R1inv^T)^T (R2inv in Y),
+      // interleaved
+      double rc[4][4];
+      lds_mm2(A, S1, S2, Y, s, acc, rc);
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int r = acc_row(i), c = acc_col(j);
+          if (r < s && c < s) Bout[r * s + c] = acc[i][j];
+          if (r < ld && c < ld) Rc[r * ld + c] = (r < s && c < s) ? rc[i][j] : 0.0;
+        }
+      return;
+    }
     // B = R2 * R1 = L^T * S1
     lds_mm<true, false>(A, S1, s, acc);
 #pragma unroll

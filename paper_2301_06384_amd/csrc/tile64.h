@@ -47,6 +47,48 @@ __device__ __forceinline__ void mm_steps(const double (*A)[LP], const double (*B
   }
 }
 
+// Two independent products in one loop (eight accumulator chains per
+// wavefront instead of four): acc1 = A1^T B1, acc2 = A2^T B2, layout as lds_mm.
+template <int NT>
+__device__ __forceinline__ void mm_steps2(const double (*A1)[LP], const double (*B1)[LP], const double (*A2)[LP],
+                                          const double (*B2)[LP], int s, dv4 (&d1)[4], dv4 (&d2)[4]) {
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63, li = l & 15, lk = l >> 4;
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int kk = 4 * t + lk;
+    const bool in = kk < s;
+    const double a1 = A1[kk][16 * w + li], a2 = A2[kk][16 * w + li];
+    double b1[4], b2[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      b1[b] = B1[kk][16 * b + li];
+      b2[b] = B2[kk][16 * b + li];
+    }
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      d1[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(in ? a1 : 0.0, in ? b1[b] : 0.0, d1[b], 0, 0, 0);
+      d2[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(in ? a2 : 0.0, in ? b2[b] : 0.0, d2[b], 0, 0, 0);
+    }
+  }
+}
+__device__ __forceinline__ void lds_mm2(const double (*A1)[LP], const double (*B1)[LP], const double (*A2)[LP],
+                                        const double (*B2)[LP], int s, double (&acc1)[4][4], double (&acc2)[4][4]) {
+  dv4 d1[4], d2[4];
+#pragma unroll
+  for (int b = 0; b < 4; ++b) d1[b] = d2[b] = dv4{0.0, 0.0, 0.0, 0.0};
+  if (s > 48) mm_steps2<16>(A1, B1, A2, B2, s, d1, d2);
+  else if (s > 32) mm_steps2<12>(A1, B1, A2, B2, s, d1, d2);
+  else if (s > 16) mm_steps2<8>(A1, B1, A2, B2, s, d1, d2);
+  else mm_steps2<4>(A1, B1, A2, B2, s, d1, d2);
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      acc1[a][b] = d1[b][a];
+      acc2[a][b] = d2[b][a];
+    }
+}
+
 // acc = A^T B summed over the first s rows of two 64 x 64 LDS operands
 // (256 threads).  Wave w computes output rows 16w .. 16w+15 as four 16 x 16
 // tiles of v_mfma_f64_16x16x4f64: lane l = i + 16k holds A[4t+k][16w+i] and
