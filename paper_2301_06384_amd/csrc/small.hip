@@ -31,7 +31,7 @@ cholqr_factor_kernel(const double* __restrict__ G, int ld, int s, int pass,
                      double* __restrict__ R, double* __restrict__ Rinv, double* __restrict__ diag_out,
                      int* __restrict__ n_defl) {
   __shared__ double rjj_sh;
-  __shared__ int ndef_sh;
+  __shared__ int ndef_sh, clamp_sh;
   const int tid = threadIdx.x;
   const double eta = 1e-7;
   for (int q = tid; q < ld * ld; q += SB) {
@@ -45,9 +45,13 @@ cholqr_factor_kernel(const double* __restrict__ G, int ld, int s, int pass,
     if (tid == 0) {
       const double piv = W[j * ld + j];
       double r = 0.0;
+      int cl = 0;
       if (pass == 1) {
         const double g0 = G[j * ld + j];
-        if (g0 > thr * thr) r = sqrt(fmax(piv, eta * eta * g0));
+        if (g0 > thr * thr) {
+          r = sqrt(fmax(piv, eta * eta * g0));
+          cl = !(piv >= eta * eta * g0);   // clamped: decoupled below
+        }
       } else {
         if (piv > 0.0) {
           r = sqrt(piv);
@@ -56,12 +60,15 @@ cholqr_factor_kernel(const double* __restrict__ G, int ld, int s, int pass,
       }
       if (r == 0.0) ndef_sh++;
       rjj_sh = r;
+      clamp_sh = cl;
       diag_out[j] = r;
       R[j * ld + j] = r;
     }
     __syncthreads();
     const double rjj = rjj_sh;
-    if (rjj != 0.0) {
+    // a clamped pivot keeps its (clamped) diagonal but no coupling to the
+    // later columns: R[j][c] = 0 for c > j, no Schur update
+    if (rjj != 0.0 && !clamp_sh) {
       for (int c = j + 1 + tid; c < s; c += SB) R[j * ld + c] = W[j * ld + c] / rjj;
       __syncthreads();
       const int w = s - j - 1;
@@ -666,6 +673,7 @@ cholqr_blk_kernel(const double* __restrict__ G, int ld, int s, int pass, const d
   __shared__ __align__(16) double S1[WS][LP];
   __shared__ __align__(16) double S2[WS][LP];
   __shared__ double g0[WS], dp[WS], dg[WS];
+  __shared__ int clf[WS];
   __shared__ double red[2][ST];
   const int tid = threadIdx.x;
   const int tx = tid & 15, ty = tid >> 4;
@@ -734,7 +742,7 @@ cholqr_blk_kernel(const double* __restrict__ G, int ld, int s, int pass, const d
       }
     __syncthreads();
   } else {
-    blk_chol_inv(A, Y, S1, s, pass, g0, dp, thr, dg, nullptr);
+    blk_chol_inv(A, Y, S1, s, pass, g0, dp, thr, dg, nullptr, clf);
   }
   // R = L^T, Rinv = Y^T (upper), coalesced stores with zero padding; skipped
   // when the caller passes null (pass 2 returns its factors through Rc and B)
@@ -843,7 +851,7 @@ banded_factor_blk_kernel(int m, int s, const double* __restrict__ Hd, const doub
         }
       __syncthreads();
     }
-    blk_chol_inv(A, Y, SB, s, 0, nullptr, nullptr, 0.0, nullptr, bad);
+    blk_chol_inv(A, Y, SB, s, 0, nullptr, nullptr, 0.0, nullptr, bad, nullptr);
     double* LiG = Linv_all + (int64_t)j * ss;
     for (int i = ty; i < s; i += 16)
       for (int c = tx; c < s; c += 16) LiG[i * s + c] = (c <= i) ? Y[i][c] : 0.0;

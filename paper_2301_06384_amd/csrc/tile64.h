@@ -153,8 +153,13 @@ __device__ __forceinline__ void stage64(double (*D)[LP], const double* __restric
 // Inside a diagonal block the pivots follow the rules of `mode`:
 //   0: plain (non-positive pivot -> *bad = 3, pivot 1 used);
 //   1 / 2: the CholQR deflation rules (see cholqr_factor_kernel).
-// Deflated columns give zero columns of L and zero rows of Y.  Indices s..63
-// are padded with an identity block.  Z is clobbered.
+// Deflated columns give zero columns of L and zero rows of Y.  A column whose
+// pivot rule 1 clamps (numerically dependent on the earlier ones) is kept with
+// its clamped diagonal but decoupled: its entries of L below the diagonal are
+// zero, so no later column is eliminated against it; without that, chains of
+// clamped pivots compound 1 / l factors in L^{-1} until it overflows.  The
+// flags go to clf[column] when clf is not null.  Indices s..63 are padded with
+// an identity block.  Z is clobbered.
 // 1/sqrt(p) for p > 0: hardware estimate refined by two Newton steps.
 __device__ __forceinline__ double rsqrt_nr(double p) {
   double y = __builtin_amdgcn_rsq(p);
@@ -166,9 +171,12 @@ __device__ __forceinline__ double rsqrt_nr(double p) {
 // Pivot rule of column j (global index gj): returns l_jj and 1 / l_jj (0 for
 // a deflated column).  gjj = original Gram diagonal (mode 1), dpj = first-pass
 // diagonal (mode 2).
+// cl (rule 1): the pivot was clamped; the column is then decoupled (its
+// entries of L below the diagonal are zero), see blk_chol_inv_t.
 template <int MODE>
 __device__ __forceinline__ void chol_pivot(double piv, int gj, int s, double gjj, double dpj, double thr, int* bad,
-                                           double& l, double& inv) {
+                                           double& l, double& inv, bool& cl) {
+  cl = false;
   // branch-free: the reciprocal square root is taken of a safe argument and
   // the rule selects the result
   if (MODE == 0) {
@@ -180,6 +188,7 @@ __device__ __forceinline__ void chol_pivot(double piv, int gj, int s, double gjj
   } else if (MODE == 1) {
     const double eta = 1e-7;
     const bool keep = gjj > thr * thr;
+    cl = keep && gj < s && !(piv >= eta * eta * gjj);
     const double pp = keep ? fmax(piv, eta * eta * gjj) : 1.0;
     const double y = rsqrt_nr(pp);
     l = keep ? pp * y : 0.0;
@@ -217,26 +226,32 @@ __device__ __forceinline__ double readlane_d(double v, int lane) {
 template <int MODE, int J>
 struct DiagStep {
   __device__ __forceinline__ static void run(double (&v)[16], int c, bool ylane, int o, int s, double gl, double dl,
-                                             double thr, int* bad, double* dg, double (*A)[LP], double piv) {
+                                             double thr, int* bad, double* dg, int* clf, double (*A)[LP],
+                                             double piv) {
     const double gjj = MODE == 1 ? readlane_d(gl, J) : 0.0;
     const double dpj = MODE == 2 ? readlane_d(dl, J) : 0.0;
     double ljj, inv;
-    chol_pivot<MODE>(piv, o + J, s, gjj, dpj, thr, bad, ljj, inv);
-    if (dg && threadIdx.x == 0) dg[o + J] = (o + J < s) ? ljj : 0.0;
-    const double f = v[J] * inv;
+    bool cl;
+    chol_pivot<MODE>(piv, o + J, s, gjj, dpj, thr, bad, ljj, inv, cl);
+    if (threadIdx.x == 0) {
+      if (dg) dg[o + J] = (o + J < s) ? ljj : 0.0;
+      if (clf) clf[o + J] = cl ? 1 : 0;
+    }
+    // a clamped pivot decouples its column: L[c][J] = 0 below the diagonal
+    const double f = (cl && !ylane) ? 0.0 : v[J] * inv;
     if (ylane) v[J] = f;
     double pnext = 0.0;
     if (J + 1 < 16) pnext = readlane_d(fma(-f, f, v[J + 1 < 16 ? J + 1 : J]), J + 1);
     if (threadIdx.x < 16) A[o + c][o + J] = c > J ? f : (c == J ? ljj : 0.0);
 #pragma unroll
     for (int r = J + 1; r < 16; ++r) v[r] = fma(-A[o + r][o + J], f, v[r]);
-    DiagStep<MODE, J + 1>::run(v, c, ylane, o, s, gl, dl, thr, bad, dg, A, pnext);
+    DiagStep<MODE, J + 1>::run(v, c, ylane, o, s, gl, dl, thr, bad, dg, clf, A, pnext);
   }
 };
 template <int MODE>
 struct DiagStep<MODE, 16> {
   __device__ __forceinline__ static void run(double (&)[16], int, bool, int, int, double, double, double, int*,
-                                             double*, double (*)[LP], double) {}
+                                             double*, int*, double (*)[LP], double) {}
 };
 
 // 16 x 16 tile product on FP64 matrix cores (v_mfma_f64_16x16x4f64, lane
@@ -268,7 +283,7 @@ __device__ __forceinline__ void tile_store(double (*A)[LP], int r0, int c0, dv4 
 
 template <int MODE>
 __device__ __forceinline__ void blk_chol_inv_t(double (*A)[LP], double (*Y)[LP], double (*Z)[LP], int s, const double* g0,
-                               const double* dprev, double thr, double* dg, int* bad) {
+                               const double* dprev, double thr, double* dg, int* bad, int* clf) {
   const int tid = threadIdx.x;
   const int wv = tid >> 6;
   const int nbk = (s + 15) >> 4;
@@ -295,7 +310,7 @@ __device__ __forceinline__ void blk_chol_inv_t(double (*A)[LP], double (*Y)[LP],
       // the pivot rule's per-column data, lane c holding column o + c
       const double gl = (MODE == 1 && o + c < s) ? g0[o + c] : 0.0;
       const double dl = (MODE == 2 && o + c < s) ? dprev[o + c] : 0.0;
-      DiagStep<MODE, 0>::run(v, c, ylane, o, s, gl, dl, thr, bad, dg, A, readlane_d(v[0], 0));   // L_bb into A
+      DiagStep<MODE, 0>::run(v, c, ylane, o, s, gl, dl, thr, bad, dg, clf, A, readlane_d(v[0], 0));   // L_bb into A
       if (tid >= 16 && tid < 32) {
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
@@ -322,6 +337,8 @@ __device__ __forceinline__ void blk_chol_inv_t(double (*A)[LP], double (*Y)[LP],
         else tile_store(Y, o, 16 * (t2 - T), mma_tile<false, false>(Z, o, o, Z, o, 16 * (t2 - T), res2));
       }
       __syncthreads();
+      // columns with a clamped pivot stay decoupled (lane i holds column o + i)
+      if (clf && clf[o + (threadIdx.x & 15)]) res = res2 = dv4{0.0, 0.0, 0.0, 0.0};
       if (task < T) tile_store(A, o + 16 * (1 + task), o, res);
       if (task + 4 < T) tile_store(A, o + 16 * (1 + task + 4), o, res2);
     }
@@ -355,10 +372,10 @@ __device__ __forceinline__ void blk_chol_inv_t(double (*A)[LP], double (*Y)[LP],
 }
 
 __device__ __forceinline__ void blk_chol_inv(double (*A)[LP], double (*Y)[LP], double (*Z)[LP], int s, int mode, const double* g0,
-                             const double* dprev, double thr, double* dg, int* bad) {
-  if (mode == 0) blk_chol_inv_t<0>(A, Y, Z, s, g0, dprev, thr, dg, bad);
-  else if (mode == 1) blk_chol_inv_t<1>(A, Y, Z, s, g0, dprev, thr, dg, bad);
-  else blk_chol_inv_t<2>(A, Y, Z, s, g0, dprev, thr, dg, bad);
+                             const double* dprev, double thr, double* dg, int* bad, int* clf) {
+  if (mode == 0) blk_chol_inv_t<0>(A, Y, Z, s, g0, dprev, thr, dg, bad, clf);
+  else if (mode == 1) blk_chol_inv_t<1>(A, Y, Z, s, g0, dprev, thr, dg, bad, clf);
+  else blk_chol_inv_t<2>(A, Y, Z, s, g0, dprev, thr, dg, bad, clf);
 }
 
 }  // namespace gk

@@ -102,7 +102,7 @@ __device__ __forceinline__ void wterm(double (&tot)[4][4], double sign, const do
 // g0 / dp / dg: per-column data of the pivot rule (LDS, global column index).
 template <int MODE>
 __device__ __forceinline__ void wide_chol_inv(double* __restrict__ A, double* __restrict__ Y, int ld, int s, const double* g0,
-                              const double* dp, double thr, double* dg, int* bad, double (*T0)[LP],
+                              const double* dp, double thr, double* dg, int* bad, int* clf, double (*T0)[LP],
                               double (*T1)[LP], double (*T2)[LP], double (*T3)[LP]) {
   const int tid = threadIdx.x;
   const int tx = tid & 15, ty = tid >> 4;
@@ -119,7 +119,7 @@ __device__ __forceinline__ void wide_chol_inv(double* __restrict__ A, double* __
     }
     __syncthreads();
     blk_chol_inv_t<MODE>(T0, T1, T2, sb, g0 ? g0 + 64 * b : nullptr, dp ? dp + 64 * b : nullptr, thr,
-                         dg ? dg + 64 * b : nullptr, bad);
+                         dg ? dg + 64 * b : nullptr, bad, clf ? clf + 64 * b : nullptr);
     // L_bb, Y_bb out; T3 = Y_bb^T for the panel products
     for (int i = ty; i < WS; i += 16)
       for (int c = tx; c < WS; c += 16) {
@@ -138,6 +138,14 @@ __device__ __forceinline__ void wide_chol_inv(double* __restrict__ A, double* __
       __syncthreads();
       double acc[4][4];
       lds_mm<true, false>(T2, T3, sb, acc);
+      if (clf) {
+        // columns with a clamped pivot stay decoupled
+#pragma unroll
+        for (int bb = 0; bb < 4; ++bb)
+          if (clf[64 * b + acc_col(bb)])
+#pragma unroll
+            for (int a = 0; a < 4; ++a) acc[a][bb] = 0.0;
+      }
       tile_put(A, ld, s, i, b, acc);
     }
     // trailing update of the lower tiles
@@ -191,6 +199,7 @@ cholqr_wide_kernel(const double* __restrict__ G, int ld, int s, int pass, const 
   __shared__ __align__(16) double T2[WS][LP];
   __shared__ __align__(16) double T3[WS][LP];
   __shared__ double g0[WCOL], dp[WCOL], dg[WCOL];
+  __shared__ int clf[WCOL];
   const int tid = threadIdx.x;
   const int nQ = (s + 63) >> 6;
   for (int q = tid; q < ld * ld; q += ST) Aw[q] = G[q];
@@ -200,9 +209,9 @@ cholqr_wide_kernel(const double* __restrict__ G, int ld, int s, int pass, const 
   }
   __syncthreads();
   if (pass == 1)
-    wide_chol_inv<1>(Aw, Yw, ld, s, g0, dp, thr, dg, nullptr, T0, T1, T2, T3);
+    wide_chol_inv<1>(Aw, Yw, ld, s, g0, dp, thr, dg, nullptr, clf, T0, T1, T2, T3);
   else
-    wide_chol_inv<2>(Aw, Yw, ld, s, g0, dp, thr, dg, nullptr, T0, T1, T2, T3);
+    wide_chol_inv<2>(Aw, Yw, ld, s, g0, dp, thr, dg, nullptr, clf, T0, T1, T2, T3);
   // R = L^T, Rinv = Y^T (upper, zero padded); skipped when R is null
   if (R)
     for (int q = tid; q < ld * ld; q += ST) {
@@ -356,7 +365,7 @@ banded_factor_wide_kernel(int m, int s, const double* __restrict__ Hd, const dou
         tile_put(Aw, s, s, I, J, t);
       }
     double* Li = Linv + j * ss;
-    wide_chol_inv<0>(Aw, Li, s, s, nullptr, nullptr, 0.0, nullptr, bad, T0, T1, T2, T3);
+    wide_chol_inv<0>(Aw, Li, s, s, nullptr, nullptr, 0.0, nullptr, bad, nullptr, T0, T1, T2, T3);
     if (j + 1 < m) {
       // Lsub_j = B_j Linv_j^T: tile (I, J) sums over K <= J (Linv_j lower)
       for (int I = 0; I < nQ; ++I)

@@ -135,6 +135,29 @@ def test_exhaustion_and_deflation():
     assert rel(P, dense.phi_columns(L.to_scipy(), W, phi)) < 1e-10
 
 
+@pytest.mark.parametrize("s,m,ref", [(64, 5, "dense"), (128, 3, "dense"), (72, 4, "krylov"), (100, 3, "krylov")])
+def test_wide_exhaustion_and_deflation(s, m, ref):
+    # Blocks that run out of new directions on a 256-node grid, where
+    # the block Krylov space is the whole space ("dense": exact, compared with
+    # the spectral oracle) or stops growing ("krylov": deflation leaves a
+    # smaller space; compared with the Krylov oracle of the same depth).
+    # Numerically dependent columns take the clamped-pivot route of the first
+    # CholQR pass and must be deflated by the second without overflow.
+    L = I.grid((16, 16))
+    g = gk.Graph.from_laplacian(L)
+    W = I.samples(L.n, s, 11)
+    for phi in [dict(kind="diffusion", t=0.6), dict(kind="spline", eps=0.03, k=2.0)]:
+        if ref == "dense":
+            R = dense.phi_columns(L.to_scipy(), W, phi)
+        else:
+            R = krylov.cbl(L.to_scipy(), W, phi, m)["P"]
+        for prec, flags in (("fp64", 0), ("mixed", 0), ("mixed", gk.FULL_REORTH)):
+            P, K, st = gk.krylov_kernel_columns(g, W, phi, m, "cbl", prec, flags=flags)
+            assert np.all(np.isfinite(P))
+            assert st.n_deflated > 0
+            assert rel(P, R) < TOL[prec], (prec, flags, phi, rel(P, R))
+
+
 def test_banded_and_spectral_phi_agree():
     L, g = G("rgg2003")
     W = I.samples(L.n, 12, 3)
