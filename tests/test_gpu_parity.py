@@ -302,6 +302,38 @@ def test_device_io_matches_host():
     assert np.array_equal(kout.cpu().numpy().T, Kh)
 
 
+def test_empty_and_degenerate_requests():
+    # no samples / no Krylov steps are refused; m = 1 (H_11 alone) and m = 2
+    # (below the depth at which partial reorthogonalisation starts) match the
+    # oracle
+    L, g = G("rgg2003")
+    phi = dict(kind="diffusion", t=0.9)
+    for bad in (dict(samples=[], m=4), dict(samples=[1, 2], m=0)):
+        with pytest.raises(gk.GKError) as e:
+            gk.krylov_kernel_columns(g, bad["samples"], phi, bad["m"])
+        assert e.value.code == gk.EINVAL
+    W = I.samples(L.n, 7, 5)
+    for m in (1, 2):
+        ref = krylov.cbl(L.to_scipy(), W, phi, m)["P"]
+        for prec in ("fp64", "mixed"):
+            P, K, st = gk.krylov_kernel_columns(g, W, phi, m, "cbl", prec)
+            assert rel(P, ref) < TOL[prec], (m, prec, rel(P, ref))
+
+
+@pytest.mark.parametrize("s,m", [(600, 2), (1024, 1)])
+def test_widths_above_512(s, m):
+    # blocks wider than the 8 x 8 tiles of 64 (up to the maximum s = 1024):
+    # generic CholQR, full reorthogonalisation, the one-thread-per-entry
+    # Chebyshev step and the generic banded solve
+    L, g = G("rgg2003")
+    W = I.samples(L.n, s, 13)
+    for phi in (dict(kind="diffusion", t=0.5), dict(kind="spline", eps=0.05, k=2.0)):
+        ref = krylov.cbl(L.to_scipy(), W, phi, m)["P"]
+        for prec in ("fp64", "mixed"):
+            P, K, st = gk.krylov_kernel_columns(g, W, phi, m, "cbl", prec)
+            assert rel(P, ref) < TOL[prec], (s, m, prec, phi, rel(P, ref))
+
+
 def test_error_paths_on_device():
     L, g = G("rgg2003")
     phi = dict(kind="diffusion", t=1.0)
