@@ -38,7 +38,6 @@ ROOFS = {
     "panel_update_self": ("mfma", 78.6, "TFLOP/s", "panel.hip"),
     "panel_apply_self": ("mfma", 78.6, "TFLOP/s", "panel.hip"),
     "panel_apply_write": ("mfma", 78.6, "TFLOP/s", "panel.hip"),
-    "panel_self": ("mfma", 78.6, "TFLOP/s", "panel.hip"),
     "arch_gram": ("mfma", 157.3, "TFLOP/s", "arch.hip"),
     "arch_update": ("mfma", 157.3, "TFLOP/s", "arch.hip"),
     "gram": ("mfma", 78.6, "TFLOP/s", "ortho.hip"),

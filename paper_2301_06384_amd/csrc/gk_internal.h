@@ -169,9 +169,6 @@ void launch_cholqr_reg(const double* G, int ld, int s, int pass, const double* d
                        double* Bout, hipStream_t st);
 void launch_banded_spline_reg(int m, int s, const double* Hd, const double* Bd, double eps, int k, double* work,
                               double* U, int* bad, hipStream_t st);
-void launch_cholqr_flag(const double* G, int ld, int s, int pass, const double* diag_prev, double thr, double* R,
-                        double* Rinv, double* diag_out, int* n_defl, const double* R1, const double* R1inv, double* Rc,
-                        double* Bout, const int* flag, hipStream_t st);
 // Block orthogonality estimate (partial reorthogonalisation) for s <= 512.
 // est_part holds m * omega_est_per_block(s) entries; rhs_wide is null for
 // s <= 64 and omega_wide_scratch_elems(m, s) doubles otherwise.
@@ -185,7 +182,7 @@ bool wide_ok(int ld);
 size_t cholqr_wide_scratch_elems(int ld);
 void launch_cholqr_wide(const double* G, int ld, int s, int pass, const double* diag_prev, double thr, double* wk,
                         double* R, double* Rinv, double* diag_out, int* n_defl, const double* R1, const double* R1inv,
-                        double* Rc, double* Bout, const int* flag, hipStream_t st);
+                        double* Rc, double* Bout, hipStream_t st);
 size_t omega_wide_scratch_elems(int m, int s);
 void launch_omega_wide(int k, int s, int ld, const double* Wk, const double* Wkm1, double* Wk1, const double* Hd,
                        const double* Bd, const double* Rc, double nu, double* rhs, double* est_part, hipStream_t st);
@@ -205,7 +202,7 @@ void launch_small_solve(int s, const double* K, double gamma, const double* y, d
                         int* piv, bool spd, int* bad, hipStream_t st);
 
 // panel.hip -- fused row-panel MFMA passes (ld in {16, 32, 48, 64})
-enum { PM_GRAMV = 0, PM_UPDATE_SELF = 1, PM_APPLY_SELF = 2, PM_APPLY_WRITE = 3, PM_SELF = 4 };
+enum { PM_GRAMV = 0, PM_UPDATE_SELF = 1, PM_APPLY_SELF = 2, PM_APPLY_WRITE = 3 };
 bool panel_ok(int ld);
 // arch.hip -- projection against the float32 archive on FP32 matrix cores
 bool arch_ok(int ld);
@@ -217,7 +214,7 @@ void launch_arch_assemble(int64_t n, int ld, int s, BlockList A, const double* U
 size_t panel_scratch_elems(int64_t n, int ld);
 void launch_panel(int mode, int64_t n, int ld, int nbv, const double* X, double* Xout, float* X32,
                   const double* V0, const double* V1, const double* Cupd, const double* Rm, double* part,
-                  double* Cout, hipStream_t st, const int* flag = nullptr);
+                  double* Cout, hipStream_t st);
 
 // krylov.hip -- one call of the compute entry points
 struct CallArgs {
@@ -259,7 +256,7 @@ enum Phase { PH_SPMM = 0, PH_ORTH, PH_REORTH, PH_PHI, PH_ASM, PH_FIT, PH_TOTAL }
 // algorithmic bytes and flops of that launch.  kt_start / kt_finish bracket a
 // call on the calling thread; gk_kernel_timings returns the aggregate.
 enum KernelClass {
-  KC_SPMM = 0, KC_PANEL_GRAMV, KC_PANEL_UPDATE_SELF, KC_PANEL_APPLY_SELF, KC_PANEL_APPLY_WRITE, KC_PANEL_SELF,
+  KC_SPMM = 0, KC_PANEL_GRAMV, KC_PANEL_UPDATE_SELF, KC_PANEL_APPLY_SELF, KC_PANEL_APPLY_WRITE,
   KC_GRAM, KC_TSGEMM, KC_ARCH_GRAM, KC_ARCH_UPDATE, KC_REDUCE, KC_CHOLQR, KC_OMEGA, KC_BANDED_FACTOR,
   KC_BANDED_SOLVE, KC_CHEB, KC_EIG, KC_ASSEMBLE, KC_PREDICT, KC_COUNT
 };

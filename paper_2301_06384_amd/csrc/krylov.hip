@@ -460,9 +460,34 @@ static void run_cbl(Job& J) {
         launch_cholqr_reg(G, ld, s, 1, nullptr, J.thr(), R1, R1i, d1, nullptr, nullptr, nullptr, nullptr, nullptr, st);
       else if (widek)
         launch_cholqr_wide(G, ld, s, 1, nullptr, J.thr(), W, R1, R1i, d1, nullptr, nullptr, nullptr, nullptr, nullptr,
-                           nullptr, st);
+                           st);
       else
         launch_cholqr_factor(G, ld, s, 1, nullptr, J.thr(), W, R1, R1i, d1, nullptr, st);
+      if (pro && k >= 1) {
+        // Orthogonality estimate of the new block, taken after the first
+        // CholQR pass with B_k^{-1} ~ R1^{-1} (B_k = R2 R1, R2 = I + O(u)), so
+        // a flagged X is projected against the archive blocks 0..k-2 before
+        // it is normalised (the local blocks were handled exactly in float64
+        // above).  The second pass then absorbs the change: Y = X R1^{-1} has
+        // moved by |V_a^T Y| ~ tau, and CholQR of Y restores orthonormality.
+        // One projection suffices: from a loss of at most tau it reaches the
+        // floor set by the float32 archive.  At k = 1 the estimate has no
+        // block to act on.
+        const int* fk = fr + k;
+        launch_omega(k, s, ld, Wr[k % 3], Wr[(k + 2) % 3], Wr[(k + 1) % 3], Hd, Bd, R1i, om_nu, om_tau, om_floor_re,
+                     om_floor_loc, est_part, fr, forced, J.dscal + 1, J.dflags + 3, om_rhs, st);
+        if (k >= 2) {
+          J.tm.begin(PH_REORTH);
+          BlockList all{Va, blk, k - 1, true};
+          if (part_arch) {
+            launch_arch_reorth(n, ld, all, X, C, part_arch, fk, st);
+          } else {
+            launch_gram(n, ld, all, X, C, part_all, fk, st);
+            launch_tsgemm(n, ld, all, C, X, X, nullptr, -1.0, 1.0, fk, st);
+          }
+          J.tm.begin(PH_ORTH);
+        }
+      }
       if (pan) {
         launch_panel(PM_APPLY_SELF, n, ld, 0, X, nullptr, nullptr, nullptr, nullptr, nullptr, R1i, ppart, G, st);
       } else {
@@ -475,53 +500,11 @@ static void run_cbl(Job& J) {
                           Bd + (int64_t)k * s * s, st);
       } else if (widek) {
         launch_cholqr_wide(G, ld, s, 2, d1, J.thr(), W, nullptr, nullptr, d2, J.dflags + 1, R1, R1i, R12i,
-                           Bd + (int64_t)k * s * s, nullptr, st);
+                           Bd + (int64_t)k * s * s, st);
       } else {
         launch_cholqr_factor(G, ld, s, 2, d1, J.thr(), W, R2, R2i, d2, J.dflags + 1, st);
         launch_small_gemm(ld, ld, ld, R1i, ld, false, R2i, ld, false, R12i, ld, 1.0, 0.0, st);
         launch_small_gemm(s, s, s, R2, ld, false, R1, ld, false, Bd + (int64_t)k * s * s, s, 1.0, 0.0, st);
-      }
-      if (pro && k >= 1) {
-        const int* fk = fr + k;
-        launch_omega(k, s, ld, Wr[k % 3], Wr[(k + 2) % 3], Wr[(k + 1) % 3], Hd, Bd, R12i, om_nu, om_tau, om_floor_re,
-                     om_floor_loc, est_part, fr, forced, J.dscal + 1, J.dflags + 3, om_rhs, st);
-        // flagged: reorthogonalise X against the archive blocks 0..k-2 (the
-        // local blocks were handled exactly in float64) and redo CholQR2.  One
-        // pass suffices: from a loss of at most tau it reaches the floor set by
-        // the float32 archive.  At k = 1 the estimate has no block to act on.
-        if (k >= 2) {
-          J.tm.begin(PH_REORTH);
-          BlockList all{Va, blk, k - 1, true};
-          if (part_arch) {
-            launch_arch_reorth(n, ld, all, X, C, part_arch, fk, st);
-          } else {
-            launch_gram(n, ld, all, X, C, part_all, fk, st);
-            launch_tsgemm(n, ld, all, C, X, X, nullptr, -1.0, 1.0, fk, st);
-          }
-          if (pan)
-            launch_panel(PM_SELF, n, ld, 0, X, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, ppart, G, st, fk);
-          else
-            launch_gram(n, ld, xl, X, G, part, fk, st);   // one-block Gram: `part` covers it
-          if (wave)
-            launch_cholqr_flag(G, ld, s, 1, nullptr, J.thr(), R1, R1i, d1, nullptr, nullptr, nullptr, nullptr, nullptr,
-                               fk, st);
-          else
-            launch_cholqr_wide(G, ld, s, 1, nullptr, J.thr(), W, R1, R1i, d1, nullptr, nullptr, nullptr, nullptr,
-                               nullptr, fk, st);
-          if (pan) {
-            launch_panel(PM_APPLY_SELF, n, ld, 0, X, nullptr, nullptr, nullptr, nullptr, nullptr, R1i, ppart, G, st, fk);
-          } else {
-            launch_tsgemm(n, ld, xl, R1i, nullptr, Y, nullptr, 1.0, 0.0, fk, st);
-            launch_gram(n, ld, BlockList{Y, blk, 1, false}, Y, G, part, fk, st);
-          }
-          if (wave)
-            launch_cholqr_flag(G, ld, s, 2, d1, J.thr(), nullptr, nullptr, d2, nullptr, R1, R1i, R12i,
-                               Bd + (int64_t)k * s * s, fk, st);
-          else
-            launch_cholqr_wide(G, ld, s, 2, d1, J.thr(), W, nullptr, nullptr, d2, nullptr, R1, R1i, R12i,
-                               Bd + (int64_t)k * s * s, fk, st);
-          J.tm.begin(PH_ORTH);
-        }
       }
       float* arch32 = mixed ? Va + (int64_t)(k + 1) * blk : nullptr;
       if (pan)

@@ -37,7 +37,6 @@ struct PanelArgs {
   const double* C;       // (nbv*ld) x ld update coefficients (UPDATE)
   const double* Rm;      // ld x ld upper triangular right factor (APPLY)
   double* part;          // [gridDim.x][ngb*ld][ld] Gram partials
-  const int* flag;       // when non-null and *flag == 0 the pass is skipped
 };
 
 // NT: ld / 16.  NBV: local blocks staged.  UPDATE: X_new = X - [V] C.
@@ -45,7 +44,6 @@ struct PanelArgs {
 // (symmetric: only tiles gi <= xj are formed, the partial is mirrored).
 template <int NT, int NBV, bool UPDATE, bool APPLY, bool GRAMV, bool SELF, bool WRITE, bool W32>
 __global__ void __launch_bounds__(PT_THREADS, 2) panel_kernel(PanelArgs p) {
-  if (p.flag && *p.flag == 0) return;
   constexpr int LD = NT * 16;
   constexpr int P = LD + 4;                      // LDS row pitch (doubles)
   constexpr int KS = LD / 4;                     // MFMA k-steps over ld
@@ -286,9 +284,6 @@ static void panel_dispatch(PanelMode mode, int nbv, const PanelArgs& a, int grid
       if (a.X32) GK_PK(0, false, true, false, false, true, true);
       else GK_PK(0, false, true, false, false, true, false);
       break;
-    case PM_SELF:
-      GK_PK(0, false, false, false, true, false, false);
-      break;
   }
 #undef GK_PK
   GK_HIP(hipGetLastError());
@@ -297,21 +292,19 @@ static void panel_dispatch(PanelMode mode, int nbv, const PanelArgs& a, int grid
 // Launch one panel pass and (when it produces a Gram) reduce it into C.
 void launch_panel(int mode, int64_t n, int ld, int nbv, const double* X, double* Xout, float* X32,
                   const double* V0, const double* V1, const double* Cupd, const double* Rm, double* part,
-                  double* Cout, hipStream_t st, const int* flag) {
-  PanelArgs a{n, X, Xout, X32, V0, V1, Cupd, Rm, part, flag};
+                  double* Cout, hipStream_t st) {
+  PanelArgs a{n, X, Xout, X32, V0, V1, Cupd, Rm, part};
   const int grid = panel_grid(n);
   const PanelMode pm = (PanelMode)mode;
   // algorithmic bytes / flops of the pass (block = n x ld float64)
   const double blk = 8.0 * (double)n * ld, nl2 = (double)n * ld * ld, self = (double)n * ld * (ld + 1);
-  static const int kc[5] = {KC_PANEL_GRAMV, KC_PANEL_UPDATE_SELF, KC_PANEL_APPLY_SELF, KC_PANEL_APPLY_WRITE,
-                            KC_PANEL_SELF};
+  static const int kc[4] = {KC_PANEL_GRAMV, KC_PANEL_UPDATE_SELF, KC_PANEL_APPLY_SELF, KC_PANEL_APPLY_WRITE};
   double kb = 0, kf = 0;
   switch (pm) {
     case PM_GRAMV: kb = blk * (1 + nbv); kf = 2.0 * nl2 * nbv; break;
     case PM_UPDATE_SELF: kb = blk * (2 + nbv); kf = 2.0 * nl2 * nbv + self; break;
     case PM_APPLY_SELF: kb = blk; kf = 2.0 * self; break;
     case PM_APPLY_WRITE: kb = blk * (X32 ? 2.5 : 2.0); kf = self; break;
-    case PM_SELF: kb = blk; kf = self; break;
   }
   kt_begin(kc[pm], st);
   switch (ld) {
@@ -321,12 +314,12 @@ void launch_panel(int mode, int64_t n, int ld, int nbv, const double* X, double*
     case 64: panel_dispatch<4>(pm, nbv, a, grid, st); break;
     default: throw Error{GK_EUNSUPPORTED, "panel kernel needs ld in {16,32,48,64}"};
   }
-  kt_end(st, kb, kf, flag);
+  kt_end(st, kb, kf);
   int ngb = 0;
   if (pm == PM_GRAMV) ngb = nbv;
-  if (pm == PM_UPDATE_SELF || pm == PM_APPLY_SELF || pm == PM_SELF) ngb = 1;
+  if (pm == PM_UPDATE_SELF || pm == PM_APPLY_SELF) ngb = 1;
   if (ngb > 0) {
-    launch_reduce_parts((int64_t)ngb * ld * ld, grid, part, Cout, flag, st);
+    launch_reduce_parts((int64_t)ngb * ld * ld, grid, part, Cout, nullptr, st);
   }
 }
 

@@ -159,7 +159,7 @@ void PhaseTimer::collect(gk_stats* s) {
 namespace {
 const char* const kKernelClassName[KC_COUNT] = {
     "spmm_diff",          "panel_gramv",     "panel_update_self", "panel_apply_self", "panel_apply_write",
-    "panel_self",         "gram",            "tsgemm",            "arch_gram",        "arch_update",
+    "gram",               "tsgemm",          "arch_gram",         "arch_update",
     "reduce_parts",       "cholqr",          "omega",             "banded_factor",    "banded_solve",
     "cheb_step",          "jacobi_eig",      "assemble",          "predict"};
 struct KtRec {

@@ -661,13 +661,11 @@ namespace gk {
 //   pass 1: R1 = chol(G) with clamped pivots, R1inv, diag_out = diag(R1)
 //   pass 2: R2 with the combined-diagonal deflation rule, R2inv, and the
 //           products Rc = R1inv R2inv and B = R2 R1 (s x s, H_{k+1,k}).
-// flag (may be null): when *flag == 0 the kernel does nothing.
 __global__ void __launch_bounds__(ST)
 cholqr_blk_kernel(const double* __restrict__ G, int ld, int s, int pass, const double* __restrict__ diag_prev,
                   double thr, double* __restrict__ R, double* __restrict__ Rinv, double* __restrict__ diag_out,
                   int* __restrict__ n_defl, const double* __restrict__ R1, const double* __restrict__ R1inv,
-                  double* __restrict__ Rc, double* __restrict__ Bout, const int* __restrict__ flag) {
-  if (flag && *flag == 0) return;
+                  double* __restrict__ Rc, double* __restrict__ Bout) {
   __shared__ __align__(16) double A[WS][LP];
   __shared__ __align__(16) double Y[WS][LP];
   __shared__ __align__(16) double S1[WS][LP];
@@ -1015,7 +1013,9 @@ banded_solve_kernel(int m, int s, int kpow, const double* __restrict__ Linv_all,
 // symmetry of L gives
 //   B_k^T W_{k+1,j} = W_{k,j+1} B_j + W_{k,j} H_j - H_k W_{k,j}
 //                     + W_{k,j-1} B_{j-1}^T - B_{k-1} W_{k-1,j} + (rounding),
-// so W_{k+1,j} = B_k^{-T} (...) with B_k^{-1} = Rc from the QR.  The rounding
+// so W_{k+1,j} = B_k^{-T} (...).  B_k^{-1} is taken as Rc = R1^{-1} of the
+// first CholQR pass (B_k = R2 R1 with R2 = I + O(u)), so that the decision
+// comes before the block is normalised.  The rounding
 // term is modelled pessimistically by +-nu added in the direction of each
 // entry.  One workgroup per j <= k-2; W_{k+1,k-1} and W_{k+1,k} are kept at a
 // floor because the new block is orthogonalised against V_{k-1}, V_k.
@@ -1167,19 +1167,9 @@ void launch_cholqr_reg(const double* G, int ld, int s, int pass, const double* d
                        double* Bout, hipStream_t st) {
   kt_begin(KC_CHOLQR, st);
   hipLaunchKernelGGL(cholqr_blk_kernel, dim3(1), dim3(ST), 0, st, G, ld, s, pass, diag_prev, thr, R, Rinv, diag_out,
-                     n_defl, R1, R1inv, Rc, Bout, (const int*)nullptr);
+                     n_defl, R1, R1inv, Rc, Bout);
   GK_HIP(hipGetLastError());
   kt_end(st, 8.0 * 4 * ld * ld, (double)s * s * s);
-}
-
-void launch_cholqr_flag(const double* G, int ld, int s, int pass, const double* diag_prev, double thr, double* R,
-                        double* Rinv, double* diag_out, int* n_defl, const double* R1, const double* R1inv, double* Rc,
-                        double* Bout, const int* flag, hipStream_t st) {
-  kt_begin(KC_CHOLQR, st);
-  hipLaunchKernelGGL(cholqr_blk_kernel, dim3(1), dim3(ST), 0, st, G, ld, s, pass, diag_prev, thr, R, Rinv, diag_out,
-                     n_defl, R1, R1inv, Rc, Bout, flag);
-  GK_HIP(hipGetLastError());
-  kt_end(st, 8.0 * 4 * ld * ld, (double)s * s * s, flag);
 }
 
 void launch_omega(int k, int s, int ld, const double* Wk, const double* Wkm1, double* Wk1, const double* Hd,

@@ -192,8 +192,7 @@ cholqr_wide_kernel(const double* __restrict__ G, int ld, int s, int pass, const 
                    double thr, double* __restrict__ Aw, double* __restrict__ Yw, double* __restrict__ R,
                    double* __restrict__ Rinv, double* __restrict__ diag_out, int* __restrict__ n_defl,
                    const double* __restrict__ R1, const double* __restrict__ R1inv, double* __restrict__ Rc,
-                   double* __restrict__ Bout, const int* __restrict__ flag) {
-  if (flag && *flag == 0) return;
+                   double* __restrict__ Bout) {
   __shared__ __align__(16) double T0[WS][LP];
   __shared__ __align__(16) double T1[WS][LP];
   __shared__ __align__(16) double T2[WS][LP];
@@ -251,12 +250,12 @@ size_t cholqr_wide_scratch_elems(int ld) { return (size_t)2 * ld * ld; }
 
 void launch_cholqr_wide(const double* G, int ld, int s, int pass, const double* diag_prev, double thr, double* wk,
                         double* R, double* Rinv, double* diag_out, int* n_defl, const double* R1, const double* R1inv,
-                        double* Rc, double* Bout, const int* flag, hipStream_t st) {
+                        double* Rc, double* Bout, hipStream_t st) {
   kt_begin(KC_CHOLQR, st);
   hipLaunchKernelGGL(cholqr_wide_kernel, dim3(1), dim3(ST), 0, st, G, ld, s, pass, diag_prev, thr, wk,
-                     wk + (size_t)ld * ld, R, Rinv, diag_out, n_defl, R1, R1inv, Rc, Bout, flag);
+                     wk + (size_t)ld * ld, R, Rinv, diag_out, n_defl, R1, R1inv, Rc, Bout);
   GK_HIP(hipGetLastError());
-  kt_end(st, 8.0 * 6 * ld * ld, (double)s * s * s * (pass == 2 ? 3.0 : 1.0), flag);
+  kt_end(st, 8.0 * 6 * ld * ld, (double)s * s * s * (pass == 2 ? 3.0 : 1.0));
 }
 
 // ------------------------------------------------- orthogonality estimate
