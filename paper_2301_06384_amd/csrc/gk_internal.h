@@ -214,7 +214,7 @@ void launch_arch_assemble(int64_t n, int ld, int s, BlockList A, const double* U
 size_t panel_scratch_elems(int64_t n, int ld);
 void launch_panel(int mode, int64_t n, int ld, int nbv, const double* X, double* Xout, float* X32,
                   const double* V0, const double* V1, const double* Cupd, const double* Rm, double* part,
-                  double* Cout, hipStream_t st);
+                  double* Cout, hipStream_t st, double* H = nullptr, int hs = 0);
 
 // krylov.hip -- one call of the compute entry points
 struct CallArgs {

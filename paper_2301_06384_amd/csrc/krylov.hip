@@ -427,8 +427,9 @@ static void run_cbl(Job& J) {
     for (int pass = 0; pass < local_passes; ++pass) {
       if (pan) {
         launch_panel(PM_GRAMV, n, ld, nbv, X, nullptr, nullptr, V0, V1, nullptr, nullptr, ppart, C, st);
-        if (pass == 0) launch_store_H(C + (int64_t)(nbv - 1) * l2, ld, s, Hd + (int64_t)k * s * s, st);
-        launch_panel(PM_UPDATE_SELF, n, ld, nbv, X, X, nullptr, V0, V1, C, nullptr, ppart, G, st);
+        // the update pass also stores H_kk = sym(C_k) on the first pass
+        launch_panel(PM_UPDATE_SELF, n, ld, nbv, X, X, nullptr, V0, V1, C, nullptr, ppart, G, st,
+                     pass == 0 ? Hd + (int64_t)k * s * s : nullptr, s);
       } else {
         launch_gram(n, ld, loc, X, C, part, nullptr, st);
         if (pass == 0) launch_store_H(C + (int64_t)(loc.nb - 1) * l2, ld, s, Hd + (int64_t)k * s * s, st);

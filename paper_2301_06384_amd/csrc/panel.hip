@@ -37,6 +37,8 @@ struct PanelArgs {
   const double* C;       // (nbv*ld) x ld update coefficients (UPDATE)
   const double* Rm;      // ld x ld upper triangular right factor (APPLY)
   double* part;          // [gridDim.x][ngb*ld][ld] Gram partials
+  double* H;             // UPDATE: when non-null, H = sym of the last coefficient block (hs x hs)
+  int hs;
 };
 
 // NT: ld / 16.  NBV: local blocks staged.  UPDATE: X_new = X - [V] C.
@@ -64,6 +66,15 @@ __global__ void __launch_bounds__(PT_THREADS, 2) panel_kernel(PanelArgs p) {
   const int l = tid & 63;
   const int li = l & 15;
   const int lk = l >> 4;
+  if (UPDATE && p.H && blockIdx.x == 0) {
+    // H_kk of the three-term recurrence: the coefficient block of the newest
+    // basis block, symmetrised
+    const double* Cl = p.C + (int64_t)(NBV - 1) * LD * LD;
+    for (int q = tid; q < p.hs * p.hs; q += PT_THREADS) {
+      const int i = q / p.hs, c = q - i * p.hs;
+      p.H[q] = 0.5 * (Cl[i * LD + c] + Cl[c * LD + i]);
+    }
+  }
 
   // Update / apply product: wavefront w owns one 16-column tile (unt) of X_new
   // over UP slabs of 16 rows; its right operands stay in registers for the
@@ -292,8 +303,8 @@ static void panel_dispatch(PanelMode mode, int nbv, const PanelArgs& a, int grid
 // Launch one panel pass and (when it produces a Gram) reduce it into C.
 void launch_panel(int mode, int64_t n, int ld, int nbv, const double* X, double* Xout, float* X32,
                   const double* V0, const double* V1, const double* Cupd, const double* Rm, double* part,
-                  double* Cout, hipStream_t st) {
-  PanelArgs a{n, X, Xout, X32, V0, V1, Cupd, Rm, part};
+                  double* Cout, hipStream_t st, double* H, int hs) {
+  PanelArgs a{n, X, Xout, X32, V0, V1, Cupd, Rm, part, H, hs};
   const int grid = panel_grid(n);
   const PanelMode pm = (PanelMode)mode;
   // algorithmic bytes / flops of the pass (block = n x ld float64)

@@ -1017,100 +1017,98 @@ banded_solve_kernel(int m, int s, int kpow, const double* __restrict__ Linv_all,
 // first CholQR pass (B_k = R2 R1 with R2 = I + O(u)), so that the decision
 // comes before the block is normalised.  The rounding
 // term is modelled pessimistically by +-nu added in the direction of each
-// entry.  One workgroup per j <= k-2; W_{k+1,k-1} and W_{k+1,k} are kept at a
-// floor because the new block is orthogonalised against V_{k-1}, V_k.
+// entry.  Every product is column-separable, so the output is split into
+// 16-column slices: one workgroup per (j <= k-2, slice), each forming its
+// slice of the right-hand side and of W_{k+1,j} from full 64 x 64 left
+// operands and 64 x 16 right operands.  W_{k+1,k-1} and W_{k+1,k} are kept at
+// a floor because the new block is orthogonalised against V_{k-1}, V_k.
+__device__ __forceinline__ void fetch_slice(const double* __restrict__ src, int s, int c0, bool tr,
+                                            double (&v)[4]) {
+  const int c = c0 + (threadIdx.x & 15);
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int r = (threadIdx.x + ST * e) >> 4;
+    const bool in = src && r < s && c < s;
+    v[e] = in ? src[tr ? c * s + r : r * s + c] : 0.0;
+  }
+}
+__device__ __forceinline__ void put_slice(double (*D)[SLP], const double (&v)[4]) {
+#pragma unroll
+  for (int e = 0; e < 4; ++e) D[(threadIdx.x + ST * e) >> 4][threadIdx.x & 15] = v[e];
+}
+
 __global__ void __launch_bounds__(ST)
 omega_kernel(int k, int s, int ld, const double* __restrict__ Wk, const double* __restrict__ Wkm1,
              double* __restrict__ Wk1, const double* __restrict__ Hd, const double* __restrict__ Bd,
              const double* __restrict__ Rc, double nu, double* __restrict__ est_part) {
-  __shared__ __align__(16) double S1[WS][LP];
-  __shared__ __align__(16) double S2[WS][LP];
-  __shared__ __align__(16) double S3[WS][LP];
-  __shared__ __align__(16) double S4[WS][LP];
-  __shared__ double red[ST];
-  const int j = blockIdx.x;
+  __shared__ __align__(16) double SL[3][WS][LP];   // left operands
+  __shared__ double SR[3][WS][SLP];                // right operand slices
+  __shared__ double red[ST / 64];
+  const int j = blockIdx.x, q = blockIdx.y, c0 = 16 * q;
   const int tid = threadIdx.x;
-  const int tx = tid & 15, ty = tid >> 4;
-  const int ss = s * s;
-  double tot[4][4], acc[4][4];
-  auto addto = [&](double sign) {
+  const int64_t ss = (int64_t)s * s;
+  double tot[4], acc[4];
+  // Left operands are staged so that lds_mm_slice (A^T B) forms M B:
+  // transposed for W and B_{k-1}, as they are for the symmetric H_k.
+  double l0[16], l1[16], l2[16], r0[4], r1[4], r2[4];
+  // W_{k,j+1} B_j + W_{k,j} H_j - H_k W_{k,j}
+  fetch64(Wk + (j + 1) * ss, s, s, l0);
+  fetch64(Wk + j * ss, s, s, l1);
+  fetch64(Hd + (int64_t)k * ss, s, s, l2);
+  fetch_slice(Bd + j * ss, s, c0, false, r0);
+  fetch_slice(Hd + j * ss, s, c0, false, r1);
+  fetch_slice(Wk + j * ss, s, c0, false, r2);
+  put64T(SL[0], l0); put64T(SL[1], l1); put64(SL[2], l2);
+  put_slice(SR[0], r0); put_slice(SR[1], r1); put_slice(SR[2], r2);
+  __syncthreads();
+  // W_{k,j-1} B_{j-1}^T - B_{k-1} W_{k-1,j}: loads in flight during the products
+  fetch64(j >= 1 ? Wk + (j - 1) * ss : nullptr, s, s, l0);
+  fetch64(Bd + (int64_t)(k - 1) * ss, s, s, l1);
+  fetch_slice(j >= 1 ? Bd + (j - 1) * ss : nullptr, s, c0, true, r0);
+  fetch_slice(Wkm1 + j * ss, s, c0, false, r1);
+  lds_mm_slice(SL[0], SR[0], s, tot);
+  lds_mm_slice(SL[1], SR[1], s, acc);
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < 4; ++a) tot[a] += acc[a];
+  lds_mm_slice(SL[2], SR[2], s, acc);
 #pragma unroll
-      for (int b = 0; b < 4; ++b) tot[a][b] += sign * acc[a][b];
-  };
-  // Every product runs as X^T B (contiguous operand reads); left operands
-  // are staged transposed, and the H blocks are symmetric.
-  {
-    // W_{k,j+1} B_j + W_{k,j} H_j
-    double v1[16], v2[16], v3[16], v4[16];
-    fetch64(Wk + (int64_t)(j + 1) * ss, s, s, v1);
-    fetch64(Bd + (int64_t)j * ss, s, s, v2);
-    fetch64(Wk + (int64_t)j * ss, s, s, v3);
-    fetch64(Hd + (int64_t)j * ss, s, s, v4);
-    put64T(S1, v1); put64(S2, v2); put64T(S3, v3); put64(S4, v4);
-  }
+  for (int a = 0; a < 4; ++a) tot[a] -= acc[a];
   __syncthreads();
-  lds_mm<true, false>(S1, S2, s, tot);
-  lds_mm<true, false>(S3, S4, s, acc);
-  addto(1.0);
+  put64T(SL[0], l0); put64T(SL[1], l1);
+  put_slice(SR[0], r0); put_slice(SR[1], r1);
   __syncthreads();
-  {
-    // - H_k W_{k,j} + W_{k,j-1} B_{j-1}^T
-    double v1[16], v2[16], v3[16], v4[16];
-    fetch64(Hd + (int64_t)k * ss, s, s, v1);
-    fetch64(Wk + (int64_t)j * ss, s, s, v3);
-    fetch64(j >= 1 ? Wk + (int64_t)(j - 1) * ss : nullptr, s, s, v2);
-    fetch64(j >= 1 ? Bd + (int64_t)(j - 1) * ss : nullptr, s, s, v4);
-    put64(S1, v1); put64(S3, v3); put64T(S2, v2); put64T(S4, v4);
-  }
-  __syncthreads();
-  lds_mm<true, false>(S1, S3, s, acc);   // H_k symmetric: H_k^T W_{k,j}
-  addto(-1.0);
+  fetch64(Rc, s, ld, l2);
   if (j >= 1) {
-    lds_mm<true, false>(S2, S4, s, acc);   // (W_{k,j-1}^T)^T (B_{j-1}^T)
-    addto(1.0);
-  }
-  __syncthreads();
-  {
-    // - B_{k-1} W_{k-1,j}, then W_{k+1,j} = Rc^T (RHS + rounding model)
-    double v1[16], v2[16], v4[16];
-    fetch64(Bd + (int64_t)(k - 1) * ss, s, s, v1);
-    fetch64(Wkm1 + (int64_t)j * ss, s, s, v2);
-    fetch64(Rc, s, ld, v4);
-    put64T(S1, v1); put64(S2, v2); put64(S4, v4);
-  }
-  __syncthreads();
-  lds_mm<true, false>(S1, S2, s, acc);
-  addto(-1.0);
+    lds_mm_slice(SL[0], SR[0], s, acc);
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+    for (int a = 0; a < 4; ++a) tot[a] += acc[a];
+  }
+  lds_mm_slice(SL[1], SR[1], s, acc);
+  // W_{k+1,j} = Rc^T (RHS + rounding model)
+  const int w = tid >> 6, li = tid & 15, lk = (tid & 63) >> 4;
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const int r = acc_row(a), c = acc_col(b);
-      S3[r][c] = (r < s && c < s) ? tot[a][b] + copysign(nu, tot[a][b]) : 0.0;
-    }
+  for (int a = 0; a < 4; ++a) {
+    const int r = 16 * w + 4 * a + lk, c = c0 + li;
+    const double t = tot[a] - acc[a];
+    SR[2][r][li] = (r < s && c < s) ? t + copysign(nu, t) : 0.0;
+  }
+  put64(SL[2], l2);
   __syncthreads();
-  lds_mm<true, false>(S4, S3, s, acc);
+  lds_mm_slice(SL[2], SR[2], s, acc);
   double mx = 0.0;
-  double* out = Wk1 + (int64_t)j * ss;
+  double* out = Wk1 + j * ss;
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const int r = acc_row(a), c = acc_col(b);
-      if (r < s && c < s) {
-        out[r * s + c] = acc[a][b];
-        mx = fmax(mx, fabs(acc[a][b]));
-      }
+  for (int a = 0; a < 4; ++a) {
+    const int r = 16 * w + 4 * a + lk, c = c0 + li;
+    if (r < s && c < s) {
+      out[r * s + c] = acc[a];
+      mx = fmax(mx, fabs(acc[a]));
     }
-  red[tid] = mx;
-  __syncthreads();
-  for (int w = ST / 2; w > 0; w >>= 1) {
-    if (tid < w) red[tid] = fmax(red[tid], red[tid + w]);
-    __syncthreads();
   }
-  if (tid == 0) est_part[j] = red[0];
+  for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o));
+  if ((tid & 63) == 0) red[w] = mx;
+  __syncthreads();
+  if (tid == 0) est_part[j * gridDim.y + q] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
 }
 
 // Decision after the estimate of step k: reorthogonalise when the estimate
@@ -1159,7 +1157,7 @@ bool small_wave_ok(int ld) { return ld <= WS; }
 
 int omega_est_per_block(int s) {
   const int nq = (s + WS - 1) / WS;
-  return s > WS ? nq * nq : 1;
+  return s > WS ? nq * nq : (s + 15) / 16;
 }
 
 void launch_cholqr_reg(const double* G, int ld, int s, int pass, const double* diag_prev, double thr, double* R,
@@ -1183,8 +1181,8 @@ void launch_omega(int k, int s, int ld, const double* Wk, const double* Wkm1, do
       launch_omega_wide(k, s, ld, Wk, Wkm1, Wk1, Hd, Bd, Rc, nu, rhs_wide, est_part, st);
     } else {
       kt_begin(KC_OMEGA, st);
-      hipLaunchKernelGGL(omega_kernel, dim3(nj), dim3(ST), 0, st, k, s, ld, Wk, Wkm1, Wk1, Hd, Bd, Rc, nu,
-                         est_part);
+      hipLaunchKernelGGL(omega_kernel, dim3(nj, (s + 15) / 16), dim3(ST), 0, st, k, s, ld, Wk, Wkm1, Wk1, Hd, Bd,
+                         Rc, nu, est_part);
       GK_HIP(hipGetLastError());
       kt_end(st, 8.0 * 10 * nj * (double)s * s, 12.0 * nj * (double)s * s * s);
     }
