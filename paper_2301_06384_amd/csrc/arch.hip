@@ -37,8 +37,8 @@ __device__ __forceinline__ f4 mfma32(float a, float b, f4 c) {
 // level of a 32-term float sum.
 constexpr int AG_WAVES = 16;
 constexpr int AG_THREADS = 64 * AG_WAVES;
-constexpr int AG_SUB = 64;        // rows staged per LDS round
-constexpr int AG_FLUSH = 8;       // 4-row steps between float64 flushes
+constexpr int AG_SUB = 128;       // rows staged per LDS round
+constexpr int AG_FLUSH = 4;       // 4-row steps between float64 flushes
 constexpr int AG_TARGET_WG = 256; // one workgroup per compute unit
 
 constexpr int ag_blocks(int nt) { return AG_WAVES / nt; }
@@ -85,20 +85,48 @@ arch_gram_kernel(int64_t n, const float* __restrict__ Q, int64_t qstride, int nb
   }
 
   // Loads never sit behind a branch: rows past the range read the last valid
-  // row and are zeroed by a select, so a wavefront keeps all the loads of a
-  // flush group in flight before its MFMAs wait on them.
-  for (int64_t r0 = rb; r0 < re; r0 += AG_SUB) {
-    static_assert(AG_SUB * LD == NT * AG_THREADS, "one element per thread and column tile");
-    double xv[NT];
+  // row and are zeroed by a select.  The archive rows of a flush group are
+  // loaded one group ahead (across rounds too), into alternating register
+  // sets, so a wavefront's products never wait on the loads just issued.
+  constexpr int NG = AG_SUB / (4 * AG_FLUSH);   // flush groups per round
+  auto load_group = [&](int64_t rg, float (&a)[AG_FLUSH][NT]) {
+#pragma unroll
+    for (int s8 = 0; s8 < AG_FLUSH; ++s8) {
+      const int64_t r = rg + 4 * s8 + lk;
+      load_row_seg<NT>(Qj + (r < re ? r : re - 1) * LD + NT * li, a[s8]);
+    }
+  };
+  auto run_group = [&](int64_t r0, int h, const float (&a)[AG_FLUSH][NT]) {
+#pragma unroll
+    for (int s8 = 0; s8 < AG_FLUSH; ++s8) {
+      const int s4 = h * AG_FLUSH + s8;
+      const bool in = r0 + 4 * s4 + lk < re;
+      const float b = sX[(4 * s4 + lk) * P + 16 * t + li];
+#pragma unroll
+      for (int e = 0; e < NT; ++e) acc[e] = mfma32(in ? a[s8][e] : 0.f, b, acc[e]);
+    }
 #pragma unroll
     for (int e = 0; e < NT; ++e) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) a64[e][q] += (double)acc[e][q];
+      acc[e] = f4{0.f, 0.f, 0.f, 0.f};
+    }
+  };
+  float ga[AG_FLUSH][NT], gb[AG_FLUSH][NT];
+  load_group(rb, ga);
+  for (int64_t r0 = rb; r0 < re; r0 += AG_SUB) {
+    static_assert(AG_SUB * LD == 2 * NT * AG_THREADS, "two elements per thread and column tile");
+    static_assert(NG % 2 == 0, "flush groups alternate between two register sets");
+    double xv[2 * NT];
+#pragma unroll
+    for (int e = 0; e < 2 * NT; ++e) {
       const int q = tid + e * AG_THREADS;
       const int rr = q / LD, cc = q - rr * LD;
       const int64_t r = r0 + rr;
       xv[e] = X[(r < re ? r : re - 1) * LD + cc];
     }
 #pragma unroll
-    for (int e = 0; e < NT; ++e) {
+    for (int e = 0; e < 2 * NT; ++e) {
       const int q = tid + e * AG_THREADS;
       const int rr = q / LD, cc = q - rr * LD;
       sX[rr * P + cc] = r0 + rr < re ? (float)xv[e] : 0.f;
@@ -106,28 +134,12 @@ arch_gram_kernel(int64_t n, const float* __restrict__ Q, int64_t qstride, int nb
     __syncthreads();
     if (active) {
 #pragma unroll
-      for (int h = 0; h < AG_SUB / (4 * AG_FLUSH); ++h) {
-        float a[AG_FLUSH][NT];
-#pragma unroll
-        for (int s8 = 0; s8 < AG_FLUSH; ++s8) {
-          const int64_t r = r0 + 4 * (h * AG_FLUSH + s8) + lk;
-          load_row_seg<NT>(Qj + (r < re ? r : re - 1) * LD + NT * li, a[s8]);
-        }
-        __builtin_amdgcn_sched_barrier(0);   // keep the group's loads ahead of its MFMAs
-#pragma unroll
-        for (int s8 = 0; s8 < AG_FLUSH; ++s8) {
-          const int s4 = h * AG_FLUSH + s8;
-          const bool in = r0 + 4 * s4 + lk < re;
-          const float b = sX[(4 * s4 + lk) * P + 16 * t + li];
-#pragma unroll
-          for (int e = 0; e < NT; ++e) acc[e] = mfma32(in ? a[s8][e] : 0.f, b, acc[e]);
-        }
-#pragma unroll
-        for (int e = 0; e < NT; ++e) {
-#pragma unroll
-          for (int q = 0; q < 4; ++q) a64[e][q] += (double)acc[e][q];
-          acc[e] = f4{0.f, 0.f, 0.f, 0.f};
-        }
+      for (int h = 0; h < NG; h += 2) {
+        // the group after h + 1 is the first of the next round at the end
+        load_group(r0 + 4 * (h + 1) * AG_FLUSH, gb);
+        run_group(r0, h, ga);
+        load_group(r0 + 4 * (h + 2) * AG_FLUSH, ga);
+        run_group(r0, h + 1, gb);
       }
     }
     __syncthreads();
@@ -203,40 +215,41 @@ arch_update_kernel(int64_t n, const float* __restrict__ Q, int64_t qstride, int 
     }
   };
 
-  float qcur[2][KQ];
+  // One archive block per step.  The loads of the next block (at the end the
+  // last block again, unused) are issued unconditionally before the
+  // products, so the wait in front of the first product covers only the
+  // current block's operands; the two register sets alternate.
+  auto step = [&](int jb, const float (&qc)[2][KQ], float (&qn)[2][KQ]) {
+    const int jn = jb + 1 < nb ? jb + 1 : nb - 1;
+    double cnext[CE];
+    fetch_c(jn, cnext);
+    load_q(jn, qn);
+    if (jb < nb) {
+      const float* sc = sC[jb & 1];
+#pragma unroll
+      for (int e = 0; e < KQ; ++e) {
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          const float cv = sc[(lk * KQ + e) * PC + 16 * t + li];
+#pragma unroll
+          for (int g = 0; g < 2; ++g) acc[g][t] = mfma32(cv, qc[g][e], acc[g][t]);
+        }
+      }
+    }
+    if (jb + 1 < nb) put_c((jb & 1) ^ 1, cnext);
+    __syncthreads();
+  };
+  float q0[2][KQ], q1[2][KQ];
   {
     double c0[CE];
     fetch_c(0, c0);
     put_c(0, c0);
   }
-  load_q(0, qcur);
+  load_q(0, q0);
   __syncthreads();
-  for (int jb = 0; jb < nb; ++jb) {
-    const int buf = jb & 1;
-    double cnext[CE];
-    float qnext[2][KQ];
-    if (jb + 1 < nb) {
-      fetch_c(jb + 1, cnext);
-      load_q(jb + 1, qnext);
-    }
-    const float* sc = sC[buf];
-#pragma unroll
-    for (int e = 0; e < KQ; ++e) {
-#pragma unroll
-      for (int t = 0; t < NT; ++t) {
-        const float cv = sc[(lk * KQ + e) * PC + 16 * t + li];
-#pragma unroll
-        for (int g = 0; g < 2; ++g) acc[g][t] = mfma32(cv, qcur[g][e], acc[g][t]);
-      }
-    }
-    if (jb + 1 < nb) put_c(buf ^ 1, cnext);
-    __syncthreads();
-    if (jb + 1 < nb) {
-#pragma unroll
-      for (int g = 0; g < 2; ++g)
-#pragma unroll
-        for (int e = 0; e < KQ; ++e) qcur[g][e] = qnext[g][e];
-    }
+  for (int jb = 0; jb < nb; jb += 2) {
+    step(jb, q0, q1);
+    step(jb + 1, q1, q0);
   }
   // D_{g,t}[4k + r][i] = (Q C)[row 16 g + i][16 t + 4 k + r]
 #pragma unroll
@@ -323,22 +336,27 @@ arch_assemble_kernel(int64_t n, const float* __restrict__ Q, int64_t qstride, in
     }
   };
 
+  // The next block's archive rows are loaded before the products
+  // (unconditionally, the last block again at the end), so the wait in front
+  // of the first product covers only the current block.  The next coefficient
+  // block is staged after the products: the float64 accumulators leave no
+  // registers to hold it across them.
   float qcur[2][KQ];
   stage(0, 0);
   load_q(0, qcur);
   __syncthreads();
   for (int jb = 0; jb < nb; ++jb) {
-    const int buf = jb & 1;
     float qnext[2][KQ];
-    if (jb + 1 < nb) load_q(jb + 1, qnext);
-    const float* sc = sC[buf];
+    load_q(jb + 1 < nb ? jb + 1 : nb - 1, qnext);
+    __builtin_amdgcn_sched_barrier(0);   // keep the loads ahead of the products
+    const float* sc = sC[jb & 1];
 #pragma unroll
     for (int e = 0; e < KQ; ++e) {
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
-        const float cv = sc[(lk * KQ + e) * PC + 16 * t + li];
+        const float c = sc[(lk * KQ + e) * PC + 16 * t + li];
 #pragma unroll
-        for (int g = 0; g < 2; ++g) acc[g][t] = mfma32(cv, qcur[g][e], acc[g][t]);
+        for (int g = 0; g < 2; ++g) acc[g][t] = mfma32(c, qcur[g][e], acc[g][t]);
       }
     }
 #pragma unroll
@@ -349,16 +367,12 @@ arch_assemble_kernel(int64_t n, const float* __restrict__ Q, int64_t qstride, in
         for (int q = 0; q < 4; ++q) a64[g][t][q] += (double)acc[g][t][q];
         acc[g][t] = f4{0.f, 0.f, 0.f, 0.f};
       }
-    // the next coefficient block is staged after the MFMAs: the float64
-    // accumulators leave no registers for a longer prefetch
-    if (jb + 1 < nb) stage(jb + 1, buf ^ 1);
+    if (jb + 1 < nb) stage(jb + 1, (jb & 1) ^ 1);
     __syncthreads();
-    if (jb + 1 < nb) {
 #pragma unroll
-      for (int g = 0; g < 2; ++g)
+    for (int g = 0; g < 2; ++g)
 #pragma unroll
-        for (int e = 0; e < KQ; ++e) qcur[g][e] = qnext[g][e];
-    }
+      for (int e = 0; e < KQ; ++e) qcur[g][e] = qnext[g][e];
   }
   // D_{g,t}[4k + r][i] = P[row 16 g + i][16 t + 4 k + r]
 #pragma unroll
