@@ -26,36 +26,23 @@ __device__ __forceinline__ f4 mfma32(float a, float b, f4 c) {
 }
 
 // ------------------------------------------------------------- Gram C = Q^T X
-// Workgroup = 16 wavefronts; wavefront w owns column tile t = w % NT of
-// archive block j = (16 / NT) bx + w / NT and accumulates C_j[:, 16t .. 16t+15]
-// over the row range of blockIdx.y.  X rows are staged in LDS as float
-// (shared by all wavefronts); Q rows stream from memory straight into MFMA
-// operands: lane (i, k) of a 4-row step loads the NT consecutive floats
-// Q_j[r + k][NT i .. NT i + NT - 1], so operand e (< NT) covers the archive
-// columns {NT i + e}.  The float MFMA accumulators are added into float64
+// Workgroup = 16 wavefronts over BPW = 16 / NT archive blocks and the row
+// range of blockIdx.y; wavefront w owns column tile t = w % NT of block
+// j = BPW bx + w / NT and accumulates C_j[:, 16t .. 16t+15] (NT row tiles).
+// Rows go through LDS in rounds of AG_ROWS: every archive and X element is
+// loaded once per workgroup (the NT wavefronts of a block share its rows),
+// and the next round's loads are issued into registers before the current
+// round's products, so a full round of products covers their latency.  X is
+// staged as float.  The float MFMA accumulators are added into float64
 // registers every 32 rows, which keeps the accumulation error of C at the
 // level of a 32-term float sum.
 constexpr int AG_WAVES = 16;
 constexpr int AG_THREADS = 64 * AG_WAVES;
-constexpr int AG_SUB = 128;       // rows staged per LDS round
-constexpr int AG_FLUSH = 4;       // 4-row steps between float64 flushes
+constexpr int AG_ROWS = 64;       // rows staged per LDS round
+constexpr int AG_FLUSH = 8;       // 4-row steps between float64 flushes
 constexpr int AG_TARGET_WG = 256; // one workgroup per compute unit
 
 constexpr int ag_blocks(int nt) { return AG_WAVES / nt; }
-
-template <int NT>
-__device__ __forceinline__ void load_row_seg(const float* __restrict__ p, float (&a)[NT]) {
-  if constexpr (NT == 4) {
-    const f4 v = *reinterpret_cast<const f4*>(p);
-    a[0] = v[0]; a[1] = v[1]; a[2] = v[2]; a[3] = v[3];
-  } else if constexpr (NT == 2) {
-    const float2 v = *reinterpret_cast<const float2*>(p);
-    a[0] = v.x; a[1] = v.y;
-  } else {
-#pragma unroll
-    for (int e = 0; e < NT; ++e) a[e] = p[e];
-  }
-}
 
 template <int NT>
 __global__ void __launch_bounds__(AG_THREADS, 1)
@@ -63,15 +50,19 @@ arch_gram_kernel(int64_t n, const float* __restrict__ Q, int64_t qstride, int nb
                  double* __restrict__ part, int64_t rpc, const int* __restrict__ flag) {
   if (flag && *flag == 0) return;
   constexpr int LD = 16 * NT;
-  constexpr int P = LD + 16;                 // LDS pitch (floats)
+  constexpr int P = LD + 16;                 // LDS pitch (floats): the 4-row operand reads avoid bank conflicts
   constexpr int BPW = ag_blocks(NT);
-  __shared__ float sX[AG_SUB * P];
+  constexpr int Q4 = BPW * AG_ROWS * LD / 4; // float4 of archive rows per round
+  constexpr int QV = (Q4 + AG_THREADS - 1) / AG_THREADS;
+  constexpr int XE = AG_ROWS * LD / AG_THREADS;
+  static_assert(XE * AG_THREADS == AG_ROWS * LD, "whole X rows per round");
+  __shared__ __align__(16) float sQ[BPW * AG_ROWS * P];
+  __shared__ float sX[AG_ROWS * P];
   const int tid = threadIdx.x;
   const int w = tid >> 6, l = tid & 63, li = l & 15, lk = l >> 4;
   const int wb = w / NT, t = w - wb * NT;
-  const int j = blockIdx.x * BPW + wb;
-  const bool active = wb < BPW && j < nb;
-  const float* Qj = Q + (int64_t)(active ? j : 0) * qstride;
+  const int j0 = blockIdx.x * BPW;
+  const bool active = wb < BPW && j0 + wb < nb;
   const int64_t rb = (int64_t)blockIdx.y * rpc;
   const int64_t re = min(n, rb + rpc);
 
@@ -84,73 +75,79 @@ arch_gram_kernel(int64_t n, const float* __restrict__ Q, int64_t qstride, int nb
     for (int r = 0; r < 4; ++r) a64[e][r] = 0.0;
   }
 
-  // Loads never sit behind a branch: rows past the range read the last valid
-  // row and are zeroed by a select.  The archive rows of a flush group are
-  // loaded one group ahead (across rounds too), into alternating register
-  // sets, so a wavefront's products never wait on the loads just issued.
-  constexpr int NG = AG_SUB / (4 * AG_FLUSH);   // flush groups per round
-  auto load_group = [&](int64_t rg, float (&a)[AG_FLUSH][NT]) {
+  // Loads never sit behind a branch: rows past the range read row re - 1,
+  // blocks past nb read block nb - 1 and entries past the round repeat the
+  // last one; X rows past the range are zeroed in LDS, which cancels them.
+  f4 qv[QV];
+  double xv[XE];
+  auto load_round = [&](int64_t r0) {
 #pragma unroll
-    for (int s8 = 0; s8 < AG_FLUSH; ++s8) {
-      const int64_t r = rg + 4 * s8 + lk;
-      load_row_seg<NT>(Qj + (r < re ? r : re - 1) * LD + NT * li, a[s8]);
-    }
-  };
-  auto run_group = [&](int64_t r0, int h, const float (&a)[AG_FLUSH][NT]) {
-#pragma unroll
-    for (int s8 = 0; s8 < AG_FLUSH; ++s8) {
-      const int s4 = h * AG_FLUSH + s8;
-      const bool in = r0 + 4 * s4 + lk < re;
-      const float b = sX[(4 * s4 + lk) * P + 16 * t + li];
-#pragma unroll
-      for (int e = 0; e < NT; ++e) acc[e] = mfma32(in ? a[s8][e] : 0.f, b, acc[e]);
+    for (int e = 0; e < QV; ++e) {
+      const int q = min(tid + e * AG_THREADS, Q4 - 1) * 4;
+      const int b = q / (AG_ROWS * LD), rem = q - b * (AG_ROWS * LD);
+      const int rr = rem / LD, cc = rem - rr * LD;
+      const int64_t r = min(r0 + rr, re - 1);
+      const int jb = min(j0 + b, nb - 1);
+      qv[e] = *reinterpret_cast<const f4*>(Q + (int64_t)jb * qstride + r * LD + cc);
     }
 #pragma unroll
-    for (int e = 0; e < NT; ++e) {
-#pragma unroll
-      for (int q = 0; q < 4; ++q) a64[e][q] += (double)acc[e][q];
-      acc[e] = f4{0.f, 0.f, 0.f, 0.f};
-    }
-  };
-  float ga[AG_FLUSH][NT], gb[AG_FLUSH][NT];
-  load_group(rb, ga);
-  for (int64_t r0 = rb; r0 < re; r0 += AG_SUB) {
-    static_assert(AG_SUB * LD == 2 * NT * AG_THREADS, "two elements per thread and column tile");
-    static_assert(NG % 2 == 0, "flush groups alternate between two register sets");
-    double xv[2 * NT];
-#pragma unroll
-    for (int e = 0; e < 2 * NT; ++e) {
+    for (int e = 0; e < XE; ++e) {
       const int q = tid + e * AG_THREADS;
       const int rr = q / LD, cc = q - rr * LD;
-      const int64_t r = r0 + rr;
-      xv[e] = X[(r < re ? r : re - 1) * LD + cc];
+      xv[e] = X[min(r0 + rr, re - 1) * LD + cc];
+    }
+  };
+  auto store_round = [&](int64_t r0) {
+#pragma unroll
+    for (int e = 0; e < QV; ++e) {
+      const int q4 = tid + e * AG_THREADS;
+      const int q = q4 * 4;
+      const int b = q / (AG_ROWS * LD), rem = q - b * (AG_ROWS * LD);
+      const int rr = rem / LD, cc = rem - rr * LD;
+      if (q4 < Q4) *reinterpret_cast<f4*>(&sQ[(b * AG_ROWS + rr) * P + cc]) = qv[e];
     }
 #pragma unroll
-    for (int e = 0; e < 2 * NT; ++e) {
+    for (int e = 0; e < XE; ++e) {
       const int q = tid + e * AG_THREADS;
       const int rr = q / LD, cc = q - rr * LD;
       sX[rr * P + cc] = r0 + rr < re ? (float)xv[e] : 0.f;
     }
+  };
+
+  load_round(rb);
+  const float* sQw = sQ + wb * AG_ROWS * P;
+  for (int64_t r0 = rb; r0 < re; r0 += AG_ROWS) {
+    store_round(r0);
     __syncthreads();
+    load_round(r0 + AG_ROWS);   // past the range at the end: clamped, unused
     if (active) {
 #pragma unroll
-      for (int h = 0; h < NG; h += 2) {
-        // the group after h + 1 is the first of the next round at the end
-        load_group(r0 + 4 * (h + 1) * AG_FLUSH, gb);
-        run_group(r0, h, ga);
-        load_group(r0 + 4 * (h + 2) * AG_FLUSH, ga);
-        run_group(r0, h + 1, gb);
+      for (int h = 0; h < AG_ROWS / (4 * AG_FLUSH); ++h) {
+#pragma unroll
+        for (int s8 = 0; s8 < AG_FLUSH; ++s8) {
+          const int rr = 4 * (h * AG_FLUSH + s8) + lk;
+          // B (4 x 16) = X[rows][16 t ..], A (16 x 4) = Q_j[rows][16 a ..]^T
+          const float b = sX[rr * P + 16 * t + li];
+#pragma unroll
+          for (int a = 0; a < NT; ++a) acc[a] = mfma32(sQw[rr * P + 16 * a + li], b, acc[a]);
+        }
+#pragma unroll
+        for (int a = 0; a < NT; ++a) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) a64[a][q] += (double)acc[a][q];
+          acc[a] = f4{0.f, 0.f, 0.f, 0.f};
+        }
       }
     }
     __syncthreads();
   }
   if (active) {
-    // D_e[4k + r][i] = C_j[NT (4k + r) + e][16 t + i]
-    double* P0 = part + ((int64_t)blockIdx.y * nb + j) * LD * LD;
+    // D_a[4k + r][i] = C_j[16 a + 4 k + r][16 t + i]
+    double* P0 = part + ((int64_t)blockIdx.y * nb + j0 + wb) * LD * LD;
 #pragma unroll
-    for (int e = 0; e < NT; ++e)
+    for (int a = 0; a < NT; ++a)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) P0[(NT * (4 * lk + r) + e) * LD + 16 * t + li] = a64[e][r];
+      for (int r = 0; r < 4; ++r) P0[(16 * a + 4 * lk + r) * LD + 16 * t + li] = a64[a][r];
   }
 }
 
@@ -397,11 +394,11 @@ static void arch_gram_geometry(int64_t n, int nb, int ld, int* ngroups, int* nch
   const int bpw = ag_blocks(ld / 16);
   *ngroups = (nb + bpw - 1) / bpw;
   int64_t want = AG_TARGET_WG / *ngroups;    // at most one round of workgroups
-  const int64_t maxc = (n + AG_SUB - 1) / AG_SUB;
+  const int64_t maxc = (n + AG_ROWS - 1) / AG_ROWS;
   if (want > maxc) want = maxc;
   if (want < 1) want = 1;
   int64_t r = (n + want - 1) / want;
-  r = ((r + AG_SUB - 1) / AG_SUB) * AG_SUB;
+  r = ((r + AG_ROWS - 1) / AG_ROWS) * AG_ROWS;
   *rpc = r;
   *nchunks = (int)((n + r - 1) / r);
 }
