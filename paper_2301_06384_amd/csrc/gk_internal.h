@@ -164,9 +164,10 @@ void launch_cholqr_wave(const double* G, int ld, int s, int pass, const double* 
                         double* Rc, double* Bout, hipStream_t st);
 void launch_banded_spline_wave(int m, int s, const double* Hd, const double* Bd, double eps, int k, double* work,
                                double* U, int* bad, hipStream_t st);
+// BT (pass 2, may be null): B^T zero padded to ld x ld
 void launch_cholqr_reg(const double* G, int ld, int s, int pass, const double* diag_prev, double thr, double* R,
                        double* Rinv, double* diag_out, int* n_defl, const double* R1, const double* R1inv, double* Rc,
-                       double* Bout, hipStream_t st);
+                       double* Bout, double* BT, hipStream_t st);
 void launch_banded_spline_reg(int m, int s, const double* Hd, const double* Bd, double eps, int k, double* work,
                               double* U, int* bad, hipStream_t st);
 // Block orthogonality estimate (partial reorthogonalisation) for s <= 512.

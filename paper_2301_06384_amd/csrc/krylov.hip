@@ -424,8 +424,18 @@ static void run_cbl(Job& J) {
     const double* V0 = k > 0 ? Vkm1 : Vk;
     const double* V1 = k > 0 ? Vk : nullptr;
     const int local_passes = mixed ? 1 : 2;
+    // GK_MIXED on the panel kernels takes the recurrence as written in Alg. 1:
+    // X = L Q_k - Q_{k-1} H_{k-1,k} with H_{k-1,k} = B_{k-1}^T from the previous
+    // QR (coefficient block 0 of C, stored by the second CholQR pass), and
+    // H_kk = Q_k^T L Q_k, so the Gram pass projects onto Q_k alone.  GK_FP64
+    // projects onto both local blocks twice (classical Gram-Schmidt, twice).
+    const bool rec = mixed && pan && k > 0;
     for (int pass = 0; pass < local_passes; ++pass) {
-      if (pan) {
+      if (rec) {
+        launch_panel(PM_GRAMV, n, ld, 1, X, nullptr, nullptr, Vk, nullptr, nullptr, nullptr, ppart, C + l2, st);
+        launch_panel(PM_UPDATE_SELF, n, ld, 2, X, X, nullptr, Vkm1, Vk, C, nullptr, ppart, G, st,
+                     Hd + (int64_t)k * s * s, s);
+      } else if (pan) {
         launch_panel(PM_GRAMV, n, ld, nbv, X, nullptr, nullptr, V0, V1, nullptr, nullptr, ppart, C, st);
         // the update pass also stores H_kk = sym(C_k) on the first pass
         launch_panel(PM_UPDATE_SELF, n, ld, nbv, X, X, nullptr, V0, V1, C, nullptr, ppart, G, st,
@@ -458,7 +468,8 @@ static void run_cbl(Job& J) {
     if (k + 1 < m) {
       // CholQR2: X = Q_{k+1} H_{k+1,k}
       if (wave)
-        launch_cholqr_reg(G, ld, s, 1, nullptr, J.thr(), R1, R1i, d1, nullptr, nullptr, nullptr, nullptr, nullptr, st);
+        launch_cholqr_reg(G, ld, s, 1, nullptr, J.thr(), R1, R1i, d1, nullptr, nullptr, nullptr, nullptr, nullptr,
+                          nullptr, st);
       else if (widek)
         launch_cholqr_wide(G, ld, s, 1, nullptr, J.thr(), W, R1, R1i, d1, nullptr, nullptr, nullptr, nullptr, nullptr,
                            st);
@@ -497,8 +508,9 @@ static void run_cbl(Job& J) {
         launch_gram(n, ld, yl, Y, G, part, nullptr, st);
       }
       if (wave) {
+        // the mixed panel path takes H_{k,k+1} = B_k^T of the next step from C
         launch_cholqr_reg(G, ld, s, 2, d1, J.thr(), nullptr, nullptr, d2, J.dflags + 1, R1, R1i, R12i,
-                          Bd + (int64_t)k * s * s, st);
+                          Bd + (int64_t)k * s * s, (mixed && pan) ? C : nullptr, st);
       } else if (widek) {
         launch_cholqr_wide(G, ld, s, 2, d1, J.thr(), W, nullptr, nullptr, d2, J.dflags + 1, R1, R1i, R12i,
                            Bd + (int64_t)k * s * s, st);

@@ -660,12 +660,13 @@ namespace gk {
 // CholQR factor of a Gram matrix (ld <= 64), 256 threads.
 //   pass 1: R1 = chol(G) with clamped pivots, R1inv, diag_out = diag(R1)
 //   pass 2: R2 with the combined-diagonal deflation rule, R2inv, and the
-//           products Rc = R1inv R2inv and B = R2 R1 (s x s, H_{k+1,k}).
+//           products Rc = R1inv R2inv and B = R2 R1 (s x s, H_{k+1,k}),
+//           and (BT non-null) B^T = H_{k,k+1} zero padded to ld x ld.
 __global__ void __launch_bounds__(ST)
 cholqr_blk_kernel(const double* __restrict__ G, int ld, int s, int pass, const double* __restrict__ diag_prev,
                   double thr, double* __restrict__ R, double* __restrict__ Rinv, double* __restrict__ diag_out,
                   int* __restrict__ n_defl, const double* __restrict__ R1, const double* __restrict__ R1inv,
-                  double* __restrict__ Rc, double* __restrict__ Bout) {
+                  double* __restrict__ Rc, double* __restrict__ Bout, double* __restrict__ BT) {
   __shared__ __align__(16) double A[WS][LP];
   __shared__ __align__(16) double Y[WS][LP];
   __shared__ __align__(16) double S1[WS][LP];
@@ -781,6 +782,7 @@ cholqr_blk_kernel(const double* __restrict__ G, int ld, int s, int pass, const d
         for (int j = 0; j < 4; ++j) {
           const int r = acc_row(i), c = acc_col(j);
           if (r < s && c < s) Bout[r * s + c] = acc[i][j];
+          if (BT && r < ld && c < ld) BT[c * ld + r] = (r < s && c < s) ? acc[i][j] : 0.0;
           if (r < ld && c < ld) Rc[r * ld + c] = (r < s && c < s) ? rc[i][j] : 0.0;
         }
       return;
@@ -793,6 +795,7 @@ cholqr_blk_kernel(const double* __restrict__ G, int ld, int s, int pass, const d
       for (int j = 0; j < 4; ++j) {
         const int r = acc_row(i), c = acc_col(j);
         if (r < s && c < s) Bout[r * s + c] = acc[i][j];
+        if (BT && r < ld && c < ld) BT[c * ld + r] = (r < s && c < s) ? acc[i][j] : 0.0;
       }
     __syncthreads();
     // S1 <- R2inv = Y^T; Rc = R1inv * R2inv = (R1inv^T)^T R2inv
@@ -1162,10 +1165,10 @@ int omega_est_per_block(int s) {
 
 void launch_cholqr_reg(const double* G, int ld, int s, int pass, const double* diag_prev, double thr, double* R,
                        double* Rinv, double* diag_out, int* n_defl, const double* R1, const double* R1inv, double* Rc,
-                       double* Bout, hipStream_t st) {
+                       double* Bout, double* BT, hipStream_t st) {
   kt_begin(KC_CHOLQR, st);
   hipLaunchKernelGGL(cholqr_blk_kernel, dim3(1), dim3(ST), 0, st, G, ld, s, pass, diag_prev, thr, R, Rinv, diag_out,
-                     n_defl, R1, R1inv, Rc, Bout);
+                     n_defl, R1, R1inv, Rc, Bout, BT);
   GK_HIP(hipGetLastError());
   kt_end(st, 8.0 * 4 * ld * ld, (double)s * s * s);
 }
