@@ -20,7 +20,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libgk.so")
 ARCH = "gfx950"
 
-SOURCES = ["spmm.hip", "ortho.hip", "small.hip", "wide.hip", "panel.hip", "arch.hip", "krylov.hip", "runtime.cpp", "graph.cpp", "serve.cpp"]
+SOURCES = ["spmm.hip", "ortho.hip", "small.hip", "wide.hip", "bcr.hip", "panel.hip", "arch.hip", "krylov.hip", "runtime.cpp", "graph.cpp", "serve.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 CFLAGS = [

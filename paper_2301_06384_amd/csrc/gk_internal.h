@@ -168,6 +168,9 @@ void launch_banded_spline_wave(int m, int s, const double* Hd, const double* Bd,
 void launch_cholqr_reg(const double* G, int ld, int s, int pass, const double* diag_prev, double thr, double* R,
                        double* Rinv, double* diag_out, int* n_defl, const double* R1, const double* R1inv, double* Rc,
                        double* Bout, double* BT, hipStream_t st);
+// bcr.hip -- (eps I + H_m)^{-k} F_1 by block cyclic reduction (s <= 64);
+// work holds bcr_work_elems(m, s) doubles
+size_t bcr_work_elems(int m, int s);
 void launch_banded_spline_reg(int m, int s, const double* Hd, const double* Bd, double eps, int k, double* work,
                               double* U, int* bad, hipStream_t st);
 // Block orthogonality estimate (partial reorthogonalisation) for s <= 512.

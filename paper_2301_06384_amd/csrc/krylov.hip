@@ -280,7 +280,7 @@ static void phi_stage_block(Job& J, const double* Hd, const double* Bd, double* 
   if (int_spline && !(J.flags & GK_PHI_EIG)) {
     // exact banded evaluation (block tridiagonal Cholesky solves)
     if (small_wave_ok(s)) {
-      double* work = J.ar.get<double>(banded_work_elems(m, s));
+      double* work = J.ar.get<double>(bcr_work_elems(m, s));
       launch_banded_spline_reg(m, s, Hd, Bd, J.phi.eps, (int)kk, work, U, J.dflags + 0, J.st);
     } else if (wide_ok(s)) {
       double* work = J.ar.get<double>(banded_wide_work_elems(m, s));

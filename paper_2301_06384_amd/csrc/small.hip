@@ -813,82 +813,7 @@ cholqr_blk_kernel(const double* __restrict__ G, int ld, int s, int pass, const d
   }
 }
 
-// Banded spline factor phase (s <= 64): for each block j
-//   A = eps I + H_jj - Lsub_{j-1} Lsub_{j-1}^T ; A = L_jj L_jj^T ;
-//   Linv_j = L_jj^{-1} ; Lsub_j = H_{j+1,j} Linv_j^T
-__global__ void __launch_bounds__(ST)
-banded_factor_blk_kernel(int m, int s, const double* __restrict__ Hd, const double* __restrict__ Bd, double eps,
-                         double* __restrict__ Linv_all, double* __restrict__ Lsub_all, int* __restrict__ bad) {
-  __shared__ __align__(16) double A[WS][LP];
-  __shared__ __align__(16) double Y[WS][LP];
-  __shared__ __align__(16) double SB[WS][LP];
-  __shared__ __align__(16) double Ls[WS][LP];
-  const int tid = threadIdx.x;
-  const int tx = tid & 15, ty = tid >> 4;
-  const int ss = s * s;
-  double hv[16], bv[16];
-  fetch64(Hd, s, s, hv);
-  for (int j = 0; j < m; ++j) {
-    // A = eps I + H_jj (operands of the next block are fetched ahead)
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-      for (int b = 0; b < 4; ++b)
-        if (ty + 16 * a == tx + 16 * b && ty + 16 * a < s) hv[4 * a + b] += eps;
-    put64(A, hv);
-    fetch64(Bd + (int64_t)j * ss, s, s, bv);
-    __syncthreads();
-    if (j + 1 < m) fetch64(Hd + (int64_t)(j + 1) * ss, s, s, hv);
-    if (j > 0) {
-      double acc[4][4];
-      lds_mm<true, false>(Ls, Ls, s, acc);   // Ls holds Lsub_{j-1}^T: Lsub Lsub^T
-      __syncthreads();
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int jj = 0; jj < 4; ++jj) {
-          const int r = acc_row(i), c = acc_col(jj);
-          if (r < s && c < s) A[r][c] -= acc[i][jj];
-        }
-      __syncthreads();
-    }
-    blk_chol_inv(A, Y, SB, s, 0, nullptr, nullptr, 0.0, nullptr, bad, nullptr);
-    double* LiG = Linv_all + (int64_t)j * ss;
-    for (int i = ty; i < s; i += 16)
-      for (int c = tx; c < s; c += 16) LiG[i * s + c] = (c <= i) ? Y[i][c] : 0.0;
-    if (j + 1 < m) {
-      // SB served as elimination workspace; stage H_{j+1,j} transposed now,
-      // and Y^T into A (L itself is no longer needed)
-      put64T(SB, bv);
-      for (int i = ty; i < WS; i += 16)
-        for (int c = tx; c < WS; c += 16) A[c][i] = (i < s && c < s) ? Y[i][c] : 0.0;
-      __syncthreads();
-      // Lsub_j = H_{j+1,j} Y^T (Y has zeros above its diagonal: exact)
-      double acc[4][4];
-      lds_mm<true, false>(SB, A, s, acc);
-      __syncthreads();
-      double* LsG = Lsub_all + (int64_t)j * ss;
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int jj = 0; jj < 4; ++jj) {
-          const int r = acc_row(i), c = acc_col(jj);
-          Ls[c][r] = (r < s && c < s) ? acc[i][jj] : 0.0;   // kept transposed
-          if (r < s && c < s) LsG[r * s + c] = acc[i][jj];
-        }
-    }
-    __syncthreads();
-  }
-}
-
-// Solve phase: kpow times  Y <- (L L^T)^{-1} Y  with Y = U (m s x s), starting
-// from U = F_1, as forward (L) and backward (L^T) block substitutions:
-//   forward  Y_j <- Linv_j (Y_j - Lsub_{j-1} Y_{j-1})
-//   backward Y_j <- Linv_j^T (Y_j - Lsub_j^T Y_{j+1})
-// The columns of U are independent: one workgroup of 256 threads per
-// 16-column slice (grid ceil(s / 16)).  The operands of the next block step
-// are fetched into registers while the current one computes; the slice of
-// the neighbouring block stays in LDS.
+// 64 x 16 column slices of a product (the orthogonality estimate below).
 constexpr int SLP = 17;   // LDS pitch of a 64 x 16 slice
 
 // acc[a] = (A^T B)[acc_row(a)][lane & 15] for a 16-column slice B, summed
@@ -914,99 +839,6 @@ __device__ __forceinline__ void lds_mm_slice(const double (*A)[LP], const double
   else mm_slice_steps<4>(A, B, s, d0, d1);
 #pragma unroll
   for (int a = 0; a < 4; ++a) acc[a] = d0[a] + d1[a];
-}
-
-__global__ void __launch_bounds__(ST)
-banded_solve_kernel(int m, int s, int kpow, const double* __restrict__ Linv_all, const double* __restrict__ Lsub_all,
-                    double* __restrict__ U) {
-  __shared__ __align__(16) double SL[WS][LP];   // Lsub
-  __shared__ __align__(16) double SI[WS][LP];   // Linv
-  __shared__ double T[WS][SLP];                 // right-hand side slice
-  __shared__ double SY[WS][SLP];                // slice of the previous step's result
-  const int tid = threadIdx.x;
-  const int li = tid & 15;
-  const int c0 = 16 * blockIdx.x;
-  const int ss = s * s;
-  const int nsteps = 2 * kpow * m;
-  // step -> (direction, block)
-  auto blk_of = [&](int st, int& dir, int& j) {
-    const int w = st % (2 * m);
-    dir = w / m;
-    const int jj = w - dir * m;
-    j = dir == 0 ? jj : m - 1 - jj;
-  };
-  auto has_nb = [&](int dir, int j) { return dir == 0 ? (j > 0) : (j + 1 < m); };
-  // slice element e of this thread: row (tid + 256 e) / 16, column c0 + tid % 16
-  auto fetch_slice = [&](const double* Yj, double (&v)[4]) {
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int r = (tid + 256 * e) >> 4, c = c0 + li;
-      v[e] = (r < s && c < s) ? Yj[r * s + c] : 0.0;
-    }
-  };
-  // U = F_1 on this slice (first block identity)
-  for (int64_t q = tid; q < (int64_t)m * s * 16; q += ST) {
-    const int64_t r = q >> 4;
-    const int c = c0 + (int)(q & 15);
-    if (c < s) U[r * s + c] = (r == c) ? 1.0 : 0.0;
-  }
-  __syncthreads();
-  double pi[16], pl[16], pt[4];
-  {
-    int dir, j;
-    blk_of(0, dir, j);
-    fetch64(Linv_all + (int64_t)j * ss, s, s, pi);
-    fetch64(nullptr, s, s, pl);
-    fetch_slice(U + (int64_t)j * ss, pt);
-  }
-  int pj = -1;
-  for (int st = 0; st < nsteps; ++st) {
-    int dir, j;
-    blk_of(st, dir, j);
-    const bool nb = has_nb(dir, j);
-    // products run as C = X^T B: the forward sweep stages Lsub and Linv transposed
-    if (dir == 0) {
-      put64T(SI, pi);
-      put64T(SL, pl);
-    } else {
-      put64(SI, pi);
-      put64(SL, pl);
-    }
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int r = (tid + 256 * e) >> 4;
-      // the previous step finished this very block at the turn of a sweep
-      T[r][li] = (j == pj) ? SY[r][li] : pt[e];
-    }
-    __syncthreads();
-    if (st + 1 < nsteps) {
-      int d2, j2;
-      blk_of(st + 1, d2, j2);
-      fetch64(Linv_all + (int64_t)j2 * ss, s, s, pi);
-      fetch64(has_nb(d2, j2) ? Lsub_all + (int64_t)(d2 == 0 ? j2 - 1 : j2) * ss : nullptr, s, s, pl);
-      fetch_slice(U + (int64_t)j2 * ss, pt);
-    }
-    double acc[4];
-    if (nb) {
-      lds_mm_slice(SL, SY, s, acc);   // Lsub_{j-1} Y_{j-1} (forward) or Lsub_j^T Y_{j+1} (backward)
-      __syncthreads();
-#pragma unroll
-      for (int a = 0; a < 4; ++a) T[acc_row(a)][li] -= acc[a];
-      __syncthreads();
-    }
-    lds_mm_slice(SI, T, s, acc);     // Linv_j T (forward) or Linv_j^T T (backward)
-    __syncthreads();   // SY is read above (nb) and rewritten below
-    double* Y = U + (int64_t)j * ss;
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      const int r = acc_row(a), c = c0 + li;
-      const bool in = r < s && c < s;
-      SY[r][li] = in ? acc[a] : 0.0;
-      if (in) Y[r * s + c] = acc[a];
-    }
-    __syncthreads();
-    pj = j;
-  }
 }
 
 // ---------------------------------------------------------------------
@@ -1194,21 +1026,6 @@ void launch_omega(int k, int s, int ld, const double* Wk, const double* Wkm1, do
   hipLaunchKernelGGL(omega_decide_kernel, dim3(1), dim3(ST), 0, st, k, s, nj > 0 ? nj : 0, ne, est_part, tau,
                      floor_re, floor_loc, Wk1, fr, forced, est_out, nre);
   GK_HIP(hipGetLastError());
-}
-
-void launch_banded_spline_reg(int m, int s, const double* Hd, const double* Bd, double eps, int k, double* work,
-                              double* U, int* bad, hipStream_t st) {
-  const size_t ss = (size_t)s * s;
-  double* Linv = work;
-  double* Lsub = work + m * ss;
-  kt_begin(KC_BANDED_FACTOR, st);
-  hipLaunchKernelGGL(banded_factor_blk_kernel, dim3(1), dim3(ST), 0, st, m, s, Hd, Bd, eps, Linv, Lsub, bad);
-  GK_HIP(hipGetLastError());
-  kt_end(st, 8.0 * 4 * m * (double)ss, (double)m * ss * s * (2.0 + 1.0 / 3.0 + 1.0));
-  kt_begin(KC_BANDED_SOLVE, st);
-  hipLaunchKernelGGL(banded_solve_kernel, dim3((s + 15) / 16), dim3(ST), 0, st, m, s, k, Linv, Lsub, U);
-  GK_HIP(hipGetLastError());
-  kt_end(st, 8.0 * 4 * 2 * k * m * (double)ss, 4.0 * 2 * k * m * (double)ss * s);
 }
 
 }  // namespace gk

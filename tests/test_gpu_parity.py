@@ -241,6 +241,22 @@ def test_wide_blocks(s, phi):
             assert st.as_dict()["phi_method"] == "banded"
 
 
+@pytest.mark.parametrize("s,m", [(16, 1), (16, 2), (16, 3), (16, 5), (16, 8), (16, 13), (16, 31), (64, 2),
+                                 (64, 5), (64, 7)])
+def test_cyclic_reduction_spline_matches_spectral(s, m):
+    # (eps I + H_m)^(-k) F_1 by block cyclic reduction (block widths up to
+    # 64; m = 1, powers of two and odd depths exercise every level shape)
+    # against the spectral decomposition of the same H_m, for k = 1, 2, 3
+    L, g = G("rgg2003")
+    W = I.samples(L.n, s, 11)
+    for k in (1.0, 2.0, 3.0):
+        phi = dict(kind="spline", eps=0.03, k=k)
+        Pb, Kb, sb = gk.krylov_kernel_columns(g, W, phi, m, "cbl", "fp64")
+        Pe, Ke, se = gk.krylov_kernel_columns(g, W, phi, m, "cbl", "fp64", flags=gk.PHI_EIG)
+        assert sb.as_dict()["phi_method"] == "banded" and se.as_dict()["phi_method"] == "eig"
+        assert rel(Pb, Pe) < 1e-11 and rel(Kb, Ke) < 1e-11, (s, m, k, rel(Pb, Pe))
+
+
 @pytest.mark.parametrize("s", [100, 192])
 def test_wide_banded_spline_matches_spectral(s):
     # the tiled banded evaluation of (eps I + H_m)^(-k) F_1 against the
