@@ -28,7 +28,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
-# Roof of each kernel class: (bound, peak, unit, source file).  Peaks are the
+# Roof of each kernel class: (bound, peak, unit, source file or files).  Peaks are the
 # MI355X datasheet figures: HBM3E 8 TB/s, FP64 vector and FP64 matrix
 # 78.6 TFLOP/s, FP32 matrix 157.3 TFLOP/s (dense).
 ROOFS = {
@@ -44,12 +44,12 @@ ROOFS = {
     "tsgemm": ("mfma", 78.6, "TFLOP/s", "ortho.hip"),
     "assemble": ("mfma", 157.3, "TFLOP/s", "arch.hip"),
     "predict": ("hbm", HBM_PEAK_GBS, "GB/s", "ortho.hip"),
-    "cholqr": ("alu", 78.6, "TFLOP/s", "small.hip"),
-    "omega": ("alu", 78.6, "TFLOP/s", "small.hip"),
-    "banded_factor": ("alu", 78.6, "TFLOP/s", "small.hip"),
-    "banded_solve": ("alu", 78.6, "TFLOP/s", "small.hip"),
-    "cheb_step": ("alu", 78.6, "TFLOP/s", "small.hip"),
-    "jacobi_eig": ("alu", 78.6, "TFLOP/s", "small.hip"),
+    "cholqr": ("alu", 78.6, "TFLOP/s", ("small.hip", "tile64.h")),
+    "omega": ("alu", 78.6, "TFLOP/s", ("small.hip", "tile64.h")),
+    "banded_factor": ("alu", 78.6, "TFLOP/s", ("bcr.hip", "tile64.h")),
+    "banded_solve": ("alu", 78.6, "TFLOP/s", ("bcr.hip", "tile64.h")),
+    "cheb_step": ("alu", 78.6, "TFLOP/s", ("small.hip", "tile64.h")),
+    "jacobi_eig": ("alu", 78.6, "TFLOP/s", ("small.hip", "tile64.h")),
 }
 
 
@@ -278,7 +278,7 @@ def main():
     dom = max(agg.values(), key=lambda k: k["total_ms"])
     bound, peak, unit, ach = _achieved(dom)
     src = ROOFS.get(dom["name"], (None, None, None, "small.hip"))[3]
-    traffic = _traffic_from_profile(dom["name"], "rgg100k_s64", _kernel_hash([src]))
+    traffic = _traffic_from_profile(dom["name"], "rgg100k_s64", _kernel_hash([src] if isinstance(src, str) else src))
     value = s / (ms_mixed * 1e-3)
     res = {
         "metric": "kernel cols/s at 1e-5 rel err vs FP64 path",
