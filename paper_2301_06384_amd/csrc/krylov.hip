@@ -405,10 +405,11 @@ static void run_cbl(Job& J) {
       part_all = J.ar.get<double>(pe_all);
     }
   }
-  // tolerances of the estimate: threshold, floor after a reorthogonalisation
-  // against the float32 archive, floor of the two explicitly orthogonalised
-  // neighbours, and the per-step rounding model
-  const double om_tau = 1e-4, om_floor_re = 2e-8, om_floor_loc = 1e-14;
+  // tolerances of the estimate: threshold (semi-orthogonality at the square
+  // root of the unit roundoff of the float32 archive, 2^-12), floor after a
+  // reorthogonalisation against the float32 archive, floor of the two
+  // explicitly orthogonalised neighbours, and the per-step rounding model
+  const double om_tau = 0x1p-12, om_floor_re = 2e-8, om_floor_loc = 1e-14;
   const double om_nu = 1.1102230246251565e-16 * g->lambda_max * std::sqrt((double)s);
   for (int k = 0; k < m; ++k) {
     double* Vk = V64(k);
