@@ -194,7 +194,8 @@ void launch_spmm(const gk_graph* g, bool fp32_weights, int ld, const double* V, 
   const double vb = 8.0 * (double)g->n * ld;
   kt_begin(KC_SPMM, st);
   // lanes per row: at most 64 (one wavefront), VPT doubles each
-  if (ld <= 128) {
+  // (16 lanes per row at ld = 64: 4 doubles each measured faster than 2 or 8)
+  if (ld <= 32) {
     spmm_dispatch_w<2>(g, fp32_weights, ld, V, Vprev, out, a, b, gmul, acc, e, e_dev, st);
   } else if (ld <= 256) {
     spmm_dispatch_w<4>(g, fp32_weights, ld, V, Vprev, out, a, b, gmul, acc, e, e_dev, st);
