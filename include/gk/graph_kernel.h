@@ -104,6 +104,10 @@ typedef enum {
 #define GK_PHI_EIG       0x4u   /* form phi(H_m) F_1 through the spectral decomposition of H_m even
                                    where an exact banded evaluation exists */
 #define GK_TIMING        0x8u   /* record per-phase device times into gk_stats (adds events) */
+#define GK_NO_REORTH     0x10u  /* GK_MIXED diagnostic: no reorthogonalisation against the stored basis
+                                   (local orthogonalisation only), to study the loss of orthogonality;
+                                   the results lose accuracy */
+/* Any other flag bit is rejected with GK_EINVAL. */
 
 /* ------------------------------------------------------------- statistics */
 typedef struct {

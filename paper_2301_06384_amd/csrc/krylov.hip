@@ -339,7 +339,7 @@ static void run_cbl(Job& J) {
   const int64_t blk = n * ld;
   const bool mixed = J.mixed();
   const bool full = J.full_reorth();
-  const bool no_reorth = mixed && (J.flags & 0x10u);
+  const bool no_reorth = mixed && (J.flags & GK_NO_REORTH);
   hipStream_t st = J.st;
   // storage
   double* Vb = nullptr;     // FP64 basis (GK_FP64)
@@ -553,7 +553,7 @@ static void run_scalar_lanczos(Job& J, bool global) {
   const int64_t blk = n * ld;
   const bool mixed = J.mixed();
   const bool full = J.full_reorth();
-  const bool no_reorth = mixed && (J.flags & 0x10u);
+  const bool no_reorth = mixed && (J.flags & GK_NO_REORTH);
   hipStream_t st = J.st;
   double* Vb = nullptr;
   double* ring = nullptr;
@@ -746,6 +746,8 @@ static void validate_common(const CallArgs& a) {
   GK_REQUIRE(a.samples, GK_EINVAL, "samples is NULL");
   GK_REQUIRE(a.variant >= GK_CBL && a.variant <= GK_CHEB2, GK_EINVAL, "unknown variant");
   GK_REQUIRE(a.precision == GK_FP64 || a.precision == GK_MIXED, GK_EINVAL, "unknown precision");
+  GK_REQUIRE((a.flags & ~(GK_IO_DEVICE | GK_FULL_REORTH | GK_PHI_EIG | GK_TIMING | GK_NO_REORTH)) == 0, GK_EINVAL,
+             "unknown flag bits");
   phi_check(*a.phi);
   if (a.fit) {
     GK_REQUIRE(a.y, GK_EINVAL, "y is NULL");

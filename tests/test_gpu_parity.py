@@ -365,6 +365,13 @@ def test_error_paths_on_device():
     with pytest.raises(gk.GKError) as e:
         gk.krylov_kernel_columns(g, [1, 2], dict(kind="diffusion", t=-1.0), 4)
     assert e.value.code == gk.EINVAL
+    with pytest.raises(gk.GKError) as e:   # flag bits the header does not define
+        gk.krylov_kernel_columns(g, [1, 2], phi, 4, flags=0x40)
+    assert e.value.code == gk.EINVAL
+    # the diagnostic flag switches the archive projection off and nothing else
+    W = I.samples(L.n, 16, 2)
+    P0, _, s0 = gk.krylov_kernel_columns(g, W, phi, 12, "cbl", "mixed", flags=gk.NO_REORTH)
+    assert s0.n_reorth == 0 and np.all(np.isfinite(P0))
     # diffusion with t = 0 gives E_W exactly
     P, K, _ = gk.krylov_kernel_columns(g, [3, 9], dict(kind="diffusion", t=0.0), 4)
     E = dense.unit_block(L.n, [3, 9])
