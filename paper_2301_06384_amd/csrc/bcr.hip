@@ -26,7 +26,7 @@ namespace gk {
 
 namespace {
 
-// write the s x s part of a 64 x 64 accumulator tile: dst[r * s + c] = sign * acc
+// write the s x s part of a 64 x 64 accumulator tile: dst[r * s + c] = acc
 __device__ __forceinline__ void store_acc(double* __restrict__ dst, int s, const double (&acc)[4][4]) {
 #pragma unroll
   for (int a = 0; a < 4; ++a)
