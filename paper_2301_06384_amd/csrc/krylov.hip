@@ -714,6 +714,7 @@ uint64_t footprint_bytes(int64_t n, int s, int m, int variant, int precision) {
     const double ms = (double)m * s;
     if (variant == GK_CBL) {
       b += 2 * ms * ms * 8.0 + (double)m * ld * ld * 8.0 + 4.0 * m * s * s * 8.0;
+      if (small_wave_ok(s)) b += 8.0 * bcr_work_elems(m, s);   // spline by cyclic reduction
       // Gram partials of the orthogonalisation passes
       const bool full = !mixed || (variant == GK_CBL && !(small_wave_ok(ld) || wide_ok(ld)));
       size_t pe = 0;
