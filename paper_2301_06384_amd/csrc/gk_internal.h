@@ -186,7 +186,7 @@ bool wide_ok(int ld);
 size_t cholqr_wide_scratch_elems(int ld);
 void launch_cholqr_wide(const double* G, int ld, int s, int pass, const double* diag_prev, double thr, double* wk,
                         double* R, double* Rinv, double* diag_out, int* n_defl, const double* R1, const double* R1inv,
-                        double* Rc, double* Bout, hipStream_t st);
+                        double* Rc, double* Bout, double* BT, hipStream_t st);
 size_t omega_wide_scratch_elems(int m, int s);
 void launch_omega_wide(int k, int s, int ld, const double* Wk, const double* Wkm1, double* Wk1, const double* Hd,
                        const double* Bd, const double* Rc, double nu, double* rhs, double* est_part, hipStream_t st);

@@ -425,17 +425,22 @@ static void run_cbl(Job& J) {
     const double* V0 = k > 0 ? Vkm1 : Vk;
     const double* V1 = k > 0 ? Vk : nullptr;
     const int local_passes = mixed ? 1 : 2;
-    // GK_MIXED on the panel kernels takes the recurrence as written in Alg. 1:
-    // X = L Q_k - Q_{k-1} H_{k-1,k} with H_{k-1,k} = B_{k-1}^T from the previous
-    // QR (coefficient block 0 of C, stored by the second CholQR pass), and
-    // H_kk = Q_k^T L Q_k, so the Gram pass projects onto Q_k alone.  GK_FP64
-    // projects onto both local blocks twice (classical Gram-Schmidt, twice).
-    const bool rec = mixed && pan && k > 0;
+    // GK_MIXED (block widths up to 512) takes the recurrence as written in
+    // Alg. 1: X = L Q_k - Q_{k-1} H_{k-1,k} with H_{k-1,k} = B_{k-1}^T from the
+    // previous QR (coefficient block 0 of C, stored by the second CholQR pass),
+    // and H_kk = Q_k^T L Q_k, so the Gram pass projects onto Q_k alone.
+    // GK_FP64 projects onto both local blocks twice (classical Gram-Schmidt,
+    // twice).
+    const bool rec = mixed && (pan || widek) && k > 0;
     for (int pass = 0; pass < local_passes; ++pass) {
-      if (rec) {
+      if (rec && pan) {
         launch_panel(PM_GRAMV, n, ld, 1, X, nullptr, nullptr, Vk, nullptr, nullptr, nullptr, ppart, C + l2, st);
         launch_panel(PM_UPDATE_SELF, n, ld, 2, X, X, nullptr, Vkm1, Vk, C, nullptr, ppart, G, st,
                      Hd + (int64_t)k * s * s, s);
+      } else if (rec) {
+        launch_gram(n, ld, BlockList{Vk, blk, 1, false}, X, C + l2, part, nullptr, st);
+        launch_store_H(C + l2, ld, s, Hd + (int64_t)k * s * s, st);
+        launch_tsgemm(n, ld, loc, C, X, X, nullptr, -1.0, 1.0, nullptr, st);
       } else if (pan) {
         launch_panel(PM_GRAMV, n, ld, nbv, X, nullptr, nullptr, V0, V1, nullptr, nullptr, ppart, C, st);
         // the update pass also stores H_kk = sym(C_k) on the first pass
@@ -473,7 +478,7 @@ static void run_cbl(Job& J) {
                           nullptr, st);
       else if (widek)
         launch_cholqr_wide(G, ld, s, 1, nullptr, J.thr(), W, R1, R1i, d1, nullptr, nullptr, nullptr, nullptr, nullptr,
-                           st);
+                           nullptr, st);
       else
         launch_cholqr_factor(G, ld, s, 1, nullptr, J.thr(), W, R1, R1i, d1, nullptr, st);
       if (pro && k >= 1) {
@@ -514,7 +519,7 @@ static void run_cbl(Job& J) {
                           Bd + (int64_t)k * s * s, (mixed && pan) ? C : nullptr, st);
       } else if (widek) {
         launch_cholqr_wide(G, ld, s, 2, d1, J.thr(), W, nullptr, nullptr, d2, J.dflags + 1, R1, R1i, R12i,
-                           Bd + (int64_t)k * s * s, st);
+                           Bd + (int64_t)k * s * s, mixed ? C : nullptr, st);
       } else {
         launch_cholqr_factor(G, ld, s, 2, d1, J.thr(), W, R2, R2i, d2, J.dflags + 1, st);
         launch_small_gemm(ld, ld, ld, R1i, ld, false, R2i, ld, false, R12i, ld, 1.0, 0.0, st);

@@ -192,7 +192,7 @@ cholqr_wide_kernel(const double* __restrict__ G, int ld, int s, int pass, const 
                    double thr, double* __restrict__ Aw, double* __restrict__ Yw, double* __restrict__ R,
                    double* __restrict__ Rinv, double* __restrict__ diag_out, int* __restrict__ n_defl,
                    const double* __restrict__ R1, const double* __restrict__ R1inv, double* __restrict__ Rc,
-                   double* __restrict__ Bout) {
+                   double* __restrict__ Bout, double* __restrict__ BT) {
   __shared__ __align__(16) double T0[WS][LP];
   __shared__ __align__(16) double T1[WS][LP];
   __shared__ __align__(16) double T2[WS][LP];
@@ -244,16 +244,24 @@ cholqr_wide_kernel(const double* __restrict__ G, int ld, int s, int pass, const 
     const int i = q / ld, c = q % ld;
     if (i >= s || c >= s) Rc[q] = 0.0;
   }
+  if (BT) {
+    // B^T zero padded to ld x ld, from this workgroup's B written above
+    __syncthreads();
+    for (int q = tid; q < ld * ld; q += ST) {
+      const int i = q / ld, c = q % ld;
+      BT[q] = (i < s && c < s) ? Bout[(int64_t)c * s + i] : 0.0;
+    }
+  }
 }
 
 size_t cholqr_wide_scratch_elems(int ld) { return (size_t)2 * ld * ld; }
 
 void launch_cholqr_wide(const double* G, int ld, int s, int pass, const double* diag_prev, double thr, double* wk,
                         double* R, double* Rinv, double* diag_out, int* n_defl, const double* R1, const double* R1inv,
-                        double* Rc, double* Bout, hipStream_t st) {
+                        double* Rc, double* Bout, double* BT, hipStream_t st) {
   kt_begin(KC_CHOLQR, st);
   hipLaunchKernelGGL(cholqr_wide_kernel, dim3(1), dim3(ST), 0, st, G, ld, s, pass, diag_prev, thr, wk,
-                     wk + (size_t)ld * ld, R, Rinv, diag_out, n_defl, R1, R1inv, Rc, Bout);
+                     wk + (size_t)ld * ld, R, Rinv, diag_out, n_defl, R1, R1inv, Rc, Bout, BT);
   GK_HIP(hipGetLastError());
   kt_end(st, 8.0 * 6 * ld * ld, (double)s * s * s * (pass == 2 ? 3.0 : 1.0));
 }
