@@ -107,9 +107,11 @@ size_t gram_scratch_elems(int64_t n, int nb, int ld);
 // C (nb*ld x ld) = A^T B,  B = n x ld double block; `part` scratch
 void launch_gram(int64_t n, int ld, BlockList A, const double* B, double* C, double* part,
                  const int* flag, hipStream_t st);
-// out = beta*in + alpha*(A * C), C (nb*ld x ld); optional float copy of out
+// out = beta*in + alpha*(A * C), C (nb*ld x ld); optional float copy of out.
+// upper: C (one block) is upper triangular with zeros stored below the
+// diagonal, and the contraction stops at each column tile's diagonal.
 void launch_tsgemm(int64_t n, int ld, BlockList A, const double* C, const double* in, double* out,
-                   float* out32, double alpha, double beta, const int* flag, hipStream_t st);
+                   float* out32, double alpha, double beta, const int* flag, hipStream_t st, bool upper = false);
 // column-major n x s output P[perm(i), c] = sum_a A[i,a] U[a,c]
 void launch_assemble(int64_t n, int ld, int s, BlockList A, const double* U, int ldu, double* P,
                      const int64_t* perm, hipStream_t st);
@@ -201,7 +203,10 @@ void launch_btd_cheb_tile(int m, int s, const double* Hd, const double* Bd, cons
 void launch_cheb_diffusion(int m, int s, const double* Hd, const double* Bd, double t, double Lam, int deg,
                            const double* coef, double* Y0, double* Y1, double* Y2, double* U, hipStream_t st);
 // deterministic sum of nparts equally long partial vectors: out[i] = sum_c part[c*len + i]
-void launch_reduce_parts(int64_t len, int nparts, const double* part, double* out, const int* flag, hipStream_t st);
+// sym_ld > 0: the parts hold the tiles on and above the diagonal of a symmetric
+// sym_ld x sym_ld matrix (64 x 64 tiles); out receives the whole matrix
+void launch_reduce_parts(int64_t len, int nparts, const double* part, double* out, const int* flag, hipStream_t st,
+                         int sym_ld = 0);
 void launch_small_solve(int s, const double* K, double gamma, const double* y, double* c, double* work,
                         int* piv, bool spd, int* bad, hipStream_t st);
 

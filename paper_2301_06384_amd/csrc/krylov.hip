@@ -509,7 +509,7 @@ static void run_cbl(Job& J) {
       if (pan) {
         launch_panel(PM_APPLY_SELF, n, ld, 0, X, nullptr, nullptr, nullptr, nullptr, nullptr, R1i, ppart, G, st);
       } else {
-        launch_tsgemm(n, ld, xl, R1i, nullptr, Y, nullptr, 1.0, 0.0, nullptr, st);
+        launch_tsgemm(n, ld, xl, R1i, nullptr, Y, nullptr, 1.0, 0.0, nullptr, st, true);
         BlockList yl{Y, blk, 1, false};
         launch_gram(n, ld, yl, Y, G, part, nullptr, st);
       }
@@ -530,7 +530,7 @@ static void run_cbl(Job& J) {
         launch_panel(PM_APPLY_WRITE, n, ld, 0, X, V64(k + 1), arch32, nullptr, nullptr, nullptr, R12i, ppart,
                      nullptr, st);
       else
-        launch_tsgemm(n, ld, xl, R12i, nullptr, V64(k + 1), arch32, 1.0, 0.0, nullptr, st);
+        launch_tsgemm(n, ld, xl, R12i, nullptr, V64(k + 1), arch32, 1.0, 0.0, nullptr, st, true);
     } else {
       // ||X_m||_F: residual indicator (the unused H_{m+1,m})
       hipLaunchKernelGGL(trace_sqrt_kernel, dim3(1), dim3(256), 0, st, G, ld, s, J.dscal);

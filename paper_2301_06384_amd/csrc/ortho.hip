@@ -86,14 +86,21 @@ gram_kernel(int64_t n, int ld, const void* __restrict__ Abase, int64_t astride, 
 // out[i] = sum_{c < nparts} part[c*len + i] in a fixed order: block b owns
 // outputs [16b, 16b+16); its 16 thread groups sum interleaved parts (eight
 // running sums per thread, so eight loads are in flight, combined pairwise),
-// then the 16 group sums are added in group order.
+// then the 16 group sums are added in group order.  sym_ld > 0: the parts
+// hold only the 64 x 64 tiles on and above the diagonal of a symmetric
+// sym_ld x sym_ld matrix; entries below read their mirror.
 __global__ void __launch_bounds__(256)
 reduce_parts_kernel(int64_t len, int nparts, const double* __restrict__ part, double* __restrict__ out,
-                    const int* __restrict__ flag) {
+                    const int* __restrict__ flag, int sym_ld) {
   if (flag && *flag == 0) return;
   __shared__ double red[16][17];
   const int o = threadIdx.x & 15, g = threadIdx.x >> 4;
   const int64_t i = (int64_t)blockIdx.x * 16 + o;
+  int64_t src = i;
+  if (sym_ld > 0 && i < len) {
+    const int64_t r = i / sym_ld, c = i - r * sym_ld;
+    if ((r >> 6) > (c >> 6)) src = c * sym_ld + r;
+  }
   double s = 0.0;
   if (i < len) {
     double a[8];
@@ -102,8 +109,8 @@ reduce_parts_kernel(int64_t len, int nparts, const double* __restrict__ part, do
     int c = g;
     for (; c + 16 * 7 < nparts; c += 16 * 8)
 #pragma unroll
-      for (int u = 0; u < 8; ++u) a[u] += part[(int64_t)(c + 16 * u) * len + i];
-    for (; c < nparts; c += 16) a[0] += part[(int64_t)c * len + i];
+      for (int u = 0; u < 8; ++u) a[u] += part[(int64_t)(c + 16 * u) * len + src];
+    for (; c < nparts; c += 16) a[0] += part[(int64_t)c * len + src];
     s = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
   }
   red[g][o] = s;
@@ -115,10 +122,11 @@ reduce_parts_kernel(int64_t len, int nparts, const double* __restrict__ part, do
   }
 }
 
-void launch_reduce_parts(int64_t len, int nparts, const double* part, double* out, const int* flag, hipStream_t st) {
+void launch_reduce_parts(int64_t len, int nparts, const double* part, double* out, const int* flag, hipStream_t st,
+                        int sym_ld) {
   kt_begin(KC_REDUCE, st);
   hipLaunchKernelGGL(reduce_parts_kernel, dim3((unsigned)((len + 15) / 16)), dim3(256), 0, st, len, nparts, part, out,
-                     flag);
+                     flag, sym_ld);
   GK_HIP(hipGetLastError());
   kt_end(st, 8.0 * (double)len * (nparts + 1), (double)len * nparts, flag);
 }
@@ -197,8 +205,9 @@ template <bool F32>
 __global__ void __launch_bounds__(256)
 gram_mfma_kernel(int64_t n, int ld, const void* __restrict__ Abase, int64_t astride, int nb,
                  const double* __restrict__ B, double* __restrict__ part, int64_t rows_per_chunk,
-                 const int* __restrict__ flag) {
+                 const int* __restrict__ flag, int sym) {
   if (flag && *flag == 0) return;
+  if (sym && blockIdx.x > blockIdx.y) return;   // B^T B: the tiles below the diagonal are mirrors
   __shared__ __align__(16) double sA[MG_RS][MG_P];
   __shared__ __align__(16) double sB[MG_RS][MG_P];
   const int pa = nb * ld;
@@ -281,7 +290,7 @@ __global__ void __launch_bounds__(256)
 tsgemm_mfma_kernel(int64_t n, int ld, const void* __restrict__ Abase, int64_t astride, int nb,
                    const double* __restrict__ C, int ldc, int ncols, const double* __restrict__ in,
                    double* __restrict__ out, float* __restrict__ out32, double alpha, double beta, int64_t ldo,
-                   const int64_t* __restrict__ perm, const int* __restrict__ flag) {
+                   const int64_t* __restrict__ perm, const int* __restrict__ flag, int upper) {
   if (flag && *flag == 0) return;
   __shared__ __align__(16) double sAT[MT_K][MT_R + 2];
   __shared__ __align__(16) double sC[MT_K][MT_C + 2];
@@ -325,8 +334,10 @@ tsgemm_mfma_kernel(int64_t n, int ld, const void* __restrict__ Abase, int64_t as
       else vc.zero();
     }
   };
+  // upper triangular C (one block): rows past the column tile are zero
+  const int aend = upper ? min(pa, b0 + MT_C) : pa;
   fetch(0);
-  for (int a0 = 0; a0 < pa; a0 += MT_K) {
+  for (int a0 = 0; a0 < aend; a0 += MT_K) {
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < 8; ++q) sAT[ak + q][ar] = va.get(q);
@@ -340,7 +351,7 @@ tsgemm_mfma_kernel(int64_t n, int ld, const void* __restrict__ Abase, int64_t as
         *reinterpret_cast<double2*>(&sC[cr][cc + 2 * q]) = make_double2(vc.get(2 * q), vc.get(2 * q + 1));
     }
     __syncthreads();
-    if (a0 + MT_K < pa) fetch(a0 + MT_K);
+    if (a0 + MT_K < aend) fetch(a0 + MT_K);
 #pragma unroll
     for (int ks = 0; ks < MT_K / 4; ++ks) {
       double av[2], bv[2];
@@ -408,14 +419,17 @@ void launch_gram(int64_t n, int ld, BlockList A, const double* B, double* C, dou
   int64_t rpc;
   gram_geometry(n, A.nb, ld, &nx, &ny, &nch, &rpc);
   dim3 grid(nx, ny, nch);
+  // the Gram of a block with itself is symmetric: only the tiles on and
+  // above the diagonal are formed
+  const bool sym = mfma_ok(ld) && A.nb == 1 && !A.f32 && A.base == (const void*)B;
   kt_begin(KC_GRAM, st);
   if (mfma_ok(ld)) {
     if (A.f32)
       hipLaunchKernelGGL(gram_mfma_kernel<true>, grid, dim3(256), 0, st, n, ld, A.base, A.stride, A.nb, B, part, rpc,
-                         flag);
+                         flag, 0);
     else
       hipLaunchKernelGGL(gram_mfma_kernel<false>, grid, dim3(256), 0, st, n, ld, A.base, A.stride, A.nb, B, part,
-                         rpc, flag);
+                         rpc, flag, sym ? 1 : 0);
   } else if (A.f32)
     hipLaunchKernelGGL(gram_kernel<true>, grid, dim3(256), 0, st, n, ld, A.base, A.stride, A.nb, B,
                        part, rpc, flag);
@@ -424,7 +438,7 @@ void launch_gram(int64_t n, int ld, BlockList A, const double* B, double* C, dou
                        part, rpc, flag);
   GK_HIP(hipGetLastError());
   kt_end(st, (double)n * ld * ((A.f32 ? 4.0 : 8.0) * A.nb + 8.0), 2.0 * (double)n * ld * ld * A.nb, flag);
-  launch_reduce_parts((int64_t)A.nb * ld * ld, nch, part, C, flag, st);
+  launch_reduce_parts((int64_t)A.nb * ld * ld, nch, part, C, flag, st, sym ? ld : 0);
 }
 
 // ------------------------------------------------------- tall-skinny GEMM
@@ -519,17 +533,18 @@ tsgemm_kernel(int64_t n, int ld, int ncols, const void* __restrict__ Abase, int6
 }
 
 void launch_tsgemm(int64_t n, int ld, BlockList A, const double* C, const double* in, double* out,
-                   float* out32, double alpha, double beta, const int* flag, hipStream_t st) {
+                   float* out32, double alpha, double beta, const int* flag, hipStream_t st, bool upper) {
+  const int up = (upper && A.nb == 1) ? 1 : 0;
   dim3 grid((unsigned)((n + T_TR - 1) / T_TR), (ld + T_TB - 1) / T_TB);
   kt_begin(KC_TSGEMM, st);
   if (mfma_ok(ld)) {
     static_assert(MT_R == T_TR && MT_C == T_TB, "same tile grid");
     if (A.f32)
       hipLaunchKernelGGL((tsgemm_mfma_kernel<true, false>), grid, dim3(256), 0, st, n, ld, A.base, A.stride, A.nb, C,
-                         ld, ld, in, out, out32, alpha, beta, (int64_t)ld, (const int64_t*)nullptr, flag);
+                         ld, ld, in, out, out32, alpha, beta, (int64_t)ld, (const int64_t*)nullptr, flag, up);
     else
       hipLaunchKernelGGL((tsgemm_mfma_kernel<false, false>), grid, dim3(256), 0, st, n, ld, A.base, A.stride, A.nb,
-                         C, ld, ld, in, out, out32, alpha, beta, (int64_t)ld, (const int64_t*)nullptr, flag);
+                         C, ld, ld, in, out, out32, alpha, beta, (int64_t)ld, (const int64_t*)nullptr, flag, up);
   } else if (A.f32)
     hipLaunchKernelGGL((tsgemm_kernel<true, false>), grid, dim3(256), 0, st, n, ld, ld, A.base, A.stride,
                        A.nb, C, ld, in, out, out32, alpha, beta, (int64_t)ld, (const int64_t*)nullptr,
@@ -550,10 +565,12 @@ void launch_assemble(int64_t n, int ld, int s, BlockList A, const double* U, int
   if (mfma_ok(ld)) {
     if (A.f32)
       hipLaunchKernelGGL((tsgemm_mfma_kernel<true, true>), grid, dim3(256), 0, st, n, ld, A.base, A.stride, A.nb, U,
-                         ldu, s, (const double*)nullptr, P, (float*)nullptr, 1.0, 0.0, n, perm, (const int*)nullptr);
+                         ldu, s, (const double*)nullptr, P, (float*)nullptr, 1.0, 0.0, n, perm, (const int*)nullptr,
+                         0);
     else
       hipLaunchKernelGGL((tsgemm_mfma_kernel<false, true>), grid, dim3(256), 0, st, n, ld, A.base, A.stride, A.nb, U,
-                         ldu, s, (const double*)nullptr, P, (float*)nullptr, 1.0, 0.0, n, perm, (const int*)nullptr);
+                         ldu, s, (const double*)nullptr, P, (float*)nullptr, 1.0, 0.0, n, perm, (const int*)nullptr,
+                         0);
   } else if (A.f32)
     hipLaunchKernelGGL((tsgemm_kernel<true, true>), grid, dim3(256), 0, st, n, ld, s, A.base, A.stride,
                        A.nb, U, ldu, (const double*)nullptr, P, (float*)nullptr, 1.0, 0.0, n, perm,
