@@ -45,7 +45,7 @@ struct PanelArgs {
 // APPLY: X_new = X Rm.  GRAMV: Gram [V]^T X_new.  SELF: Gram X_new^T X_new
 // (symmetric: only tiles gi <= xj are formed, the partial is mirrored).
 template <int NT, int NBV, bool UPDATE, bool APPLY, bool GRAMV, bool SELF, bool WRITE, bool W32>
-__global__ void __launch_bounds__(PT_THREADS, 2) panel_kernel(PanelArgs p) {
+__global__ void __launch_bounds__(PT_THREADS, (GRAMV || SELF) ? 2 : 3) panel_kernel(PanelArgs p) {
   constexpr int LD = NT * 16;
   constexpr int P = LD + 4;                      // LDS row pitch (doubles)
   constexpr int KS = LD / 4;                     // MFMA k-steps over ld
@@ -305,8 +305,10 @@ void launch_panel(int mode, int64_t n, int ld, int nbv, const double* X, double*
                   const double* V0, const double* V1, const double* Cupd, const double* Rm, double* part,
                   double* Cout, hipStream_t st, double* H, int hs) {
   PanelArgs a{n, X, Xout, X32, V0, V1, Cupd, Rm, part, H, hs};
-  const int grid = panel_grid(n);
   const PanelMode pm = (PanelMode)mode;
+  // the write pass forms no Gram (no partials) and fits three workgroups per CU
+  const int grid = pm == PM_APPLY_WRITE ? (int)std::min<int64_t>((n + PT_ROWS - 1) / PT_ROWS, 3 * PT_MAXGRID / 2)
+                                        : panel_grid(n);
   // algorithmic bytes / flops of the pass (block = n x ld float64)
   const double blk = 8.0 * (double)n * ld, nl2 = (double)n * ld * ld, self = (double)n * ld * (ld + 1);
   static const int kc[4] = {KC_PANEL_GRAMV, KC_PANEL_UPDATE_SELF, KC_PANEL_APPLY_SELF, KC_PANEL_APPLY_WRITE};
