@@ -45,7 +45,7 @@ struct PanelArgs {
 // APPLY: X_new = X Rm.  GRAMV: Gram [V]^T X_new.  SELF: Gram X_new^T X_new
 // (symmetric: only tiles gi <= xj are formed, the partial is mirrored).
 template <int NT, int NBV, bool UPDATE, bool APPLY, bool GRAMV, bool SELF, bool WRITE, bool W32>
-__global__ void __launch_bounds__(PT_THREADS, (GRAMV || SELF) ? 2 : 3) panel_kernel(PanelArgs p) {
+__global__ void __launch_bounds__(PT_THREADS, APPLY ? 3 : 2) panel_kernel(PanelArgs p) {
   constexpr int LD = NT * 16;
   constexpr int P = LD + 4;                      // LDS row pitch (doubles)
   constexpr int KS = LD / 4;                     // MFMA k-steps over ld
@@ -270,6 +270,9 @@ int panel_grid(int64_t n) {
   return (int)std::min<int64_t>(nt, PT_MAXGRID);
 }
 
+// Room for the largest set of Gram partials: two blocks over panel_grid(n)
+// workgroups, or one block over up to 3/2 as many (the passes that run three
+// workgroups per CU).
 size_t panel_scratch_elems(int64_t n, int ld) { return (size_t)panel_grid(n) * 3 * ld * ld; }
 
 typedef int PanelMode;
@@ -306,9 +309,10 @@ void launch_panel(int mode, int64_t n, int ld, int nbv, const double* X, double*
                   double* Cout, hipStream_t st, double* H, int hs) {
   PanelArgs a{n, X, Xout, X32, V0, V1, Cupd, Rm, part, H, hs};
   const PanelMode pm = (PanelMode)mode;
-  // the write pass forms no Gram (no partials) and fits three workgroups per CU
-  const int grid = pm == PM_APPLY_WRITE ? (int)std::min<int64_t>((n + PT_ROWS - 1) / PT_ROWS, 3 * PT_MAXGRID / 2)
-                                        : panel_grid(n);
+  // the apply passes fit three workgroups per CU (their at most one Gram
+  // block of partials stays within the scratch of panel_scratch_elems)
+  const bool three = pm == PM_APPLY_WRITE || pm == PM_APPLY_SELF;
+  const int grid = three ? (int)std::min<int64_t>((n + PT_ROWS - 1) / PT_ROWS, 3 * PT_MAXGRID / 2) : panel_grid(n);
   // algorithmic bytes / flops of the pass (block = n x ld float64)
   const double blk = 8.0 * (double)n * ld, nl2 = (double)n * ld * ld, self = (double)n * ld * (ld + 1);
   static const int kc[4] = {KC_PANEL_GRAMV, KC_PANEL_UPDATE_SELF, KC_PANEL_APPLY_SELF, KC_PANEL_APPLY_WRITE};
