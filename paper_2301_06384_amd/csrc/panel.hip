@@ -47,7 +47,9 @@ struct PanelArgs {
 template <int NT, int NBV, bool UPDATE, bool APPLY, bool GRAMV, bool SELF, bool WRITE, bool W32>
 __global__ void __launch_bounds__(PT_THREADS, APPLY ? 3 : 2) panel_kernel(PanelArgs p) {
   constexpr int LD = NT * 16;
-  constexpr int P = LD + 4;                      // LDS row pitch (doubles)
+  // LDS row pitch (doubles): P / 2 odd, so the 16 rows that one matrix-core
+  // operand read takes down a column fall in distinct banks
+  constexpr int P = LD + 2;
   constexpr int KS = LD / 4;                     // MFMA k-steps over ld
   constexpr int NGB = (GRAMV ? NBV : 0) + (SELF ? 1 : 0);
   constexpr bool SYM = SELF && !GRAMV;
@@ -55,11 +57,13 @@ __global__ void __launch_bounds__(PT_THREADS, APPLY ? 3 : 2) panel_kernel(PanelA
   constexpr int TPW = (NPAIR + 3) / 4;           // Gram tiles per wavefront
   constexpr bool NEED_V = NBV > 0 && (UPDATE || GRAMV);
   constexpr int NBC = UPDATE ? NBV : (APPLY ? 1 : 0);   // coefficient blocks in registers
-  // prefetch of the next tile (registers permitting: not with the two-block
-  // update, whose coefficients already fill them)
-  constexpr bool PF = !(UPDATE && NBV > 1 && NT > 2);
-  __shared__ double sX[PT_ROWS * P];
-  __shared__ double sV[(NEED_V ? NBV : 1) * PT_ROWS * P];
+  // rows per tile: 16 for the two-block update at ld >= 48, whose
+  // coefficients fill half the registers, so that the next tile's rows still
+  // fit in registers while the current tile is processed
+  constexpr bool HALF = UPDATE && NBV > 1 && NT > 2;
+  constexpr int TR = HALF ? 16 : PT_ROWS;
+  __shared__ double sX[TR * P];
+  __shared__ double sV[(NEED_V ? NBV : 1) * TR * P];
 
   const int tid = threadIdx.x;
   const int w = tid >> 6;
@@ -79,7 +83,7 @@ __global__ void __launch_bounds__(PT_THREADS, APPLY ? 3 : 2) panel_kernel(PanelA
   // Update / apply product: wavefront w owns one 16-column tile (unt) of X_new
   // over UP slabs of 16 rows; its right operands stay in registers for the
   // whole kernel.
-  constexpr int UP = NT >= 3 ? 2 : 1;
+  constexpr int UP = NT >= 3 ? TR / 16 : 1;
   const int unt = NT >= 3 ? w : (w >> 1);
   const int us0 = NT >= 3 ? 0 : (w & 1);
   const bool uact = unt < NT;
@@ -123,11 +127,11 @@ __global__ void __launch_bounds__(PT_THREADS, APPLY ? 3 : 2) panel_kernel(PanelA
 #pragma unroll
   for (int t = 0; t < (TPW > 0 ? TPW : 1); ++t) gacc[t] = d4{0.0, 0.0, 0.0, 0.0};
 
-  const int64_t ntiles = (p.n + PT_ROWS - 1) / PT_ROWS;
+  const int64_t ntiles = (p.n + TR - 1) / TR;
   // Tile rows go through registers: loads of the next tile are issued right
   // after the current one is in LDS, so they are in flight during its
   // products (rows past n read row n - 1 and are zeroed at the LDS store).
-  constexpr int SQ = PT_ROWS * LD / PT_THREADS;
+  constexpr int SQ = TR * LD / PT_THREADS;
   double lx[SQ], l0[NEED_V ? SQ : 1], l1[NEED_V && NBV > 1 ? SQ : 1];
   auto fetch_tile = [&](int64_t r0) {
 #pragma unroll
@@ -143,10 +147,9 @@ __global__ void __launch_bounds__(PT_THREADS, APPLY ? 3 : 2) panel_kernel(PanelA
       }
     }
   };
-  if (PF && (int64_t)blockIdx.x < ntiles) fetch_tile((int64_t)blockIdx.x * PT_ROWS);
+  if ((int64_t)blockIdx.x < ntiles) fetch_tile((int64_t)blockIdx.x * TR);
   for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-    const int64_t r0 = tile * PT_ROWS;
-    if (!PF) fetch_tile(r0);
+    const int64_t r0 = tile * TR;
 #pragma unroll
     for (int e = 0; e < SQ; ++e) {
       const int q = e * PT_THREADS + tid;
@@ -155,11 +158,11 @@ __global__ void __launch_bounds__(PT_THREADS, APPLY ? 3 : 2) panel_kernel(PanelA
       sX[rr * P + cc] = in ? lx[e] : 0.0;
       if (NEED_V) {
         sV[rr * P + cc] = in ? l0[e] : 0.0;
-        if (NBV > 1) sV[PT_ROWS * P + rr * P + cc] = in ? l1[e] : 0.0;
+        if (NBV > 1) sV[TR * P + rr * P + cc] = in ? l1[e] : 0.0;
       }
     }
     __syncthreads();
-    if (PF && tile + gridDim.x < ntiles) fetch_tile((tile + gridDim.x) * PT_ROWS);
+    if (tile + gridDim.x < ntiles) fetch_tile((tile + gridDim.x) * TR);
     // ---- X_new for the (slabs, column tile) of this wavefront
     if (UPDATE || APPLY) {
       d4 acc[UP];
@@ -176,7 +179,7 @@ __global__ void __launch_bounds__(PT_THREADS, APPLY ? 3 : 2) panel_kernel(PanelA
         if (UPDATE) {
 #pragma unroll
           for (int b = 0; b < (NBV > 0 ? NBV : 1); ++b) {
-            const double* sv = sV + b * PT_ROWS * P;
+            const double* sv = sV + b * TR * P;
 #pragma unroll
             for (int ks = 0; ks < KS; ++ks) {
 #pragma unroll
@@ -212,7 +215,7 @@ __global__ void __launch_bounds__(PT_THREADS, APPLY ? 3 : 2) panel_kernel(PanelA
       __syncthreads();
       if (WRITE || W32) {
 #pragma unroll
-        for (int q0 = 0; q0 < PT_ROWS * LD; q0 += PT_THREADS) {
+        for (int q0 = 0; q0 < TR * LD; q0 += PT_THREADS) {
           const int q = q0 + tid;
           const int rr = q / LD, cc = q - rr * LD;
           const int64_t r = r0 + rr;
@@ -231,12 +234,16 @@ __global__ void __launch_bounds__(PT_THREADS, APPLY ? 3 : 2) panel_kernel(PanelA
         const int gi = tgi[t], xj = txj[t];
         if (gi >= 0) {
           const int gb = gi / NT, gc0 = 16 * (gi - gb * NT);
-          const double* gsrc = (GRAMV && gb < NBV) ? (sV + gb * PT_ROWS * P) : sX;
+          const double* gsrc = (GRAMV && gb < NBV) ? (sV + gb * TR * P) : sX;
           d4 a4 = gacc[t];
 #pragma unroll
-          for (int k0 = 0; k0 < PT_ROWS; k0 += 4) {
-            const double a = gsrc[(k0 + lk) * P + gc0 + li];
-            const double b = sX[(k0 + lk) * P + 16 * xj + li];
+          for (int k0 = 0; k0 < TR; k0 += 4) {
+            // step k0 of a 16-row block takes rows t, t + 8, t + 4, t + 12
+            // (t = k0 / 4 within the block): rows read together by half a
+            // wavefront are 8 apart, 8 P = 16 mod 32 double banks
+            const int row = (k0 & ~15) + ((k0 & 15) >> 2) + 8 * (lk & 1) + 4 * (lk >> 1);
+            const double a = gsrc[row * P + gc0 + li];
+            const double b = sX[row * P + 16 * xj + li];
             a4 = mfma64(a, b, a4);
           }
           gacc[t] = a4;

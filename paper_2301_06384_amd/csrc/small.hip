@@ -676,6 +676,13 @@ cholqr_blk_kernel(const double* __restrict__ G, int ld, int s, int pass, const d
   __shared__ double red[2][ST];
   const int tid = threadIdx.x;
   const int tx = tid & 15, ty = tid >> 4;
+  // the second pass's first-pass factors are loaded up front, their latency
+  // hidden behind the factorisation
+  double v1[16], v2[16];
+  if (pass == 2) {
+    fetch64(R1, s, ld, v1);
+    fetch64(R1inv, s, ld, v2);
+  }
   stage64(A, G, s, ld);
   for (int q = tid; q < s; q += ST) {
     g0[q] = G[q * ld + q];
@@ -762,13 +769,8 @@ cholqr_blk_kernel(const double* __restrict__ G, int ld, int s, int pass, const d
       n_defl[0] += cnt;
       if (fast) n_defl[4] += 1;   // counter slot four entries after the deflation count
     }
-    {
-      double v1[16], v2[16];
-      fetch64(R1, s, ld, v1);
-      fetch64(R1inv, s, ld, v2);
-      put64(S1, v1);
-      put64T(S2, v2);
-    }
+    put64(S1, v1);
+    put64T(S2, v2);
     __syncthreads();
     double acc[4][4];
     if (fast && !R) {
