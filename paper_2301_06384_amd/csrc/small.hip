@@ -726,7 +726,8 @@ cholqr_blk_kernel(const double* __restrict__ G, int ld, int s, int pass, const d
       }
     __syncthreads();
     double mm[4][4], u2[4][4];
-    lds_mm2(S1, S1, S2, S1, s, mm, u2);    // U^T U and U U
+    // U^T U and U U, upper block triangles (only c >= r is read below)
+    lds_mm2_upper<KR_LEAD, KR_BAND>(S1, S1, S2, S1, s, mm, u2);
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -777,7 +778,7 @@ cholqr_blk_kernel(const double* __restrict__ G, int ld, int s, int pass, const d
       // B = R2 R1 = L^T S1 and Rc = R1inv R2inv = (R1inv^T)^T (R2inv in Y),
       // interleaved
       double rc[4][4];
-      lds_mm2(A, S1, S2, Y, s, acc, rc);
+      lds_mm2_upper<KR_BAND, KR_BAND>(A, S1, S2, Y, s, acc, rc);   // products of upper triangular factors
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -953,35 +954,37 @@ omega_kernel(int k, int s, int ld, const double* __restrict__ Wk, const double* 
 // carries the lost orthogonality one block further).  After a
 // reorthogonalisation the estimates restart from floor_re (the float32
 // archive limits the attainable orthogonality); the two local blocks are
-// always at floor_loc.
+// always at floor_loc.  Every workgroup reduces the per-slice estimates
+// itself (the same maximum in each) and resets its share of the blocks;
+// workgroup 0 alone records the decision.
 __global__ void __launch_bounds__(ST)
 omega_decide_kernel(int k, int s, int nj, int ne, const double* __restrict__ est_part, double tau, double floor_re,
                     double floor_loc, double* __restrict__ Wk1, int* __restrict__ fr, int* __restrict__ forced,
                     double* __restrict__ est_out, int* __restrict__ nre) {
-  __shared__ int go_sh;
+  __shared__ double red[ST / 64];
   const int tid = threadIdx.x;
-  const int ss = s * s;
-  if (tid == 0) {
-    double e = 0.0;
-    for (int j = 0; j < ne; ++j) e = fmax(e, est_part[j]);
-    const int f = forced[k];
-    const int go = (e > tau || f) ? 1 : 0;
+  const int64_t ss = (int64_t)s * s;
+  double e = 0.0;
+  for (int j = tid; j < ne; j += ST) e = fmax(e, est_part[j]);
+  for (int o = 32; o > 0; o >>= 1) e = fmax(e, __shfl_xor(e, o));
+  if ((tid & 63) == 0) red[tid >> 6] = e;
+  __syncthreads();
+  e = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+  const int f = forced[k];
+  const int go = (e > tau || f) ? 1 : 0;
+  if (blockIdx.x == 0 && tid == 0) {
     fr[k] = go;
     forced[k + 1] = (go && !f) ? 1 : 0;
-    if (go) {
-      *nre += 1;
-      e = floor_re;
+    if (go) *nre += 1;
+    *est_out = fmax(*est_out, go ? floor_re : e);
+  }
+  if (go)
+    for (int64_t q = (int64_t)blockIdx.x * ST + tid; q < nj * ss; q += (int64_t)gridDim.x * ST) Wk1[q] = floor_re;
+  if (blockIdx.x == 0)
+    for (int64_t q = tid; q < 2 * ss; q += ST) {
+      const int64_t jj = k - 1 + q / ss;
+      if (jj >= 0) Wk1[jj * ss + q % ss] = floor_loc;
     }
-    *est_out = fmax(*est_out, e);
-    go_sh = go;
-  }
-  __syncthreads();
-  if (go_sh)
-    for (int q = tid; q < nj * ss; q += ST) Wk1[q] = floor_re;
-  for (int q = tid; q < 2 * ss; q += ST) {
-    const int jj = k - 1 + q / ss;
-    if (jj >= 0) Wk1[(int64_t)jj * ss + q % ss] = floor_loc;
-  }
 }
 
 
@@ -1025,7 +1028,9 @@ void launch_omega(int k, int s, int ld, const double* Wk, const double* Wkm1, do
     }
   }
   const int ne = nj > 0 ? nj * omega_est_per_block(s) : 0;
-  hipLaunchKernelGGL(omega_decide_kernel, dim3(1), dim3(ST), 0, st, k, s, nj > 0 ? nj : 0, ne, est_part, tau,
+  // one workgroup per block of estimates to reset (at most 64)
+  const int dgrid = nj < 1 ? 1 : (nj < 64 ? nj : 64);
+  hipLaunchKernelGGL(omega_decide_kernel, dim3(dgrid), dim3(ST), 0, st, k, s, nj > 0 ? nj : 0, ne, est_part, tau,
                      floor_re, floor_loc, Wk1, fr, forced, est_out, nre);
   GK_HIP(hipGetLastError());
 }

@@ -89,6 +89,60 @@ __device__ __forceinline__ void lds_mm2(const double (*A1)[LP], const double (*B
     }
 }
 
+// lds_mm2 restricted to the output tiles on and above the block diagonal
+// (wave w forms tiles (w, b), b >= w) and to the contraction tiles whose
+// terms can be non-zero; the tiles below the diagonal are left zero.  Per
+// product, KR_LEAD sums contraction tiles 0..w (A^T B with A and B upper
+// triangular: U^T U) and KR_BAND tiles w..b (A^T and B upper triangular: the
+// product is upper triangular).  The skipped terms are exact zeros, so the
+// formed tiles equal those of lds_mm2 bit for bit.
+enum { KR_LEAD = 0, KR_BAND = 1 };
+template <int W, int K1, int K2>
+__device__ __forceinline__ void mm_steps2_upper(const double (*A1)[LP], const double (*B1)[LP],
+                                                const double (*A2)[LP], const double (*B2)[LP], int s, dv4 (&d1)[4],
+                                                dv4 (&d2)[4]) {
+  const int l = threadIdx.x & 63, li = l & 15, lk = l >> 4;
+#pragma unroll
+  for (int t = 0; t < 16; ++t) {
+    const int kt = t >> 2;
+    const int kk = 4 * t + lk;
+    const bool in = kk < s;
+    const double a1 = A1[kk][16 * W + li], a2 = A2[kk][16 * W + li];
+#pragma unroll
+    for (int b = W; b < 4; ++b) {
+      const bool u1 = K1 == KR_LEAD ? kt <= W : (kt >= W && kt <= b);
+      const bool u2 = K2 == KR_LEAD ? kt <= W : (kt >= W && kt <= b);
+      if (u1) d1[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(in ? a1 : 0.0, in ? B1[kk][16 * b + li] : 0.0, d1[b], 0, 0, 0);
+      if (u2) d2[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(in ? a2 : 0.0, in ? B2[kk][16 * b + li] : 0.0, d2[b], 0, 0, 0);
+    }
+  }
+}
+template <int K1, int K2>
+__device__ __forceinline__ void lds_mm2_upper(const double (*A1)[LP], const double (*B1)[LP], const double (*A2)[LP],
+                                              const double (*B2)[LP], int s, double (&acc1)[4][4],
+                                              double (&acc2)[4][4]) {
+  if (s <= 48) {   // few contraction steps: the full products
+    lds_mm2(A1, B1, A2, B2, s, acc1, acc2);
+    return;
+  }
+  dv4 d1[4], d2[4];
+#pragma unroll
+  for (int b = 0; b < 4; ++b) d1[b] = d2[b] = dv4{0.0, 0.0, 0.0, 0.0};
+  switch (__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6))) {
+    case 0: mm_steps2_upper<0, K1, K2>(A1, B1, A2, B2, s, d1, d2); break;
+    case 1: mm_steps2_upper<1, K1, K2>(A1, B1, A2, B2, s, d1, d2); break;
+    case 2: mm_steps2_upper<2, K1, K2>(A1, B1, A2, B2, s, d1, d2); break;
+    default: mm_steps2_upper<3, K1, K2>(A1, B1, A2, B2, s, d1, d2); break;
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      acc1[a][b] = d1[b][a];
+      acc2[a][b] = d2[b][a];
+    }
+}
+
 // acc = A^T B summed over the first s rows of two 64 x 64 LDS operands
 // (256 threads).  Wave w computes output rows 16w .. 16w+15 as four 16 x 16
 // tiles of v_mfma_f64_16x16x4f64: lane l = i + 16k holds A[4t+k][16w+i] and
