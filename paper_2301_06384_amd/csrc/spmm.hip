@@ -5,7 +5,7 @@
 // counted in Table 1.  Blocks are row-major n x ld (ld >= s, zero padded),
 // so a neighbour's row is one contiguous ld*8-byte segment: each row of the
 // output is owned by ld/VPT consecutive lanes that read VPT doubles of every
-// neighbour row with one vector load (coalesced gathers).
+// neighbour row as 16-byte vector loads (coalesced gathers).
 //
 // (L v)_i = d_i v_i - sum_{j != i} w_ij v_j with d_i = sum_j w_ij + c_i
 // accumulated in float64; with float32 weights d_i is the float64 sum of the
@@ -16,41 +16,25 @@ namespace gk {
 
 enum { W_UNIT = 0, W_F64 = 1, W_F32 = 2 };
 
+// A lane moves VPT doubles of a row as VPT / 2 16-byte chunks; chunk q of the
+// lane with index r within its row sits at column 2 r + q * cs (cs = twice the
+// lanes per row), so each chunk instruction of the row's lanes covers one
+// contiguous stretch of the row (whole cache lines) instead of every other
+// 16 bytes of all of it.
 template <int VPT>
-struct VecD;
-template <>
-struct VecD<1> {
-  __device__ static void load(const double* p, double* v) { v[0] = p[0]; }
-  __device__ static void store(double* p, const double* v) { p[0] = v[0]; }
-};
-template <>
-struct VecD<2> {
-  __device__ static void load(const double* p, double* v) {
-    double2 t = *reinterpret_cast<const double2*>(p);
-    v[0] = t.x; v[1] = t.y;
+__device__ __forceinline__ void load_row(const double* p, int cs, double (&v)[VPT]) {
+#pragma unroll
+  for (int q = 0; q < VPT / 2; ++q) {
+    const double2 t = *reinterpret_cast<const double2*>(p + q * cs);
+    v[2 * q] = t.x;
+    v[2 * q + 1] = t.y;
   }
-  __device__ static void store(double* p, const double* v) {
-    *reinterpret_cast<double2*>(p) = make_double2(v[0], v[1]);
-  }
-};
-template <>
-struct VecD<4> {
-  __device__ static void load(const double* p, double* v) {
-    VecD<2>::load(p, v); VecD<2>::load(p + 2, v + 2);
-  }
-  __device__ static void store(double* p, const double* v) {
-    VecD<2>::store(p, v); VecD<2>::store(p + 2, v + 2);
-  }
-};
-template <>
-struct VecD<8> {
-  __device__ static void load(const double* p, double* v) {
-    VecD<4>::load(p, v); VecD<4>::load(p + 4, v + 4);
-  }
-  __device__ static void store(double* p, const double* v) {
-    VecD<4>::store(p, v); VecD<4>::store(p + 4, v + 4);
-  }
-};
+}
+template <int VPT>
+__device__ __forceinline__ void store_row(double* p, int cs, const double (&v)[VPT]) {
+#pragma unroll
+  for (int q = 0; q < VPT / 2; ++q) *reinterpret_cast<double2*>(p + q * cs) = make_double2(v[2 * q], v[2 * q + 1]);
+}
 
 template <int VPT, int WM, bool SHFL>
 __global__ void __launch_bounds__(256)
@@ -70,7 +54,8 @@ spmm_diff_kernel(int64_t n, int ld, const int32_t* __restrict__ rp, const int32_
   const int64_t t = (int64_t)lb * blockDim.x + threadIdx.x;
   const int64_t row = t / slots;
   if (row >= n) return;
-  const int c0 = (int)(t - row * slots) * VPT;
+  const int lr = (int)(t - row * slots);   // lane index within the row
+  const int c0 = 2 * lr, cs = 2 * slots;
   double s[VPT];
 #pragma unroll
   for (int q = 0; q < VPT; ++q) s[q] = 0.0;
@@ -79,7 +64,6 @@ spmm_diff_kernel(int64_t n, int ld, const int32_t* __restrict__ rp, const int32_
     // The lanes of a row (a power of two dividing 64, so a row never straddles
     // wavefronts) load `slots` column indices and weights at once, then walk
     // them with lane shuffles, four gathers in flight.
-    const int lr = c0 / VPT;
     const int gbase = (int)(threadIdx.x & 63) - lr;
     for (int pc = p0; pc < p1; pc += slots) {
       const int pp = pc + lr;
@@ -100,7 +84,7 @@ spmm_diff_kernel(int64_t n, int ld, const int32_t* __restrict__ rp, const int32_
           w[u] = __shfl(myw, gbase + k + u);
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) VecD<VPT>::load(V + (int64_t)j[u] * ld + c0, v[u]);
+        for (int u = 0; u < 4; ++u) load_row<VPT>(V + (int64_t)j[u] * ld + c0, cs, v[u]);
 #pragma unroll
         for (int u = 0; u < 4; ++u)
 #pragma unroll
@@ -110,7 +94,7 @@ spmm_diff_kernel(int64_t n, int ld, const int32_t* __restrict__ rp, const int32_
         const int j0 = __shfl(myj, gbase + k);
         const double w0 = __shfl(myw, gbase + k);
         double v0[VPT];
-        VecD<VPT>::load(V + (int64_t)j0 * ld + c0, v0);
+        load_row<VPT>(V + (int64_t)j0 * ld + c0, cs, v0);
 #pragma unroll
         for (int q = 0; q < VPT; ++q) s[q] = fma(w0, v0[q], s[q]);
       }
@@ -124,8 +108,8 @@ spmm_diff_kernel(int64_t n, int ld, const int32_t* __restrict__ rp, const int32_
       if (WM == W_F64) { w0 = w64[p]; w1 = w64[p + 1]; }
       if (WM == W_F32) { w0 = (double)w32[p]; w1 = (double)w32[p + 1]; }
       double v0[VPT], v1[VPT];
-      VecD<VPT>::load(V + (int64_t)j0 * ld + c0, v0);
-      VecD<VPT>::load(V + (int64_t)j1 * ld + c0, v1);
+      load_row<VPT>(V + (int64_t)j0 * ld + c0, cs, v0);
+      load_row<VPT>(V + (int64_t)j1 * ld + c0, cs, v1);
 #pragma unroll
       for (int q = 0; q < VPT; ++q) s[q] = fma(w0, v0[q], fma(w1, v1[q], s[q]));
     }
@@ -135,30 +119,30 @@ spmm_diff_kernel(int64_t n, int ld, const int32_t* __restrict__ rp, const int32_
       if (WM == W_F64) w0 = w64[p];
       if (WM == W_F32) w0 = (double)w32[p];
       double v0[VPT];
-      VecD<VPT>::load(V + (int64_t)j0 * ld + c0, v0);
+      load_row<VPT>(V + (int64_t)j0 * ld + c0, cs, v0);
 #pragma unroll
       for (int q = 0; q < VPT; ++q) s[q] = fma(w0, v0[q], s[q]);
     }
   }
   double vi[VPT], o[VPT];
-  VecD<VPT>::load(V + row * ld + c0, vi);
+  load_row<VPT>(V + row * ld + c0, cs, vi);
   const double di = d[row];
 #pragma unroll
   for (int q = 0; q < VPT; ++q) o[q] = a * (di * vi[q] - s[q]) + b * vi[q];
   if (Vprev) {
     double vp[VPT];
-    VecD<VPT>::load(Vprev + row * ld + c0, vp);
+    load_row<VPT>(Vprev + row * ld + c0, cs, vp);
 #pragma unroll
     for (int q = 0; q < VPT; ++q) o[q] += gm * vp[q];
   }
-  VecD<VPT>::store(out + row * ld + c0, o);
+  store_row<VPT>(out + row * ld + c0, cs, o);
   if (acc) {
     if (e_dev) e = *e_dev;
     double ac[VPT];
-    VecD<VPT>::load(acc + row * ld + c0, ac);
+    load_row<VPT>(acc + row * ld + c0, cs, ac);
 #pragma unroll
     for (int q = 0; q < VPT; ++q) ac[q] = fma(e, o[q], ac[q]);
-    VecD<VPT>::store(acc + row * ld + c0, ac);
+    store_row<VPT>(acc + row * ld + c0, cs, ac);
   }
 }
 
