@@ -203,10 +203,10 @@ void launch_btd_cheb_tile(int m, int s, const double* Hd, const double* Bd, cons
 void launch_cheb_diffusion(int m, int s, const double* Hd, const double* Bd, double t, double Lam, int deg,
                            const double* coef, double* Y0, double* Y1, double* Y2, double* U, hipStream_t st);
 // deterministic sum of nparts equally long partial vectors: out[i] = sum_c part[c*len + i]
-// sym_ld > 0: the parts hold the tiles on and above the diagonal of a symmetric
-// sym_ld x sym_ld matrix (64 x 64 tiles); out receives the whole matrix
+// sym_ld > 0: the parts hold the sym_t x sym_t tiles on and above the diagonal
+// of a symmetric sym_ld x sym_ld matrix; out receives the whole matrix
 void launch_reduce_parts(int64_t len, int nparts, const double* part, double* out, const int* flag, hipStream_t st,
-                         int sym_ld = 0);
+                         int sym_ld = 0, int sym_t = 64);
 void launch_small_solve(int s, const double* K, double gamma, const double* y, double* c, double* work,
                         int* piv, bool spd, int* bad, hipStream_t st);
 

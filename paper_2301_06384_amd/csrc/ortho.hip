@@ -87,19 +87,24 @@ gram_kernel(int64_t n, int ld, const void* __restrict__ Abase, int64_t astride, 
 // outputs [16b, 16b+16); its 16 thread groups sum interleaved parts (eight
 // running sums per thread, so eight loads are in flight, combined pairwise),
 // then the 16 group sums are added in group order.  sym_ld > 0: the parts
-// hold only the 64 x 64 tiles on and above the diagonal of a symmetric
-// sym_ld x sym_ld matrix; entries below read their mirror.
+// hold only the sym_t x sym_t tiles on and above the diagonal of a symmetric
+// sym_ld x sym_ld matrix (sym_ld and sym_t multiples of 16, so a block's
+// outputs lie in one row of one tile); blocks below the diagonal return at
+// once and those above it also write the mirrored entries.
 __global__ void __launch_bounds__(256)
 reduce_parts_kernel(int64_t len, int nparts, const double* __restrict__ part, double* __restrict__ out,
-                    const int* __restrict__ flag, int sym_ld) {
+                    const int* __restrict__ flag, int sym_ld, int sym_t) {
   if (flag && *flag == 0) return;
   __shared__ double red[16][17];
   const int o = threadIdx.x & 15, g = threadIdx.x >> 4;
   const int64_t i = (int64_t)blockIdx.x * 16 + o;
-  int64_t src = i;
-  if (sym_ld > 0 && i < len) {
-    const int64_t r = i / sym_ld, c = i - r * sym_ld;
-    if ((r >> 6) > (c >> 6)) src = c * sym_ld + r;
+  const int64_t src = i;
+  int64_t mirror = -1;
+  if (sym_ld > 0) {
+    const int64_t r = ((int64_t)blockIdx.x * 16) / sym_ld, c = i - r * sym_ld;
+    const int64_t tr = r / sym_t, tc = ((int64_t)blockIdx.x * 16 - r * sym_ld) / sym_t;
+    if (tr > tc) return;   // the whole block: lower tiles come from their mirror
+    if (tr < tc) mirror = c * sym_ld + r;
   }
   double s = 0.0;
   if (i < len) {
@@ -119,16 +124,23 @@ reduce_parts_kernel(int64_t len, int nparts, const double* __restrict__ part, do
     double t = 0.0;
     for (int q = 0; q < 16; ++q) t += red[q][o];
     out[i] = t;
+    if (mirror >= 0) out[mirror] = t;
   }
 }
 
 void launch_reduce_parts(int64_t len, int nparts, const double* part, double* out, const int* flag, hipStream_t st,
-                        int sym_ld) {
+                        int sym_ld, int sym_t) {
+  // entries read per part: the whole vector, or the tiles on and above the diagonal
+  double rd = (double)len;
+  if (sym_ld > 0) {
+    const double nt = sym_ld / sym_t;
+    rd = nt * (nt + 1) / 2 * sym_t * sym_t;
+  }
   kt_begin(KC_REDUCE, st);
   hipLaunchKernelGGL(reduce_parts_kernel, dim3((unsigned)((len + 15) / 16)), dim3(256), 0, st, len, nparts, part, out,
-                     flag, sym_ld);
+                     flag, sym_ld, sym_t);
   GK_HIP(hipGetLastError());
-  kt_end(st, 8.0 * (double)len * (nparts + 1), (double)len * nparts, flag);
+  kt_end(st, 8.0 * (rd * nparts + len), rd * nparts, flag);
 }
 
 // Blocks 64 and wider use the FP64 matrix-core kernels below (rows staged

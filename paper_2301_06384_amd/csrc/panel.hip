@@ -43,7 +43,8 @@ struct PanelArgs {
 
 // NT: ld / 16.  NBV: local blocks staged.  UPDATE: X_new = X - [V] C.
 // APPLY: X_new = X Rm.  GRAMV: Gram [V]^T X_new.  SELF: Gram X_new^T X_new
-// (symmetric: only tiles gi <= xj are formed, the partial is mirrored).
+// (symmetric: only tiles gi <= xj are formed and written to the partial; the
+// reduction mirrors them).
 template <int NT, int NBV, bool UPDATE, bool APPLY, bool GRAMV, bool SELF, bool WRITE, bool W32>
 __global__ void __launch_bounds__(PT_THREADS, APPLY ? 3 : 2) panel_kernel(PanelArgs p) {
   constexpr int LD = NT * 16;
@@ -263,7 +264,6 @@ __global__ void __launch_bounds__(PT_THREADS, APPLY ? 3 : 2) panel_kernel(PanelA
         for (int r = 0; r < 4; ++r) {
           const int row = 16 * gi + 4 * r + lk, col = 16 * xj + li;
           P0[(int64_t)row * LD + col] = gacc[t][r];
-          if (SYM && gi != xj) P0[(int64_t)col * LD + row] = gacc[t][r];
         }
       }
     }
@@ -343,7 +343,9 @@ void launch_panel(int mode, int64_t n, int ld, int nbv, const double* X, double*
   if (pm == PM_GRAMV) ngb = nbv;
   if (pm == PM_UPDATE_SELF || pm == PM_APPLY_SELF) ngb = 1;
   if (ngb > 0) {
-    launch_reduce_parts((int64_t)ngb * ld * ld, grid, part, Cout, nullptr, st);
+    // the symmetric Gram's partials hold only its 16 x 16 tiles on and above the diagonal
+    const bool sym = pm == PM_UPDATE_SELF || pm == PM_APPLY_SELF;
+    launch_reduce_parts((int64_t)ngb * ld * ld, grid, part, Cout, nullptr, st, sym ? ld : 0, 16);
   }
 }
 
