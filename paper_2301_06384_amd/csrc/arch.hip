@@ -16,6 +16,7 @@
 //   B (4 x 16):  lane l holds B[k][i]
 //   D (16 x 16): register r of lane l holds D[4 k + r][i]
 #include "gk_internal.h"
+#include "decide.h"
 
 namespace gk {
 
@@ -47,8 +48,15 @@ constexpr int ag_blocks(int nt) { return AG_WAVES / nt; }
 template <int NT>
 __global__ void __launch_bounds__(AG_THREADS, 1)
 arch_gram_kernel(int64_t n, const float* __restrict__ Q, int64_t qstride, int nb, const double* __restrict__ X,
-                 double* __restrict__ part, int64_t rpc, const int* __restrict__ flag) {
-  if (flag && *flag == 0) return;
+                 double* __restrict__ part, int64_t rpc, const int* __restrict__ flag, OmegaDecide dec) {
+  if (dec.fr) {
+    // the reorthogonalisation decision, taken by every workgroup (no launch
+    // of its own on the steps that do not project)
+    __shared__ double dred[AG_THREADS / 64];
+    if (!omega_decide(dec, blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y, dred)) return;
+  } else if (flag && *flag == 0) {
+    return;
+  }
   constexpr int LD = 16 * NT;
   constexpr int P = LD + 16;                 // LDS pitch (floats): the 4-row operand reads avoid bank conflicts
   constexpr int BPW = ag_blocks(NT);
@@ -415,7 +423,8 @@ size_t arch_scratch_elems(int64_t n, int nb_max, int ld) {
 }
 
 template <int NT>
-static void arch_launch(int64_t n, BlockList A, double* X, double* C, double* part, const int* flag, hipStream_t st) {
+static void arch_launch(int64_t n, BlockList A, double* X, double* C, double* part, const int* flag, hipStream_t st,
+                        const OmegaDecide* dec) {
   const float* Q = static_cast<const float*>(A.base);
   int ng, nc;
   int64_t rpc;
@@ -423,8 +432,9 @@ static void arch_launch(int64_t n, BlockList A, double* X, double* C, double* pa
   const double qb = 4.0 * (double)n * 16 * NT * A.nb, xb = 8.0 * (double)n * 16 * NT;
   const double fl = 2.0 * (double)n * 16 * NT * 16 * NT * A.nb;
   kt_begin(KC_ARCH_GRAM, st);
+  const OmegaDecide dv = dec ? *dec : OmegaDecide{};
   hipLaunchKernelGGL(arch_gram_kernel<NT>, dim3(ng, nc), dim3(AG_THREADS), 0, st, n, Q, A.stride, A.nb,
-                     (const double*)X, part, rpc, flag);
+                     (const double*)X, part, rpc, flag, dv);
   GK_HIP(hipGetLastError());
   kt_end(st, qb + xb, fl, flag);
   const int64_t len = (int64_t)A.nb * 16 * NT * 16 * NT;
@@ -437,15 +447,18 @@ static void arch_launch(int64_t n, BlockList A, double* X, double* C, double* pa
 }
 
 // One projection X -= Q (Q^T X) against the float32 archive A (A.f32, A.stride
-// > 0, blocks n x ld row-major).  C receives the nb*ld x ld coefficients.
+// > 0, blocks n x ld row-major).  C receives the nb*ld x ld coefficients.  The
+// Gram launch takes the decision dec when given (its workgroups return at
+// once when it is negative) and otherwise tests the flag.
 void launch_arch_reorth(int64_t n, int ld, BlockList A, double* X, double* C, double* part, const int* flag,
-                        hipStream_t st) {
+                        hipStream_t st, const OmegaDecide* dec) {
   GK_REQUIRE(A.f32 && A.stride > 0 && A.nb >= 1, GK_EUNSUPPORTED, "archive projection needs a float32 archive");
+  GK_REQUIRE(!dec || (dec->fr && flag == dec->fr + dec->k), GK_EINVAL, "the decision must write the gating flag");
   switch (ld) {
-    case 16: arch_launch<1>(n, A, X, C, part, flag, st); break;
-    case 32: arch_launch<2>(n, A, X, C, part, flag, st); break;
-    case 48: arch_launch<3>(n, A, X, C, part, flag, st); break;
-    case 64: arch_launch<4>(n, A, X, C, part, flag, st); break;
+    case 16: arch_launch<1>(n, A, X, C, part, flag, st, dec); break;
+    case 32: arch_launch<2>(n, A, X, C, part, flag, st, dec); break;
+    case 48: arch_launch<3>(n, A, X, C, part, flag, st, dec); break;
+    case 64: arch_launch<4>(n, A, X, C, part, flag, st, dec); break;
     default: throw Error{GK_EUNSUPPORTED, "archive projection needs ld in {16,32,48,64}"};
   }
 }

@@ -175,13 +175,28 @@ void launch_cholqr_reg(const double* G, int ld, int s, int pass, const double* d
 size_t bcr_work_elems(int m, int s);
 void launch_banded_spline_reg(int m, int s, const double* Hd, const double* Bd, double eps, int k, double* work,
                               double* U, int* bad, hipStream_t st);
+// Arguments of the reorthogonalisation decision of step k (decide.h): the
+// per-slice estimates, the threshold and floors, the next estimate block set
+// W_{k+1,*} (s x s blocks) and the decision records.
+struct OmegaDecide {
+  int k, s, nj, ne;
+  const double* est_part;
+  double tau, floor_re, floor_loc;
+  double* Wk1;
+  int* fr;
+  int* forced;
+  double* est_out;
+  int* nre;
+};
 // Block orthogonality estimate (partial reorthogonalisation) for s <= 512.
 // est_part holds m * omega_est_per_block(s) entries; rhs_wide is null for
-// s <= 64 and omega_wide_scratch_elems(m, s) doubles otherwise.
+// s <= 64 and omega_wide_scratch_elems(m, s) doubles otherwise.  With defer
+// non-null the decision is not launched: its arguments go to *defer for the
+// archive projection to take (launch_arch_reorth).
 void launch_omega(int k, int s, int ld, const double* Wk, const double* Wkm1, double* Wk1, const double* Hd,
                   const double* Bd, const double* Rc, double nu, double tau, double floor_re, double floor_loc,
                   double* est_part, int* fr, int* forced, double* est_out, int* nre, double* rhs_wide,
-                  hipStream_t st);
+                  hipStream_t st, OmegaDecide* defer = nullptr);
 int omega_est_per_block(int s);
 // Small kernels for widths 65..512 (tiles of 64, one workgroup each).
 bool wide_ok(int ld);
@@ -216,8 +231,10 @@ bool panel_ok(int ld);
 // arch.hip -- projection against the float32 archive on FP32 matrix cores
 bool arch_ok(int ld);
 size_t arch_scratch_elems(int64_t n, int nb_max, int ld);
+// flag gates the three launches; with dec non-null the first one takes the
+// reorthogonalisation decision itself (it writes the flag, dec->fr + dec->k).
 void launch_arch_reorth(int64_t n, int ld, BlockList A, double* X, double* C, double* part, const int* flag,
-                        hipStream_t st);
+                        hipStream_t st, const OmegaDecide* dec = nullptr);
 void launch_arch_assemble(int64_t n, int ld, int s, BlockList A, const double* U, double* P, const int64_t* perm,
                           hipStream_t st);
 size_t panel_scratch_elems(int64_t n, int ld);

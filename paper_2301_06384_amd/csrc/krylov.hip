@@ -492,13 +492,17 @@ static void run_cbl(Job& J) {
         // floor set by the float32 archive.  At k = 1 the estimate has no
         // block to act on.
         const int* fk = fr + k;
+        // with the archive projection to follow, its first launch takes the
+        // decision (no launch of its own)
+        const bool defer = k >= 2 && part_arch;
+        OmegaDecide dec{};
         launch_omega(k, s, ld, Wr[k % 3], Wr[(k + 2) % 3], Wr[(k + 1) % 3], Hd, Bd, R1i, om_nu, om_tau, om_floor_re,
-                     om_floor_loc, est_part, fr, forced, J.dscal + 1, J.dflags + 3, om_rhs, st);
+                     om_floor_loc, est_part, fr, forced, J.dscal + 1, J.dflags + 3, om_rhs, st, defer ? &dec : nullptr);
         if (k >= 2) {
           J.tm.begin(PH_REORTH);
           BlockList all{Va, blk, k - 1, true};
           if (part_arch) {
-            launch_arch_reorth(n, ld, all, X, C, part_arch, fk, st);
+            launch_arch_reorth(n, ld, all, X, C, part_arch, fk, st, &dec);
           } else {
             launch_gram(n, ld, all, X, C, part_all, fk, st);
             launch_tsgemm(n, ld, all, C, X, X, nullptr, -1.0, 1.0, fk, st);

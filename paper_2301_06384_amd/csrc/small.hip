@@ -7,6 +7,7 @@
 // need no grid-wide synchronisation.
 #include "gk_internal.h"
 #include "tile64.h"
+#include "decide.h"
 
 namespace gk {
 
@@ -949,42 +950,12 @@ omega_kernel(int k, int s, int ld, const double* __restrict__ Wk, const double* 
   if (tid == 0) est_part[j * gridDim.y + q] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
 }
 
-// Decision after the estimate of step k: reorthogonalise when the estimate
-// exceeds tau, and once more on the next step (the three-term coupling
-// carries the lost orthogonality one block further).  After a
-// reorthogonalisation the estimates restart from floor_re (the float32
-// archive limits the attainable orthogonality); the two local blocks are
-// always at floor_loc.  Every workgroup reduces the per-slice estimates
-// itself (the same maximum in each) and resets its share of the blocks;
-// workgroup 0 alone records the decision.
-__global__ void __launch_bounds__(ST)
-omega_decide_kernel(int k, int s, int nj, int ne, const double* __restrict__ est_part, double tau, double floor_re,
-                    double floor_loc, double* __restrict__ Wk1, int* __restrict__ fr, int* __restrict__ forced,
-                    double* __restrict__ est_out, int* __restrict__ nre) {
+// The reorthogonalisation decision of step k as a launch of its own (when no
+// archive projection follows to take it): one workgroup per block of
+// estimates to reset.
+__global__ void __launch_bounds__(ST) omega_decide_kernel(OmegaDecide d) {
   __shared__ double red[ST / 64];
-  const int tid = threadIdx.x;
-  const int64_t ss = (int64_t)s * s;
-  double e = 0.0;
-  for (int j = tid; j < ne; j += ST) e = fmax(e, est_part[j]);
-  for (int o = 32; o > 0; o >>= 1) e = fmax(e, __shfl_xor(e, o));
-  if ((tid & 63) == 0) red[tid >> 6] = e;
-  __syncthreads();
-  e = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
-  const int f = forced[k];
-  const int go = (e > tau || f) ? 1 : 0;
-  if (blockIdx.x == 0 && tid == 0) {
-    fr[k] = go;
-    forced[k + 1] = (go && !f) ? 1 : 0;
-    if (go) *nre += 1;
-    *est_out = fmax(*est_out, go ? floor_re : e);
-  }
-  if (go)
-    for (int64_t q = (int64_t)blockIdx.x * ST + tid; q < nj * ss; q += (int64_t)gridDim.x * ST) Wk1[q] = floor_re;
-  if (blockIdx.x == 0)
-    for (int64_t q = tid; q < 2 * ss; q += ST) {
-      const int64_t jj = k - 1 + q / ss;
-      if (jj >= 0) Wk1[jj * ss + q % ss] = floor_loc;
-    }
+  omega_decide(d, blockIdx.x, gridDim.x, red);
 }
 
 
@@ -1013,7 +984,7 @@ void launch_cholqr_reg(const double* G, int ld, int s, int pass, const double* d
 void launch_omega(int k, int s, int ld, const double* Wk, const double* Wkm1, double* Wk1, const double* Hd,
                   const double* Bd, const double* Rc, double nu, double tau, double floor_re, double floor_loc,
                   double* est_part, int* fr, int* forced, double* est_out, int* nre, double* rhs_wide,
-                  hipStream_t st) {
+                  hipStream_t st, OmegaDecide* defer) {
   const int nj = k - 1;   // recurrence for j <= k-2
   if (nj > 0) {
     if (s > WS) {
@@ -1028,10 +999,14 @@ void launch_omega(int k, int s, int ld, const double* Wk, const double* Wkm1, do
     }
   }
   const int ne = nj > 0 ? nj * omega_est_per_block(s) : 0;
+  const OmegaDecide d{k, s, nj > 0 ? nj : 0, ne, est_part, tau, floor_re, floor_loc, Wk1, fr, forced, est_out, nre};
+  if (defer) {
+    *defer = d;
+    return;
+  }
   // one workgroup per block of estimates to reset (at most 64)
   const int dgrid = nj < 1 ? 1 : (nj < 64 ? nj : 64);
-  hipLaunchKernelGGL(omega_decide_kernel, dim3(dgrid), dim3(ST), 0, st, k, s, nj > 0 ? nj : 0, ne, est_part, tau,
-                     floor_re, floor_loc, Wk1, fr, forced, est_out, nre);
+  hipLaunchKernelGGL(omega_decide_kernel, dim3(dgrid), dim3(ST), 0, st, d);
   GK_HIP(hipGetLastError());
 }
 
