@@ -2,7 +2,8 @@
 // orthogonalisation of classical block Lanczos (Alg. 1: H_kk = Q_k^T X,
 // X -= Q_k H_kk, QR of X) with block widths ld in {16, 32, 48, 64}.
 //
-// A workgroup (4 wavefronts) walks over 32-row tiles of the n x ld blocks.
+// A workgroup (4 wavefronts) walks over row tiles of the n x ld blocks (32
+// rows; 16 for the two-block update at ld >= 48).
 // Per tile it stages the rows of X and of the local basis blocks in LDS, forms
 // the updated rows X_new (X - V C, or X R) on MFMA, optionally writes them,
 // and accumulates Gram products G^T X_new (G = basis blocks and/or X_new

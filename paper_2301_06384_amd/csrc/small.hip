@@ -684,6 +684,14 @@ cholqr_blk_kernel(const double* __restrict__ G, int ld, int s, int pass, const d
     fetch64(R1, s, ld, v1);
     fetch64(R1inv, s, ld, v2);
   }
+  // deflation and series-path counters of the second pass: read now, written
+  // back at the end, so their latency is off the critical path
+  const bool rec = pass == 2 && n_defl && tid == 0;
+  int nd0 = 0, nd4 = 0;
+  if (rec) {
+    nd0 = n_defl[0];
+    nd4 = n_defl[4];   // counter slot four entries after the deflation count
+  }
   stage64(A, G, s, ld);
   for (int q = tid; q < s; q += ST) {
     g0[q] = G[q * ld + q];
@@ -765,12 +773,14 @@ cholqr_blk_kernel(const double* __restrict__ G, int ld, int s, int pass, const d
     }
   for (int q = tid; q < ld; q += ST) diag_out[q] = (q < s) ? dg[q] : 0.0;
   if (pass == 2) {
-    if (tid == 0 && n_defl) {
-      int cnt = 0;
-      for (int j = 0; j < s; ++j) cnt += (dg[j] == 0.0);
-      n_defl[0] += cnt;
-      if (fast) n_defl[4] += 1;   // counter slot four entries after the deflation count
-    }
+    auto record = [&]() {
+      if (rec) {
+        int cnt = 0;
+        for (int j = 0; j < s; ++j) cnt += (dg[j] == 0.0);
+        n_defl[0] = nd0 + cnt;
+        n_defl[4] = nd4 + (fast ? 1 : 0);
+      }
+    };
     put64(S1, v1);
     put64T(S2, v2);
     __syncthreads();
@@ -789,6 +799,7 @@ cholqr_blk_kernel(const double* __restrict__ G, int ld, int s, int pass, const d
           if (BT && r < ld && c < ld) BT[c * ld + r] = (r < s && c < s) ? acc[i][j] : 0.0;
           if (r < ld && c < ld) Rc[r * ld + c] = (r < s && c < s) ? rc[i][j] : 0.0;
         }
+      record();
       return;
     }
     // B = R2 * R1 = L^T * S1
@@ -814,6 +825,7 @@ cholqr_blk_kernel(const double* __restrict__ G, int ld, int s, int pass, const d
         const int r = acc_row(i), c = acc_col(j);
         if (r < ld && c < ld) Rc[r * ld + c] = (r < s && c < s) ? acc[i][j] : 0.0;
       }
+    record();
   }
 }
 
