@@ -27,30 +27,29 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# MI355X datasheet peaks (dense): FP64 vector and matrix 78.6 TFLOP/s, FP32
+# matrix 157.3 TFLOP/s.
+PEAK_TF = {"fp64": 78.6, "fp32": 157.3}
 
-# Roof of each kernel class: (bound, peak, unit, source file or files).  Peaks are the
-# MI355X datasheet figures: HBM3E 8 TB/s, FP64 vector and FP64 matrix
-# 78.6 TFLOP/s, FP32 matrix 157.3 TFLOP/s (dense).
-ROOFS = {
-    "spmm_diff": ("hbm", HBM_PEAK_GBS, "GB/s", "spmm.hip"),
-    "reduce_parts": ("hbm", HBM_PEAK_GBS, "GB/s", "ortho.hip"),
-    "panel_gramv": ("mfma", 78.6, "TFLOP/s", "panel.hip"),
-    "panel_update_self": ("mfma", 78.6, "TFLOP/s", "panel.hip"),
-    "panel_apply_self": ("mfma", 78.6, "TFLOP/s", "panel.hip"),
-    "panel_apply_write": ("mfma", 78.6, "TFLOP/s", "panel.hip"),
-    "arch_gram": ("mfma", 157.3, "TFLOP/s", "arch.hip"),
-    "arch_update": ("mfma", 157.3, "TFLOP/s", "arch.hip"),
-    "gram": ("mfma", 78.6, "TFLOP/s", "ortho.hip"),
-    "tsgemm": ("mfma", 78.6, "TFLOP/s", "ortho.hip"),
-    "assemble": ("mfma", 157.3, "TFLOP/s", "arch.hip"),
-    "predict": ("hbm", HBM_PEAK_GBS, "GB/s", "ortho.hip"),
-    "cholqr": ("alu", 78.6, "TFLOP/s", ("small.hip", "tile64.h")),
-    "omega": ("alu", 78.6, "TFLOP/s", ("small.hip", "tile64.h")),
-    "banded_factor": ("alu", 78.6, "TFLOP/s", ("bcr.hip", "tile64.h")),
-    "banded_solve": ("alu", 78.6, "TFLOP/s", ("bcr.hip", "tile64.h")),
-    "cheb_step": ("alu", 78.6, "TFLOP/s", ("small.hip", "tile64.h")),
-    "jacobi_eig": ("alu", 78.6, "TFLOP/s", ("small.hip", "tile64.h")),
+# Kernel class -> (arithmetic of its flops, runs on the matrix cores, source
+# files).  Single-workgroup classes form latency chains: no chip-wide roof.
+CLASSES = {
+    "spmm_diff": ("fp64", False, "spmm.hip"),
+    "reduce_parts": ("fp64", False, "ortho.hip"),
+    "panel_gramv": ("fp64", True, "panel.hip"),
+    "panel_update_self": ("fp64", True, "panel.hip"),
+    "panel_apply_self": ("fp64", True, "panel.hip"),
+    "panel_apply_write": ("fp64", True, "panel.hip"),
+    "arch_gram": ("fp32", True, "arch.hip"),
+    "arch_update": ("fp32", True, "arch.hip"),
+    "gram": ("fp64", True, "ortho.hip"),
+    "tsgemm": ("fp64", True, "ortho.hip"),
+    "assemble": ("fp32", True, ("arch.hip", "ortho.hip")),
+    "predict": ("fp64", False, "ortho.hip"),
 }
+LATENCY = {"cholqr": ("small.hip", "tile64.h"), "omega": ("small.hip", "tile64.h"),
+           "banded_factor": ("bcr.hip", "tile64.h"), "banded_solve": ("bcr.hip", "tile64.h"),
+           "cheb_step": ("small.hip", "tile64.h"), "jacobi_eig": ("small.hip", "tile64.h")}
 
 
 def _kernel_hash(files):
@@ -59,6 +58,11 @@ def _kernel_hash(files):
         with open(os.path.join(ROOT, "paper_2301_06384_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
+
+
+def _sources(name):
+    src = CLASSES[name][2] if name in CLASSES else LATENCY.get(name, "small.hip")
+    return [src] if isinstance(src, str) else list(src)
 
 
 def _traffic_from_profile(kernel: str, workload: str, src_hash: str):
@@ -81,13 +85,72 @@ def _traffic_from_profile(kernel: str, workload: str, src_hash: str):
         return None
 
 
-def _achieved(k):
-    bound, peak, unit, _ = ROOFS.get(k["name"], ("alu", 78.6, "TFLOP/s", ""))
-    t = k["total_ms"] * 1e-3
+def classify(k, assemble_dtype="fp32"):
+    """Roofline of one kernel class from its algorithmic bytes and flops: the
+    bound is the roof its intensity reaches first (HBM below the ridge point
+    peak / 8 TB/s of its arithmetic, the compute roof above it); single
+    workgroup classes are latency chains and carry no chip-wide fraction."""
+    name, t = k["name"], k["total_ms"] * 1e-3
+    if name in LATENCY or name not in CLASSES:
+        return dict(bound="latency", achieved=None, peak=None, unit=None, frac=None, intensity=None)
+    dtype, mfma, _ = CLASSES[name]
+    if name == "assemble":
+        dtype = assemble_dtype
+    inten = k["alg_flops"] / k["alg_bytes"] if k["alg_bytes"] > 0 else float("inf")
+    ridge = PEAK_TF[dtype] * 1e12 / (HBM_PEAK_GBS * 1e9)
     if t <= 0:
-        return bound, peak, unit, 0.0
-    a = k["alg_bytes"] / t / 1e9 if unit == "GB/s" else k["alg_flops"] / t / 1e12
-    return bound, peak, unit, a
+        return dict(bound="hbm", achieved=0.0, peak=HBM_PEAK_GBS, unit="GB/s", frac=0.0, intensity=inten)
+    if inten < ridge:
+        a = k["alg_bytes"] / t / 1e9
+        return dict(bound="hbm", achieved=a, peak=HBM_PEAK_GBS, unit="GB/s", frac=a / HBM_PEAK_GBS,
+                    intensity=inten, ridge=ridge)
+    a = k["alg_flops"] / t / 1e12
+    return dict(bound="mfma" if mfma else "alu", achieved=a, peak=PEAK_TF[dtype], unit="TFLOP/s",
+                frac=a / PEAK_TF[dtype], intensity=inten, ridge=ridge)
+
+
+def kernel_table(agg, steps, assemble_dtype="fp32"):
+    """Per-class table and the whole-solve roofline of `steps` solves."""
+    K = float(steps)
+    table = {}
+    t_bound = lat = byt = fl = 0.0
+    for name, k in sorted(agg.items(), key=lambda kv: -kv[1]["total_ms"]):
+        c = classify(k, assemble_dtype)
+        row = {"launches_per_step": k["launches"] / K, "ms_per_step": k["total_ms"] / K,
+               "avg_launch_us": 1e3 * k["total_ms"] / k["launches"],
+               "alg_bytes_per_step": k["alg_bytes"] / K, "alg_flops_per_step": k["alg_flops"] / K, **c}
+        table[name] = row
+        if c["bound"] == "latency":
+            lat += row["ms_per_step"]
+            continue
+        dtype = assemble_dtype if name == "assemble" else CLASSES[name][0]
+        byt += row["alg_bytes_per_step"]
+        fl += row["alg_flops_per_step"]
+        t_bound += 1e3 * max(row["alg_bytes_per_step"] / (HBM_PEAK_GBS * 1e9),
+                             row["alg_flops_per_step"] / (PEAK_TF[dtype] * 1e12))
+    return table, {"alg_bytes_per_solve": byt, "alg_flops_per_solve": fl, "t_bound_ms": t_bound,
+                   "latency_chain_ms": lat}
+
+
+def collect_timings(run_timed, steps):
+    """Aggregate gk_kernel_timings over `steps` calls made with GK_TIMING."""
+    from paper_2301_06384_amd import gk
+    agg, stats = {}, None
+    for _ in range(steps):
+        st = run_timed()
+        d = st.as_dict()
+        if stats is not None:
+            for f in ("t_spmm_ms", "t_orth_ms", "t_reorth_ms", "t_phi_ms", "t_asm_ms", "t_total_ms"):
+                d[f] += stats[f]
+        stats = d
+        for k in gk.kernel_timings():
+            if k["launches"] == 0:
+                continue
+            a_ = agg.setdefault(k["name"], dict(name=k["name"], launches=0, total_ms=0.0, alg_bytes=0.0,
+                                                alg_flops=0.0))
+            for f in ("launches", "total_ms", "alg_bytes", "alg_flops"):
+                a_[f] += k[f]
+    return agg, stats
 
 
 def cpu_baseline(L, W, phi, m, s_sample: int):
@@ -176,6 +239,89 @@ def serving_bench(gk, I, n_req: int, seed: int = 0, max_active: int = 8, n_strea
                         "saturated closed-loop throughput"}
 
 
+def stream_copy_gbps(torch, dev, nbytes=1 << 30, reps=5):
+    """Measured device-to-device copy rate (read + write bytes per second):
+    the practical HBM ceiling beside the 8 TB/s datasheet figure."""
+    x = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+    y = torch.empty_like(x)
+    y.copy_(x)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        y.copy_(x)
+    e1.record()
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) * 1e-3 / reps
+    del x, y
+    torch.cuda.empty_cache()
+    return 2.0 * nbytes / t / 1e9
+
+
+def config_leg(torch, gk, I, name, variants, fp64=True):
+    """One full-size configuration: per variant, one timed call in each
+    precision (device-resident inputs and outputs), the mixed-vs-float64
+    error, and the per-kernel split of the mixed classical block Lanczos."""
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    L, W, phi, m = I.workload(name)
+    g = gk.Graph.from_laplacian(L, flags=gk.REORDER)
+    t_gen = time.perf_counter() - t0
+    s = len(W)
+    Wd = torch.as_tensor(W, device=dev)
+    stream = torch.cuda.current_stream()
+    out = {"workload": name, "n": L.n, "nnz": L.nnz, "s": s, "m": m, "graph_build_s": t_gen}
+    free, _ = torch.cuda.mem_get_info()
+    foot64 = gk.request_footprint(L.n, s, m, "cbl", "fp64")
+    out["fp64_footprint_GB"] = foot64 / 1e9
+    out["mixed_footprint_GB"] = gk.request_footprint(L.n, s, m, "cbl", "mixed") / 1e9
+    run64 = fp64 and foot64 < 0.9 * free
+
+    def call(variant, prec, P, K, flags=0):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        _, _, st = gk.krylov_kernel_columns(g, Wd, phi, m, variant, prec, flags=gk.IO_DEVICE | flags,
+                                            out_cols=P, out_kww=K)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1), st
+
+    Pm = torch.empty((s, L.n), dtype=torch.float64, device=dev)
+    Km = torch.empty((s, s), dtype=torch.float64, device=dev)
+    call("cbl", "mixed", Pm, Km)   # warm-up (allocations, code objects)
+    for variant in variants:
+        ms_m, st_m = call(variant, "mixed", Pm, Km)
+        row = {"mixed_ms": ms_m, "mixed_cols_per_s": s / (ms_m * 1e-3), "mixed_reorth_steps": st_m.n_reorth}
+        if run64:
+            P64 = torch.empty_like(Pm)
+            K64 = torch.empty_like(Km)
+            ms_d, _ = call(variant, "fp64", P64, K64)
+            row.update(fp64_ms=ms_d, fp64_cols_per_s=s / (ms_d * 1e-3), speedup_mixed_over_fp64=ms_d / ms_m,
+                       rel_err_mixed_vs_fp64=float(torch.linalg.norm(Pm - P64) / torch.linalg.norm(P64)))
+            del P64, K64
+            torch.cuda.empty_cache()
+        else:
+            row["fp64"] = (f"refused by admission: float64 footprint {foot64 / 1e9:.1f} GB above 0.9 x "
+                           f"free device memory {free / 1e9:.1f} GB")
+        if variant == "cbl":
+            Wi = torch.as_tensor(W, device=dev, dtype=torch.int64)
+            Kh = Km.cpu().numpy()
+            row["kww_min_eig"] = float(np.linalg.eigvalsh(0.5 * (Kh + Kh.T)).min())
+            row["corollary1_gap"] = float(torch.linalg.norm(Pm[:, Wi] - Km) / torch.linalg.norm(Km))
+        out[variant] = row
+        _progress(f"{name} {variant}: {row}")
+    agg, _ = collect_timings(lambda: call("cbl", "mixed", Pm, Km, gk.TIMING)[1], 1)
+    ld = s if s <= 8 else 16 * ((s + 15) // 16)
+    table, whole = kernel_table(agg, 1, "fp32" if ld <= 64 else "fp64")
+    out["cbl_mixed_kernels"] = {k: {f: v[f] for f in ("launches_per_step", "ms_per_step", "avg_launch_us", "bound",
+                                                      "achieved", "unit", "frac")} for k, v in table.items()}
+    out["cbl_mixed_whole_solve"] = whole
+    del Pm, Km
+    g.release()
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -187,6 +333,8 @@ def main():
     ap.add_argument("--reorder", type=int, default=1)
     ap.add_argument("--serving-requests", type=int, default=512,
                     help="requests of the serving leg (0 skips it)")
+    ap.add_argument("--legs", default="ba1m_diffusion,grid128c_spline",
+                    help="full-size configuration legs reported beside the benchmark ('' skips them)")
     ap.add_argument("--counters", action="store_true",
                     help="for hardware-counter runs: one mixed step, then a 1 GiB device-to-device copy of "
                          "known size (calibration of the byte counters); prints no benchmark line")
@@ -213,17 +361,17 @@ def main():
     kout = {p: torch.empty((s, s), dtype=torch.float64, device=dev) for p in ("mixed", "fp64")}
 
     def step(prec, flags=0):
-        gk.krylov_kernel_columns(g, Wd, phi, m, "cbl", prec, flags=gk.IO_DEVICE | flags,
-                                 out_cols=out[prec], out_kww=kout[prec])
+        return gk.krylov_kernel_columns(g, Wd, phi, m, "cbl", prec, flags=gk.IO_DEVICE | flags,
+                                        out_cols=out[prec], out_kww=kout[prec])
 
-    def timed(prec, steps, warmup):
+    def timed(fn, steps, warmup):
         for _ in range(warmup):
-            step(prec)
+            fn()
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
         for _ in range(steps):
-            step(prec)
+            fn()
         e1.record(stream)
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / steps
@@ -241,45 +389,35 @@ def main():
         return
 
     _progress("timing the mixed path")
-    ms_mixed = timed("mixed", args.steps, args.warmup)
+    ms_mixed = timed(lambda: step("mixed"), args.steps, args.warmup)
     _progress(f"mixed {ms_mixed:.2f} ms/step; timing the float64 path")
-    ms_fp64 = timed("fp64", max(2, args.steps // 2), 1)
+    ms_fp64 = timed(lambda: step("fp64"), max(2, args.steps // 2), 1)
     P_m = out["mixed"].cpu().numpy()
     P_d = out["fp64"].cpu().numpy()
     err = float(np.linalg.norm(P_m - P_d) / np.linalg.norm(P_d))
 
+    # the same call with host (pinned) samples and outputs: adds the n x s
+    # float64 device-to-host copy of the columns
+    _progress("timing with host outputs (D2H included)")
+    Wh = np.ascontiguousarray(W)
+    Ph = torch.empty((s, L.n), dtype=torch.float64, pin_memory=True)
+    Kh = torch.empty((s, s), dtype=torch.float64, pin_memory=True)
+    ms_d2h = timed(lambda: gk.krylov_kernel_columns(g, Wh, phi, m, "cbl", "mixed", out_cols=Ph, out_kww=Kh),
+                   args.steps, 1)
+
     _progress("per-kernel timing pass")
     # per-phase and per-kernel device times of the mixed step, from HIP events
     # the library records on the stream the kernels run on (same K steps)
-    agg = {}
-    stats = None
-    for _ in range(args.steps):
-        _, _, st = gk.krylov_kernel_columns(g, Wd, phi, m, "cbl", "mixed", flags=gk.IO_DEVICE | gk.TIMING,
-                                            out_cols=out["mixed"], out_kww=kout["mixed"])
-        d = st.as_dict()
-        if stats is not None:
-            for f in ("t_spmm_ms", "t_orth_ms", "t_reorth_ms", "t_phi_ms", "t_asm_ms", "t_total_ms"):
-                d[f] += stats[f]
-        stats = d
-        for k in gk.kernel_timings():
-            if k["launches"] == 0:
-                continue
-            a_ = agg.setdefault(k["name"], dict(name=k["name"], launches=0, total_ms=0.0, alg_bytes=0.0,
-                                                alg_flops=0.0))
-            for f in ("launches", "total_ms", "alg_bytes", "alg_flops"):
-                a_[f] += k[f]
+    agg, stats = collect_timings(lambda: step("mixed", gk.TIMING)[2], args.steps)
     K = float(args.steps)
-    kernels = {}
-    for name, k in sorted(agg.items(), key=lambda kv: -kv[1]["total_ms"]):
-        bound, peak, unit, ach = _achieved(k)
-        kernels[name] = {"launches_per_step": k["launches"] / K, "ms_per_step": k["total_ms"] / K,
-                         "avg_launch_us": 1e3 * k["total_ms"] / k["launches"], "bound": bound,
-                         "achieved": ach, "unit": unit, "frac": ach / peak}
-    dom = max(agg.values(), key=lambda k: k["total_ms"])
-    bound, peak, unit, ach = _achieved(dom)
-    src = ROOFS.get(dom["name"], (None, None, None, "small.hip"))[3]
-    traffic = _traffic_from_profile(dom["name"], "rgg100k_s64", _kernel_hash([src] if isinstance(src, str) else src))
+    kernels, whole = kernel_table(agg, args.steps, "fp32")
+    copy_gbps = stream_copy_gbps(torch, dev)
+    dom_name = max((k for k in kernels if kernels[k]["bound"] != "latency"), key=lambda k: kernels[k]["ms_per_step"])
+    dom = kernels[dom_name]
+    traffic = _traffic_from_profile(dom_name, "rgg100k_s64", _kernel_hash(_sources(dom_name)))
     value = s / (ms_mixed * 1e-3)
+    whole.update(ms_per_step=ms_mixed, frac=whole["t_bound_ms"] / ms_mixed,
+                 achieved_GBps=whole["alg_bytes_per_solve"] / (ms_mixed * 1e-3) / 1e9)
     res = {
         "metric": "kernel cols/s at 1e-5 rel err vs FP64 path",
         "value": value if err <= 1e-5 else None,
@@ -296,6 +434,8 @@ def main():
         "config": {"workload": "rgg100k_knn8_spline_eps0.01_k2_s64_m40_cbl", "n": L.n, "nnz": L.nnz,
                    "s": s, "m": m, "reorder": bool(args.reorder)},
         "rel_err_vs_fp64_path": err,
+        "value_with_d2h": {"cols_per_s": s / (ms_d2h * 1e-3), "ms_per_step": ms_d2h,
+                           "note": "samples on the host, columns and K_WW copied to pinned host memory"},
         "fp64_path": {"ms_per_step": ms_fp64, "cols_per_s": s / (ms_fp64 * 1e-3),
                       "speedup_mixed_over_fp64": ms_fp64 / ms_mixed},
         "phase_ms": {k: stats[k] / K for k in ("t_spmm_ms", "t_orth_ms", "t_reorth_ms", "t_phi_ms", "t_asm_ms",
@@ -304,16 +444,31 @@ def main():
         "mixed_reorth_steps": stats["n_reorth"],
         "mixed_orth_estimate": stats["orth_est"],
         "mixed_qr2_series_steps": stats["n_qr2_series"],
-        "roofline": {"kernel": dom["name"], "bound": bound, "achieved": ach, "peak": peak, "unit": unit,
-                     "frac": ach / peak, "traffic": traffic,
-                     "avg_launch_ms": dom["total_ms"] / dom["launches"],
-                     "alg_bytes_per_launch": dom["alg_bytes"] / dom["launches"],
-                     "alg_flops_per_launch": dom["alg_flops"] / dom["launches"]},
+        "stream_copy_GBps": copy_gbps,
+        "roofline": {"kernel": dom_name, "bound": dom["bound"], "achieved": dom["achieved"], "peak": dom["peak"],
+                     "unit": dom["unit"], "frac": dom["frac"], "traffic": traffic,
+                     "frac_of_stream_copy": (dom["achieved"] / copy_gbps) if dom["unit"] == "GB/s" else None,
+                     "intensity_flop_per_byte": dom["intensity"], "ridge_flop_per_byte": dom.get("ridge"),
+                     "avg_launch_ms": dom["avg_launch_us"] * 1e-3,
+                     "alg_bytes_per_launch": dom["alg_bytes_per_step"] / dom["launches_per_step"],
+                     "alg_flops_per_launch": dom["alg_flops_per_step"] / dom["launches_per_step"]},
+        "whole_solve_roofline": whole,
         "kernels": kernels,
     }
+    del Ph, Kh
     if args.serving_requests > 0:
         _progress("serving leg")
         res["serving"] = serving_bench(gk, I, args.serving_requests)
+    g.release()
+    del out, kout
+    torch.cuda.empty_cache()
+    legs = [x for x in args.legs.split(",") if x]
+    if legs:
+        res["configs"] = {}
+        for name in legs:
+            _progress(f"configuration leg {name}")
+            variants = ("cbl", "gbl") if name.startswith("ba") else ("cbl",)
+            res["configs"][name] = config_leg(torch, gk, I, name, variants)
     if not args.no_cpu:
         _progress("cpu baseline (oracle)")
         res["cpu_baseline"] = cpu_baseline(L, W, phi, m, args.cpu_sample)

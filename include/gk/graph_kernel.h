@@ -104,9 +104,17 @@ typedef enum {
 #define GK_PHI_EIG       0x4u   /* form phi(H_m) F_1 through the spectral decomposition of H_m even
                                    where an exact banded evaluation exists */
 #define GK_TIMING        0x8u   /* record per-phase device times into gk_stats (adds events) */
-#define GK_NO_REORTH     0x10u  /* GK_MIXED diagnostic: no reorthogonalisation against the stored basis
-                                   (local orthogonalisation only), to study the loss of orthogonality;
-                                   the results lose accuracy */
+#define GK_NO_REORTH     0x10u  /* diagnostic: no reorthogonalisation against the stored basis (local
+                                   orthogonalisation only, Alg. 1 / Alg. 2 as printed), to study the
+                                   loss of orthogonality; the results lose accuracy once Ritz values
+                                   converge */
+#define GK_TWO_PASS      0x20u  /* memory-lean classical block Lanczos in float64 (GK_CBL, GK_FP64 only,
+                                   else GK_EUNSUPPORTED): the basis storage m*n*N of Table 2 is replaced
+                                   by three blocks.  Pass 1 runs Alg. 1 keeping the projected matrix and
+                                   the coefficients of every step; pass 2 regenerates the basis from
+                                   them (bit for bit) and accumulates the columns.  With no stored basis
+                                   there is no reorthogonalisation against older blocks: the result is
+                                   Alg. 1 with local (two-pass Gram-Schmidt) orthogonalisation */
 /* Any other flag bit is rejected with GK_EINVAL. */
 
 /* ------------------------------------------------------------- statistics */
@@ -184,9 +192,10 @@ int kernel_machine_fit_predict(gk_graph* g, const int64_t* samples, int32_t s, c
                                gk_stats* st);
 
 /* Device bytes a request would hold (basis archive, recurrence blocks,
- * projected matrix, workspaces); pure arithmetic, callable without a GPU. */
+ * projected matrix, workspaces) for the call flags `flags` (GK_TWO_PASS
+ * changes the storage); pure arithmetic, callable without a GPU. */
 int gk_request_footprint(int64_t n, int32_t s, int32_t m, int32_t variant, int32_t precision,
-                         uint64_t* bytes);
+                         uint32_t flags, uint64_t* bytes);
 
 /* -------------------------------------------------------------- serving
  * Continuous batching: requests are admitted while a slot is free and the

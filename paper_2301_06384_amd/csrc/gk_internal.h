@@ -37,6 +37,9 @@ struct Error {
 void* dev_alloc(size_t bytes);
 void dev_free(void* p);
 hipStream_t current_stream();
+// Wait for and drop the reuse events of every cached block (before the
+// streams they were recorded on are destroyed).
+void cache_settle();
 
 // A set of device buffers released together (RAII).
 struct Arena {
@@ -110,8 +113,10 @@ void launch_gram(int64_t n, int ld, BlockList A, const double* B, double* C, dou
 // out = beta*in + alpha*(A * C), C (nb*ld x ld); optional float copy of out.
 // upper: C (one block) is upper triangular with zeros stored below the
 // diagonal, and the contraction stops at each column tile's diagonal.
+// tri0 (accounting only): the first coefficient block is triangular.
 void launch_tsgemm(int64_t n, int ld, BlockList A, const double* C, const double* in, double* out,
-                   float* out32, double alpha, double beta, const int* flag, hipStream_t st, bool upper = false);
+                   float* out32, double alpha, double beta, const int* flag, hipStream_t st, bool upper = false,
+                   bool tri0 = false);
 // column-major n x s output P[perm(i), c] = sum_a A[i,a] U[a,c]
 void launch_assemble(int64_t n, int ld, int s, BlockList A, const double* U, int ldu, double* P,
                      const int64_t* perm, hipStream_t st);
@@ -222,8 +227,9 @@ void launch_cheb_diffusion(int m, int s, const double* Hd, const double* Bd, dou
 // of a symmetric sym_ld x sym_ld matrix; out receives the whole matrix
 void launch_reduce_parts(int64_t len, int nparts, const double* part, double* out, const int* flag, hipStream_t st,
                          int sym_ld = 0, int sym_t = 64);
+// piv_rel: LU pivots at or below piv_rel * max|K + gamma I| count as singular
 void launch_small_solve(int s, const double* K, double gamma, const double* y, double* c, double* work,
-                        int* piv, bool spd, int* bad, hipStream_t st);
+                        int* piv, bool spd, double piv_rel, int* bad, hipStream_t st);
 
 // panel.hip -- fused row-panel MFMA passes (ld in {16, 32, 48, 64})
 enum { PM_GRAMV = 0, PM_UPDATE_SELF = 1, PM_APPLY_SELF = 2, PM_APPLY_WRITE = 3 };
@@ -240,7 +246,7 @@ void launch_arch_assemble(int64_t n, int ld, int s, BlockList A, const double* U
 size_t panel_scratch_elems(int64_t n, int ld);
 void launch_panel(int mode, int64_t n, int ld, int nbv, const double* X, double* Xout, float* X32,
                   const double* V0, const double* V1, const double* Cupd, const double* Rm, double* part,
-                  double* Cout, hipStream_t st, double* H = nullptr, int hs = 0);
+                  double* Cout, hipStream_t st, double* H = nullptr, int hs = 0, bool tri0 = false);
 
 // krylov.hip -- one call of the compute entry points
 struct CallArgs {
@@ -260,7 +266,7 @@ struct CallArgs {
   bool fit;
 };
 int run_call(const CallArgs& a, hipStream_t stream);
-uint64_t footprint_bytes(int64_t n, int s, int m, int variant, int precision);
+uint64_t footprint_bytes(int64_t n, int s, int m, int variant, int precision, uint32_t flags = 0);
 void set_thread_stream(hipStream_t s);
 
 // ------------------------------------------------------------- timing

@@ -38,10 +38,26 @@ __global__ void pad_rows_kernel(int nb, int s, int ld, const double* __restrict_
   Up[t] = (r < s) ? U[((int64_t)b * s + r) * s + c] : 0.0;
 }
 
+// out (ld x ld) = block k of U (m*s x s), zero padded: out[r, c] = U[k*s + r, c]
+__global__ void pad_block_kernel(int k, int s, int ld, const double* __restrict__ U, double* __restrict__ out) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ld * ld) return;
+  const int r = t / ld, c = t % ld;
+  out[t] = (r < s && c < s) ? U[((int64_t)k * s + r) * s + c] : 0.0;
+}
+
+// out (ld x s) = [I_s; 0]
+__global__ void ident_rows_kernel(int s, int ld, double* __restrict__ out) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ld * s) return;
+  out[t] = (t / s == t % s) ? 1.0 : 0.0;
+}
+
 // gbl: coef_j = sum_{c<s} cd[j*ld + c]; D[j*ld + c] = coef_j (c < ld);
 // optionally store coef of the last block into alpha_out
 __global__ void frob_coef_kernel(int nb, int s, int ld, const double* __restrict__ cd, double* __restrict__ D,
-                                 double* __restrict__ alpha_out) {
+                                 double* __restrict__ alpha_out, const int* __restrict__ flag) {
+  if (flag && *flag == 0) return;
   const int j = blockIdx.x;
   __shared__ double red[256];
   double v = 0.0;
@@ -90,6 +106,84 @@ __global__ void col_norm_kernel(int s, int ld, const double* __restrict__ cd, do
   if (c < s && beta_out) beta_out[c] = keep;
   if (c < s && resid) resid[c] = b;
   scale[c] = (keep > 0.0) ? 1.0 / keep : 0.0;
+}
+
+// Orthogonality estimate of the scalar-coefficient Lanczos variants (gbl:
+// one recurrence in the Frobenius inner product; sbl: one per column), the
+// omega recurrence of partial reorthogonalisation (Simon 1984) on the
+// tridiagonal coefficients of Alg. 2 / Sec. 3.3:
+//   b_k w_{k+1,j} = b_j w_{k,j+1} + (a_j - a_k) w_{k,j} + b_{j-1} w_{k,j-1}
+//                   - b_{k-1} w_{k-1,j} +- nu,
+// with w_{k,j} = q_k . q_j, a_j = alpha, b_j = beta (coupling q_j, q_{j+1})
+// and b_k the norm of X before it is normalised (from cd, its column sums
+// of squares).  The two local neighbours sit at floor_loc (they are
+// orthogonalised explicitly in float64).  Decision as for the block
+// estimate: project X against the archive when max_j |w_{k+1,j}| > tau, and
+// once more on the next step; after a projection the estimates restart at
+// floor_re.  One workgroup; nw recurrences (1 for gbl, s for sbl).
+__global__ void __launch_bounds__(1024)
+omega_scalar_kernel(int k, int nw, int s, int global, const double* __restrict__ alpha,
+                    const double* __restrict__ beta, const double* __restrict__ cd, double thr, double nu,
+                    double tau, double floor_re, double floor_loc, const double* __restrict__ Okm1,
+                    const double* __restrict__ Ok, double* __restrict__ Ok1, int* __restrict__ fr,
+                    int* __restrict__ forced, double* __restrict__ est_out, int* __restrict__ nre) {
+  __shared__ double bk[1024];
+  __shared__ double red[1024];
+  const int tid = threadIdx.x;
+  if (global) {
+    double v = 0.0;
+    for (int c = tid; c < s; c += 1024) v += cd[c];
+    red[tid] = v;
+    __syncthreads();
+    for (int w = 512; w > 0; w >>= 1) {
+      if (tid < w) red[tid] += red[tid + w];
+      __syncthreads();
+    }
+    if (tid == 0) bk[0] = sqrt(red[0]);
+  } else {
+    for (int c = tid; c < nw; c += 1024) bk[c] = sqrt(cd[c]);
+  }
+  __syncthreads();
+  const int64_t tot = (int64_t)(k - 1 > 0 ? k - 1 : 0) * nw;   // j = 0..k-2
+  double mx = 0.0;
+  for (int64_t q = tid; q < tot; q += 1024) {
+    const int j = (int)(q / nw), c = (int)(q % nw);
+    const double b = bk[c];
+    double w = 0.0;
+    if (b >= thr) {
+      const int64_t jc = (int64_t)j * nw + c;
+      w = beta[jc] * Ok[jc + nw] + (alpha[jc] - alpha[(int64_t)k * nw + c]) * Ok[jc];
+      if (j > 0) w += beta[jc - nw] * Ok[jc - nw];
+      w -= beta[(int64_t)(k - 1) * nw + c] * Okm1[jc];
+      w = (w + copysign(nu, w)) / b;
+    }
+    Ok1[(int64_t)j * nw + c] = w;
+    mx = fmax(mx, fabs(w));
+  }
+  red[tid] = mx;
+  __syncthreads();
+  for (int w = 512; w > 0; w >>= 1) {
+    if (tid < w) red[tid] = fmax(red[tid], red[tid + w]);
+    __syncthreads();
+  }
+  const double e = red[0];
+  const int f = forced[k];
+  const bool go = e > tau || f;
+  if (tid == 0) {
+    fr[k] = go ? 1 : 0;
+    forced[k + 1] = (go && !f) ? 1 : 0;
+    if (go) *nre += 1;
+    *est_out = fmax(*est_out, go ? floor_re : e);
+  }
+  if (go)
+    for (int64_t q = tid; q < tot; q += 1024) {
+      const int c = (int)(q % nw);
+      Ok1[q] = bk[c] >= thr ? floor_re : 0.0;
+    }
+  for (int q = tid; q < 2 * nw; q += 1024) {
+    const int j = k - 1 + q / nw, c = q % nw;
+    if (j >= 0) Ok1[(int64_t)j * nw + c] = bk[c] >= thr ? floor_loc : 0.0;
+  }
 }
 
 // dense symmetric tridiagonal matrices from (alpha, beta): batch b uses
@@ -237,13 +331,13 @@ struct Job {
   double* dscal = nullptr;        // [0] residual norm
   double* poly_dev = nullptr;
   bool mixed() const { return precision == GK_MIXED; }
-  // Full reorthogonalisation every step: always for GK_FP64 and for the
-  // scalar-coefficient variants (gbl, sbl: their projections are column dot
-  // products, memory-bound and cheap), on request for GK_MIXED cbl, and for
-  // GK_MIXED cbl blocks wider than 512 (the orthogonality estimate of partial
-  // reorthogonalisation is built for widths up to 512).
+  // Full reorthogonalisation every step: always for GK_FP64, on request for
+  // GK_MIXED, and for GK_MIXED cbl blocks wider than 512 (the block
+  // orthogonality estimate of partial reorthogonalisation is built for widths
+  // up to 512).  GK_MIXED gbl / sbl use scalar estimates at any width.
   bool full_reorth() const {
-    return !mixed() || (flags & GK_FULL_REORTH) || variant != GK_CBL || !(small_wave_ok(ld) || wide_ok(ld));
+    if (flags & GK_TWO_PASS) return false;   // no stored basis to project against
+    return !mixed() || (flags & GK_FULL_REORTH) || (variant == GK_CBL && !(small_wave_ok(ld) || wide_ok(ld)));
   }
   double thr() const { return 1e-12 * g->lambda_max; }
   // result of the Krylov stage
@@ -339,14 +433,19 @@ static void run_cbl(Job& J) {
   const int64_t blk = n * ld;
   const bool mixed = J.mixed();
   const bool full = J.full_reorth();
-  const bool no_reorth = mixed && (J.flags & GK_NO_REORTH);
+  const bool no_reorth = (J.flags & GK_NO_REORTH) != 0;
+  // memory-lean two-pass form (GK_FP64): pass 1 keeps three blocks and the
+  // coefficients of every step; pass 2 regenerates the basis from them
+  const bool two = (J.flags & GK_TWO_PASS) != 0;
   hipStream_t st = J.st;
   // storage
   double* Vb = nullptr;     // FP64 basis (GK_FP64)
-  double* ring = nullptr;   // 3 FP64 recurrence blocks (GK_MIXED)
+  double* ring = nullptr;   // 3 FP64 recurrence blocks (GK_MIXED, two-pass)
   float* Va = nullptr;      // FP32 archive (GK_MIXED)
-  if (!mixed) Vb = J.ar.get<double>((size_t)m * blk);
-  else {
+  if (!mixed) {
+    if (two) ring = J.ar.get<double>((size_t)3 * blk);
+    else Vb = J.ar.get<double>((size_t)m * blk);
+  } else {
     ring = J.ar.get<double>((size_t)3 * blk);
     Va = J.ar.get<float>((size_t)m * blk);
   }
@@ -372,7 +471,13 @@ static void run_cbl(Job& J) {
   double* Bd = J.ar.get<double>((size_t)m * s * s);
   launch_zero(Bd, (size_t)m * s * s * sizeof(double), st);
 
-  auto V64 = [&](int k) -> double* { return mixed ? ring + (int64_t)(k % 3) * blk : Vb + (int64_t)k * blk; };
+  auto V64 = [&](int k) -> double* {
+    return (mixed || two) ? ring + (int64_t)(k % 3) * blk : Vb + (int64_t)k * blk;
+  };
+  // two-pass: the local coefficients of both Gram-Schmidt passes and the
+  // normalisation R1^-1 R2^-1 of every step, kept for the replay
+  double* Cst = two ? J.ar.get<double>((size_t)m * 4 * l2) : nullptr;
+  double* Rst = two ? J.ar.get<double>((size_t)m * l2) : nullptr;
   // start block Q_1 = E_W (Alg. 1)
   launch_start_block(n, ld, s, J.samp, 1.0, V64(0), mixed ? Va : nullptr, st);
 
@@ -436,20 +541,22 @@ static void run_cbl(Job& J) {
       if (rec && pan) {
         launch_panel(PM_GRAMV, n, ld, 1, X, nullptr, nullptr, Vk, nullptr, nullptr, nullptr, ppart, C + l2, st);
         launch_panel(PM_UPDATE_SELF, n, ld, 2, X, X, nullptr, Vkm1, Vk, C, nullptr, ppart, G, st,
-                     Hd + (int64_t)k * s * s, s);
+                     Hd + (int64_t)k * s * s, s, true);
       } else if (rec) {
         launch_gram(n, ld, BlockList{Vk, blk, 1, false}, X, C + l2, part, nullptr, st);
         launch_store_H(C + l2, ld, s, Hd + (int64_t)k * s * s, st);
-        launch_tsgemm(n, ld, loc, C, X, X, nullptr, -1.0, 1.0, nullptr, st);
+        launch_tsgemm(n, ld, loc, C, X, X, nullptr, -1.0, 1.0, nullptr, st, false, true);
       } else if (pan) {
-        launch_panel(PM_GRAMV, n, ld, nbv, X, nullptr, nullptr, V0, V1, nullptr, nullptr, ppart, C, st);
+        double* Cp = two ? Cst + ((int64_t)k * 2 + pass) * 2 * l2 : C;
+        launch_panel(PM_GRAMV, n, ld, nbv, X, nullptr, nullptr, V0, V1, nullptr, nullptr, ppart, Cp, st);
         // the update pass also stores H_kk = sym(C_k) on the first pass
-        launch_panel(PM_UPDATE_SELF, n, ld, nbv, X, X, nullptr, V0, V1, C, nullptr, ppart, G, st,
+        launch_panel(PM_UPDATE_SELF, n, ld, nbv, X, X, nullptr, V0, V1, Cp, nullptr, ppart, G, st,
                      pass == 0 ? Hd + (int64_t)k * s * s : nullptr, s);
       } else {
-        launch_gram(n, ld, loc, X, C, part, nullptr, st);
-        if (pass == 0) launch_store_H(C + (int64_t)(loc.nb - 1) * l2, ld, s, Hd + (int64_t)k * s * s, st);
-        launch_tsgemm(n, ld, loc, C, X, X, nullptr, -1.0, 1.0, nullptr, st);
+        double* Cp = two ? Cst + ((int64_t)k * 2 + pass) * 2 * l2 : C;
+        launch_gram(n, ld, loc, X, Cp, part, nullptr, st);
+        if (pass == 0) launch_store_H(Cp + (int64_t)(loc.nb - 1) * l2, ld, s, Hd + (int64_t)k * s * s, st);
+        launch_tsgemm(n, ld, loc, Cp, X, X, nullptr, -1.0, 1.0, nullptr, st);
       }
     }
     J.tm.begin(PH_REORTH);
@@ -517,24 +624,25 @@ static void run_cbl(Job& J) {
         BlockList yl{Y, blk, 1, false};
         launch_gram(n, ld, yl, Y, G, part, nullptr, st);
       }
+      double* R12k = two ? Rst + (int64_t)k * l2 : R12i;
       if (wave) {
         // the mixed panel path takes H_{k,k+1} = B_k^T of the next step from C
-        launch_cholqr_reg(G, ld, s, 2, d1, J.thr(), nullptr, nullptr, d2, J.dflags + 1, R1, R1i, R12i,
+        launch_cholqr_reg(G, ld, s, 2, d1, J.thr(), nullptr, nullptr, d2, J.dflags + 1, R1, R1i, R12k,
                           Bd + (int64_t)k * s * s, (mixed && pan) ? C : nullptr, st);
       } else if (widek) {
-        launch_cholqr_wide(G, ld, s, 2, d1, J.thr(), W, nullptr, nullptr, d2, J.dflags + 1, R1, R1i, R12i,
+        launch_cholqr_wide(G, ld, s, 2, d1, J.thr(), W, nullptr, nullptr, d2, J.dflags + 1, R1, R1i, R12k,
                            Bd + (int64_t)k * s * s, mixed ? C : nullptr, st);
       } else {
         launch_cholqr_factor(G, ld, s, 2, d1, J.thr(), W, R2, R2i, d2, J.dflags + 1, st);
-        launch_small_gemm(ld, ld, ld, R1i, ld, false, R2i, ld, false, R12i, ld, 1.0, 0.0, st);
+        launch_small_gemm(ld, ld, ld, R1i, ld, false, R2i, ld, false, R12k, ld, 1.0, 0.0, st);
         launch_small_gemm(s, s, s, R2, ld, false, R1, ld, false, Bd + (int64_t)k * s * s, s, 1.0, 0.0, st);
       }
       float* arch32 = mixed ? Va + (int64_t)(k + 1) * blk : nullptr;
       if (pan)
-        launch_panel(PM_APPLY_WRITE, n, ld, 0, X, V64(k + 1), arch32, nullptr, nullptr, nullptr, R12i, ppart,
+        launch_panel(PM_APPLY_WRITE, n, ld, 0, X, V64(k + 1), arch32, nullptr, nullptr, nullptr, R12k, ppart,
                      nullptr, st);
       else
-        launch_tsgemm(n, ld, xl, R12i, nullptr, V64(k + 1), arch32, 1.0, 0.0, nullptr, st, true);
+        launch_tsgemm(n, ld, xl, R12k, nullptr, V64(k + 1), arch32, 1.0, 0.0, nullptr, st, true);
     } else {
       // ||X_m||_F: residual indicator (the unused H_{m+1,m})
       hipLaunchKernelGGL(trace_sqrt_kernel, dim3(1), dim3(256), 0, st, G, ld, s, J.dscal);
@@ -545,6 +653,51 @@ static void run_cbl(Job& J) {
   double* U = J.ar.get<double>((size_t)m * s * s);
   J.K = J.ar.get<double>((size_t)s * s);
   phi_stage_block(J, Hd, Bd, U, J.K);
+  if (two) {
+    // Pass 2: regenerate Q_1 .. Q_m with the stored coefficients (the same
+    // kernels on the same operands, so the same blocks bit for bit) and
+    // accumulate P = sum_k Q_k U_k (Alg. 1 output) as they appear.
+    J.tm.begin(PH_ASM);
+    double* Pacc = J.ar.get<double>(blk);
+    double* Uk = J.ar.get<double>(l2);
+    launch_zero(Pacc, (size_t)blk * sizeof(double), st);
+    launch_start_block(n, ld, s, J.samp, 1.0, V64(0), nullptr, st);
+    for (int k = 0; k < m; ++k) {
+      double* Vk = V64(k);
+      hipLaunchKernelGGL(pad_block_kernel, dim3(nblk((int64_t)l2)), dim3(256), 0, st, k, s, ld, U, Uk);
+      GK_HIP(hipGetLastError());
+      launch_tsgemm(n, ld, BlockList{Vk, blk, 1, false}, Uk, Pacc, Pacc, nullptr, 1.0, 1.0, nullptr, st);
+      if (k + 1 == m) break;
+      double* Vkm1 = k > 0 ? V64(k - 1) : nullptr;
+      const int nbv = k > 0 ? 2 : 1;
+      BlockList loc = (k > 0) ? BlockList{Vkm1, (int64_t)(Vk - Vkm1), 2, false} : BlockList{Vk, blk, 1, false};
+      const double* V0 = k > 0 ? Vkm1 : Vk;
+      const double* V1 = k > 0 ? Vk : nullptr;
+      launch_spmm(g, false, ld, Vk, nullptr, X, 1.0, 0.0, 0.0, nullptr, 0.0, nullptr, st);
+      for (int pass = 0; pass < 2; ++pass) {
+        const double* Cp = Cst + ((int64_t)k * 2 + pass) * 2 * l2;
+        if (pan)
+          launch_panel(PM_UPDATE_SELF, n, ld, nbv, X, X, nullptr, V0, V1, Cp, nullptr, ppart, G, st, nullptr, s);
+        else
+          launch_tsgemm(n, ld, loc, Cp, X, X, nullptr, -1.0, 1.0, nullptr, st);
+      }
+      const double* R12k = Rst + (int64_t)k * l2;
+      if (pan)
+        launch_panel(PM_APPLY_WRITE, n, ld, 0, X, V64(k + 1), nullptr, nullptr, nullptr, nullptr, R12k, ppart,
+                     nullptr, st);
+      else
+        launch_tsgemm(n, ld, BlockList{X, blk, 1, false}, R12k, nullptr, V64(k + 1), nullptr, 1.0, 0.0, nullptr,
+                      st, true);
+    }
+    // P and the predictor now come from the one accumulated block
+    J.Upad = J.ar.get<double>((size_t)ld * s);
+    hipLaunchKernelGGL(ident_rows_kernel, dim3(nblk((int64_t)ld * s)), dim3(256), 0, st, s, ld, J.Upad);
+    GK_HIP(hipGetLastError());
+    J.arch = BlockList{Pacc, blk, 1, false};
+    J.spd = J.phi.kind != GK_PHI_POLYNOMIAL;
+    J.tm.end();
+    return;
+  }
   J.Upad = J.ar.get<double>((size_t)m * ld * s);
   hipLaunchKernelGGL(pad_rows_kernel, dim3(nblk((int64_t)m * ld * s)), dim3(256), 0, st, m, s, ld, U, J.Upad);
   GK_HIP(hipGetLastError());
@@ -562,7 +715,7 @@ static void run_scalar_lanczos(Job& J, bool global) {
   const int64_t blk = n * ld;
   const bool mixed = J.mixed();
   const bool full = J.full_reorth();
-  const bool no_reorth = mixed && (J.flags & GK_NO_REORTH);
+  const bool no_reorth = (J.flags & GK_NO_REORTH) != 0;
   hipStream_t st = J.st;
   double* Vb = nullptr;
   double* ring = nullptr;
@@ -584,6 +737,26 @@ static void run_scalar_lanczos(Job& J, bool global) {
   launch_zero(beta, (size_t)m * ab * sizeof(double), st);
   double* resid = J.ar.get<double>(ab);
   auto V64 = [&](int k) -> double* { return mixed ? ring + (int64_t)(k % 3) * blk : Vb + (int64_t)k * blk; };
+  // partial reorthogonalisation (GK_MIXED): scalar omega recurrences, one per
+  // Lanczos run (nw = 1 for gbl, s for sbl), ring of three estimate rows
+  const bool pro = mixed && !full && !no_reorth && m > 2;
+  const int nw = global ? 1 : s;
+  double* Om[3] = {nullptr, nullptr, nullptr};
+  int* fr = nullptr;
+  int* forced = nullptr;
+  if (pro) {
+    for (int i = 0; i < 3; ++i) {
+      Om[i] = J.ar.get<double>((size_t)m * nw);
+      launch_zero(Om[i], (size_t)m * nw * sizeof(double), st);
+    }
+    fr = J.ar.get<int>(m);
+    forced = J.ar.get<int>(m + 1);
+    launch_zero(forced, sizeof(int) * (m + 1), st);
+  }
+  // thresholds as for the block estimate of cbl; the rounding term is the
+  // local error of one step, 2 u_64 Lambda
+  const double om_tau = 0x1p-12, om_floor_re = 2e-8, om_floor_loc = 1e-14;
+  const double om_nu = 2.0 * 1.1102230246251565e-16 * g->lambda_max;
   // Q_1 = E_W / sqrt(N) (Alg. 2) or E_W (sequential, each column a unit vector)
   launch_start_block(n, ld, s, J.samp, global ? 1.0 / std::sqrt((double)s) : 1.0, V64(0),
                      mixed ? Va : nullptr, st);
@@ -598,7 +771,7 @@ static void run_scalar_lanczos(Job& J, bool global) {
       launch_coldots(n, ld, loc, X, cd, part, nullptr, st);
       if (global) {
         hipLaunchKernelGGL(frob_coef_kernel, dim3(loc.nb), dim3(256), 0, st, loc.nb, s, ld, cd, D,
-                           pass == 0 ? alpha + k : (double*)nullptr);
+                           pass == 0 ? alpha + k : (double*)nullptr, (const int*)nullptr);
       } else {
         // per-column coefficients are the dots themselves; alpha_k = D of Q_k
         GK_HIP(hipMemcpyAsync(D, cd, sizeof(double) * loc.nb * ld, hipMemcpyDeviceToDevice, st));
@@ -618,7 +791,7 @@ static void run_scalar_lanczos(Job& J, bool global) {
         launch_coldots(n, ld, all, X, cd, part, nullptr, st);
         if (global)
           hipLaunchKernelGGL(frob_coef_kernel, dim3(all.nb), dim3(256), 0, st, all.nb, s, ld, cd, D,
-                             (double*)nullptr);
+                             (double*)nullptr, (const int*)nullptr);
         else
           GK_HIP(hipMemcpyAsync(D, cd, sizeof(double) * all.nb * ld, hipMemcpyDeviceToDevice, st));
         launch_axpy_diag(n, ld, all, D, X, nullptr, st);
@@ -627,6 +800,29 @@ static void run_scalar_lanczos(Job& J, bool global) {
     J.tm.begin(PH_ORTH);
     BlockList xl{X, blk, 1, false};
     launch_coldots(n, ld, xl, X, cd, part, nullptr, st);
+    if (pro && k >= 1 && k + 1 < m) {
+      // partial reorthogonalisation: estimate from the norm of X, then (when
+      // flagged) one projection against the float32 archive blocks 0..k-2 and
+      // the norm again
+      hipLaunchKernelGGL(omega_scalar_kernel, dim3(1), dim3(1024), 0, st, k, nw, s, global ? 1 : 0, alpha, beta, cd,
+                         J.thr(), om_nu, om_tau, om_floor_re, om_floor_loc, Om[(k + 2) % 3], Om[k % 3],
+                         Om[(k + 1) % 3], fr, forced, J.dscal + 1, J.dflags + 3);
+      GK_HIP(hipGetLastError());
+      if (k >= 2) {
+        J.tm.begin(PH_REORTH);
+        const int* fk = fr + k;
+        BlockList arc{Va, blk, k - 1, true};
+        launch_coldots(n, ld, arc, X, cd, part, fk, st);
+        if (global) {
+          hipLaunchKernelGGL(frob_coef_kernel, dim3(arc.nb), dim3(256), 0, st, arc.nb, s, ld, cd, D,
+                             (double*)nullptr, fk);
+          GK_HIP(hipGetLastError());
+        }
+        launch_axpy_diag(n, ld, arc, global ? D : cd, X, fk, st);
+        launch_coldots(n, ld, xl, X, cd, part, fk, st);
+        J.tm.begin(PH_ORTH);
+      }
+    }
     if (global)
       hipLaunchKernelGGL(frob_norm_kernel, dim3(1), dim3(256), 0, st, s, ld, cd, J.thr(),
                          (k + 1 < m) ? beta + k : (double*)nullptr, scale, resid);
@@ -710,17 +906,39 @@ static void run_cheb(Job& J, bool squared) {
 }
 
 // ----------------------------------------------------------- call wrapper
-uint64_t footprint_bytes(int64_t n, int s, int m, int variant, int precision) {
+uint64_t footprint_bytes(int64_t n, int s, int m, int variant, int precision, uint32_t flags) {
   const int ld = block_ld(s);
   const double blk8 = (double)n * ld * 8.0;
   double b = 0;
   const bool mixed = precision == GK_MIXED;
+  if ((flags & GK_TWO_PASS) && variant == GK_CBL && !mixed) {
+    // three recurrence blocks, X, Y, the accumulated columns, the stored
+    // coefficients, the Gram partials of the local passes, the projected
+    // matrix and the phi stage
+    const double l2 = (double)ld * ld * 8.0, ms = (double)m * s;
+    size_t pe = 0;
+    for (int nb = 1; nb <= 2; ++nb) pe = std::max(pe, gram_scratch_elems(n, nb, ld));
+    b = 6 * blk8 + 5.0 * m * l2 + 8.0 * pe + 2 * ms * ms * 8.0 + 8.0 * l2 + 4.0 * m * s * s * 8.0;
+    if (panel_ok(ld)) b += 8.0 * panel_scratch_elems(n, ld);
+    if (small_wave_ok(s)) b += 8.0 * bcr_work_elems(m, s);
+    if (wide_ok(ld)) b += 8.0 * cholqr_wide_scratch_elems(ld);
+    b += (double)n * s * 8.0 + 64.0 * (1 << 20);
+    return (uint64_t)b;
+  }
   if (variant == GK_CHEB || variant == GK_CHEB2) {
     b = blk8 * (variant == GK_CHEB2 ? 5 : 4);
   } else {
     b = mixed ? (3 * blk8 + m * blk8 / 2) : m * blk8;
     b += 2 * blk8;   // X, Y
     const double ms = (double)m * s;
+    if (variant == GK_GBL || variant == GK_SBL) {
+      // column-dot partials, coefficients, tridiagonal coefficients, the
+      // eigendecompositions of the tridiagonal matrices, and the estimates
+      const double nw = variant == GK_GBL ? 1.0 : (double)s;
+      b += 8.0 * coldots_scratch_elems(n, m, ld) + 2.0 * m * ld * 8.0 + 2.0 * m * nw * 8.0 + 3.0 * nw * 8.0;
+      b += nw * (2.0 * m * m + 2.0 * m) * 8.0 + 8.0 * 2.0 * eig_order_elems(m, (int)nw);
+      b += 3.0 * m * nw * 8.0 + 8.0 * m * ld;
+    }
     if (variant == GK_CBL) {
       b += 2 * ms * ms * 8.0 + (double)m * ld * ld * 8.0 + 4.0 * m * s * s * 8.0;
       if (small_wave_ok(s)) b += 8.0 * bcr_work_elems(m, s);   // spline by cyclic reduction
@@ -756,8 +974,11 @@ static void validate_common(const CallArgs& a) {
   GK_REQUIRE(a.samples, GK_EINVAL, "samples is NULL");
   GK_REQUIRE(a.variant >= GK_CBL && a.variant <= GK_CHEB2, GK_EINVAL, "unknown variant");
   GK_REQUIRE(a.precision == GK_FP64 || a.precision == GK_MIXED, GK_EINVAL, "unknown precision");
-  GK_REQUIRE((a.flags & ~(GK_IO_DEVICE | GK_FULL_REORTH | GK_PHI_EIG | GK_TIMING | GK_NO_REORTH)) == 0, GK_EINVAL,
-             "unknown flag bits");
+  GK_REQUIRE((a.flags & ~(GK_IO_DEVICE | GK_FULL_REORTH | GK_PHI_EIG | GK_TIMING | GK_NO_REORTH | GK_TWO_PASS)) == 0,
+             GK_EINVAL, "unknown flag bits");
+  if (a.flags & GK_TWO_PASS)
+    GK_REQUIRE(a.variant == GK_CBL && a.precision == GK_FP64, GK_EUNSUPPORTED,
+               "the two-pass form is built for classical block Lanczos in float64");
   phi_check(*a.phi);
   if (a.fit) {
     GK_REQUIRE(a.y, GK_EINVAL, "y is NULL");
@@ -780,6 +1001,8 @@ static void check_samples_host(const int64_t* h, int s, int64_t n) {
 
 int run_call(const CallArgs& a, hipStream_t stream) {
   validate_common(a);
+  // a status left by the caller's own earlier HIP calls is not this call's
+  (void)hipGetLastError();
   gk_graph* g = a.g;
   const bool dev_io = (a.flags & GK_IO_DEVICE) != 0;
   // samples: validate on the host
@@ -870,7 +1093,10 @@ int run_call(const CallArgs& a, hipStream_t stream) {
     coef = (dev_io && a.coef_out) ? a.coef_out : J.ar.get<double>(s);
     double* wk = J.ar.get<double>((size_t)s * s);
     int* piv = J.ar.get<int>(s);
-    launch_small_solve(s, J.K, a.gamma, y, coef, wk, piv, J.spd, J.dflags + 2, stream);
+    // K gathered from the float32 archive (mixed gbl / sbl) carries float32
+    // rounding; elsewhere it is formed in float64
+    const double piv_rel = (J.arch.f32 && !J.Upad) ? 0x1p-20 : 0x1p-40;
+    launch_small_solve(s, J.K, a.gamma, y, coef, wk, piv, J.spd, piv_rel, J.dflags + 2, stream);
     J.tm.begin(PH_ASM);
     if (a.pred_out) {
       const int nbk = J.arch.nb;
@@ -915,7 +1141,7 @@ int run_call(const CallArgs& a, hipStream_t stream) {
     a.st->resid_norm = hscal[0];
     a.st->phi_method = J.phi_method;
     a.st->footprint_bytes = J.ar.bytes;
-    a.st->n_reorth = (J.variant <= GK_SBL && J.full_reorth()) ? std::max(J.m - 1, 0)
+    a.st->n_reorth = (J.variant <= GK_SBL && J.full_reorth() && !(J.flags & GK_NO_REORTH)) ? std::max(J.m - 1, 0)
                                                                                        : hflags[3];
     a.st->orth_est = hscal[1];
     const double wb = g->unit ? 0.0 : (J.mixed() ? 4.0 : 8.0);
@@ -963,11 +1189,12 @@ int kernel_machine_fit_predict(gk_graph* g, const int64_t* samples, int32_t s, c
   return guarded(a);
 }
 
-int gk_request_footprint(int64_t n, int32_t s, int32_t m, int32_t variant, int32_t precision, uint64_t* bytes) {
+int gk_request_footprint(int64_t n, int32_t s, int32_t m, int32_t variant, int32_t precision, uint32_t flags,
+                         uint64_t* bytes) {
   if (!bytes || n < 1 || s < 1 || s > 1024 || m < 1 || m > 4096 || variant < GK_CBL || variant > GK_CHEB2 ||
       (precision != GK_FP64 && precision != GK_MIXED))
     return GK_EINVAL;
-  *bytes = gk::footprint_bytes(n, s, m, variant, precision);
+  *bytes = gk::footprint_bytes(n, s, m, variant, precision, flags);
   return GK_OK;
 }
 

@@ -449,7 +449,11 @@ void launch_gram(int64_t n, int ld, BlockList A, const double* B, double* C, dou
     hipLaunchKernelGGL(gram_kernel<false>, grid, dim3(256), 0, st, n, ld, A.base, A.stride, A.nb, B,
                        part, rpc, flag);
   GK_HIP(hipGetLastError());
-  kt_end(st, (double)n * ld * ((A.f32 ? 4.0 : 8.0) * A.nb + 8.0), 2.0 * (double)n * ld * ld * A.nb, flag);
+  // method's own work: the Gram of a block with itself reads it once and
+  // forms one triangle
+  const bool self_gram = A.nb == 1 && A.base == (const void*)B;
+  kt_end(st, self_gram ? 8.0 * n * ld : (double)n * ld * ((A.f32 ? 4.0 : 8.0) * A.nb + 8.0),
+         self_gram ? (double)n * ld * (ld + 1) : 2.0 * (double)n * ld * ld * A.nb, flag);
   launch_reduce_parts((int64_t)A.nb * ld * ld, nch, part, C, flag, st, sym ? ld : 0);
 }
 
@@ -545,7 +549,8 @@ tsgemm_kernel(int64_t n, int ld, int ncols, const void* __restrict__ Abase, int6
 }
 
 void launch_tsgemm(int64_t n, int ld, BlockList A, const double* C, const double* in, double* out,
-                   float* out32, double alpha, double beta, const int* flag, hipStream_t st, bool upper) {
+                   float* out32, double alpha, double beta, const int* flag, hipStream_t st, bool upper,
+                   bool tri0) {
   const int up = (upper && A.nb == 1) ? 1 : 0;
   dim3 grid((unsigned)((n + T_TR - 1) / T_TR), (ld + T_TB - 1) / T_TB);
   kt_begin(KC_TSGEMM, st);
@@ -566,8 +571,11 @@ void launch_tsgemm(int64_t n, int ld, BlockList A, const double* C, const double
                        A.stride, A.nb, C, ld, in, out, out32, alpha, beta, (int64_t)ld,
                        (const int64_t*)nullptr, flag);
   GK_HIP(hipGetLastError());
+  // method's own flops: a triangular coefficient block (R^-1, or B_{k-1}^T
+  // of the recurrence) costs n ld (ld + 1)
+  const int ntri = (up || tri0) ? 1 : 0;
   kt_end(st, (double)n * ld * ((A.f32 ? 4.0 : 8.0) * A.nb + (beta != 0.0 ? 16.0 : 8.0) + (out32 ? 4.0 : 0.0)),
-         2.0 * (double)n * ld * ld * A.nb, flag);
+         2.0 * (double)n * ld * ld * (A.nb - ntri) + ntri * (double)n * ld * (ld + 1), flag);
 }
 
 void launch_assemble(int64_t n, int ld, int s, BlockList A, const double* U, int ldu, double* P,

@@ -314,7 +314,7 @@ static void panel_dispatch(PanelMode mode, int nbv, const PanelArgs& a, int grid
 // Launch one panel pass and (when it produces a Gram) reduce it into C.
 void launch_panel(int mode, int64_t n, int ld, int nbv, const double* X, double* Xout, float* X32,
                   const double* V0, const double* V1, const double* Cupd, const double* Rm, double* part,
-                  double* Cout, hipStream_t st, double* H, int hs) {
+                  double* Cout, hipStream_t st, double* H, int hs, bool tri0) {
   PanelArgs a{n, X, Xout, X32, V0, V1, Cupd, Rm, part, H, hs};
   const PanelMode pm = (PanelMode)mode;
   // the apply passes fit three workgroups per CU (their at most one Gram
@@ -327,7 +327,8 @@ void launch_panel(int mode, int64_t n, int ld, int nbv, const double* X, double*
   double kb = 0, kf = 0;
   switch (pm) {
     case PM_GRAMV: kb = blk * (1 + nbv); kf = 2.0 * nl2 * nbv; break;
-    case PM_UPDATE_SELF: kb = blk * (2 + nbv); kf = 2.0 * nl2 * nbv + self; break;
+    // tri0: the first coefficient block is triangular (B_{k-1}^T of the recurrence)
+    case PM_UPDATE_SELF: kb = blk * (2 + nbv); kf = 2.0 * nl2 * (nbv - (tri0 ? 1 : 0)) + (tri0 ? self : 0.0) + self; break;
     case PM_APPLY_SELF: kb = blk; kf = 2.0 * self; break;
     case PM_APPLY_WRITE: kb = blk * (X32 ? 2.5 : 2.0); kf = self; break;
   }

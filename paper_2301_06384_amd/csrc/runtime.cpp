@@ -16,8 +16,9 @@ void set_detail(const std::string& msg) { t_detail = msg; }
 // ------------------------------------------------------------ allocator
 // Default: a size-keyed cache over hipMalloc.  A block returned to the cache
 // carries an event recorded on the stream that last used it; a later
-// allocation on another stream waits for that event before reuse.  Nothing
-// is returned to HIP until process exit (or gk_trim).
+// allocation on another stream waits for that event before reuse.  Cached
+// blocks go back to HIP only when an allocation fails (the cache is released
+// and the allocation retried once) or at process exit.
 namespace {
 struct CachedBlock {
   void* p;
@@ -56,8 +57,11 @@ void* dev_alloc(size_t bytes) {
     c.free_blocks.erase(it);
     c.cached_bytes -= b.bytes;
     if (b.ev) {
-      (void)hipStreamWaitEvent(t_stream, b.ev, 0);
+      if (hipEventQuery(b.ev) != hipSuccess) (void)hipStreamWaitEvent(t_stream, b.ev, 0);
       (void)hipEventDestroy(b.ev);
+      // best-effort calls: do not leave their status behind for the next
+      // launch check (the event's stream may have been destroyed since)
+      (void)hipGetLastError();
     }
     c.live[b.p] = b.bytes;
     c.live_bytes += b.bytes;
@@ -77,6 +81,7 @@ void* dev_alloc(size_t bytes) {
     }
     c.free_blocks.clear();
     c.cached_bytes = 0;
+    (void)hipGetLastError();
     e = hipMalloc(&p, bytes);
     if (e != hipSuccess) {
       (void)hipGetLastError();
@@ -108,11 +113,26 @@ void dev_free(void* p) {
       ev = nullptr;
     }
   }
+  (void)hipGetLastError();
   c.free_blocks.emplace(b, CachedBlock{p, b, ev});
   c.cached_bytes += b;
 }
 
 void set_thread_stream(hipStream_t s) { t_stream = s; }
+
+void cache_settle() {
+  if (g_alloc_fn) return;
+  Cache& c = cache();
+  std::lock_guard<std::mutex> lk(c.mu);
+  for (auto& kv : c.free_blocks) {
+    if (kv.second.ev) {
+      (void)hipEventSynchronize(kv.second.ev);
+      (void)hipEventDestroy(kv.second.ev);
+      kv.second.ev = nullptr;
+    }
+  }
+  (void)hipGetLastError();
+}
 
 // ------------------------------------------------------------ timers
 void PhaseTimer::begin(int phase) {

@@ -185,7 +185,7 @@ int gk_submit(const gk_request* r, uint64_t* ticket) {
   q->samples.assign(r->samples, r->samples + r->s);
   q->y.assign(r->y, r->y + r->s);
   if (r->phi.kind == GK_PHI_POLYNOMIAL) q->poly.assign(r->phi.poly, r->phi.poly + r->phi.poly_len);
-  q->foot = footprint_bytes(r->graph->n, r->s, r->m, r->variant, r->precision);
+  q->foot = footprint_bytes(r->graph->n, r->s, r->m, r->variant, r->precision, r->flags);
   {
     std::lock_guard<std::mutex> lk(S.mu);
     if (!S.running || S.stopping) {
@@ -232,10 +232,9 @@ int gk_serve_stop(void) {
   for (auto& t : S.workers) t.join();
   std::lock_guard<std::mutex> lk(S.mu);
   S.workers.clear();
-  for (auto st : S.streams) {
-    (void)hipStreamSynchronize(st);
-    (void)hipStreamDestroy(st);
-  }
+  for (auto st : S.streams) (void)hipStreamSynchronize(st);
+  cache_settle();
+  for (auto st : S.streams) (void)hipStreamDestroy(st);
   S.streams.clear();
   S.running = false;
   S.stopping = false;

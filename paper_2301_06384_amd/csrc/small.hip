@@ -554,18 +554,47 @@ void launch_banded_spline(int m, int s, const double* Hd, const double* Bd, doub
 
 // ------------------------------------------------------------ s x s solve
 // (K + gamma I) c = y.  spd: Cholesky; otherwise LU with partial pivoting.
-// W is scratch of s*s doubles.  bad = 4 when the system is not solvable.
+// W is scratch of s*s doubles.  bad = 4 when the system is not solvable: a
+// non-finite entry, a Cholesky pivot <= 0, or (LU) a pivot at or below
+// piv_rel * max|K + gamma I|: numerically singular at the accuracy K carries
+// (the caller passes 2^-40 for K formed in float64, a condition number beyond
+// about 1e12; 2^-20 for K gathered from a float32 basis, whose entries carry
+// float32 rounding).  The collocation matrices of gbl, sbl and cheb can be
+// singular or indefinite at small m (Sec. 8.3).
 __global__ void __launch_bounds__(SB)
 small_solve_kernel(int s, const double* __restrict__ K, double gamma, const double* __restrict__ y,
                    double* __restrict__ c, double* __restrict__ W, int* __restrict__ piv, int spd,
-                   int* __restrict__ bad) {
+                   double piv_rel, int* __restrict__ bad) {
   const int tid = threadIdx.x;
   __shared__ int pr_sh;
   __shared__ int fail_sh;
-  for (int q = tid; q < s * s; q += SB) W[q] = K[q] + ((q / s == q % s) ? gamma : 0.0);
-  for (int q = tid; q < s; q += SB) c[q] = y[q];
-  if (tid == 0) fail_sh = 0;
+  __shared__ double amax_sh[SB];
+  double am = 0.0;
+  bool fin = true;
+  for (int q = tid; q < s * s; q += SB) {
+    const double v = K[q] + ((q / s == q % s) ? gamma : 0.0);
+    W[q] = v;
+    fin = fin && isfinite(v);
+    am = fmax(am, fabs(v));
+  }
+  for (int q = tid; q < s; q += SB) {
+    c[q] = y[q];
+    fin = fin && isfinite(y[q]);
+  }
+  amax_sh[tid] = fin ? am : INFINITY;
   __syncthreads();
+  for (int w = SB / 2; w > 0; w >>= 1) {
+    if (tid < w) amax_sh[tid] = fmax(amax_sh[tid], amax_sh[tid + w]);
+    __syncthreads();
+  }
+  const double amax = amax_sh[0];
+  const double piv_floor = piv_rel * amax;
+  if (tid == 0) fail_sh = isfinite(amax) ? 0 : 1;
+  __syncthreads();
+  if (fail_sh) {
+    if (tid == 0) *bad = 4;
+    return;
+  }
   if (spd) {
     // symmetrise (K is symmetric up to rounding) and factor
     for (int q = tid; q < s * s; q += SB) {
@@ -595,7 +624,7 @@ small_solve_kernel(int s, const double* __restrict__ K, double gamma, const doub
             p = r;
           }
         pr_sh = p;
-        if (best == 0.0) fail_sh = 1;
+        if (!(best > piv_floor)) fail_sh = 1;
         piv[j] = p;
       }
       __syncthreads();
@@ -642,9 +671,9 @@ small_solve_kernel(int s, const double* __restrict__ K, double gamma, const doub
 }
 
 void launch_small_solve(int s, const double* K, double gamma, const double* y, double* c, double* work,
-                        int* piv, bool spd, int* bad, hipStream_t st) {
+                        int* piv, bool spd, double piv_rel, int* bad, hipStream_t st) {
   hipLaunchKernelGGL(small_solve_kernel, dim3(1), dim3(SB), 0, st, s, K, gamma, y, c, work, piv, spd ? 1 : 0,
-                     bad);
+                     piv_rel, bad);
   GK_HIP(hipGetLastError());
 }
 

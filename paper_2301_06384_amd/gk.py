@@ -28,7 +28,7 @@ _lib = C.CDLL(LIB_PATH)
 OK, EINVAL, ENOTSYM, ENOTLAP, EDUPSAMPLE, ERANGE, ENOMEM, ENOTSPD, EDEVICE, EUNSUPPORTED, EAGAIN, ESHUTDOWN = (
     0, -1, -2, -3, -4, -5, -6, -7, -8, -9, -10, -11)
 UNIT_WEIGHTS, ASSUME_PSD, REORDER = 0x1, 0x2, 0x4
-IO_DEVICE, FULL_REORTH, PHI_EIG, TIMING, NO_REORTH = 0x1, 0x2, 0x4, 0x8, 0x10
+IO_DEVICE, FULL_REORTH, PHI_EIG, TIMING, NO_REORTH, TWO_PASS = 0x1, 0x2, 0x4, 0x8, 0x10, 0x20
 VARIANTS = {"cbl": 0, "gbl": 1, "sbl": 2, "cheb": 3, "cheb2": 4}
 PRECISIONS = {"fp64": 0, "mixed": 1}
 PHI_KINDS = {"diffusion": 0, "spline": 1, "polynomial": 2}
@@ -87,7 +87,7 @@ _lib.kernel_machine_fit_predict.argtypes = [C.c_void_p, _P, C.c_int32, _P, C.POI
                                             C.c_int32, C.c_int32, C.c_uint32, C.c_double, _P, _P,
                                             C.POINTER(Stats)]
 _lib.kernel_machine_fit_predict.restype = C.c_int
-_lib.gk_request_footprint.argtypes = [C.c_int64, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
+_lib.gk_request_footprint.argtypes = [C.c_int64, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_uint32,
                                       C.POINTER(C.c_uint64)]
 _lib.gk_serve_start.argtypes = [C.c_int32, C.c_uint64, C.c_int32]
 _lib.gk_submit.argtypes = [C.POINTER(Request), C.POINTER(C.c_uint64)]
@@ -217,6 +217,13 @@ def krylov_kernel_columns(graph: Graph, samples, phi: dict, m: int, variant: str
         return out_cols, out_kww, st
     smp = np.ascontiguousarray(samples, dtype=np.int64)
     s = smp.size
+    if out_cols is not None or out_kww is not None:
+        # caller-provided host buffers ((s, n) and (s, s), C-contiguous; e.g.
+        # pinned torch CPU tensors), filled in place
+        rc = _lib.krylov_kernel_columns(graph.handle, _ptr(smp), s, C.byref(p), m, VARIANTS[variant],
+                                        PRECISIONS[precision], flags, _ptr(out_cols), _ptr(out_kww), C.byref(st))
+        _check(rc, "krylov_kernel_columns")
+        return out_cols, out_kww, st
     cols = np.empty((s, graph.n), dtype=np.float64) if want_cols else None   # column-major n x s
     kww = np.empty((s, s), dtype=np.float64) if want_kww else None
     rc = _lib.krylov_kernel_columns(graph.handle, _ptr(smp), s, C.byref(p), m, VARIANTS[variant],
@@ -245,9 +252,10 @@ def kernel_machine_fit_predict(graph: Graph, samples, y, phi: dict, m: int, gamm
     return coef, pred, st
 
 
-def request_footprint(n: int, s: int, m: int, variant: str = "cbl", precision: str = "mixed") -> int:
+def request_footprint(n: int, s: int, m: int, variant: str = "cbl", precision: str = "mixed",
+                      flags: int = 0) -> int:
     b = C.c_uint64()
-    _check(_lib.gk_request_footprint(n, s, m, VARIANTS[variant], PRECISIONS[precision], C.byref(b)),
+    _check(_lib.gk_request_footprint(n, s, m, VARIANTS[variant], PRECISIONS[precision], flags, C.byref(b)),
            "gk_request_footprint")
     return b.value
 

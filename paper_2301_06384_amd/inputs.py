@@ -200,6 +200,42 @@ def permute(L: CSRLaplacian, perm) -> CSRLaplacian:
                         vals=A.data.astype(np.float64), name=L.name + "_perm", unit_weights=L.unit_weights)
 
 
+def normalized_laplacian(L: CSRLaplacian) -> CSRLaplacian:
+    """Normalised Laplacian I - D^(-1/2) A D^(-1/2) of the graph whose
+    combinatorial Laplacian is L = D - A (the operator of the paper's
+    experiments, Sec. 8; the paper does not define it, the symmetric
+    normalisation is taken).  Its off-diagonal entries stay <= 0, but rows do
+    not sum to zero: the library needs GK_ASSUME_PSD for it."""
+    A = L.to_scipy()
+    d = np.asarray(A.diagonal()).ravel()
+    if np.any(d <= 0):
+        raise ValueError("isolated node: the normalised Laplacian needs degree > 0")
+    adj = sp.diags(d) - A
+    r = sp.diags(1.0 / np.sqrt(d))
+    N = (sp.eye(L.n) - r @ adj @ r).tocsr()
+    N.sort_indices()
+    return CSRLaplacian(n=L.n, row_ptr=N.indptr.astype(np.int64), col_idx=N.indices.astype(np.int32),
+                        vals=N.data.astype(np.float64), name=L.name + "_normalized")
+
+
+def planar_radius_standin(n: int = 900, n_edges: int = 7325, seed: int = 0) -> CSRLaplacian:
+    """Synthetic stand-in for the paper's 900-point planar graph (Sec. 8.2;
+    its point set is not available): n points uniform in the unit square,
+    unit-weight edges between the n_edges closest pairs (a radius graph whose
+    radius is the n_edges-th smallest pairwise distance), combinatorial
+    Laplacian."""
+    from scipy.spatial.distance import pdist
+
+    pts = np.random.default_rng(seed).random((n, 2))
+    d = pdist(pts)
+    order = np.argsort(d, kind="stable")[:n_edges]
+    iu, ju = np.triu_indices(n, 1)
+    ei, ej = iu[order], ju[order]
+    o = np.lexsort((ej, ei))
+    return laplacian_from_edges(n, ei[o], ej[o], np.ones(n_edges), name=f"planar{n}_e{n_edges}_s{seed}",
+                                unit_weights=True)
+
+
 def samples(n: int, s: int, seed: int = 0) -> np.ndarray:
     """s distinct sample nodes drawn uniformly without replacement, in draw order."""
     return np.random.default_rng(seed).choice(n, s, replace=False).astype(np.int64)

@@ -47,20 +47,30 @@ def test_ba_wide_block_cbl(ba):
 
 
 def test_ba_wide_block_gbl(ba):
-    # gbl projects against the float32 archive every step; each pass moves X
-    # by the archive's rounding (u32 |X|), which exp(-t H) carries into the
-    # result scaled by about t Lambda.  On this hub graph t Lambda ~ 1e3, so the
-    # mixed gbl path is bounded by u32 t Lambda rather than by 1e-5 (cbl,
-    # above, meets 1e-5 on the same graph).
+    # Alg. 2 at m = 20: mixed against float64 within 1e-5.  At m = 30 the
+    # gbl coefficients are forward-unstable on this hub graph: the float64
+    # path itself, run on the graph in its natural node order instead of the
+    # reordered one (a different summation order, nothing else), moves by
+    # about 6e-5.  There the mixed path is held to that rounding noise of the
+    # float64 path: within twice the natural-vs-reordered float64 difference.
     L, g = ba
     W = I.samples(L.n, 256, 0)
-    t = 0.5
-    phi = dict(kind="diffusion", t=t)
-    P64, K64, _ = gk.krylov_kernel_columns(g, W, phi, 30, "gbl", "fp64")
-    Pm, Km, _ = gk.krylov_kernel_columns(g, W, phi, 30, "gbl", "mixed")
-    lam = g.info()["lambda_max"]
+    phi = dict(kind="diffusion", t=0.5)
+    P64, K64, _ = gk.krylov_kernel_columns(g, W, phi, 20, "gbl", "fp64")
+    Pm, Km, _ = gk.krylov_kernel_columns(g, W, phi, 20, "gbl", "mixed")
+    print(f"gbl BA200k m=20 mixed vs fp64: {rel(Pm, P64):.3e}")
+    assert rel(Pm, P64) < 1e-5 and rel(Km, K64) < 1e-5
+    P64, _, _ = gk.krylov_kernel_columns(g, W, phi, 30, "gbl", "fp64")
+    Pm, _, sm = gk.krylov_kernel_columns(g, W, phi, 30, "gbl", "mixed")
+    g0 = gk.Graph.from_laplacian(L)
+    P64n, _, _ = gk.krylov_kernel_columns(g0, W, phi, 30, "gbl", "fp64")
+    g0.release()
     assert np.all(np.isfinite(P64))
-    assert rel(Pm, P64) < 2.0 ** -24 * t * lam
+    noise, err = rel(P64n, P64), rel(Pm, P64)
+    print(f"gbl BA200k m=30 mixed vs fp64 {err:.3e}; fp64 natural vs reordered node order {noise:.3e}; "
+          f"archive projections {sm.n_reorth} of 28")
+    assert err < max(1e-5, 2.0 * noise)
+    assert sm.n_reorth < 28
 
 
 def test_grid3d_s512_exhaustion_matches_dense():

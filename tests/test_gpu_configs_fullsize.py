@@ -3,13 +3,16 @@
 * Barabasi-Albert graph, N = 1,000,000, 4 edges per new node, unit weights,
   diffusion exp(-0.5 L), s = 256, m = 30: classical block Lanczos in both
   precisions (mixed against float64 to 1e-5), global block Lanczos (mixed
-  against float64 within u32 t Lambda, the bound of its float32 archive
-  projection), K_WW symmetric positive definite (Theorem 3.1) and the
+  against float64 to 1e-5 at m = 20; at m = 30, where float64 runs that
+  differ only in summation order disagree by ~2e-5, within twice that
+  float64 noise), K_WW symmetric positive definite (Theorem 3.1) and the
   Corollary 1 identity P[W, :] = K_WW.
 * 3-D grid 128^3 (N = 2,097,152) with weights U[0.5, 1.5], spline
   (0.05 I + L)^(-1), s = 512, m = 30: the mixed request is admitted (its
-  Table 2 storage fits the device, the float64 one does not) and runs; K_WW
-  is symmetric positive definite and matches the sampled rows of the columns.
+  Table 2 storage fits the device, the one-pass float64 one does not) and
+  runs; K_WW is symmetric positive definite and matches the sampled rows of
+  the columns; the float64 request in the two-pass form is admitted, runs and
+  agrees with the mixed one to 1e-5.
 
 No oracle holds these sizes; the checks are the ones that hold at any size.
 Outputs stay on the device (GK_IO_DEVICE) and are compared there.
@@ -33,10 +36,11 @@ def rel(a, b):
     return float(torch.linalg.norm(a - b) / torch.linalg.norm(b))
 
 
-def run(g, Wd, n, s, phi, m, variant, prec):
+def run(g, Wd, n, s, phi, m, variant, prec, flags=0):
     P = torch.empty((s, n), dtype=torch.float64, device=DEV)   # column j of the n x s block is row j
     K = torch.empty((s, s), dtype=torch.float64, device=DEV)
-    _, _, st = gk.krylov_kernel_columns(g, Wd, phi, m, variant, prec, flags=gk.IO_DEVICE, out_cols=P, out_kww=K)
+    _, _, st = gk.krylov_kernel_columns(g, Wd, phi, m, variant, prec, flags=gk.IO_DEVICE | flags, out_cols=P,
+                                        out_kww=K)
     torch.cuda.synchronize()
     return P, K, st
 
@@ -68,9 +72,19 @@ def test_c3_ba1m_s256_full_size():
     torch.cuda.empty_cache()
     Pg64, _, _ = run(g, Wd, L.n, s, phi, m, "gbl", "fp64")
     Pgm, _, _ = run(g, Wd, L.n, s, phi, m, "gbl", "mixed")
-    lam = g.info()["lambda_max"]
     assert bool(torch.isfinite(Pg64).all())
-    assert rel(Pgm, Pg64) < 2.0 ** -24 * t * lam
+    # gbl at m = 30 is forward-unstable here: the float64 path on the natural
+    # node order (another summation order) is the noise floor of the check
+    g0 = gk.Graph.from_laplacian(L)
+    Pg64n, _, _ = run(g0, Wd, L.n, s, phi, m, "gbl", "fp64")
+    g0.release()
+    noise, err = rel(Pg64n, Pg64), rel(Pgm, Pg64)
+    print(f"C3 gbl mixed vs fp64 {err:.3e}; fp64 natural vs reordered {noise:.3e}")
+    assert err < max(1e-5, 2.0 * noise)
+    del Pg64n
+    Pg64, _, _ = run(g, Wd, L.n, s, phi, 20, "gbl", "fp64")
+    Pgm, _, _ = run(g, Wd, L.n, s, phi, 20, "gbl", "mixed")
+    assert rel(Pgm, Pg64) < 1e-5
 
 
 def test_c5_grid128_s512_mixed_full_size():
@@ -90,3 +104,12 @@ def test_c5_grid128_s512_mixed_full_size():
     assert st.n_reorth < m - 1
     check_kww(K)
     assert rel(P[:, Wi], K) < 1e-5
+    # the float64 request in the memory-lean two-pass form (Table 2 storage of
+    # three blocks instead of m) is admitted and runs
+    assert gk.request_footprint(L.n, s, m, "cbl", "fp64", gk.TWO_PASS) < 0.9 * free
+    P2, K2, st2 = run(g, Wd, L.n, s, phi, m, "cbl", "fp64", gk.TWO_PASS)
+    assert bool(torch.isfinite(P2).all())
+    check_kww(K2)
+    err = rel(P, P2)
+    print(f"C5 mixed vs float64 two-pass: {err:.3e}")
+    assert err < 1e-5 and rel(K, K2) < 1e-5

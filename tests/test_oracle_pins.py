@@ -421,3 +421,173 @@ def test_basis_orthonormal_after_convergence(variant):
         Qb = krylov.gbl(L, W, dict(kind="diffusion", t=1.0), 60)["Q_blocks"]
         G = np.array([[np.sum(a * b) for b in Qb] for a in Qb])   # Frobenius Gram
     assert np.max(np.abs(G - np.eye(G.shape[0]))) < 1e-13
+
+
+def _lobatto_interpolant(f, deg, Lam):
+    """The degree-deg polynomial through (lam_j, f(lam_j)) on the shifted
+    Chebyshev-Lobatto grid, by barycentric Lagrange interpolation (scipy),
+    independent of the oracle's series coefficients and recurrence."""
+    from scipy.interpolate import BarycentricInterpolator
+    x = 0.5 * Lam * (1.0 - np.cos(np.pi * np.arange(deg + 1) / deg))
+    return BarycentricInterpolator(x, f(x))
+
+
+@pytest.mark.parametrize("spec", [dict(kind="diffusion", t=1.3), dict(kind="spline", eps=0.2, k=2.0)])
+def test_squared_chebyshev_spectral_form(spec):
+    # Sec. 3.4.1: cheb2 is q(L)^2 E_W with q the degree floor(m/2) Lobatto
+    # interpolant of sqrt(phi).  On the spectral decomposition L = U diag(lam) U^T
+    # this is U diag(q(lam)^2) U[W,:]^T.  Squaring an interpolant of phi
+    # itself, or taking degree m, both fail this.
+    L = I.random_weighted(45, 0.12, seed=21).to_scipy()
+    W = [2, 17, 30, 44]
+    Lam = float(np.max(np.asarray(abs(L).sum(axis=1)).ravel()))
+    lam, U = np.linalg.eigh(L.toarray())
+    f = ophi.make(spec)
+    for m in [4, 7, 12, 21]:
+        q = _lobatto_interpolant(lambda x: np.sqrt(f(x)), max(m // 2, 1), Lam)
+        ref = U @ ((q(lam) ** 2)[:, None] * U[W, :].T)
+        P = cheb.cheb2(L, W, spec, m)["P"]
+        assert np.linalg.norm(P - ref) / np.linalg.norm(ref) < 1e-11, m
+        # the plain method's own spectral form, for contrast: degree m, phi itself
+        p = _lobatto_interpolant(f, m, Lam)
+        ref1 = U @ (p(lam)[:, None] * U[W, :].T)
+        P1 = cheb.cheb(L, W, spec, m)["P"]
+        assert np.linalg.norm(P1 - ref1) / np.linalg.norm(ref1) < 1e-11, m
+
+
+def test_squared_chebyshev_converges_to_dense():
+    # Sec. 3.4.1 with Sec. 4: q_m(L)^2 E_W -> phi(L) E_W as m grows, for phi
+    # analytic on [0, Lambda] (geometric decay of the error).
+    L = I.grid((9, 8)).to_scipy()
+    W = [0, 20, 47, 71]
+    spec = dict(kind="diffusion", t=0.8)
+    ref = dense.phi_columns(L, W, spec)
+    errs = [krylov.rel_fro(cheb.cheb2(L, W, spec, m)["P"], ref) for m in (6, 12, 24, 48)]
+    assert all(b < a for a, b in zip(errs, errs[1:])), errs
+    assert errs[-1] < 1e-12, errs
+
+
+def test_predictor_bound_theorem_5_1():
+    # Theorem 5.1: ||y - y^(kr)||_2 <= ||y|| / (phi_min + gamma N) *
+    # (1 + phi_max / (phi_min + gamma N)) * ||phi(L) E_W - p(L) E_W||_2,
+    # asymptotically in m, for all five methods.  Checked against the measured
+    # predictor error of the Krylov machine against the exact one; the ratio
+    # error / kernel error stays bounded as m grows (first-order behaviour).
+    L = I.grid((12, 12)).to_scipy()
+    W = [3, 40, 77, 101, 130, 55]
+    y = np.array([1.0, -1.0, 0.5, 2.0, -0.3, 1.2])
+    Lam = krylov.gershgorin_bound(L)
+    for spec in (dict(kind="diffusion", t=0.5), dict(kind="spline", eps=0.5, k=1.0)):
+        f = ophi.make(spec)
+        fv = f(np.linspace(0.0, Lam, 4001))
+        fmin, fmax = float(fv.min()), float(fv.max())
+        for gamma in (0.0, 0.1):
+            _, y0, P0, _ = dense.fit_predict(L, W, y, spec, gamma)
+            for var in ("cbl", "gbl", "sbl", "cheb", "cheb2"):
+                ratios = []
+                for m in (6, 8, 10):
+                    if var in ("cheb", "cheb2"):
+                        r = (cheb.cheb if var == "cheb" else cheb.cheb2)(L, W, spec, m)
+                        P, K = r["P"], r["Kww_gathered"]
+                        yk = P @ np.linalg.solve(K + gamma * np.eye(len(W)), y)
+                    else:
+                        _, yk, _ = krylov.fit_predict(L, W, y, spec, m, gamma, var)
+                        P = getattr(krylov, var)(L, W, spec, m)["P"]
+                    ke = np.linalg.norm(P0 - P, 2)
+                    err = np.linalg.norm(y0 - yk)
+                    assert err <= bounds.predictor_bound(np.linalg.norm(y), fmin, fmax, gamma, ke), (var, m)
+                    ratios.append(err / ke)
+                assert max(ratios) < 3.0 * min(ratios), (var, ratios)
+
+
+def _complete_graph(n):
+    i, j = np.triu_indices(n, 1)
+    return I.laplacian_from_edges(n, i, j, np.ones(i.size), name=f"k{n}", unit_weights=True)
+
+
+def test_breakdown_on_complete_graph():
+    # Alg. 2 breakdown (h_{k+1,k} = 0): on the complete graph L = nI - J, so
+    # L^2 E_W = n L E_W and the Krylov space of E_W has two (block) dimensions.
+    # gbl stops after two vectors and is exact there; sbl breaks down per
+    # column; cbl deflates all but one direction of its second block (Sec. 3.1
+    # assumes H_{k+1,k} invertible; the reading keeps zero columns).
+    L = _complete_graph(6).to_scipy()
+    W = [0, 2, 5]
+    for spec in (dict(kind="diffusion", t=0.3), dict(kind="spline", eps=0.1, k=2.0)):
+        ref = dense.phi_columns(L, W, spec)
+        r = krylov.gbl(L, W, spec, 4)
+        assert r["m_eff"] == 2
+        assert krylov.rel_fro(r["P"], ref) < 1e-13
+        assert krylov.rel_fro(krylov.sbl(L, W, spec, 4)["P"], ref) < 1e-13
+        rc = krylov.cbl(L, W, spec, 4)
+        assert rc["n_deflated"] >= len(W) - 1
+        assert krylov.rel_fro(rc["P"], ref) < 1e-13
+
+
+# ------------------------------------------------ the paper's experiments
+
+def test_paper_sec81_lanczos_beats_chebyshev_on_path():
+    # Sec. 8.1: path graph with 201 nodes, normalised Laplacian, one central
+    # sample v_101; for every m the Lanczos approximant of phi(L) e_w has a
+    # smaller uniform error than the Chebyshev one, for exp(-200 L) and
+    # (L + 0.001 I)^(-2).  At s = 1 the three Lanczos variants coincide.
+    P = I.normalized_laplacian(I.path(201)).to_scipy()
+    for spec in (dict(kind="diffusion", t=200.0), dict(kind="spline", eps=0.001, k=2.0)):
+        ref = dense.phi_columns(P, [100], spec)
+        for m in (5, 10, 20, 40, 60):
+            e_l = np.max(np.abs(krylov.cbl(P, [100], spec, m)["P"] - ref))
+            e_c = np.max(np.abs(cheb.cheb(P, [100], spec, m)["P"] - ref))
+            assert e_l < e_c, (spec, m, e_l, e_c)
+            for v in ("gbl", "sbl"):
+                assert krylov.rel_fro(getattr(krylov, v)(P, [100], spec, m)["P"],
+                                      krylov.cbl(P, [100], spec, m)["P"]) < 1e-10
+
+
+def _sec82_problem():
+    N = I.normalized_laplacian(I.planar_radius_standin()).to_scipy()
+    W = I.samples(900, 20, 1)
+    y = (np.random.default_rng(3).random(20) < 0.5).astype(float)   # binary labels
+    return N, W, y
+
+
+def _predictor_errors(N, W, y, spec, m):
+    _, y0, _, _ = dense.fit_predict(N, W, y, spec, 0.0)
+    errs = {}
+    for v in ("cbl", "gbl", "sbl"):
+        _, yk, _ = krylov.fit_predict(N, W, y, spec, m, 0.0, v)
+        errs[v] = np.max(np.abs(yk - y0))
+    for v, f in (("cheb", cheb.cheb), ("cheb2", cheb.cheb2)):
+        r = f(N, W, spec, m)
+        errs[v] = np.max(np.abs(r["P"] @ np.linalg.solve(r["Kww_gathered"], y) - y0))
+    return errs
+
+
+def test_paper_sec82_convergence_ranking():
+    # Sec. 8.2 on the synthetic stand-in of the 900-point planar graph
+    # (normalised Laplacian, N = 20 samples, binary labels, gamma = 0): the
+    # uniform error of the interpolant falls fastest for cbl, then gbl and
+    # sbl, then the two Chebyshev methods.
+    N, W, y = _sec82_problem()
+    for spec in (dict(kind="diffusion", t=20.0), dict(kind="spline", eps=0.05, k=2.0)):
+        for m in (12, 16, 24):
+            e = _predictor_errors(N, W, y, spec, m)
+            assert e["cbl"] < min(e["gbl"], e["sbl"]), (spec, m, e)
+            assert max(e["gbl"], e["sbl"]) < min(e["cheb"], e["cheb2"]), (spec, m, e)
+
+
+def test_paper_sec83_collocation_eigenvalues():
+    # Sec. 8.3: N = 40, exp(-20 L), m = 6: E_W^T p(L) E_W has positive
+    # eigenvalues for cbl and cheb2, negative ones for gbl and cheb, and
+    # complex ones for sbl.
+    N = I.normalized_laplacian(I.planar_radius_standin()).to_scipy()
+    W = I.samples(900, 40, 1)
+    spec = dict(kind="diffusion", t=20.0)
+    ev = {}
+    ev["cbl"] = np.linalg.eigvals(krylov.cbl(N, W, spec, 6)["Kww"])
+    for v in ("gbl", "sbl"):
+        ev[v] = np.linalg.eigvals(getattr(krylov, v)(N, W, spec, 6)["Kww_gathered"])
+    ev["cheb"] = np.linalg.eigvals(cheb.cheb(N, W, spec, 6)["Kww_gathered"])
+    ev["cheb2"] = np.linalg.eigvals(cheb.cheb2(N, W, spec, 6)["Kww_gathered"])
+    assert ev["cbl"].real.min() > 0 and ev["cheb2"].real.min() > 0
+    assert ev["gbl"].real.min() < 0 and ev["cheb"].real.min() < 0
+    assert np.abs(ev["sbl"].imag).max() > 0
