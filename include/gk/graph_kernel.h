@@ -179,6 +179,25 @@ int krylov_kernel_columns(gk_graph* g, const int64_t* samples, int32_t s, const 
                           int32_t m, int32_t variant, int32_t precision, uint32_t flags,
                           double* cols_out, double* kww_out, gk_stats* st);
 
+/* krylov_kernel_columns without any device allocation, for callers that
+ * cannot allocate (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments and results as
+ * krylov_kernel_columns, with GK_IO_DEVICE required: samples, cols_out and
+ * kww_out are device pointers.  Every work buffer of the call is carved from
+ * a static device array of GK_STATIC_SCRATCH_BYTES per GPU, held from the
+ * first call on that GPU until the process ends; the call makes no
+ * hipMalloc / hipFree and no allocator-hook call.  A request whose buffers
+ * exceed the array fails with GK_ENOMEM (gk_request_footprint minus the
+ * n*s*8 output staging and a 64 MiB allowance gives the estimate checked
+ * first).  All calls on one GPU share its array: calls that overlap in time
+ * on the same GPU (other threads, other streams) race and must be
+ * serialised by the caller.  Errors as krylov_kernel_columns, plus
+ * GK_EINVAL without GK_IO_DEVICE. */
+#define GK_STATIC_SCRATCH_BYTES (128u << 20)
+int krylov_kernel_columns_noalloc(gk_graph* g, const int64_t* samples, int32_t s, const gk_phi* phi,
+                                  int32_t m, int32_t variant, int32_t precision, uint32_t flags,
+                                  double* cols_out, double* kww_out, gk_stats* st);
+
 /* Kernel RLS machine (Sec. 2.3; Alg. 3 for cbl, Sec. 5 system for the others).
  *   y         s labels at the samples (host or device)
  *   gamma     total diagonal shift >= 0 (the paper's gamma * N)

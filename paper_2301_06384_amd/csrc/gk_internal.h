@@ -41,14 +41,27 @@ hipStream_t current_stream();
 // streams they were recorded on are destroyed).
 void cache_settle();
 
-// A set of device buffers released together (RAII).
+// A set of device buffers released together (RAII).  With `pool` set, the
+// buffers are carved in order out of that caller-provided device range
+// (pool_cap bytes) instead of allocated, and a request beyond it fails with
+// GK_ENOMEM.
 struct Arena {
   std::vector<void*> ptrs;
   uint64_t bytes = 0;
+  char* pool = nullptr;
+  size_t pool_cap = 0;
   template <typename T>
   T* get(size_t count) {
     size_t b = ((count * sizeof(T) + 255) / 256) * 256;
     if (b == 0) b = 256;
+    if (pool) {
+      if (bytes + b > pool_cap)
+        throw Error{GK_ENOMEM, "request needs more than the " + std::to_string(pool_cap) +
+                                   " bytes of static device scratch"};
+      void* q = pool + bytes;
+      bytes += b;
+      return static_cast<T*>(q);
+    }
     void* p = dev_alloc(b);
     if (!p) throw Error{GK_ENOMEM, "device allocation of " + std::to_string(b) + " bytes failed"};
     ptrs.push_back(p);
@@ -264,6 +277,8 @@ struct CallArgs {
   double* pred_out;
   gk_stats* st;
   bool fit;
+  void* pool = nullptr;     // device range all buffers are carved from (no allocation), or null
+  size_t pool_cap = 0;
 };
 int run_call(const CallArgs& a, hipStream_t stream);
 uint64_t footprint_bytes(int64_t n, int s, int m, int variant, int precision, uint32_t flags = 0);

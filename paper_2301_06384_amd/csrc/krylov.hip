@@ -1013,6 +1013,8 @@ int run_call(const CallArgs& a, hipStream_t stream) {
   GK_HIP(hipSetDevice(g->device));
 
   Job J;
+  J.ar.pool = static_cast<char*>(a.pool);
+  J.ar.pool_cap = a.pool_cap;
   J.g = g;
   J.s = a.s;
   J.ld = block_ld(a.s);
@@ -1157,6 +1159,40 @@ int run_call(const CallArgs& a, hipStream_t stream) {
 
 }  // namespace gk
 
+// ------------------------------------------------- static scratch (no-alloc)
+namespace gk {
+namespace {
+// Device scratch of the allocation-free entry point: one copy per GPU, held
+// until the process ends.  Host code never passes `scratch` itself to a
+// kernel or copy (on the host the name is a stand-in, not a device address);
+// it uses the address hipGetSymbolAddress returns for the current device.
+__device__ __align__(256) unsigned char scratch[GK_STATIC_SCRATCH_BYTES];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Address of `scratch` on device `dev`, looked up once per device with that
+// device current.
+void* scratch_on(int dev) {
+  GK_REQUIRE(dev >= 0 && dev < kMaxDevices, GK_EDEVICE, "device ordinal out of range");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    int cur = 0;
+    GK_HIP(hipGetDevice(&cur));
+    GK_HIP(hipSetDevice(dev));
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    const hipError_t e2 = hipSetDevice(cur);
+    GK_REQUIRE(e == hipSuccess && ptr, GK_EDEVICE,
+               std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    GK_HIP(e2);
+    g_scratch_ptr[dev] = ptr;
+  }
+  return g_scratch_ptr[dev];
+}
+}  // namespace
+}  // namespace gk
+
 // ------------------------------------------------------------------ ABI
 extern "C" {
 
@@ -1178,6 +1214,35 @@ int krylov_kernel_columns(gk_graph* g, const int64_t* samples, int32_t s, const 
   gk::CallArgs a{g, samples, s, phi, m, variant, precision, flags, nullptr, 0.0, cols_out, kww_out,
                  nullptr, nullptr, st, false};
   return guarded(a);
+}
+
+int krylov_kernel_columns_noalloc(gk_graph* g, const int64_t* samples, int32_t s, const gk_phi* phi, int32_t m,
+                                  int32_t variant, int32_t precision, uint32_t flags, double* cols_out,
+                                  double* kww_out, gk_stats* st) {
+  try {
+    GK_REQUIRE(g, GK_EINVAL, "graph is NULL");
+    GK_REQUIRE((flags & GK_IO_DEVICE) != 0, GK_EINVAL,
+               "krylov_kernel_columns_noalloc needs GK_IO_DEVICE (device samples and outputs)");
+    GK_REQUIRE(s >= 1 && s <= 1024 && m >= 1 && m <= 4096, GK_EINVAL, "s or m out of range");
+    GK_REQUIRE(variant >= GK_CBL && variant <= GK_CHEB2 && (precision == GK_FP64 || precision == GK_MIXED),
+               GK_EINVAL, "unknown variant or precision");
+    // The request's own buffers (footprint without the host staging of the
+    // columns and the general small-buffer allowance) must fit the scratch;
+    // the carving itself enforces the exact limit.
+    const double need = (double)gk::footprint_bytes(g->n, s, m, variant, precision, flags) -
+                        (double)g->n * s * 8.0 - 64.0 * (1 << 20);
+    GK_REQUIRE(need <= (double)GK_STATIC_SCRATCH_BYTES, GK_ENOMEM,
+               "request needs about " + std::to_string((uint64_t)need) + " bytes, more than the " +
+                   std::to_string((uint64_t)GK_STATIC_SCRATCH_BYTES) + " bytes of static device scratch");
+    gk::CallArgs a{g, samples, s, phi, m, variant, precision, flags, nullptr, 0.0, cols_out, kww_out,
+                   nullptr, nullptr, st, false};
+    a.pool = gk::scratch_on(g->device);
+    a.pool_cap = GK_STATIC_SCRATCH_BYTES;
+    return guarded(a);
+  } catch (const gk::Error& e) {
+    gk::set_detail(e.msg);
+    return e.code;
+  }
 }
 
 int kernel_machine_fit_predict(gk_graph* g, const int64_t* samples, int32_t s, const double* y,

@@ -83,6 +83,8 @@ _lib.gk_graph_info.argtypes = [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_i
 _lib.krylov_kernel_columns.argtypes = [C.c_void_p, _P, C.c_int32, C.POINTER(Phi), C.c_int32, C.c_int32,
                                        C.c_int32, C.c_uint32, _P, _P, C.POINTER(Stats)]
 _lib.krylov_kernel_columns.restype = C.c_int
+_lib.krylov_kernel_columns_noalloc.argtypes = _lib.krylov_kernel_columns.argtypes
+_lib.krylov_kernel_columns_noalloc.restype = C.c_int
 _lib.kernel_machine_fit_predict.argtypes = [C.c_void_p, _P, C.c_int32, _P, C.POINTER(Phi), C.c_int32,
                                             C.c_int32, C.c_int32, C.c_uint32, C.c_double, _P, _P,
                                             C.POINTER(Stats)]
@@ -111,7 +113,7 @@ _lib.gk_kernel_timings.argtypes = [C.POINTER(KernelTiming), C.c_int32, C.POINTER
 _lib.gk_kernel_timings.restype = C.c_int
 
 EXPORTED = ["graph_kernel_init", "graph_kernel_release", "gk_graph_info", "krylov_kernel_columns",
-            "kernel_machine_fit_predict", "gk_request_footprint", "gk_serve_start", "gk_submit", "gk_poll",
+            "krylov_kernel_columns_noalloc", "kernel_machine_fit_predict", "gk_request_footprint", "gk_serve_start", "gk_submit", "gk_poll",
             "gk_serve_stop", "gk_strerror", "gk_last_error_detail", "gk_set_allocator", "gk_set_stream",
             "gk_version", "gk_kernel_timings"]
 
@@ -231,6 +233,25 @@ def krylov_kernel_columns(graph: Graph, samples, phi: dict, m: int, variant: str
     _check(rc, "krylov_kernel_columns")
     del keep
     return (None if cols is None else cols.T), (None if kww is None else kww.T), st
+
+
+def krylov_kernel_columns_noalloc(graph: Graph, samples, phi: dict, m: int, variant: str, precision: str,
+                                  out_cols, out_kww, flags: int = 0):
+    """krylov_kernel_columns on the library's static device scratch (no device
+    allocation).  samples, out_cols ((s, n) tensor, i.e. column-major n x s) and
+    out_kww are device tensors; returns (out_cols, out_kww, stats)."""
+    st = Stats()
+    p, keep = make_phi(phi)
+    s = int(samples.numel())
+    rc = _lib.krylov_kernel_columns_noalloc(graph.handle, _ptr(samples), s, C.byref(p), m, VARIANTS[variant],
+                                            PRECISIONS[precision], flags | IO_DEVICE, _ptr(out_cols),
+                                            _ptr(out_kww), C.byref(st))
+    _check(rc, "krylov_kernel_columns_noalloc")
+    del keep
+    return out_cols, out_kww, st
+
+
+STATIC_SCRATCH_BYTES = 128 << 20
 
 
 def kernel_machine_fit_predict(graph: Graph, samples, y, phi: dict, m: int, gamma: float,
