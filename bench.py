@@ -271,6 +271,8 @@ def config_leg(torch, gk, I, name, variants, fp64=True):
     Wd = torch.as_tensor(W, device=dev)
     stream = torch.cuda.current_stream()
     out = {"workload": name, "n": L.n, "nnz": L.nnz, "s": s, "m": m, "graph_build_s": t_gen}
+    gk.trim()
+    torch.cuda.empty_cache()
     free, _ = torch.cuda.mem_get_info()
     foot64 = gk.request_footprint(L.n, s, m, "cbl", "fp64")
     out["fp64_footprint_GB"] = foot64 / 1e9

@@ -265,6 +265,12 @@ const char* gk_last_error_detail(void);
  * return device memory of the current device aligned to 256 bytes, or NULL. */
 int gk_set_allocator(void* (*alloc_fn)(size_t bytes, void* ctx), void (*free_fn)(void* ptr, void* ctx),
                      void* ctx);
+/* Return the device blocks the default allocator keeps cached for reuse
+ * (freed by finished calls) to HIP, after the work that last used them has
+ * completed; *released_bytes (may be NULL) receives their size.  Blocks of
+ * calls still running are untouched.  No effect with an allocator installed
+ * by gk_set_allocator. */
+int gk_trim(uint64_t* released_bytes);
 /* Stream used by the synchronous calls of the calling thread (hipStream_t). */
 int gk_set_stream(void* hip_stream);
 /* Library version string. */

@@ -40,6 +40,8 @@ hipStream_t current_stream();
 // Wait for and drop the reuse events of every cached block (before the
 // streams they were recorded on are destroyed).
 void cache_settle();
+// Return every cached free block to HIP; bytes released.
+uint64_t cache_trim();
 
 // A set of device buffers released together (RAII).  With `pool` set, the
 // buffers are carved in order out of that caller-provided device range

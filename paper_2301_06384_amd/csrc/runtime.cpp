@@ -17,8 +17,8 @@ void set_detail(const std::string& msg) { t_detail = msg; }
 // Default: a size-keyed cache over hipMalloc.  A block returned to the cache
 // carries an event recorded on the stream that last used it; a later
 // allocation on another stream waits for that event before reuse.  Cached
-// blocks go back to HIP only when an allocation fails (the cache is released
-// and the allocation retried once) or at process exit.
+// blocks go back to HIP when an allocation fails (the cache is released and
+// the allocation retried once), on gk_trim, or at process exit.
 namespace {
 struct CachedBlock {
   void* p;
@@ -119,6 +119,25 @@ void dev_free(void* p) {
 }
 
 void set_thread_stream(hipStream_t s) { t_stream = s; }
+
+uint64_t cache_trim() {
+  if (g_alloc_fn) return 0;
+  Cache& c = cache();
+  std::lock_guard<std::mutex> lk(c.mu);
+  uint64_t released = 0;
+  for (auto& kv : c.free_blocks) {
+    if (kv.second.ev) {
+      (void)hipEventSynchronize(kv.second.ev);
+      (void)hipEventDestroy(kv.second.ev);
+    }
+    (void)hipFree(kv.second.p);
+    released += kv.second.bytes;
+  }
+  c.free_blocks.clear();
+  c.cached_bytes = 0;
+  (void)hipGetLastError();
+  return released;
+}
 
 void cache_settle() {
   if (g_alloc_fn) return;
@@ -293,6 +312,12 @@ int gk_set_allocator(void* (*alloc_fn)(size_t, void*), void (*free_fn)(void*, vo
   gk::g_alloc_fn = alloc_fn;
   gk::g_free_fn = free_fn;
   gk::g_alloc_ctx = ctx;
+  return GK_OK;
+}
+
+int gk_trim(uint64_t* released_bytes) {
+  const uint64_t r = gk::cache_trim();
+  if (released_bytes) *released_bytes = r;
   return GK_OK;
 }
 

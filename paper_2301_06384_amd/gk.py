@@ -99,6 +99,7 @@ _lib.gk_strerror.argtypes = [C.c_int]
 _lib.gk_strerror.restype = C.c_char_p
 _lib.gk_last_error_detail.restype = C.c_char_p
 _lib.gk_set_stream.argtypes = [C.c_void_p]
+_lib.gk_trim.argtypes = [C.POINTER(C.c_uint64)]
 _lib.gk_version.restype = C.c_char_p
 _ALLOC_T = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
 _FREE_T = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
@@ -114,7 +115,7 @@ _lib.gk_kernel_timings.restype = C.c_int
 
 EXPORTED = ["graph_kernel_init", "graph_kernel_release", "gk_graph_info", "krylov_kernel_columns",
             "krylov_kernel_columns_noalloc", "kernel_machine_fit_predict", "gk_request_footprint", "gk_serve_start", "gk_submit", "gk_poll",
-            "gk_serve_stop", "gk_strerror", "gk_last_error_detail", "gk_set_allocator", "gk_set_stream",
+            "gk_serve_stop", "gk_strerror", "gk_last_error_detail", "gk_set_allocator", "gk_set_stream", "gk_trim",
             "gk_version", "gk_kernel_timings"]
 
 
@@ -283,6 +284,13 @@ def request_footprint(n: int, s: int, m: int, variant: str = "cbl", precision: s
 
 def strerror(code: int) -> str:
     return _lib.gk_strerror(code).decode()
+
+
+def trim() -> int:
+    """Return the library's cached free device blocks to HIP; bytes released."""
+    b = C.c_uint64()
+    _check(_lib.gk_trim(C.byref(b)), "gk_trim")
+    return b.value
 
 
 def set_stream(stream) -> None:
