@@ -179,10 +179,12 @@ def _progress(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def serving_bench(gk, I, n_req: int, seed: int = 0, max_active: int = 8, n_streams: int = 8):
+def serving_bench(gk, I, n_req: int, seed: int = 0, max_active: int = 8, n_streams: int = 16):
     """Serving workload: 8 resident random geometric graphs (N 10k..500k),
     requests with s ~ U{4..128}, diffusion or spline kernels, m = 30, cbl,
-    mixed precision, fit + predict on all N nodes.  A closed-loop warm-up
+    mixed precision, fit + predict on all N nodes.  The server batches the
+    requests of each graph at the iteration level (one grouped SpMM and one
+    batched launch per CholQR pass per round).  A closed-loop warm-up
     measures the saturated throughput; the timed stream has Poisson arrivals
     at 0.7 x that rate.  Latency = completion - scheduled arrival."""
     t_gen = time.perf_counter()

@@ -113,6 +113,12 @@ inline int block_ld(int s) { return s <= 8 ? 8 : ((s + 15) / 16) * 16; }
 void launch_spmm(const gk_graph* g, bool fp32_weights, int ld, const double* V, const double* Vprev,
                  double* out, double a, double b, double gmul, double* acc, double e, const double* e_dev,
                  hipStream_t st);
+// X_r = L V_r for `count` blocks on the same graph (widths ld[r]) in one
+// launch per kSpmmGroup blocks; each block gets the arithmetic of its lone
+// launch_spmm(.., V_r, null, X_r, 1, 0, 0, null, ..)
+constexpr int kSpmmGroup = 16;
+void launch_spmm_group(const gk_graph* g, bool fp32_weights, int count, const int* ld, const double* const* V,
+                       double* const* X, hipStream_t st);
 
 // ortho.hip -- tall-skinny products over a list of equally shaped blocks.
 struct BlockList {
@@ -190,6 +196,29 @@ void launch_banded_spline_wave(int m, int s, const double* Hd, const double* Bd,
 void launch_cholqr_reg(const double* G, int ld, int s, int pass, const double* diag_prev, double thr, double* R,
                        double* Rinv, double* diag_out, int* n_defl, const double* R1, const double* R1inv, double* Rc,
                        double* Bout, double* BT, hipStream_t st);
+// Arguments of one CholQR factorisation (see launch_cholqr_reg); wk is the
+// ld x ld scratch pair of the 65..512 kernel.
+struct CholqrArgs {
+  const double* G;
+  int ld, s, pass;
+  const double* diag_prev;
+  double thr;
+  double* wk;
+  double* R;
+  double* Rinv;
+  double* diag_out;
+  int* n_defl;
+  const double* R1;
+  const double* R1inv;
+  double* Rc;
+  double* Bout;
+  double* BT;
+};
+constexpr int kCholqrBatch = 16;   // factorisations per batched launch (one workgroup each)
+// count factorisations in as few launches as possible; every one runs the
+// same arithmetic as a lone launch
+void launch_cholqr_reg_batched(const CholqrArgs* a, int count, hipStream_t st);    // ld <= 64
+void launch_cholqr_wide_batched(const CholqrArgs* a, int count, hipStream_t st);   // 64 < ld <= 512
 // bcr.hip -- (eps I + H_m)^{-k} F_1 by block cyclic reduction (s <= 64);
 // work holds bcr_work_elems(m, s) doubles
 size_t bcr_work_elems(int m, int s);
@@ -283,6 +312,19 @@ struct CallArgs {
   size_t pool_cap = 0;
 };
 int run_call(const CallArgs& a, hipStream_t stream);
+// Lockstep serving of classical block Lanczos calls (krylov.hip): begin
+// (validation, set-up, start block on step_stream), one Lanczos step for a
+// set of calls (grouped SpMM, batched CholQR; all on stream st), finish (phi
+// stage and outputs on fin after the step stream), complete (wait, copy the
+// results to the host, statistics; throws on a failed call), free.
+struct BatchCall;
+bool batch_eligible(const CallArgs& a);
+BatchCall* batch_begin(const CallArgs& a, hipStream_t step_stream);
+bool batch_stepping(const BatchCall* B);
+void batch_step(std::vector<BatchCall*>& calls, hipStream_t st);
+void batch_finish(BatchCall* B, hipStream_t step_stream, hipStream_t fin);
+int batch_complete(BatchCall* B);
+void batch_free(BatchCall* B);
 uint64_t footprint_bytes(int64_t n, int s, int m, int variant, int precision, uint32_t flags = 0);
 void set_thread_stream(hipStream_t s);
 

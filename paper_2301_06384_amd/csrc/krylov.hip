@@ -21,6 +21,7 @@
 //              small projection coefficients and the final linear
 //              combination.
 #include <cmath>
+#include <memory>
 
 #include "gk_internal.h"
 
@@ -426,106 +427,133 @@ static void phi_stage_block(Job& J, const double* Hd, const double* Bd, double* 
 }
 
 // ---------------------------------------------------------------- cbl
-static void run_cbl(Job& J) {
-  gk_graph* g = J.g;
-  const int64_t n = g->n;
-  const int ld = J.ld, m = J.m, s = J.s;
-  const int64_t blk = n * ld;
-  const bool mixed = J.mixed();
-  const bool full = J.full_reorth();
-  const bool no_reorth = (J.flags & GK_NO_REORTH) != 0;
-  // memory-lean two-pass form (GK_FP64): pass 1 keeps three blocks and the
-  // coefficients of every step; pass 2 regenerates the basis from them
-  const bool two = (J.flags & GK_TWO_PASS) != 0;
-  hipStream_t st = J.st;
-  // storage
+// Classical block Lanczos as a resumable sequence of phases, so that a
+// serving loop can advance many requests in lockstep (one grouped SpMM per
+// graph, one batched launch of their CholQR factors) with exactly the
+// launches, operands and order of a lone call:
+//   setup; for k: spmm(k), local(k), [k+1 < m: qr1(k), mid(k), qr2(k)],
+//   write(k); finish.
+struct CblRun {
+  Job& J;
+  gk_graph* g;
+  int64_t n;
+  int ld, m, s;
+  int64_t blk;
+  size_t l2;
+  bool mixed, full, no_reorth, two, pan, wave, widek, pro;
+  hipStream_t st;
   double* Vb = nullptr;     // FP64 basis (GK_FP64)
   double* ring = nullptr;   // 3 FP64 recurrence blocks (GK_MIXED, two-pass)
   float* Va = nullptr;      // FP32 archive (GK_MIXED)
-  if (!mixed) {
-    if (two) ring = J.ar.get<double>((size_t)3 * blk);
-    else Vb = J.ar.get<double>((size_t)m * blk);
-  } else {
-    ring = J.ar.get<double>((size_t)3 * blk);
-    Va = J.ar.get<float>((size_t)m * blk);
-  }
-  double* X = J.ar.get<double>(blk);
-  double* Y = J.ar.get<double>(blk);
-  // scratch for every block count the Gram launches use (1 .. m)
-  size_t pe = 0;
-  for (int nb = 1; nb <= (full ? m : 2); ++nb) pe = std::max(pe, gram_scratch_elems(n, nb, ld));
-  double* part = J.ar.get<double>(pe);
-  double* C = J.ar.get<double>((size_t)m * ld * ld);
-  const size_t l2 = (size_t)ld * ld;
-  const bool wave = small_wave_ok(ld), widek = wide_ok(ld);
-  double* G = J.ar.get<double>(l2);
-  double* W = J.ar.get<double>(widek ? cholqr_wide_scratch_elems(ld) : l2);
-  double* R1 = J.ar.get<double>(l2);
-  double* R1i = J.ar.get<double>(l2);
-  double* R2 = J.ar.get<double>(l2);
-  double* R2i = J.ar.get<double>(l2);
-  double* R12i = J.ar.get<double>(l2);
-  double* d1 = J.ar.get<double>(ld);
-  double* d2 = J.ar.get<double>(ld);
-  double* Hd = J.ar.get<double>((size_t)m * s * s);
-  double* Bd = J.ar.get<double>((size_t)m * s * s);
-  launch_zero(Bd, (size_t)m * s * s * sizeof(double), st);
-
-  auto V64 = [&](int k) -> double* {
-    return (mixed || two) ? ring + (int64_t)(k % 3) * blk : Vb + (int64_t)k * blk;
-  };
-  // two-pass: the local coefficients of both Gram-Schmidt passes and the
-  // normalisation R1^-1 R2^-1 of every step, kept for the replay
-  double* Cst = two ? J.ar.get<double>((size_t)m * 4 * l2) : nullptr;
-  double* Rst = two ? J.ar.get<double>((size_t)m * l2) : nullptr;
-  // start block Q_1 = E_W (Alg. 1)
-  launch_start_block(n, ld, s, J.samp, 1.0, V64(0), mixed ? Va : nullptr, st);
-
-  const bool pan = panel_ok(ld);
-  double* ppart = pan ? J.ar.get<double>(panel_scratch_elems(n, ld)) : nullptr;
-  // partial reorthogonalisation (GK_MIXED, s <= 512): block omega estimate,
-  // reorthogonalisation against the float32 archive only when it is needed
-  const bool pro = mixed && !full && !no_reorth && (wave || widek) && m > 2;
+  double *X = nullptr, *Y = nullptr, *part = nullptr, *C = nullptr, *G = nullptr, *W = nullptr;
+  double *R1 = nullptr, *R1i = nullptr, *R2 = nullptr, *R2i = nullptr, *R12i = nullptr, *d1 = nullptr,
+         *d2 = nullptr, *Hd = nullptr, *Bd = nullptr, *Cst = nullptr, *Rst = nullptr, *ppart = nullptr;
   double* Wr[3] = {nullptr, nullptr, nullptr};
-  double* est_part = nullptr;
-  double* om_rhs = nullptr;
-  int* fr = nullptr;
-  int* forced = nullptr;
-  size_t pe_all = 0;
-  double* part_all = nullptr;
-  double* part_arch = nullptr;
-  if (pro) {
-    for (int i = 0; i < 3; ++i) {
-      Wr[i] = J.ar.get<double>((size_t)m * s * s);
-      launch_zero(Wr[i], (size_t)m * s * s * sizeof(double), st);
-    }
-    est_part = J.ar.get<double>((size_t)m * omega_est_per_block(s));
-    if (widek) om_rhs = J.ar.get<double>(omega_wide_scratch_elems(m, s));
-    fr = J.ar.get<int>(m);
-    forced = J.ar.get<int>(m + 1);
-    launch_zero(forced, sizeof(int) * (m + 1), st);
-    if (arch_ok(ld)) part_arch = J.ar.get<double>(arch_scratch_elems(n, m, ld));
-    else {
-      for (int nb = 1; nb <= m; ++nb) pe_all = std::max(pe_all, gram_scratch_elems(n, nb, ld));
-      part_all = J.ar.get<double>(pe_all);
-    }
-  }
+  double *est_part = nullptr, *om_rhs = nullptr, *part_all = nullptr, *part_arch = nullptr;
+  int *fr = nullptr, *forced = nullptr;
   // tolerances of the estimate: threshold (semi-orthogonality at the square
   // root of the unit roundoff of the float32 archive, 2^-12), floor after a
   // reorthogonalisation against the float32 archive, floor of the two
   // explicitly orthogonalised neighbours, and the per-step rounding model
-  const double om_tau = 0x1p-12, om_floor_re = 2e-8, om_floor_loc = 1e-14;
-  const double om_nu = 1.1102230246251565e-16 * g->lambda_max * std::sqrt((double)s);
-  for (int k = 0; k < m; ++k) {
+  double om_tau = 0x1p-12, om_floor_re = 2e-8, om_floor_loc = 1e-14, om_nu = 0;
+
+  explicit CblRun(Job& j) : J(j) {}
+  double* V64(int k) const { return (mixed || two) ? ring + (int64_t)(k % 3) * blk : Vb + (int64_t)k * blk; }
+  // CholQR pass p (1 or 2) of step k on the single-workgroup kernels (kind 0:
+  // blocks up to 64 wide, 1: 65..512) or the generic factorisation (kind 2)
+  int qr_kind() const { return wave ? 0 : (widek ? 1 : 2); }
+
+  void setup() {
+    g = J.g;
+    n = g->n;
+    ld = J.ld;
+    m = J.m;
+    s = J.s;
+    blk = n * ld;
+    l2 = (size_t)ld * ld;
+    mixed = J.mixed();
+    full = J.full_reorth();
+    no_reorth = (J.flags & GK_NO_REORTH) != 0;
+    // memory-lean two-pass form (GK_FP64): pass 1 keeps three blocks and the
+    // coefficients of every step; pass 2 regenerates the basis from them
+    two = (J.flags & GK_TWO_PASS) != 0;
+    st = J.st;
+    if (!mixed) {
+      if (two) ring = J.ar.get<double>((size_t)3 * blk);
+      else Vb = J.ar.get<double>((size_t)m * blk);
+    } else {
+      ring = J.ar.get<double>((size_t)3 * blk);
+      Va = J.ar.get<float>((size_t)m * blk);
+    }
+    X = J.ar.get<double>(blk);
+    Y = J.ar.get<double>(blk);
+    // scratch for every block count the Gram launches use (1 .. m)
+    size_t pe = 0;
+    for (int nb = 1; nb <= (full ? m : 2); ++nb) pe = std::max(pe, gram_scratch_elems(n, nb, ld));
+    part = J.ar.get<double>(pe);
+    C = J.ar.get<double>((size_t)m * ld * ld);
+    wave = small_wave_ok(ld);
+    widek = wide_ok(ld);
+    G = J.ar.get<double>(l2);
+    W = J.ar.get<double>(widek ? cholqr_wide_scratch_elems(ld) : l2);
+    R1 = J.ar.get<double>(l2);
+    R1i = J.ar.get<double>(l2);
+    R2 = J.ar.get<double>(l2);
+    R2i = J.ar.get<double>(l2);
+    R12i = J.ar.get<double>(l2);
+    d1 = J.ar.get<double>(ld);
+    d2 = J.ar.get<double>(ld);
+    Hd = J.ar.get<double>((size_t)m * s * s);
+    Bd = J.ar.get<double>((size_t)m * s * s);
+    launch_zero(Bd, (size_t)m * s * s * sizeof(double), st);
+    // two-pass: the local coefficients of both Gram-Schmidt passes and the
+    // normalisation R1^-1 R2^-1 of every step, kept for the replay
+    if (two) {
+      Cst = J.ar.get<double>((size_t)m * 4 * l2);
+      Rst = J.ar.get<double>((size_t)m * l2);
+    }
+    // start block Q_1 = E_W (Alg. 1)
+    launch_start_block(n, ld, s, J.samp, 1.0, V64(0), mixed ? Va : nullptr, st);
+    pan = panel_ok(ld);
+    if (pan) ppart = J.ar.get<double>(panel_scratch_elems(n, ld));
+    // partial reorthogonalisation (GK_MIXED, s <= 512): block omega estimate,
+    // reorthogonalisation against the float32 archive only when it is needed
+    pro = mixed && !full && !no_reorth && (wave || widek) && m > 2;
+    if (pro) {
+      for (int i = 0; i < 3; ++i) {
+        Wr[i] = J.ar.get<double>((size_t)m * s * s);
+        launch_zero(Wr[i], (size_t)m * s * s * sizeof(double), st);
+      }
+      est_part = J.ar.get<double>((size_t)m * omega_est_per_block(s));
+      if (widek) om_rhs = J.ar.get<double>(omega_wide_scratch_elems(m, s));
+      fr = J.ar.get<int>(m);
+      forced = J.ar.get<int>(m + 1);
+      launch_zero(forced, sizeof(int) * (m + 1), st);
+      if (arch_ok(ld)) part_arch = J.ar.get<double>(arch_scratch_elems(n, m, ld));
+      else {
+        size_t pe_all = 0;
+        for (int nb = 1; nb <= m; ++nb) pe_all = std::max(pe_all, gram_scratch_elems(n, nb, ld));
+        part_all = J.ar.get<double>(pe_all);
+      }
+    }
+    om_nu = 1.1102230246251565e-16 * g->lambda_max * std::sqrt((double)s);
+  }
+
+  // X = L Q_k
+  void spmm(int k) {
+    J.tm.begin(PH_SPMM);
+    launch_spmm(g, mixed, ld, V64(k), nullptr, X, 1.0, 0.0, 0.0, nullptr, 0.0, nullptr, st);
+  }
+
+  // local block [Q_{k-1}, Q_k]:  C = local^T X;  H_kk = sym(C_k);  X -= local C
+  // (the Q_{k-1} part realises the three-term recurrence of Alg. 1), then the
+  // reorthogonalisation against the whole basis where it is done every step,
+  // and G = X^T X
+  void local(int k) {
     double* Vk = V64(k);
     double* Vkm1 = k > 0 ? V64(k - 1) : nullptr;
     const int nbv = k > 0 ? 2 : 1;
-    // X = L Q_k
-    J.tm.begin(PH_SPMM);
-    launch_spmm(g, mixed, ld, Vk, nullptr, X, 1.0, 0.0, 0.0, nullptr, 0.0, nullptr, st);
     J.tm.begin(PH_ORTH);
-    // local block [Q_{k-1}, Q_k]:  C = local^T X;  H_kk = sym(C_k);  X -= local C
-    // (the Q_{k-1} part realises the three-term recurrence of Alg. 1)
     BlockList loc = (k > 0) ? BlockList{Vkm1, (int64_t)(Vk - Vkm1), 2, false} : BlockList{Vk, blk, 1, false};
     const double* V0 = k > 0 ? Vkm1 : Vk;
     const double* V1 = k > 0 ? Vk : nullptr;
@@ -578,133 +606,179 @@ static void run_cbl(Job& J) {
     J.tm.begin(PH_ORTH);
     BlockList xl{X, blk, 1, false};
     if (!g_ready) launch_gram(n, ld, xl, X, G, part, nullptr, st);
-    if (k + 1 < m) {
-      // CholQR2: X = Q_{k+1} H_{k+1,k}
-      if (wave)
-        launch_cholqr_reg(G, ld, s, 1, nullptr, J.thr(), R1, R1i, d1, nullptr, nullptr, nullptr, nullptr, nullptr,
-                          nullptr, st);
-      else if (widek)
-        launch_cholqr_wide(G, ld, s, 1, nullptr, J.thr(), W, R1, R1i, d1, nullptr, nullptr, nullptr, nullptr, nullptr,
-                           nullptr, st);
-      else
-        launch_cholqr_factor(G, ld, s, 1, nullptr, J.thr(), W, R1, R1i, d1, nullptr, st);
-      if (pro && k >= 1) {
-        // Orthogonality estimate of the new block, taken after the first
-        // CholQR pass with B_k^{-1} ~ R1^{-1} (B_k = R2 R1, R2 = I + O(u)), so
-        // a flagged X is projected against the archive blocks 0..k-2 before
-        // it is normalised (the local blocks were handled exactly in float64
-        // above).  The second pass then absorbs the change: Y = X R1^{-1} has
-        // moved by |V_a^T Y| ~ tau, and CholQR of Y restores orthonormality.
-        // One projection suffices: from a loss of at most tau it reaches the
-        // floor set by the float32 archive.  At k = 1 the estimate has no
-        // block to act on.
-        const int* fk = fr + k;
-        // with the archive projection to follow, its first launch takes the
-        // decision (no launch of its own)
-        const bool defer = k >= 2 && part_arch;
-        OmegaDecide dec{};
-        launch_omega(k, s, ld, Wr[k % 3], Wr[(k + 2) % 3], Wr[(k + 1) % 3], Hd, Bd, R1i, om_nu, om_tau, om_floor_re,
-                     om_floor_loc, est_part, fr, forced, J.dscal + 1, J.dflags + 3, om_rhs, st, defer ? &dec : nullptr);
-        if (k >= 2) {
-          J.tm.begin(PH_REORTH);
-          BlockList all{Va, blk, k - 1, true};
-          if (part_arch) {
-            launch_arch_reorth(n, ld, all, X, C, part_arch, fk, st, &dec);
-          } else {
-            launch_gram(n, ld, all, X, C, part_all, fk, st);
-            launch_tsgemm(n, ld, all, C, X, X, nullptr, -1.0, 1.0, fk, st);
-          }
-          J.tm.begin(PH_ORTH);
+  }
+
+  // CholQR2: X = Q_{k+1} H_{k+1,k}; pass 1 factors G = X^T X
+  CholqrArgs qr1_args() const {
+    return CholqrArgs{G, ld, s, 1, nullptr, J.thr(), W, R1, R1i, d1, nullptr, nullptr, nullptr, nullptr, nullptr,
+                      nullptr};
+  }
+  // pass 2 factors the Gram of X R1^-1; the mixed recurrence takes
+  // H_{k,k+1} = B_k^T of the next step from C
+  CholqrArgs qr2_args(int k) const {
+    double* R12k = two ? Rst + (int64_t)k * l2 : R12i;
+    double* BT = (mixed && (pan || widek)) ? C : nullptr;
+    return CholqrArgs{G, ld, s, 2, d1, J.thr(), W, nullptr, nullptr, d2, J.dflags + 1, R1, R1i, R12k,
+                      Bd + (int64_t)k * s * s, BT};
+  }
+  void qr1(int k) {
+    (void)k;
+    if (wave) launch_cholqr_reg_batched(&qr1_args_storage(), 1, st);
+    else if (widek) launch_cholqr_wide_batched(&qr1_args_storage(), 1, st);
+    else launch_cholqr_factor(G, ld, s, 1, nullptr, J.thr(), W, R1, R1i, d1, nullptr, st);
+  }
+  void qr2(int k) {
+    if (wave || widek) {
+      qa_ = qr2_args(k);
+      if (wave) launch_cholqr_reg_batched(&qa_, 1, st);
+      else launch_cholqr_wide_batched(&qa_, 1, st);
+      return;
+    }
+    double* R12k = two ? Rst + (int64_t)k * l2 : R12i;
+    launch_cholqr_factor(G, ld, s, 2, d1, J.thr(), W, R2, R2i, d2, J.dflags + 1, st);
+    launch_small_gemm(ld, ld, ld, R1i, ld, false, R2i, ld, false, R12k, ld, 1.0, 0.0, st);
+    launch_small_gemm(s, s, s, R2, ld, false, R1, ld, false, Bd + (int64_t)k * s * s, s, 1.0, 0.0, st);
+  }
+  CholqrArgs qa_{};
+  const CholqrArgs& qr1_args_storage() {
+    qa_ = qr1_args();
+    return qa_;
+  }
+
+  // between the two CholQR passes: the orthogonality estimate, the flagged
+  // projection against the archive, and the Gram of X R1^-1
+  void mid(int k) {
+    if (pro && k >= 1) {
+      // Orthogonality estimate of the new block, taken after the first
+      // CholQR pass with B_k^{-1} ~ R1^{-1} (B_k = R2 R1, R2 = I + O(u)), so
+      // a flagged X is projected against the archive blocks 0..k-2 before
+      // it is normalised (the local blocks were handled exactly in float64
+      // above).  The second pass then absorbs the change: Y = X R1^{-1} has
+      // moved by |V_a^T Y| ~ tau, and CholQR of Y restores orthonormality.
+      // One projection suffices: from a loss of at most tau it reaches the
+      // floor set by the float32 archive.  At k = 1 the estimate has no
+      // block to act on.
+      const int* fk = fr + k;
+      // with the archive projection to follow, its first launch takes the
+      // decision (no launch of its own)
+      const bool defer = k >= 2 && part_arch;
+      OmegaDecide dec{};
+      launch_omega(k, s, ld, Wr[k % 3], Wr[(k + 2) % 3], Wr[(k + 1) % 3], Hd, Bd, R1i, om_nu, om_tau, om_floor_re,
+                   om_floor_loc, est_part, fr, forced, J.dscal + 1, J.dflags + 3, om_rhs, st, defer ? &dec : nullptr);
+      if (k >= 2) {
+        J.tm.begin(PH_REORTH);
+        BlockList all{Va, blk, k - 1, true};
+        if (part_arch) {
+          launch_arch_reorth(n, ld, all, X, C, part_arch, fk, st, &dec);
+        } else {
+          launch_gram(n, ld, all, X, C, part_all, fk, st);
+          launch_tsgemm(n, ld, all, C, X, X, nullptr, -1.0, 1.0, fk, st);
         }
+        J.tm.begin(PH_ORTH);
       }
-      if (pan) {
-        launch_panel(PM_APPLY_SELF, n, ld, 0, X, nullptr, nullptr, nullptr, nullptr, nullptr, R1i, ppart, G, st);
-      } else {
-        launch_tsgemm(n, ld, xl, R1i, nullptr, Y, nullptr, 1.0, 0.0, nullptr, st, true);
-        BlockList yl{Y, blk, 1, false};
-        launch_gram(n, ld, yl, Y, G, part, nullptr, st);
-      }
+    }
+    if (pan) {
+      launch_panel(PM_APPLY_SELF, n, ld, 0, X, nullptr, nullptr, nullptr, nullptr, nullptr, R1i, ppart, G, st);
+    } else {
+      BlockList xl{X, blk, 1, false};
+      launch_tsgemm(n, ld, xl, R1i, nullptr, Y, nullptr, 1.0, 0.0, nullptr, st, true);
+      BlockList yl{Y, blk, 1, false};
+      launch_gram(n, ld, yl, Y, G, part, nullptr, st);
+    }
+  }
+
+  // Q_{k+1} = X R1^-1 R2^-1 (float32 archive copy when mixed); at k = m-1
+  // ||X_m||_F as the residual indicator (the unused H_{m+1,m})
+  void write(int k) {
+    if (k + 1 < m) {
       double* R12k = two ? Rst + (int64_t)k * l2 : R12i;
-      if (wave) {
-        // the mixed panel path takes H_{k,k+1} = B_k^T of the next step from C
-        launch_cholqr_reg(G, ld, s, 2, d1, J.thr(), nullptr, nullptr, d2, J.dflags + 1, R1, R1i, R12k,
-                          Bd + (int64_t)k * s * s, (mixed && pan) ? C : nullptr, st);
-      } else if (widek) {
-        launch_cholqr_wide(G, ld, s, 2, d1, J.thr(), W, nullptr, nullptr, d2, J.dflags + 1, R1, R1i, R12k,
-                           Bd + (int64_t)k * s * s, mixed ? C : nullptr, st);
-      } else {
-        launch_cholqr_factor(G, ld, s, 2, d1, J.thr(), W, R2, R2i, d2, J.dflags + 1, st);
-        launch_small_gemm(ld, ld, ld, R1i, ld, false, R2i, ld, false, R12k, ld, 1.0, 0.0, st);
-        launch_small_gemm(s, s, s, R2, ld, false, R1, ld, false, Bd + (int64_t)k * s * s, s, 1.0, 0.0, st);
-      }
       float* arch32 = mixed ? Va + (int64_t)(k + 1) * blk : nullptr;
       if (pan)
         launch_panel(PM_APPLY_WRITE, n, ld, 0, X, V64(k + 1), arch32, nullptr, nullptr, nullptr, R12k, ppart,
                      nullptr, st);
       else
-        launch_tsgemm(n, ld, xl, R12k, nullptr, V64(k + 1), arch32, 1.0, 0.0, nullptr, st, true);
+        launch_tsgemm(n, ld, BlockList{X, blk, 1, false}, R12k, nullptr, V64(k + 1), arch32, 1.0, 0.0, nullptr, st,
+                      true);
     } else {
-      // ||X_m||_F: residual indicator (the unused H_{m+1,m})
       hipLaunchKernelGGL(trace_sqrt_kernel, dim3(1), dim3(256), 0, st, G, ld, s, J.dscal);
       GK_HIP(hipGetLastError());
     }
   }
-  J.tm.begin(PH_PHI);
-  double* U = J.ar.get<double>((size_t)m * s * s);
-  J.K = J.ar.get<double>((size_t)s * s);
-  phi_stage_block(J, Hd, Bd, U, J.K);
-  if (two) {
-    // Pass 2: regenerate Q_1 .. Q_m with the stored coefficients (the same
-    // kernels on the same operands, so the same blocks bit for bit) and
-    // accumulate P = sum_k Q_k U_k (Alg. 1 output) as they appear.
-    J.tm.begin(PH_ASM);
-    double* Pacc = J.ar.get<double>(blk);
-    double* Uk = J.ar.get<double>(l2);
-    launch_zero(Pacc, (size_t)blk * sizeof(double), st);
-    launch_start_block(n, ld, s, J.samp, 1.0, V64(0), nullptr, st);
-    for (int k = 0; k < m; ++k) {
-      double* Vk = V64(k);
-      hipLaunchKernelGGL(pad_block_kernel, dim3(nblk((int64_t)l2)), dim3(256), 0, st, k, s, ld, U, Uk);
-      GK_HIP(hipGetLastError());
-      launch_tsgemm(n, ld, BlockList{Vk, blk, 1, false}, Uk, Pacc, Pacc, nullptr, 1.0, 1.0, nullptr, st);
-      if (k + 1 == m) break;
-      double* Vkm1 = k > 0 ? V64(k - 1) : nullptr;
-      const int nbv = k > 0 ? 2 : 1;
-      BlockList loc = (k > 0) ? BlockList{Vkm1, (int64_t)(Vk - Vkm1), 2, false} : BlockList{Vk, blk, 1, false};
-      const double* V0 = k > 0 ? Vkm1 : Vk;
-      const double* V1 = k > 0 ? Vk : nullptr;
-      launch_spmm(g, false, ld, Vk, nullptr, X, 1.0, 0.0, 0.0, nullptr, 0.0, nullptr, st);
-      for (int pass = 0; pass < 2; ++pass) {
-        const double* Cp = Cst + ((int64_t)k * 2 + pass) * 2 * l2;
+
+  // phi of the projected matrix and the coefficients of the assembly
+  void finish() {
+    J.tm.begin(PH_PHI);
+    double* U = J.ar.get<double>((size_t)m * s * s);
+    J.K = J.ar.get<double>((size_t)s * s);
+    phi_stage_block(J, Hd, Bd, U, J.K);
+    if (two) {
+      // Pass 2: regenerate Q_1 .. Q_m with the stored coefficients (the same
+      // kernels on the same operands, so the same blocks bit for bit) and
+      // accumulate P = sum_k Q_k U_k (Alg. 1 output) as they appear.
+      J.tm.begin(PH_ASM);
+      double* Pacc = J.ar.get<double>(blk);
+      double* Uk = J.ar.get<double>(l2);
+      launch_zero(Pacc, (size_t)blk * sizeof(double), st);
+      launch_start_block(n, ld, s, J.samp, 1.0, V64(0), nullptr, st);
+      for (int k = 0; k < m; ++k) {
+        double* Vk = V64(k);
+        hipLaunchKernelGGL(pad_block_kernel, dim3(nblk((int64_t)l2)), dim3(256), 0, st, k, s, ld, U, Uk);
+        GK_HIP(hipGetLastError());
+        launch_tsgemm(n, ld, BlockList{Vk, blk, 1, false}, Uk, Pacc, Pacc, nullptr, 1.0, 1.0, nullptr, st);
+        if (k + 1 == m) break;
+        double* Vkm1 = k > 0 ? V64(k - 1) : nullptr;
+        const int nbv = k > 0 ? 2 : 1;
+        BlockList loc = (k > 0) ? BlockList{Vkm1, (int64_t)(Vk - Vkm1), 2, false} : BlockList{Vk, blk, 1, false};
+        const double* V0 = k > 0 ? Vkm1 : Vk;
+        const double* V1 = k > 0 ? Vk : nullptr;
+        launch_spmm(g, false, ld, Vk, nullptr, X, 1.0, 0.0, 0.0, nullptr, 0.0, nullptr, st);
+        for (int pass = 0; pass < 2; ++pass) {
+          const double* Cp = Cst + ((int64_t)k * 2 + pass) * 2 * l2;
+          if (pan)
+            launch_panel(PM_UPDATE_SELF, n, ld, nbv, X, X, nullptr, V0, V1, Cp, nullptr, ppart, G, st, nullptr, s);
+          else
+            launch_tsgemm(n, ld, loc, Cp, X, X, nullptr, -1.0, 1.0, nullptr, st);
+        }
+        const double* R12k = Rst + (int64_t)k * l2;
         if (pan)
-          launch_panel(PM_UPDATE_SELF, n, ld, nbv, X, X, nullptr, V0, V1, Cp, nullptr, ppart, G, st, nullptr, s);
+          launch_panel(PM_APPLY_WRITE, n, ld, 0, X, V64(k + 1), nullptr, nullptr, nullptr, nullptr, R12k, ppart,
+                       nullptr, st);
         else
-          launch_tsgemm(n, ld, loc, Cp, X, X, nullptr, -1.0, 1.0, nullptr, st);
+          launch_tsgemm(n, ld, BlockList{X, blk, 1, false}, R12k, nullptr, V64(k + 1), nullptr, 1.0, 0.0, nullptr,
+                        st, true);
       }
-      const double* R12k = Rst + (int64_t)k * l2;
-      if (pan)
-        launch_panel(PM_APPLY_WRITE, n, ld, 0, X, V64(k + 1), nullptr, nullptr, nullptr, nullptr, R12k, ppart,
-                     nullptr, st);
-      else
-        launch_tsgemm(n, ld, BlockList{X, blk, 1, false}, R12k, nullptr, V64(k + 1), nullptr, 1.0, 0.0, nullptr,
-                      st, true);
+      // P and the predictor now come from the one accumulated block
+      J.Upad = J.ar.get<double>((size_t)ld * s);
+      hipLaunchKernelGGL(ident_rows_kernel, dim3(nblk((int64_t)ld * s)), dim3(256), 0, st, s, ld, J.Upad);
+      GK_HIP(hipGetLastError());
+      J.arch = BlockList{Pacc, blk, 1, false};
+      J.spd = J.phi.kind != GK_PHI_POLYNOMIAL;
+      J.tm.end();
+      return;
     }
-    // P and the predictor now come from the one accumulated block
-    J.Upad = J.ar.get<double>((size_t)ld * s);
-    hipLaunchKernelGGL(ident_rows_kernel, dim3(nblk((int64_t)ld * s)), dim3(256), 0, st, s, ld, J.Upad);
+    J.Upad = J.ar.get<double>((size_t)m * ld * s);
+    hipLaunchKernelGGL(pad_rows_kernel, dim3(nblk((int64_t)m * ld * s)), dim3(256), 0, st, m, s, ld, U, J.Upad);
     GK_HIP(hipGetLastError());
-    J.arch = BlockList{Pacc, blk, 1, false};
+    J.arch = mixed ? BlockList{Va, blk, m, true} : BlockList{Vb, blk, m, false};
     J.spd = J.phi.kind != GK_PHI_POLYNOMIAL;
     J.tm.end();
-    return;
   }
-  J.Upad = J.ar.get<double>((size_t)m * ld * s);
-  hipLaunchKernelGGL(pad_rows_kernel, dim3(nblk((int64_t)m * ld * s)), dim3(256), 0, st, m, s, ld, U, J.Upad);
-  GK_HIP(hipGetLastError());
-  J.arch = mixed ? BlockList{Va, blk, m, true} : BlockList{Vb, blk, m, false};
-  J.spd = J.phi.kind != GK_PHI_POLYNOMIAL;
-  // residual: sqrt(trace(G)) of the last iteration
-  J.tm.end();
+};
+
+static void run_cbl(Job& J) {
+  CblRun R(J);
+  R.setup();
+  for (int k = 0; k < R.m; ++k) {
+    R.spmm(k);
+    R.local(k);
+    if (k + 1 < R.m) {
+      R.qr1(k);
+      R.mid(k);
+      R.qr2(k);
+    }
+    R.write(k);
+  }
+  R.finish();
 }
 
 // ---------------------------------------------------------------- gbl / sbl
@@ -999,20 +1073,46 @@ static void check_samples_host(const int64_t* h, int s, int64_t n) {
   for (int i = 1; i < s; ++i) GK_REQUIRE(v[i] != v[i - 1], GK_EDUPSAMPLE, "duplicate sample " + std::to_string(v[i]));
 }
 
-int run_call(const CallArgs& a, hipStream_t stream) {
+// One call: validation and set-up, the Krylov stage, the outputs, completion.
+// The lone entry points run the phases back to back; the serving loop
+// advances several classical block Lanczos calls in lockstep between
+// call_prepare and call_outputs (BatchCall below).
+struct CallState {
+  CallArgs a;
+  Job J;
+  bool dev_io = false;
+  std::vector<int64_t> hs;   // samples on the host (uploaded asynchronously)
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  int hflags[8] = {0};
+  double hscal[8] = {0};
+  double* hcols = nullptr;
+  double* hK = nullptr;
+  double* coef = nullptr;
+  double* pred = nullptr;
+  explicit CallState(const CallArgs& args) : a(args) {}
+  ~CallState() {
+    if (ev0) (void)hipEventDestroy(ev0);
+    if (ev1) (void)hipEventDestroy(ev1);
+  }
+};
+
+// validation, device set-up of the job and the samples (enqueued on stream)
+static void call_prepare(CallState& S, hipStream_t stream, bool timers) {
+  const CallArgs& a = S.a;
   validate_common(a);
   // a status left by the caller's own earlier HIP calls is not this call's
   (void)hipGetLastError();
   gk_graph* g = a.g;
-  const bool dev_io = (a.flags & GK_IO_DEVICE) != 0;
+  S.dev_io = (a.flags & GK_IO_DEVICE) != 0;
   // samples: validate on the host
-  std::vector<int64_t> hs(a.s);
-  if (dev_io) GK_HIP(hipMemcpy(hs.data(), a.samples, sizeof(int64_t) * a.s, hipMemcpyDeviceToHost));
+  std::vector<int64_t>& hs = S.hs;
+  hs.resize(a.s);
+  if (S.dev_io) GK_HIP(hipMemcpy(hs.data(), a.samples, sizeof(int64_t) * a.s, hipMemcpyDeviceToHost));
   else std::memcpy(hs.data(), a.samples, sizeof(int64_t) * a.s);
   check_samples_host(hs.data(), a.s, g->n);
   GK_HIP(hipSetDevice(g->device));
 
-  Job J;
+  Job& J = S.J;
   J.ar.pool = static_cast<char*>(a.pool);
   J.ar.pool_cap = a.pool_cap;
   J.g = g;
@@ -1024,14 +1124,13 @@ int run_call(const CallArgs& a, hipStream_t stream) {
   J.flags = a.flags;
   J.phi = *a.phi;
   J.st = stream;
-  J.tm.on = (a.flags & GK_TIMING) != 0;
+  J.tm.on = timers && (a.flags & GK_TIMING) != 0;
   J.tm.st = stream;
-  kt_start(J.tm.on);
-  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  if (timers) kt_start(J.tm.on);
   if (J.tm.on) {
-    GK_HIP(hipEventCreate(&ev0));
-    GK_HIP(hipEventCreate(&ev1));
-    GK_HIP(hipEventRecord(ev0, stream));
+    GK_HIP(hipEventCreate(&S.ev0));
+    GK_HIP(hipEventCreate(&S.ev1));
+    GK_HIP(hipEventRecord(S.ev0, stream));
   }
   J.dflags = J.ar.get<int>(8);
   launch_zero(J.dflags, 256, stream);
@@ -1048,22 +1147,21 @@ int run_call(const CallArgs& a, hipStream_t stream) {
   hipLaunchKernelGGL(map_samples_kernel, dim3(nblk(a.s)), dim3(256), 0, stream, a.s, samp_in,
                      g->reordered ? g->d_iperm : (const int64_t*)nullptr, J.samp);
   GK_HIP(hipGetLastError());
+}
 
-  switch (a.variant) {
-    case GK_CBL: run_cbl(J); break;
-    case GK_GBL: run_scalar_lanczos(J, true); break;
-    case GK_SBL: run_scalar_lanczos(J, false); break;
-    case GK_CHEB: run_cheb(J, false); break;
-    case GK_CHEB2: run_cheb(J, true); break;
-  }
+// assembly of the columns, K_WW, the fit and the predictor, and (copies)
+// the copies back, all enqueued on J.st
+static void call_outputs(CallState& S, bool copies = true) {
+  const CallArgs& a = S.a;
+  Job& J = S.J;
+  gk_graph* g = a.g;
+  hipStream_t stream = J.st;
   const int64_t n = g->n;
   const int s = a.s, ld = J.ld;
   const int64_t* perm = g->reordered ? g->d_perm : nullptr;
-  // outputs
-  double* hcols = nullptr;
   J.tm.begin(PH_ASM);
   if (a.cols_out) {
-    double* P = dev_io ? a.cols_out : J.ar.get<double>((size_t)n * s);
+    double* P = S.dev_io ? a.cols_out : J.ar.get<double>((size_t)n * s);
     if (J.Upad) {
       // [Q_1..Q_m] U (Alg. 1)
       if (J.arch.f32 && J.arch.stride > 0 && arch_ok(ld))
@@ -1073,89 +1171,230 @@ int run_call(const CallArgs& a, hipStream_t stream) {
     } else {
       launch_assemble_diag(n, ld, s, J.arch, J.D, P, perm, true, stream);   // sum_k u_k Q_k (Alg. 2)
     }
-    hcols = P;
+    S.hcols = P;
   }
   J.tm.end();
-  double* hK = nullptr;
   if (a.kww_out) {   // K is row-major internally; the ABI hands out column-major
-    hK = J.ar.get<double>((size_t)s * s);
-    hipLaunchKernelGGL(transpose_kernel, dim3(nblk((int64_t)s * s)), dim3(256), 0, stream, s, J.K, hK);
+    S.hK = J.ar.get<double>((size_t)s * s);
+    hipLaunchKernelGGL(transpose_kernel, dim3(nblk((int64_t)s * s)), dim3(256), 0, stream, s, J.K, S.hK);
     GK_HIP(hipGetLastError());
   }
-  double* coef = nullptr;
-  double* pred = nullptr;
   if (a.fit) {
     J.tm.begin(PH_FIT);
     const double* y = a.y;
-    if (!dev_io) {
+    if (!S.dev_io) {
       double* yd = J.ar.get<double>(s);
       GK_HIP(hipMemcpyAsync(yd, a.y, sizeof(double) * s, hipMemcpyHostToDevice, stream));
       y = yd;
     }
-    coef = (dev_io && a.coef_out) ? a.coef_out : J.ar.get<double>(s);
+    S.coef = (S.dev_io && a.coef_out) ? a.coef_out : J.ar.get<double>(s);
     double* wk = J.ar.get<double>((size_t)s * s);
     int* piv = J.ar.get<int>(s);
     // K gathered from the float32 archive (mixed gbl / sbl) carries float32
     // rounding; elsewhere it is formed in float64
     const double piv_rel = (J.arch.f32 && !J.Upad) ? 0x1p-20 : 0x1p-40;
-    launch_small_solve(s, J.K, a.gamma, y, coef, wk, piv, J.spd, piv_rel, J.dflags + 2, stream);
+    launch_small_solve(s, J.K, a.gamma, y, S.coef, wk, piv, J.spd, piv_rel, J.dflags + 2, stream);
     J.tm.begin(PH_ASM);
     if (a.pred_out) {
       const int nbk = J.arch.nb;
       double* z = J.ar.get<double>((size_t)nbk * ld);
       if (J.Upad)   // z = phi(H_m) F_1 c  (Corollary 1)
-        launch_small_gemm(nbk * ld, 1, s, J.Upad, s, false, coef, 1, false, z, 1, 1.0, 0.0, stream);
+        launch_small_gemm(nbk * ld, 1, s, J.Upad, s, false, S.coef, 1, false, z, 1, 1.0, 0.0, stream);
       else
-        hipLaunchKernelGGL(zdiag_kernel, dim3(nblk((int64_t)nbk * ld)), dim3(256), 0, stream, nbk, s, ld, J.D, coef, z);
+        hipLaunchKernelGGL(zdiag_kernel, dim3(nblk((int64_t)nbk * ld)), dim3(256), 0, stream, nbk, s, ld, J.D, S.coef,
+                           z);
       GK_HIP(hipGetLastError());
-      pred = dev_io ? a.pred_out : J.ar.get<double>(n);
-      launch_predict(n, ld, J.arch, z, pred, perm, stream);
+      S.pred = S.dev_io ? a.pred_out : J.ar.get<double>(n);
+      launch_predict(n, ld, J.arch, z, S.pred, perm, stream);
     }
     J.tm.end();
   }
-  if (J.tm.on) GK_HIP(hipEventRecord(ev1, stream));
+  if (J.tm.on) GK_HIP(hipEventRecord(S.ev1, stream));
+  if (!copies) return;
   // copy back
-  int hflags[8] = {0};
-  double hscal[8] = {0};
-  GK_HIP(hipMemcpyAsync(hflags, J.dflags, sizeof(hflags), hipMemcpyDeviceToHost, stream));
-  GK_HIP(hipMemcpyAsync(hscal, J.dscal, sizeof(hscal), hipMemcpyDeviceToHost, stream));
-  if (!dev_io) {
-    if (a.cols_out) GK_HIP(hipMemcpyAsync(a.cols_out, hcols, sizeof(double) * n * s, hipMemcpyDeviceToHost, stream));
-    if (a.coef_out && coef) GK_HIP(hipMemcpyAsync(a.coef_out, coef, sizeof(double) * s, hipMemcpyDeviceToHost, stream));
-    if (a.pred_out && pred) GK_HIP(hipMemcpyAsync(a.pred_out, pred, sizeof(double) * n, hipMemcpyDeviceToHost, stream));
+  GK_HIP(hipMemcpyAsync(S.hflags, J.dflags, sizeof(S.hflags), hipMemcpyDeviceToHost, stream));
+  GK_HIP(hipMemcpyAsync(S.hscal, J.dscal, sizeof(S.hscal), hipMemcpyDeviceToHost, stream));
+  if (!S.dev_io) {
+    if (a.cols_out)
+      GK_HIP(hipMemcpyAsync(a.cols_out, S.hcols, sizeof(double) * n * s, hipMemcpyDeviceToHost, stream));
+    if (a.coef_out && S.coef)
+      GK_HIP(hipMemcpyAsync(a.coef_out, S.coef, sizeof(double) * s, hipMemcpyDeviceToHost, stream));
+    if (a.pred_out && S.pred)
+      GK_HIP(hipMemcpyAsync(a.pred_out, S.pred, sizeof(double) * n, hipMemcpyDeviceToHost, stream));
   }
   if (a.kww_out) {
-    GK_HIP(hipMemcpyAsync(a.kww_out, hK, sizeof(double) * s * s,
-                          dev_io ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, stream));
+    GK_HIP(hipMemcpyAsync(a.kww_out, S.hK, sizeof(double) * s * s,
+                          S.dev_io ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, stream));
   }
-  GK_HIP(hipStreamSynchronize(stream));
-  kt_finish();
+}
+
+// after the stream has completed the call's work: statistics and status
+static int call_complete(CallState& S, bool timers) {
+  const CallArgs& a = S.a;
+  Job& J = S.J;
+  gk_graph* g = a.g;
+  const int64_t n = g->n;
+  const int ld = J.ld;
+  if (timers) kt_finish();
   if (a.st) {
     std::memset(a.st, 0, sizeof(gk_stats));
     J.tm.collect(a.st);
-    if (ev0 && ev1) {
+    if (S.ev0 && S.ev1) {
       float ms = 0;
-      GK_HIP(hipEventElapsedTime(&ms, ev0, ev1));
+      GK_HIP(hipEventElapsedTime(&ms, S.ev0, S.ev1));
       a.st->t_total_ms = ms;
     }
-    a.st->n_deflated = hflags[1];
-    a.st->n_qr2_series = hflags[5];
-    a.st->resid_norm = hscal[0];
+    a.st->n_deflated = S.hflags[1];
+    a.st->n_qr2_series = S.hflags[5];
+    a.st->resid_norm = S.hscal[0];
     a.st->phi_method = J.phi_method;
     a.st->footprint_bytes = J.ar.bytes;
     a.st->n_reorth = (J.variant <= GK_SBL && J.full_reorth() && !(J.flags & GK_NO_REORTH)) ? std::max(J.m - 1, 0)
-                                                                                       : hflags[3];
-    a.st->orth_est = hscal[1];
+                                                                                           : S.hflags[3];
+    a.st->orth_est = S.hscal[1];
     const double wb = g->unit ? 0.0 : (J.mixed() ? 4.0 : 8.0);
     a.st->bytes_spmm = a.st->spmm_launches * (4.0 * (n + 1) + g->nnz * (4.0 + wb) + 8.0 * n + 2.0 * 8.0 * n * ld);
   }
-  if (ev0) (void)hipEventDestroy(ev0);
-  if (ev1) (void)hipEventDestroy(ev1);
-  if (hflags[0] == 1) throw Error{GK_EINVAL, "eps + theta <= 0 for a Ritz value theta"};
-  if (hflags[0] == 3) throw Error{GK_ENOTSPD, "eps I + H_m not positive definite"};
-  if (hflags[2]) throw Error{GK_ENOTSPD, "(K_W + gamma I) c = y not solvable"};
+  if (S.hflags[0] == 1) throw Error{GK_EINVAL, "eps + theta <= 0 for a Ritz value theta"};
+  if (S.hflags[0] == 3) throw Error{GK_ENOTSPD, "eps I + H_m not positive definite"};
+  if (S.hflags[2]) throw Error{GK_ENOTSPD, "(K_W + gamma I) c = y not solvable"};
   return GK_OK;
 }
+
+int run_call(const CallArgs& a, hipStream_t stream) {
+  CallState S(a);
+  call_prepare(S, stream, true);
+  Job& J = S.J;
+  switch (a.variant) {
+    case GK_CBL: run_cbl(J); break;
+    case GK_GBL: run_scalar_lanczos(J, true); break;
+    case GK_SBL: run_scalar_lanczos(J, false); break;
+    case GK_CHEB: run_cheb(J, false); break;
+    case GK_CHEB2: run_cheb(J, true); break;
+  }
+  call_outputs(S);
+  GK_HIP(hipStreamSynchronize(stream));
+  return call_complete(S, true);
+}
+
+// ------------------------------------------------ lockstep serving support
+// A classical block Lanczos call that the serving loop advances one Lanczos
+// step at a time together with other calls: one grouped SpMM per graph and
+// one batched launch of each CholQR pass per step (same kernels, operands
+// and order as a lone call, so the same results bit for bit).
+struct BatchCall {
+  CallState S;
+  std::unique_ptr<CblRun> R;
+  int k = 0;
+  hipEvent_t done = nullptr;
+  explicit BatchCall(const CallArgs& a) : S(a) {}
+  ~BatchCall() {
+    if (done) (void)hipEventDestroy(done);
+  }
+};
+
+bool batch_eligible(const CallArgs& a) {
+  return a.variant == GK_CBL && !(a.flags & (GK_TWO_PASS | GK_IO_DEVICE | GK_TIMING));
+}
+
+BatchCall* batch_begin(const CallArgs& a, hipStream_t step_stream) {
+  std::unique_ptr<BatchCall> B(new BatchCall(a));
+  call_prepare(B->S, step_stream, false);
+  B->R.reset(new CblRun(B->S.J));
+  B->R->setup();
+  return B.release();
+}
+
+bool batch_stepping(const BatchCall* B) { return B->k < B->R->m; }
+
+void batch_step(std::vector<BatchCall*>& calls, hipStream_t st) {
+  for (BatchCall* B : calls) {
+    B->R->st = st;
+    B->S.J.st = st;
+    B->S.J.tm.st = st;
+  }
+  // grouped SpMM: one launch per graph and weight precision
+  std::vector<char> done(calls.size(), 0);
+  for (size_t i = 0; i < calls.size(); ++i) {
+    if (done[i]) continue;
+    const CblRun& Ri = *calls[i]->R;
+    std::vector<int> ld;
+    std::vector<const double*> V;
+    std::vector<double*> X;
+    for (size_t j = i; j < calls.size(); ++j) {
+      const CblRun& Rj = *calls[j]->R;
+      if (done[j] || Rj.g != Ri.g || Rj.mixed != Ri.mixed) continue;
+      done[j] = 1;
+      ld.push_back(Rj.ld);
+      V.push_back(Rj.V64(calls[j]->k));
+      X.push_back(Rj.X);
+    }
+    launch_spmm_group(Ri.g, Ri.mixed, (int)ld.size(), ld.data(), V.data(), X.data(), st);
+  }
+  for (BatchCall* B : calls) B->R->local(B->k);
+  // the first CholQR pass of every call that normalises a new block
+  std::vector<CholqrArgs> wave, wide;
+  for (BatchCall* B : calls) {
+    if (B->k + 1 >= B->R->m) continue;
+    if (B->R->qr_kind() == 0) wave.push_back(B->R->qr1_args());
+    else if (B->R->qr_kind() == 1) wide.push_back(B->R->qr1_args());
+    else B->R->qr1(B->k);
+  }
+  if (!wave.empty()) launch_cholqr_reg_batched(wave.data(), (int)wave.size(), st);
+  if (!wide.empty()) launch_cholqr_wide_batched(wide.data(), (int)wide.size(), st);
+  for (BatchCall* B : calls)
+    if (B->k + 1 < B->R->m) B->R->mid(B->k);
+  wave.clear();
+  wide.clear();
+  for (BatchCall* B : calls) {
+    if (B->k + 1 >= B->R->m) continue;
+    if (B->R->qr_kind() == 0) wave.push_back(B->R->qr2_args(B->k));
+    else if (B->R->qr_kind() == 1) wide.push_back(B->R->qr2_args(B->k));
+    else B->R->qr2(B->k);
+  }
+  if (!wave.empty()) launch_cholqr_reg_batched(wave.data(), (int)wave.size(), st);
+  if (!wide.empty()) launch_cholqr_wide_batched(wide.data(), (int)wide.size(), st);
+  for (BatchCall* B : calls) {
+    B->R->write(B->k);
+    B->k++;
+  }
+}
+
+// phi stage and outputs of a call whose steps are done, on stream fin (after
+// the work already enqueued on the step stream); records the completion event
+void batch_finish(BatchCall* B, hipStream_t step_stream, hipStream_t fin) {
+  hipEvent_t ev;
+  GK_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+  GK_HIP(hipEventRecord(ev, step_stream));
+  GK_HIP(hipStreamWaitEvent(fin, ev, 0));
+  GK_HIP(hipEventDestroy(ev));
+  B->S.J.st = fin;
+  B->S.J.tm.st = fin;
+  B->R->st = fin;
+  B->R->finish();
+  call_outputs(B->S, false);
+  GK_HIP(hipEventCreateWithFlags(&B->done, hipEventDisableTiming));
+  GK_HIP(hipEventRecord(B->done, fin));
+}
+
+// waits for the call's work, then copies its results to the host buffers
+// (synchronous copies here keep the thread that enqueues the steps from
+// ever blocking on a transfer)
+int batch_complete(BatchCall* B) {
+  GK_HIP(hipEventSynchronize(B->done));
+  CallState& S = B->S;
+  const CallArgs& a = S.a;
+  const int64_t n = a.g->n;
+  GK_HIP(hipMemcpy(S.hflags, S.J.dflags, sizeof(S.hflags), hipMemcpyDeviceToHost));
+  GK_HIP(hipMemcpy(S.hscal, S.J.dscal, sizeof(S.hscal), hipMemcpyDeviceToHost));
+  if (a.cols_out) GK_HIP(hipMemcpy(a.cols_out, S.hcols, sizeof(double) * n * a.s, hipMemcpyDeviceToHost));
+  if (a.coef_out && S.coef) GK_HIP(hipMemcpy(a.coef_out, S.coef, sizeof(double) * a.s, hipMemcpyDeviceToHost));
+  if (a.pred_out && S.pred) GK_HIP(hipMemcpy(a.pred_out, S.pred, sizeof(double) * n, hipMemcpyDeviceToHost));
+  if (a.kww_out) GK_HIP(hipMemcpy(a.kww_out, S.hK, sizeof(double) * a.s * a.s, hipMemcpyDeviceToHost));
+  return call_complete(S, false);
+}
+
+void batch_free(BatchCall* B) { delete B; }
 
 }  // namespace gk
 

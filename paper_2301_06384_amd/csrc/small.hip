@@ -692,11 +692,11 @@ namespace gk {
 //   pass 2: R2 with the combined-diagonal deflation rule, R2inv, and the
 //           products Rc = R1inv R2inv and B = R2 R1 (s x s, H_{k+1,k}),
 //           and (BT non-null) B^T = H_{k,k+1} zero padded to ld x ld.
-__global__ void __launch_bounds__(ST)
-cholqr_blk_kernel(const double* __restrict__ G, int ld, int s, int pass, const double* __restrict__ diag_prev,
-                  double thr, double* __restrict__ R, double* __restrict__ Rinv, double* __restrict__ diag_out,
-                  int* __restrict__ n_defl, const double* __restrict__ R1, const double* __restrict__ R1inv,
-                  double* __restrict__ Rc, double* __restrict__ Bout, double* __restrict__ BT) {
+__device__ __forceinline__ void
+cholqr_blk_body(const double* __restrict__ G, int ld, int s, int pass, const double* __restrict__ diag_prev,
+                double thr, double* __restrict__ R, double* __restrict__ Rinv, double* __restrict__ diag_out,
+                int* __restrict__ n_defl, const double* __restrict__ R1, const double* __restrict__ R1inv,
+                double* __restrict__ Rc, double* __restrict__ Bout, double* __restrict__ BT) {
   __shared__ __align__(16) double A[WS][LP];
   __shared__ __align__(16) double Y[WS][LP];
   __shared__ __align__(16) double S1[WS][LP];
@@ -856,6 +856,25 @@ cholqr_blk_kernel(const double* __restrict__ G, int ld, int s, int pass, const d
       }
     record();
   }
+}
+
+__global__ void __launch_bounds__(ST)
+cholqr_blk_kernel(const double* __restrict__ G, int ld, int s, int pass, const double* __restrict__ diag_prev,
+                  double thr, double* __restrict__ R, double* __restrict__ Rinv, double* __restrict__ diag_out,
+                  int* __restrict__ n_defl, const double* __restrict__ R1, const double* __restrict__ R1inv,
+                  double* __restrict__ Rc, double* __restrict__ Bout, double* __restrict__ BT) {
+  cholqr_blk_body(G, ld, s, pass, diag_prev, thr, R, Rinv, diag_out, n_defl, R1, R1inv, Rc, Bout, BT);
+}
+
+// A batch of independent factorisations, one workgroup each (the serving
+// loop advances several requests in lockstep); count <= kCholqrBatch.
+struct CholqrBatch {
+  CholqrArgs a[kCholqrBatch];
+};
+__global__ void __launch_bounds__(ST) cholqr_blk_batch_kernel(CholqrBatch b) {
+  const CholqrArgs& a = b.a[blockIdx.x];
+  cholqr_blk_body(a.G, a.ld, a.s, a.pass, a.diag_prev, a.thr, a.R, a.Rinv, a.diag_out, a.n_defl, a.R1, a.R1inv,
+                  a.Rc, a.Bout, a.BT);
 }
 
 // 64 x 16 column slices of a product (the orthogonality estimate below).
@@ -1020,6 +1039,23 @@ void launch_cholqr_reg(const double* G, int ld, int s, int pass, const double* d
                      n_defl, R1, R1inv, Rc, Bout, BT);
   GK_HIP(hipGetLastError());
   kt_end(st, 8.0 * 4 * ld * ld, (double)s * s * s);
+}
+
+void launch_cholqr_reg_batched(const CholqrArgs* a, int count, hipStream_t st) {
+  for (int c0 = 0; c0 < count; c0 += kCholqrBatch) {
+    const int nb = std::min(kCholqrBatch, count - c0);
+    CholqrBatch b{};
+    double bytes = 0, flops = 0;
+    for (int i = 0; i < nb; ++i) {
+      b.a[i] = a[c0 + i];
+      bytes += 8.0 * 4 * a[c0 + i].ld * a[c0 + i].ld;
+      flops += (double)a[c0 + i].s * a[c0 + i].s * a[c0 + i].s;
+    }
+    kt_begin(KC_CHOLQR, st);
+    hipLaunchKernelGGL(cholqr_blk_batch_kernel, dim3(nb), dim3(ST), 0, st, b);
+    GK_HIP(hipGetLastError());
+    kt_end(st, bytes, flops);
+  }
 }
 
 void launch_omega(int k, int s, int ld, const double* Wk, const double* Wkm1, double* Wk1, const double* Hd,

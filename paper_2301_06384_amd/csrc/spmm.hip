@@ -36,20 +36,22 @@ __device__ __forceinline__ void store_row(double* p, int cs, const double (&v)[V
   for (int q = 0; q < VPT / 2; ++q) *reinterpret_cast<double2*>(p + q * cs) = make_double2(v[2 * q], v[2 * q + 1]);
 }
 
+// Rows of workgroup `bid` of a grid of G workgroups (block index and grid
+// size are those of the request's own launch, also inside a grouped launch).
 template <int VPT, int WM, bool SHFL>
-__global__ void __launch_bounds__(256)
-spmm_diff_kernel(int64_t n, int ld, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
-                 const double* __restrict__ w64, const float* __restrict__ w32,
-                 const double* __restrict__ d, const double* __restrict__ V,
-                 const double* __restrict__ Vprev, double* __restrict__ out, double a, double b,
-                 double gm, double* __restrict__ acc, double e, const double* __restrict__ e_dev) {
+__device__ __forceinline__ void
+spmm_diff_body(unsigned bid, unsigned G, int64_t n, int ld, const int32_t* __restrict__ rp,
+               const int32_t* __restrict__ ci, const double* __restrict__ w64, const float* __restrict__ w32,
+               const double* __restrict__ d, const double* __restrict__ V, const double* __restrict__ Vprev,
+               double* __restrict__ out, double a, double b, double gm, double* __restrict__ acc, double e,
+               const double* __restrict__ e_dev) {
   const int slots = ld / VPT;
   // Workgroups are dealt round-robin to the 8 XCDs, each with its own L2.
   // Renumber them so that every XCD walks one contiguous range of rows: with
   // a locality ordering of the nodes, the neighbour rows it gathers are then
   // mostly fetched into one L2 instead of several.
-  const unsigned G = gridDim.x, q8 = G >> 3, r8 = G & 7;
-  const unsigned x = blockIdx.x & 7, k = blockIdx.x >> 3;
+  const unsigned q8 = G >> 3, r8 = G & 7;
+  const unsigned x = bid & 7, k = bid >> 3;
   const unsigned lb = x * q8 + (x < r8 ? x : r8) + k;
   const int64_t t = (int64_t)lb * blockDim.x + threadIdx.x;
   const int64_t row = t / slots;
@@ -143,6 +145,95 @@ spmm_diff_kernel(int64_t n, int ld, const int32_t* __restrict__ rp, const int32_
 #pragma unroll
     for (int q = 0; q < VPT; ++q) ac[q] = fma(e, o[q], ac[q]);
     store_row<VPT>(acc + row * ld + c0, cs, ac);
+  }
+}
+
+template <int VPT, int WM, bool SHFL>
+__global__ void __launch_bounds__(256)
+spmm_diff_kernel(int64_t n, int ld, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                 const double* __restrict__ w64, const float* __restrict__ w32,
+                 const double* __restrict__ d, const double* __restrict__ V,
+                 const double* __restrict__ Vprev, double* __restrict__ out, double a, double b,
+                 double gm, double* __restrict__ acc, double e, const double* __restrict__ e_dev) {
+  spmm_diff_body<VPT, WM, SHFL>(blockIdx.x, gridDim.x, n, ld, rp, ci, w64, w32, d, V, Vprev, out, a, b, gm, acc,
+                                e, e_dev);
+}
+
+// Lane layout of a block width: VPT doubles per lane (ld/VPT lanes per row),
+// and whether the row's lanes walk the neighbour list with shuffles.
+static inline int spmm_vpt(int ld) { return ld <= 32 ? 2 : (ld <= 256 ? 4 : 8); }
+static inline bool spmm_shfl(int ld) {
+  const int slots = ld / spmm_vpt(ld);
+  return slots <= 64 && (64 % slots) == 0;
+}
+static inline int64_t spmm_grid(int64_t n, int ld) { return (n * (ld / spmm_vpt(ld)) + 255) / 256; }
+
+// One launch for the products X_r = L V_r of several requests on the same
+// graph (their blocks side by side: the concatenated column segments).
+// Workgroups [start_r, start_{r+1}) belong to request r and run exactly the
+// workgroups of its lone launch, with its own lane layout.
+struct SpmmGroupArgs {
+  int count;
+  int start[kSpmmGroup + 1];
+  int ld[kSpmmGroup];
+  const double* V[kSpmmGroup];
+  double* X[kSpmmGroup];
+};
+template <int WM>
+__global__ void __launch_bounds__(256)
+spmm_group_kernel(SpmmGroupArgs ga, int64_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                  const double* __restrict__ w64, const float* __restrict__ w32, const double* __restrict__ d) {
+  int r = 0;
+  while (r + 1 < ga.count && (int)blockIdx.x >= ga.start[r + 1]) ++r;
+  const unsigned bid = blockIdx.x - ga.start[r], G = ga.start[r + 1] - ga.start[r];
+  const int ld = ga.ld[r];
+  const int vpt = ld <= 32 ? 2 : (ld <= 256 ? 4 : 8);
+  const int slots = ld / vpt;
+  const bool sh = slots <= 64 && (64 % slots) == 0;
+#define GK_SPB(V_, S_)                                                                                            \
+  spmm_diff_body<V_, WM, S_>(bid, G, n, ld, rp, ci, w64, w32, d, ga.V[r], nullptr, ga.X[r], 1.0, 0.0, 0.0, nullptr, \
+                             0.0, nullptr)
+  if (vpt == 2) {
+    if (sh) GK_SPB(2, true); else GK_SPB(2, false);
+  } else if (vpt == 4) {
+    if (sh) GK_SPB(4, true); else GK_SPB(4, false);
+  } else {
+    if (sh) GK_SPB(8, true); else GK_SPB(8, false);
+  }
+#undef GK_SPB
+}
+
+void launch_spmm_group(const gk_graph* g, bool fp32_weights, int count, const int* ld, const double* const* V,
+                       double* const* X, hipStream_t st) {
+  const double wb = g->unit ? 0.0 : (fp32_weights ? 4.0 : 8.0);
+  const double* d = fp32_weights ? g->d32 : g->d64;
+  for (int c0 = 0; c0 < count; c0 += kSpmmGroup) {
+    SpmmGroupArgs ga{};
+    ga.count = std::min(kSpmmGroup, count - c0);
+    double bytes = 0, flops = 0;
+    int64_t tot = 0;
+    for (int i = 0; i < ga.count; ++i) {
+      ga.start[i] = (int)tot;
+      ga.ld[i] = ld[c0 + i];
+      ga.V[i] = V[c0 + i];
+      ga.X[i] = X[c0 + i];
+      tot += spmm_grid(g->n, ld[c0 + i]);
+      bytes += 4.0 * (g->n + 1) + (double)g->nnz * (4.0 + wb) + 8.0 * g->n + 16.0 * (double)g->n * ld[c0 + i];
+      flops += 2.0 * ((double)g->nnz + g->n) * ld[c0 + i];
+    }
+    ga.start[ga.count] = (int)tot;
+    kt_begin(KC_SPMM, st);
+    if (g->unit)
+      hipLaunchKernelGGL(spmm_group_kernel<W_UNIT>, dim3((unsigned)tot), dim3(256), 0, st, ga, g->n, g->rp, g->ci,
+                         g->w64, g->w32, d);
+    else if (fp32_weights)
+      hipLaunchKernelGGL(spmm_group_kernel<W_F32>, dim3((unsigned)tot), dim3(256), 0, st, ga, g->n, g->rp, g->ci,
+                         g->w64, g->w32, d);
+    else
+      hipLaunchKernelGGL(spmm_group_kernel<W_F64>, dim3((unsigned)tot), dim3(256), 0, st, ga, g->n, g->rp, g->ci,
+                         g->w64, g->w32, d);
+    GK_HIP(hipGetLastError());
+    kt_end(st, bytes, flops);
   }
 }
 

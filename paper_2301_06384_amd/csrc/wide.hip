@@ -187,8 +187,8 @@ __device__ __forceinline__ void wide_chol_inv(double* __restrict__ A, double* __
 // Same factor as the 64-wide kernel (pass 1: clamped pivots, pass 2:
 // combined-diagonal deflation, then Rc = R1inv R2inv and B = R2 R1), for
 // 64 < ld <= 512.  Aw, Yw: ld x ld device scratch.
-__global__ void __launch_bounds__(ST)
-cholqr_wide_kernel(const double* __restrict__ G, int ld, int s, int pass, const double* __restrict__ diag_prev,
+__device__ __forceinline__ void
+cholqr_wide_body(const double* __restrict__ G, int ld, int s, int pass, const double* __restrict__ diag_prev,
                    double thr, double* __restrict__ Aw, double* __restrict__ Yw, double* __restrict__ R,
                    double* __restrict__ Rinv, double* __restrict__ diag_out, int* __restrict__ n_defl,
                    const double* __restrict__ R1, const double* __restrict__ R1inv, double* __restrict__ Rc,
@@ -254,6 +254,24 @@ cholqr_wide_kernel(const double* __restrict__ G, int ld, int s, int pass, const 
   }
 }
 
+__global__ void __launch_bounds__(ST)
+cholqr_wide_kernel(const double* __restrict__ G, int ld, int s, int pass, const double* __restrict__ diag_prev,
+                   double thr, double* __restrict__ Aw, double* __restrict__ Yw, double* __restrict__ R,
+                   double* __restrict__ Rinv, double* __restrict__ diag_out, int* __restrict__ n_defl,
+                   const double* __restrict__ R1, const double* __restrict__ R1inv, double* __restrict__ Rc,
+                   double* __restrict__ Bout, double* __restrict__ BT) {
+  cholqr_wide_body(G, ld, s, pass, diag_prev, thr, Aw, Yw, R, Rinv, diag_out, n_defl, R1, R1inv, Rc, Bout, BT);
+}
+
+struct CholqrWideBatch {
+  CholqrArgs a[kCholqrBatch];
+};
+__global__ void __launch_bounds__(ST) cholqr_wide_batch_kernel(CholqrWideBatch b) {
+  const CholqrArgs& a = b.a[blockIdx.x];
+  cholqr_wide_body(a.G, a.ld, a.s, a.pass, a.diag_prev, a.thr, a.wk, a.wk + (size_t)a.ld * a.ld, a.R, a.Rinv,
+                   a.diag_out, a.n_defl, a.R1, a.R1inv, a.Rc, a.Bout, a.BT);
+}
+
 size_t cholqr_wide_scratch_elems(int ld) { return (size_t)2 * ld * ld; }
 
 void launch_cholqr_wide(const double* G, int ld, int s, int pass, const double* diag_prev, double thr, double* wk,
@@ -264,6 +282,23 @@ void launch_cholqr_wide(const double* G, int ld, int s, int pass, const double* 
                      wk + (size_t)ld * ld, R, Rinv, diag_out, n_defl, R1, R1inv, Rc, Bout, BT);
   GK_HIP(hipGetLastError());
   kt_end(st, 8.0 * 6 * ld * ld, (double)s * s * s * (pass == 2 ? 3.0 : 1.0));
+}
+
+void launch_cholqr_wide_batched(const CholqrArgs* a, int count, hipStream_t st) {
+  for (int c0 = 0; c0 < count; c0 += kCholqrBatch) {
+    const int nb = std::min(kCholqrBatch, count - c0);
+    CholqrWideBatch b{};
+    double bytes = 0, flops = 0;
+    for (int i = 0; i < nb; ++i) {
+      b.a[i] = a[c0 + i];
+      bytes += 8.0 * 6 * a[c0 + i].ld * a[c0 + i].ld;
+      flops += (double)a[c0 + i].s * a[c0 + i].s * a[c0 + i].s * (a[c0 + i].pass == 2 ? 3.0 : 1.0);
+    }
+    kt_begin(KC_CHOLQR, st);
+    hipLaunchKernelGGL(cholqr_wide_batch_kernel, dim3(nb), dim3(ST), 0, st, b);
+    GK_HIP(hipGetLastError());
+    kt_end(st, bytes, flops);
+  }
 }
 
 // ------------------------------------------------- orthogonality estimate
