@@ -448,6 +448,7 @@ def main():
         "mixed_reorth_steps": stats["n_reorth"],
         "mixed_orth_estimate": stats["orth_est"],
         "mixed_qr2_series_steps": stats["n_qr2_series"],
+        "mixed_qr2_skipped_steps": stats["n_qr2_skipped"],
         "stream_copy_GBps": copy_gbps,
         "roofline": {"kernel": dom_name, "bound": dom["bound"], "achieved": dom["achieved"], "peak": dom["peak"],
                      "unit": dom["unit"], "frac": dom["frac"], "traffic": traffic,

@@ -134,6 +134,7 @@ typedef struct {
   int32_t n_deflated;     /* basis columns deflated (rank-deficient QR) */
   int32_t phi_method;     /* 0 eigendecomposition, 1 banded Cholesky, 2 Chebyshev-on-H, 3 Horner */
   int32_t n_qr2_series;   /* second CholQR passes taken by the series expansion of chol(I + E) */
+  int32_t n_qr2_skipped;  /* GK_MIXED: second CholQR passes left out (first factor final, no projection) */
   uint64_t footprint_bytes; /* device bytes the call held */
 } gk_stats;
 

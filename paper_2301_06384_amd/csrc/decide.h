@@ -32,6 +32,8 @@ __device__ __forceinline__ bool omega_decide(const OmegaDecide& d, int wg, int n
     d.fr[d.k] = go ? 1 : 0;
     d.forced[d.k + 1] = (go && !f) ? 1 : 0;
     if (go) *d.nre += 1;
+    // a projected X needs the second CholQR pass
+    if (go && d.gate) *d.gate = 1;
     *d.est_out = fmax(*d.est_out, go ? d.floor_re : e);
   }
   const int64_t q0 = (int64_t)wg * nt + tid, qs = (int64_t)nwg * nt;

@@ -213,6 +213,11 @@ struct CholqrArgs {
   double* Rc;
   double* Bout;
   double* BT;
+  // Pass 1 with gate set (GK_MIXED): when the factor is well conditioned and
+  // no column was clamped, pass 1 completes the factorisation itself (Rc =
+  // R1inv, B = R1) and writes 0 to *gate, else 1.  Pass 2 does nothing when
+  // *gate == 0.  Null: pass 2 always runs.
+  int* gate;
 };
 constexpr int kCholqrBatch = 16;   // factorisations per batched launch (one workgroup each)
 // count factorisations in as few launches as possible; every one runs the
@@ -236,6 +241,7 @@ struct OmegaDecide {
   int* forced;
   double* est_out;
   int* nre;
+  int* gate;   // second CholQR pass needed (set when X is projected), or null
 };
 // Block orthogonality estimate (partial reorthogonalisation) for s <= 512.
 // est_part holds m * omega_est_per_block(s) entries; rhs_wide is null for
@@ -245,7 +251,7 @@ struct OmegaDecide {
 void launch_omega(int k, int s, int ld, const double* Wk, const double* Wkm1, double* Wk1, const double* Hd,
                   const double* Bd, const double* Rc, double nu, double tau, double floor_re, double floor_loc,
                   double* est_part, int* fr, int* forced, double* est_out, int* nre, double* rhs_wide,
-                  hipStream_t st, OmegaDecide* defer = nullptr);
+                  hipStream_t st, OmegaDecide* defer = nullptr, int* gate = nullptr);
 int omega_est_per_block(int s);
 // Small kernels for widths 65..512 (tiles of 64, one workgroup each).
 bool wide_ok(int ld);
@@ -288,9 +294,11 @@ void launch_arch_reorth(int64_t n, int ld, BlockList A, double* X, double* C, do
 void launch_arch_assemble(int64_t n, int ld, int s, BlockList A, const double* U, double* P, const int64_t* perm,
                           hipStream_t st);
 size_t panel_scratch_elems(int64_t n, int ld);
+// flag: the pass and its reduction do nothing when *flag == 0
 void launch_panel(int mode, int64_t n, int ld, int nbv, const double* X, double* Xout, float* X32,
                   const double* V0, const double* V1, const double* Cupd, const double* Rm, double* part,
-                  double* Cout, hipStream_t st, double* H = nullptr, int hs = 0, bool tri0 = false);
+                  double* Cout, hipStream_t st, double* H = nullptr, int hs = 0, bool tri0 = false,
+                  const int* flag = nullptr);
 
 // krylov.hip -- one call of the compute entry points
 struct CallArgs {

@@ -328,7 +328,8 @@ struct Job {
   PhaseTimer tm;
   int64_t* samp = nullptr;        // device numbering
   int* dflags = nullptr;          // [0] phi bad, [1] deflations, [2] solve bad, [3] reorth count,
-                                  // [5] second CholQR passes by series expansion
+                                  // [5] second CholQR passes by series expansion, [6] second
+                                  // CholQR passes left out
   double* dscal = nullptr;        // [0] residual norm
   double* poly_dev = nullptr;
   bool mixed() const { return precision == GK_MIXED; }
@@ -451,6 +452,10 @@ struct CblRun {
   double* Wr[3] = {nullptr, nullptr, nullptr};
   double *est_part = nullptr, *om_rhs = nullptr, *part_all = nullptr, *part_arch = nullptr;
   int *fr = nullptr, *forced = nullptr;
+  // GK_MIXED on the single-workgroup factorisations: the first CholQR pass
+  // sets *gate = 0 when its factor is final, the archive projection sets it
+  // back to 1; the Gram of X R1^-1 and the second pass run only at 1
+  int* gate = nullptr;
   // tolerances of the estimate: threshold (semi-orthogonality at the square
   // root of the unit roundoff of the float32 archive, 2^-12), floor after a
   // reorthogonalisation against the float32 archive, floor of the two
@@ -516,6 +521,7 @@ struct CblRun {
     launch_start_block(n, ld, s, J.samp, 1.0, V64(0), mixed ? Va : nullptr, st);
     pan = panel_ok(ld);
     if (pan) ppart = J.ar.get<double>(panel_scratch_elems(n, ld));
+    if (mixed && (wave || widek)) gate = J.ar.get<int>(1);
     // partial reorthogonalisation (GK_MIXED, s <= 512): block omega estimate,
     // reorthogonalisation against the float32 archive only when it is needed
     pro = mixed && !full && !no_reorth && (wave || widek) && m > 2;
@@ -608,10 +614,14 @@ struct CblRun {
     if (!g_ready) launch_gram(n, ld, xl, X, G, part, nullptr, st);
   }
 
-  // CholQR2: X = Q_{k+1} H_{k+1,k}; pass 1 factors G = X^T X
-  CholqrArgs qr1_args() const {
-    return CholqrArgs{G, ld, s, 1, nullptr, J.thr(), W, R1, R1i, d1, nullptr, nullptr, nullptr, nullptr, nullptr,
-                      nullptr};
+  // CholQR2: X = Q_{k+1} H_{k+1,k}; pass 1 factors G = X^T X (with the gate,
+  // it also writes the final factors when the second pass is not needed)
+  CholqrArgs qr1_args(int k) const {
+    double* R12k = two ? Rst + (int64_t)k * l2 : R12i;
+    double* BT = (mixed && (pan || widek)) ? C : nullptr;
+    if (!gate) return CholqrArgs{G, ld, s, 1, nullptr, J.thr(), W, R1, R1i, d1};
+    return CholqrArgs{G,       ld,      s,       1,    nullptr, J.thr(), W, R1, R1i, d1, nullptr, nullptr, nullptr,
+                      R12k, Bd + (int64_t)k * s * s, BT, gate};
   }
   // pass 2 factors the Gram of X R1^-1; the mixed recurrence takes
   // H_{k,k+1} = B_k^T of the next step from C
@@ -619,12 +629,11 @@ struct CblRun {
     double* R12k = two ? Rst + (int64_t)k * l2 : R12i;
     double* BT = (mixed && (pan || widek)) ? C : nullptr;
     return CholqrArgs{G, ld, s, 2, d1, J.thr(), W, nullptr, nullptr, d2, J.dflags + 1, R1, R1i, R12k,
-                      Bd + (int64_t)k * s * s, BT};
+                      Bd + (int64_t)k * s * s, BT, gate};
   }
   void qr1(int k) {
-    (void)k;
-    if (wave) launch_cholqr_reg_batched(&qr1_args_storage(), 1, st);
-    else if (widek) launch_cholqr_wide_batched(&qr1_args_storage(), 1, st);
+    if (wave) launch_cholqr_reg_batched(&qr1_args_storage(k), 1, st);
+    else if (widek) launch_cholqr_wide_batched(&qr1_args_storage(k), 1, st);
     else launch_cholqr_factor(G, ld, s, 1, nullptr, J.thr(), W, R1, R1i, d1, nullptr, st);
   }
   void qr2(int k) {
@@ -640,8 +649,8 @@ struct CblRun {
     launch_small_gemm(s, s, s, R2, ld, false, R1, ld, false, Bd + (int64_t)k * s * s, s, 1.0, 0.0, st);
   }
   CholqrArgs qa_{};
-  const CholqrArgs& qr1_args_storage() {
-    qa_ = qr1_args();
+  const CholqrArgs& qr1_args_storage(int k) {
+    qa_ = qr1_args(k);
     return qa_;
   }
 
@@ -664,7 +673,8 @@ struct CblRun {
       const bool defer = k >= 2 && part_arch;
       OmegaDecide dec{};
       launch_omega(k, s, ld, Wr[k % 3], Wr[(k + 2) % 3], Wr[(k + 1) % 3], Hd, Bd, R1i, om_nu, om_tau, om_floor_re,
-                   om_floor_loc, est_part, fr, forced, J.dscal + 1, J.dflags + 3, om_rhs, st, defer ? &dec : nullptr);
+                   om_floor_loc, est_part, fr, forced, J.dscal + 1, J.dflags + 3, om_rhs, st, defer ? &dec : nullptr,
+                   gate);
       if (k >= 2) {
         J.tm.begin(PH_REORTH);
         BlockList all{Va, blk, k - 1, true};
@@ -678,12 +688,13 @@ struct CblRun {
       }
     }
     if (pan) {
-      launch_panel(PM_APPLY_SELF, n, ld, 0, X, nullptr, nullptr, nullptr, nullptr, nullptr, R1i, ppart, G, st);
+      launch_panel(PM_APPLY_SELF, n, ld, 0, X, nullptr, nullptr, nullptr, nullptr, nullptr, R1i, ppart, G, st,
+                   nullptr, 0, false, gate);
     } else {
       BlockList xl{X, blk, 1, false};
-      launch_tsgemm(n, ld, xl, R1i, nullptr, Y, nullptr, 1.0, 0.0, nullptr, st, true);
+      launch_tsgemm(n, ld, xl, R1i, nullptr, Y, nullptr, 1.0, 0.0, gate, st, true);
       BlockList yl{Y, blk, 1, false};
-      launch_gram(n, ld, yl, Y, G, part, nullptr, st);
+      launch_gram(n, ld, yl, Y, G, part, gate, st);
     }
   }
 
@@ -1246,6 +1257,7 @@ static int call_complete(CallState& S, bool timers) {
     }
     a.st->n_deflated = S.hflags[1];
     a.st->n_qr2_series = S.hflags[5];
+    a.st->n_qr2_skipped = S.hflags[6];
     a.st->resid_norm = S.hscal[0];
     a.st->phi_method = J.phi_method;
     a.st->footprint_bytes = J.ar.bytes;
@@ -1336,8 +1348,8 @@ void batch_step(std::vector<BatchCall*>& calls, hipStream_t st) {
   std::vector<CholqrArgs> wave, wide;
   for (BatchCall* B : calls) {
     if (B->k + 1 >= B->R->m) continue;
-    if (B->R->qr_kind() == 0) wave.push_back(B->R->qr1_args());
-    else if (B->R->qr_kind() == 1) wide.push_back(B->R->qr1_args());
+    if (B->R->qr_kind() == 0) wave.push_back(B->R->qr1_args(B->k));
+    else if (B->R->qr_kind() == 1) wide.push_back(B->R->qr1_args(B->k));
     else B->R->qr1(B->k);
   }
   if (!wave.empty()) launch_cholqr_reg_batched(wave.data(), (int)wave.size(), st);

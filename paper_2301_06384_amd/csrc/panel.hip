@@ -40,6 +40,7 @@ struct PanelArgs {
   double* part;          // [gridDim.x][ngb*ld][ld] Gram partials
   double* H;             // UPDATE: when non-null, H = sym of the last coefficient block (hs x hs)
   int hs;
+  const int* flag;       // non-null: the pass does nothing when *flag == 0
 };
 
 // NT: ld / 16.  NBV: local blocks staged.  UPDATE: X_new = X - [V] C.
@@ -67,6 +68,7 @@ __global__ void __launch_bounds__(PT_THREADS, APPLY ? 3 : 2) panel_kernel(PanelA
   __shared__ double sX[TR * P];
   __shared__ double sV[(NEED_V ? NBV : 1) * TR * P];
 
+  if (p.flag && *p.flag == 0) return;
   const int tid = threadIdx.x;
   const int w = tid >> 6;
   const int l = tid & 63;
@@ -314,8 +316,8 @@ static void panel_dispatch(PanelMode mode, int nbv, const PanelArgs& a, int grid
 // Launch one panel pass and (when it produces a Gram) reduce it into C.
 void launch_panel(int mode, int64_t n, int ld, int nbv, const double* X, double* Xout, float* X32,
                   const double* V0, const double* V1, const double* Cupd, const double* Rm, double* part,
-                  double* Cout, hipStream_t st, double* H, int hs, bool tri0) {
-  PanelArgs a{n, X, Xout, X32, V0, V1, Cupd, Rm, part, H, hs};
+                  double* Cout, hipStream_t st, double* H, int hs, bool tri0, const int* flag) {
+  PanelArgs a{n, X, Xout, X32, V0, V1, Cupd, Rm, part, H, hs, flag};
   const PanelMode pm = (PanelMode)mode;
   // the apply passes fit three workgroups per CU (their at most one Gram
   // block of partials stays within the scratch of panel_scratch_elems)
@@ -347,7 +349,7 @@ void launch_panel(int mode, int64_t n, int ld, int nbv, const double* X, double*
   if (ngb > 0) {
     // the symmetric Gram's partials hold only its 16 x 16 tiles on and above the diagonal
     const bool sym = pm == PM_UPDATE_SELF || pm == PM_APPLY_SELF;
-    launch_reduce_parts((int64_t)ngb * ld * ld, grid, part, Cout, nullptr, st, sym ? ld : 0, 16);
+    launch_reduce_parts((int64_t)ngb * ld * ld, grid, part, Cout, flag, st, sym ? ld : 0, 16);
   }
 }
 

@@ -696,7 +696,14 @@ __device__ __forceinline__ void
 cholqr_blk_body(const double* __restrict__ G, int ld, int s, int pass, const double* __restrict__ diag_prev,
                 double thr, double* __restrict__ R, double* __restrict__ Rinv, double* __restrict__ diag_out,
                 int* __restrict__ n_defl, const double* __restrict__ R1, const double* __restrict__ R1inv,
-                double* __restrict__ Rc, double* __restrict__ Bout, double* __restrict__ BT) {
+                double* __restrict__ Rc, double* __restrict__ Bout, double* __restrict__ BT,
+                int* __restrict__ gate) {
+  // second pass not needed (decided by the first pass and the projection):
+  // counted in the slot five entries after the deflation count
+  if (pass == 2 && gate && *gate == 0) {
+    if (threadIdx.x == 0 && n_defl) n_defl[5] += 1;
+    return;
+  }
   __shared__ __align__(16) double A[WS][LP];
   __shared__ __align__(16) double Y[WS][LP];
   __shared__ __align__(16) double S1[WS][LP];
@@ -801,6 +808,51 @@ cholqr_blk_body(const double* __restrict__ G, int ld, int s, int pass, const dou
       }
     }
   for (int q = tid; q < ld; q += ST) diag_out[q] = (q < s) ? dg[q] : 0.0;
+  if (pass == 1 && gate) {
+    // One pass leaves X R^-1 orthonormal to about s u kappa(R)^2.  Bound
+    // kappa_2(R) by sqrt(|R|_1 |R|_inf |R^-1|_1 |R^-1|_inf) (R = L^T, R^-1 =
+    // Y^T): when that gives 1e-10 or better and no pivot was clamped, the
+    // first factor is final: Rc = R^-1, B = R, and the gate tells the second
+    // pass (and the Gram launch before it) to do nothing.
+    __syncthreads();
+    double nrm = 0.0;
+    const int grp = tid >> 6, q = tid & 63;
+    if (q < s) {
+      // L and L^-1 are lower triangular: row q holds columns 0..q, column q
+      // rows q..s-1 (the strict upper triangle of A still holds G)
+      const bool row = (grp & 1) == 0;
+      const int j0 = row ? 0 : q, j1 = row ? q + 1 : s;
+      for (int j = j0; j < j1; ++j) {
+        const double a = grp == 0 ? A[q][j] : (grp == 1 ? A[j][q] : (grp == 2 ? Y[q][j] : Y[j][q]));
+        nrm += fabs(a);
+      }
+    }
+    for (int o = 32; o > 0; o >>= 1) nrm = fmax(nrm, __shfl_xor(nrm, o));
+    int clamp = (q < s) ? (clf[q] != 0 || dg[q] == 0.0) : 0;
+    for (int o = 32; o > 0; o >>= 1) clamp |= __shfl_xor(clamp, o);
+    if (q == 0) {
+      red[0][grp] = nrm;
+      red[1][grp] = clamp ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    const double kap2 = red[0][0] * red[0][1] * red[0][2] * red[0][3];   // bound on kappa_2(R)^2
+    const bool clamped = red[1][0] + red[1][1] + red[1][2] + red[1][3] > 0.0;
+    const bool skip = !clamped && kap2 * (double)s * 0x1p-53 <= 1e-10;
+    if (tid == 0) *gate = skip ? 0 : 1;
+    if (skip) {
+      for (int qq = tid; qq < ld * ld; qq += ST) {
+        const int i = qq / ld, c = qq - i * ld;
+        const bool in = i < s && c < s && c >= i;
+        Rc[qq] = in ? Y[c][i] : 0.0;
+        if (BT) BT[qq] = (i < s && c < s && i >= c) ? A[i][c] : 0.0;   // R^T
+      }
+      for (int qq = tid; qq < s * s; qq += ST) {
+        const int i = qq / s, c = qq - i * s;
+        Bout[qq] = c >= i ? A[c][i] : 0.0;
+      }
+    }
+    return;
+  }
   if (pass == 2) {
     auto record = [&]() {
       if (rec) {
@@ -863,7 +915,7 @@ cholqr_blk_kernel(const double* __restrict__ G, int ld, int s, int pass, const d
                   double thr, double* __restrict__ R, double* __restrict__ Rinv, double* __restrict__ diag_out,
                   int* __restrict__ n_defl, const double* __restrict__ R1, const double* __restrict__ R1inv,
                   double* __restrict__ Rc, double* __restrict__ Bout, double* __restrict__ BT) {
-  cholqr_blk_body(G, ld, s, pass, diag_prev, thr, R, Rinv, diag_out, n_defl, R1, R1inv, Rc, Bout, BT);
+  cholqr_blk_body(G, ld, s, pass, diag_prev, thr, R, Rinv, diag_out, n_defl, R1, R1inv, Rc, Bout, BT, nullptr);
 }
 
 // A batch of independent factorisations, one workgroup each (the serving
@@ -874,7 +926,7 @@ struct CholqrBatch {
 __global__ void __launch_bounds__(ST) cholqr_blk_batch_kernel(CholqrBatch b) {
   const CholqrArgs& a = b.a[blockIdx.x];
   cholqr_blk_body(a.G, a.ld, a.s, a.pass, a.diag_prev, a.thr, a.R, a.Rinv, a.diag_out, a.n_defl, a.R1, a.R1inv,
-                  a.Rc, a.Bout, a.BT);
+                  a.Rc, a.Bout, a.BT, a.gate);
 }
 
 // 64 x 16 column slices of a product (the orthogonality estimate below).
@@ -1061,7 +1113,7 @@ void launch_cholqr_reg_batched(const CholqrArgs* a, int count, hipStream_t st) {
 void launch_omega(int k, int s, int ld, const double* Wk, const double* Wkm1, double* Wk1, const double* Hd,
                   const double* Bd, const double* Rc, double nu, double tau, double floor_re, double floor_loc,
                   double* est_part, int* fr, int* forced, double* est_out, int* nre, double* rhs_wide,
-                  hipStream_t st, OmegaDecide* defer) {
+                  hipStream_t st, OmegaDecide* defer, int* gate) {
   const int nj = k - 1;   // recurrence for j <= k-2
   if (nj > 0) {
     if (s > WS) {
@@ -1076,7 +1128,8 @@ void launch_omega(int k, int s, int ld, const double* Wk, const double* Wkm1, do
     }
   }
   const int ne = nj > 0 ? nj * omega_est_per_block(s) : 0;
-  const OmegaDecide d{k, s, nj > 0 ? nj : 0, ne, est_part, tau, floor_re, floor_loc, Wk1, fr, forced, est_out, nre};
+  const OmegaDecide d{k, s, nj > 0 ? nj : 0, ne, est_part, tau, floor_re, floor_loc, Wk1, fr, forced, est_out, nre,
+                      gate};
   if (defer) {
     *defer = d;
     return;

@@ -192,7 +192,13 @@ cholqr_wide_body(const double* __restrict__ G, int ld, int s, int pass, const do
                    double thr, double* __restrict__ Aw, double* __restrict__ Yw, double* __restrict__ R,
                    double* __restrict__ Rinv, double* __restrict__ diag_out, int* __restrict__ n_defl,
                    const double* __restrict__ R1, const double* __restrict__ R1inv, double* __restrict__ Rc,
-                   double* __restrict__ Bout, double* __restrict__ BT) {
+                   double* __restrict__ Bout, double* __restrict__ BT, int* __restrict__ gate) {
+  // second pass not needed (decided by the first pass and the projection):
+  // counted in the slot five entries after the deflation count
+  if (pass == 2 && gate && *gate == 0) {
+    if (threadIdx.x == 0 && n_defl) n_defl[5] += 1;
+    return;
+  }
   __shared__ __align__(16) double T0[WS][LP];
   __shared__ __align__(16) double T1[WS][LP];
   __shared__ __align__(16) double T2[WS][LP];
@@ -220,6 +226,72 @@ cholqr_wide_body(const double* __restrict__ G, int ld, int s, int pass, const do
       Rinv[q] = in ? Yw[(int64_t)c * ld + i] : 0.0;
     }
   for (int q = tid; q < ld; q += ST) diag_out[q] = (q < s) ? dg[q] : 0.0;
+  if (pass == 1 && gate) {
+    // One pass leaves X R^-1 orthonormal to about s u kappa(R)^2.  Bound
+    // kappa_2(R)^2 by |L|_1 |L|_inf |L^-1|_1 |L^-1|_inf (R = L^T); when that
+    // gives 1e-10 or better and no pivot was clamped, the first factor is
+    // final (Rc = R^-1, B = R) and the gate tells the second pass (and the
+    // Gram launch before it) to do nothing.  Column sums one thread per
+    // column, row sums one wavefront per row (both lower triangles).
+    __shared__ double nred[5][ST / 64];
+    __syncthreads();
+    const int lane = tid & 63, wv = tid >> 6;
+    double c1 = 0.0, c2 = 0.0, r1 = 0.0, r2 = 0.0;
+    for (int c = tid; c < s; c += ST) {
+      double a = 0.0, b = 0.0;
+      for (int i = c; i < s; ++i) {
+        a += fabs(Aw[(int64_t)i * ld + c]);
+        b += fabs(Yw[(int64_t)i * ld + c]);
+      }
+      c1 = fmax(c1, a);
+      c2 = fmax(c2, b);
+    }
+    for (int i = wv; i < s; i += ST / 64) {
+      double a = 0.0, b = 0.0;
+      for (int j = lane; j <= i; j += 64) {
+        a += fabs(Aw[(int64_t)i * ld + j]);
+        b += fabs(Yw[(int64_t)i * ld + j]);
+      }
+      for (int o = 32; o > 0; o >>= 1) {
+        a += __shfl_xor(a, o);
+        b += __shfl_xor(b, o);
+      }
+      r1 = fmax(r1, a);
+      r2 = fmax(r2, b);
+    }
+    double cl = 0.0;
+    for (int q = tid; q < s; q += ST) cl = (clf[q] != 0 || dg[q] == 0.0) ? 1.0 : cl;
+    for (int o = 32; o > 0; o >>= 1) {
+      c1 = fmax(c1, __shfl_xor(c1, o));
+      c2 = fmax(c2, __shfl_xor(c2, o));
+      cl = fmax(cl, __shfl_xor(cl, o));
+    }
+    if (lane == 0) {
+      nred[0][wv] = c1;
+      nred[1][wv] = c2;
+      nred[2][wv] = r1;
+      nred[3][wv] = r2;
+      nred[4][wv] = cl;
+    }
+    __syncthreads();
+    double nm[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int w = 0; w < ST / 64; ++w)
+      for (int t = 0; t < 5; ++t) nm[t] = fmax(nm[t], nred[t][w]);
+    const bool skip = nm[4] == 0.0 && nm[0] * nm[1] * nm[2] * nm[3] * (double)s * 0x1p-53 <= 1e-10;
+    if (tid == 0) *gate = skip ? 0 : 1;
+    if (skip) {
+      for (int q = tid; q < ld * ld; q += ST) {
+        const int i = q / ld, c = q - i * ld;
+        Rc[q] = (i < s && c < s && c >= i) ? Yw[(int64_t)c * ld + i] : 0.0;
+        if (BT) BT[q] = (i < s && c < s && i >= c) ? Aw[(int64_t)i * ld + c] : 0.0;   // R^T
+      }
+      for (int q = tid; q < s * s; q += ST) {
+        const int i = q / s, c = q - i * s;
+        Bout[q] = c >= i ? Aw[(int64_t)c * ld + i] : 0.0;
+      }
+    }
+    return;
+  }
   if (pass != 2) return;
   if (tid == 0 && n_defl) {
     int cnt = 0;
@@ -260,7 +332,8 @@ cholqr_wide_kernel(const double* __restrict__ G, int ld, int s, int pass, const 
                    double* __restrict__ Rinv, double* __restrict__ diag_out, int* __restrict__ n_defl,
                    const double* __restrict__ R1, const double* __restrict__ R1inv, double* __restrict__ Rc,
                    double* __restrict__ Bout, double* __restrict__ BT) {
-  cholqr_wide_body(G, ld, s, pass, diag_prev, thr, Aw, Yw, R, Rinv, diag_out, n_defl, R1, R1inv, Rc, Bout, BT);
+  cholqr_wide_body(G, ld, s, pass, diag_prev, thr, Aw, Yw, R, Rinv, diag_out, n_defl, R1, R1inv, Rc, Bout, BT,
+                   nullptr);
 }
 
 struct CholqrWideBatch {
@@ -269,7 +342,7 @@ struct CholqrWideBatch {
 __global__ void __launch_bounds__(ST) cholqr_wide_batch_kernel(CholqrWideBatch b) {
   const CholqrArgs& a = b.a[blockIdx.x];
   cholqr_wide_body(a.G, a.ld, a.s, a.pass, a.diag_prev, a.thr, a.wk, a.wk + (size_t)a.ld * a.ld, a.R, a.Rinv,
-                   a.diag_out, a.n_defl, a.R1, a.R1inv, a.Rc, a.Bout, a.BT);
+                   a.diag_out, a.n_defl, a.R1, a.R1inv, a.Rc, a.Bout, a.BT, a.gate);
 }
 
 size_t cholqr_wide_scratch_elems(int ld) { return (size_t)2 * ld * ld; }

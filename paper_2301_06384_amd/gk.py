@@ -54,6 +54,7 @@ class Stats(C.Structure):
                 ("t_fit_ms", C.c_double), ("spmm_launches", C.c_double), ("bytes_spmm", C.c_double),
                 ("resid_norm", C.c_double), ("orth_est", C.c_double), ("n_reorth", C.c_int32),
                 ("n_deflated", C.c_int32), ("phi_method", C.c_int32), ("n_qr2_series", C.c_int32),
+                ("n_qr2_skipped", C.c_int32),
                 ("footprint_bytes", C.c_uint64)]
 
     def as_dict(self):
