@@ -241,6 +241,27 @@ def test_wide_blocks(s, phi):
             assert st.as_dict()["phi_method"] == "banded"
 
 
+@pytest.mark.parametrize("s", [16, 64, 100, 256])
+def test_second_cholqr_pass_gate(s):
+    # the mixed path leaves out the second CholQR pass where the first factor
+    # is final (well-conditioned blocks, no archive projection at that step);
+    # the float64 path always takes both passes
+    L, g = G("rgg2003")
+    W = I.samples(L.n, s, 300 + s)
+    phi = dict(kind="spline", eps=0.01, k=2.0)
+    m = 14 if s <= 100 else 6
+    ref = krylov.cbl(L.to_scipy(), W, phi, m)["P"]
+    P, K, st = gk.krylov_kernel_columns(g, W, phi, m, "cbl", "mixed")
+    assert rel(P, ref) < TOL["mixed"], rel(P, ref)
+    print(f"s={s} m={m}: second CholQR passes left out {st.n_qr2_skipped}, projections {st.n_reorth}")
+    assert 0 <= st.n_qr2_skipped <= (m - 1) - st.n_reorth, (st.n_qr2_skipped, st.n_reorth)
+    if s <= 100:
+        assert st.n_qr2_skipped > 0
+    P64, K64, st64 = gk.krylov_kernel_columns(g, W, phi, m, "cbl", "fp64")
+    assert st64.n_qr2_skipped == 0
+    assert rel(P, P64) < TOL["mixed"]
+
+
 @pytest.mark.parametrize("s,m", [(16, 1), (16, 2), (16, 3), (16, 5), (16, 8), (16, 13), (16, 31), (64, 2),
                                  (64, 5), (64, 7)])
 def test_cyclic_reduction_spline_matches_spectral(s, m):
