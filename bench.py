@@ -179,6 +179,107 @@ def _progress(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+# ------------------------------------------------ rocprofv3 summaries (host)
+def kernel_class_of(name: str):
+    """Kernel class (as the library's own timings name them) of a rocprofv3
+    kernel name, or None for kernels outside the path."""
+    base = name.split("(")[0]
+    args = []
+    if "<" in base:
+        args = [a.strip() for a in base[base.index("<") + 1:base.rindex(">")].split(",")]
+        base = base[:base.index("<")]
+    base = base.split("::")[-1]
+    if base.startswith("panel_kernel") and len(args) >= 8:
+        upd, app, grv, slf = (a == "true" for a in args[2:6])
+        return ("panel_gramv" if grv else "panel_update_self" if upd else
+                "panel_apply_self" if (app and slf) else "panel_apply_write")
+    if base.startswith("tsgemm_mfma_kernel"):
+        return "assemble" if len(args) >= 2 and args[1] == "true" else "tsgemm"
+    table = [("spmm_", "spmm_diff"), ("reduce_parts", "reduce_parts"), ("arch_gram", "arch_gram"),
+             ("arch_update", "arch_update"), ("arch_assemble", "assemble"), ("gram_", "gram"),
+             ("tsgemm", "tsgemm"), ("predict", "predict"), ("cholqr", "cholqr"), ("omega", "omega"),
+             ("bcr_", "banded"), ("banded_", "banded"), ("btd_cheb", "cheb_step"), ("jacobi", "jacobi_eig")]
+    for pre, cls in table:
+        if base.startswith(pre):
+            return cls
+    return None
+
+
+def _csv_rows(d, suffix):
+    import csv
+    import glob
+    files = sorted(glob.glob(os.path.join(d, "**", f"*{suffix}"), recursive=True))
+    if not files:
+        raise SystemExit(f"no *{suffix} under {d}")
+    with open(files[-1], newline="") as fh:
+        return list(csv.DictReader(fh))
+
+
+def summarize_profiles(stats_dir, fetch_dir, write_dir, workload, tag, cmd_stats, cmd_pmc):
+    """Write profiles/kernel_stats_<tag>.txt from a `rocprofv3 --kernel-trace
+    --stats` run and profiles/<class>_<tag>_traffic.txt from two `--pmc` runs
+    (FETCH_SIZE, WRITE_SIZE) of `bench.py --counters`, whose 1 GiB copy
+    calibrates the byte counters."""
+    out = os.path.join(ROOT, "profiles")
+    if stats_dir:
+        rows = _csv_rows(stats_dir, "kernel_stats.csv")
+        lines = [f"# rocprofv3 kernel statistics, benchmark workload {workload}",
+                 f"# command: {cmd_stats}",
+                 f"# {'kernel':<62} {'calls':>6} {'total_ms':>10} {'avg_us':>10} {'min_us':>9} {'max_us':>9}"]
+        rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+        for r in rows:
+            lines.append(f"{r['Name'][:62]:<64} {int(r['Calls']):>6} {float(r['TotalDurationNs']) * 1e-6:>10.3f} "
+                         f"{float(r['AverageNs']) * 1e-3:>10.2f} {float(r['MinNs']) * 1e-3:>9.2f} "
+                         f"{float(r['MaxNs']) * 1e-3:>9.2f}")
+        with open(os.path.join(out, f"kernel_stats_{tag}.txt"), "w") as fh:
+            fh.write("\n".join(lines) + "\n")
+    if not (fetch_dir and write_dir):
+        return
+    per = {}
+    calib = {}
+    for ctr, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        disp = {}
+        for r in _csv_rows(d, "counter_collection.csv"):
+            if r.get("Counter_Name") != ctr:
+                continue
+            key = (r["Dispatch_Id"], r["Kernel_Name"])
+            disp[key] = disp.get(key, 0.0) + float(r["Counter_Value"])
+        copies = [v for (i, nm), v in disp.items() if "copyBuffer" in nm or "copy" in nm.lower()]
+        if not copies:
+            raise SystemExit(f"{ctr}: the calibration copy is missing")
+        calib[ctr] = max(copies)
+        for (i, nm), v in disp.items():
+            cls = kernel_class_of(nm)
+            if cls is None:
+                continue
+            e = per.setdefault(cls, {}).setdefault(ctr, [])
+            e.append(v)
+    nbytes = float(1 << 30)
+    fs = nbytes / 1024.0 / calib["FETCH_SIZE"]   # KiB counted per KiB moved
+    ws = nbytes / 1024.0 / calib["WRITE_SIZE"]
+    for cls, c in sorted(per.items()):
+        if "FETCH_SIZE" not in c or "WRITE_SIZE" not in c:
+            continue
+        fk = sum(c["FETCH_SIZE"]) / len(c["FETCH_SIZE"])
+        wk = sum(c["WRITE_SIZE"]) / len(c["WRITE_SIZE"])
+        srcs = _sources(cls) if (cls in CLASSES or cls in LATENCY) else ["small.hip"]
+        lines = [f"# HBM traffic of {cls} per dispatch, benchmark workload {workload} (one mixed step)",
+                 f"# commands: {cmd_pmc.format(ctr='FETCH_SIZE')}  ;  {cmd_pmc.format(ctr='WRITE_SIZE')}",
+                 f"# calibration: bench.py --counters copies 1 GiB device-to-device after the step; the counters "
+                 f"read FETCH_SIZE {calib['FETCH_SIZE']:.1f} KiB and WRITE_SIZE {calib['WRITE_SIZE']:.1f} KiB for it",
+                 f"kernel: {cls}",
+                 f"source_files: {' '.join(srcs)}",
+                 f"source_hash: {_kernel_hash(srcs)}",
+                 f"dispatches: {len(c['FETCH_SIZE'])}",
+                 f"fetch_kib_per_dispatch: {fk:.3f}",
+                 f"write_kib_per_dispatch: {wk:.3f}",
+                 f"fetch_scale: {fs:.5f}",
+                 f"write_scale: {ws:.5f}",
+                 f"hbm_bytes_per_launch: {1024.0 * (fk * fs + wk * ws):.1f}"]
+        with open(os.path.join(out, f"{cls}_{tag}_traffic.txt"), "w") as fh:
+            fh.write("\n".join(lines) + "\n")
+
+
 def serving_bench(gk, I, n_req: int, seed: int = 0, max_active: int = 8, n_streams: int = 16):
     """Serving workload: 8 resident random geometric graphs (N 10k..500k),
     requests with s ~ U{4..128}, diffusion or spline kernels, m = 30, cbl,
@@ -342,7 +443,21 @@ def main():
     ap.add_argument("--counters", action="store_true",
                     help="for hardware-counter runs: one mixed step, then a 1 GiB device-to-device copy of "
                          "known size (calibration of the byte counters); prints no benchmark line")
+    ap.add_argument("--summarize", nargs=3, metavar=("STATS_DIR", "FETCH_DIR", "WRITE_DIR"),
+                    help="host only: write the profiles/ summaries from rocprofv3 output directories "
+                         "('-' skips one) and exit")
     args = ap.parse_args()
+    if args.summarize:
+        sd, fd, wd = (None if x == "-" else x for x in args.summarize)
+        tag = {"rgg100k_spline": "rgg100k_s64"}.get(args.workload, args.workload)
+        pre = "cd /tmp && export TMPDIR=/tmp && "
+        summarize_profiles(sd, fd, wd, args.workload, tag,
+                           pre + "rocprofv3 --kernel-trace --stats --output-format csv -d <out>/prof_stats -o stats "
+                                 "-- python3 <repo>/bench.py --steps 3 --warmup 1 --no-cpu --serving-requests 0 "
+                                 "--legs ''",
+                           pre + "rocprofv3 --pmc {ctr} --output-format csv -d <out>/pmc -o pmc -- python3 "
+                                 "<repo>/bench.py --counters")
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); multi-GPU sharding is not built",
               file=sys.stderr)

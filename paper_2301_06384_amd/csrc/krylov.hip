@@ -452,10 +452,12 @@ struct CblRun {
   double* Wr[3] = {nullptr, nullptr, nullptr};
   double *est_part = nullptr, *om_rhs = nullptr, *part_all = nullptr, *part_arch = nullptr;
   int *fr = nullptr, *forced = nullptr;
-  // GK_MIXED on the single-workgroup factorisations: the first CholQR pass
-  // sets *gate = 0 when its factor is final, the archive projection sets it
-  // back to 1; the Gram of X R1^-1 and the second pass run only at 1
+  // GK_MIXED on the single-workgroup factorisations, one entry per step: the
+  // first CholQR pass sets gate[k] = 0 when its factor is final, the archive
+  // projection sets it back to 1; the Gram of X R1^-1 and the second pass run
+  // only at 1
   int* gate = nullptr;
+  int* gk(int k) const { return gate ? gate + k : nullptr; }
   // tolerances of the estimate: threshold (semi-orthogonality at the square
   // root of the unit roundoff of the float32 archive, 2^-12), floor after a
   // reorthogonalisation against the float32 archive, floor of the two
@@ -521,7 +523,7 @@ struct CblRun {
     launch_start_block(n, ld, s, J.samp, 1.0, V64(0), mixed ? Va : nullptr, st);
     pan = panel_ok(ld);
     if (pan) ppart = J.ar.get<double>(panel_scratch_elems(n, ld));
-    if (mixed && (wave || widek)) gate = J.ar.get<int>(1);
+    if (mixed && (wave || widek)) gate = J.ar.get<int>(m);
     // partial reorthogonalisation (GK_MIXED, s <= 512): block omega estimate,
     // reorthogonalisation against the float32 archive only when it is needed
     pro = mixed && !full && !no_reorth && (wave || widek) && m > 2;
@@ -620,8 +622,8 @@ struct CblRun {
     double* R12k = two ? Rst + (int64_t)k * l2 : R12i;
     double* BT = (mixed && (pan || widek)) ? C : nullptr;
     if (!gate) return CholqrArgs{G, ld, s, 1, nullptr, J.thr(), W, R1, R1i, d1};
-    return CholqrArgs{G,       ld,      s,       1,    nullptr, J.thr(), W, R1, R1i, d1, nullptr, nullptr, nullptr,
-                      R12k, Bd + (int64_t)k * s * s, BT, gate};
+    return CholqrArgs{G,       ld,      s,       1, nullptr, J.thr(), W, R1, R1i, d1, nullptr, nullptr, nullptr, R12k,
+                      Bd + (int64_t)k * s * s, BT, gk(k)};
   }
   // pass 2 factors the Gram of X R1^-1; the mixed recurrence takes
   // H_{k,k+1} = B_k^T of the next step from C
@@ -629,7 +631,7 @@ struct CblRun {
     double* R12k = two ? Rst + (int64_t)k * l2 : R12i;
     double* BT = (mixed && (pan || widek)) ? C : nullptr;
     return CholqrArgs{G, ld, s, 2, d1, J.thr(), W, nullptr, nullptr, d2, J.dflags + 1, R1, R1i, R12k,
-                      Bd + (int64_t)k * s * s, BT, gate};
+                      Bd + (int64_t)k * s * s, BT, gk(k)};
   }
   void qr1(int k) {
     if (wave) launch_cholqr_reg_batched(&qr1_args_storage(k), 1, st);
@@ -674,7 +676,7 @@ struct CblRun {
       OmegaDecide dec{};
       launch_omega(k, s, ld, Wr[k % 3], Wr[(k + 2) % 3], Wr[(k + 1) % 3], Hd, Bd, R1i, om_nu, om_tau, om_floor_re,
                    om_floor_loc, est_part, fr, forced, J.dscal + 1, J.dflags + 3, om_rhs, st, defer ? &dec : nullptr,
-                   gate);
+                   gk(k));
       if (k >= 2) {
         J.tm.begin(PH_REORTH);
         BlockList all{Va, blk, k - 1, true};
@@ -689,12 +691,12 @@ struct CblRun {
     }
     if (pan) {
       launch_panel(PM_APPLY_SELF, n, ld, 0, X, nullptr, nullptr, nullptr, nullptr, nullptr, R1i, ppart, G, st,
-                   nullptr, 0, false, gate);
+                   nullptr, 0, false, gk(k));
     } else {
       BlockList xl{X, blk, 1, false};
-      launch_tsgemm(n, ld, xl, R1i, nullptr, Y, nullptr, 1.0, 0.0, gate, st, true);
+      launch_tsgemm(n, ld, xl, R1i, nullptr, Y, nullptr, 1.0, 0.0, gk(k), st, true);
       BlockList yl{Y, blk, 1, false};
-      launch_gram(n, ld, yl, Y, G, part, gate, st);
+      launch_gram(n, ld, yl, Y, G, part, gk(k), st);
     }
   }
 

@@ -342,7 +342,7 @@ void launch_panel(int mode, int64_t n, int ld, int nbv, const double* X, double*
     case 64: panel_dispatch<4>(pm, nbv, a, grid, st); break;
     default: throw Error{GK_EUNSUPPORTED, "panel kernel needs ld in {16,32,48,64}"};
   }
-  kt_end(st, kb, kf);
+  kt_end(st, kb, kf, flag);
   int ngb = 0;
   if (pm == PM_GRAMV) ngb = nbv;
   if (pm == PM_UPDATE_SELF || pm == PM_APPLY_SELF) ngb = 1;

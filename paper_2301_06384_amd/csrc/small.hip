@@ -708,7 +708,7 @@ cholqr_blk_body(const double* __restrict__ G, int ld, int s, int pass, const dou
   __shared__ __align__(16) double Y[WS][LP];
   __shared__ __align__(16) double S1[WS][LP];
   __shared__ __align__(16) double S2[WS][LP];
-  __shared__ double g0[WS], dp[WS], dg[WS];
+  __shared__ double g0[WS], dp[WS], dg[WS], dq[WS];
   __shared__ int clf[WS];
   __shared__ double red[2][ST];
   const int tid = threadIdx.x;
@@ -732,6 +732,7 @@ cholqr_blk_body(const double* __restrict__ G, int ld, int s, int pass, const dou
   for (int q = tid; q < s; q += ST) {
     g0[q] = G[q * ld + q];
     dp[q] = (pass == 2) ? diag_prev[q] : 0.0;
+    if (pass == 1 && gate) dq[q] = sqrt(fmax(g0[q], 0.0));
   }
   __syncthreads();
   // Second pass with G = I + E, |E| <= 1e-6 and no column near the deflation
@@ -796,6 +797,52 @@ cholqr_blk_body(const double* __restrict__ G, int ld, int s, int pass, const dou
   } else {
     blk_chol_inv(A, Y, S1, s, pass, g0, dp, thr, dg, nullptr, clf);
   }
+  // Pass 1 with a gate: one pass leaves X R^-1 orthonormal to about
+  // s u |D R^-1|_2^2 with D = diag(G)^(1/2) (Gram and Cholesky errors are
+  // relative to the column norms), and |D R^-1|_2^2 <= |Z|_1 |Z|_inf for
+  // Z = L^-1 D (R = L^T, L^-1 in Y).  When that gives 1e-10 or better and no
+  // pivot was clamped, the first factor is final: Rc = R^-1, B = R and B^T
+  // are written with R and R^-1 below, and the gate tells the second pass
+  // (and the Gram launch before it) to do nothing.
+  // Thread (q, h): row q and column q of Z over entries 16h .. 16h+15.
+  __shared__ int skip_s;
+  bool sk = false;
+  if (pass == 1 && gate) {
+    const int q = tid & 63, h = tid >> 6;
+    double rs = 0.0, cs = 0.0;
+#pragma unroll
+    for (int jj = 0; jj < 16; ++jj) {
+      const int j = 16 * h + jj;
+      const bool inr = q < s && j <= q, inc = q < s && j < s && j >= q;
+      const double zr = Y[q][j], zc = Y[j][q];
+      rs += inr ? fabs(zr) * dq[j] : 0.0;
+      cs += inc ? fabs(zc) : 0.0;
+    }
+    red[0][tid] = rs;
+    red[1][tid] = cs;
+    __syncthreads();
+    if (tid < 64) {
+      double r = 0.0, c = 0.0;
+      for (int hh = 0; hh < 4; ++hh) {
+        r += red[0][64 * hh + q];
+        c += red[1][64 * hh + q];
+      }
+      c *= (q < s) ? dq[q] : 0.0;
+      double cl = (q < s && (clf[q] != 0 || dg[q] == 0.0)) ? 1.0 : 0.0;
+      for (int o = 32; o > 0; o >>= 1) {
+        r = fmax(r, __shfl_xor(r, o));
+        c = fmax(c, __shfl_xor(c, o));
+        cl = fmax(cl, __shfl_xor(cl, o));
+      }
+      if (tid == 0) {
+        const bool skip = cl == 0.0 && r * c * (double)s * 0x1p-53 <= 1e-10;
+        *gate = skip ? 0 : 1;
+        skip_s = skip ? 1 : 0;
+      }
+    }
+    __syncthreads();
+    sk = skip_s != 0;
+  }
   // R = L^T, Rinv = Y^T (upper), coalesced stores with zero padding; skipped
   // when the caller passes null (pass 2 returns its factors through Rc and B)
   if (R)
@@ -803,56 +850,18 @@ cholqr_blk_body(const double* __restrict__ G, int ld, int s, int pass, const dou
       const int c = tid & 63;   // ld <= 64: one row per wavefront pass
       if (c < ld) {
         const bool in = i < s && c < s && c >= i;
-        R[i * ld + c] = in ? A[c][i] : 0.0;
-        Rinv[i * ld + c] = in ? Y[c][i] : 0.0;
+        const double r = in ? A[c][i] : 0.0, ri = in ? Y[c][i] : 0.0;
+        R[i * ld + c] = r;
+        Rinv[i * ld + c] = ri;
+        if (sk) {
+          Rc[i * ld + c] = ri;
+          if (BT) BT[i * ld + c] = (i < s && c < s && i >= c) ? A[i][c] : 0.0;   // R^T
+          if (i < s && c < s) Bout[i * s + c] = r;
+        }
       }
     }
   for (int q = tid; q < ld; q += ST) diag_out[q] = (q < s) ? dg[q] : 0.0;
-  if (pass == 1 && gate) {
-    // One pass leaves X R^-1 orthonormal to about s u kappa(R)^2.  Bound
-    // kappa_2(R) by sqrt(|R|_1 |R|_inf |R^-1|_1 |R^-1|_inf) (R = L^T, R^-1 =
-    // Y^T): when that gives 1e-10 or better and no pivot was clamped, the
-    // first factor is final: Rc = R^-1, B = R, and the gate tells the second
-    // pass (and the Gram launch before it) to do nothing.
-    __syncthreads();
-    double nrm = 0.0;
-    const int grp = tid >> 6, q = tid & 63;
-    if (q < s) {
-      // L and L^-1 are lower triangular: row q holds columns 0..q, column q
-      // rows q..s-1 (the strict upper triangle of A still holds G)
-      const bool row = (grp & 1) == 0;
-      const int j0 = row ? 0 : q, j1 = row ? q + 1 : s;
-      for (int j = j0; j < j1; ++j) {
-        const double a = grp == 0 ? A[q][j] : (grp == 1 ? A[j][q] : (grp == 2 ? Y[q][j] : Y[j][q]));
-        nrm += fabs(a);
-      }
-    }
-    for (int o = 32; o > 0; o >>= 1) nrm = fmax(nrm, __shfl_xor(nrm, o));
-    int clamp = (q < s) ? (clf[q] != 0 || dg[q] == 0.0) : 0;
-    for (int o = 32; o > 0; o >>= 1) clamp |= __shfl_xor(clamp, o);
-    if (q == 0) {
-      red[0][grp] = nrm;
-      red[1][grp] = clamp ? 1.0 : 0.0;
-    }
-    __syncthreads();
-    const double kap2 = red[0][0] * red[0][1] * red[0][2] * red[0][3];   // bound on kappa_2(R)^2
-    const bool clamped = red[1][0] + red[1][1] + red[1][2] + red[1][3] > 0.0;
-    const bool skip = !clamped && kap2 * (double)s * 0x1p-53 <= 1e-10;
-    if (tid == 0) *gate = skip ? 0 : 1;
-    if (skip) {
-      for (int qq = tid; qq < ld * ld; qq += ST) {
-        const int i = qq / ld, c = qq - i * ld;
-        const bool in = i < s && c < s && c >= i;
-        Rc[qq] = in ? Y[c][i] : 0.0;
-        if (BT) BT[qq] = (i < s && c < s && i >= c) ? A[i][c] : 0.0;   // R^T
-      }
-      for (int qq = tid; qq < s * s; qq += ST) {
-        const int i = qq / s, c = qq - i * s;
-        Bout[qq] = c >= i ? A[c][i] : 0.0;
-      }
-    }
-    return;
-  }
+  if (pass == 1) return;
   if (pass == 2) {
     auto record = [&]() {
       if (rec) {

@@ -183,6 +183,34 @@ __device__ __forceinline__ void wide_chol_inv(double* __restrict__ A, double* __
   __syncthreads();
 }
 
+// dst (ld x ld) = the transpose of the lower triangle of src (ld x ld), zero
+// padded, through 64 x 64 LDS tiles (coalesced reads and writes); dst2
+// (non-null) receives its leading n2 x n2 block with leading dimension n2.
+__device__ __forceinline__ void put_upper_transposed(double* __restrict__ dst, double* __restrict__ dst2, int n2,
+                                                     const double* __restrict__ src, int ld, int s,
+                                                     double (*T)[LP]) {
+  const int tid = threadIdx.x, tx = tid & 63, ty = tid >> 6;
+  const int nT = (ld + 63) >> 6;
+  for (int I = 0; I < nT; ++I)
+    for (int J = 0; J < nT; ++J) {
+      if (I <= J) {
+        __syncthreads();
+        for (int r = ty; r < 64; r += ST / 64) {
+          const int gr = 64 * J + r, gc = 64 * I + tx;
+          T[r][tx] = (gr < s && gc < s && gc <= gr) ? src[(int64_t)gr * ld + gc] : 0.0;
+        }
+        __syncthreads();
+      }
+      for (int r = ty; r < 64; r += ST / 64) {
+        const int gr = 64 * I + r, gc = 64 * J + tx;
+        const double v = (I <= J) ? T[tx][r] : 0.0;
+        if (gr < ld && gc < ld) dst[(int64_t)gr * ld + gc] = v;
+        if (dst2 && gr < n2 && gc < n2) dst2[(int64_t)gr * n2 + gc] = v;
+      }
+    }
+  __syncthreads();
+}
+
 // ---------------------------------------------------------------- CholQR
 // Same factor as the 64-wide kernel (pass 1: clamped pivots, pass 2:
 // combined-diagonal deflation, then Rc = R1inv R2inv and B = R2 R1), for
@@ -217,81 +245,65 @@ cholqr_wide_body(const double* __restrict__ G, int ld, int s, int pass, const do
     wide_chol_inv<1>(Aw, Yw, ld, s, g0, dp, thr, dg, nullptr, clf, T0, T1, T2, T3);
   else
     wide_chol_inv<2>(Aw, Yw, ld, s, g0, dp, thr, dg, nullptr, clf, T0, T1, T2, T3);
-  // R = L^T, Rinv = Y^T (upper, zero padded); skipped when R is null
-  if (R)
-    for (int q = tid; q < ld * ld; q += ST) {
-      const int i = q / ld, c = q % ld;
-      const bool in = i < s && c < s && c >= i;
-      R[q] = in ? Aw[(int64_t)c * ld + i] : 0.0;
-      Rinv[q] = in ? Yw[(int64_t)c * ld + i] : 0.0;
-    }
-  for (int q = tid; q < ld; q += ST) diag_out[q] = (q < s) ? dg[q] : 0.0;
+  // Pass 1 with a gate: one pass leaves X R^-1 orthonormal to about
+  // s u |D R^-1|_2^2 with D = diag(G)^(1/2) (Gram and Cholesky errors are
+  // relative to the column norms), and |D R^-1|_2^2 <= |Z|_1 |Z|_inf for
+  // Z = L^-1 D (R = L^T, L^-1 in Yw).  When that gives 1e-10 or better and
+  // no pivot was clamped, the first factor is final: Rc = R^-1, B = R and
+  // B^T are written with R and R^-1 below, and the gate tells the second
+  // pass (and the Gram launch before it) to do nothing.  Column sums one
+  // thread per column, row sums one wavefront per row.
+  bool sk = false;
   if (pass == 1 && gate) {
-    // One pass leaves X R^-1 orthonormal to about s u kappa(R)^2.  Bound
-    // kappa_2(R)^2 by |L|_1 |L|_inf |L^-1|_1 |L^-1|_inf (R = L^T); when that
-    // gives 1e-10 or better and no pivot was clamped, the first factor is
-    // final (Rc = R^-1, B = R) and the gate tells the second pass (and the
-    // Gram launch before it) to do nothing.  Column sums one thread per
-    // column, row sums one wavefront per row (both lower triangles).
-    __shared__ double nred[5][ST / 64];
-    __syncthreads();
+    __shared__ double nred[3][ST / 64];
+    __shared__ int skip_s;
     const int lane = tid & 63, wv = tid >> 6;
-    double c1 = 0.0, c2 = 0.0, r1 = 0.0, r2 = 0.0;
+    double cmax = 0.0, rmax = 0.0, cl = 0.0;
     for (int c = tid; c < s; c += ST) {
-      double a = 0.0, b = 0.0;
-      for (int i = c; i < s; ++i) {
-        a += fabs(Aw[(int64_t)i * ld + c]);
-        b += fabs(Yw[(int64_t)i * ld + c]);
-      }
-      c1 = fmax(c1, a);
-      c2 = fmax(c2, b);
+      double a = 0.0;
+      for (int i = c; i < s; ++i) a += fabs(Yw[(int64_t)i * ld + c]);
+      cmax = fmax(cmax, a * sqrt(fmax(g0[c], 0.0)));
+      cl = (clf[c] != 0 || dg[c] == 0.0) ? 1.0 : cl;
     }
     for (int i = wv; i < s; i += ST / 64) {
-      double a = 0.0, b = 0.0;
-      for (int j = lane; j <= i; j += 64) {
-        a += fabs(Aw[(int64_t)i * ld + j]);
-        b += fabs(Yw[(int64_t)i * ld + j]);
-      }
-      for (int o = 32; o > 0; o >>= 1) {
-        a += __shfl_xor(a, o);
-        b += __shfl_xor(b, o);
-      }
-      r1 = fmax(r1, a);
-      r2 = fmax(r2, b);
+      double a = 0.0;
+      for (int j = lane; j <= i; j += 64) a += fabs(Yw[(int64_t)i * ld + j]) * sqrt(fmax(g0[j], 0.0));
+      for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o);
+      rmax = fmax(rmax, a);
     }
-    double cl = 0.0;
-    for (int q = tid; q < s; q += ST) cl = (clf[q] != 0 || dg[q] == 0.0) ? 1.0 : cl;
     for (int o = 32; o > 0; o >>= 1) {
-      c1 = fmax(c1, __shfl_xor(c1, o));
-      c2 = fmax(c2, __shfl_xor(c2, o));
+      cmax = fmax(cmax, __shfl_xor(cmax, o));
       cl = fmax(cl, __shfl_xor(cl, o));
     }
     if (lane == 0) {
-      nred[0][wv] = c1;
-      nred[1][wv] = c2;
-      nred[2][wv] = r1;
-      nred[3][wv] = r2;
-      nred[4][wv] = cl;
+      nred[0][wv] = cmax;
+      nred[1][wv] = rmax;
+      nred[2][wv] = cl;
     }
     __syncthreads();
-    double nm[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int w = 0; w < ST / 64; ++w)
-      for (int t = 0; t < 5; ++t) nm[t] = fmax(nm[t], nred[t][w]);
-    const bool skip = nm[4] == 0.0 && nm[0] * nm[1] * nm[2] * nm[3] * (double)s * 0x1p-53 <= 1e-10;
-    if (tid == 0) *gate = skip ? 0 : 1;
-    if (skip) {
+    if (tid == 0) {
+      double nm[3] = {0.0, 0.0, 0.0};
+      for (int w = 0; w < ST / 64; ++w)
+        for (int t = 0; t < 3; ++t) nm[t] = fmax(nm[t], nred[t][w]);
+      const bool skip = nm[2] == 0.0 && nm[0] * nm[1] * (double)s * 0x1p-53 <= 1e-10;
+      *gate = skip ? 0 : 1;
+      skip_s = skip ? 1 : 0;
+    }
+    __syncthreads();
+    sk = skip_s != 0;
+  }
+  // R = L^T, Rinv = Y^T (upper, zero padded) through 64 x 64 LDS transposes;
+  // skipped when R is null
+  if (R) {
+    put_upper_transposed(R, sk ? Bout : nullptr, s, Aw, ld, s, T0);      // B = R (s x s)
+    put_upper_transposed(Rinv, sk ? Rc : nullptr, ld, Yw, ld, s, T1);   // Rc = R^-1 (ld x ld)
+    if (sk && BT)
       for (int q = tid; q < ld * ld; q += ST) {
         const int i = q / ld, c = q - i * ld;
-        Rc[q] = (i < s && c < s && c >= i) ? Yw[(int64_t)c * ld + i] : 0.0;
-        if (BT) BT[q] = (i < s && c < s && i >= c) ? Aw[(int64_t)i * ld + c] : 0.0;   // R^T
+        BT[q] = (i < s && c < s && i >= c) ? Aw[q] : 0.0;   // R^T = L
       }
-      for (int q = tid; q < s * s; q += ST) {
-        const int i = q / s, c = q - i * s;
-        Bout[q] = c >= i ? Aw[(int64_t)c * ld + i] : 0.0;
-      }
-    }
-    return;
   }
+  for (int q = tid; q < ld; q += ST) diag_out[q] = (q < s) ? dg[q] : 0.0;
   if (pass != 2) return;
   if (tid == 0 && n_defl) {
     int cnt = 0;
