@@ -425,6 +425,209 @@ tsgemm_mfma_kernel(int64_t n, int ld, const void* __restrict__ Abase, int64_t as
       }
 }
 
+// ---------------------------- FP32 matrix-core products with the archive
+// The float32 basis archive against a float64 block (reorthogonalisation
+// coefficients C = Q^T X and the update X -= Q C), on v_mfma_f32_16x16x4f32:
+// the coefficients only need the accuracy of the archive itself (unit
+// roundoff 2^-24 relative to |Q||X|), so X and C are rounded to float in
+// LDS, and the float accumulators are added into float64 every 32 terms.
+// Same tiles as the FP64 kernels above; operand layout of the float MFMA:
+// lane l = i + 16 k holds A[i][k] and B[k][i], accumulator register r holds
+// D[4 k + r][i].  LDS pitch 80 floats (16 mod 32): the four 16-lane rows of
+// an operand read fall in distinct bank halves.
+typedef float f4v __attribute__((ext_vector_type(4)));
+constexpr int FP = 80;
+
+__global__ void __launch_bounds__(256)
+gram_f32mma_kernel(int64_t n, int ld, const float* __restrict__ Abase, int64_t astride, int nb,
+                   const double* __restrict__ B, double* __restrict__ part, int64_t rows_per_chunk,
+                   const int* __restrict__ flag) {
+  if (flag && *flag == 0) return;
+  __shared__ __align__(16) float sA[MG_RS][FP];
+  __shared__ __align__(16) float sB[MG_RS][FP];
+  const int pa = nb * ld;
+  const int a0 = blockIdx.x * MG_T, b0 = blockIdx.y * MG_T;
+  const int64_t rb = (int64_t)blockIdx.z * rows_per_chunk;
+  const int64_t re = min(n, rb + rows_per_chunk);
+  const int tid = threadIdx.x;
+  const int w = tid >> 6, l = tid & 63, li = l & 15, lk = l >> 4;
+  const int wa = 32 * (w >> 1), wb = 32 * (w & 1);
+  const int sr = tid >> 3, sc = 8 * (tid & 7);
+  const int ga = a0 + sc, gb = b0 + sc;
+  const bool aok = ga < pa, bok = gb < ld;
+  int64_t aoff = 0;
+  if (aok) {
+    const int blk = ga / ld;
+    aoff = (int64_t)blk * astride + (ga - blk * ld);
+  }
+  f4v acc[2][2];
+  double a64[2][2][4];
+#pragma unroll
+  for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < 2; ++tj) {
+      acc[ti][tj] = f4v{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int q = 0; q < 4; ++q) a64[ti][tj][q] = 0.0;
+    }
+  Raw8<true> va;
+  Raw8<false> vb;
+  auto fetch = [&](int64_t r0) {
+    const int64_t r = r0 + sr;
+    if (r < re && aok) va.load(Abase, aoff + r * ld);
+    else va.zero();
+    if (r < re && bok) vb.load(B, r * ld + gb);
+    else vb.zero();
+  };
+  fetch(rb);
+  for (int64_t r0 = rb; r0 < re; r0 += MG_RS) {
+    __syncthreads();
+    *reinterpret_cast<float4*>(&sA[sr][sc]) = va.f[0];
+    *reinterpret_cast<float4*>(&sA[sr][sc + 4]) = va.f[1];
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+      *reinterpret_cast<float4*>(&sB[sr][sc + 4 * q]) =
+          make_float4((float)vb.get(4 * q), (float)vb.get(4 * q + 1), (float)vb.get(4 * q + 2), (float)vb.get(4 * q + 3));
+    __syncthreads();
+    if (r0 + MG_RS < re) fetch(r0 + MG_RS);
+#pragma unroll
+    for (int ks = 0; ks < MG_RS / 4; ++ks) {
+      float av[2], bv[2];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        av[t] = sA[4 * ks + lk][wa + 16 * t + li];
+        bv[t] = sB[4 * ks + lk][wb + 16 * t + li];
+      }
+#pragma unroll
+      for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+        for (int tj = 0; tj < 2; ++tj)
+          acc[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[ti], bv[tj], acc[ti][tj], 0, 0, 0);
+    }
+#pragma unroll
+    for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+      for (int tj = 0; tj < 2; ++tj) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) a64[ti][tj][q] += (double)acc[ti][tj][q];
+        acc[ti][tj] = f4v{0.f, 0.f, 0.f, 0.f};
+      }
+  }
+  double* P = part + (int64_t)blockIdx.z * pa * ld;
+#pragma unroll
+  for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int a = a0 + wa + 16 * ti + 4 * lk + q, b = b0 + wb + 16 * tj + li;
+        if (a < pa && b < ld) P[(int64_t)a * ld + b] = a64[ti][tj][q];
+      }
+}
+
+// out[r, b] = beta in[r, b] + alpha sum_a Q[r, a] C[a, b] (row-major, ld
+// columns), one 64-row x 64-column tile per workgroup, 32 contraction
+// indices per stage (the archive rows staged transposed).
+__global__ void __launch_bounds__(256)
+tsgemm_f32mma_kernel(int64_t n, int ld, const float* __restrict__ Abase, int64_t astride, int nb,
+                     const double* __restrict__ C, const double* __restrict__ in, double* __restrict__ out,
+                     double alpha, double beta, const int* __restrict__ flag) {
+  if (flag && *flag == 0) return;
+  __shared__ __align__(16) float sAT[MT_K][FP];
+  __shared__ __align__(16) float sC[MT_K][FP];
+  const int pa = nb * ld;
+  const int64_t r0 = (int64_t)blockIdx.x * MT_R;
+  const int b0 = blockIdx.y * MT_C;
+  const int tid = threadIdx.x;
+  const int w = tid >> 6, l = tid & 63, li = l & 15, lk = l >> 4;
+  const int wr = 32 * (w >> 1), wc = 32 * (w & 1);
+  const int ar = tid >> 2, ak = 8 * (tid & 3);     // archive staging: row, 8 contraction indices
+  const int cr = tid >> 3, cc = 8 * (tid & 7);     // coefficient staging: row, 8 columns
+  const int64_t arow = r0 + ar;
+  const bool cok = b0 + cc < ld;
+  f4v acc[2][2];
+  double a64[2][2][4];
+#pragma unroll
+  for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < 2; ++tj) {
+      acc[ti][tj] = f4v{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int q = 0; q < 4; ++q) a64[ti][tj][q] = 0.0;
+    }
+  Raw8<true> va;
+  Raw8<false> vc;
+  auto fetch = [&](int a0) {
+    const int ga = a0 + ak;
+    if (arow < n && ga < pa) {
+      const int blk = ga / ld;
+      va.load(Abase, (int64_t)blk * astride + arow * ld + (ga - blk * ld));
+    } else {
+      va.zero();
+    }
+    const int gc = a0 + cr;
+    if (gc < pa && cok) vc.load(C, (int64_t)gc * ld + b0 + cc);
+    else vc.zero();
+  };
+  fetch(0);
+  for (int a0 = 0; a0 < pa; a0 += MT_K) {
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 8; ++q) sAT[ak + q][ar] = (float)va.get(q);
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+      *reinterpret_cast<float4*>(&sC[cr][cc + 4 * q]) =
+          make_float4((float)vc.get(4 * q), (float)vc.get(4 * q + 1), (float)vc.get(4 * q + 2), (float)vc.get(4 * q + 3));
+    __syncthreads();
+    if (a0 + MT_K < pa) fetch(a0 + MT_K);
+#pragma unroll
+    for (int ks = 0; ks < MT_K / 4; ++ks) {
+      float av[2], bv[2];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        av[t] = sAT[4 * ks + lk][wr + 16 * t + li];
+        bv[t] = sC[4 * ks + lk][wc + 16 * t + li];
+      }
+#pragma unroll
+      for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+        for (int tj = 0; tj < 2; ++tj)
+          acc[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[ti], bv[tj], acc[ti][tj], 0, 0, 0);
+    }
+#pragma unroll
+    for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+      for (int tj = 0; tj < 2; ++tj) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) a64[ti][tj][q] += (double)acc[ti][tj][q];
+        acc[ti][tj] = f4v{0.f, 0.f, 0.f, 0.f};
+      }
+  }
+  // the 16 `in` values of this thread are loaded together (rows and columns
+  // out of range read element 0 and are not stored)
+  double inv[2][2][4];
+#pragma unroll
+  for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int64_t r = r0 + wr + 16 * ti + 4 * lk + q;
+        const int b = b0 + wc + 16 * tj + li;
+        inv[ti][tj][q] = (beta != 0.0) ? in[(r < n && b < ld) ? r * ld + b : 0] : 0.0;
+      }
+#pragma unroll
+  for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int64_t r = r0 + wr + 16 * ti + 4 * lk + q;
+        const int b = b0 + wc + 16 * tj + li;
+        if (r < n && b < ld) out[r * ld + b] = alpha * a64[ti][tj][q] + beta * inv[ti][tj][q];
+      }
+}
+
 void launch_gram(int64_t n, int ld, BlockList A, const double* B, double* C, double* part,
                  const int* flag, hipStream_t st) {
   int nx, ny, nch;
@@ -434,11 +637,14 @@ void launch_gram(int64_t n, int ld, BlockList A, const double* B, double* C, dou
   // the Gram of a block with itself is symmetric: only the tiles on and
   // above the diagonal are formed
   const bool sym = mfma_ok(ld) && A.nb == 1 && !A.f32 && A.base == (const void*)B;
-  kt_begin(KC_GRAM, st);
+  // the float32 archive (reorthogonalisation coefficients) on the FP32
+  // matrix cores
+  const bool f32mma = mfma_ok(ld) && A.f32;
+  kt_begin(f32mma ? KC_ARCH_GRAM : KC_GRAM, st);
   if (mfma_ok(ld)) {
     if (A.f32)
-      hipLaunchKernelGGL(gram_mfma_kernel<true>, grid, dim3(256), 0, st, n, ld, A.base, A.stride, A.nb, B, part, rpc,
-                         flag, 0);
+      hipLaunchKernelGGL(gram_f32mma_kernel, grid, dim3(256), 0, st, n, ld, (const float*)A.base, A.stride, A.nb, B,
+                         part, rpc, flag);
     else
       hipLaunchKernelGGL(gram_mfma_kernel<false>, grid, dim3(256), 0, st, n, ld, A.base, A.stride, A.nb, B, part,
                          rpc, flag, sym ? 1 : 0);
@@ -553,10 +759,17 @@ void launch_tsgemm(int64_t n, int ld, BlockList A, const double* C, const double
                    bool tri0) {
   const int up = (upper && A.nb == 1) ? 1 : 0;
   dim3 grid((unsigned)((n + T_TR - 1) / T_TR), (ld + T_TB - 1) / T_TB);
-  kt_begin(KC_TSGEMM, st);
+  // the float32 archive (reorthogonalisation update) on the FP32 matrix
+  // cores; a triangular coefficient block or a float copy of the output
+  // keeps the float64 kernel
+  const bool f32mma = mfma_ok(ld) && A.f32 && !up && !out32;
+  kt_begin(f32mma ? KC_ARCH_UPDATE : KC_TSGEMM, st);
   if (mfma_ok(ld)) {
     static_assert(MT_R == T_TR && MT_C == T_TB, "same tile grid");
-    if (A.f32)
+    if (f32mma)
+      hipLaunchKernelGGL(tsgemm_f32mma_kernel, grid, dim3(256), 0, st, n, ld, (const float*)A.base, A.stride, A.nb, C,
+                         in, out, alpha, beta, flag);
+    else if (A.f32)
       hipLaunchKernelGGL((tsgemm_mfma_kernel<true, false>), grid, dim3(256), 0, st, n, ld, A.base, A.stride, A.nb, C,
                          ld, ld, in, out, out32, alpha, beta, (int64_t)ld, (const int64_t*)nullptr, flag, up);
     else
