@@ -117,6 +117,11 @@ void launch_spmm(const gk_graph* g, bool fp32_weights, int ld, const double* V, 
 // launch per kSpmmGroup blocks; each block gets the arithmetic of its lone
 // launch_spmm(.., V_r, null, X_r, 1, 0, 0, null, ..)
 constexpr int kSpmmGroup = 16;
+// 64-wide blocks: X = L V (a = 1, b = 0) and C = V^T X (64 x 64, from its
+// upper tiles, mirrored) in one pass; part: spmm_gram64_grid(n) * 64 * 64
+int spmm_gram64_grid(int64_t n);
+void launch_spmm_gram64(const gk_graph* g, bool fp32_weights, const double* V, double* X, double* part, double* C,
+                        hipStream_t st);
 void launch_spmm_group(const gk_graph* g, bool fp32_weights, int count, const int* ld, const double* const* V,
                        double* const* X, hipStream_t st);
 

@@ -547,10 +547,15 @@ struct CblRun {
     om_nu = 1.1102230246251565e-16 * g->lambda_max * std::sqrt((double)s);
   }
 
-  // X = L Q_k
+  // X = L Q_k.  GK_MIXED at ld = 64 forms Q_k^T X in the same pass (the
+  // Gram of the recurrence form below; block 1 of C at k > 0, block 0 at k = 0)
+  bool fused = false;
+  bool fusable() const { return mixed && pan && ld == 64; }
   void spmm(int k) {
     J.tm.begin(PH_SPMM);
-    launch_spmm(g, mixed, ld, V64(k), nullptr, X, 1.0, 0.0, 0.0, nullptr, 0.0, nullptr, st);
+    fused = fusable();
+    if (fused) launch_spmm_gram64(g, mixed, V64(k), X, ppart, k > 0 ? C + l2 : C, st);
+    else launch_spmm(g, mixed, ld, V64(k), nullptr, X, 1.0, 0.0, 0.0, nullptr, 0.0, nullptr, st);
   }
 
   // local block [Q_{k-1}, Q_k]:  C = local^T X;  H_kk = sym(C_k);  X -= local C
@@ -575,7 +580,8 @@ struct CblRun {
     const bool rec = mixed && (pan || widek) && k > 0;
     for (int pass = 0; pass < local_passes; ++pass) {
       if (rec && pan) {
-        launch_panel(PM_GRAMV, n, ld, 1, X, nullptr, nullptr, Vk, nullptr, nullptr, nullptr, ppart, C + l2, st);
+        if (!fused)
+          launch_panel(PM_GRAMV, n, ld, 1, X, nullptr, nullptr, Vk, nullptr, nullptr, nullptr, ppart, C + l2, st);
         launch_panel(PM_UPDATE_SELF, n, ld, 2, X, X, nullptr, Vkm1, Vk, C, nullptr, ppart, G, st,
                      Hd + (int64_t)k * s * s, s, true);
       } else if (rec) {
@@ -584,7 +590,8 @@ struct CblRun {
         launch_tsgemm(n, ld, loc, C, X, X, nullptr, -1.0, 1.0, nullptr, st, false, true);
       } else if (pan) {
         double* Cp = two ? Cst + ((int64_t)k * 2 + pass) * 2 * l2 : C;
-        launch_panel(PM_GRAMV, n, ld, nbv, X, nullptr, nullptr, V0, V1, nullptr, nullptr, ppart, Cp, st);
+        if (!(fused && pass == 0))
+          launch_panel(PM_GRAMV, n, ld, nbv, X, nullptr, nullptr, V0, V1, nullptr, nullptr, ppart, Cp, st);
         // the update pass also stores H_kk = sym(C_k) on the first pass
         launch_panel(PM_UPDATE_SELF, n, ld, nbv, X, X, nullptr, V0, V1, Cp, nullptr, ppart, G, st,
                      pass == 0 ? Hd + (int64_t)k * s * s : nullptr, s);
@@ -1327,8 +1334,17 @@ void batch_step(std::vector<BatchCall*>& calls, hipStream_t st) {
     B->S.J.st = st;
     B->S.J.tm.st = st;
   }
-  // grouped SpMM: one launch per graph and weight precision
+  // grouped SpMM: one launch per graph and weight precision; 64-wide mixed
+  // calls take their own product with the Gram fused (the arithmetic of
+  // their lone run)
   std::vector<char> done(calls.size(), 0);
+  for (size_t i = 0; i < calls.size(); ++i) {
+    calls[i]->R->fused = false;
+    if (calls[i]->R->fusable()) {
+      calls[i]->R->spmm(calls[i]->k);
+      done[i] = 1;
+    }
+  }
   for (size_t i = 0; i < calls.size(); ++i) {
     if (done[i]) continue;
     const CblRun& Ri = *calls[i]->R;

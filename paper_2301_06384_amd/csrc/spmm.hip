@@ -237,6 +237,176 @@ void launch_spmm_group(const gk_graph* g, bool fp32_weights, int count, const in
   }
 }
 
+// ------------------------------------------- X = L V with C = V^T X fused
+// For 64-wide blocks: the product X = L V (as spmm_diff_body, 16 lanes per
+// row, 4 doubles each, the same summation order) and the Gram C = V^T X of
+// the three-term recurrence (H_kk = Q_k^T L Q_k, symmetric, so only its
+// 16 x 16 tiles on and above the diagonal) in one pass: each workgroup
+// computes 32 rows of X at a time, writes them out and stages them with the
+// rows of V (already loaded for the diagonal term) in LDS, and its eight
+// wavefronts accumulate the ten upper tiles of C on FP64 matrix cores
+// (v_mfma_f64_16x16x4f64: lane l = i + 16 k holds A[i][k] and B[k][i],
+// accumulator register r holds D[4 r + k][i]).  Partials: one 64 x 64
+// upper-tile set per workgroup, reduced (and mirrored) in float64 in a fixed
+// order by launch_reduce_parts.  (Walking two rows per lane group doubles
+// the gathers in flight per wavefront but, at 152 VGPRs, halves the
+// wavefronts per CU: no faster.)
+constexpr int SG_THREADS = 512;   // 32 rows of 16 lanes
+constexpr int SG_ROWS = 32;
+constexpr int SG_P = 66;          // LDS pitch (doubles)
+constexpr int SG_MAXGRID = 512;   // two workgroups per CU
+typedef double sg_d4 __attribute__((ext_vector_type(4)));
+
+template <int WM>
+__device__ __forceinline__ double sg_weight(const double* __restrict__ w64, const float* __restrict__ w32, int p) {
+  return (WM == W_F64) ? w64[p] : (WM == W_F32 ? (double)w32[p] : 1.0);
+}
+
+template <int WM>
+__global__ void __launch_bounds__(SG_THREADS, 2)
+spmm_gram64_kernel(int64_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                   const double* __restrict__ w64, const float* __restrict__ w32, const double* __restrict__ d,
+                   const double* __restrict__ V, double* __restrict__ out, double* __restrict__ part) {
+  constexpr int LD = 64, VPT = 4, SLOTS = 16, CS = 32;
+  __shared__ __align__(16) double sX[SG_ROWS * SG_P];
+  __shared__ __align__(16) double sV[SG_ROWS * SG_P];
+  const int tid = threadIdx.x;
+  const int g = tid >> 4, lr = tid & 15;
+  const int c0 = 2 * lr;
+  const int gbase = (tid & 63) - lr;
+  const int w = tid >> 6, l = tid & 63, li = l & 15, lk = l >> 4;
+  // upper tiles (gi <= xj) of the 4 x 4 tile grid: wavefront w owns tile w
+  // and, for w < 2, tile w + 8
+  int tgi[2] = {-1, -1}, txj[2] = {-1, -1};
+  {
+    int cnt = 0;
+    for (int i = 0; i < 4; ++i)
+      for (int j = i; j < 4; ++j) {
+        if (cnt == w) { tgi[0] = i; txj[0] = j; }
+        if (cnt == w + 8) { tgi[1] = i; txj[1] = j; }
+        ++cnt;
+      }
+  }
+  sg_d4 acc[2] = {sg_d4{0.0, 0.0, 0.0, 0.0}, sg_d4{0.0, 0.0, 0.0, 0.0}};
+  // each XCD (workgroups are dealt round-robin to the 8 XCDs) walks one
+  // contiguous range of row tiles, as the plain product does
+  const int64_t ntiles = (n + SG_ROWS - 1) / SG_ROWS;
+  const unsigned G = gridDim.x, x = blockIdx.x & 7, kx = blockIdx.x >> 3;
+  const unsigned gx = (G >> 3) + (x < (G & 7) ? 1u : 0u);   // workgroups on this XCD
+  const int64_t chunk = (ntiles + 7) / 8;
+  const int64_t t_begin = (int64_t)x * chunk, t_end = min(ntiles, t_begin + chunk);
+  for (int64_t tile = t_begin + kx; tile < t_end; tile += gx) {
+    const int64_t row = tile * SG_ROWS + g;
+    double o[VPT], vi[VPT];
+    if (row < n) {
+      double sacc[VPT];
+#pragma unroll
+      for (int q = 0; q < VPT; ++q) sacc[q] = 0.0;
+      const int p0 = rp[row], p1 = rp[row + 1];
+      for (int pc = p0; pc < p1; pc += SLOTS) {
+        const int pp = pc + lr;
+        int myj = 0;
+        double myw = 0.0;
+        if (pp < p1) {
+          myj = ci[pp];
+          myw = sg_weight<WM>(w64, w32, pp);
+        }
+        const int cnt = min(SLOTS, p1 - pc);
+        int k = 0;
+        for (; k + 3 < cnt; k += 4) {
+          int j[4];
+          double wv[4], v[4][VPT];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            j[u] = __shfl(myj, gbase + k + u);
+            wv[u] = __shfl(myw, gbase + k + u);
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) load_row<VPT>(V + (int64_t)j[u] * LD + c0, CS, v[u]);
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int q = 0; q < VPT; ++q) sacc[q] = fma(wv[u], v[u][q], sacc[q]);
+        }
+        for (; k < cnt; ++k) {
+          const int j0 = __shfl(myj, gbase + k);
+          const double w0 = __shfl(myw, gbase + k);
+          double v0[VPT];
+          load_row<VPT>(V + (int64_t)j0 * LD + c0, CS, v0);
+#pragma unroll
+          for (int q = 0; q < VPT; ++q) sacc[q] = fma(w0, v0[q], sacc[q]);
+        }
+      }
+      load_row<VPT>(V + row * LD + c0, CS, vi);
+      const double di = d[row];
+#pragma unroll
+      for (int q = 0; q < VPT; ++q) o[q] = di * vi[q] - sacc[q];
+      store_row<VPT>(out + row * LD + c0, CS, o);
+    } else {
+#pragma unroll
+      for (int q = 0; q < VPT; ++q) o[q] = vi[q] = 0.0;
+    }
+    // lane lr of row g holds columns 2 lr, 2 lr + 1, 2 lr + 32, 2 lr + 33
+#pragma unroll
+    for (int q = 0; q < VPT / 2; ++q) {
+      *reinterpret_cast<double2*>(&sX[g * SG_P + c0 + q * CS]) = make_double2(o[2 * q], o[2 * q + 1]);
+      *reinterpret_cast<double2*>(&sV[g * SG_P + c0 + q * CS]) = make_double2(vi[2 * q], vi[2 * q + 1]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      const int gi = tgi[t], xj = txj[t];
+      if (gi >= 0) {
+#pragma unroll
+        for (int k0 = 0; k0 < SG_ROWS; k0 += 4) {
+          // rows read together by half a wavefront are 8 apart (as in the
+          // panel kernels): 8 SG_P = 16 mod 32 double banks
+          const int rr = (k0 & ~15) + ((k0 & 15) >> 2) + 8 * (lk & 1) + 4 * (lk >> 1);
+          acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(sV[rr * SG_P + 16 * gi + li], sX[rr * SG_P + 16 * xj + li],
+                                                        acc[t], 0, 0, 0);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  double* P0 = part + (int64_t)blockIdx.x * LD * LD;
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    const int gi = tgi[t], xj = txj[t];
+    if (gi >= 0) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) P0[(16 * gi + 4 * r + lk) * LD + 16 * xj + li] = acc[t][r];
+    }
+  }
+}
+
+int spmm_gram64_grid(int64_t n) {
+  const int64_t nt = (n + SG_ROWS - 1) / SG_ROWS;
+  return (int)std::min<int64_t>(nt, SG_MAXGRID);
+}
+
+void launch_spmm_gram64(const gk_graph* g, bool fp32_weights, const double* V, double* X, double* part, double* C,
+                        hipStream_t st) {
+  const int grid = spmm_gram64_grid(g->n);
+  const double wb = g->unit ? 0.0 : (fp32_weights ? 4.0 : 8.0);
+  const double* d = fp32_weights ? g->d32 : g->d64;
+  kt_begin(KC_SPMM, st);
+  if (g->unit)
+    hipLaunchKernelGGL(spmm_gram64_kernel<W_UNIT>, dim3(grid), dim3(SG_THREADS), 0, st, g->n, g->rp, g->ci, g->w64,
+                       g->w32, d, V, X, part);
+  else if (fp32_weights)
+    hipLaunchKernelGGL(spmm_gram64_kernel<W_F32>, dim3(grid), dim3(SG_THREADS), 0, st, g->n, g->rp, g->ci, g->w64,
+                       g->w32, d, V, X, part);
+  else
+    hipLaunchKernelGGL(spmm_gram64_kernel<W_F64>, dim3(grid), dim3(SG_THREADS), 0, st, g->n, g->rp, g->ci, g->w64,
+                       g->w32, d, V, X, part);
+  GK_HIP(hipGetLastError());
+  // the product's own traffic (the Gram reads nothing more); flops of both
+  kt_end(st, 4.0 * (g->n + 1) + (double)g->nnz * (4.0 + wb) + 8.0 * g->n + 2.0 * 8.0 * g->n * 64,
+         2.0 * ((double)g->nnz + g->n) * 64 + (double)g->n * 64 * 65);
+  launch_reduce_parts((int64_t)64 * 64, grid, part, C, nullptr, st, 64, 16);
+}
+
 template <int VPT>
 static void spmm_dispatch_w(const gk_graph* g, bool fp32w, int ld, const double* V, const double* Vp,
                             double* out, double a, double b, double gm, double* acc, double e,
