@@ -111,3 +111,19 @@ def test_ba200k_gbl_m20_against_oracle(ba200k, prec):
     err = compare(ref, P, K)
     print(f"BA200k gbl m=20 {prec}: {err:.3e} (archive projections {st.n_reorth})")
     assert err < TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_grid48_s512_against_oracle(prec):
+    # the widest block (s = 512, tiled 65..512 kernels) on a 3-D grid
+    L = I.grid((48, 48, 48), weights="uniform", seed=0)
+    g = gk.Graph.from_laplacian(L, flags=gk.REORDER)
+    try:
+        ref = load("grid48_spline_oracle.txt")["cbl"]
+        W = I.samples(L.n, 512, 0)
+        P, K, st = gk.krylov_kernel_columns(g, W, dict(kind="spline", eps=0.05, k=1.0), 30, "cbl", prec)
+    finally:
+        g.release()
+    err = compare(ref, P, K)
+    print(f"grid48 s=512 cbl {prec}: {err:.3e} (archive projections {st.n_reorth})")
+    assert err < TOL[prec]
