@@ -458,11 +458,14 @@ struct CblRun {
   // only at 1
   int* gate = nullptr;
   int* gk(int k) const { return gate ? gate + k : nullptr; }
-  // tolerances of the estimate: threshold (semi-orthogonality at the square
-  // root of the unit roundoff of the float32 archive, 2^-12), floor after a
-  // reorthogonalisation against the float32 archive, floor of the two
-  // explicitly orthogonalised neighbours, and the per-step rounding model
-  double om_tau = 0x1p-12, om_floor_re = 2e-8, om_floor_loc = 1e-14, om_nu = 0;
+  // tolerances of the estimate: threshold, floor after a reorthogonalisation
+  // against the float32 archive, floor of the two explicitly orthogonalised
+  // neighbours, and the per-step rounding model.  The threshold is 2^-16:
+  // semi-orthogonality (2^-12, the square root of the archive's unit
+  // roundoff) keeps the Ritz values, but on hub-dominated graphs it let the
+  // kernel columns drift to 1.7e-5 from the float64 path; 2^-16 keeps them
+  // within 5e-7 there
+  double om_tau = 0x1p-16, om_floor_re = 2e-8, om_floor_loc = 1e-14, om_nu = 0;
 
   explicit CblRun(Job& j) : J(j) {}
   double* V64(int k) const { return (mixed || two) ? ring + (int64_t)(k % 3) * blk : Vb + (int64_t)k * blk; }
