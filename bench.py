@@ -417,7 +417,7 @@ def config_leg(torch, gk, I, name, variants, fp64=True):
         _progress(f"{name} {variant}: {row}")
     agg, _ = collect_timings(lambda: call("cbl", "mixed", Pm, Km, gk.TIMING)[1], 1)
     ld = s if s <= 8 else 16 * ((s + 15) // 16)
-    table, whole = kernel_table(agg, 1, "fp32" if ld <= 64 else "fp64")
+    table, whole = kernel_table(agg, 1, "fp32")
     out["cbl_mixed_kernels"] = {k: {f: v[f] for f in ("launches_per_step", "ms_per_step", "avg_launch_us", "bound",
                                                       "achieved", "unit", "frac")} for k, v in table.items()}
     out["cbl_mixed_whole_solve"] = whole

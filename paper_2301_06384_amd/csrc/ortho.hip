@@ -97,34 +97,40 @@ reduce_parts_kernel(int64_t len, int nparts, const double* __restrict__ part, do
   if (flag && *flag == 0) return;
   __shared__ double red[16][17];
   const int o = threadIdx.x & 15, g = threadIdx.x >> 4;
-  const int64_t i = (int64_t)blockIdx.x * 16 + o;
-  const int64_t src = i;
-  int64_t mirror = -1;
-  if (sym_ld > 0) {
-    const int64_t r = ((int64_t)blockIdx.x * 16) / sym_ld, c = i - r * sym_ld;
-    const int64_t tr = r / sym_t, tc = ((int64_t)blockIdx.x * 16 - r * sym_ld) / sym_t;
-    if (tr > tc) return;   // the whole block: lower tiles come from their mirror
-    if (tr < tc) mirror = c * sym_ld + r;
-  }
-  double s = 0.0;
-  if (i < len) {
-    double a[8];
+  // groups of 16 outputs, taken in turn by the workgroups of a capped grid
+  // (a gated launch that has nothing to do then dispatches few workgroups)
+  const int64_t ngrp = (len + 15) / 16;
+  for (int64_t gb = blockIdx.x; gb < ngrp; gb += gridDim.x) {
+    const int64_t i = gb * 16 + o;
+    const int64_t src = i;
+    int64_t mirror = -1;
+    if (sym_ld > 0) {
+      const int64_t r = (gb * 16) / sym_ld, c = i - r * sym_ld;
+      const int64_t tr = r / sym_t, tc = (gb * 16 - r * sym_ld) / sym_t;
+      if (tr > tc) continue;   // the whole group: lower tiles come from their mirror
+      if (tr < tc) mirror = c * sym_ld + r;
+    }
+    double s = 0.0;
+    if (i < len) {
+      double a[8];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) a[u] = 0.0;
-    int c = g;
-    for (; c + 16 * 7 < nparts; c += 16 * 8)
+      for (int u = 0; u < 8; ++u) a[u] = 0.0;
+      int c = g;
+      for (; c + 16 * 7 < nparts; c += 16 * 8)
 #pragma unroll
-      for (int u = 0; u < 8; ++u) a[u] += part[(int64_t)(c + 16 * u) * len + src];
-    for (; c < nparts; c += 16) a[0] += part[(int64_t)c * len + src];
-    s = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
-  }
-  red[g][o] = s;
-  __syncthreads();
-  if (g == 0 && i < len) {
-    double t = 0.0;
-    for (int q = 0; q < 16; ++q) t += red[q][o];
-    out[i] = t;
-    if (mirror >= 0) out[mirror] = t;
+        for (int u = 0; u < 8; ++u) a[u] += part[(int64_t)(c + 16 * u) * len + src];
+      for (; c < nparts; c += 16) a[0] += part[(int64_t)c * len + src];
+      s = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+    }
+    red[g][o] = s;
+    __syncthreads();
+    if (g == 0 && i < len) {
+      double t = 0.0;
+      for (int q = 0; q < 16; ++q) t += red[q][o];
+      out[i] = t;
+      if (mirror >= 0) out[mirror] = t;
+    }
+    __syncthreads();
   }
 }
 
@@ -137,8 +143,9 @@ void launch_reduce_parts(int64_t len, int nparts, const double* part, double* ou
     rd = nt * (nt + 1) / 2 * sym_t * sym_t;
   }
   kt_begin(KC_REDUCE, st);
-  hipLaunchKernelGGL(reduce_parts_kernel, dim3((unsigned)((len + 15) / 16)), dim3(256), 0, st, len, nparts, part, out,
-                     flag, sym_ld, sym_t);
+  const int64_t ngrp = (len + 15) / 16;
+  hipLaunchKernelGGL(reduce_parts_kernel, dim3((unsigned)std::min<int64_t>(ngrp, 1024)), dim3(256), 0, st, len, nparts,
+                     part, out, flag, sym_ld, sym_t);
   GK_HIP(hipGetLastError());
   kt_end(st, 8.0 * (rd * nparts + len), rd * nparts, flag);
 }
@@ -628,6 +635,107 @@ tsgemm_f32mma_kernel(int64_t n, int ld, const float* __restrict__ Abase, int64_t
       }
 }
 
+// Assembly P[perm(r), c] = sum_a Q[r, a] U[a, c] (c < ncols) from the
+// float32 archive on FP32 matrix cores, U rounded to float (the accuracy of
+// the archive itself, as for the 64-wide assembly of arch.hip); float
+// accumulators added into float64 after every 32 contraction indices;
+// column-major output (leading dimension ldo) written through an LDS
+// transpose, each column as contiguous rows.
+__global__ void __launch_bounds__(256)
+assemble_f32mma_kernel(int64_t n, int ld, const float* __restrict__ Abase, int64_t astride, int nb,
+                       const double* __restrict__ U, int ldu, int ncols, double* __restrict__ out, int64_t ldo,
+                       const int64_t* __restrict__ perm) {
+  __shared__ __align__(16) float sAT[MT_K][FP];
+  __shared__ __align__(16) float sC[MT_K][FP];
+  __shared__ double sO[MT_C][MT_R + 1];
+  const int pa = nb * ld;
+  const int64_t r0 = (int64_t)blockIdx.x * MT_R;
+  const int b0 = blockIdx.y * MT_C;
+  const int tid = threadIdx.x;
+  const int w = tid >> 6, l = tid & 63, li = l & 15, lk = l >> 4;
+  const int wr = 32 * (w >> 1), wc = 32 * (w & 1);
+  const int ar = tid >> 2, ak = 8 * (tid & 3);     // archive staging: row, 8 contraction indices
+  const int cr = tid >> 3, cc = 8 * (tid & 7);     // coefficient staging: row, 8 columns
+  const int64_t arow = r0 + ar;
+  f4v acc[2][2];
+  double a64[2][2][4];
+#pragma unroll
+  for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < 2; ++tj) {
+      acc[ti][tj] = f4v{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int q = 0; q < 4; ++q) a64[ti][tj][q] = 0.0;
+    }
+  Raw8<true> va;
+  double vcs[8];   // scalar coefficient loads (ldu need not be even)
+  auto fetch = [&](int a0) {
+    const int ga = a0 + ak;
+    if (arow < n && ga < pa) {
+      const int blk = ga / ld;
+      va.load(Abase, (int64_t)blk * astride + arow * ld + (ga - blk * ld));
+    } else {
+      va.zero();
+    }
+    const int gc = a0 + cr;
+    const int gcc = gc < pa ? gc : pa - 1;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int col = b0 + cc + q;
+      vcs[q] = U[(int64_t)gcc * ldu + (col < ncols ? col : ncols - 1)];
+    }
+  };
+  fetch(0);
+  for (int a0 = 0; a0 < pa; a0 += MT_K) {
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 8; ++q) sAT[ak + q][ar] = (float)va.get(q);
+    {
+      const bool rin = a0 + cr < pa;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) sC[cr][cc + q] = (rin && b0 + cc + q < ncols) ? (float)vcs[q] : 0.f;
+    }
+    __syncthreads();
+    if (a0 + MT_K < pa) fetch(a0 + MT_K);
+#pragma unroll
+    for (int ks = 0; ks < MT_K / 4; ++ks) {
+      float av[2], bv[2];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        av[t] = sAT[4 * ks + lk][wr + 16 * t + li];
+        bv[t] = sC[4 * ks + lk][wc + 16 * t + li];
+      }
+#pragma unroll
+      for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+        for (int tj = 0; tj < 2; ++tj)
+          acc[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[ti], bv[tj], acc[ti][tj], 0, 0, 0);
+    }
+#pragma unroll
+    for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+      for (int tj = 0; tj < 2; ++tj) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) a64[ti][tj][q] += (double)acc[ti][tj][q];
+        acc[ti][tj] = f4v{0.f, 0.f, 0.f, 0.f};
+      }
+  }
+  // D[4 k + r][i]: row wr + 16 ti + 4 lk + r, column wc + 16 tj + li
+#pragma unroll
+  for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) sO[wc + 16 * tj + li][wr + 16 * ti + 4 * lk + q] = a64[ti][tj][q];
+  __syncthreads();
+  for (int q = tid; q < MT_C * MT_R; q += 256) {
+    const int cc2 = q / MT_R, rr = q - cc2 * MT_R;
+    const int64_t r = r0 + rr;
+    const int b = b0 + cc2;
+    if (r < n && b < ncols) out[(int64_t)b * ldo + (perm ? perm[r] : r)] = sO[cc2][rr];
+  }
+}
+
 void launch_gram(int64_t n, int ld, BlockList A, const double* B, double* C, double* part,
                  const int* flag, hipStream_t st) {
   int nx, ny, nch;
@@ -797,9 +905,8 @@ void launch_assemble(int64_t n, int ld, int s, BlockList A, const double* U, int
   kt_begin(KC_ASSEMBLE, st);
   if (mfma_ok(ld)) {
     if (A.f32)
-      hipLaunchKernelGGL((tsgemm_mfma_kernel<true, true>), grid, dim3(256), 0, st, n, ld, A.base, A.stride, A.nb, U,
-                         ldu, s, (const double*)nullptr, P, (float*)nullptr, 1.0, 0.0, n, perm, (const int*)nullptr,
-                         0);
+      hipLaunchKernelGGL(assemble_f32mma_kernel, grid, dim3(256), 0, st, n, ld, (const float*)A.base, A.stride, A.nb,
+                         U, ldu, s, P, n, perm);
     else
       hipLaunchKernelGGL((tsgemm_mfma_kernel<false, true>), grid, dim3(256), 0, st, n, ld, A.base, A.stride, A.nb, U,
                          ldu, s, (const double*)nullptr, P, (float*)nullptr, 1.0, 0.0, n, perm, (const int*)nullptr,
