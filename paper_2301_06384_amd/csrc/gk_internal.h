@@ -275,8 +275,16 @@ int cheb_diffusion_degree(double t, double Lam);
 void launch_btd_cheb_tile(int m, int s, const double* Hd, const double* Bd, const double* Y, const double* Yp,
                           double* out, double alpha, double beta, double gamma, double* acc, const double* coef,
                           int kk, hipStream_t st);
-void launch_cheb_diffusion(int m, int s, const double* Hd, const double* Bd, double t, double Lam, int deg,
-                           const double* coef, double* Y0, double* Y1, double* Y2, double* U, hipStream_t st);
+// U (m s x s) = sum_{k <= deg} coef[k] T_k(I - 2 H_m / Lam) F_1 (Chebyshev
+// series through the block tridiagonal H_m; t is not used)
+void launch_cheb_series(int m, int s, const double* Hd, const double* Bd, double t, double Lam, int deg,
+                        const double* coef, double* Y0, double* Y1, double* Y2, double* U, hipStream_t st);
+// largest projected matrix (m s) the one-workgroup spectral decomposition takes
+constexpr int kEigMaxOrder = 4096;
+// Chebyshev-Lobatto coefficients of a spline or polynomial phi of degree deg
+// on [0, Lam]: f at the points, then the cosine sums (angles reduced exactly)
+void launch_cheb_coef_phi(int deg, double Lam, const gk_phi& phi, const double* poly_dev, double* fv, double* a,
+                          hipStream_t st);
 // deterministic sum of nparts equally long partial vectors: out[i] = sum_c part[c*len + i]
 // sym_ld > 0: the parts hold the sym_t x sym_t tiles on and above the diagonal
 // of a symmetric sym_ld x sym_ld matrix; out receives the whole matrix

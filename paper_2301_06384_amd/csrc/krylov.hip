@@ -401,7 +401,59 @@ static void phi_stage_block(Job& J, const double* Hd, const double* Bd, double* 
     double* Y0 = J.ar.get<double>(tot);
     double* Y1 = J.ar.get<double>(tot);
     double* Y2 = J.ar.get<double>(tot);
-    launch_cheb_diffusion(m, s, Hd, Bd, J.phi.t, Lam, deg, coef, Y0, Y1, Y2, U, J.st);
+    launch_cheb_series(m, s, Hd, Bd, J.phi.t, Lam, deg, coef, Y0, Y1, Y2, U, J.st);
+    launch_store_H(U, s, s, K, J.st);          // K = sym(U[0:s, :])
+    J.phi_method = 2;
+    return;
+  }
+  if (ms > kEigMaxOrder && !(J.flags & GK_PHI_EIG)) {
+    // Projected matrices beyond the one-workgroup spectral decomposition:
+    // phi(H_m) F_1 by the Chebyshev series of phi on [0, Lambda] (spec(H_m)
+    // lies there, Theorem 3.1).  A polynomial is its own finite series; for
+    // a spline (eps + lam)^-k the coefficients decay like rho^-k with
+    // rho = x0 + sqrt(x0^2 - 1), x0 = 1 + 2 eps / Lambda (its pole at
+    // lam = -eps), so the degree starts at 40 / ln rho and doubles until
+    // the tail is below 1e-16 of the largest coefficient.
+    const double Lam = J.g->lambda_max;
+    const bool poly = J.phi.kind == GK_PHI_POLYNOMIAL;
+    int deg;
+    if (poly) {
+      deg = std::max(1, J.phi.poly_len - 1);
+    } else {
+      const double x0 = 1.0 + 2.0 * J.phi.eps / Lam;
+      const double rho = x0 + std::sqrt(x0 * x0 - 1.0);
+      deg = (int)std::min(32768.0, std::ceil(40.0 / std::log(rho)) + 16.0);
+    }
+    double* coef = nullptr;
+    for (;;) {
+      coef = J.ar.get<double>(deg + 1);
+      double* fv = J.ar.get<double>(deg + 1);
+      launch_cheb_coef_phi(deg, Lam, J.phi, J.poly_dev, fv, coef, J.st);
+      if (poly) break;
+      std::vector<double> h(deg + 1);
+      GK_HIP(hipMemcpyAsync(h.data(), coef, sizeof(double) * (deg + 1), hipMemcpyDeviceToHost, J.st));
+      GK_HIP(hipStreamSynchronize(J.st));
+      double amax = 0.0;
+      for (double v : h) amax = std::max(amax, std::fabs(v));
+      GK_REQUIRE(std::isfinite(amax), GK_EINVAL, "non-finite Chebyshev coefficients of phi");
+      double tail = 0.0;
+      for (int q = std::max(0, deg - 8); q <= deg; ++q) tail = std::max(tail, std::fabs(h[q]));
+      if (tail <= 1e-16 * amax) {
+        // drop the negligible end of the series
+        int last = deg;
+        while (last > 1 && std::fabs(h[last]) <= 1e-17 * amax) --last;
+        deg = last;
+        break;
+      }
+      GK_REQUIRE(deg < 32768, GK_EUNSUPPORTED,
+                 "the Chebyshev series of this spline needs more than 32768 terms on [0, Lambda]");
+      deg = std::min(32768, 2 * deg);
+    }
+    const size_t tot = (size_t)m * s * s;
+    double* Y0 = J.ar.get<double>(tot);
+    double* Y1 = J.ar.get<double>(tot);
+    double* Y2 = J.ar.get<double>(tot);
+    launch_cheb_series(m, s, Hd, Bd, 0.0, Lam, deg, coef, Y0, Y1, Y2, U, J.st);
     launch_store_H(U, s, s, K, J.st);          // K = sym(U[0:s, :])
     J.phi_method = 2;
     return;
@@ -1084,9 +1136,13 @@ static void validate_common(const CallArgs& a) {
   const int64_t ms = (int64_t)a.m * a.s;
   const bool banded_ok = a.phi->kind == GK_PHI_SPLINE && a.phi->k == std::floor(a.phi->k) && a.phi->k <= 16;
   const bool cheb_ok = a.phi->kind == GK_PHI_DIFFUSION;
-  if (a.variant == GK_CBL && (!(banded_ok || cheb_ok) || (a.flags & GK_PHI_EIG)))
-    GK_REQUIRE(ms <= 4096, GK_EUNSUPPORTED,
+  // beyond kEigMaxOrder splines and polynomials take the Chebyshev series;
+  // the spectral decomposition itself (GK_PHI_EIG) stays one workgroup
+  if (a.variant == GK_CBL && (a.flags & GK_PHI_EIG))
+    GK_REQUIRE(ms <= kEigMaxOrder, GK_EUNSUPPORTED,
                "the single-workgroup spectral decomposition is limited to m*s <= 4096");
+  (void)banded_ok;
+  (void)cheb_ok;
 }
 
 static void check_samples_host(const int64_t* h, int s, int64_t n) {

@@ -1206,13 +1206,53 @@ __global__ void f1_init_kernel(int64_t rows, int s, double* __restrict__ Y, doub
 // The coefficients 2 e^{-z} I_k(z) fall below 1e-17 before k = sqrt(80 z) + 24
 // for every z (they decay like exp(-k^2 / (2 z)) once k exceeds sqrt(z));
 // sqrt(90 z) + 24 keeps a margin.
+__global__ void cheb_fvals_kernel(int deg, double Lam, int kind, double eps, double kexp,
+                                  const double* __restrict__ poly, int plen, double* __restrict__ f) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j > deg) return;
+  const double lam = 0.5 * Lam * (1.0 - cospi((double)j / deg));
+  double v;
+  if (kind == GK_PHI_SPLINE) {
+    v = pow(eps + lam, -kexp);
+  } else {
+    v = 0.0;
+    for (int q = plen - 1; q >= 0; --q) v = v * lam + poly[q];
+  }
+  f[j] = v;
+}
+// a_k = (2/deg) sum_j'' f_j cos(pi j k / deg), a_0 and a_deg halved; the
+// angle j k / deg is reduced modulo 2 in integers before cospi
+__global__ void cheb_dct_kernel(int deg, const double* __restrict__ f, double* __restrict__ a) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k > deg) return;
+  const int64_t two = 2 * (int64_t)deg;
+  double acc = 0.0;
+  for (int j = 0; j <= deg; ++j) {
+    const int64_t r = ((int64_t)j * k) % two;
+    const double w = (j == 0 || j == deg) ? 0.5 : 1.0;
+    acc += w * f[j] * cospi((double)r / deg);
+  }
+  acc *= 2.0 / deg;
+  if (k == 0 || k == deg) acc *= 0.5;
+  a[k] = acc;
+}
+void launch_cheb_coef_phi(int deg, double Lam, const gk_phi& phi, const double* poly_dev, double* fv, double* a,
+                          hipStream_t st) {
+  const unsigned nb = (unsigned)((deg + 1 + 255) / 256);
+  hipLaunchKernelGGL(cheb_fvals_kernel, dim3(nb), dim3(256), 0, st, deg, Lam, (int)phi.kind, phi.eps, phi.k,
+                     poly_dev, phi.poly_len, fv);
+  GK_HIP(hipGetLastError());
+  hipLaunchKernelGGL(cheb_dct_kernel, dim3(nb), dim3(256), 0, st, deg, (const double*)fv, a);
+  GK_HIP(hipGetLastError());
+}
+
 int cheb_diffusion_degree(double t, double Lam) {
   const double z = 0.5 * t * Lam;
   const double k = sqrt(90.0 * z) + 24.0;
   return (int)fmin(4096.0, ceil(k));
 }
 
-void launch_cheb_diffusion(int m, int s, const double* Hd, const double* Bd, double t, double Lam, int deg,
+void launch_cheb_series(int m, int s, const double* Hd, const double* Bd, double t, double Lam, int deg,
                            const double* coef, double* Y0, double* Y1, double* Y2, double* U, hipStream_t st) {
   const int64_t tot = (int64_t)m * s * s;
   const unsigned nb = (unsigned)((tot + 255) / 256);

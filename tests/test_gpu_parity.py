@@ -371,6 +371,30 @@ def test_widths_above_512(s, m):
             assert rel(P, ref) < TOL[prec], (s, m, prec, phi, rel(P, ref))
 
 
+@pytest.mark.parametrize("phi", [dict(kind="spline", eps=0.1, k=1.5), dict(kind="polynomial", coef=[1.0, -0.3, 0.02])])
+def test_large_projected_matrix_chebyshev_phi(phi):
+    # m s = 4160 > 4096: a non-integer spline or a polynomial goes through
+    # the Chebyshev series of phi on [0, Lambda] instead of the one-workgroup
+    # spectral decomposition (which refuses this size)
+    L = I.grid((20, 20, 20), weights="uniform", seed=2)
+    g = gk.Graph.from_laplacian(L)
+    try:
+        W = I.samples(L.n, 104, 5)
+        m = 40
+        ref = krylov.cbl(L.to_scipy(), W, phi, m)
+        for prec in ("fp64", "mixed"):
+            P, K, st = gk.krylov_kernel_columns(g, W, phi, m, "cbl", prec)
+            assert st.as_dict()["phi_method"] != "eig"
+            ep, ek = rel(P, ref["P"]), rel(K, ref["Kww"])
+            print(f"m s = {m * len(W)} {phi['kind']} {prec}: P {ep:.3e}, K_WW {ek:.3e}")
+            assert ep < TOL[prec] and ek < TOL[prec], (prec, ep, ek)
+        with pytest.raises(gk.GKError) as e:   # the spectral path itself stays limited
+            gk.krylov_kernel_columns(g, W, phi, m, "cbl", "fp64", flags=gk.PHI_EIG)
+        assert e.value.code == gk.EUNSUPPORTED
+    finally:
+        g.release()
+
+
 def test_error_paths_on_device():
     L, g = G("rgg2003")
     phi = dict(kind="diffusion", t=1.0)
