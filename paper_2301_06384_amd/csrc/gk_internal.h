@@ -85,6 +85,11 @@ struct gk_graph {
   bool unit = false;
   double lambda_max = 0;    // Gershgorin bound of spec(L)
   int max_row = 0;          // max off-diagonal entries of a row
+  // Rows [xr[x], xr[x+1]) are the product's share of XCD x (workgroups are
+  // dealt round-robin to the 8 XCDs): contiguous ranges of about equal cost
+  // (off-diagonal entries + 3 row accesses), so a degree skew over the node
+  // order does not load one XCD's L2 and fabric link with most gathers.
+  int64_t xr[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   // device arrays (node order of the device, see perm)
   int32_t* rp = nullptr;    // n+1
   int32_t* ci = nullptr;    // nnz
@@ -118,8 +123,10 @@ void launch_spmm(const gk_graph* g, bool fp32_weights, int ld, const double* V, 
 // launch_spmm(.., V_r, null, X_r, 1, 0, 0, null, ..)
 constexpr int kSpmmGroup = 16;
 // 64-wide blocks: X = L V (a = 1, b = 0) and C = V^T X (64 x 64, from its
-// upper tiles, mirrored) in one pass; part: spmm_gram64_grid(n) * 64 * 64
-int spmm_gram64_grid(int64_t n);
+// upper tiles, mirrored) in one pass; part: spmm_gram64_grid(g) * 64 * 64
+// doubles, at most spmm_gram64_scratch_elems(n) for any graph of n nodes
+int spmm_gram64_grid(const gk_graph* g);
+size_t spmm_gram64_scratch_elems(int64_t n);
 void launch_spmm_gram64(const gk_graph* g, bool fp32_weights, const double* V, double* X, double* part, double* C,
                         hipStream_t st);
 void launch_spmm_group(const gk_graph* g, bool fp32_weights, int count, const int* ld, const double* const* V,

@@ -184,6 +184,22 @@ static void upload(gk_graph* g, const HostLap& H, const std::vector<int64_t>* or
     rp[k + 1] = (int32_t)ci.size();
     maxrow = std::max(maxrow, (int)row.size());
   }
+  // per-XCD row ranges of equal cost for the products
+  {
+    const double tot = (double)ci.size() + 3.0 * (double)n;
+    int64_t i = 0;
+    double acc = 0.0;
+    g->xr[0] = 0;
+    for (int x = 1; x < 8; ++x) {
+      const double goal = tot * x / 8.0;
+      while (i < n && acc + 0.5 * (rp[i + 1] - rp[i] + 3.0) <= goal) {
+        acc += rp[i + 1] - rp[i] + 3.0;
+        ++i;
+      }
+      g->xr[x] = i;
+    }
+    g->xr[8] = n;
+  }
   g->n = n;
   g->nnz = (int64_t)ci.size();
   g->unit = H.unit;

@@ -27,6 +27,11 @@
 
 namespace gk {
 
+// Gram partials of the panel passes and of the fused 64-wide product + Gram
+static size_t pass_scratch_elems(int64_t n, int ld) {
+  return std::max(panel_scratch_elems(n, ld), ld == 64 ? spmm_gram64_scratch_elems(n) : (size_t)0);
+}
+
 // ------------------------------------------------------------ glue kernels
 // Upad[b*ld + r, c] = U[b*s + r, c] (r < s), zero for padding rows
 __global__ void pad_rows_kernel(int nb, int s, int ld, const double* __restrict__ U, double* __restrict__ Up) {
@@ -577,7 +582,7 @@ struct CblRun {
     // start block Q_1 = E_W (Alg. 1)
     launch_start_block(n, ld, s, J.samp, 1.0, V64(0), mixed ? Va : nullptr, st);
     pan = panel_ok(ld);
-    if (pan) ppart = J.ar.get<double>(panel_scratch_elems(n, ld));
+    if (pan) ppart = J.ar.get<double>(pass_scratch_elems(n, ld));
     if (mixed && (wave || widek)) gate = J.ar.get<int>(m);
     // partial reorthogonalisation (GK_MIXED, s <= 512): block omega estimate,
     // reorthogonalisation against the float32 archive only when it is needed
@@ -1068,7 +1073,7 @@ uint64_t footprint_bytes(int64_t n, int s, int m, int variant, int precision, ui
     size_t pe = 0;
     for (int nb = 1; nb <= 2; ++nb) pe = std::max(pe, gram_scratch_elems(n, nb, ld));
     b = 6 * blk8 + 5.0 * m * l2 + 8.0 * pe + 2 * ms * ms * 8.0 + 8.0 * l2 + 4.0 * m * s * s * 8.0;
-    if (panel_ok(ld)) b += 8.0 * panel_scratch_elems(n, ld);
+    if (panel_ok(ld)) b += 8.0 * pass_scratch_elems(n, ld);
     if (small_wave_ok(s)) b += 8.0 * bcr_work_elems(m, s);
     if (wide_ok(ld)) b += 8.0 * cholqr_wide_scratch_elems(ld);
     b += (double)n * s * 8.0 + 64.0 * (1 << 20);
@@ -1096,7 +1101,7 @@ uint64_t footprint_bytes(int64_t n, int s, int m, int variant, int precision, ui
       size_t pe = 0;
       for (int nb = 1; nb <= (full ? m : 2); ++nb) pe = std::max(pe, gram_scratch_elems(n, nb, ld));
       b += 8.0 * pe;
-      if (panel_ok(ld)) b += 8.0 * panel_scratch_elems(n, ld);
+      if (panel_ok(ld)) b += 8.0 * pass_scratch_elems(n, ld);
       if (mixed) {
         // partial reorthogonalisation: estimate blocks and archive partials
         b += 3.0 * m * s * s * 8.0;

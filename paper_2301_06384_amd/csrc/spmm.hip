@@ -36,27 +36,44 @@ __device__ __forceinline__ void store_row(double* p, int cs, const double (&v)[V
   for (int q = 0; q < VPT / 2; ++q) *reinterpret_cast<double2*>(p + q * cs) = make_double2(v[2 * q], v[2 * q + 1]);
 }
 
-// Rows of workgroup `bid` of a grid of G workgroups (block index and grid
-// size are those of the request's own launch, also inside a grouped launch).
+// Row ranges of the 8 XCDs (the graph's xr), passed by value.
+struct XcdRows {
+  int64_t r[9];
+};
+static inline XcdRows xcd_rows(const gk_graph* g) {
+  XcdRows x;
+  for (int i = 0; i < 9; ++i) x.r[i] = g->xr[i];
+  return x;
+}
+// Workgroups per XCD for `rows_per_unit` rows each: the widest range decides.
+static inline int64_t xcd_units(const gk_graph* g, int64_t rows_per_unit) {
+  int64_t u = 0;
+  for (int x = 0; x < 8; ++x) u = std::max(u, (g->xr[x + 1] - g->xr[x] + rows_per_unit - 1) / rows_per_unit);
+  return u;
+}
+
+// Rows of workgroup `bid` (index within the request's own launch, also inside
+// a grouped launch, whose request segments start at multiples of 8).
+// Workgroups are dealt round-robin to the 8 XCDs, each with its own L2:
+// workgroup bid runs on XCD bid % 8 and takes the (bid / 8)-th run of rows of
+// that XCD's range, so every XCD walks one contiguous, cost-balanced range of
+// rows and, with a locality ordering of the nodes, gathers mostly through its
+// own L2.  A row's slots lanes never straddle workgroups (256 / slots rows
+// per workgroup; lanes beyond them idle).
 template <int VPT, int WM, bool SHFL>
 __device__ __forceinline__ void
-spmm_diff_body(unsigned bid, unsigned G, int64_t n, int ld, const int32_t* __restrict__ rp,
+spmm_diff_body(unsigned bid, const XcdRows& xr, int64_t n, int ld, const int32_t* __restrict__ rp,
                const int32_t* __restrict__ ci, const double* __restrict__ w64, const float* __restrict__ w32,
                const double* __restrict__ d, const double* __restrict__ V, const double* __restrict__ Vprev,
                double* __restrict__ out, double a, double b, double gm, double* __restrict__ acc, double e,
                const double* __restrict__ e_dev) {
   const int slots = ld / VPT;
-  // Workgroups are dealt round-robin to the 8 XCDs, each with its own L2.
-  // Renumber them so that every XCD walks one contiguous range of rows: with
-  // a locality ordering of the nodes, the neighbour rows it gathers are then
-  // mostly fetched into one L2 instead of several.
-  const unsigned q8 = G >> 3, r8 = G & 7;
+  const int rpw = (int)blockDim.x / slots;
+  const int rin = (int)threadIdx.x / slots;
   const unsigned x = bid & 7, k = bid >> 3;
-  const unsigned lb = x * q8 + (x < r8 ? x : r8) + k;
-  const int64_t t = (int64_t)lb * blockDim.x + threadIdx.x;
-  const int64_t row = t / slots;
-  if (row >= n) return;
-  const int lr = (int)(t - row * slots);   // lane index within the row
+  const int64_t row = xr.r[x] + (int64_t)k * rpw + rin;
+  if (rin >= rpw || row >= xr.r[x + 1]) return;
+  const int lr = (int)threadIdx.x - rin * slots;   // lane index within the row
   const int c0 = 2 * lr, cs = 2 * slots;
   double s[VPT];
 #pragma unroll
@@ -154,9 +171,9 @@ spmm_diff_kernel(int64_t n, int ld, const int32_t* __restrict__ rp, const int32_
                  const double* __restrict__ w64, const float* __restrict__ w32,
                  const double* __restrict__ d, const double* __restrict__ V,
                  const double* __restrict__ Vprev, double* __restrict__ out, double a, double b,
-                 double gm, double* __restrict__ acc, double e, const double* __restrict__ e_dev) {
-  spmm_diff_body<VPT, WM, SHFL>(blockIdx.x, gridDim.x, n, ld, rp, ci, w64, w32, d, V, Vprev, out, a, b, gm, acc,
-                                e, e_dev);
+                 double gm, double* __restrict__ acc, double e, const double* __restrict__ e_dev, XcdRows xr) {
+  spmm_diff_body<VPT, WM, SHFL>(blockIdx.x, xr, n, ld, rp, ci, w64, w32, d, V, Vprev, out, a, b, gm, acc, e,
+                                e_dev);
 }
 
 // Lane layout of a block width: VPT doubles per lane (ld/VPT lanes per row),
@@ -166,7 +183,9 @@ static inline bool spmm_shfl(int ld) {
   const int slots = ld / spmm_vpt(ld);
   return slots <= 64 && (64 % slots) == 0;
 }
-static inline int64_t spmm_grid(int64_t n, int ld) { return (n * (ld / spmm_vpt(ld)) + 255) / 256; }
+static inline int64_t spmm_grid(const gk_graph* g, int ld) {
+  return 8 * xcd_units(g, 256 / (ld / spmm_vpt(ld)));
+}
 
 // One launch for the products X_r = L V_r of several requests on the same
 // graph (their blocks side by side: the concatenated column segments).
@@ -182,16 +201,17 @@ struct SpmmGroupArgs {
 template <int WM>
 __global__ void __launch_bounds__(256)
 spmm_group_kernel(SpmmGroupArgs ga, int64_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
-                  const double* __restrict__ w64, const float* __restrict__ w32, const double* __restrict__ d) {
+                  const double* __restrict__ w64, const float* __restrict__ w32, const double* __restrict__ d,
+                  XcdRows xr) {
   int r = 0;
   while (r + 1 < ga.count && (int)blockIdx.x >= ga.start[r + 1]) ++r;
-  const unsigned bid = blockIdx.x - ga.start[r], G = ga.start[r + 1] - ga.start[r];
+  const unsigned bid = blockIdx.x - ga.start[r];
   const int ld = ga.ld[r];
   const int vpt = ld <= 32 ? 2 : (ld <= 256 ? 4 : 8);
   const int slots = ld / vpt;
   const bool sh = slots <= 64 && (64 % slots) == 0;
 #define GK_SPB(V_, S_)                                                                                            \
-  spmm_diff_body<V_, WM, S_>(bid, G, n, ld, rp, ci, w64, w32, d, ga.V[r], nullptr, ga.X[r], 1.0, 0.0, 0.0, nullptr, \
+  spmm_diff_body<V_, WM, S_>(bid, xr, n, ld, rp, ci, w64, w32, d, ga.V[r], nullptr, ga.X[r], 1.0, 0.0, 0.0, nullptr, \
                              0.0, nullptr)
   if (vpt == 2) {
     if (sh) GK_SPB(2, true); else GK_SPB(2, false);
@@ -217,7 +237,7 @@ void launch_spmm_group(const gk_graph* g, bool fp32_weights, int count, const in
       ga.ld[i] = ld[c0 + i];
       ga.V[i] = V[c0 + i];
       ga.X[i] = X[c0 + i];
-      tot += spmm_grid(g->n, ld[c0 + i]);
+      tot += spmm_grid(g, ld[c0 + i]);
       bytes += 4.0 * (g->n + 1) + (double)g->nnz * (4.0 + wb) + 8.0 * g->n + 16.0 * (double)g->n * ld[c0 + i];
       flops += 2.0 * ((double)g->nnz + g->n) * ld[c0 + i];
     }
@@ -225,13 +245,13 @@ void launch_spmm_group(const gk_graph* g, bool fp32_weights, int count, const in
     kt_begin(KC_SPMM, st);
     if (g->unit)
       hipLaunchKernelGGL(spmm_group_kernel<W_UNIT>, dim3((unsigned)tot), dim3(256), 0, st, ga, g->n, g->rp, g->ci,
-                         g->w64, g->w32, d);
+                         g->w64, g->w32, d, xcd_rows(g));
     else if (fp32_weights)
       hipLaunchKernelGGL(spmm_group_kernel<W_F32>, dim3((unsigned)tot), dim3(256), 0, st, ga, g->n, g->rp, g->ci,
-                         g->w64, g->w32, d);
+                         g->w64, g->w32, d, xcd_rows(g));
     else
       hipLaunchKernelGGL(spmm_group_kernel<W_F64>, dim3((unsigned)tot), dim3(256), 0, st, ga, g->n, g->rp, g->ci,
-                         g->w64, g->w32, d);
+                         g->w64, g->w32, d, xcd_rows(g));
     GK_HIP(hipGetLastError());
     kt_end(st, bytes, flops);
   }
@@ -266,7 +286,7 @@ template <int WM>
 __global__ void __launch_bounds__(SG_THREADS, 2)
 spmm_gram64_kernel(int64_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
                    const double* __restrict__ w64, const float* __restrict__ w32, const double* __restrict__ d,
-                   const double* __restrict__ V, double* __restrict__ out, double* __restrict__ part) {
+                   const double* __restrict__ V, double* __restrict__ out, double* __restrict__ part, XcdRows xr) {
   constexpr int LD = 64, VPT = 4, SLOTS = 16, CS = 32;
   __shared__ __align__(16) double sX[SG_ROWS * SG_P];
   __shared__ __align__(16) double sV[SG_ROWS * SG_P];
@@ -288,17 +308,16 @@ spmm_gram64_kernel(int64_t n, const int32_t* __restrict__ rp, const int32_t* __r
       }
   }
   sg_d4 acc[2] = {sg_d4{0.0, 0.0, 0.0, 0.0}, sg_d4{0.0, 0.0, 0.0, 0.0}};
-  // each XCD (workgroups are dealt round-robin to the 8 XCDs) walks one
-  // contiguous range of row tiles, as the plain product does
-  const int64_t ntiles = (n + SG_ROWS - 1) / SG_ROWS;
-  const unsigned G = gridDim.x, x = blockIdx.x & 7, kx = blockIdx.x >> 3;
-  const unsigned gx = (G >> 3) + (x < (G & 7) ? 1u : 0u);   // workgroups on this XCD
-  const int64_t chunk = (ntiles + 7) / 8;
-  const int64_t t_begin = (int64_t)x * chunk, t_end = min(ntiles, t_begin + chunk);
-  for (int64_t tile = t_begin + kx; tile < t_end; tile += gx) {
-    const int64_t row = tile * SG_ROWS + g;
+  // each XCD (workgroups are dealt round-robin to the 8 XCDs; the grid is a
+  // multiple of 8) walks the row tiles of its own range of the graph's
+  // cost-balanced split, as the plain product does
+  const unsigned x = blockIdx.x & 7, kx = blockIdx.x >> 3, gx = gridDim.x >> 3;
+  const int64_t rb = xr.r[x], re = xr.r[x + 1];
+  const int64_t ntiles = (re - rb + SG_ROWS - 1) / SG_ROWS;
+  for (int64_t tile = kx; tile < ntiles; tile += gx) {
+    const int64_t row = rb + tile * SG_ROWS + g;
     double o[VPT], vi[VPT];
-    if (row < n) {
+    if (row < re) {
       double sacc[VPT];
 #pragma unroll
       for (int q = 0; q < VPT; ++q) sacc[q] = 0.0;
@@ -380,26 +399,30 @@ spmm_gram64_kernel(int64_t n, const int32_t* __restrict__ rp, const int32_t* __r
   }
 }
 
-int spmm_gram64_grid(int64_t n) {
-  const int64_t nt = (n + SG_ROWS - 1) / SG_ROWS;
-  return (int)std::min<int64_t>(nt, SG_MAXGRID);
+int spmm_gram64_grid(const gk_graph* g) {
+  return (int)std::min<int64_t>(8 * xcd_units(g, SG_ROWS), SG_MAXGRID);
+}
+size_t spmm_gram64_scratch_elems(int64_t n) {
+  // a range of the split holds at most n rows
+  return (size_t)std::min<int64_t>(8 * ((n + SG_ROWS - 1) / SG_ROWS), SG_MAXGRID) * 64 * 64;
 }
 
 void launch_spmm_gram64(const gk_graph* g, bool fp32_weights, const double* V, double* X, double* part, double* C,
                         hipStream_t st) {
-  const int grid = spmm_gram64_grid(g->n);
+  const int grid = spmm_gram64_grid(g);
+  const XcdRows xr = xcd_rows(g);
   const double wb = g->unit ? 0.0 : (fp32_weights ? 4.0 : 8.0);
   const double* d = fp32_weights ? g->d32 : g->d64;
   kt_begin(KC_SPMM, st);
   if (g->unit)
     hipLaunchKernelGGL(spmm_gram64_kernel<W_UNIT>, dim3(grid), dim3(SG_THREADS), 0, st, g->n, g->rp, g->ci, g->w64,
-                       g->w32, d, V, X, part);
+                       g->w32, d, V, X, part, xr);
   else if (fp32_weights)
     hipLaunchKernelGGL(spmm_gram64_kernel<W_F32>, dim3(grid), dim3(SG_THREADS), 0, st, g->n, g->rp, g->ci, g->w64,
-                       g->w32, d, V, X, part);
+                       g->w32, d, V, X, part, xr);
   else
     hipLaunchKernelGGL(spmm_gram64_kernel<W_F64>, dim3(grid), dim3(SG_THREADS), 0, st, g->n, g->rp, g->ci, g->w64,
-                       g->w32, d, V, X, part);
+                       g->w32, d, V, X, part, xr);
   GK_HIP(hipGetLastError());
   // the product's own traffic (the Gram reads nothing more); flops of both
   kt_end(st, 4.0 * (g->n + 1) + (double)g->nnz * (4.0 + wb) + 8.0 * g->n + 2.0 * 8.0 * g->n * 64,
@@ -412,14 +435,15 @@ static void spmm_dispatch_w(const gk_graph* g, bool fp32w, int ld, const double*
                             double* out, double a, double b, double gm, double* acc, double e,
                             const double* e_dev, hipStream_t st) {
   const int slots = ld / VPT;
-  const int64_t threads = g->n * slots;
   const int bs = 256;
-  const int64_t grid = (threads + bs - 1) / bs;
+  const int64_t grid = spmm_grid(g, ld);
+  if (grid == 0) return;
+  const XcdRows xr = xcd_rows(g);
   const double* d = fp32w ? g->d32 : g->d64;
   const bool shfl = slots <= 64 && (64 % slots) == 0;
 #define GK_SPMM(WM_, SH_)                                                                                   \
   hipLaunchKernelGGL((spmm_diff_kernel<VPT, WM_, SH_>), dim3((unsigned)grid), dim3(bs), 0, st, g->n, ld, g->rp, \
-                     g->ci, g->w64, g->w32, d, V, Vp, out, a, b, gm, acc, e, e_dev)
+                     g->ci, g->w64, g->w32, d, V, Vp, out, a, b, gm, acc, e, e_dev, xr)
   if (g->unit) {
     if (shfl) GK_SPMM(W_UNIT, true); else GK_SPMM(W_UNIT, false);
   } else if (fp32w) {
