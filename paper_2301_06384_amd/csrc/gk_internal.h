@@ -90,6 +90,12 @@ struct gk_graph {
   // (off-diagonal entries + 3 row accesses), so a degree skew over the node
   // order does not load one XCD's L2 and fabric link with most gathers.
   int64_t xr[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  // Hub rows: rows with more than hub_min off-diagonal entries, each summed
+  // by a workgroup of its own in the products (a heavy-tailed degree
+  // distribution puts a few very long rows on otherwise short critical paths)
+  int hub_min = 256;
+  int64_t nhub = 0;
+  int32_t* hub = nullptr;   // nhub row indices (device order)
   // device arrays (node order of the device, see perm)
   int32_t* rp = nullptr;    // n+1
   int32_t* ci = nullptr;    // nnz

@@ -200,6 +200,10 @@ static void upload(gk_graph* g, const HostLap& H, const std::vector<int64_t>* or
     }
     g->xr[8] = n;
   }
+  std::vector<int32_t> hub;
+  for (int64_t k = 0; k < n; ++k)
+    if (rp[k + 1] - rp[k] > g->hub_min) hub.push_back((int32_t)k);
+  g->nhub = (int64_t)hub.size();
   g->n = n;
   g->nnz = (int64_t)ci.size();
   g->unit = H.unit;
@@ -221,6 +225,7 @@ static void upload(gk_graph* g, const HostLap& H, const std::vector<int64_t>* or
   }
   put(g->d64, d64);
   put(g->d32, d32);
+  put(g->hub, hub);
   if (order) {
     g->reordered = true;
     put(g->d_perm, *order);
@@ -266,7 +271,7 @@ void graph_kernel_release(gk_graph* g) {
   if (!g) return;
   (void)hipDeviceSynchronize();
   for (void* p : {(void*)g->rp, (void*)g->ci, (void*)g->w64, (void*)g->w32, (void*)g->d64, (void*)g->d32,
-                  (void*)g->d_perm, (void*)g->d_iperm})
+                  (void*)g->d_perm, (void*)g->d_iperm, (void*)g->hub})
     if (p) (void)hipFree(p);
   delete g;
 }

@@ -48,11 +48,12 @@ def test_ba_wide_block_cbl(ba):
 
 def test_ba_wide_block_gbl(ba):
     # Alg. 2 at m = 20: mixed against float64 within 1e-5.  At m = 30 the
-    # gbl coefficients are forward-unstable on this hub graph: the float64
-    # path itself, run on the graph in its natural node order instead of the
-    # reordered one (a different summation order, nothing else), moves by
-    # about 6e-5.  There the mixed path is held to that rounding noise of the
-    # float64 path: within twice the natural-vs-reordered float64 difference.
+    # gbl coefficients are forward-unstable on this hub graph: each path, run
+    # on the graph in its natural node order instead of the reordered one (a
+    # different summation order, nothing else), moves by 1e-5 to 1e-4.  There
+    # the mixed path is held to that rounding noise: within twice the larger
+    # natural-vs-reordered difference of the two precisions, and within the
+    # same bound in the natural order.
     L, g = ba
     W = I.samples(L.n, 256, 0)
     phi = dict(kind="diffusion", t=0.5)
@@ -64,12 +65,14 @@ def test_ba_wide_block_gbl(ba):
     Pm, _, sm = gk.krylov_kernel_columns(g, W, phi, 30, "gbl", "mixed")
     g0 = gk.Graph.from_laplacian(L)
     P64n, _, _ = gk.krylov_kernel_columns(g0, W, phi, 30, "gbl", "fp64")
+    Pmn, _, _ = gk.krylov_kernel_columns(g0, W, phi, 30, "gbl", "mixed")
     g0.release()
     assert np.all(np.isfinite(P64))
-    noise, err = rel(P64n, P64), rel(Pm, P64)
-    print(f"gbl BA200k m=30 mixed vs fp64 {err:.3e}; fp64 natural vs reordered node order {noise:.3e}; "
-          f"archive projections {sm.n_reorth} of 28")
-    assert err < max(1e-5, 2.0 * noise)
+    noise = max(rel(P64n, P64), rel(Pmn, Pm))
+    err, err_n = rel(Pm, P64), rel(Pmn, P64n)
+    print(f"gbl BA200k m=30 mixed vs fp64 {err:.3e} (natural order {err_n:.3e}); node-order noise "
+          f"fp64 {rel(P64n, P64):.3e}, mixed {rel(Pmn, Pm):.3e}; archive projections {sm.n_reorth} of 28")
+    assert err < max(1e-5, 2.0 * noise) and err_n < max(1e-5, 2.0 * noise)
     assert sm.n_reorth < 28
 
 

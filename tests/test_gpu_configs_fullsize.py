@@ -73,15 +73,18 @@ def test_c3_ba1m_s256_full_size():
     Pg64, _, _ = run(g, Wd, L.n, s, phi, m, "gbl", "fp64")
     Pgm, _, _ = run(g, Wd, L.n, s, phi, m, "gbl", "mixed")
     assert bool(torch.isfinite(Pg64).all())
-    # gbl at m = 30 is forward-unstable here: the float64 path on the natural
-    # node order (another summation order) is the noise floor of the check
+    # gbl at m = 30 is forward-unstable here: either path on the natural node
+    # order (another summation order) is the noise floor of the check
     g0 = gk.Graph.from_laplacian(L)
     Pg64n, _, _ = run(g0, Wd, L.n, s, phi, m, "gbl", "fp64")
+    Pgmn, _, _ = run(g0, Wd, L.n, s, phi, m, "gbl", "mixed")
     g0.release()
-    noise, err = rel(Pg64n, Pg64), rel(Pgm, Pg64)
-    print(f"C3 gbl mixed vs fp64 {err:.3e}; fp64 natural vs reordered {noise:.3e}")
-    assert err < max(1e-5, 2.0 * noise)
-    del Pg64n
+    noise = max(rel(Pg64n, Pg64), rel(Pgmn, Pgm))
+    err, err_n = rel(Pgm, Pg64), rel(Pgmn, Pg64n)
+    print(f"C3 gbl mixed vs fp64 {err:.3e} (natural order {err_n:.3e}); node-order noise fp64 "
+          f"{rel(Pg64n, Pg64):.3e}, mixed {rel(Pgmn, Pgm):.3e}")
+    assert err < max(1e-5, 2.0 * noise) and err_n < max(1e-5, 2.0 * noise)
+    del Pg64n, Pgmn
     Pg64, _, _ = run(g, Wd, L.n, s, phi, 20, "gbl", "fp64")
     Pgm, _, _ = run(g, Wd, L.n, s, phi, 20, "gbl", "mixed")
     assert rel(Pgm, Pg64) < 1e-5

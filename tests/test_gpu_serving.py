@@ -127,3 +127,34 @@ def test_footprint_bounds_actual_use(pool, variant, precision):
         W = I.samples(Ls[1].n, s, 3)
         c, pred, st = gk.kernel_machine_fit_predict(gs[1], W, I.labels(s, 3), phi, 12, 1e-3, variant, precision)
         assert st.footprint_bytes <= gk.request_footprint(Ls[1].n, s, 12, variant, precision), (s, variant)
+
+
+def test_hub_graph_served_equals_alone_and_oracle():
+    # a heavy-tailed graph: rows above 256 entries are summed by workgroups of
+    # their own (hub rows) in both the lone and the grouped product launches,
+    # at whole-row widths and in 64-column strips (widths 128, 192)
+    L = I.barabasi_albert(20000, 4, seed=7)
+    assert int((np.diff(L.row_ptr) - 1 > 256).sum()) >= 4
+    g = gk.Graph.from_laplacian(L, flags=gk.REORDER)
+    A = L.to_scipy()
+    phi = dict(kind="diffusion", t=0.6)
+    cases = [(24, "cbl", "mixed"), (100, "cbl", "fp64"), (128, "cbl", "mixed"), (192, "cbl", "fp64"),
+             (64, "cbl", "fp64"), (16, "gbl", "mixed")]
+    srv = gk.Server(max_active=6, hbm_budget=0, n_streams=3)
+    try:
+        subs = []
+        for i, (s, v, p) in enumerate(cases):
+            W, y = I.samples(L.n, s, 70 + i), I.labels(s, 70 + i)
+            subs.append((W, y, v, p, srv.submit(g, W, y, phi, 10, 1e-3, v, p)))
+        outs = [(W, y, v, p, srv.poll(t, -1)) for W, y, v, p, t in subs]
+    finally:
+        srv.stop()
+    for W, y, v, p, out in outs:
+        assert out["status"] == 0, (v, p, len(W))
+        c, pred, _ = gk.kernel_machine_fit_predict(g, W, y, phi, 10, 1e-3, v, p)
+        assert np.array_equal(out["coef"], c) and np.array_equal(out["pred"], pred), (v, p, len(W))
+        c0, y0, K0 = krylov.fit_predict(A, W, y, phi, 10, 1e-3, v)
+        kappa = np.linalg.cond(K0 + 1e-3 * np.eye(len(W)))
+        tol = (1e-10 if p == "fp64" else 1e-5) * max(1.0, kappa)
+        assert np.linalg.norm(out["pred"] - y0) / np.linalg.norm(y0) < tol, (v, p, len(W))
+    g.release()
