@@ -40,14 +40,14 @@ CLASSES = {
     "panel_update_self": ("fp64", True, "panel.hip"),
     "panel_apply_self": ("fp64", True, "panel.hip"),
     "panel_apply_write": ("fp64", True, "panel.hip"),
-    "arch_gram": ("fp32", True, "arch.hip"),
-    "arch_update": ("fp32", True, "arch.hip"),
+    "arch_gram": ("fp32", True, ("arch.hip", "ortho.hip")),     # ld <= 64 / wider blocks
+    "arch_update": ("fp32", True, ("arch.hip", "ortho.hip")),
     "gram": ("fp64", True, "ortho.hip"),
     "tsgemm": ("fp64", True, "ortho.hip"),
     "assemble": ("fp32", True, ("arch.hip", "ortho.hip")),
     "predict": ("fp64", False, "ortho.hip"),
 }
-LATENCY = {"cholqr": ("small.hip", "tile64.h"), "omega": ("small.hip", "tile64.h"),
+LATENCY = {"cholqr": ("small.hip", "tile64.h", "wide.hip"), "omega": ("small.hip", "tile64.h", "wide.hip"),
            "banded_factor": ("bcr.hip", "tile64.h"), "banded_solve": ("bcr.hip", "tile64.h"),
            "cheb_step": ("small.hip", "tile64.h"), "jacobi_eig": ("small.hip", "tile64.h")}
 
@@ -180,6 +180,15 @@ def _progress(msg):
 
 
 # ------------------------------------------------ rocprofv3 summaries (host)
+# descriptive names of the workloads (graph, kernel, block width, depth, variant)
+WORKLOAD_NAMES = {
+    "rgg100k_spline": "rgg100k_knn8_spline_eps0.01_k2_s64_m40_cbl",
+    "ba1m_diffusion": "ba1m_m4_diffusion_t0.5_s256_m30_cbl",
+    "grid128c_spline": "grid128cube_uniform_spline_eps0.05_k1_s512_m30_cbl",
+    "grid32_diffusion": "grid32x32_diffusion_t1_s8_m20_cbl",
+}
+
+
 def kernel_class_of(name: str):
     """Kernel class (as the library's own timings name them) of a rocprofv3
     kernel name, or None for kernels outside the path."""
@@ -196,7 +205,8 @@ def kernel_class_of(name: str):
     if base.startswith("tsgemm_mfma_kernel"):
         return "assemble" if len(args) >= 2 and args[1] == "true" else "tsgemm"
     table = [("spmm_", "spmm_diff"), ("reduce_parts", "reduce_parts"), ("arch_gram", "arch_gram"),
-             ("arch_update", "arch_update"), ("arch_assemble", "assemble"), ("gram_", "gram"),
+             ("arch_update", "arch_update"), ("arch_assemble", "assemble"), ("gram_f32mma", "arch_gram"),
+             ("tsgemm_f32mma", "arch_update"), ("assemble_f32mma", "assemble"), ("gram_", "gram"),
              ("tsgemm", "tsgemm"), ("predict", "predict"), ("cholqr", "cholqr"), ("omega", "omega"),
              ("bcr_", "banded"), ("banded_", "banded"), ("btd_cheb", "cheb_step"), ("jacobi", "jacobi_eig")]
     for pre, cls in table:
@@ -451,12 +461,13 @@ def main():
         sd, fd, wd = (None if x == "-" else x for x in args.summarize)
         tag = {"rgg100k_spline": "rgg100k_s64"}.get(args.workload, args.workload)
         pre = "cd /tmp && export TMPDIR=/tmp && "
+        wl = "" if args.workload == "rgg100k_spline" else f"--workload {args.workload} "
+        steps = "--steps 3 --warmup 1" if not wl else "--steps 1 --warmup 1"
         summarize_profiles(sd, fd, wd, args.workload, tag,
                            pre + "rocprofv3 --kernel-trace --stats --output-format csv -d <out>/prof_stats -o stats "
-                                 "-- python3 <repo>/bench.py --steps 3 --warmup 1 --no-cpu --serving-requests 0 "
-                                 "--legs ''",
+                                 f"-- python3 <repo>/bench.py {wl}{steps} --no-cpu --serving-requests 0 --legs ''",
                            pre + "rocprofv3 --pmc {ctr} --output-format csv -d <out>/pmc -o pmc -- python3 "
-                                 "<repo>/bench.py --counters")
+                                 f"<repo>/bench.py {wl}--counters")
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); multi-GPU sharding is not built",
@@ -550,7 +561,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64+f32",
         "data": "synthetic",
-        "config": {"workload": "rgg100k_knn8_spline_eps0.01_k2_s64_m40_cbl", "n": L.n, "nnz": L.nnz,
+        "config": {"workload": WORKLOAD_NAMES.get(args.workload, args.workload), "n": L.n, "nnz": L.nnz,
                    "s": s, "m": m, "reorder": bool(args.reorder)},
         "rel_err_vs_fp64_path": err,
         "value_with_d2h": {"cols_per_s": s / (ms_d2h * 1e-3), "ms_per_step": ms_d2h,

@@ -165,11 +165,38 @@ static void gram_geometry(int64_t n, int nb, int ld, int* nx, int* ny, int* nch,
   if (want > maxc) want = maxc;
   if (want < 1) want = 1;
   if (want > 1024) want = 1024;
+  // a multiple of 8 chunks, so that every XCD gets the same number of them
+  // (the MFMA Gram kernels run each chunk's tiles on one XCD); chunks past
+  // the last row are empty and contribute zero partials
+  want = (want + 7) / 8 * 8;
   int64_t r = (n + want - 1) / want;
   r = ((r + rs - 1) / rs) * rs;
   *rpc = r;
-  *nch = (int)((n + r - 1) / r);
+  *nch = (int)want;
 }
+
+// Workgroup order of the MFMA tile kernels (one-dimensional grids).
+// Workgroups are dealt round-robin to the 8 XCDs, each with its own L2.
+// Gram (tiles nx x ny per row chunk): the nx ny tiles of chunk c are
+// consecutive workgroups of XCD c % 8, so the rows of a chunk are fetched
+// into one L2 and read there by all its tiles, not once per tile.
+__device__ __forceinline__ void gram_tile(int nx, int ny, int& ta, int& tb, int& tc) {
+  const unsigned L = blockIdx.x, x = L & 7, j = L >> 3, T = (unsigned)(nx * ny);
+  const unsigned t = j % T;
+  tc = (int)((j / T) * 8 + x);
+  ta = (int)(t % (unsigned)nx);
+  tb = (int)(t / (unsigned)nx);
+}
+// Row-tile products (row tiles x ny column tiles): the ny column tiles of
+// row tile rt are consecutive workgroups of XCD rt % 8, so the rows they all
+// read come from one L2.  False past the last row tile.
+__device__ __forceinline__ bool row_tile(int64_t nrt, int ny, int64_t& rt, int& tb) {
+  const unsigned L = blockIdx.x, x = L & 7, j = L >> 3;
+  tb = (int)(j % (unsigned)ny);
+  rt = (int64_t)(j / (unsigned)ny) * 8 + x;
+  return rt < nrt;
+}
+static inline unsigned row_tile_grid(int64_t nrt, int ny) { return (unsigned)(8 * ((nrt + 7) / 8) * ny); }
 
 size_t gram_scratch_elems(int64_t n, int nb, int ld) {
   int nx, ny, nch;
@@ -226,12 +253,14 @@ gram_mfma_kernel(int64_t n, int ld, const void* __restrict__ Abase, int64_t astr
                  const double* __restrict__ B, double* __restrict__ part, int64_t rows_per_chunk,
                  const int* __restrict__ flag, int sym) {
   if (flag && *flag == 0) return;
-  if (sym && blockIdx.x > blockIdx.y) return;   // B^T B: the tiles below the diagonal are mirrors
+  const int pa = nb * ld;
+  int ta, tb, tc;
+  gram_tile((pa + MG_T - 1) / MG_T, (ld + MG_T - 1) / MG_T, ta, tb, tc);
+  if (sym && ta > tb) return;   // B^T B: the tiles below the diagonal are mirrors
   __shared__ __align__(16) double sA[MG_RS][MG_P];
   __shared__ __align__(16) double sB[MG_RS][MG_P];
-  const int pa = nb * ld;
-  const int a0 = blockIdx.x * MG_T, b0 = blockIdx.y * MG_T;
-  const int64_t rb = (int64_t)blockIdx.z * rows_per_chunk;
+  const int a0 = ta * MG_T, b0 = tb * MG_T;
+  const int64_t rb = (int64_t)tc * rows_per_chunk;
   const int64_t re = min(n, rb + rows_per_chunk);
   const int tid = threadIdx.x;
   const int w = tid >> 6, l = tid & 63, li = l & 15, lk = l >> 4;
@@ -284,7 +313,7 @@ gram_mfma_kernel(int64_t n, int ld, const void* __restrict__ Abase, int64_t astr
           acc[ti][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[ti], bv[tj], acc[ti][tj], 0, 0, 0);
     }
   }
-  double* P = part + (int64_t)blockIdx.z * pa * ld;
+  double* P = part + (int64_t)tc * pa * ld;
 #pragma unroll
   for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
@@ -315,8 +344,11 @@ tsgemm_mfma_kernel(int64_t n, int ld, const void* __restrict__ Abase, int64_t as
   __shared__ __align__(16) double sC[MT_K][MT_C + 2];
   __shared__ double sO[COLMAJ ? MT_C : 1][MT_R + 1];
   const int pa = nb * ld;
-  const int64_t r0 = (int64_t)blockIdx.x * MT_R;
-  const int b0 = blockIdx.y * MT_C;
+  int64_t rt;
+  int tb;
+  if (!row_tile((n + MT_R - 1) / MT_R, ((COLMAJ ? ncols : ld) + MT_C - 1) / MT_C, rt, tb)) return;
+  const int64_t r0 = rt * MT_R;
+  const int b0 = tb * MT_C;
   const int tid = threadIdx.x;
   const int w = tid >> 6, l = tid & 63, li = l & 15, lk = l >> 4;
   const int wr = 32 * (w >> 1), wc = 32 * (w & 1);
@@ -453,8 +485,10 @@ gram_f32mma_kernel(int64_t n, int ld, const float* __restrict__ Abase, int64_t a
   __shared__ __align__(16) float sA[MG_RS][FP];
   __shared__ __align__(16) float sB[MG_RS][FP];
   const int pa = nb * ld;
-  const int a0 = blockIdx.x * MG_T, b0 = blockIdx.y * MG_T;
-  const int64_t rb = (int64_t)blockIdx.z * rows_per_chunk;
+  int ta, tb, tc;
+  gram_tile((pa + MG_T - 1) / MG_T, (ld + MG_T - 1) / MG_T, ta, tb, tc);
+  const int a0 = ta * MG_T, b0 = tb * MG_T;
+  const int64_t rb = (int64_t)tc * rows_per_chunk;
   const int64_t re = min(n, rb + rows_per_chunk);
   const int tid = threadIdx.x;
   const int w = tid >> 6, l = tid & 63, li = l & 15, lk = l >> 4;
@@ -520,7 +554,7 @@ gram_f32mma_kernel(int64_t n, int ld, const float* __restrict__ Abase, int64_t a
         acc[ti][tj] = f4v{0.f, 0.f, 0.f, 0.f};
       }
   }
-  double* P = part + (int64_t)blockIdx.z * pa * ld;
+  double* P = part + (int64_t)tc * pa * ld;
 #pragma unroll
   for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
@@ -543,8 +577,11 @@ tsgemm_f32mma_kernel(int64_t n, int ld, const float* __restrict__ Abase, int64_t
   __shared__ __align__(16) float sAT[MT_K][FP];
   __shared__ __align__(16) float sC[MT_K][FP];
   const int pa = nb * ld;
-  const int64_t r0 = (int64_t)blockIdx.x * MT_R;
-  const int b0 = blockIdx.y * MT_C;
+  int64_t rt;
+  int tb;
+  if (!row_tile((n + MT_R - 1) / MT_R, (ld + MT_C - 1) / MT_C, rt, tb)) return;
+  const int64_t r0 = rt * MT_R;
+  const int b0 = tb * MT_C;
   const int tid = threadIdx.x;
   const int w = tid >> 6, l = tid & 63, li = l & 15, lk = l >> 4;
   const int wr = 32 * (w >> 1), wc = 32 * (w & 1);
@@ -649,8 +686,11 @@ assemble_f32mma_kernel(int64_t n, int ld, const float* __restrict__ Abase, int64
   __shared__ __align__(16) float sC[MT_K][FP];
   __shared__ double sO[MT_C][MT_R + 1];
   const int pa = nb * ld;
-  const int64_t r0 = (int64_t)blockIdx.x * MT_R;
-  const int b0 = blockIdx.y * MT_C;
+  int64_t rt;
+  int tb;
+  if (!row_tile((n + MT_R - 1) / MT_R, (ncols + MT_C - 1) / MT_C, rt, tb)) return;
+  const int64_t r0 = rt * MT_R;
+  const int b0 = tb * MT_C;
   const int tid = threadIdx.x;
   const int w = tid >> 6, l = tid & 63, li = l & 15, lk = l >> 4;
   const int wr = 32 * (w >> 1), wc = 32 * (w & 1);
@@ -750,11 +790,12 @@ void launch_gram(int64_t n, int ld, BlockList A, const double* B, double* C, dou
   const bool f32mma = mfma_ok(ld) && A.f32;
   kt_begin(f32mma ? KC_ARCH_GRAM : KC_GRAM, st);
   if (mfma_ok(ld)) {
+    const dim3 g1((unsigned)(nx * ny * nch));   // chunk-major per XCD (gram_tile)
     if (A.f32)
-      hipLaunchKernelGGL(gram_f32mma_kernel, grid, dim3(256), 0, st, n, ld, (const float*)A.base, A.stride, A.nb, B,
+      hipLaunchKernelGGL(gram_f32mma_kernel, g1, dim3(256), 0, st, n, ld, (const float*)A.base, A.stride, A.nb, B,
                          part, rpc, flag);
     else
-      hipLaunchKernelGGL(gram_mfma_kernel<false>, grid, dim3(256), 0, st, n, ld, A.base, A.stride, A.nb, B, part,
+      hipLaunchKernelGGL(gram_mfma_kernel<false>, g1, dim3(256), 0, st, n, ld, A.base, A.stride, A.nb, B, part,
                          rpc, flag, sym ? 1 : 0);
   } else if (A.f32)
     hipLaunchKernelGGL(gram_kernel<true>, grid, dim3(256), 0, st, n, ld, A.base, A.stride, A.nb, B,
@@ -874,14 +915,15 @@ void launch_tsgemm(int64_t n, int ld, BlockList A, const double* C, const double
   kt_begin(f32mma ? KC_ARCH_UPDATE : KC_TSGEMM, st);
   if (mfma_ok(ld)) {
     static_assert(MT_R == T_TR && MT_C == T_TB, "same tile grid");
+    const dim3 g1(row_tile_grid((n + MT_R - 1) / MT_R, (ld + MT_C - 1) / MT_C));   // row_tile order
     if (f32mma)
-      hipLaunchKernelGGL(tsgemm_f32mma_kernel, grid, dim3(256), 0, st, n, ld, (const float*)A.base, A.stride, A.nb, C,
+      hipLaunchKernelGGL(tsgemm_f32mma_kernel, g1, dim3(256), 0, st, n, ld, (const float*)A.base, A.stride, A.nb, C,
                          in, out, alpha, beta, flag);
     else if (A.f32)
-      hipLaunchKernelGGL((tsgemm_mfma_kernel<true, false>), grid, dim3(256), 0, st, n, ld, A.base, A.stride, A.nb, C,
+      hipLaunchKernelGGL((tsgemm_mfma_kernel<true, false>), g1, dim3(256), 0, st, n, ld, A.base, A.stride, A.nb, C,
                          ld, ld, in, out, out32, alpha, beta, (int64_t)ld, (const int64_t*)nullptr, flag, up);
     else
-      hipLaunchKernelGGL((tsgemm_mfma_kernel<false, false>), grid, dim3(256), 0, st, n, ld, A.base, A.stride, A.nb,
+      hipLaunchKernelGGL((tsgemm_mfma_kernel<false, false>), g1, dim3(256), 0, st, n, ld, A.base, A.stride, A.nb,
                          C, ld, ld, in, out, out32, alpha, beta, (int64_t)ld, (const int64_t*)nullptr, flag, up);
   } else if (A.f32)
     hipLaunchKernelGGL((tsgemm_kernel<true, false>), grid, dim3(256), 0, st, n, ld, ld, A.base, A.stride,
@@ -904,11 +946,12 @@ void launch_assemble(int64_t n, int ld, int s, BlockList A, const double* U, int
   dim3 grid((unsigned)((n + T_TR - 1) / T_TR), (s + T_TB - 1) / T_TB);
   kt_begin(KC_ASSEMBLE, st);
   if (mfma_ok(ld)) {
+    const dim3 g1(row_tile_grid((n + MT_R - 1) / MT_R, (s + MT_C - 1) / MT_C));   // row_tile order
     if (A.f32)
-      hipLaunchKernelGGL(assemble_f32mma_kernel, grid, dim3(256), 0, st, n, ld, (const float*)A.base, A.stride, A.nb,
+      hipLaunchKernelGGL(assemble_f32mma_kernel, g1, dim3(256), 0, st, n, ld, (const float*)A.base, A.stride, A.nb,
                          U, ldu, s, P, n, perm);
     else
-      hipLaunchKernelGGL((tsgemm_mfma_kernel<false, true>), grid, dim3(256), 0, st, n, ld, A.base, A.stride, A.nb, U,
+      hipLaunchKernelGGL((tsgemm_mfma_kernel<false, true>), g1, dim3(256), 0, st, n, ld, A.base, A.stride, A.nb, U,
                          ldu, s, (const double*)nullptr, P, (float*)nullptr, 1.0, 0.0, n, perm, (const int*)nullptr,
                          0);
   } else if (A.f32)
