@@ -233,14 +233,32 @@ def summarize_profiles(stats_dir, fetch_dir, write_dir, workload, tag, cmd_stats
     out = os.path.join(ROOT, "profiles")
     if stats_dir:
         rows = _csv_rows(stats_dir, "kernel_stats.csv")
+        # register and LDS use per kernel from the trace of the same run:
+        # waves per SIMD = min(8, 512 // (VGPR + AGPR), LDS-limited
+        # workgroups per CU (160 KiB) x waves per workgroup / 4 SIMDs)
+        res = {}
+        for t in _csv_rows(stats_dir, "kernel_trace.csv"):
+            if t["Kernel_Name"] in res:
+                continue
+            v, a, lds = int(t["VGPR_Count"]), int(t["Accum_VGPR_Count"]), int(t["LDS_Block_Size"])
+            wg = int(t["Workgroup_Size_X"]) * int(t["Workgroup_Size_Y"]) * int(t["Workgroup_Size_Z"])
+            wpg = max(1, (wg + 63) // 64)
+            occ = min(8, 512 // max(1, v + a))
+            if lds > 0:
+                occ = min(occ, (163840 // lds) * wpg // 4)
+            res[t["Kernel_Name"]] = (v, a, lds, occ)
         lines = [f"# rocprofv3 kernel statistics, benchmark workload {workload}",
                  f"# command: {cmd_stats}",
-                 f"# {'kernel':<62} {'calls':>6} {'total_ms':>10} {'avg_us':>10} {'min_us':>9} {'max_us':>9}"]
+                 "# vgpr/agpr: registers per lane; lds: bytes per workgroup; w/simd: waves per SIMD the registers "
+                 "and LDS allow (at most 8)",
+                 f"# {'kernel':<62} {'calls':>6} {'total_ms':>10} {'avg_us':>10} {'min_us':>9} {'max_us':>9} "
+                 f"{'vgpr':>5} {'agpr':>5} {'lds':>6} {'w/simd':>6}"]
         rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
         for r in rows:
+            v, a, lds, occ = res.get(r["Name"], (-1, -1, -1, -1))
             lines.append(f"{r['Name'][:62]:<64} {int(r['Calls']):>6} {float(r['TotalDurationNs']) * 1e-6:>10.3f} "
                          f"{float(r['AverageNs']) * 1e-3:>10.2f} {float(r['MinNs']) * 1e-3:>9.2f} "
-                         f"{float(r['MaxNs']) * 1e-3:>9.2f}")
+                         f"{float(r['MaxNs']) * 1e-3:>9.2f} {v:>5} {a:>5} {lds:>6} {occ:>6}")
         with open(os.path.join(out, f"kernel_stats_{tag}.txt"), "w") as fh:
             fh.write("\n".join(lines) + "\n")
     if not (fetch_dir and write_dir):

@@ -311,7 +311,10 @@ def test_reorder_is_transparent():
         assert rel(P1, P0) < TOL[prec]
         c0, p0, _ = gk.kernel_machine_fit_predict(g0, W, y, phi, 10, 1e-3, "cbl", prec)
         c1, p1, _ = gk.kernel_machine_fit_predict(g1, W, y, phi, 10, 1e-3, "cbl", prec)
-        assert rel(p1, p0) < TOL[prec] * 100
+        # the predictor solves (K_WW + gamma I) c = y: a perturbation of K_WW
+        # reaches c and the predictions amplified by the condition number
+        kappa = np.linalg.cond(K0 + 1e-3 * np.eye(len(W)))
+        assert rel(p1, p0) < TOL[prec] * max(1.0, kappa), (prec, kappa, rel(p1, p0))
 
 
 def test_deterministic_bitwise():
