@@ -609,8 +609,11 @@ struct CblRun {
 
   // X = L Q_k.  GK_MIXED at ld = 64 forms Q_k^T X in the same pass (the
   // Gram of the recurrence form below; block 1 of C at k > 0, block 0 at k = 0)
+  // on graphs without hub rows: the fused pass walks a hub row with one lane
+  // group inside its row tiles (BA 600k at s = 64: 994 us fused against
+  // 401 + 127 us for the product with hub workgroups and the Gram pass)
   bool fused = false;
-  bool fusable() const { return mixed && pan && ld == 64; }
+  bool fusable() const { return mixed && pan && ld == 64 && g->nhub == 0; }
   void spmm(int k) {
     J.tm.begin(PH_SPMM);
     fused = fusable();

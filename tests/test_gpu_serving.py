@@ -139,8 +139,8 @@ def test_hub_graph_served_equals_alone_and_oracle():
     A = L.to_scipy()
     phi = dict(kind="diffusion", t=0.6)
     cases = [(24, "cbl", "mixed"), (100, "cbl", "fp64"), (128, "cbl", "mixed"), (192, "cbl", "fp64"),
-             (64, "cbl", "fp64"), (16, "gbl", "mixed")]
-    srv = gk.Server(max_active=6, hbm_budget=0, n_streams=3)
+             (64, "cbl", "fp64"), (64, "cbl", "mixed"), (16, "gbl", "mixed")]
+    srv = gk.Server(max_active=7, hbm_budget=0, n_streams=3)
     try:
         subs = []
         for i, (s, v, p) in enumerate(cases):
