@@ -247,9 +247,8 @@ struct Raw8<false> {
 // B[r0+k][b+i]; accumulator register q holds output row 4q + k, column i).
 // The next 32 rows are fetched into registers while the current ones are
 // multiplied.
-template <bool F32>
 __global__ void __launch_bounds__(256)
-gram_mfma_kernel(int64_t n, int ld, const void* __restrict__ Abase, int64_t astride, int nb,
+gram_mfma_kernel(int64_t n, int ld, const double* __restrict__ Abase, int64_t astride, int nb,
                  const double* __restrict__ B, double* __restrict__ part, int64_t rows_per_chunk,
                  const int* __restrict__ flag, int sym) {
   if (flag && *flag == 0) return;
@@ -265,36 +264,43 @@ gram_mfma_kernel(int64_t n, int ld, const void* __restrict__ Abase, int64_t astr
   const int tid = threadIdx.x;
   const int w = tid >> 6, l = tid & 63, li = l & 15, lk = l >> 4;
   const int wa = 32 * (w >> 1), wb = 32 * (w & 1);
-  // staging: row sr, columns sc .. sc+7 (never across a block: ld % 16 == 0)
-  const int sr = tid >> 3, sc = 8 * (tid & 7);
-  const int ga = a0 + sc, gb = b0 + sc;
-  const bool aok = ga < pa, bok = gb < ld;
-  int64_t aoff = 0;
-  if (aok) {
-    const int blk = ga / ld;
-    aoff = (int64_t)blk * astride + (ga - blk * ld);
+  // staging: row sr; lane sj / 2 of the row's 8 moves the 16-byte chunks at
+  // columns sj + 16 q (q = 0..3), so each load and each LDS store
+  // instruction of the 8 lanes covers 128 contiguous bytes (a chunk never
+  // crosses a block: ld % 16 == 0)
+  const int sr = tid >> 3, sj = 2 * (tid & 7);
+  int64_t aoff[4];
+  bool aok[4], bok[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int ga = a0 + sj + 16 * q;
+    aok[q] = ga < pa;
+    const int blk = aok[q] ? ga / ld : 0;
+    aoff[q] = (int64_t)blk * astride + (ga - blk * ld);
+    bok[q] = b0 + sj + 16 * q < ld;
   }
   d4v acc[2][2];
 #pragma unroll
   for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
     for (int tj = 0; tj < 2; ++tj) acc[ti][tj] = d4v{0.0, 0.0, 0.0, 0.0};
-  Raw8<F32> va;
-  Raw8<false> vb;
+  double2 va[4], vb[4];
   auto fetch = [&](int64_t r0) {
     const int64_t r = r0 + sr;
-    if (r < re && aok) va.load(Abase, aoff + r * ld);
-    else va.zero();
-    if (r < re && bok) vb.load(B, r * ld + gb);
-    else vb.zero();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      va[q] = (r < re && aok[q]) ? *reinterpret_cast<const double2*>(Abase + aoff[q] + r * ld) : make_double2(0.0, 0.0);
+      vb[q] = (r < re && bok[q]) ? *reinterpret_cast<const double2*>(B + r * ld + b0 + sj + 16 * q)
+                                 : make_double2(0.0, 0.0);
+    }
   };
   fetch(rb);
   for (int64_t r0 = rb; r0 < re; r0 += MG_RS) {
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      *reinterpret_cast<double2*>(&sA[sr][sc + 2 * q]) = make_double2(va.get(2 * q), va.get(2 * q + 1));
-      *reinterpret_cast<double2*>(&sB[sr][sc + 2 * q]) = make_double2(vb.get(2 * q), vb.get(2 * q + 1));
+      *reinterpret_cast<double2*>(&sA[sr][sj + 16 * q]) = va[q];
+      *reinterpret_cast<double2*>(&sB[sr][sj + 16 * q]) = vb[q];
     }
     __syncthreads();
     if (r0 + MG_RS < re) fetch(r0 + MG_RS);
@@ -333,6 +339,17 @@ gram_mfma_kernel(int64_t n, int ld, const void* __restrict__ Abase, int64_t astr
 // (leading dimension ldo, row r to perm[r]) through an LDS transpose, C with
 // leading dimension ldc, no in / out32.
 constexpr int MT_R = 64, MT_C = 64, MT_K = 32;
+// The transposed staging writes contraction index k of tile row r at column
+// (r + tsw(k)) mod 64 of LDS row k.  One store instruction writes rows
+// k = 8 g + q (g = 0..3 by lane, q fixed) of 16 tile rows: unrotated, the
+// four g fell on the same banks; rotated by 8 g they cover all 32 banks of
+// a half-wavefront (floats), or each bank twice (doubles).  The product
+// loop reads four consecutive k at once, which share one rotation.
+__device__ __forceinline__ int tsw(int k) { return 8 * ((k >> 3) & 3); }
+// Coefficient staging: lane j of a row's 8 holds the elements q = 0..7 at
+// columns cpos(j, q), pairs 16 columns apart, so each pair-wide load or
+// store instruction of the 8 lanes covers one contiguous stretch of the row.
+__device__ __forceinline__ int cpos(int j, int q) { return 2 * j + 16 * (q >> 1) + (q & 1); }
 template <bool F32, bool COLMAJ>
 __global__ void __launch_bounds__(256)
 tsgemm_mfma_kernel(int64_t n, int ld, const void* __restrict__ Abase, int64_t astride, int nb,
@@ -353,17 +370,16 @@ tsgemm_mfma_kernel(int64_t n, int ld, const void* __restrict__ Abase, int64_t as
   const int w = tid >> 6, l = tid & 63, li = l & 15, lk = l >> 4;
   const int wr = 32 * (w >> 1), wc = 32 * (w & 1);
   const int ar = tid >> 2, ak = 8 * (tid & 3);     // A staging: row, 8 contraction indices
-  const int cr = tid >> 3, cc = 8 * (tid & 7);     // C staging: row, 8 columns
+  const int cr = tid >> 3, cj = tid & 7;           // C staging: row, lane of the row (columns cpos)
   const int64_t arow = r0 + ar;
-  const bool cok = b0 + cc < ld;
   double vcs[COLMAJ ? 8 : 1];   // column-major case: scalar coefficient loads (ldc need not be even)
+  double2 vcp[COLMAJ ? 1 : 4];
   d4v acc[2][2];
 #pragma unroll
   for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
     for (int tj = 0; tj < 2; ++tj) acc[ti][tj] = d4v{0.0, 0.0, 0.0, 0.0};
   Raw8<F32> va;
-  Raw8<false> vc;
   auto fetch = [&](int a0) {
     const int ga = a0 + ak;
     if (arow < n && ga < pa) {
@@ -377,12 +393,16 @@ tsgemm_mfma_kernel(int64_t n, int ld, const void* __restrict__ Abase, int64_t as
       const int gcc = gc < pa ? gc : pa - 1;
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
-        const int col = b0 + cc + q;
+        const int col = b0 + cpos(cj, q);
         vcs[q] = C[(int64_t)gcc * ldc + (col < ncols ? col : ncols - 1)];
       }
     } else {
-      if (gc < pa && cok) vc.load(C, (int64_t)gc * ld + b0 + cc);
-      else vc.zero();
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int col = b0 + 2 * cj + 16 * q;
+        vcp[q] = (gc < pa && col < ld) ? *reinterpret_cast<const double2*>(C + (int64_t)gc * ld + col)
+                                       : make_double2(0.0, 0.0);
+      }
     }
   };
   // upper triangular C (one block): rows past the column tile are zero
@@ -391,15 +411,14 @@ tsgemm_mfma_kernel(int64_t n, int ld, const void* __restrict__ Abase, int64_t as
   for (int a0 = 0; a0 < aend; a0 += MT_K) {
     __syncthreads();
 #pragma unroll
-    for (int q = 0; q < 8; ++q) sAT[ak + q][ar] = va.get(q);
+    for (int q = 0; q < 8; ++q) sAT[ak + q][(ar + tsw(ak)) & 63] = va.get(q);
     if (COLMAJ) {
       const bool rin = a0 + cr < pa;
 #pragma unroll
-      for (int q = 0; q < 8; ++q) sC[cr][cc + q] = (rin && b0 + cc + q < ncols) ? vcs[q] : 0.0;
+      for (int q = 0; q < 8; ++q) sC[cr][cpos(cj, q)] = (rin && b0 + cpos(cj, q) < ncols) ? vcs[q] : 0.0;
     } else {
 #pragma unroll
-      for (int q = 0; q < 4; ++q)
-        *reinterpret_cast<double2*>(&sC[cr][cc + 2 * q]) = make_double2(vc.get(2 * q), vc.get(2 * q + 1));
+      for (int q = 0; q < 4; ++q) *reinterpret_cast<double2*>(&sC[cr][2 * cj + 16 * q]) = vcp[q];
     }
     __syncthreads();
     if (a0 + MT_K < aend) fetch(a0 + MT_K);
@@ -408,7 +427,7 @@ tsgemm_mfma_kernel(int64_t n, int ld, const void* __restrict__ Abase, int64_t as
       double av[2], bv[2];
 #pragma unroll
       for (int t = 0; t < 2; ++t) {
-        av[t] = sAT[4 * ks + lk][wr + 16 * t + li];
+        av[t] = sAT[4 * ks + lk][(wr + 16 * t + li + tsw(4 * ks)) & 63];
         bv[t] = sC[4 * ks + lk][wc + 16 * t + li];
       }
 #pragma unroll
@@ -493,14 +512,22 @@ gram_f32mma_kernel(int64_t n, int ld, const float* __restrict__ Abase, int64_t a
   const int tid = threadIdx.x;
   const int w = tid >> 6, l = tid & 63, li = l & 15, lk = l >> 4;
   const int wa = 32 * (w >> 1), wb = 32 * (w & 1);
-  const int sr = tid >> 3, sc = 8 * (tid & 7);
-  const int ga = a0 + sc, gb = b0 + sc;
-  const bool aok = ga < pa, bok = gb < ld;
-  int64_t aoff = 0;
-  if (aok) {
-    const int blk = ga / ld;
-    aoff = (int64_t)blk * astride + (ga - blk * ld);
+  // staging: row sr; lane j of the row's 8 moves the archive's 16-byte
+  // chunks at columns 4 j + 32 q (q = 0, 1) and X's at columns 2 j + 16 q
+  // (q = 0..3), so each load and LDS store instruction of the 8 lanes covers
+  // a contiguous stretch of the row (a chunk never crosses a block)
+  const int sr = tid >> 3, sj = tid & 7;
+  int64_t aoff[2];
+  bool aok[2], bok[4];
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int ga = a0 + 4 * sj + 32 * q;
+    aok[q] = ga < pa;
+    const int blk = aok[q] ? ga / ld : 0;
+    aoff[q] = (int64_t)blk * astride + (ga - blk * ld);
   }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) bok[q] = b0 + 2 * sj + 16 * q < ld;
   f4v acc[2][2];
   double a64[2][2][4];
 #pragma unroll
@@ -511,24 +538,27 @@ gram_f32mma_kernel(int64_t n, int ld, const float* __restrict__ Abase, int64_t a
 #pragma unroll
       for (int q = 0; q < 4; ++q) a64[ti][tj][q] = 0.0;
     }
-  Raw8<true> va;
-  Raw8<false> vb;
+  float4 va[2];
+  double2 vb[4];
   auto fetch = [&](int64_t r0) {
     const int64_t r = r0 + sr;
-    if (r < re && aok) va.load(Abase, aoff + r * ld);
-    else va.zero();
-    if (r < re && bok) vb.load(B, r * ld + gb);
-    else vb.zero();
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+      va[q] = (r < re && aok[q]) ? *reinterpret_cast<const float4*>(Abase + aoff[q] + r * ld)
+                                 : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      vb[q] = (r < re && bok[q]) ? *reinterpret_cast<const double2*>(B + r * ld + b0 + 2 * sj + 16 * q)
+                                 : make_double2(0.0, 0.0);
   };
   fetch(rb);
   for (int64_t r0 = rb; r0 < re; r0 += MG_RS) {
     __syncthreads();
-    *reinterpret_cast<float4*>(&sA[sr][sc]) = va.f[0];
-    *reinterpret_cast<float4*>(&sA[sr][sc + 4]) = va.f[1];
 #pragma unroll
-    for (int q = 0; q < 2; ++q)
-      *reinterpret_cast<float4*>(&sB[sr][sc + 4 * q]) =
-          make_float4((float)vb.get(4 * q), (float)vb.get(4 * q + 1), (float)vb.get(4 * q + 2), (float)vb.get(4 * q + 3));
+    for (int q = 0; q < 2; ++q) *reinterpret_cast<float4*>(&sA[sr][4 * sj + 32 * q]) = va[q];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      *reinterpret_cast<float2*>(&sB[sr][2 * sj + 16 * q]) = make_float2((float)vb[q].x, (float)vb[q].y);
     __syncthreads();
     if (r0 + MG_RS < re) fetch(r0 + MG_RS);
 #pragma unroll
@@ -586,9 +616,8 @@ tsgemm_f32mma_kernel(int64_t n, int ld, const float* __restrict__ Abase, int64_t
   const int w = tid >> 6, l = tid & 63, li = l & 15, lk = l >> 4;
   const int wr = 32 * (w >> 1), wc = 32 * (w & 1);
   const int ar = tid >> 2, ak = 8 * (tid & 3);     // archive staging: row, 8 contraction indices
-  const int cr = tid >> 3, cc = 8 * (tid & 7);     // coefficient staging: row, 8 columns
+  const int cr = tid >> 3, cj = tid & 7;           // coefficient staging: row, lane of the row
   const int64_t arow = r0 + ar;
-  const bool cok = b0 + cc < ld;
   f4v acc[2][2];
   double a64[2][2][4];
 #pragma unroll
@@ -600,7 +629,7 @@ tsgemm_f32mma_kernel(int64_t n, int ld, const float* __restrict__ Abase, int64_t
       for (int q = 0; q < 4; ++q) a64[ti][tj][q] = 0.0;
     }
   Raw8<true> va;
-  Raw8<false> vc;
+  double2 vcp[4];
   auto fetch = [&](int a0) {
     const int ga = a0 + ak;
     if (arow < n && ga < pa) {
@@ -610,18 +639,21 @@ tsgemm_f32mma_kernel(int64_t n, int ld, const float* __restrict__ Abase, int64_t
       va.zero();
     }
     const int gc = a0 + cr;
-    if (gc < pa && cok) vc.load(C, (int64_t)gc * ld + b0 + cc);
-    else vc.zero();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int col = b0 + 2 * cj + 16 * q;
+      vcp[q] = (gc < pa && col < ld) ? *reinterpret_cast<const double2*>(C + (int64_t)gc * ld + col)
+                                     : make_double2(0.0, 0.0);
+    }
   };
   fetch(0);
   for (int a0 = 0; a0 < pa; a0 += MT_K) {
     __syncthreads();
 #pragma unroll
-    for (int q = 0; q < 8; ++q) sAT[ak + q][ar] = (float)va.get(q);
+    for (int q = 0; q < 8; ++q) sAT[ak + q][(ar + tsw(ak)) & 63] = (float)va.get(q);
 #pragma unroll
-    for (int q = 0; q < 2; ++q)
-      *reinterpret_cast<float4*>(&sC[cr][cc + 4 * q]) =
-          make_float4((float)vc.get(4 * q), (float)vc.get(4 * q + 1), (float)vc.get(4 * q + 2), (float)vc.get(4 * q + 3));
+    for (int q = 0; q < 4; ++q)
+      *reinterpret_cast<float2*>(&sC[cr][2 * cj + 16 * q]) = make_float2((float)vcp[q].x, (float)vcp[q].y);
     __syncthreads();
     if (a0 + MT_K < pa) fetch(a0 + MT_K);
 #pragma unroll
@@ -629,7 +661,7 @@ tsgemm_f32mma_kernel(int64_t n, int ld, const float* __restrict__ Abase, int64_t
       float av[2], bv[2];
 #pragma unroll
       for (int t = 0; t < 2; ++t) {
-        av[t] = sAT[4 * ks + lk][wr + 16 * t + li];
+        av[t] = sAT[4 * ks + lk][(wr + 16 * t + li + tsw(4 * ks)) & 63];
         bv[t] = sC[4 * ks + lk][wc + 16 * t + li];
       }
 #pragma unroll
@@ -695,7 +727,7 @@ assemble_f32mma_kernel(int64_t n, int ld, const float* __restrict__ Abase, int64
   const int w = tid >> 6, l = tid & 63, li = l & 15, lk = l >> 4;
   const int wr = 32 * (w >> 1), wc = 32 * (w & 1);
   const int ar = tid >> 2, ak = 8 * (tid & 3);     // archive staging: row, 8 contraction indices
-  const int cr = tid >> 3, cc = 8 * (tid & 7);     // coefficient staging: row, 8 columns
+  const int cr = tid >> 3, cj = tid & 7;           // coefficient staging: row, lane of the row
   const int64_t arow = r0 + ar;
   f4v acc[2][2];
   double a64[2][2][4];
@@ -721,7 +753,7 @@ assemble_f32mma_kernel(int64_t n, int ld, const float* __restrict__ Abase, int64
     const int gcc = gc < pa ? gc : pa - 1;
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
-      const int col = b0 + cc + q;
+      const int col = b0 + cpos(cj, q);
       vcs[q] = U[(int64_t)gcc * ldu + (col < ncols ? col : ncols - 1)];
     }
   };
@@ -729,11 +761,11 @@ assemble_f32mma_kernel(int64_t n, int ld, const float* __restrict__ Abase, int64
   for (int a0 = 0; a0 < pa; a0 += MT_K) {
     __syncthreads();
 #pragma unroll
-    for (int q = 0; q < 8; ++q) sAT[ak + q][ar] = (float)va.get(q);
+    for (int q = 0; q < 8; ++q) sAT[ak + q][(ar + tsw(ak)) & 63] = (float)va.get(q);
     {
       const bool rin = a0 + cr < pa;
 #pragma unroll
-      for (int q = 0; q < 8; ++q) sC[cr][cc + q] = (rin && b0 + cc + q < ncols) ? (float)vcs[q] : 0.f;
+      for (int q = 0; q < 8; ++q) sC[cr][cpos(cj, q)] = (rin && b0 + cpos(cj, q) < ncols) ? (float)vcs[q] : 0.f;
     }
     __syncthreads();
     if (a0 + MT_K < pa) fetch(a0 + MT_K);
@@ -742,7 +774,7 @@ assemble_f32mma_kernel(int64_t n, int ld, const float* __restrict__ Abase, int64
       float av[2], bv[2];
 #pragma unroll
       for (int t = 0; t < 2; ++t) {
-        av[t] = sAT[4 * ks + lk][wr + 16 * t + li];
+        av[t] = sAT[4 * ks + lk][(wr + 16 * t + li + tsw(4 * ks)) & 63];
         bv[t] = sC[4 * ks + lk][wc + 16 * t + li];
       }
 #pragma unroll
@@ -795,8 +827,8 @@ void launch_gram(int64_t n, int ld, BlockList A, const double* B, double* C, dou
       hipLaunchKernelGGL(gram_f32mma_kernel, g1, dim3(256), 0, st, n, ld, (const float*)A.base, A.stride, A.nb, B,
                          part, rpc, flag);
     else
-      hipLaunchKernelGGL(gram_mfma_kernel<false>, g1, dim3(256), 0, st, n, ld, A.base, A.stride, A.nb, B, part,
-                         rpc, flag, sym ? 1 : 0);
+      hipLaunchKernelGGL(gram_mfma_kernel, g1, dim3(256), 0, st, n, ld, (const double*)A.base, A.stride, A.nb, B,
+                         part, rpc, flag, sym ? 1 : 0);
   } else if (A.f32)
     hipLaunchKernelGGL(gram_kernel<true>, grid, dim3(256), 0, st, n, ld, A.base, A.stride, A.nb, B,
                        part, rpc, flag);
