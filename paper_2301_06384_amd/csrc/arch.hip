@@ -167,6 +167,15 @@ arch_gram_kernel(int64_t n, const float* __restrict__ Q, int64_t qstride, int nb
 // operand e contracts over the columns {k LD/4 + e}.  The coefficient block
 // C_j (float64) is staged in LDS as float, double buffered over j.
 constexpr int AU_ROWS = 128;
+// Pitch (floats) of the coefficients staged for the update and the assembly:
+// a product step reads rows lk KQ + e (KQ = 4 NT) at 16 consecutive columns
+// per lane group lk, and LDS serves 32-bit reads 32 lanes at a time over 32
+// banks, so KQ PC = 16 (mod 32) puts groups lk = 0, 1 (and 2, 3) on disjoint
+// bank halves.
+constexpr int arch_pc(int nt) { return 16 * nt + (nt == 4 ? 1 : (nt == 2 ? 2 : 4)); }
+static_assert((4 * arch_pc(1)) % 32 == 16 && (8 * arch_pc(2)) % 32 == 16 && (12 * arch_pc(3)) % 32 == 16 &&
+                  (16 * arch_pc(4)) % 32 == 16,
+              "coefficient pitch");
 
 template <int NT>
 __global__ void __launch_bounds__(256, 2)
@@ -175,7 +184,7 @@ arch_update_kernel(int64_t n, const float* __restrict__ Q, int64_t qstride, int 
   if (flag && *flag == 0) return;
   constexpr int LD = 16 * NT;
   constexpr int KQ = LD / 4;                 // floats per lane per block row
-  constexpr int PC = LD + 4;                 // LDS pitch of the staged coefficients
+  constexpr int PC = arch_pc(NT);            // LDS pitch of the staged coefficients
   __shared__ float sC[2][LD * PC];
   const int tid = threadIdx.x;
   const int w = tid >> 6, l = tid & 63, li = l & 15, lk = l >> 4;
@@ -282,7 +291,7 @@ arch_assemble_kernel(int64_t n, const float* __restrict__ Q, int64_t qstride, in
                      int s, double* __restrict__ P, const int64_t* __restrict__ perm) {
   constexpr int LD = 16 * NT;
   constexpr int KQ = LD / 4;
-  constexpr int PC = LD + 4;
+  constexpr int PC = arch_pc(NT);
   __shared__ float sC[2][LD * PC];
   const int tid = threadIdx.x;
   const int w = tid >> 6, l = tid & 63, li = l & 15, lk = l >> 4;

@@ -341,11 +341,13 @@ gram_mfma_kernel(int64_t n, int ld, const double* __restrict__ Abase, int64_t as
 constexpr int MT_R = 64, MT_C = 64, MT_K = 32;
 // The transposed staging writes contraction index k of tile row r at column
 // (r + tsw(k)) mod 64 of LDS row k.  One store instruction writes rows
-// k = 8 g + q (g = 0..3 by lane, q fixed) of 16 tile rows: unrotated, the
-// four g fell on the same banks; rotated by 8 g they cover all 32 banks of
-// a half-wavefront (floats), or each bank twice (doubles).  The product
-// loop reads four consecutive k at once, which share one rotation.
-__device__ __forceinline__ int tsw(int k) { return 8 * ((k >> 3) & 3); }
+// k = 8 g + q (g = 0..3 by lane, q fixed): unrotated, the four g fell on the
+// same banks.  LDS serves 32-bit accesses 32 lanes at a time and 64-bit ones
+// 16 lanes at a time over 32 four-byte banks, so floats are rotated by 8 g
+// columns and doubles by 4 g, which spreads each group over all banks.  The
+// product loop reads four consecutive k at once, which share one rotation.
+template <typename T>
+__device__ __forceinline__ int tsw(int k) { return (sizeof(T) == 8 ? 4 : 8) * ((k >> 3) & 3); }
 // Coefficient staging: lane j of a row's 8 holds the elements q = 0..7 at
 // columns cpos(j, q), pairs 16 columns apart, so each pair-wide load or
 // store instruction of the 8 lanes covers one contiguous stretch of the row.
@@ -411,7 +413,7 @@ tsgemm_mfma_kernel(int64_t n, int ld, const void* __restrict__ Abase, int64_t as
   for (int a0 = 0; a0 < aend; a0 += MT_K) {
     __syncthreads();
 #pragma unroll
-    for (int q = 0; q < 8; ++q) sAT[ak + q][(ar + tsw(ak)) & 63] = va.get(q);
+    for (int q = 0; q < 8; ++q) sAT[ak + q][(ar + tsw<double>(ak)) & 63] = va.get(q);
     if (COLMAJ) {
       const bool rin = a0 + cr < pa;
 #pragma unroll
@@ -427,7 +429,7 @@ tsgemm_mfma_kernel(int64_t n, int ld, const void* __restrict__ Abase, int64_t as
       double av[2], bv[2];
 #pragma unroll
       for (int t = 0; t < 2; ++t) {
-        av[t] = sAT[4 * ks + lk][(wr + 16 * t + li + tsw(4 * ks)) & 63];
+        av[t] = sAT[4 * ks + lk][(wr + 16 * t + li + tsw<double>(4 * ks)) & 63];
         bv[t] = sC[4 * ks + lk][wc + 16 * t + li];
       }
 #pragma unroll
@@ -650,7 +652,7 @@ tsgemm_f32mma_kernel(int64_t n, int ld, const float* __restrict__ Abase, int64_t
   for (int a0 = 0; a0 < pa; a0 += MT_K) {
     __syncthreads();
 #pragma unroll
-    for (int q = 0; q < 8; ++q) sAT[ak + q][(ar + tsw(ak)) & 63] = (float)va.get(q);
+    for (int q = 0; q < 8; ++q) sAT[ak + q][(ar + tsw<float>(ak)) & 63] = (float)va.get(q);
 #pragma unroll
     for (int q = 0; q < 4; ++q)
       *reinterpret_cast<float2*>(&sC[cr][2 * cj + 16 * q]) = make_float2((float)vcp[q].x, (float)vcp[q].y);
@@ -661,7 +663,7 @@ tsgemm_f32mma_kernel(int64_t n, int ld, const float* __restrict__ Abase, int64_t
       float av[2], bv[2];
 #pragma unroll
       for (int t = 0; t < 2; ++t) {
-        av[t] = sAT[4 * ks + lk][(wr + 16 * t + li + tsw(4 * ks)) & 63];
+        av[t] = sAT[4 * ks + lk][(wr + 16 * t + li + tsw<float>(4 * ks)) & 63];
         bv[t] = sC[4 * ks + lk][wc + 16 * t + li];
       }
 #pragma unroll
@@ -761,7 +763,7 @@ assemble_f32mma_kernel(int64_t n, int ld, const float* __restrict__ Abase, int64
   for (int a0 = 0; a0 < pa; a0 += MT_K) {
     __syncthreads();
 #pragma unroll
-    for (int q = 0; q < 8; ++q) sAT[ak + q][(ar + tsw(ak)) & 63] = (float)va.get(q);
+    for (int q = 0; q < 8; ++q) sAT[ak + q][(ar + tsw<float>(ak)) & 63] = (float)va.get(q);
     {
       const bool rin = a0 + cr < pa;
 #pragma unroll
@@ -774,7 +776,7 @@ assemble_f32mma_kernel(int64_t n, int ld, const float* __restrict__ Abase, int64
       float av[2], bv[2];
 #pragma unroll
       for (int t = 0; t < 2; ++t) {
-        av[t] = sAT[4 * ks + lk][(wr + 16 * t + li + tsw(4 * ks)) & 63];
+        av[t] = sAT[4 * ks + lk][(wr + 16 * t + li + tsw<float>(4 * ks)) & 63];
         bv[t] = sC[4 * ks + lk][wc + 16 * t + li];
       }
 #pragma unroll
