@@ -263,14 +263,18 @@ int gk_serve_stop(void);
 const char* gk_strerror(int code);
 const char* gk_last_error_detail(void);
 /* Device memory hooks (e.g. a framework's caching allocator).  alloc must
- * return device memory of the current device aligned to 256 bytes, or NULL. */
+ * return device memory of the current device aligned to 256 bytes, or NULL.
+ * Both hooks or neither (NULL, NULL: the library's own cache again);
+ * otherwise GK_EINVAL.  Calls and serving requests started afterwards
+ * allocate through the new hooks; every block is returned to the allocator
+ * that made it, also when the hooks change while it is in use. */
 int gk_set_allocator(void* (*alloc_fn)(size_t bytes, void* ctx), void (*free_fn)(void* ptr, void* ctx),
                      void* ctx);
-/* Return the device blocks the default allocator keeps cached for reuse
- * (freed by finished calls) to HIP, after the work that last used them has
+/* Return the device blocks the library's own cache keeps for reuse (freed
+ * by finished calls) to HIP, after the work that last used them has
  * completed; *released_bytes (may be NULL) receives their size.  Blocks of
- * calls still running are untouched.  No effect with an allocator installed
- * by gk_set_allocator. */
+ * calls still running, and blocks of an allocator installed with
+ * gk_set_allocator, are untouched. */
 int gk_trim(uint64_t* released_bytes);
 /* Stream used by the synchronous calls of the calling thread (hipStream_t). */
 int gk_set_stream(void* hip_stream);

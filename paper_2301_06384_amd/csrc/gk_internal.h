@@ -34,8 +34,15 @@ struct Error {
   } while (0)
 
 // ------------------------------------------------------------- allocation
-void* dev_alloc(size_t bytes);
-void dev_free(void* p);
+// The free hook of the allocator that made a block (null: the library's own
+// cache), kept with the block so that it goes back there even when another
+// allocator has been installed since.
+struct FreeHook {
+  void (*fn)(void*, void*) = nullptr;
+  void* ctx = nullptr;
+};
+void* dev_alloc(size_t bytes, FreeHook* made_by);
+void dev_free(void* p, const FreeHook& made_by);
 hipStream_t current_stream();
 // Wait for and drop the reuse events of every cached block (before the
 // streams they were recorded on are destroyed).
@@ -49,6 +56,7 @@ uint64_t cache_trim();
 // GK_ENOMEM.
 struct Arena {
   std::vector<void*> ptrs;
+  std::vector<FreeHook> hooks;
   uint64_t bytes = 0;
   char* pool = nullptr;
   size_t pool_cap = 0;
@@ -64,14 +72,16 @@ struct Arena {
       bytes += b;
       return static_cast<T*>(q);
     }
-    void* p = dev_alloc(b);
+    FreeHook h;
+    void* p = dev_alloc(b, &h);
     if (!p) throw Error{GK_ENOMEM, "device allocation of " + std::to_string(b) + " bytes failed"};
     ptrs.push_back(p);
+    hooks.push_back(h);
     bytes += b;
     return static_cast<T*>(p);
   }
   ~Arena() {
-    for (void* p : ptrs) dev_free(p);
+    for (size_t i = 0; i < ptrs.size(); ++i) dev_free(ptrs[i], hooks[i]);
   }
 };
 

@@ -36,6 +36,8 @@ Cache& cache() {
   static Cache* c = new Cache();   // never destroyed: blocks may outlive static destruction order
   return *c;
 }
+// the installed allocator hooks, read and written as one triple
+std::mutex g_hook_mu;
 void* (*g_alloc_fn)(size_t, void*) = nullptr;
 void (*g_free_fn)(void*, void*) = nullptr;
 void* g_alloc_ctx = nullptr;
@@ -44,11 +46,18 @@ thread_local hipStream_t t_stream = nullptr;
 
 hipStream_t current_stream() { return t_stream; }
 
-void* dev_alloc(size_t bytes) {
-  if (g_alloc_fn) {
-    void* p = g_alloc_fn(bytes, g_alloc_ctx);
-    return p;
+void* dev_alloc(size_t bytes, FreeHook* made_by) {
+  void* (*afn)(size_t, void*);
+  FreeHook h;
+  {
+    std::lock_guard<std::mutex> lk(g_hook_mu);
+    afn = g_alloc_fn;
+    h.fn = g_free_fn;
+    h.ctx = g_alloc_ctx;
   }
+  *made_by = h;
+  if (afn) return afn(bytes, h.ctx);
+  made_by->fn = nullptr;
   Cache& c = cache();
   std::lock_guard<std::mutex> lk(c.mu);
   auto it = c.free_blocks.lower_bound(bytes);
@@ -93,10 +102,10 @@ void* dev_alloc(size_t bytes) {
   return p;
 }
 
-void dev_free(void* p) {
+void dev_free(void* p, const FreeHook& made_by) {
   if (!p) return;
-  if (g_free_fn) {
-    g_free_fn(p, g_alloc_ctx);
+  if (made_by.fn) {
+    made_by.fn(p, made_by.ctx);
     return;
   }
   Cache& c = cache();
@@ -121,7 +130,6 @@ void dev_free(void* p) {
 void set_thread_stream(hipStream_t s) { t_stream = s; }
 
 uint64_t cache_trim() {
-  if (g_alloc_fn) return 0;
   Cache& c = cache();
   std::lock_guard<std::mutex> lk(c.mu);
   uint64_t released = 0;
@@ -140,7 +148,6 @@ uint64_t cache_trim() {
 }
 
 void cache_settle() {
-  if (g_alloc_fn) return;
   Cache& c = cache();
   std::lock_guard<std::mutex> lk(c.mu);
   for (auto& kv : c.free_blocks) {
@@ -309,6 +316,7 @@ const char* gk_last_error_detail(void) { return gk::t_detail.c_str(); }
 
 int gk_set_allocator(void* (*alloc_fn)(size_t, void*), void (*free_fn)(void*, void*), void* ctx) {
   if ((alloc_fn == nullptr) != (free_fn == nullptr)) return GK_EINVAL;
+  std::lock_guard<std::mutex> lk(gk::g_hook_mu);
   gk::g_alloc_fn = alloc_fn;
   gk::g_free_fn = free_fn;
   gk::g_alloc_ctx = ctx;

@@ -319,6 +319,12 @@ def use_torch_allocator() -> None:
     _check(_lib.gk_set_allocator(fa, ff, None), "gk_set_allocator")
 
 
+def reset_allocator() -> None:
+    """Back to the library's own device cache (gk_set_allocator(NULL, NULL))."""
+    _check(_lib.gk_set_allocator(_ALLOC_T(), _FREE_T(), None), "gk_set_allocator")
+    _alloc_keep[:] = []
+
+
 # -------------------------------------------------------------------- serving
 class Server:
     """Continuous-batching serving loop (gk_serve_start / gk_submit / gk_poll)."""
