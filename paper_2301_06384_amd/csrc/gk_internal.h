@@ -42,7 +42,9 @@ struct FreeHook {
   void* ctx = nullptr;
 };
 void* dev_alloc(size_t bytes, FreeHook* made_by);
-void dev_free(void* p, const FreeHook& made_by);
+// settled: the stream that used the block has completed all its work, so the
+// cache may hand it out again at once (no reuse event)
+void dev_free(void* p, const FreeHook& made_by, bool settled = false);
 hipStream_t current_stream();
 // Wait for and drop the reuse events of every cached block (before the
 // streams they were recorded on are destroyed).
@@ -80,8 +82,10 @@ struct Arena {
     bytes += b;
     return static_cast<T*>(p);
   }
+  // set once the stream of the arena's work has been synchronised
+  bool settled = false;
   ~Arena() {
-    for (size_t i = 0; i < ptrs.size(); ++i) dev_free(ptrs[i], hooks[i]);
+    for (size_t i = 0; i < ptrs.size(); ++i) dev_free(ptrs[i], hooks[i], settled);
   }
 };
 

@@ -1362,6 +1362,7 @@ int run_call(const CallArgs& a, hipStream_t stream) {
   }
   call_outputs(S);
   GK_HIP(hipStreamSynchronize(stream));
+  J.ar.settled = true;   // its blocks are idle: cached without reuse events
   return call_complete(S, true);
 }
 

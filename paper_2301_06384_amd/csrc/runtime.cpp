@@ -102,7 +102,7 @@ void* dev_alloc(size_t bytes, FreeHook* made_by) {
   return p;
 }
 
-void dev_free(void* p, const FreeHook& made_by) {
+void dev_free(void* p, const FreeHook& made_by, bool settled) {
   if (!p) return;
   if (made_by.fn) {
     made_by.fn(p, made_by.ctx);
@@ -116,7 +116,7 @@ void dev_free(void* p, const FreeHook& made_by) {
   c.live.erase(it);
   c.live_bytes -= b;
   hipEvent_t ev = nullptr;
-  if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess) {
+  if (!settled && hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess) {
     if (hipEventRecord(ev, t_stream) != hipSuccess) {
       (void)hipEventDestroy(ev);
       ev = nullptr;
