@@ -448,6 +448,15 @@ def config_leg(torch, gk, I, name, variants, fp64=True):
     table, whole = kernel_table(agg, 1, "fp32")
     out["cbl_mixed_kernels"] = {k: {f: v[f] for f in ("launches_per_step", "ms_per_step", "avg_launch_us", "bound",
                                                       "achieved", "unit", "frac")} for k, v in table.items()}
+    # measured HBM-side traffic (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)
+    # per launch from a committed profile of this workload taken on the
+    # current kernel sources, over the launch time measured here (per-launch
+    # averages include the gated launches of steps that do not project)
+    for k, v in out["cbl_mixed_kernels"].items():
+        srcs = _sources(k) if (k in CLASSES or k in LATENCY) else None
+        tb = _traffic_from_profile(k, name, _kernel_hash(srcs)) if srcs else None
+        v["traffic_bytes_per_launch"] = tb
+        v["traffic_GBps"] = (tb / (v["avg_launch_us"] * 1e-6) / 1e9) if (tb and v["avg_launch_us"]) else None
     out["cbl_mixed_whole_solve"] = whole
     del Pm, Km
     g.release()
