@@ -65,10 +65,10 @@ def _sources(name):
     return [src] if isinstance(src, str) else list(src)
 
 
-def _traffic_from_profile(kernel: str, workload: str, src_hash: str):
+def _traffic_from_profile(kernel: str, workload: str, src_hash: str, prof_dir=None):
     """HBM bytes per launch of a kernel from a committed rocprofv3 --pmc
     summary, only if it was taken on the current kernel source."""
-    p = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.txt")
+    p = os.path.join(prof_dir or os.path.join(ROOT, "profiles"), f"{kernel}_{workload}_traffic.txt")
     if not os.path.exists(p):
         return None
     vals = {}
@@ -225,12 +225,12 @@ def _csv_rows(d, suffix):
         return list(csv.DictReader(fh))
 
 
-def summarize_profiles(stats_dir, fetch_dir, write_dir, workload, tag, cmd_stats, cmd_pmc):
+def summarize_profiles(stats_dir, fetch_dir, write_dir, workload, tag, cmd_stats, cmd_pmc, out_dir=None):
     """Write profiles/kernel_stats_<tag>.txt from a `rocprofv3 --kernel-trace
     --stats` run and profiles/<class>_<tag>_traffic.txt from two `--pmc` runs
     (FETCH_SIZE, WRITE_SIZE) of `bench.py --counters`, whose 1 GiB copy
     calibrates the byte counters."""
-    out = os.path.join(ROOT, "profiles")
+    out = out_dir or os.path.join(ROOT, "profiles")
     if stats_dir:
         rows = _csv_rows(stats_dir, "kernel_stats.csv")
         # register and LDS use per kernel from the trace of the same run:
