@@ -49,7 +49,9 @@ CLASSES = {
 }
 LATENCY = {"cholqr": ("small.hip", "tile64.h", "wide.hip"), "omega": ("small.hip", "tile64.h", "wide.hip"),
            "banded_factor": ("bcr.hip", "tile64.h"), "banded_solve": ("bcr.hip", "tile64.h"),
-           "cheb_step": ("small.hip", "tile64.h"), "jacobi_eig": ("small.hip", "tile64.h")}
+           "cheb_step": ("small.hip", "tile64.h"), "jacobi_eig": ("small.hip", "tile64.h"),
+           # rocprofv3 names of both banded phases (bcr_*, banded_*) map to one class
+           "banded": ("bcr.hip", "small.hip", "tile64.h", "wide.hip")}
 
 
 def _kernel_hash(files):
