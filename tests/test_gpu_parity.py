@@ -45,6 +45,8 @@ def G(name):
             L = I.disjoint_union(I.random_weighted(12, 0.3, seed=1), I.random_weighted(20, 0.2, seed=2))
         elif name == "grid3d":
             L = I.grid((9, 8, 7), weights="uniform", seed=4)
+        elif name == "ba20k":
+            L = I.barabasi_albert(20000, 4, seed=7)
         else:
             raise KeyError(name)
         _graphs[name] = (L, gk.Graph.from_laplacian(L))
@@ -424,3 +426,19 @@ def test_error_paths_on_device():
     P, K, _ = gk.krylov_kernel_columns(g, [3, 9], dict(kind="diffusion", t=0.0), 4)
     E = dense.unit_block(L.n, [3, 9])
     assert np.max(np.abs(P - E)) < 1e-14
+
+
+@pytest.mark.parametrize("s", [272, 520, 1000])
+def test_hub_rows_at_wide_unshuffled_layouts(s):
+    # the product's hub rows (more than 256 entries; the natural order of a
+    # Barabasi-Albert graph puts them first) on workgroups of their own, at
+    # block widths whose lane layout walks the neighbour list without
+    # shuffles: 34, 66 and 126 lanes per row, 7, 3 and 2 lane groups
+    L, g = G("ba20k")
+    assert int((np.diff(L.row_ptr) - 1 > 256).sum()) >= 4
+    W = I.samples(L.n, s, 300 + s)
+    phi = dict(kind="diffusion", t=0.3)
+    ref = krylov.cbl(L.to_scipy(), W, phi, 3)["P"]
+    for prec in ("fp64", "mixed"):
+        P, _, _ = gk.krylov_kernel_columns(g, W, phi, 3, "cbl", prec)
+        assert rel(P, ref) < TOL[prec], (s, prec, rel(P, ref))
