@@ -498,38 +498,42 @@ tsgemm_mfma_kernel(int64_t n, int ld, const void* __restrict__ Abase, int64_t as
 typedef float f4v __attribute__((ext_vector_type(4)));
 constexpr int FP = 80;
 
-__global__ void __launch_bounds__(256)
+// 64 archive columns x 128 columns of X per workgroup of 8 wavefronts (wave
+// w owns the 32 x 32 quarter (w % 2, w / 2)): each staged archive tile
+// serves two 64-column halves of X, so the archive rows of a chunk are read
+// by half as many workgroups as with 64 x 64 tiles.
+constexpr int MG_TB2 = 128, FPB = MG_TB2 + 16;   // LDS pitch 144 floats (16 mod 32)
+__global__ void __launch_bounds__(512)
 gram_f32mma_kernel(int64_t n, int ld, const float* __restrict__ Abase, int64_t astride, int nb,
                    const double* __restrict__ B, double* __restrict__ part, int64_t rows_per_chunk,
                    const int* __restrict__ flag) {
   if (flag && *flag == 0) return;
   __shared__ __align__(16) float sA[MG_RS][FP];
-  __shared__ __align__(16) float sB[MG_RS][FP];
+  __shared__ __align__(16) float sB[MG_RS][FPB];
   const int pa = nb * ld;
   int ta, tb, tc;
-  gram_tile((pa + MG_T - 1) / MG_T, (ld + MG_T - 1) / MG_T, ta, tb, tc);
-  const int a0 = ta * MG_T, b0 = tb * MG_T;
+  gram_tile((pa + MG_T - 1) / MG_T, (ld + MG_TB2 - 1) / MG_TB2, ta, tb, tc);
+  const int a0 = ta * MG_T, b0 = tb * MG_TB2;
   const int64_t rb = (int64_t)tc * rows_per_chunk;
   const int64_t re = min(n, rb + rows_per_chunk);
   const int tid = threadIdx.x;
   const int w = tid >> 6, l = tid & 63, li = l & 15, lk = l >> 4;
-  const int wa = 32 * (w >> 1), wb = 32 * (w & 1);
-  // staging: row sr; lane j of the row's 8 moves the archive's 16-byte
-  // chunks at columns 4 j + 32 q (q = 0, 1) and X's at columns 2 j + 16 q
-  // (q = 0..3), so each load and LDS store instruction of the 8 lanes covers
-  // a contiguous stretch of the row (a chunk never crosses a block)
-  const int sr = tid >> 3, sj = tid & 7;
-  int64_t aoff[2];
-  bool aok[2], bok[4];
-#pragma unroll
-  for (int q = 0; q < 2; ++q) {
-    const int ga = a0 + 4 * sj + 32 * q;
-    aok[q] = ga < pa;
-    const int blk = aok[q] ? ga / ld : 0;
-    aoff[q] = (int64_t)blk * astride + (ga - blk * ld);
+  const int wa = 32 * (w & 1), wb = 32 * (w >> 1);
+  // staging: row sr; lane sj of the row's 16 moves the archive's 16-byte
+  // chunk at column 4 sj and X's at columns 2 sj + 32 q (q = 0..3), so each
+  // load and LDS store instruction of the 16 lanes covers a contiguous
+  // stretch of the row (a chunk never crosses a block: ld % 16 == 0)
+  const int sr = tid >> 4, sj = tid & 15;
+  const int ga = a0 + 4 * sj;
+  const bool aok = ga < pa;
+  int64_t aoff = 0;
+  if (aok) {
+    const int blk = ga / ld;
+    aoff = (int64_t)blk * astride + (ga - blk * ld);
   }
+  bool bok[4];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) bok[q] = b0 + 2 * sj + 16 * q < ld;
+  for (int q = 0; q < 4; ++q) bok[q] = b0 + 2 * sj + 32 * q < ld;
   f4v acc[2][2];
   double a64[2][2][4];
 #pragma unroll
@@ -540,27 +544,23 @@ gram_f32mma_kernel(int64_t n, int ld, const float* __restrict__ Abase, int64_t a
 #pragma unroll
       for (int q = 0; q < 4; ++q) a64[ti][tj][q] = 0.0;
     }
-  float4 va[2];
+  float4 va;
   double2 vb[4];
   auto fetch = [&](int64_t r0) {
     const int64_t r = r0 + sr;
-#pragma unroll
-    for (int q = 0; q < 2; ++q)
-      va[q] = (r < re && aok[q]) ? *reinterpret_cast<const float4*>(Abase + aoff[q] + r * ld)
-                                 : make_float4(0.f, 0.f, 0.f, 0.f);
+    va = (r < re && aok) ? *reinterpret_cast<const float4*>(Abase + aoff + r * ld) : make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
     for (int q = 0; q < 4; ++q)
-      vb[q] = (r < re && bok[q]) ? *reinterpret_cast<const double2*>(B + r * ld + b0 + 2 * sj + 16 * q)
+      vb[q] = (r < re && bok[q]) ? *reinterpret_cast<const double2*>(B + r * ld + b0 + 2 * sj + 32 * q)
                                  : make_double2(0.0, 0.0);
   };
   fetch(rb);
   for (int64_t r0 = rb; r0 < re; r0 += MG_RS) {
     __syncthreads();
-#pragma unroll
-    for (int q = 0; q < 2; ++q) *reinterpret_cast<float4*>(&sA[sr][4 * sj + 32 * q]) = va[q];
+    *reinterpret_cast<float4*>(&sA[sr][4 * sj]) = va;
 #pragma unroll
     for (int q = 0; q < 4; ++q)
-      *reinterpret_cast<float2*>(&sB[sr][2 * sj + 16 * q]) = make_float2((float)vb[q].x, (float)vb[q].y);
+      *reinterpret_cast<float2*>(&sB[sr][2 * sj + 32 * q]) = make_float2((float)vb[q].x, (float)vb[q].y);
     __syncthreads();
     if (r0 + MG_RS < re) fetch(r0 + MG_RS);
 #pragma unroll
@@ -825,9 +825,9 @@ void launch_gram(int64_t n, int ld, BlockList A, const double* B, double* C, dou
   kt_begin(f32mma ? KC_ARCH_GRAM : KC_GRAM, st);
   if (mfma_ok(ld)) {
     const dim3 g1((unsigned)(nx * ny * nch));   // chunk-major per XCD (gram_tile)
-    if (A.f32)
-      hipLaunchKernelGGL(gram_f32mma_kernel, g1, dim3(256), 0, st, n, ld, (const float*)A.base, A.stride, A.nb, B,
-                         part, rpc, flag);
+    if (A.f32)   // 64 x 128 tiles: the chunk count of the 64 x 64 geometry
+      hipLaunchKernelGGL(gram_f32mma_kernel, dim3((unsigned)(nx * ((ld + MG_TB2 - 1) / MG_TB2) * nch)), dim3(512), 0,
+                         st, n, ld, (const float*)A.base, A.stride, A.nb, B, part, rpc, flag);
     else
       hipLaunchKernelGGL(gram_mfma_kernel, g1, dim3(256), 0, st, n, ld, (const double*)A.base, A.stride, A.nb, B,
                          part, rpc, flag, sym ? 1 : 0);
