@@ -3,9 +3,13 @@
 // The products L*Q_k of Alg. 1 / Alg. 2 (and T_k(I - 2L/Lambda) E_W of the
 // Chebyshev recurrence, Sec. 3.4) are the block matrix-vector products
 // counted in Table 1.  Blocks are row-major n x ld (ld >= s, zero padded),
-// so a neighbour's row is one contiguous ld*8-byte segment: each row of the
-// output is owned by ld/VPT consecutive lanes that read VPT doubles of every
-// neighbour row as 16-byte vector loads (coalesced gathers).
+// so a neighbour's row is one contiguous ld*8-byte segment.  The product is
+// formed over column strips of width ws (ld, or 64 for wider blocks that are
+// multiples of 64, one strip after the other): each row of a strip is owned
+// by ws/VPT consecutive lanes that read VPT doubles of every neighbour's
+// segment as 16-byte vector loads (coalesced gathers).  The rows are split
+// among the 8 XCDs by cost, and rows with very many entries (hub rows) are
+// summed by a workgroup of their own.
 //
 // (L v)_i = d_i v_i - sum_{j != i} w_ij v_j with d_i = sum_j w_ij + c_i
 // accumulated in float64; with float32 weights d_i is the float64 sum of the
