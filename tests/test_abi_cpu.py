@@ -121,3 +121,34 @@ def test_footprint_arithmetic():
         gk.request_footprint(0, 4, 4)
     with pytest.raises(gk.GKError):
         gk.request_footprint(10, 2000, 4)
+
+
+def test_struct_layouts_match_header(tmp_path):
+    # the ctypes structures of the binding against the C header: every field
+    # offset and every struct size, from a program compiled with the header
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("no C compiler")
+    structs = {"gk_phi": gk.Phi, "gk_stats": gk.Stats, "gk_request": gk.Request, "gk_result": gk.Result,
+               "gk_kernel_timing": gk.KernelTiming}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "gk/graph_kernel.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'  printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {}
+    for line in out:
+        if line:
+            cname, field, val = line.split()
+            got[(cname, field)] = int(val)
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == C.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
