@@ -9,7 +9,10 @@
 // accuracy of the archive itself (unit roundoff 2^-24 relative to |Q||X|), so
 // the products run as v_mfma_f32_16x16x4f32 with float accumulation over short
 // row runs that are added into float64; partial sums are reduced in float64 in
-// a fixed order (bitwise reproducible, no atomics).
+// a fixed order (bitwise reproducible, no atomics).  The update at widths
+// that are multiples of 64 (update_bf3_kernel, also used for the wide blocks)
+// forms the same float32-accurate product on the BF16 matrix cores from a
+// three-part split of its operands.
 //
 // v_mfma_f32_16x16x4f32 operand layout (lane l of 64, i = l % 16, k = l / 16):
 //   A (16 x 4):  lane l holds A[i][k]
@@ -279,6 +282,198 @@ arch_update_kernel(int64_t n, const float* __restrict__ Q, int64_t qstride, int 
   }
 }
 
+// ------------------------------------- update X -= Q C on BF16 matrix cores
+// For ld a multiple of 64: the same product as above on the BF16 matrix
+// cores, which issue sixteen times the FP32 rate.  Every float32 operand x is
+// cut into three bfloat16 parts by truncation, x0 = the upper 16 bits of x,
+// x1 = those of x - x0 and x2 = x - x0 - x1; the cut is exact, each part
+// carrying 8 of the 24 significand bits.  Of the nine part products of q c
+// the six with i + j <= 2 are formed; the other three are below 2^-24 |q| |c|,
+// the rounding level of float32 itself.  Each part product is exact in the
+// float accumulator, so the sum has the accuracy of the float32 product.
+//
+// v_mfma_f32_16x16x32_bf16 operand layout (lane l, i = l % 16, k = l / 16):
+//   A (16 x 32): lane l holds A[i][8 k .. 8 k + 7]
+//   B (32 x 16): lane l holds B[8 k .. 8 k + 7][i]
+//   D (16 x 16): register r of lane l holds D[4 k + r][i]
+//
+// Workgroup = 4 wavefronts over 128 rows and 64 columns of X (column tile
+// tb); wavefront w owns rows 32 w .. 32 w + 31 as two groups of 16.  The
+// contraction runs over the archive columns in chunks of 64 (a chunk never
+// crosses an archive block since ld % 64 == 0).  Per chunk, a lane splits its
+// archive entries Q[row][32 h + 8 k .. + 7] (h = 0, 1) into the B operands,
+// and the workgroup splits the 64 x 64 coefficient tile once into three
+// planes in LDS.  A plane is stored per X column as 32 dwords of contraction
+// index pairs, its 16-byte chunks XOR-swizzled by the column, so that the
+// 128-bit operand reads and stores (eight lanes at a time) spread over all
+// 32 banks.  The float accumulators
+// run over the whole contraction: the update is a small correction of X.
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef unsigned u4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ f4 mfma_bf3(u4 a, u4 b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, a), __builtin_bit_cast(bf8, b), c, 0, 0, 0);
+}
+
+// the three parts of x in the lower halves, of y in the upper halves
+__device__ __forceinline__ void split3(float x, float y, unsigned& h, unsigned& m, unsigned& l) {
+  const unsigned xb = __float_as_uint(x), yb = __float_as_uint(y);
+  const float xr = x - __uint_as_float(xb & 0xffff0000u), yr = y - __uint_as_float(yb & 0xffff0000u);
+  const unsigned xrb = __float_as_uint(xr), yrb = __float_as_uint(yr);
+  const float xl = xr - __uint_as_float(xrb & 0xffff0000u), yl = yr - __uint_as_float(yrb & 0xffff0000u);
+  h = __builtin_amdgcn_perm(yb, xb, 0x07060302u);
+  m = __builtin_amdgcn_perm(yrb, xrb, 0x07060302u);
+  l = __builtin_amdgcn_perm(__float_as_uint(yl), __float_as_uint(xl), 0x07060302u);
+}
+
+constexpr int UB_PLANE = 64 * 32;   // dwords per coefficient plane
+
+__global__ void __launch_bounds__(256, 3)
+update_bf3_kernel(int64_t n, int ld, const float* __restrict__ Q, int64_t qstride, int nb,
+                  const double* __restrict__ C, double* __restrict__ X, const int* __restrict__ flag) {
+  if (flag && *flag == 0) return;
+  // tiles: the column tiles of row tile rt are consecutive workgroups of XCD
+  // rt % 8, so the archive rows they share come from one L2
+  const int nct = ld >> 6;
+  const int64_t nrt = (n + AU_ROWS - 1) / AU_ROWS;
+  const unsigned L = blockIdx.x, xcd = L & 7, jt = L >> 3;
+  const int tb = (int)(jt % (unsigned)nct);
+  const int64_t rt = (int64_t)(jt / (unsigned)nct) * 8 + xcd;
+  if (rt >= nrt) return;
+  const int b0 = 64 * tb;
+  const int nch = nb * nct;   // 64-index chunks of the contraction
+  __shared__ __align__(16) unsigned sC[2][3 * UB_PLANE];
+  const int tid = threadIdx.x;
+  const int w = tid >> 6, l = tid & 63, li = l & 15, lk = l >> 4;
+  const int64_t R0 = rt * AU_ROWS + 32 * w;
+
+  f4 acc[2][4];
+#pragma unroll
+  for (int g = 0; g < 2; ++g)
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc[g][t] = f4{0.f, 0.f, 0.f, 0.f};
+
+  // coefficient staging: wavefront w stages rows 16 w .. 16 w + 15 of the
+  // 64 x 64 tile, lane l column l (64 consecutive doubles per load), and
+  // stores them as the 16-byte chunks 2 w and 2 w + 1 of column l
+  const int wu = __builtin_amdgcn_readfirstlane(w);
+  auto fetch_c = [&](int jc, double (&cv)[16]) {
+    const double* Cj = C + ((int64_t)jc * 64 + 16 * wu) * ld + b0;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) cv[j] = Cj[(int64_t)j * ld + l];
+  };
+  auto put_c = [&](int buf, const double (&cv)[16]) {
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      u4 h, m, lo;
+#pragma unroll
+      for (int p = 0; p < 4; ++p) {
+        unsigned x0, x1, x2;
+        split3((float)cv[8 * e + 2 * p], (float)cv[8 * e + 2 * p + 1], x0, x1, x2);
+        h[p] = x0;
+        m[p] = x1;
+        lo[p] = x2;
+      }
+      const int o = l * 32 + (((2 * wu + e) ^ (l & 7)) << 2);
+      *reinterpret_cast<u4*>(&sC[buf][o]) = h;
+      *reinterpret_cast<u4*>(&sC[buf][UB_PLANE + o]) = m;
+      *reinterpret_cast<u4*>(&sC[buf][2 * UB_PLANE + o]) = lo;
+    }
+  };
+  // lane (i, k) of row group g: Q[row][32 h + 8 k .. 32 h + 8 k + 7] of the chunk
+  auto load_q = [&](int jc, float (&qv)[2][16]) {
+    const int blk = jc / nct;
+    const float* Qj = Q + (int64_t)blk * qstride + 64 * (jc - blk * nct);
+#pragma unroll
+    for (int g = 0; g < 2; ++g) {
+      // rows past n read row n - 1: their results are never stored
+      const int64_t r = R0 + 16 * g + li;
+      const int64_t rc = r < n ? r : n - 1;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const f4 x = *reinterpret_cast<const f4*>(Qj + rc * ld + 32 * (v >> 1) + 8 * lk + 4 * (v & 1));
+        qv[g][4 * v] = x[0];
+        qv[g][4 * v + 1] = x[1];
+        qv[g][4 * v + 2] = x[2];
+        qv[g][4 * v + 3] = x[3];
+      }
+    }
+  };
+
+  // One chunk per step.  The next chunk's archive rows (at the end the last
+  // chunk again, unused) are loaded before the products; its coefficients,
+  // read from L2, once half the archive operands are spent (registers).
+  auto step = [&](int jc, const float (&qc)[2][16], float (&qn)[2][16]) {
+    const int jn = jc + 1 < nch ? jc + 1 : nch - 1;
+    double cnext[16];
+    load_q(jn, qn);
+    const unsigned* sc = sC[jc & 1];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      if (h == 1) fetch_c(jn, cnext);
+      if (jc >= nch) continue;
+      u4 bh[2], bm[2], bl[2];
+#pragma unroll
+      for (int g = 0; g < 2; ++g)
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+          unsigned x0, x1, x2;
+          split3(qc[g][8 * h + 2 * p], qc[g][8 * h + 2 * p + 1], x0, x1, x2);
+          bh[g][p] = x0;
+          bm[g][p] = x1;
+          bl[g][p] = x2;
+        }
+      const int ch = ((4 * h + lk) ^ (li & 7)) << 2;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const unsigned* base = sc + (16 * t + li) * 32 + ch;
+        const u4 ah = *reinterpret_cast<const u4*>(base);
+        const u4 am = *reinterpret_cast<const u4*>(base + UB_PLANE);
+        const u4 al = *reinterpret_cast<const u4*>(base + 2 * UB_PLANE);
+        // smallest part products first
+#pragma unroll
+        for (int g = 0; g < 2; ++g) acc[g][t] = mfma_bf3(al, bh[g], acc[g][t]);
+#pragma unroll
+        for (int g = 0; g < 2; ++g) acc[g][t] = mfma_bf3(am, bm[g], acc[g][t]);
+#pragma unroll
+        for (int g = 0; g < 2; ++g) acc[g][t] = mfma_bf3(ah, bl[g], acc[g][t]);
+#pragma unroll
+        for (int g = 0; g < 2; ++g) acc[g][t] = mfma_bf3(am, bh[g], acc[g][t]);
+#pragma unroll
+        for (int g = 0; g < 2; ++g) acc[g][t] = mfma_bf3(ah, bm[g], acc[g][t]);
+#pragma unroll
+        for (int g = 0; g < 2; ++g) acc[g][t] = mfma_bf3(ah, bh[g], acc[g][t]);
+      }
+    }
+    if (jc + 1 < nch) put_c((jc & 1) ^ 1, cnext);
+    __syncthreads();
+  };
+  float q0[2][16], q1[2][16];
+  {
+    double c0[16];
+    fetch_c(0, c0);
+    put_c(0, c0);
+  }
+  load_q(0, q0);
+  __syncthreads();
+  for (int jc = 0; jc < nch; jc += 2) {
+    step(jc, q0, q1);
+    step(jc + 1, q1, q0);
+  }
+  // D_{g,t}[4k + r][i] = (Q C)[row 16 g + i][b0 + 16 t + 4 k + r]
+#pragma unroll
+  for (int g = 0; g < 2; ++g) {
+    const int64_t r = R0 + 16 * g + li;
+    if (r >= n) continue;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      double* xp = X + r * ld + b0 + 16 * t + 4 * lk;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) xp[q] -= (double)acc[g][t][q];
+    }
+  }
+}
+
 // ------------------------------------------------------- assembly P = Q U
 // P[perm(r), c] = sum_j Q_j[r, :] U_j[:, c] for c < s (Alg. 1 output
 // [Q_1 .. Q_m] phi(H_m) F_1): float32 archive and coefficients rounded to
@@ -407,6 +602,21 @@ arch_assemble_kernel(int64_t n, const float* __restrict__ Q, int64_t qstride, in
 // ------------------------------------------------------------------ launchers
 bool arch_ok(int ld) { return ld == 16 || ld == 32 || ld == 48 || ld == 64; }
 
+bool update_bf3_ok(int ld) { return ld >= 64 && ld % 64 == 0; }
+
+void launch_update_bf3(int64_t n, int ld, BlockList A, const double* C, double* X, const int* flag, hipStream_t st) {
+  GK_REQUIRE(A.f32 && A.stride > 0 && A.nb >= 1 && update_bf3_ok(ld) && n >= 1, GK_EUNSUPPORTED,
+             "the BF16 archive update needs a float32 archive and ld % 64 == 0");
+  const int64_t nrt = (n + AU_ROWS - 1) / AU_ROWS;
+  const int64_t grid = 8 * ((nrt + 7) / 8) * (ld / 64);
+  GK_REQUIRE(grid <= 0x7fffffff, GK_EUNSUPPORTED, "archive update grid too large");
+  kt_begin(KC_ARCH_UPDATE, st);
+  hipLaunchKernelGGL(update_bf3_kernel, dim3((unsigned)grid), dim3(256), 0, st, n, ld,
+                     static_cast<const float*>(A.base), A.stride, A.nb, C, X, flag);
+  GK_HIP(hipGetLastError());
+  kt_end(st, 4.0 * (double)n * ld * A.nb + 16.0 * (double)n * ld, 2.0 * (double)n * ld * ld * A.nb, flag);
+}
+
 static void arch_gram_geometry(int64_t n, int nb, int ld, int* ngroups, int* nchunks, int64_t* rpc) {
   const int bpw = ag_blocks(ld / 16);
   *ngroups = (nb + bpw - 1) / bpw;
@@ -448,11 +658,15 @@ static void arch_launch(int64_t n, BlockList A, double* X, double* C, double* pa
   kt_end(st, qb + xb, fl, flag);
   const int64_t len = (int64_t)A.nb * 16 * NT * 16 * NT;
   launch_reduce_parts(len, nc, part, C, flag, st);
-  kt_begin(KC_ARCH_UPDATE, st);
-  hipLaunchKernelGGL(arch_update_kernel<NT>, dim3((unsigned)((n + AU_ROWS - 1) / AU_ROWS)), dim3(256), 0, st, n, Q,
-                     A.stride, A.nb, (const double*)C, X, flag);
-  GK_HIP(hipGetLastError());
-  kt_end(st, qb + 2.0 * xb, fl, flag);
+  if constexpr (NT == 4) {
+    launch_update_bf3(n, 64, A, C, X, flag, st);
+  } else {
+    kt_begin(KC_ARCH_UPDATE, st);
+    hipLaunchKernelGGL(arch_update_kernel<NT>, dim3((unsigned)((n + AU_ROWS - 1) / AU_ROWS)), dim3(256), 0, st, n,
+                       Q, A.stride, A.nb, (const double*)C, X, flag);
+    GK_HIP(hipGetLastError());
+    kt_end(st, qb + 2.0 * xb, fl, flag);
+  }
 }
 
 // One projection X -= Q (Q^T X) against the float32 archive A (A.f32, A.stride

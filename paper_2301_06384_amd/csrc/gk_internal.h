@@ -333,6 +333,10 @@ void launch_arch_reorth(int64_t n, int ld, BlockList A, double* X, double* C, do
                         hipStream_t st, const OmegaDecide* dec = nullptr);
 void launch_arch_assemble(int64_t n, int ld, int s, BlockList A, const double* U, double* P, const int64_t* perm,
                           hipStream_t st);
+// X -= A C on the BF16 matrix cores (three-part split of every float32
+// operand) for a float32 archive and ld % 64 == 0; C is nb*ld x ld row-major.
+bool update_bf3_ok(int ld);
+void launch_update_bf3(int64_t n, int ld, BlockList A, const double* C, double* X, const int* flag, hipStream_t st);
 size_t panel_scratch_elems(int64_t n, int ld);
 // flag: the pass and its reduction do nothing when *flag == 0
 void launch_panel(int mode, int64_t n, int ld, int nbv, const double* X, double* Xout, float* X32,

@@ -941,6 +941,11 @@ void launch_tsgemm(int64_t n, int ld, BlockList A, const double* C, const double
                    float* out32, double alpha, double beta, const int* flag, hipStream_t st, bool upper,
                    bool tri0) {
   const int up = (upper && A.nb == 1) ? 1 : 0;
+  // X -= A C against the float32 archive at widths 64 k: BF16 matrix cores
+  if (A.f32 && !up && !out32 && !tri0 && in == out && alpha == -1.0 && beta == 1.0 && update_bf3_ok(ld)) {
+    launch_update_bf3(n, ld, A, C, out, flag, st);
+    return;
+  }
   dim3 grid((unsigned)((n + T_TR - 1) / T_TR), (ld + T_TB - 1) / T_TB);
   // the float32 archive (reorthogonalisation update) on the FP32 matrix
   // cores; a triangular coefficient block or a float copy of the output
