@@ -28,8 +28,10 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 # MI355X datasheet peaks (dense): FP64 vector and matrix 78.6 TFLOP/s, FP32
-# matrix 157.3 TFLOP/s.
-PEAK_TF = {"fp64": 78.6, "fp32": 157.3}
+# matrix 157.3 TFLOP/s, BF16 matrix 2.5 PFLOP/s.  "bf16x6": float32-accurate
+# products formed as six BF16 part products each (a three-part split of both
+# operands), so a sixth of the BF16 peak.
+PEAK_TF = {"fp64": 78.6, "fp32": 157.3, "bf16x6": 2500.0 / 6}
 
 # Kernel class -> (arithmetic of its flops, runs on the matrix cores, source
 # files).  Single-workgroup classes form latency chains: no chip-wide roof.
@@ -41,7 +43,9 @@ CLASSES = {
     "panel_apply_self": ("fp64", True, "panel.hip"),
     "panel_apply_write": ("fp64", True, "panel.hip"),
     "arch_gram": ("fp32", True, ("arch.hip", "ortho.hip")),     # ld <= 64 / wider blocks
-    "arch_update": ("fp32", True, ("arch.hip", "ortho.hip")),
+    # widths 64 k (every benchmark workload) run on the BF16 cores; 16, 32
+    # and 48, and wide blocks of other widths, keep the FP32 kernels
+    "arch_update": ("bf16x6", True, ("arch.hip", "ortho.hip")),
     "gram": ("fp64", True, "ortho.hip"),
     "tsgemm": ("fp64", True, "ortho.hip"),
     "assemble": ("fp32", True, ("arch.hip", "ortho.hip")),
@@ -207,7 +211,8 @@ def kernel_class_of(name: str):
     if base.startswith("tsgemm_mfma_kernel"):
         return "assemble" if len(args) >= 2 and args[1] == "true" else "tsgemm"
     table = [("spmm_", "spmm_diff"), ("reduce_parts", "reduce_parts"), ("arch_gram", "arch_gram"),
-             ("arch_update", "arch_update"), ("arch_assemble", "assemble"), ("gram_f32mma", "arch_gram"),
+             ("arch_update", "arch_update"), ("update_bf3", "arch_update"), ("arch_assemble", "assemble"),
+             ("gram_f32mma", "arch_gram"),
              ("tsgemm_f32mma", "arch_update"), ("assemble_f32mma", "assemble"), ("gram_", "gram"),
              ("tsgemm", "tsgemm"), ("predict", "predict"), ("cholqr", "cholqr"), ("omega", "omega"),
              ("bcr_", "banded"), ("banded_", "banded"), ("btd_cheb", "cheb_step"), ("jacobi", "jacobi_eig")]
@@ -237,12 +242,15 @@ def summarize_profiles(stats_dir, fetch_dir, write_dir, workload, tag, cmd_stats
         rows = _csv_rows(stats_dir, "kernel_stats.csv")
         # register and LDS use per kernel from the trace of the same run:
         # waves per SIMD = min(8, 512 // (VGPR + AGPR), LDS-limited
-        # workgroups per CU (160 KiB) x waves per workgroup / 4 SIMDs)
+        # workgroups per CU (160 KiB) x waves per workgroup / 4 SIMDs).
+        # The trace's VGPR_Count is half the unified register allocation on
+        # gfx950 (it equals the compiler's .amdhsa_next_free_vgpr, rounded to
+        # the granule of 8, divided by 2), so it is doubled here.
         res = {}
         for t in _csv_rows(stats_dir, "kernel_trace.csv"):
             if t["Kernel_Name"] in res:
                 continue
-            v, a, lds = int(t["VGPR_Count"]), int(t["Accum_VGPR_Count"]), int(t["LDS_Block_Size"])
+            v, a, lds = 2 * int(t["VGPR_Count"]), int(t["Accum_VGPR_Count"]), int(t["LDS_Block_Size"])
             wg = int(t["Workgroup_Size_X"]) * int(t["Workgroup_Size_Y"]) * int(t["Workgroup_Size_Z"])
             wpg = max(1, (wg + 63) // 64)
             occ = min(8, 512 // max(1, v + a))
@@ -251,8 +259,8 @@ def summarize_profiles(stats_dir, fetch_dir, write_dir, workload, tag, cmd_stats
             res[t["Kernel_Name"]] = (v, a, lds, occ)
         lines = [f"# rocprofv3 kernel statistics, benchmark workload {workload}",
                  f"# command: {cmd_stats}",
-                 "# vgpr/agpr: registers per lane; lds: bytes per workgroup; w/simd: waves per SIMD the registers "
-                 "and LDS allow (at most 8)",
+                 "# vgpr/agpr: registers per lane (vgpr: the unified allocation, twice the trace's VGPR_Count); "
+                 "lds: bytes per workgroup; w/simd: waves per SIMD the registers and LDS allow (at most 8)",
                  f"# {'kernel':<62} {'calls':>6} {'total_ms':>10} {'avg_us':>10} {'min_us':>9} {'max_us':>9} "
                  f"{'vgpr':>5} {'agpr':>5} {'lds':>6} {'w/simd':>6}"]
         rows.sort(key=lambda r: -float(r["TotalDurationNs"]))

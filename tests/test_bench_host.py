@@ -21,6 +21,7 @@ import bench  # noqa: E402
     ("void gk::tsgemm_mfma_kernel<false, false>(long, int, void const*)", "tsgemm"),
     ("gk::gram_f32mma_kernel(long, int, float const*, long, int)", "arch_gram"),
     ("gk::tsgemm_f32mma_kernel(long, int, float const*)", "arch_update"),
+    ("gk::update_bf3_kernel(long, int, float const*, long, int, double const*, double*, int const*)", "arch_update"),
     ("gk::assemble_f32mma_kernel(long, int, float const*)", "assemble"),
     ("gk::gram_mfma_kernel(long, int, double const*)", "gram"),
     ("void gk::arch_gram_kernel<4>(long, float const*)", "arch_gram"),
@@ -44,6 +45,10 @@ def test_classify_bound_follows_intensity():
     high = bench.classify(dict(name="arch_gram", total_ms=1.0, alg_bytes=1e9, alg_flops=1e11))
     assert high["bound"] == "mfma" and high["peak"] == 157.3
     assert high["achieved"] == pytest.approx(100.0)
+    # the archive update runs on the BF16 cores (six part products per float32
+    # product): at 32 flop/B it sits below that ridge (52 flop/B) on HBM
+    upd = bench.classify(dict(name="arch_update", total_ms=1.0, alg_bytes=1e9, alg_flops=3.2e10))
+    assert upd["bound"] == "hbm" and upd["ridge"] == pytest.approx(2500.0 / 6 / 8)
     # single-workgroup chains carry no chip-wide fraction
     lat = bench.classify(dict(name="cholqr", total_ms=1.0, alg_bytes=1e6, alg_flops=1e6))
     assert lat["bound"] == "latency" and lat["frac"] is None
