@@ -287,10 +287,13 @@ arch_update_kernel(int64_t n, const float* __restrict__ Q, int64_t qstride, int 
 // cores, which issue sixteen times the FP32 rate.  Every float32 operand x is
 // cut into three bfloat16 parts by truncation, x0 = the upper 16 bits of x,
 // x1 = those of x - x0 and x2 = x - x0 - x1; the cut is exact, each part
-// carrying 8 of the 24 significand bits.  Of the nine part products of q c
-// the six with i + j <= 2 are formed; the other three are below 2^-24 |q| |c|,
-// the rounding level of float32 itself.  Each part product is exact in the
-// float accumulator, so the sum has the accuracy of the float32 product.
+// carrying 8 of the 24 significand bits (|x1| < 2^-7 |x|, |x2| < 2^-15 |x|).
+// Of the nine part products of q c the six with i + j <= 2 are formed; the
+// other three are together below 2^-21 |q| |c|, a few float32 rounding units.
+// Each part product is exact in the float accumulator.  The update is a
+// correction of X of relative size 2^-16 or less (it runs when the estimated
+// loss of orthogonality reaches that), so this is far below the float32
+// rounding of the archive itself.
 //
 // v_mfma_f32_16x16x32_bf16 operand layout (lane l, i = l % 16, k = l / 16):
 //   A (16 x 32): lane l holds A[i][8 k .. 8 k + 7]
