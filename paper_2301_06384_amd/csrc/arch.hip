@@ -291,9 +291,9 @@ arch_update_kernel(int64_t n, const float* __restrict__ Q, int64_t qstride, int 
 // Of the nine part products of q c the six with i + j <= 2 are formed; the
 // other three are together below 2^-21 |q| |c|, a few float32 rounding units.
 // Each part product is exact in the float accumulator.  The update is a
-// correction of X of relative size 2^-16 or less (it runs when the estimated
-// loss of orthogonality reaches that), so this is far below the float32
-// rounding of the archive itself.
+// small correction of X (it runs when the estimated loss of orthogonality
+// reaches 2^-16 in cbl, 2^-12 in gbl and sbl), so this error is far below the
+// float32 rounding of the archive itself.
 //
 // v_mfma_f32_16x16x32_bf16 operand layout (lane l, i = l % 16, k = l / 16):
 //   A (16 x 32): lane l holds A[i][8 k .. 8 k + 7]
@@ -309,8 +309,7 @@ arch_update_kernel(int64_t n, const float* __restrict__ Q, int64_t qstride, int 
 // planes in LDS.  A plane is stored per X column as 32 dwords of contraction
 // index pairs, its 16-byte chunks XOR-swizzled by the column, so that the
 // 128-bit operand reads and stores (eight lanes at a time) spread over all
-// 32 banks.  The float accumulators
-// run over the whole contraction: the update is a small correction of X.
+// 32 banks.  The float accumulators run over the whole contraction.
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef unsigned u4 __attribute__((ext_vector_type(4)));
 
