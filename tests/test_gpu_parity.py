@@ -243,6 +243,21 @@ def test_wide_blocks(s, phi):
             assert st.as_dict()["phi_method"] == "banded"
 
 
+@pytest.mark.parametrize("s", [192, 256, 512])
+def test_wide_projection_every_step(s):
+    # the archive update at widths 64k runs on the BF16 matrix cores (three-
+    # part split of its float32 operands); with a projection at every step it
+    # runs on each one, at up to 8 column tiles of 64
+    L, g = G("rgg2003")
+    W = I.samples(L.n, s, 40 + s)
+    m = 3
+    phi = dict(kind="spline", eps=0.02, k=2.0)
+    ref = krylov.cbl(L.to_scipy(), W, phi, m)["P"]
+    P, K, st = gk.krylov_kernel_columns(g, W, phi, m, "cbl", "mixed", flags=gk.FULL_REORTH)
+    assert st.n_reorth == m - 1
+    assert rel(P, ref) < TOL["mixed"], (s, rel(P, ref))
+
+
 @pytest.mark.parametrize("s", [16, 64, 100, 256])
 def test_second_cholqr_pass_gate(s):
     # the mixed path leaves out the second CholQR pass where the first factor
